@@ -1,0 +1,287 @@
+/*
+ * Reference (oracle) implementation of Iterative Perturbation Theory, plain FP64.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct CPU checker
+ * that the HIP path is compared against.  It shares no code, header, table or
+ * helper with the product library; only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load it.
+ *
+ * What it computes (Kenmoe, Kriemann, Smerlak, Zadorin, "A fast iterative
+ * algorithm for near-diagonal eigenvalue problems"):
+ *   M = D + Delta, theta = diag(D) pairwise distinct (Sec. 3, "partition").
+ *   For a requested index i, g_i = (1/(theta_j - theta_i))_{j != i}, (g_i)_i = 0
+ *   (Alg. 1, step computing g_i; inverse-gap matrix G_jk = 1/(theta_j - theta_k)).
+ *   The map f_i(z) = e_i + g_i o (z (Delta z)_i - Delta z)   (eq. single_line_dyn)
+ *   is iterated from z = e_i (or a supplied warm start) while
+ *   |z - f_i(z)| / |z| > eta  (Alg. 1 loop test), the eigenvalue is
+ *   lambda_i = (M z)_i = theta_i + (Delta z)_i          (Alg. 1 return step).
+ *   Applying f_{idx[c]} to every requested column c is exactly the matrix map
+ *   F(Z) = I + G o (Z D(Delta Z) - Delta Z) restricted to those columns
+ *   (eq. dyn, Alg. 2), because each column is an independent fixed-point problem.
+ *
+ * Readings taken where the paper is silent (each is listed in the design notes):
+ *   - the norm in the stopping test is the Euclidean norm of the column
+ *     (per-column relative step s_c);
+ *   - the returned eigenvector is the iterate z that passed the test, and
+ *     lambda uses (Delta z)_i of that same z (no extra product);
+ *   - a column is DIVERGED when any entry of f_i(z) or s is non-finite, when
+ *     |f_i(z) - e_i| exceeds div_norm, or when s grew on div_growth consecutive
+ *     sweeps; it is NOT_CONVERGED when max_iter sweeps end without a decision.
+ *     In both cases the last computed iterate f_i(z) is returned, with lambda from
+ *     the (Delta z)_i of that sweep.
+ *   - a warm start has its entry i overwritten with 1 (chart z_i = 1).
+ *
+ * Arithmetic: FP64, every dot product summed in ascending index order, compiled
+ * with -ffp-contract=off so no fused multiply-add changes the rounding.  OpenMP
+ * runs independent columns in parallel; a column's arithmetic does not depend on
+ * the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { OR_CONVERGED = 0, OR_NOT_CONVERGED = 1, OR_DIVERGED = 2 };
+
+/* y = Delta z for a dense row-major Delta (leading dimension lda). */
+static void dense_apply(int64_t n, const double *delta, int64_t lda, const double *z, double *y) {
+    for (int64_t j = 0; j < n; ++j) {
+        const double *row = delta + j * lda;
+        double acc = 0.0;
+        for (int64_t l = 0; l < n; ++l) acc += row[l] * z[l];
+        y[j] = acc;
+    }
+}
+
+/* y = Delta z for a CSR Delta (entries of a row summed in storage order). */
+static void csr_apply(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                      const double *z, double *y) {
+    for (int64_t j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int64_t p = row_ptr[j]; p < row_ptr[j + 1]; ++p) acc += val[p] * z[col[p]];
+        y[j] = acc;
+    }
+}
+
+typedef struct {
+    int64_t n;
+    /* dense */
+    const double *delta;
+    int64_t lda;
+    /* csr */
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+} op_t;
+
+static void op_apply(const op_t *A, const double *z, double *y) {
+    if (A->delta) dense_apply(A->n, A->delta, A->lda, z, y);
+    else csr_apply(A->n, A->row_ptr, A->col, A->val, z, y);
+}
+
+/* One application of f_i (eq. single_line_dyn): w = e_i + g o (z d - y), with
+ * y = Delta z and d = y_i.  Returns d. */
+static double map_once(const op_t *A, const double *theta, int64_t i, const double *g,
+                       const double *z, double *y, double *w) {
+    const int64_t n = A->n;
+    op_apply(A, z, y);
+    const double d = y[i];
+    for (int64_t j = 0; j < n; ++j) w[j] = (j == i) ? 1.0 : g[j] * (z[j] * d - y[j]);
+    (void)theta;
+    return d;
+}
+
+static void inverse_gaps(int64_t n, const double *theta, int64_t i, double *g) {
+    for (int64_t j = 0; j < n; ++j) g[j] = (j == i) ? 0.0 : 1.0 / (theta[j] - theta[i]);
+}
+
+/* Alg. 1 for one column.  z (length n) holds the start on entry and the returned
+ * vector on exit. */
+static void solve_column(const op_t *A, const double *theta, int64_t i, double tol, int max_iter,
+                         double div_norm, int div_growth, double *z, double *g, double *y, double *w,
+                         double *lambda, int32_t *status, int32_t *sweeps, double *step) {
+    const int64_t n = A->n;
+    inverse_gaps(n, theta, i, g);
+    z[i] = 1.0;
+    double prev_s = INFINITY;
+    int grow = 0;
+    double d = 0.0, s = INFINITY;
+    for (int t = 1; t <= max_iter; ++t) {
+        d = map_once(A, theta, i, g, z, y, w);
+        double num = 0.0, den = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double e = w[j] - z[j];
+            num += e * e;
+            den += z[j] * z[j];
+        }
+        s = sqrt(num) / sqrt(den);
+        if (s <= tol) {               /* z passed the test: return it */
+            *lambda = theta[i] + d;
+            *status = OR_CONVERGED;
+            *sweeps = t;
+            *step = s;
+            return;
+        }
+        int finite = isfinite(s);
+        double dist2 = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double e = w[j] - (j == i ? 1.0 : 0.0);
+            if (!isfinite(w[j])) finite = 0;
+            dist2 += e * e;
+        }
+        grow = (s > prev_s) ? grow + 1 : 0;
+        prev_s = s;
+        memcpy(z, w, (size_t)n * sizeof(double));
+        if (!finite || !(sqrt(dist2) <= div_norm) || grow >= div_growth) {
+            *lambda = theta[i] + d;
+            *status = OR_DIVERGED;
+            *sweeps = t;
+            *step = s;
+            return;
+        }
+    }
+    *lambda = theta[i] + d;
+    *status = OR_NOT_CONVERGED;
+    *sweeps = max_iter;
+    *step = s;
+}
+
+/* rho = |M z - lambda z|_2 / |z|_2 with M z = theta o z + Delta z (plain definition). */
+static double eigen_residual(const op_t *A, const double *theta, const double *z, double lambda, double *y) {
+    const int64_t n = A->n;
+    op_apply(A, z, y);
+    double r2 = 0.0, z2 = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double r = theta[j] * z[j] + y[j] - lambda * z[j];
+        r2 += r * r;
+        z2 += z[j] * z[j];
+    }
+    return sqrt(r2) / sqrt(z2);
+}
+
+static int solve_columns(const op_t *A, const double *theta, int64_t k, const int32_t *idx,
+                         const double *z0, int64_t ldz0, double tol, int max_iter, double div_norm,
+                         int div_growth, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
+                         int32_t *sweeps_out, double *step_out, double *resid_out) {
+    const int64_t n = A->n;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc((size_t)n * 4 * sizeof(double));
+        if (!buf) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+            double *z = buf, *g = buf + n, *y = buf + 2 * n, *w = buf + 3 * n;
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t c = 0; c < k; ++c) {
+                const int64_t i = idx ? idx[c] : c;
+                for (int64_t j = 0; j < n; ++j) z[j] = z0 ? z0[j * ldz0 + c] : (j == i ? 1.0 : 0.0);
+                double lam, st;
+                int32_t stat, sw;
+                solve_column(A, theta, i, tol, max_iter, div_norm, div_growth, z, g, y, w, &lam, &stat, &sw, &st);
+                for (int64_t j = 0; j < n; ++j) z_out[j * ldz + c] = z[j];
+                lambda_out[c] = lam;
+                status_out[c] = stat;
+                if (sweeps_out) sweeps_out[c] = sw;
+                if (step_out) step_out[c] = st;
+                if (resid_out) resid_out[c] = eigen_residual(A, theta, z, lam, y);
+            }
+            free(buf);
+        }
+    }
+    return fail ? -1 : 0;
+}
+
+/* ---------------------------------------------------------------- public */
+
+void oracle_set_threads(int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Dense IPT on the requested columns.  Delta: n x n row-major (lda).  idx: k
+ * requested diagonal indices (NULL means 0..k-1).  z0: optional n x k row-major
+ * warm start (ldz0).  Outputs z_out (n x k row-major, ldz), lambda_out[k],
+ * status_out[k], and optional sweeps_out / step_out / resid_out. */
+int oracle_ipt_dense(int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                     const int32_t *idx, const double *z0, int64_t ldz0, double tol, int max_iter,
+                     double div_norm, int div_growth, double *z_out, int64_t ldz, double *lambda_out,
+                     int32_t *status_out, int32_t *sweeps_out, double *step_out, double *resid_out) {
+    op_t A = {n, delta, lda, NULL, NULL, NULL};
+    return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
+                         lambda_out, status_out, sweeps_out, step_out, resid_out);
+}
+
+/* Same with a CSR Delta (row_ptr[n+1], col[nnz], val[nnz]). */
+int oracle_ipt_csr(int64_t n, const double *theta, const int32_t *row_ptr, const int32_t *col,
+                   const double *val, int64_t k, const int32_t *idx, const double *z0, int64_t ldz0,
+                   double tol, int max_iter, double div_norm, int div_growth, double *z_out, int64_t ldz,
+                   double *lambda_out, int32_t *status_out, int32_t *sweeps_out, double *step_out,
+                   double *resid_out) {
+    op_t A = {n, NULL, 0, row_ptr, col, val};
+    return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
+                         lambda_out, status_out, sweeps_out, step_out, resid_out);
+}
+
+/* The iterates z^(0..t) of f_i from a start z (no stopping test): out is
+ * (t+1) x n row-major, out[0] = start with entry i set to 1. */
+int oracle_ipt_trace(int64_t n, const double *theta, const double *delta, int64_t lda, int64_t i,
+                     const double *z_start, int t, double *out) {
+    op_t A = {n, delta, lda, NULL, NULL, NULL};
+    double *g = (double *)malloc((size_t)n * 2 * sizeof(double));
+    if (!g) return -1;
+    double *y = g + n;
+    inverse_gaps(n, theta, i, g);
+    for (int64_t j = 0; j < n; ++j) out[j] = z_start ? z_start[j] : (j == i ? 1.0 : 0.0);
+    out[i] = 1.0;
+    for (int s = 1; s <= t; ++s) map_once(&A, theta, i, g, out + (int64_t)(s - 1) * n, y, out + (int64_t)s * n);
+    free(g);
+    return 0;
+}
+
+/* One application of f_i to z (dense Delta); returns d = (Delta z)_i. */
+double oracle_ipt_map(int64_t n, const double *theta, const double *delta, int64_t lda, int64_t i,
+                      const double *z, double *w) {
+    op_t A = {n, delta, lda, NULL, NULL, NULL};
+    double *g = (double *)malloc((size_t)n * 2 * sizeof(double));
+    if (!g) return NAN;
+    double *y = g + n;
+    inverse_gaps(n, theta, i, g);
+    const double d = map_once(&A, theta, i, g, z, y, w);
+    free(g);
+    return d;
+}
+
+/* Batched dense IPT: problem b has size ns[b], theta at theta_pool + theta_off[b],
+ * row-major Delta at delta_pool + delta_off[b], and its full spectrum is written to
+ * z_pool + z_off[b] (n_b x n_b row-major), lambda_pool + theta_off[b],
+ * status_pool + theta_off[b].  Problems are independent; this is a loop. */
+int oracle_ipt_batched(int32_t count, const int32_t *ns, const int64_t *theta_off, const int64_t *delta_off,
+                       const int64_t *z_off, const double *theta_pool, const double *delta_pool, double tol,
+                       int max_iter, double div_norm, int div_growth, double *z_pool, double *lambda_pool,
+                       int32_t *status_pool, int32_t *sweeps_pool) {
+    for (int32_t b = 0; b < count; ++b) {
+        const int64_t n = ns[b];
+        int rc = oracle_ipt_dense(n, theta_pool + theta_off[b], delta_pool + delta_off[b], n, n, NULL, NULL, 0, tol,
+                                  max_iter, div_norm, div_growth, z_pool + z_off[b], n, lambda_pool + theta_off[b],
+                                  status_pool + theta_off[b], sweeps_pool ? sweeps_pool + theta_off[b] : NULL, NULL,
+                                  NULL);
+        if (rc) return rc;
+    }
+    return 0;
+}
