@@ -1,0 +1,180 @@
+/*
+ * ipt.h -- C ABI of the MI355X (gfx950) Iterative Perturbation Theory eigensolver.
+ *
+ * The method (Kenmoe, Kriemann, Smerlak, Zadorin, "A fast iterative algorithm for
+ * near-diagonal eigenvalue problems"):
+ *   M = D + Delta with D diagonal, theta = diag(D) pairwise distinct (Sec. 3, the
+ *   partition; any split is allowed and Delta may have a non-zero diagonal).
+ *   G_jk = 1/(theta_j - theta_k) for j != k, G_jj = 0 (inverse gaps matrix).
+ *   For each requested index i = idx[c], column c of Z is iterated with
+ *     f_i(z) = e_i + g_i o (z (Delta z)_i - Delta z)          (eq. single_line_dyn)
+ *   i.e. all columns at once Z <- F(Z) = I + G o (Z D(Delta Z) - Delta Z)  (eq. dyn)
+ *   from Z = I (Alg. 1 / Alg. 2), until the per-column relative step
+ *   s_c = |F(Z)_c - Z_c|_2 / |Z_c|_2 is <= tol.  The returned eigenvector is the
+ *   iterate that passed the test (entry i equals 1, intermediate normalisation) and
+ *   lambda_c = (M Z)_ic = theta_i + (Delta Z)_ic from that same sweep (Alg. 1/2
+ *   return steps).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller (allocated with
+ *     hipMalloc or by PyTorch on the GPU), except where a parameter says "host".
+ *     The library never frees or retains caller memory past the call.
+ *   - Matrices are row-major: element (j, c) of an n x k matrix X with leading
+ *     dimension ldx is X[j*ldx + c].
+ *   - Work is ordered on the handle's stream.  A solve call returns when its
+ *     outputs are written (it waits on the stream for the stop decision), so the
+ *     outputs are ready on return.  One handle per stream; a handle is not
+ *     thread-safe.  Handles may be created on any device; a handle uses the device
+ *     that was current at ipt_create.
+ *   - Errors are returned as ipt_status, never by aborting.  ipt_last_error gives
+ *     a human-readable message for the last failing call on a handle.  On
+ *     IPT_EINVAL, IPT_EDEGENERATE, IPT_ENOMEM and IPT_EHIP the output arrays are
+ *     unspecified.  IPT_ENOTCONV means every output is written and some column's
+ *     status is not IPT_CONVERGED.
+ */
+#ifndef IPT_H
+#define IPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ipt_status {
+    IPT_OK = 0,
+    IPT_EINVAL = 1,      /* bad sizes, pointers, indices or options; non-finite theta */
+    IPT_EDEGENERATE = 2, /* theta_j == theta_idx[c] for some j != idx[c]: G undefined (Sec. 3) */
+    IPT_ENOTCONV = 3,    /* outputs written, some column NOT_CONVERGED or DIVERGED */
+    IPT_EHIP = 4,        /* a HIP runtime call failed */
+    IPT_ENOMEM = 5       /* workspace allocation failed */
+} ipt_status;
+
+/* Per-column status written to col_status[c]. */
+enum { IPT_CONVERGED = 0, IPT_NOT_CONVERGED = 1, IPT_DIVERGED = 2 };
+
+/* Arithmetic of the product Delta x Z in a sweep. */
+enum {
+    IPT_PREC_FP64 = 0,   /* every product in FP64 (plain IPT) */
+    IPT_PREC_LADDER = 1  /* low precision -> FP32 -> FP64; only FP64 sweeps may certify */
+};
+/* Low rung of the ladder. */
+enum { IPT_LOW_BF16 = 0, IPT_LOW_FP16 = 1, IPT_LOW_NONE = 2 /* start the ladder at FP32 */ };
+
+/* Precision tags recorded per sweep in ipt_info.sweep_prec. */
+enum { IPT_SWEEP_EXACT_FIRST = 0, IPT_SWEEP_LOW = 1, IPT_SWEEP_FP32 = 2, IPT_SWEEP_FP64 = 3 };
+
+typedef struct ipt_opts {
+    double tol;         /* eta of the stopping test (per-column relative step); default 1e-10 */
+    int32_t max_iter;   /* maximum sweeps; default 100; 1 <= max_iter <= 100000 */
+    int32_t precision;  /* IPT_PREC_FP64 (default) or IPT_PREC_LADDER */
+    int32_t low_type;   /* IPT_LOW_BF16 (default), IPT_LOW_FP16 or IPT_LOW_NONE */
+    int32_t sync_every; /* sweeps launched between host checks of the device stop flag; 0 = auto */
+    double tau_low;     /* ladder: leave the low rung once max step <= tau_low; default 1e-5 */
+    double tau_32;      /* ladder: leave FP32 once max step <= tau_32; default 1e-9 */
+    double div_norm;    /* DIVERGED when |f_i(z) - e_i|_2 > div_norm; default 1e3 */
+    int32_t div_growth; /* DIVERGED when s grew on this many consecutive FP64 sweeps; default 8 */
+    int32_t flags;      /* bit 0 (IPT_FLAG_NO_NORM): skip |M|_1 and report resid unnormalised */
+} ipt_opts;
+
+#define IPT_FLAG_NO_NORM 1
+#define IPT_HIST 128
+
+/* Host struct filled by a solve (may be NULL). */
+typedef struct ipt_info {
+    int32_t sweeps;        /* sweeps executed (applications of F) */
+    int32_t converged;     /* columns CONVERGED */
+    int32_t not_converged; /* columns NOT_CONVERGED */
+    int32_t diverged;      /* columns DIVERGED */
+    int64_t matvecs;       /* sum over sweeps of the columns multiplied by Delta */
+    double max_step;       /* max over columns of the deciding step s_c */
+    double norm1;          /* |M|_1 = max column sum of |D + Delta| (0 if IPT_FLAG_NO_NORM) */
+    double max_resid;      /* max over CONVERGED columns of |M z - lambda z|_2 / (|M|_1 |z|_2) */
+    float time_ms;         /* device time of the solve, from the first kernel to the outputs */
+    int32_t hist_len;      /* entries used in the per-sweep arrays below (min(sweeps, IPT_HIST)) */
+    int32_t sweep_prec[IPT_HIST];     /* IPT_SWEEP_* of each sweep */
+    int32_t sweep_active[IPT_HIST];   /* active columns entering each sweep */
+    double sweep_max_step[IPT_HIST];  /* max s_c over the active columns of each sweep */
+} ipt_info;
+
+/* Optional per-column device outputs (any member may be NULL). */
+typedef struct ipt_colinfo {
+    int32_t *sweeps; /* [k] sweep at which the column's status was decided */
+    double *step;    /* [k] s_c of the deciding sweep */
+    double *resid;   /* [k] |M z_c - lambda_c z_c|_2 / (|M|_1 |z_c|_2), from F(Z) - Z = -G o (MZ - Z Lambda) */
+} ipt_colinfo;
+
+typedef struct ipt_context *ipt_handle;
+
+/* Fill *o with the defaults listed in ipt_opts. */
+void ipt_opts_default(ipt_opts *o);
+
+/* Create a handle bound to the current device and to `stream` (a hipStream_t; NULL
+ * is the null stream).  The handle owns a workspace that grows on demand and is
+ * released by ipt_destroy.  Errors: IPT_EINVAL (h NULL), IPT_EHIP, IPT_ENOMEM. */
+ipt_status ipt_create(ipt_handle *h, void *stream);
+ipt_status ipt_destroy(ipt_handle h);
+/* Rebind the handle to another stream on the same device. */
+ipt_status ipt_set_stream(ipt_handle h, void *stream);
+
+/*
+ * Dense solve (Alg. 1 on the requested columns; Alg. 2 when idx covers 0..n-1).
+ *   n          problem size, 1 <= n <= 2^20
+ *   theta      [n] FP64, the diagonal of D; must be finite
+ *   delta      n x n FP64 row-major, leading dimension lda >= n
+ *   k          number of requested columns, 1 <= k <= n
+ *   idx        [k] int32 distinct indices in [0, n); NULL means idx[c] = c (then any k <= n)
+ *   z0         optional n x k FP64 warm start (leading dimension ldz0 >= k); NULL = cold start
+ *              from Z = I (the first sweep is then computed without a product, since
+ *              F(I) = I - G o Delta restricted to the requested columns).  Entry idx[c]
+ *              of column c is taken as 1 whatever z0 holds there (chart z_i = 1, Sec. 2).
+ *   opts       host struct, NULL for defaults
+ *   z_out      n x k FP64 row-major output (leading dimension ldz >= k); may not alias inputs
+ *   lambda_out [k] FP64 eigenvalues; col_status [k] int32 IPT_CONVERGED/NOT_CONVERGED/DIVERGED
+ *   info       optional host struct; ci optional per-column device outputs
+ * A CONVERGED column holds the certified iterate and lambda from the same sweep.
+ * NOT_CONVERGED / DIVERGED columns hold the last computed iterate and the lambda
+ * estimate of the last sweep.  Returns IPT_OK, IPT_ENOTCONV, IPT_EINVAL,
+ * IPT_EDEGENERATE, IPT_ENOMEM or IPT_EHIP.
+ */
+ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda,
+                           int64_t k, const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts *opts,
+                           double *z_out, int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info,
+                           const ipt_colinfo *ci);
+
+/*
+ * Sparse solve with Delta in CSR form (few eigenpairs of a sparse near-diagonal M,
+ * Sec. 6.1): row_ptr [n+1] int32 (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz),
+ * col [nnz] int32 in [0, n), val [nnz] FP64.  Duplicate entries are summed.  Other
+ * arguments as for ipt_solve_dense.  The precision ladder uses FP32 then FP64.
+ */
+ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int32_t *row_ptr, const int32_t *col,
+                         const double *val, int64_t nnz, int64_t k, const int32_t *idx, const double *z0,
+                         int64_t ldz0, const ipt_opts *opts, double *z_out, int64_t ldz, double *lambda_out,
+                         int32_t *col_status, ipt_info *info, const ipt_colinfo *ci);
+
+/*
+ * Batched full-spectrum solve of `count` independent dense problems of uneven size.
+ *   ns, theta_off, delta_off, z_off   HOST arrays [count]: size n_b (1 <= n_b <= 4096) and the
+ *                                     element offsets of problem b in the pools
+ *   theta_pool   FP64 device pool; theta of problem b at theta_pool + theta_off[b] ([n_b])
+ *   delta_pool   FP64 device pool; row-major n_b x n_b Delta at delta_pool + delta_off[b]
+ *   z_pool       FP64 device pool; row-major n_b x n_b output at z_pool + z_off[b]
+ *   lambda_pool, status_pool   outputs at + theta_off[b] ([n_b] each)
+ * Every problem is solved for its full spectrum with the same options; info
+ * aggregates over the whole batch.
+ */
+ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
+                             const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
+                             const double *delta_pool, const ipt_opts *opts, double *z_pool, double *lambda_pool,
+                             int32_t *status_pool, ipt_info *info);
+
+/* Static description of a status code. */
+const char *ipt_status_string(ipt_status s);
+/* Message of the last failing call on h ("" if none); valid until the next call on h. */
+const char *ipt_last_error(ipt_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPT_H */

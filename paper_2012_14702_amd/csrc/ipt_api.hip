@@ -1,0 +1,373 @@
+// C ABI of the IPT library: handles, argument checks, workspace, and the host loop
+// that launches the sweeps of Alg. 1 / Alg. 2 on one stream.  Every step of a
+// sweep runs in the device kernels; the host only launches and, every
+// sync_every sweeps, reads the device stop flag.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "ipt_internal.h"
+
+using namespace ipt;
+
+struct ipt_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    Ctrl *host_ctrl = nullptr;  // pinned copy of the control block
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    std::string last_error;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) changed = (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+ipt_status fail(ipt_handle h, ipt_status st, const std::string &msg) {
+    if (h) h->last_error = msg;
+    return st;
+}
+
+#define IPT_HIP(h, expr)                                                                              \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess) return fail((h), IPT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Bump allocator over the handle's workspace (256-byte aligned slices).
+struct Carve {
+    size_t off = 0;
+    char *base = nullptr;
+    template <typename T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+ipt_status ensure_ws(ipt_handle h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return IPT_OK;
+    IPT_HIP(h, hipStreamSynchronize(h->stream));
+    if (h->ws) IPT_HIP(h, hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+    size_t want = bytes + bytes / 8;  // head-room for slightly larger follow-up solves
+    hipError_t e = hipMalloc(&h->ws, want);
+    if (e != hipSuccess) {
+        want = bytes;
+        e = hipMalloc(&h->ws, want);
+    }
+    if (e != hipSuccess) {
+        h->ws = nullptr;
+        (void)hipGetLastError();
+        return fail(h, IPT_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    h->ws_bytes = want;
+    return IPT_OK;
+}
+
+ipt_status check_opts(ipt_handle h, const ipt_opts *in, ipt_opts &o) {
+    ipt_opts_default(&o);
+    if (in) o = *in;
+    if (!(o.tol >= 0.0) || !isfinite(o.tol)) return fail(h, IPT_EINVAL, "opts.tol must be finite and >= 0");
+    if (o.max_iter < 1 || o.max_iter > 100000) return fail(h, IPT_EINVAL, "opts.max_iter must be in [1, 100000]");
+    if (o.precision != IPT_PREC_FP64 && o.precision != IPT_PREC_LADDER)
+        return fail(h, IPT_EINVAL, "opts.precision must be IPT_PREC_FP64 or IPT_PREC_LADDER");
+    if (o.low_type < IPT_LOW_BF16 || o.low_type > IPT_LOW_NONE) return fail(h, IPT_EINVAL, "opts.low_type invalid");
+    if (o.sync_every < 0) return fail(h, IPT_EINVAL, "opts.sync_every must be >= 0");
+    if (!(o.div_norm > 0.0)) return fail(h, IPT_EINVAL, "opts.div_norm must be > 0");
+    if (o.div_growth < 1) return fail(h, IPT_EINVAL, "opts.div_growth must be >= 1");
+    if (!(o.tau_low >= 0.0) || !(o.tau_32 >= 0.0)) return fail(h, IPT_EINVAL, "opts.tau_low/tau_32 must be >= 0");
+    return IPT_OK;
+}
+
+DevOpts dev_opts(const ipt_opts &o) {
+    DevOpts d;
+    d.tol = o.tol;
+    d.tau_low = o.tau_low;
+    d.tau_32 = o.tau_32;
+    d.div_norm = o.div_norm;
+    d.max_iter = o.max_iter;
+    d.div_growth = o.div_growth;
+    d.ladder = o.precision == IPT_PREC_LADDER;
+    d.low_type = o.low_type;
+    return d;
+}
+
+void fill_info(const Ctrl &c, ipt_info *info, float ms) {
+    if (!info) return;
+    memset(info, 0, sizeof(*info));
+    info->sweeps = c.sweeps;
+    info->converged = c.n_conv;
+    info->not_converged = c.n_notconv;
+    info->diverged = c.n_div;
+    info->matvecs = c.matvecs;
+    uint64_t b;
+    double v;
+    b = c.dec_maxstep;
+    memcpy(&v, &b, 8);
+    info->max_step = v;
+    b = c.norm1_bits;
+    memcpy(&v, &b, 8);
+    info->norm1 = v;
+    b = c.acc_maxres;
+    memcpy(&v, &b, 8);
+    info->max_resid = v;
+    info->time_ms = ms;
+    info->hist_len = c.sweeps < IPT_HIST ? c.sweeps : IPT_HIST;
+    for (int q = 0; q < info->hist_len; ++q) {
+        info->sweep_prec[q] = c.hist_prec[q];
+        info->sweep_active[q] = c.hist_active[q];
+        info->sweep_max_step[q] = c.hist_step[q];
+    }
+}
+
+// Reads the error/done words of the control block (one small copy and a wait).
+ipt_status poll_ctrl(ipt_handle h, Ctrl *dev, int32_t &error, int32_t &done) {
+    IPT_HIP(h, hipMemcpyAsync(h->host_ctrl, dev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    IPT_HIP(h, hipStreamSynchronize(h->stream));
+    error = h->host_ctrl->error;
+    done = h->host_ctrl->done;
+    return IPT_OK;
+}
+
+ipt_status finish(ipt_handle h, Ctrl *dev, int64_t k, ipt_info *info) {
+    IPT_HIP(h, hipEventRecord(h->ev_stop, h->stream));
+    IPT_HIP(h, hipMemcpyAsync(h->host_ctrl, dev, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+    IPT_HIP(h, hipStreamSynchronize(h->stream));
+    float ms = 0.f;
+    IPT_HIP(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
+    const Ctrl &c = *h->host_ctrl;
+    if (c.error == IPT_EDEGENERATE)
+        return fail(h, IPT_EDEGENERATE, "theta_j == theta_idx[c] for some j != idx[c]: inverse gap undefined");
+    if (c.error) return fail(h, IPT_EINVAL, "idx out of range or repeated, or theta not finite");
+    fill_info(c, info, ms);
+    if (c.n_conv == k) return IPT_OK;
+    h->last_error = "some columns did not converge";
+    return IPT_ENOTCONV;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ipt_opts_default(ipt_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->tol = 1e-10;
+    o->max_iter = 100;
+    o->precision = IPT_PREC_FP64;
+    o->low_type = IPT_LOW_BF16;
+    o->sync_every = 0;
+    o->tau_low = 1e-5;
+    o->tau_32 = 1e-9;
+    o->div_norm = 1e3;
+    o->div_growth = 8;
+    o->flags = 0;
+}
+
+ipt_status ipt_create(ipt_handle *out, void *stream) {
+    if (!out) return IPT_EINVAL;
+    *out = nullptr;
+    ipt_context *h = new (std::nothrow) ipt_context();
+    if (!h) return IPT_ENOMEM;
+    if (hipGetDevice(&h->device) != hipSuccess || hipEventCreate(&h->ev_start) != hipSuccess ||
+        hipEventCreate(&h->ev_stop) != hipSuccess) {
+        delete h;
+        return IPT_EHIP;
+    }
+    if (hipHostMalloc((void **)&h->host_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+        (void)hipEventDestroy(h->ev_start);
+        (void)hipEventDestroy(h->ev_stop);
+        delete h;
+        return IPT_ENOMEM;
+    }
+    h->stream = (hipStream_t)stream;
+    *out = h;
+    return IPT_OK;
+}
+
+ipt_status ipt_destroy(ipt_handle h) {
+    if (!h) return IPT_EINVAL;
+    DeviceGuard g(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->host_ctrl) (void)hipHostFree(h->host_ctrl);
+    (void)hipEventDestroy(h->ev_start);
+    (void)hipEventDestroy(h->ev_stop);
+    delete h;
+    return IPT_OK;
+}
+
+ipt_status ipt_set_stream(ipt_handle h, void *stream) {
+    if (!h) return IPT_EINVAL;
+    h->stream = (hipStream_t)stream;
+    return IPT_OK;
+}
+
+const char *ipt_status_string(ipt_status s) {
+    switch (s) {
+        case IPT_OK: return "IPT_OK";
+        case IPT_EINVAL: return "IPT_EINVAL: invalid argument";
+        case IPT_EDEGENERATE: return "IPT_EDEGENERATE: repeated unperturbed eigenvalue, inverse gap undefined";
+        case IPT_ENOTCONV: return "IPT_ENOTCONV: some columns did not converge";
+        case IPT_EHIP: return "IPT_EHIP: HIP runtime error";
+        case IPT_ENOMEM: return "IPT_ENOMEM: out of device memory";
+    }
+    return "unknown ipt_status";
+}
+
+const char *ipt_last_error(ipt_handle h) { return h ? h->last_error.c_str() : "invalid handle"; }
+
+ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                           const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts *opts, double *z_out,
+                           int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info,
+                           const ipt_colinfo *ci) {
+    if (!h) return IPT_EINVAL;
+    h->last_error.clear();
+    if (n < 1 || n > (int64_t(1) << 20)) return fail(h, IPT_EINVAL, "n must be in [1, 2^20]");
+    if (k < 1 || k > n) return fail(h, IPT_EINVAL, "k must be in [1, n]");
+    if (lda < n) return fail(h, IPT_EINVAL, "lda must be >= n");
+    if (ldz < k) return fail(h, IPT_EINVAL, "ldz must be >= k");
+    if (z0 && ldz0 < k) return fail(h, IPT_EINVAL, "ldz0 must be >= k");
+    if (!theta || !delta || !z_out || !lambda_out || !col_status)
+        return fail(h, IPT_EINVAL, "theta, delta, z_out, lambda_out and col_status must be non-NULL");
+    ipt_opts o;
+    if (ipt_status st = check_opts(h, opts, o)) return st;
+    const DevOpts dopt = dev_opts(o);
+    const bool ladder = dopt.ladder;
+    const bool cold = (z0 == nullptr);
+    DeviceGuard guard(h->device);
+    hipStream_t s = h->stream;
+
+    const int64_t np = round_up(n, TILE_M), kp = round_up(k, TILE_N);
+    const int64_t nrt = np / TILE_M, ntn = kp / TILE_N;
+    const bool direct = (n % TILE_M == 0) && (lda % 2 == 0) && (((uintptr_t)delta & 15) == 0);
+    const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
+    const int32_t lt = (o.low_type == IPT_LOW_FP16) ? LT_F16 : LT_BF16;
+    const bool use_low = ladder && o.low_type != IPT_LOW_NONE;
+
+    // Workspace layout (sizes first, then carve).
+    auto layout = [&](Carve &cv, double **zb, ColState &cs, double **dpart, double **part, uint32_t **bitmap,
+                      double **scratch, double **dpad, void **dlo, float **d32, void **zt, Ctrl **ctrl) {
+        zb[0] = cv.take<double>(np * kp);
+        zb[1] = cv.take<double>(np * kp);
+        *dpart = cv.take<double>(DIAG_SPLIT * kp);
+        *part = cv.take<double>(nrt * kp * NPART);
+        cs.state = cv.take<int32_t>(kp);
+        cs.sweeps = cv.take<int32_t>(kp);
+        cs.grow = cv.take<int32_t>(kp);
+        cs.par = cv.take<int32_t>(kp);
+        cs.idx = cv.take<int32_t>(kp);
+        cs.tile_stamp = cv.take<int32_t>(ntn < kp ? kp : ntn);
+        cs.prev = cv.take<double>(kp);
+        cs.step = cv.take<double>(kp);
+        cs.lam = cv.take<double>(kp);
+        cs.resid = cv.take<double>(kp);
+        *bitmap = cv.take<uint32_t>((n + 31) / 32);
+        *scratch = norm ? cv.take<double>(64 * n > 2 * n ? 64 * n : 2 * n) : nullptr;
+        *dpad = direct ? nullptr : cv.take<double>(np * np);
+        *dlo = use_low ? (void *)cv.take<uint16_t>(np * np) : nullptr;
+        *d32 = ladder ? cv.take<float>(np * np) : nullptr;
+        *zt = ladder ? (void *)cv.take<float>(kp * np) : nullptr;
+        *ctrl = cv.take<Ctrl>(1);
+    };
+    double *zb[2];
+    ColState cs;
+    double *dpart, *part, *scratch, *dpad;
+    uint32_t *bitmap;
+    void *dlo, *zt;
+    float *d32;
+    Ctrl *ctrl;
+    Carve sizing;
+    layout(sizing, zb, cs, &dpart, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
+    if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
+    Carve cv;
+    cv.base = (char *)h->ws;
+    layout(cv, zb, cs, &dpart, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
+
+    IPT_HIP(h, hipEventRecord(h->ev_start, s));
+    const int32_t start_prec = cold ? PREC_EXACT_FIRST : (ladder ? PREC_F32 : PREC_F64);
+    IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kp, bitmap, start_prec, (int32_t)ntn, 0));
+    IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
+    if (norm) IPT_HIP(h, launch_norm1_dense(s, ctrl, theta, delta, lda, n, scratch));
+    const double *dA = delta;
+    int64_t ldA = lda;
+    if (!direct) {
+        IPT_HIP(h, launch_copy_pad(s, delta, lda, dpad, np, n, np));
+        dA = dpad;
+        ldA = np;
+    }
+    if (ladder) {
+        if (use_low && lt == LT_F16) IPT_HIP(h, launch_absmax(s, ctrl, dA, n, n, ldA));
+        if (use_low) IPT_HIP(h, launch_cast_delta(s, ctrl, dA, ldA, dlo, np, n, np, lt));
+        IPT_HIP(h, launch_cast_delta(s, ctrl, dA, ldA, d32, np, n, np, LT_F32));
+    }
+    if (cold) {
+        IPT_HIP(h, launch_zero_pad(s, zb[0], kp, n, np, k, kp));
+    } else {
+        IPT_HIP(h, launch_load_z0(s, ctrl, z0, ldz0, zb[0], kp, cs.idx, n, np, k, kp));
+        IPT_HIP(h, launch_zero_pad(s, zb[1], kp, n, np, k, kp));
+    }
+
+    const int sync_every = o.sync_every > 0 ? o.sync_every : 1;
+    for (int32_t t = 1; t <= o.max_iter; ++t) {
+        const bool first_exact = cold && t == 1;
+        const int32_t in_par = first_exact ? PAR_UNIT : ((t - 1) & 1);
+        const int32_t out_par = t & 1;
+        double *zin = zb[(t - 1) & 1], *zout = zb[t & 1];
+        if (first_exact) {
+            IPT_HIP(h, launch_sweep1_dense(s, ctrl, theta, dA, ldA, cs, dpart, zout, kp, part, n, np, kp));
+        } else {
+            if (ladder) {
+                if (use_low) IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, lt, PREC_LOW));
+                IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, LT_F32, PREC_F32));
+            }
+            IPT_HIP(h, launch_diag_dense(s, ctrl, dA, ldA, zin, kp, cs, dpart, n, kp));
+            if (ladder) {
+                if (use_low)
+                    IPT_HIP(h, launch_gemm_low(s, ctrl, PREC_LOW, dlo, np, zt, np, dA, ldA, zin, zout, kp, theta, cs,
+                                               dpart, part, n, np, kp, t, lt));
+                IPT_HIP(h, launch_gemm_low(s, ctrl, PREC_F32, d32, np, zt, np, dA, ldA, zin, zout, kp, theta, cs,
+                                           dpart, part, n, np, kp, t, LT_F32));
+            }
+            IPT_HIP(h, launch_gemm_f64(s, ctrl, dA, ldA, zin, zout, kp, theta, cs, dpart, part, n, np, kp, t));
+        }
+        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dpart, theta, part, nrt, kp, t, in_par, out_par));
+        IPT_HIP(h, launch_control(s, ctrl, dopt, t));
+        if (t % sync_every == 0 || t == o.max_iter) {
+            int32_t err, done;
+            if (ipt_status st = poll_ctrl(h, ctrl, err, done)) return st;
+            if (err || done) break;
+        }
+    }
+    IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lambda_out, col_status, n, k, ci));
+    return finish(h, ctrl, k, info);
+}
+
+ipt_status ipt_solve_csr(ipt_handle h, int64_t, const double *, const int32_t *, const int32_t *, const double *,
+                         int64_t, int64_t, const int32_t *, const double *, int64_t, const ipt_opts *, double *, int64_t,
+                         double *, int32_t *, ipt_info *, const ipt_colinfo *) {
+    return fail(h, IPT_EINVAL, "sparse path not built yet");
+}
+
+ipt_status ipt_solve_batched(ipt_handle h, int32_t, const int32_t *, const int64_t *, const int64_t *, const int64_t *,
+                             const double *, const double *, const ipt_opts *, double *, double *, int32_t *,
+                             ipt_info *) {
+    return fail(h, IPT_EINVAL, "batched path not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,381 @@
+// The product Y = Delta Z of an IPT sweep on the gfx950 matrix cores, with the rest
+// of the sweep fused into the epilogue:
+//   W_jc = (Z_jc d_c - Y_jc) / (theta_j - theta_i)  (j != i),  W_ic = 1      (eq. dyn)
+// plus the per-column partial sums of |W - Z|^2, |Z|^2, |(theta_j - theta_i)(W - Z)|^2
+// and |W - e_i|^2 over each 128-row tile (reduced in a fixed order by the finalize
+// kernel).  By F(Z) - Z = -G o (M Z - Z Lambda), the third sum is the squared
+// eigen-residual |M z - lambda z|^2 of the column.
+//
+// Two kernels:
+//  * FP64: v_mfma_f64_16x16x4f64, 128x128 block tile, 4 waves of 64x64, BK = 16,
+//    double-buffered LDS.  Delta (padded to a multiple of 128) and Z are read in place.
+//  * low precision (BF16 / FP16 with v_mfma_f32_16x16x32_*, FP32 with
+//    v_mfma_f32_16x16x4f32), FP32 accumulation, "NT" operands: Delta_lo row-major and
+//    the transposed shadow of the split iterate Z - E.  The epilogue adds back
+//    Delta E exactly in FP64 (Y = Delta[:, i] + Delta_lo (Z - E)_lo), so only the small
+//    correction Z - E sees low precision.
+#include <math.h>
+
+#include "ipt_internal.h"
+
+namespace ipt {
+
+namespace {
+
+constexpr int kDiagSplit = DIAG_SPLIT;
+constexpr int BM = TILE_M, BN = TILE_N;
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+
+// Block -> (row tile, column tile).  Workgroups are dispatched round-robin over the
+// 8 XCDs; consecutive block ids are first regrouped per XCD so that each XCD works
+// on a compact patch of tiles (8 row tiles wide) sharing Delta rows and Z columns
+// in its own L2.
+__device__ inline void tile_of(int bid, int nblocks, int ntm, int ntn, int &tm, int &tn) {
+    const int full = nblocks & ~7;
+    int pid = bid;
+    if (bid < full) pid = (bid & 7) * (full >> 3) + (bid >> 3);
+    constexpr int GM = 8;
+    const int per_group = GM * ntn;
+    const int group = pid / per_group;
+    const int first_m = group * GM;
+    const int gsz = (ntm - first_m) < GM ? (ntm - first_m) : GM;
+    const int in = pid - group * per_group;
+    tm = first_m + in % gsz;
+    tn = in / gsz;
+}
+
+// Shared epilogue.  Each lane holds 4 column blocks (jb) x 16 rows of the block
+// tile; row_of(ib, r) gives the tile row of accumulator (ib, r), which depends on
+// the MFMA family.  y_of(ib, jb, r, j, i) returns the FP64 product value.
+struct EpiCtx {
+    const double *theta;
+    const double *zin;
+    double *zout;
+    int64_t ldzb;
+    ColState cs;
+    const double *dpart;
+    double *part;
+    int64_t n, kp;
+};
+
+template <class RowOf, class YOf>
+__device__ inline void sweep_epilogue(const EpiCtx &e, int tm, int tn, int wm, int wn, int lane, RowOf row_of,
+                                      YOf y_of, double (*red)[BN][NPART]) {
+    int64_t cols[4];
+    int32_t ii[4];
+    double ti[4], dd[4];
+    bool act[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        const int64_t c = (int64_t)tn * BN + wn * 64 + 16 * jb + (lane & 15);
+        cols[jb] = c;
+        act[jb] = e.cs.state[c] == COL_ACTIVE;
+        ii[jb] = e.cs.idx[c];
+        ti[jb] = e.theta[ii[jb]];
+        double d = 0.0;
+        for (int s = 0; s < kDiagSplit; ++s) d += e.dpart[(int64_t)s * e.kp + c];
+        dd[jb] = d;
+    }
+    double sums[4][NPART];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) sums[jb][q] = 0.0;
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t j = (int64_t)tm * BM + wm * 64 + row_of(ib, r, lane);
+            if (j >= e.n) continue;
+            const double tj = e.theta[j];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                if (!act[jb]) continue;
+                const int64_t c = cols[jb];
+                const double z = e.zin[j * e.ldzb + c];
+                double w, st, gs, de;
+                if (j == ii[jb]) {
+                    w = 1.0;
+                    st = w - z;
+                    gs = 0.0;
+                    de = 0.0;
+                } else {
+                    const double y = y_of(ib, jb, r, j, ii[jb]);
+                    const double gap = tj - ti[jb];
+                    w = (z * dd[jb] - y) / gap;
+                    st = w - z;
+                    gs = gap * st;
+                    de = w;
+                }
+                e.zout[j * e.ldzb + c] = w;
+                sums[jb][0] += st * st;
+                sums[jb][1] += z * z;
+                sums[jb][2] += gs * gs;
+                sums[jb][3] += de * de;
+            }
+        }
+    }
+    // Reduce over the 4 lane groups holding the same columns (fixed pattern), then
+    // over the two waves that share the column block, in a fixed order.
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) {
+            double v = sums[jb][q];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            sums[jb][q] = v;
+        }
+    if (lane < 16) {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int q = 0; q < NPART; ++q) red[wm][wn * 64 + 16 * jb + lane][q] = sums[jb][q];
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < BN) {
+        const int64_t c = (int64_t)tn * BN + t;
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) e.part[((int64_t)tm * e.kp + c) * NPART + q] = red[0][t][q] + red[1][t][q];
+    }
+}
+
+// ------------------------------------------------------------------- FP64
+constexpr int BK64 = 16;
+
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(const Ctrl *ctrl, const double *__restrict__ delta, int64_t lda,
+                                                     const double *__restrict__ zin, double *__restrict__ zout,
+                                                     int64_t ldzb, const double *__restrict__ theta, ColState cs,
+                                                     const double *__restrict__ dpart, double *__restrict__ part,
+                                                     int64_t n, int64_t np, int64_t kp, int32_t sweep) {
+    if (ctrl->error || ctrl->done || ctrl->prec != PREC_F64) return;
+    const int ntm = (int)(np / BM), ntn = (int)(kp / BN);
+    int tm, tn;
+    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
+    if (cs.tile_stamp[tn] != sweep - 1) return;  // no active column in this column tile
+
+    __shared__ double As[2][BM][BK64 + 1];
+    __shared__ double Bs[2][BK64][BN];
+    __shared__ double red[2][BN][NPART];
+
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
+    const double *Ab = delta + (int64_t)tm * BM * lda;
+    const double *Bb = zin + (int64_t)tn * BN;
+    const int a_r = t >> 3, a_k = 2 * (t & 7);
+    const int b_r = t >> 4, b_c = (t & 15) * 8;
+
+    double2 ra[4], rb[4];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[q] = *(const double2 *)(Ab + (int64_t)(a_r + 32 * q) * lda + k0 + a_k);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rb[q] = *(const double2 *)(Bb + (k0 + b_r) * ldzb + b_c + 2 * q);
+    };
+    auto sstore = [&](int s) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[s][a_r + 32 * q][a_k] = ra[q].x;
+            As[s][a_r + 32 * q][a_k + 1] = ra[q].y;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(double2 *)&Bs[s][b_r][b_c + 2 * q] = rb[q];
+    };
+
+    d4_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    const int nk = (int)(np / BK64);
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK64);
+#pragma unroll
+        for (int kk = 0; kk < BK64 / 4; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) a[ib] = As[cur][wm * 64 + 16 * ib + (lane & 15)][4 * kk + (lane >> 4)];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) b[jb] = Bs[cur][4 * kk + (lane >> 4)][wn * 64 + 16 * jb + (lane & 15)];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ib], b[jb], acc[ib][jb], 0, 0, 0);
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+
+    EpiCtx e{theta, zin, zout, ldzb, cs, dpart, part, n, kp};
+    // v_mfma_f64_16x16x4f64: lane l, register r holds row 4r + l/16, column l%16.
+    auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * r + (l >> 4); };
+    auto y_of = [&](int ib, int jb, int r, int64_t, int32_t) { return acc[ib][jb][r]; };
+    sweep_epilogue(e, tm, tn, wm, wn, lane, row_of, y_of, red);
+}
+
+// ------------------------------------------------------------ low precision
+template <typename T>
+struct LowCfg;
+template <>
+struct LowCfg<__bf16> {
+    static constexpr int BK = 64, KSTEP = 32, VEC = 8, PAD = 8;
+};
+template <>
+struct LowCfg<_Float16> {
+    static constexpr int BK = 64, KSTEP = 32, VEC = 8, PAD = 8;
+};
+template <>
+struct LowCfg<float> {
+    static constexpr int BK = 32, KSTEP = 4, VEC = 1, PAD = 1;
+};
+
+template <typename T>
+__device__ inline f4_t mfma_low(const T *a, const T *b, f4_t c);
+template <>
+__device__ inline f4_t mfma_low<__bf16>(const __bf16 *a, const __bf16 *b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf8_t *)a, *(const bf8_t *)b, c, 0, 0, 0);
+}
+template <>
+__device__ inline f4_t mfma_low<_Float16>(const _Float16 *a, const _Float16 *b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(*(const h8_t *)a, *(const h8_t *)b, c, 0, 0, 0);
+}
+template <>
+__device__ inline f4_t mfma_low<float>(const float *a, const float *b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_gemm_low(const Ctrl *ctrl, int32_t want_prec, const T *__restrict__ dlo,
+                                                     int64_t ldd, const T *__restrict__ zt, int64_t ldt,
+                                                     const double *__restrict__ delta, int64_t lda,
+                                                     const double *__restrict__ zin, double *__restrict__ zout,
+                                                     int64_t ldzb, const double *__restrict__ theta, ColState cs,
+                                                     const double *__restrict__ dpart, double *__restrict__ part,
+                                                     int64_t n, int64_t np, int64_t kp, int32_t sweep,
+                                                     bool scaled) {
+    if (ctrl->error || ctrl->done || ctrl->prec != want_prec) return;
+    const double unscale = scaled ? 1.0 / (ctrl->dscale * ctrl->zscale) : 1.0;
+    using C = LowCfg<T>;
+    constexpr int BK = C::BK, LDP = C::BK + C::PAD;
+    const int ntm = (int)(np / BM), ntn = (int)(kp / BN);
+    int tm, tn;
+    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
+    if (cs.tile_stamp[tn] != sweep - 1) return;
+
+    __shared__ __attribute__((aligned(16))) T As[2][BM][LDP];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BN][LDP];
+    __shared__ double red[2][BN][NPART];
+
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
+    // Each block row of BK elements is 128 bytes = 8 chunks of 16 bytes; 256 threads
+    // move 4 rows' worth of chunks per pass, 4 passes cover 128 rows.
+    constexpr int EPC = 16 / sizeof(T);  // elements per 16-byte chunk
+    const int l_r = t >> 3, l_c = (t & 7) * EPC;
+    const T *Ab = dlo + (int64_t)tm * BM * ldd;
+    const T *Bb = zt + (int64_t)tn * BN * ldt;
+    uint4 ra[4], rb[4];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[q] = *(const uint4 *)(Ab + (int64_t)(l_r + 32 * q) * ldd + k0 + l_c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rb[q] = *(const uint4 *)(Bb + (int64_t)(l_r + 32 * q) * ldt + k0 + l_c);
+    };
+    auto sstore = [&](int s) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if constexpr (C::PAD % EPC == 0) {
+                *(uint4 *)&As[s][l_r + 32 * q][l_c] = ra[q];
+                *(uint4 *)&Bs[s][l_r + 32 * q][l_c] = rb[q];
+            } else {
+                const T *pa = (const T *)&ra[q];
+                const T *pb = (const T *)&rb[q];
+#pragma unroll
+                for (int e2 = 0; e2 < EPC; ++e2) {
+                    As[s][l_r + 32 * q][l_c + e2] = pa[e2];
+                    Bs[s][l_r + 32 * q][l_c + e2] = pb[e2];
+                }
+            }
+        }
+    };
+
+    f4_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int nk = (int)(np / BK);
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK / C::KSTEP; ++kk) {
+            const int koff = kk * C::KSTEP + C::VEC * (lane >> 4);
+            const T *a[4];
+            const T *b[4];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) a[ib] = &As[cur][wm * 64 + 16 * ib + (lane & 15)][koff];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) b[jb] = &Bs[cur][wn * 64 + 16 * jb + (lane & 15)][koff];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = mfma_low<T>(a[ib], b[jb], acc[ib][jb]);
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+
+    EpiCtx e{theta, zin, zout, ldzb, cs, dpart, part, n, kp};
+    // f32-accumulating 16x16 MFMAs: lane l, register r holds row 4(l/16) + r, column l%16.
+    auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * (l >> 4) + r; };
+    auto y_of = [&](int ib, int jb, int r, int64_t j, int32_t i) {
+        return delta[j * lda + i] + unscale * (double)acc[ib][jb][r];
+    };
+    sweep_epilogue(e, tm, tn, wm, wn, lane, row_of, y_of, red);
+}
+
+}  // namespace
+
+hipError_t launch_gemm_f64(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
+                           double *zout, int64_t ldzb, const double *theta, ColState cs, const double *dpart,
+                           double *part, int64_t n, int64_t np, int64_t kp, int32_t sweep) {
+    const int blocks = (int)((np / BM) * (kp / BN));
+    k_gemm_f64<<<blocks, 256, 0, s>>>(ctrl, delta, lda, zin, zout, ldzb, theta, cs, dpart, part, n, np, kp, sweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_low(hipStream_t s, const Ctrl *ctrl, int32_t want_prec, const void *dlo, int64_t ldd,
+                           const void *zt, int64_t ldt, const double *delta, int64_t lda, const double *zin,
+                           double *zout, int64_t ldzb, const double *theta, ColState cs, const double *dpart,
+                           double *part, int64_t n, int64_t np, int64_t kp, int32_t sweep, int32_t type) {
+    const int blocks = (int)((np / BM) * (kp / BN));
+    if (type == LT_F32)
+        k_gemm_low<float><<<blocks, 256, 0, s>>>(ctrl, want_prec, (const float *)dlo, ldd, (const float *)zt, ldt, delta,
+                                                 lda, zin, zout, ldzb, theta, cs, dpart, part, n, np, kp, sweep,
+                                                 false);
+    else if (type == LT_BF16)
+        k_gemm_low<__bf16><<<blocks, 256, 0, s>>>(ctrl, want_prec, (const __bf16 *)dlo, ldd, (const __bf16 *)zt, ldt,
+                                                  delta, lda, zin, zout, ldzb, theta, cs, dpart, part, n, np, kp, sweep,
+                                                  false);
+    else
+        k_gemm_low<_Float16><<<blocks, 256, 0, s>>>(ctrl, want_prec, (const _Float16 *)dlo, ldd, (const _Float16 *)zt,
+                                                    ldt, delta, lda, zin, zout, ldzb, theta, cs, dpart, part, n, np, kp,
+                                                    sweep, true);
+    return hipGetLastError();
+}
+
+}  // namespace ipt

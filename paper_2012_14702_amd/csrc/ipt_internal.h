@@ -1,0 +1,124 @@
+// Internal declarations of the gfx950 IPT library: device control block, column
+// states, workspace layout and the host-side launchers of every kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ipt.h"
+
+namespace ipt {
+
+// Column states kept on the device.  ACTIVE columns are iterated; the others are
+// frozen and their final value sits in the ping-pong buffer named by col_par.
+enum : int32_t { COL_ACTIVE = -1, COL_CONVERGED = IPT_CONVERGED, COL_NOT_CONVERGED = IPT_NOT_CONVERGED,
+                 COL_DIVERGED = IPT_DIVERGED, COL_PAD = -2 };
+
+// Where a frozen column's final value lives: buffer 0 or 1, or the unit vector
+// e_i (a column certified by the first sweep of a cold start).
+enum : int32_t { PAR_BUF0 = 0, PAR_BUF1 = 1, PAR_UNIT = 2 };
+
+// Sweep precisions (same numbering as IPT_SWEEP_*).
+enum : int32_t { PREC_EXACT_FIRST = IPT_SWEEP_EXACT_FIRST, PREC_LOW = IPT_SWEEP_LOW, PREC_F32 = IPT_SWEEP_FP32,
+                 PREC_F64 = IPT_SWEEP_FP64 };
+
+// Device control block of one solve.  Written by the setup, finalize and control
+// kernels; read at the start of every sweep kernel, which returns at once when
+// `done` is set or when the sweep's precision is not its own.
+struct Ctrl {
+    int32_t error;       // IPT_EINVAL / IPT_EDEGENERATE found by the device checks, else 0
+    int32_t done;        // 1 once no column is active or max_iter sweeps ran
+    int32_t prec;        // precision of the next sweep
+    int32_t sweeps;      // sweeps executed
+    int32_t active;      // active columns entering the next sweep
+    int32_t acc_active;  // finalize accumulator: columns still active after this sweep
+    int32_t n_conv, n_notconv, n_div;
+    int32_t pad0;
+    uint64_t acc_maxstep;  // finalize accumulator: max s_c (bit pattern of a non-negative double)
+    uint64_t acc_maxres;   // max normalised eigen-residual over converged columns (bits)
+    uint64_t dec_maxstep;  // max deciding step over decided columns (bits)
+    uint64_t norm1_bits;   // |M|_1 (bits), set by the norm kernel
+    uint64_t acc_maxdist;  // finalize accumulator: max |W_c - e_i| over active columns (bits)
+    uint64_t dmax_bits;    // max |Delta_jl| (bits), set when the FP16 rung needs a scale
+    double dscale;         // power-of-two scale of the low-precision Delta shadow (1 unless FP16)
+    double zscale;         // power-of-two scale of the low-precision (Z - E) shadow (1 unless FP16)
+    int64_t matvecs;
+    double prev_maxstep;
+    int32_t hist_prec[IPT_HIST];
+    int32_t hist_active[IPT_HIST];
+    double hist_step[IPT_HIST];
+};
+
+// Options as the kernels see them.
+struct DevOpts {
+    double tol, tau_low, tau_32, div_norm;
+    int32_t max_iter, div_growth, ladder, low_type;
+};
+
+// Per-column state arrays (length kp).
+struct ColState {
+    int32_t *state;   // COL_*
+    int32_t *sweeps;  // deciding sweep
+    int32_t *grow;    // consecutive FP64 sweeps with a growing step
+    int32_t *par;     // PAR_* of frozen columns
+    double *prev;     // previous step
+    double *step;     // deciding step
+    double *lam;      // lambda of the deciding sweep
+    double *resid;    // normalised eigen-residual of the deciding sweep
+    int32_t *idx;     // requested indices (padding columns hold 0)
+    int32_t *tile_stamp;  // per column tile of width TILE_N: last sweep in which it had an active column
+};
+
+constexpr int TILE_M = 128;   // rows of Delta / Y per GEMM tile, and per partial-sum row tile
+constexpr int TILE_N = 128;   // columns of Z / Y per GEMM tile
+constexpr int NPART = 4;      // partial sums per (row tile, column): step^2, z^2, (gap*step)^2, |w-e|^2
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// -------------------------------------------------------------- launchers
+constexpr int DIAG_SPLIT = 8;  // partial sums per d_c (dpart is DIAG_SPLIT x kp)
+
+// Setup and bookkeeping (ipt_setup.hip)
+hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
+                       int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp);
+hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
+                              int64_t k);
+hipError_t launch_norm1_dense(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
+                              int64_t n, double *scratch);
+hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
+                            const int32_t *col, const double *val, int64_t n, double *scratch);
+hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld);
+hipError_t launch_copy_pad(hipStream_t s, const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n,
+                           int64_t np);
+hipError_t launch_load_z0(hipStream_t s, const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb,
+                          int64_t ldzb, const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kp);
+hipError_t launch_zero_pad(hipStream_t s, double *zb, int64_t ldzb, int64_t n, int64_t np, int64_t k, int64_t kp);
+hipError_t launch_sweep1_dense(hipStream_t s, const Ctrl *ctrl, const double *theta, const double *delta,
+                               int64_t lda, ColState cs, double *dpart, double *zout, int64_t ldzb, double *part,
+                               int64_t n, int64_t np, int64_t kp);
+hipError_t launch_diag_dense(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
+                             int64_t ldzb, ColState cs, double *dpart, int64_t n, int64_t kp);
+hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, const double *dpart,
+                           const double *theta, const double *part, int64_t nrt, int64_t kp, int32_t sweep,
+                           int32_t in_par, int32_t out_par);
+hipError_t launch_control(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep);
+hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
+                          int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
+                          int64_t n, int64_t k, const ipt_colinfo *ci);
+hipError_t launch_cast_delta(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, void *dst,
+                             int64_t ldd, int64_t n, int64_t np, int32_t type);
+hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
+                         int64_t ldt, int64_t np, int64_t kp, int32_t type, int32_t want_prec);
+
+// GEMM sweeps (ipt_gemm.hip).  Each returns at once unless ctrl->prec is its precision.
+hipError_t launch_gemm_f64(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
+                           double *zout, int64_t ldzb, const double *theta, ColState cs, const double *dpart,
+                           double *part, int64_t n, int64_t np, int64_t kp, int32_t sweep);
+hipError_t launch_gemm_low(hipStream_t s, const Ctrl *ctrl, int32_t want_prec, const void *dlo, int64_t ldd,
+                           const void *zt, int64_t ldt, const double *delta, int64_t lda, const double *zin,
+                           double *zout, int64_t ldzb, const double *theta, ColState cs, const double *dpart,
+                           double *part, int64_t n, int64_t np, int64_t kp, int32_t sweep, int32_t type);
+
+// Element types of the low-precision shadows.
+enum : int32_t { LT_BF16 = 0, LT_F16 = 1, LT_F32 = 2 };
+
+}  // namespace ipt

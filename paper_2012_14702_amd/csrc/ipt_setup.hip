@@ -1,0 +1,594 @@
+// Setup, first-sweep, diagonal, finalize, control and copy-out kernels of the IPT
+// sweep (everything except the products Delta x Z).
+//
+// Notation: theta = diag(D), i = idx[c] the index column c continues, Z is the
+// current iterate (row-major, buffer leading dimension ldzb, padded to np rows and
+// kp columns with zeros), W = F(Z) its image under the map of eq. dyn.
+#include <math.h>
+
+#include "ipt_internal.h"
+
+namespace ipt {
+
+namespace {
+
+constexpr int kDiagSplit = DIAG_SPLIT;  // partial sums of each d_c (see the diagonal kernel)
+
+__device__ inline uint64_t dbits(double x) {
+    // Bit pattern of a non-negative double (NaN mapped to +inf) so that unsigned
+    // integer max equals floating-point max; used for order-independent maxima.
+    if (!(x >= 0.0)) x = INFINITY;
+    return (uint64_t)__double_as_longlong(x);
+}
+
+__device__ inline double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
+
+__global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k) {
+    Ctrl c = {};
+    c.prec = start_prec;
+    c.active = (int32_t)k;
+    c.prev_maxstep = INFINITY;
+    c.dscale = 1.0;
+    c.zscale = 1.0;
+    *ctrl = c;
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t v) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+__global__ void k_init_cols(Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k, int64_t kp,
+                            uint32_t *bitmap, int32_t ntiles, int32_t start_stamp) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c < ntiles) cs.tile_stamp[c] = start_stamp;
+    if (c >= kp) return;
+    int32_t state = COL_PAD, i = 0;
+    if (c < k) {
+        const int64_t ii = idx_user ? (int64_t)idx_user[c] : c;
+        if (ii < 0 || ii >= n) {
+            atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
+        } else {
+            const uint32_t bit = 1u << (ii & 31);
+            const uint32_t old = atomicOr(&bitmap[ii >> 5], bit);
+            if (old & bit) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);  // duplicate index
+            i = (int32_t)ii;
+        }
+        state = COL_ACTIVE;
+    }
+    cs.idx[c] = i;
+    cs.state[c] = state;
+    cs.sweeps[c] = 0;
+    cs.grow[c] = 0;
+    cs.par[c] = PAR_BUF0;
+    cs.prev[c] = INFINITY;
+    cs.step[c] = INFINITY;
+    cs.lam[c] = 0.0;
+    cs.resid[c] = 0.0;
+}
+
+// theta must be finite, and theta_j != theta_i for every j != i = idx[c]: the
+// inverse gaps G_ji are then defined for every requested column.
+__global__ void k_check_theta(Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n, int64_t k) {
+    __shared__ double ti[256];
+    __shared__ int32_t ii[256];
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.y * 256;
+    const int64_t cc = c0 + threadIdx.x;
+    if (cc < k) {
+        ii[threadIdx.x] = idx[cc];
+        ti[threadIdx.x] = theta[idx[cc]];
+    }
+    __syncthreads();
+    if (j >= n) return;
+    const double tj = theta[j];
+    if (blockIdx.y == 0 && !isfinite(tj)) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
+    const int64_t cend = (k - c0 < 256) ? (k - c0) : 256;
+    bool degen = false;
+    for (int64_t q = 0; q < cend; ++q) degen |= (tj == ti[q]) && (j != ii[q]);
+    if (degen) atomicMax(&ctrl->error, (int32_t)IPT_EDEGENERATE);
+}
+
+// |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Stage 1: column sums over
+// row chunks (coalesced: consecutive threads take consecutive columns).
+__global__ void k_norm1_dense_part(const double *theta, const double *delta, int64_t lda, int64_t n, int64_t rows,
+                                   double *scratch) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int64_t r0 = (int64_t)blockIdx.y * rows;
+    int64_t r1 = r0 + rows;
+    if (r1 > n) r1 = n;
+    double acc = 0.0;
+    for (int64_t j = r0; j < r1; ++j) {
+        double m = delta[j * lda + c];
+        if (j == c) m += theta[c];
+        acc += fabs(m);
+    }
+    scratch[(int64_t)blockIdx.y * n + c] = acc;
+}
+
+__global__ void k_norm1_reduce(Ctrl *ctrl, const double *scratch, int64_t n, int64_t chunks) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double acc = 0.0;
+    for (int64_t q = 0; q < chunks; ++q) acc += scratch[q * n + c];
+    atomicMax((unsigned long long *)&ctrl->norm1_bits, (unsigned long long)dbits(acc));
+}
+
+// CSR column sums: off-diagonal |Delta_jc| go to scratch[c], diagonal entries of
+// Delta to scratch[n + c] (added to theta_c before taking the modulus).  Double
+// atomics: the norm is a diagnostic (it scales the reported eigen-residual) and
+// takes no part in any decision.
+__global__ void k_norm1_csr_part(const int32_t *row_ptr, const int32_t *col, const double *val, int64_t n,
+                                 double *scratch) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int32_t p = row_ptr[j]; p < row_ptr[j + 1]; ++p) {
+        const int32_t c = col[p];
+        if (c == j) atomicAdd(&scratch[n + c], val[p]);
+        else atomicAdd(&scratch[c], fabs(val[p]));
+    }
+}
+
+__global__ void k_norm1_csr_reduce(Ctrl *ctrl, const double *theta, const double *scratch, int64_t n) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const double v = scratch[c] + fabs(theta[c] + scratch[n + c]);
+    atomicMax((unsigned long long *)&ctrl->norm1_bits, (unsigned long long)dbits(v));
+}
+
+__global__ void k_zero_f64(double *p, int64_t count) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = 0.0;
+}
+
+// dst (np x np, ldd) <- src (n x n, lds) with zero padding.
+__global__ void k_copy_pad(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, int64_t np) {
+    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t j = blockIdx.y;
+    if (l >= np) return;
+    dst[j * ldd + l] = (j < n && l < n) ? src[j * lds + l] : 0.0;
+}
+
+// Warm start: Z <- z0 with Z[idx[c], c] = 1 (chart U_i); padding zero.
+__global__ void k_load_z0(const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
+                          const int32_t *idx, int64_t n, int64_t k, int64_t kp) {
+    if (ctrl->error) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t j = blockIdx.y;
+    if (c >= kp) return;
+    double v = 0.0;
+    if (j < n && c < k) v = (j == idx[c]) ? 1.0 : z0[j * ldz0 + c];
+    zb[j * ldzb + c] = v;
+}
+
+// Zero the padding rows [n, np) and padding columns [k, kp) of a Z buffer.
+__global__ void k_zero_pad(double *zb, int64_t ldzb, int64_t n, int64_t np, int64_t k, int64_t kp) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t j = blockIdx.y;
+    if (c >= kp) return;
+    if (j >= n || c >= k) zb[j * ldzb + c] = 0.0;
+}
+
+// Block-wide reduction of per-thread column partials laid out as 4 row groups of
+// 64 columns: thread (cx = t & 63, ry = t >> 6).  Sums the 4 groups in a fixed order
+// and writes part[rt][c][q].
+__device__ inline void store_col_partials(double (*sh)[4][64], const double v[NPART], int cx, int ry, double *part,
+                                          int64_t rt, int64_t kp, int64_t c) {
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) sh[ry][q][cx] = v[q];
+    __syncthreads();
+    if (ry == 0) {
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) {
+            const double s = ((sh[0][q][cx] + sh[1][q][cx]) + sh[2][q][cx]) + sh[3][q][cx];
+            part[(rt * kp + c) * NPART + q] = s;
+        }
+    }
+}
+
+// First sweep of a cold start (Z = I): W = F(I) needs no product because
+// Delta I = Delta exactly.  W_jc = -Delta_ji / (theta_j - theta_i) for j != i,
+// W_ic = 1, d_c = Delta_ii (eq. dyn at Z = I; the first-order RS term of
+// eq. ARS-alpha).  Block: one row tile of TILE_M rows x 64 columns.
+__global__ __launch_bounds__(256) void k_sweep1_dense(const Ctrl *ctrl, const double *theta, const double *delta,
+                                                      int64_t lda, ColState cs, double *dpart, double *zout,
+                                                      int64_t ldzb, double *part, int64_t n, int64_t kp) {
+    if (ctrl->error || ctrl->done) return;
+    __shared__ double sh[4][4][64];
+    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    const int64_t rt = blockIdx.y;
+    const int64_t c = (int64_t)blockIdx.x * 64 + cx;
+    const bool colok = cs.state[c] == COL_ACTIVE;
+    const int32_t i = cs.idx[c];
+    const double ti = theta[i];
+    double v[NPART] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < TILE_M / 4; ++q) {
+        const int64_t j = rt * TILE_M + ry + 4 * q;
+        double w = 0.0;
+        if (colok && j < n) {
+            if (j == i) {
+                w = 1.0;
+                v[1] += 1.0;  // z_ii^2
+            } else {
+                const double gap = theta[j] - ti;
+                w = -delta[j * lda + i] / gap;
+                const double st = w;  // z_jc = 0
+                v[0] += st * st;
+                v[2] += (gap * st) * (gap * st);
+                v[3] += w * w;
+            }
+        }
+        zout[j * ldzb + c] = w;
+    }
+    if (colok && rt == (int64_t)(i / TILE_M) && ry == 0) {
+        dpart[c] = delta[(int64_t)i * lda + i];
+        for (int s = 1; s < kDiagSplit; ++s) dpart[(int64_t)s * kp + c] = 0.0;
+    }
+    store_col_partials(sh, v, cx, ry, part, rt, kp, c);
+}
+
+// d_c = (Delta Z)_{i,c} = sum_l Delta_il Z_lc in FP64 for the active columns.
+// Block: 64 columns x one of kDiagSplit contiguous ranges of l; the ranges' sums
+// are added in a fixed order by the consumers (GEMM epilogue and finalize).
+__global__ __launch_bounds__(256) void k_diag_dense(const Ctrl *ctrl, const double *delta, int64_t lda,
+                                                    const double *zin, int64_t ldzb, ColState cs, double *dpart,
+                                                    int64_t n, int64_t kp) {
+    if (ctrl->error || ctrl->done) return;
+    __shared__ double dt[64][65];
+    __shared__ double zt[64][65];
+    __shared__ double red[4][64];
+    __shared__ int32_t any;
+    const int t = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    if (t == 0) any = 0;
+    __syncthreads();
+    if (t < 64 && cs.state[c0 + t] == COL_ACTIVE) any = 1;
+    __syncthreads();
+    if (!any) return;
+    const int64_t span = (n + kDiagSplit - 1) / kDiagSplit;
+    const int64_t lbeg = (int64_t)blockIdx.y * span;
+    int64_t lend = lbeg + span;
+    if (lend > n) lend = n;
+    const int cx = t & 63, p = t >> 6;
+    double acc = 0.0;
+    const int lr = t >> 2, lq = (t & 3) * 16;  // loader: row lr, 16 consecutive entries from lq
+    const int32_t irow = cs.idx[c0 + lr];
+    for (int64_t l0 = lbeg; l0 < lend; l0 += 64) {
+        // dt[cc][ll] = Delta[idx[c0 + cc], l0 + ll];  zt[ll][cc] = Z[l0 + ll, c0 + cc]
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t l = l0 + lq + e;
+            dt[lr][lq + e] = (l < lend) ? delta[(int64_t)irow * lda + l] : 0.0;
+        }
+        const bool rowok = (l0 + lr) < lend;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) zt[lr][lq + e] = rowok ? zin[(l0 + lr) * ldzb + c0 + lq + e] : 0.0;
+        __syncthreads();
+        for (int e = 0; e < 16; ++e) acc += dt[cx][16 * p + e] * zt[16 * p + e][cx];
+        __syncthreads();
+    }
+    red[p][cx] = acc;
+    __syncthreads();
+    if (p == 0) {
+        const double s = ((red[0][cx] + red[1][cx]) + red[2][cx]) + red[3][cx];
+        dpart[(int64_t)blockIdx.y * kp + c0 + cx] = s;
+    }
+}
+
+// Finalize sweep t for every active column: reduce the partial sums over row
+// tiles in order, form s_c = |W_c - Z_c| / |Z_c| (Alg. 1 loop test, Euclidean
+// norms), and decide.  Only an exact sweep (FP64 product, or the product-free
+// first sweep) may certify a column; a certified column keeps its input iterate
+// and lambda_c = theta_i + d_c of this sweep (Alg. 1/2 return steps).
+__global__ void k_finalize(Ctrl *ctrl, DevOpts o, ColState cs, const double *dpart, const double *theta,
+                           const double *part, int64_t nrt, int64_t kp, int32_t sweep, int32_t in_par,
+                           int32_t out_par) {
+    if (ctrl->error || ctrl->done) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= kp || cs.state[c] != COL_ACTIVE) return;
+    double p[NPART] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t rt = 0; rt < nrt; ++rt)
+        for (int q = 0; q < NPART; ++q) p[q] += part[(rt * kp + c) * NPART + q];
+    double d = 0.0;
+    for (int s = 0; s < kDiagSplit; ++s) d += dpart[(int64_t)s * kp + c];
+    const double s = sqrt(p[0]) / sqrt(p[1]);
+    const int32_t prec = ctrl->prec;
+    const bool exact = (prec == PREC_F64) || (prec == PREC_EXACT_FIRST);
+    const double nrm = bitsd(ctrl->norm1_bits);
+    const double resid = sqrt(p[2]) / (nrm > 0.0 ? nrm : 1.0) / sqrt(p[1]);
+    const int32_t i = cs.idx[c];
+    atomicMax((unsigned long long *)&ctrl->acc_maxstep, (unsigned long long)dbits(s));
+    int32_t decided = -1, par = 0;
+    if (exact && s <= o.tol) {
+        decided = COL_CONVERGED;
+        par = in_par;
+        atomicMax((unsigned long long *)&ctrl->acc_maxres, (unsigned long long)dbits(resid));
+    } else {
+        const bool bad = !isfinite(s) || !(sqrt(p[3]) <= o.div_norm);
+        int32_t grow = cs.grow[c];
+        if (exact) {
+            grow = (s > cs.prev[c]) ? grow + 1 : 0;
+            cs.prev[c] = s;
+            cs.grow[c] = grow;
+        }
+        if (bad || grow >= o.div_growth) {
+            decided = COL_DIVERGED;
+            par = out_par;
+        } else if (sweep >= o.max_iter) {
+            decided = COL_NOT_CONVERGED;
+            par = out_par;
+        }
+    }
+    if (decided >= 0) {
+        cs.state[c] = decided;
+        cs.par[c] = par;
+        cs.sweeps[c] = sweep;
+        cs.step[c] = s;
+        cs.lam[c] = theta[i] + d;
+        cs.resid[c] = resid;
+        atomicAdd(decided == COL_CONVERGED ? &ctrl->n_conv : decided == COL_DIVERGED ? &ctrl->n_div : &ctrl->n_notconv,
+                  1);
+        atomicMax((unsigned long long *)&ctrl->dec_maxstep, (unsigned long long)dbits(s));
+    } else {
+        atomicAdd(&ctrl->acc_active, 1);
+        atomicMax((unsigned long long *)&ctrl->acc_maxdist, (unsigned long long)dbits(sqrt(p[3])));
+        cs.tile_stamp[c / TILE_N] = sweep;
+    }
+}
+
+// Bookkeeping after sweep t and the precision of sweep t+1 (the ladder): leave the
+// low rung when the max step is <= tau_low or stops falling, leave FP32 when it is
+// <= tau_32 or stops falling; FP64 is final.
+__global__ void k_control(Ctrl *ctrl, DevOpts o, int32_t sweep) {
+    if (ctrl->error || ctrl->done) return;
+    const double ms = bitsd(ctrl->acc_maxstep);
+    const int32_t prec = ctrl->prec;
+    if (sweep - 1 < IPT_HIST) {
+        ctrl->hist_prec[sweep - 1] = prec;
+        ctrl->hist_active[sweep - 1] = ctrl->active;
+        ctrl->hist_step[sweep - 1] = ms;
+    }
+    if (prec != PREC_EXACT_FIRST) ctrl->matvecs += ctrl->active;
+    ctrl->active = ctrl->acc_active;
+    ctrl->acc_active = 0;
+    ctrl->acc_maxstep = 0;
+    ctrl->sweeps = sweep;
+    if (ctrl->active == 0 || sweep >= o.max_iter) ctrl->done = 1;
+    int32_t next = PREC_F64;
+    if (o.ladder) {
+        const bool stalled = !(ms < ctrl->prev_maxstep);
+        if (prec == PREC_EXACT_FIRST) {
+            next = (ms <= o.tau_32) ? PREC_F64 : (ms <= o.tau_low || o.low_type == IPT_LOW_NONE) ? PREC_F32 : PREC_LOW;
+        } else if (prec == PREC_LOW) {
+            next = (ms <= o.tau_32) ? PREC_F64 : (ms <= o.tau_low || stalled) ? PREC_F32 : PREC_LOW;
+        } else if (prec == PREC_F32) {
+            next = (ms <= o.tau_32 || stalled) ? PREC_F64 : PREC_F32;
+        }
+    }
+    ctrl->prec = next;
+    ctrl->prev_maxstep = ms;
+    // FP16 rung: scale Z - E by a power of two so that its largest entry (bounded
+    // by max_c |W_c - e_i|) lands near 2^13, well inside the FP16 range.
+    if (o.ladder && o.low_type == IPT_LOW_FP16) {
+        const double md = bitsd(ctrl->acc_maxdist);
+        ctrl->zscale = (md > 0.0 && isfinite(md)) ? exp2(floor(log2(8192.0 / md))) : 1.0;
+    }
+    ctrl->acc_maxdist = 0;
+}
+
+// max |x_jl| over a rows x cols matrix (leading dimension ld) -> ctrl->dmax_bits;
+// then the FP16 scale of the Delta shadow.
+__global__ void k_absmax(Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld) {
+    double m = 0.0;
+    const int64_t count = rows * cols;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, fabs(x[(t / cols) * ld + t % cols]));
+    atomicMax((unsigned long long *)&ctrl->dmax_bits, (unsigned long long)dbits(m));
+}
+
+__global__ void k_set_dscale(Ctrl *ctrl) {
+    const double md = bitsd(ctrl->dmax_bits);
+    ctrl->dscale = (md > 0.0 && isfinite(md)) ? exp2(floor(log2(8192.0 / md))) : 1.0;
+}
+
+// z_out[:, c] <- the buffer holding column c's final value; lambda, status and the
+// optional per-column outputs.
+__global__ void k_copyout(const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1, int64_t ldzb,
+                          double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out, int64_t n, int64_t k,
+                          int32_t *ci_sweeps, double *ci_step, double *ci_resid) {
+    if (ctrl->error) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * 64;
+    if (c >= k) return;
+    const int32_t par = cs.par[c];
+    const int32_t i = cs.idx[c];
+    const double *src = (par == PAR_BUF1) ? buf1 : buf0;
+    int64_t j1 = j0 + 64;
+    if (j1 > n) j1 = n;
+    for (int64_t j = j0; j < j1; ++j) z_out[j * ldz + c] = (par == PAR_UNIT) ? (j == i ? 1.0 : 0.0) : src[j * ldzb + c];
+    if (blockIdx.y == 0) {
+        lambda_out[c] = cs.lam[c];
+        const int32_t st = cs.state[c];
+        status_out[c] = (st == COL_ACTIVE) ? IPT_NOT_CONVERGED : st;
+        if (ci_sweeps) ci_sweeps[c] = cs.sweeps[c];
+        if (ci_step) ci_step[c] = cs.step[c];
+        if (ci_resid) ci_resid[c] = cs.resid[c];
+    }
+}
+
+// Low-precision shadows (precision ladder).  Delta_lo = lowp(scale * Delta),
+// np x np with zero padding.
+template <typename T>
+__device__ inline T to_low(double x);
+template <>
+__device__ inline float to_low<float>(double x) { return (float)x; }
+template <>
+__device__ inline __bf16 to_low<__bf16>(double x) { return (__bf16)(float)x; }
+template <>
+__device__ inline _Float16 to_low<_Float16>(double x) { return (_Float16)(float)x; }
+
+template <typename T>
+__global__ void k_cast_delta(const Ctrl *ctrl, const double *delta, int64_t lda, T *dst, int64_t ldd, int64_t n,
+                             int64_t np, bool scaled) {
+    if (ctrl->error) return;
+    const double scale = scaled ? ctrl->dscale : 1.0;
+    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t j = blockIdx.y;
+    if (l >= np) return;
+    const double v = (j < n && l < n) ? delta[j * lda + l] * scale : 0.0;
+    dst[j * ldd + l] = to_low<T>(v);
+}
+
+// Transposed shadow of the split iterate: zt[c][j] = lowp(scale * (Z_jc - [j == i])).
+// Only Z - E goes through low precision; Delta E is added back exactly in FP64
+// by the GEMM epilogue.  64 x 64 tiles transposed through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cast_z(const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs,
+                                                T *zt, int64_t ldt, bool scaled, int32_t want_prec) {
+    if (ctrl->error || ctrl->done || ctrl->prec != want_prec) return;
+    const double scale = scaled ? ctrl->zscale : 1.0;
+    __shared__ double tile[64][65];
+    const int64_t j0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int t = threadIdx.x;
+    for (int q = 0; q < 16; ++q) {
+        const int r = (t >> 6) + 4 * q, cc = t & 63;
+        const int64_t j = j0 + r, c = c0 + cc;
+        double v = zin[j * ldzb + c];
+        if (j == cs.idx[c] && cs.state[c] != COL_PAD) v -= 1.0;
+        tile[r][cc] = v * scale;
+    }
+    __syncthreads();
+    for (int q = 0; q < 16; ++q) {
+        const int cc = (t >> 6) + 4 * q, r = t & 63;
+        zt[(c0 + cc) * ldt + j0 + r] = to_low<T>(tile[r][cc]);
+    }
+}
+
+inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) / per); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
+                       int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp) {
+    k_ctrl_init<<<1, 1, 0, s>>>(ctrl, start_prec, k);
+    const int64_t words = (n + 31) / 32;
+    k_fill_u32<<<blocks_for(words, 256) < 1024 ? blocks_for(words, 256) : 1024, 256, 0, s>>>(bitmap, words, 0u);
+    const int64_t m = kp > ntiles_n ? kp : ntiles_n;
+    k_init_cols<<<blocks_for(m, 256), 256, 0, s>>>(ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
+                              int64_t k) {
+    dim3 g(blocks_for(n, 256), blocks_for(k, 256));
+    k_check_theta<<<g, 256, 0, s>>>(ctrl, theta, idx, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm1_dense(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
+                              int64_t n, double *scratch) {
+    int64_t chunks = n / 64;
+    if (chunks < 1) chunks = 1;
+    if (chunks > 64) chunks = 64;
+    const int64_t rows = (n + chunks - 1) / chunks;
+    chunks = (n + rows - 1) / rows;
+    dim3 g(blocks_for(n, 256), (unsigned)chunks);
+    k_norm1_dense_part<<<g, 256, 0, s>>>(theta, delta, lda, n, rows, scratch);
+    k_norm1_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, scratch, n, chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
+                            const int32_t *col, const double *val, int64_t n, double *scratch) {
+    k_zero_f64<<<blocks_for(2 * n, 256) < 2048 ? blocks_for(2 * n, 256) : 2048, 256, 0, s>>>(scratch, 2 * n);
+    k_norm1_csr_part<<<blocks_for(n, 256), 256, 0, s>>>(row_ptr, col, val, n, scratch);
+    k_norm1_csr_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, theta, scratch, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_pad(hipStream_t s, const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n,
+                           int64_t np) {
+    dim3 g(blocks_for(np, 256), (unsigned)np);
+    k_copy_pad<<<g, 256, 0, s>>>(src, lds, dst, ldd, n, np);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_z0(hipStream_t s, const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
+                          const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kp) {
+    dim3 g(blocks_for(kp, 256), (unsigned)np);
+    k_load_z0<<<g, 256, 0, s>>>(ctrl, z0, ldz0, zb, ldzb, idx, n, k, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_pad(hipStream_t s, double *zb, int64_t ldzb, int64_t n, int64_t np, int64_t k, int64_t kp) {
+    dim3 g(blocks_for(kp, 256), (unsigned)np);
+    k_zero_pad<<<g, 256, 0, s>>>(zb, ldzb, n, np, k, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep1_dense(hipStream_t s, const Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
+                               ColState cs, double *dpart, double *zout, int64_t ldzb, double *part, int64_t n,
+                               int64_t np, int64_t kp) {
+    dim3 g((unsigned)(kp / 64), (unsigned)(np / TILE_M));
+    k_sweep1_dense<<<g, 256, 0, s>>>(ctrl, theta, delta, lda, cs, dpart, zout, ldzb, part, n, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_dense(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
+                             int64_t ldzb, ColState cs, double *dpart, int64_t n, int64_t kp) {
+    dim3 g((unsigned)(kp / 64), kDiagSplit);
+    k_diag_dense<<<g, 256, 0, s>>>(ctrl, delta, lda, zin, ldzb, cs, dpart, n, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, const double *dpart,
+                           const double *theta, const double *part, int64_t nrt, int64_t kp, int32_t sweep,
+                           int32_t in_par, int32_t out_par) {
+    k_finalize<<<blocks_for(kp, 256), 256, 0, s>>>(ctrl, o, cs, dpart, theta, part, nrt, kp, sweep, in_par, out_par);
+    return hipGetLastError();
+}
+
+hipError_t launch_control(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep) {
+    k_control<<<1, 1, 0, s>>>(ctrl, o, sweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
+                          int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out, int64_t n,
+                          int64_t k, const ipt_colinfo *ci) {
+    dim3 g(blocks_for(k, 256), blocks_for(n, 64));
+    k_copyout<<<g, 256, 0, s>>>(ctrl, cs, buf0, buf1, ldzb, z_out, ldz, lambda_out, status_out, n, k,
+                                ci ? ci->sweeps : nullptr, ci ? ci->step : nullptr, ci ? ci->resid : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_delta(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, void *dst, int64_t ldd,
+                             int64_t n, int64_t np, int32_t type) {
+    dim3 g(blocks_for(np, 256), (unsigned)np);
+    if (type == LT_F32) k_cast_delta<float><<<g, 256, 0, s>>>(ctrl, delta, lda, (float *)dst, ldd, n, np, false);
+    else if (type == LT_BF16) k_cast_delta<__bf16><<<g, 256, 0, s>>>(ctrl, delta, lda, (__bf16 *)dst, ldd, n, np, false);
+    else k_cast_delta<_Float16><<<g, 256, 0, s>>>(ctrl, delta, lda, (_Float16 *)dst, ldd, n, np, true);
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld) {
+    int b = blocks_for(rows * cols, 256);
+    if (b > 4096) b = 4096;
+    k_absmax<<<b, 256, 0, s>>>(ctrl, x, rows, cols, ld);
+    k_set_dscale<<<1, 1, 0, s>>>(ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
+                         int64_t ldt, int64_t np, int64_t kp, int32_t type, int32_t want_prec) {
+    dim3 g((unsigned)(kp / 64), (unsigned)(np / 64));
+    if (type == LT_F32) k_cast_z<float><<<g, 256, 0, s>>>(ctrl, zin, ldzb, cs, (float *)zt, ldt, false, want_prec);
+    else if (type == LT_BF16) k_cast_z<__bf16><<<g, 256, 0, s>>>(ctrl, zin, ldzb, cs, (__bf16 *)zt, ldt, false, want_prec);
+    else k_cast_z<_Float16><<<g, 256, 0, s>>>(ctrl, zin, ldzb, cs, (_Float16 *)zt, ldt, true, want_prec);
+    return hipGetLastError();
+}
+
+}  // namespace ipt

@@ -1,0 +1,299 @@
+"""ctypes binding of include/ipt.h.  Argument marshalling only: every step of a
+solve runs in the HIP kernels of libipt.so.  Tensors must be CUDA (ROCm) tensors
+on the handle's device; the library writes the outputs in place on the current
+torch stream."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libipt.so")
+
+IPT_OK, IPT_EINVAL, IPT_EDEGENERATE, IPT_ENOTCONV, IPT_EHIP, IPT_ENOMEM = range(6)
+CONVERGED, NOT_CONVERGED, DIVERGED = 0, 1, 2
+PREC_FP64, PREC_LADDER = 0, 1
+LOW_BF16, LOW_FP16, LOW_NONE = 0, 1, 2
+SWEEP_NAMES = {0: "exact-first", 1: "low", 2: "fp32", 3: "fp64"}
+IPT_HIST = 128
+FLAG_NO_NORM = 1
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("low_type", C.c_int32),
+                ("sync_every", C.c_int32), ("tau_low", C.c_double), ("tau_32", C.c_double),
+                ("div_norm", C.c_double), ("div_growth", C.c_int32), ("flags", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("converged", C.c_int32), ("not_converged", C.c_int32),
+                ("diverged", C.c_int32), ("matvecs", C.c_int64), ("max_step", C.c_double), ("norm1", C.c_double),
+                ("max_resid", C.c_double), ("time_ms", C.c_float), ("hist_len", C.c_int32),
+                ("sweep_prec", C.c_int32 * IPT_HIST), ("sweep_active", C.c_int32 * IPT_HIST),
+                ("sweep_max_step", C.c_double * IPT_HIST)]
+
+    def as_dict(self):
+        h = self.hist_len
+        return {"sweeps": self.sweeps, "converged": self.converged, "not_converged": self.not_converged,
+                "diverged": self.diverged, "matvecs": self.matvecs, "max_step": self.max_step,
+                "norm1": self.norm1, "max_resid": self.max_resid, "time_ms": self.time_ms,
+                "sweep_prec": [SWEEP_NAMES[p] for p in self.sweep_prec[:h]],
+                "sweep_active": list(self.sweep_active[:h]), "sweep_max_step": list(self.sweep_max_step[:h])}
+
+
+class ColInfo(C.Structure):
+    _fields_ = [("sweeps", C.c_void_p), ("step", C.c_void_p), ("resid", C.c_void_p)]
+
+
+class IPTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%s)" % (msg, status))
+        self.status = status
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB
+
+
+def _hip_runtimes():
+    try:
+        maps = open("/proc/self/maps").read().splitlines()
+    except OSError:
+        return []
+    return sorted({ln.split()[-1] for ln in maps if "libamdhip64" in ln})
+
+
+def load_library():
+    """Load libipt.so; raises if it has not been built (there is no fallback).
+
+    torch is imported first so that its HIP runtime is the one in the process:
+    libipt.so then binds to it by soname and the streams and device pointers that
+    torch hands over belong to the same runtime.  Two HIP runtimes in one process
+    are refused."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        raise ImportError("libipt.so is not built: run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
+    import torch  # noqa: F401  (loads the HIP runtime the tensors live in)
+    lib = C.CDLL(_LIB)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise ImportError("two HIP runtimes are loaded (%s); import torch before loading libipt.so" % runtimes)
+    p, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    lib.ipt_opts_default.argtypes = [C.POINTER(Opts)]
+    lib.ipt_opts_default.restype = None
+    lib.ipt_create.argtypes = [C.POINTER(p), p]
+    lib.ipt_destroy.argtypes = [p]
+    lib.ipt_set_stream.argtypes = [p, p]
+    lib.ipt_solve_dense.argtypes = [p, i64, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
+                                    C.POINTER(Info), C.POINTER(ColInfo)]
+    lib.ipt_solve_csr.argtypes = [p, i64, p, p, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
+                                  C.POINTER(Info), C.POINTER(ColInfo)]
+    lib.ipt_solve_batched.argtypes = [p, i32, p, p, p, p, p, p, C.POINTER(Opts), p, p, p, C.POINTER(Info)]
+    lib.ipt_status_string.argtypes = [C.c_int]
+    lib.ipt_status_string.restype = C.c_char_p
+    lib.ipt_last_error.argtypes = [p]
+    lib.ipt_last_error.restype = C.c_char_p
+    for fn in ("ipt_create", "ipt_destroy", "ipt_set_stream", "ipt_solve_dense", "ipt_solve_csr",
+               "ipt_solve_batched"):
+        getattr(lib, fn).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load_library().ipt_opts_default(C.byref(o))
+    for key, val in kw.items():
+        if not hasattr(o, key):
+            raise TypeError("unknown option " + key)
+        setattr(o, key, val)
+    return o
+
+
+class Handle:
+    """An ipt_handle bound to the current device and torch stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        lib = load_library()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._h = C.c_void_p()
+        st = lib.ipt_create(C.byref(self._h), C.c_void_p(s.cuda_stream))
+        if st != IPT_OK:
+            raise IPTError(st, "ipt_create failed")
+        self._stream = s
+
+    def set_stream(self, stream):
+        load_library().ipt_set_stream(self._h, C.c_void_p(stream.cuda_stream))
+        self._stream = stream
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def last_error(self) -> str:
+        return load_library().ipt_last_error(self._h).decode()
+
+    def close(self):
+        if self._h:
+            load_library().ipt_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_handles = {}
+
+
+def _handle(h):
+    if h is not None:
+        return h
+    import torch
+    key = (torch.cuda.current_device(), torch.cuda.current_stream().cuda_stream)
+    if key not in _default_handles:
+        _default_handles[key] = Handle()
+    return _default_handles[key]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check(t, dtype, name, cuda=True):
+    import torch
+    if t is None:
+        return
+    if cuda and not t.is_cuda:
+        raise ValueError(name + " must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s" % (name, dtype))
+
+
+def _opts(opts, kw):
+    if opts is None:
+        return default_opts(**kw)
+    for key, val in kw.items():
+        setattr(opts, key, val)
+    return opts
+
+
+class Result(dict):
+    __getattr__ = dict.__getitem__
+
+
+def _colinfo(k, want):
+    import torch
+    if not want:
+        return None, None
+    dev = torch.cuda.current_device()
+    sw = torch.empty(k, dtype=torch.int32, device=dev)
+    stp = torch.empty(k, dtype=torch.float64, device=dev)
+    res = torch.empty(k, dtype=torch.float64, device=dev)
+    ci = ColInfo(sw.data_ptr(), stp.data_ptr(), res.data_ptr())
+    return ci, (sw, stp, res)
+
+
+def _finish(lib, h, st, z, lam, status, info, extra, raise_on=(IPT_EINVAL, IPT_EDEGENERATE, IPT_EHIP, IPT_ENOMEM)):
+    if st in raise_on:
+        raise IPTError(st, h.last_error())
+    r = Result(z=z, lam=lam, status=status, info=info.as_dict(), code=st)
+    if extra is not None:
+        r["sweeps"], r["step"], r["resid"] = extra
+    return r
+
+
+def ipt_solve_dense(theta, delta, idx=None, z0=None, opts=None, handle=None, colinfo=True, z_out=None, **kw):
+    """Dense IPT solve (ipt_solve_dense).  theta [n] f64, delta [n, n] f64 (row-major,
+    row stride = lda), idx [k] int32 or None, z0 [n, k] f64 or None.  Returns a Result
+    with z [n, k], lam [k], status [k] and info (a dict of ipt_info)."""
+    import torch
+    lib = load_library()
+    h = _handle(handle)
+    _check(theta, torch.float64, "theta")
+    _check(delta, torch.float64, "delta")
+    _check(idx, torch.int32, "idx")
+    _check(z0, torch.float64, "z0")
+    n = theta.shape[0]
+    if delta.dim() != 2 or delta.shape[0] != n or delta.shape[1] != n or delta.stride(1) != 1:
+        raise ValueError("delta must be n x n with unit column stride")
+    k = n if idx is None else idx.shape[0]
+    if z0 is not None and (z0.dim() != 2 or z0.shape[0] != n or z0.shape[1] != k or z0.stride(1) != 1):
+        raise ValueError("z0 must be n x k with unit column stride")
+    dev = theta.device
+    if z_out is None:
+        z_out = torch.empty((n, k), dtype=torch.float64, device=dev)
+    lam = torch.empty(k, dtype=torch.float64, device=dev)
+    status = torch.empty(k, dtype=torch.int32, device=dev)
+    o = _opts(opts, kw)
+    info = Info()
+    ci, extra = _colinfo(k, colinfo)
+    st = lib.ipt_solve_dense(h.ptr, n, _ptr(theta), _ptr(delta), delta.stride(0), k, _ptr(idx), _ptr(z0),
+                             z0.stride(0) if z0 is not None else 0, C.byref(o), _ptr(z_out), z_out.stride(0),
+                             _ptr(lam), _ptr(status), C.byref(info), C.byref(ci) if ci is not None else None)
+    return _finish(lib, h, st, z_out, lam, status, info, extra)
+
+
+def ipt_solve_csr(theta, row_ptr, col, val, idx, z0=None, opts=None, handle=None, colinfo=True, **kw):
+    """Sparse IPT solve (ipt_solve_csr) with Delta in CSR form (int32 row_ptr/col,
+    f64 val) for the requested columns idx [k] int32."""
+    import torch
+    lib = load_library()
+    h = _handle(handle)
+    _check(theta, torch.float64, "theta")
+    _check(row_ptr, torch.int32, "row_ptr")
+    _check(col, torch.int32, "col")
+    _check(val, torch.float64, "val")
+    _check(idx, torch.int32, "idx")
+    _check(z0, torch.float64, "z0")
+    n = theta.shape[0]
+    k = idx.shape[0]
+    dev = theta.device
+    z = torch.empty((n, k), dtype=torch.float64, device=dev)
+    lam = torch.empty(k, dtype=torch.float64, device=dev)
+    status = torch.empty(k, dtype=torch.int32, device=dev)
+    o = _opts(opts, kw)
+    info = Info()
+    ci, extra = _colinfo(k, colinfo)
+    st = lib.ipt_solve_csr(h.ptr, n, _ptr(theta), _ptr(row_ptr), _ptr(col), _ptr(val), val.shape[0], k, _ptr(idx),
+                           _ptr(z0), z0.stride(0) if z0 is not None else 0, C.byref(o), _ptr(z), z.stride(0),
+                           _ptr(lam), _ptr(status), C.byref(info), C.byref(ci) if ci is not None else None)
+    return _finish(lib, h, st, z, lam, status, info, extra)
+
+
+def ipt_solve_batched(ns, theta_pool, delta_pool, theta_off=None, delta_off=None, opts=None, handle=None, **kw):
+    """Batched full-spectrum IPT (ipt_solve_batched).  ns: host int sequence of sizes;
+    pools are GPU f64 tensors; offsets default to the packed layout.  Returns z_pool
+    (same layout as delta_pool), lam_pool and status_pool (same layout as theta_pool)."""
+    import torch
+    lib = load_library()
+    h = _handle(handle)
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    if theta_off is None:
+        theta_off = np.concatenate([[0], np.cumsum(ns.astype(np.int64))[:-1]]).astype(np.int64)
+    if delta_off is None:
+        delta_off = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
+    theta_off = np.ascontiguousarray(theta_off, dtype=np.int64)
+    delta_off = np.ascontiguousarray(delta_off, dtype=np.int64)
+    _check(theta_pool, torch.float64, "theta_pool")
+    _check(delta_pool, torch.float64, "delta_pool")
+    z = torch.empty_like(delta_pool)
+    lam = torch.empty_like(theta_pool)
+    status = torch.empty(theta_pool.shape[0], dtype=torch.int32, device=theta_pool.device)
+    o = _opts(opts, kw)
+    info = Info()
+    hp = lambda a: a.ctypes.data_as(C.c_void_p)
+    st = lib.ipt_solve_batched(h.ptr, ns.shape[0], hp(ns), hp(theta_off), hp(delta_off), hp(delta_off),
+                               _ptr(theta_pool), _ptr(delta_pool), C.byref(o), _ptr(z), _ptr(lam), _ptr(status),
+                               C.byref(info))
+    return _finish(lib, h, st, z, lam, status, info, None)

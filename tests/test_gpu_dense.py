@@ -1,0 +1,157 @@
+"""GPU parity of the dense IPT path (C ABI ipt_solve_dense) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import dev, host, say, t
+from parity import check
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ipt():
+    from paper_2012_14702_amd import ipt as mod
+    mod.load_library()
+    dev()
+    return mod
+
+
+def _solve(ipt, theta, delta, idx=None, z0=None, **kw):
+    r = ipt.ipt_solve_dense(t(theta), t(delta), idx=None if idx is None else t(idx.astype(np.int32)),
+                            z0=None if z0 is None else t(z0), **kw)
+    return host(r)
+
+
+def test_small_full_spectrum_parity(ipt):
+    """n = 256, eps = 0.01, full spectrum, stop at max column step 1e-12."""
+    say("dense n=256 eps=0.01 fp64")
+    th, de = W.dense_sym_gaussian(256, 0.01, 0)
+    g = _solve(ipt, th, de, tol=1e-12)
+    ref = oracle.ipt_dense(th, de, tol=1e-12)
+    out = check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12, gpu_sweeps=g.sweeps)
+    assert out["compared"] == 256
+    assert np.all(np.diag(g.z) == 1.0)
+    assert abs(g.info["norm1"] - oracle.norm1(th, de)) <= 1e-13 * oracle.norm1(th, de)
+
+
+@pytest.mark.parametrize("n,k,kind,eps", [(1, 1, "full", 0.1), (2, 2, "full", 0.2), (3, 2, "rand", 0.2),
+                                          (129, 129, "full", 0.02), (300, 37, "rand", 0.03),
+                                          (257, 200, "low", 0.02), (640, 640, "full", 0.05),
+                                          (500, 130, "rand", 0.01)])
+def test_ragged_shapes(ipt, n, k, kind, eps):
+    """Sizes that are not tile multiples, subsets of columns in any order."""
+    say("dense ragged n=%d k=%d %s" % (n, k, kind))
+    th, de = W.dense_sym_gaussian(n, eps, 3)
+    rng = np.random.default_rng(n)
+    idx = {"full": None, "rand": rng.permutation(n)[:k], "low": np.arange(k)}[kind]
+    g = _solve(ipt, th, de, idx=idx, tol=1e-12)
+    ref = oracle.ipt_dense(th, de, idx=idx, tol=1e-12)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12, gpu_sweeps=g.sweeps)
+    cols = np.arange(k) if idx is None else idx
+    assert np.all(g.z[cols, np.arange(k)] == 1.0)
+
+
+def test_nonsymmetric_paper_family(ipt):
+    """The paper's non-symmetric dense family diag(i) + 0.01 R, R ~ U[0,1]."""
+    say("dense nonsym n=384")
+    th, de = W.dense_uniform_nonsym(384, 0.01, 1)
+    g = _solve(ipt, th, de, tol=1e-12)
+    ref = oracle.ipt_dense(th, de, tol=1e-12)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12, gpu_sweeps=g.sweeps)
+
+
+@pytest.mark.parametrize("eps,want", [(0.3, 0), (0.9, 1), (2.0, 2)])
+def test_two_by_two_statuses(ipt, eps, want):
+    """2x2 example: converges below sqrt(3)/2, cycles at 0.9, diverges at 2."""
+    say("dense 2x2 eps=%g" % eps)
+    th, de = W.two_by_two(eps)
+    g = _solve(ipt, th, de, tol=1e-12, max_iter=300)
+    ref = oracle.ipt_dense(th, de, tol=1e-12, max_iter=300)
+    assert np.all(ref.status == want)
+    assert np.all(g.status == want)
+    if want == 0:
+        check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12)
+
+
+def test_warm_start_resume_and_determinism(ipt):
+    """Stopping after 2 sweeps and resuming from the returned iterate equals the
+    uninterrupted solve bit for bit; two identical solves are bitwise equal."""
+    say("dense resume n=384")
+    th, de = W.dense_sym_gaussian(384, 0.03, 2)
+    full = _solve(ipt, th, de, tol=1e-12)
+    again = _solve(ipt, th, de, tol=1e-12)
+    np.testing.assert_array_equal(full.z, again.z)
+    np.testing.assert_array_equal(full.lam, again.lam)
+    part = _solve(ipt, th, de, tol=1e-12, max_iter=2)
+    assert np.all(part.status == 1)
+    res = _solve(ipt, th, de, z0=part.z, tol=1e-12)
+    np.testing.assert_array_equal(res.z, full.z)
+    np.testing.assert_array_equal(res.lam, full.lam)
+    np.testing.assert_array_equal(res.sweeps + 2, full.sweeps)
+    ref = oracle.ipt_dense(th, de, z0=part.z, tol=1e-12)
+    check(res.z, res.lam, res.status, ref, oracle.norm1(th, de), 1e-12)
+
+
+def test_invalid_arguments(ipt):
+    say("dense invalid args")
+    th, de = W.dense_sym_gaussian(64, 0.01, 0)
+    with pytest.raises(ipt.IPTError) as e:
+        _solve(ipt, th, de, idx=np.array([1, 5, 1]))
+    assert e.value.status == ipt.IPT_EINVAL
+    with pytest.raises(ipt.IPTError) as e:
+        _solve(ipt, th, de, idx=np.array([0, 64]))
+    assert e.value.status == ipt.IPT_EINVAL
+    bad = th.copy()
+    bad[7] = np.nan
+    with pytest.raises(ipt.IPTError) as e:
+        _solve(ipt, bad, de)
+    assert e.value.status == ipt.IPT_EINVAL
+    deg = th.copy()
+    deg[9] = deg[3]
+    with pytest.raises(ipt.IPTError) as e:
+        _solve(ipt, deg, de, idx=np.array([3, 20]))
+    assert e.value.status == ipt.IPT_EDEGENERATE
+    # a repeated theta outside the requested columns' gaps is fine
+    deg2 = th.copy()
+    deg2[40] = deg2[41] = 100.5
+    r = _solve(ipt, deg2, de, idx=np.array([3, 20]), tol=1e-12)
+    assert np.all(r.status == 0)
+    with pytest.raises(ipt.IPTError) as e:
+        _solve(ipt, th, de, tol=-1.0)
+    assert e.value.status == ipt.IPT_EINVAL
+
+
+@pytest.mark.parametrize("eps", [0.01, 0.05])
+@pytest.mark.parametrize("low", ["bf16", "fp16", "none"])
+def test_ladder_parity(ipt, eps, low):
+    """Precision ladder: low -> FP32 -> FP64; only FP64 sweeps certify, so the
+    answer matches the FP64 oracle to the same bounds."""
+    say("dense ladder n=1024 eps=%g low=%s" % (eps, low))
+    th, de = W.dense_sym_gaussian(1024, eps, 0)
+    lt = {"bf16": ipt.LOW_BF16, "fp16": ipt.LOW_FP16, "none": ipt.LOW_NONE}[low]
+    g = _solve(ipt, th, de, tol=1e-10, precision=ipt.PREC_LADDER, low_type=lt)
+    ref = oracle.ipt_dense(th, de, tol=1e-10)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-10)
+    assert g.info["sweep_prec"][-1] == "fp64"
+    if low != "none":
+        assert "low" in g.info["sweep_prec"]
+
+
+@pytest.mark.parametrize("eps", [0.01, 0.05])
+@pytest.mark.parametrize("prec", ["fp64", "ladder"])
+def test_large_full_spectrum_sampled(ipt, eps, prec):
+    """n = 4096 full spectrum in the benchmarked configuration; the oracle solves a
+    sample of columns (each column is an independent fixed-point problem)."""
+    say("dense n=4096 eps=%g %s" % (eps, prec))
+    th, de = W.dense_sym_gaussian(4096, eps, 0)
+    p = ipt.PREC_LADDER if prec == "ladder" else ipt.PREC_FP64
+    g = _solve(ipt, th, de, tol=1e-10, precision=p)
+    assert np.all(g.status == 0)
+    cols = np.unique(np.concatenate([[0, 1, 127, 128, 2047, 2048, 4094, 4095],
+                                     np.random.default_rng(5).integers(0, 4096, 24)])).astype(np.int32)
+    ref = oracle.ipt_dense(th, de, idx=cols, tol=1e-10, resid=False)
+    check(g.z[:, cols], g.lam[cols], g.status[cols], ref, oracle.norm1(th, de), 1e-10,
+          gpu_sweeps=g.sweeps[cols] if prec == "fp64" else None)
+    assert np.all(g.z[np.arange(4096), np.arange(4096)] == 1.0)
