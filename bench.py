@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the IPT hot path on one MI355X.
+
+A step is one full-spectrum IPT solve (setup, product-free first sweep, the
+Delta x Z sweeps with their fused epilogues, finalize, copy-out) of the dense
+n = 4096 problem D = diag(1..n), Delta = eps (R + R^T)/2, R iid N(0, 1/n), seed 0,
+with inputs already resident in HBM.  The headline value is eigenpairs/s at
+per-column relative step 1e-10 with the BF16 -> FP32 -> FP64 precision ladder
+(only FP64 sweeps certify); plain FP64 IPT on the same matrix, and eps = 0.05,
+are reported alongside.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "eigenpairs/s at rel. residual 1e-10: mixed-prec/warm-start vs plain FP64"
+PEAK = {"fp64": 78.6, "fp32": 157.3, "low": 2500.0}  # TFLOP/s, MI355X dense MFMA
+HBM_PEAK = 8000.0  # GB/s
+PROFILE = os.path.join(ROOT, "profiles", "gemm_f64_dense_n4096_traffic.txt")
+GEMM_SRC = os.path.join(ROOT, "paper_2012_14702_amd", "csrc", "ipt_gemm.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_sha():
+    return hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per FP64 GEMM launch from the committed rocprofv3 --pmc summary,
+    or None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(PROFILE):
+        return None
+    vals = {}
+    for line in open(PROFILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha") != source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def solve_many(ipt, handle, theta, delta, zbuf, opts, steps):
+    import torch
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = ipt.ipt_solve_dense(theta, delta, opts=opts, handle=handle, colinfo=False, z_out=zbuf)
+        infos.append(r.info)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, infos, r
+
+
+def gemm_stats(infos, n, prec):
+    """Algorithmic flops 2 n^2 k_active per product launch of the given precision,
+    and the summed device time of those launches (HIP events on the solve stream)."""
+    flops, ms, launches = 0.0, 0.0, 0
+    for inf in infos:
+        for p, act in zip(inf["sweep_prec"], inf["sweep_active"]):
+            if p == prec:
+                flops += 2.0 * n * n * act
+                launches += 1
+        ms += inf["prec_ms"][prec]
+    return flops, ms, launches
+
+
+def cpu_baseline(theta, delta, seconds):
+    import numpy as np
+    import oracle
+    threads = oracle.max_threads()
+    n = theta.shape[0]
+    probe = min(n, 2 * threads)
+    t0 = time.perf_counter()
+    oracle.ipt_dense(theta, delta, idx=np.arange(probe, dtype=np.int32), tol=1e-10, resid=False)
+    per_col = (time.perf_counter() - t0) / probe
+    cols = int(max(probe, min(n, seconds / max(per_col, 1e-9))))
+    cols = max(threads, cols // threads * threads)
+    idx = np.arange(cols, dtype=np.int32)
+    t0 = time.perf_counter()
+    r = oracle.ipt_dense(theta, delta, idx=idx, tol=1e-10, resid=False)
+    dt = time.perf_counter() - t0
+    conv = int((r.status == 0).sum())
+    return {"value": conv / dt, "unit": "eigenpairs/s", "cores": threads, "kind": "oracle",
+            "sample": "columns 0..%d of the same n=%d matrix (independent per-column solves, tol 1e-10, "
+                      "plain C FP64, OpenMP over columns); %.1f s" % (cols - 1, n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--eps", type=float, default=0.01)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["all", "ladder", "fp64"], default="all",
+                    help="restrict to one mode (for profiler runs)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the IPT solve here runs on a single MI355X and no multi-GPU "
+              "path is built (requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2012_14702_amd import ipt
+
+    ipt.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.n
+    handle = ipt.Handle()
+
+    def prep(eps):
+        th, de = workloads.dense_sym_gaussian(n, eps, 0)
+        return th, de, torch.from_numpy(th).to(dev), torch.from_numpy(de).to(dev)
+
+    zbuf = torch.empty((n, n), dtype=torch.float64, device=dev)
+    modes = {"ladder": dict(precision=ipt.PREC_LADDER, low_type=ipt.LOW_BF16),
+             "fp64": dict(precision=ipt.PREC_FP64)}
+    if args.only != "all":
+        modes = {args.only: modes[args.only]}
+    results = {}
+    host = {}
+    for eps in ([args.eps, 0.05] if args.only == "all" and args.eps != 0.05 else [args.eps]):
+        th, de, thd, ded = prep(eps)
+        host[eps] = (th, de)
+        for name, kw in modes.items():
+            o = ipt.default_opts(tol=1e-10, flags=ipt.FLAG_TIME_KERNELS, **kw)
+            log("eps=%g mode=%s warmup %d" % (eps, name, args.warmup))
+            solve_many(ipt, handle, thd, ded, zbuf, o, args.warmup)
+            steps = args.steps if eps == args.eps else max(3, args.steps // 4)
+            log("eps=%g mode=%s timing %d steps" % (eps, name, steps))
+            sec, infos, last = solve_many(ipt, handle, thd, ded, zbuf, o, steps)
+            conv = int(last.info["converged"])
+            results[(eps, name)] = {"sec": sec, "infos": infos, "conv": conv, "eigenpairs_per_s": conv / sec,
+                                    "device_ms": float(np.mean([i["time_ms"] for i in infos])),
+                                    "sweeps": infos[-1]["sweeps"], "sweep_prec": infos[-1]["sweep_prec"],
+                                    "sweep_max_step": [float("%.3g" % s) for s in infos[-1]["sweep_max_step"]]}
+            log("eps=%g mode=%s: %.3f ms/solve, %d converged, sweeps %s" % (
+                eps, name, sec * 1e3, conv, infos[-1]["sweep_prec"]))
+        del thd, ded
+
+    head_mode = "ladder" if "ladder" in modes else "fp64"
+    head = results[(args.eps, head_mode)]
+    # roofline of the dominant kernel (the FP64 GEMM sweep)
+    f64_flops, f64_ms, f64_launches = gemm_stats(head["infos"], n, "fp64")
+    achieved = f64_flops / (f64_ms * 1e-3) / 1e12 if f64_ms > 0 else 0.0
+    traffic = read_traffic()
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK["fp64"], 4), "traffic": traffic,
+                "kernel": "k_gemm_f64 (FP64 MFMA sweep GEMM + fused epilogue)",
+                "launches": f64_launches, "avg_launch_ms": round(f64_ms / max(f64_launches, 1), 4),
+                "flops_per_launch": f64_flops / max(f64_launches, 1)}
+    per_prec = {}
+    for prec in ("low", "fp32", "fp64", "exact-first"):
+        fl, ms, la = gemm_stats(head["infos"], n, prec)
+        if la:
+            entry = {"launches": la, "avg_launch_ms": round(ms / la, 4)}
+            if prec in PEAK:
+                entry["tflops"] = round(fl / (ms * 1e-3) / 1e12, 2)
+                entry["frac_of_peak"] = round(fl / (ms * 1e-3) / 1e12 / PEAK[prec], 4)
+            per_prec[prec] = entry
+
+    out = {
+        "metric": METRIC,
+        "value": round(head["eigenpairs_per_s"], 1),
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["sec"] * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16->f32->f64 ladder (f64 certifies)" if head_mode == "ladder" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "dense full spectrum n=%d, D=diag(1..n), Delta=eps*(R+R^T)/2, R iid N(0,1/n) "
+                               "seed 0, eps=%g, k=n, tol 1e-10 (per-column relative step)" % (n, args.eps),
+                   "mode": head_mode, "global_batch": 1, "parallelism": "none (1 GPU)"},
+        "roofline": roofline,
+        "kernels": per_prec,
+        "solve": {"%s eps=%g" % (m, e): {"eigenpairs_per_s": round(v["eigenpairs_per_s"], 1),
+                                         "ms_per_solve": round(v["sec"] * 1e3, 4), "device_ms": round(v["device_ms"], 4),
+                                         "converged": v["conv"], "sweeps": v["sweeps"], "sweep_prec": v["sweep_prec"],
+                                         "sweep_max_step": v["sweep_max_step"]}
+                  for (e, m), v in results.items()},
+    }
+    if ("fp64" in modes) and ("ladder" in modes):
+        out["ladder_speedup_vs_fp64"] = round(results[(args.eps, "fp64")]["sec"] / results[(args.eps, "ladder")]["sec"], 3)
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
+        th, de = host[args.eps]
+        out["cpu_baseline"] = cpu_baseline(th, de, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

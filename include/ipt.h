@@ -74,10 +74,14 @@ typedef struct ipt_opts {
     double tau_32;      /* ladder: leave FP32 once max step <= tau_32; default 1e-9 */
     double div_norm;    /* DIVERGED when |f_i(z) - e_i|_2 > div_norm; default 1e3 */
     int32_t div_growth; /* DIVERGED when s grew on this many consecutive FP64 sweeps; default 8 */
-    int32_t flags;      /* bit 0 (IPT_FLAG_NO_NORM): skip |M|_1 and report resid unnormalised */
+    int32_t flags;      /* IPT_FLAG_* bits */
 } ipt_opts;
 
+/* Skip |M|_1 (one extra pass over Delta) and report resid unnormalised. */
 #define IPT_FLAG_NO_NORM 1
+/* Bracket every product kernel launch with HIP events on the handle's stream and
+ * report the device time per sweep precision in ipt_info.prec_ms. */
+#define IPT_FLAG_TIME_KERNELS 2
 #define IPT_HIST 128
 
 /* Host struct filled by a solve (may be NULL). */
@@ -95,6 +99,11 @@ typedef struct ipt_info {
     int32_t sweep_prec[IPT_HIST];     /* IPT_SWEEP_* of each sweep */
     int32_t sweep_active[IPT_HIST];   /* active columns entering each sweep */
     double sweep_max_step[IPT_HIST];  /* max s_c over the active columns of each sweep */
+    /* With IPT_FLAG_TIME_KERNELS, indexed by IPT_SWEEP_*: summed device time of the
+     * kernel that computed each sweep's product (the product-free first sweep, the
+     * low-precision, FP32 or FP64 GEMM / SpMM) and the number of such sweeps. */
+    float prec_ms[4];
+    int32_t prec_sweeps[4];
 } ipt_info;
 
 /* Optional per-column device outputs (any member may be NULL). */

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "ipt_internal.h"
 
@@ -18,6 +19,7 @@ struct ipt_context {
     size_t ws_bytes = 0;
     Ctrl *host_ctrl = nullptr;  // pinned copy of the control block
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    std::vector<hipEvent_t> tev;  // kernel-timing events (IPT_FLAG_TIME_KERNELS), reused across solves
     std::string last_error;
 };
 
@@ -135,6 +137,43 @@ void fill_info(const Ctrl &c, ipt_info *info, float ms) {
     }
 }
 
+// Kernel timing: for sweep t and product slot q (0 exact-first / 1 low / 2 f32 /
+// 3 f64) a pair of events brackets the launch.  Only the launch whose precision
+// matches the sweep's does work; its time is attributed through hist_prec.
+struct Timer {
+    ipt_handle h;
+    bool on;
+    int max_iter;
+    hipError_t ensure() {
+        if (!on) return hipSuccess;
+        const size_t want = (size_t)(max_iter < IPT_HIST ? max_iter : IPT_HIST) * 8;
+        while (h->tev.size() < want) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            h->tev.push_back(e);
+        }
+        return hipSuccess;
+    }
+    hipError_t mark(int32_t t, int q, int end, hipStream_t s) {
+        if (!on || t - 1 >= IPT_HIST) return hipSuccess;
+        return hipEventRecord(h->tev[((size_t)(t - 1) * 4 + q) * 2 + end], s);
+    }
+    void collect(const Ctrl &c, ipt_info *info) {
+        if (!on || !info) return;
+        const int hl = c.sweeps < IPT_HIST ? c.sweeps : IPT_HIST;
+        for (int t = 1; t <= hl; ++t) {
+            const int q = c.hist_prec[t - 1];
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, h->tev[((size_t)(t - 1) * 4 + q) * 2], h->tev[((size_t)(t - 1) * 4 + q) * 2 + 1]) ==
+                hipSuccess) {
+                info->prec_ms[q] += ms;
+                info->prec_sweeps[q] += 1;
+            }
+        }
+    }
+};
+
 // Reads the error/done words of the control block (one small copy and a wait).
 ipt_status poll_ctrl(ipt_handle h, Ctrl *dev, int32_t &error, int32_t &done) {
     IPT_HIP(h, hipMemcpyAsync(h->host_ctrl, dev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
@@ -144,7 +183,7 @@ ipt_status poll_ctrl(ipt_handle h, Ctrl *dev, int32_t &error, int32_t &done) {
     return IPT_OK;
 }
 
-ipt_status finish(ipt_handle h, Ctrl *dev, int64_t k, ipt_info *info) {
+ipt_status finish(ipt_handle h, Ctrl *dev, int64_t k, ipt_info *info, Timer *timer) {
     IPT_HIP(h, hipEventRecord(h->ev_stop, h->stream));
     IPT_HIP(h, hipMemcpyAsync(h->host_ctrl, dev, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
     IPT_HIP(h, hipStreamSynchronize(h->stream));
@@ -155,6 +194,7 @@ ipt_status finish(ipt_handle h, Ctrl *dev, int64_t k, ipt_info *info) {
         return fail(h, IPT_EDEGENERATE, "theta_j == theta_idx[c] for some j != idx[c]: inverse gap undefined");
     if (c.error) return fail(h, IPT_EINVAL, "idx out of range or repeated, or theta not finite");
     fill_info(c, info, ms);
+    if (timer) timer->collect(c, info);
     if (c.n_conv == k) return IPT_OK;
     h->last_error = "some columns did not converge";
     return IPT_ENOTCONV;
@@ -208,6 +248,7 @@ ipt_status ipt_destroy(ipt_handle h) {
     if (h->host_ctrl) (void)hipHostFree(h->host_ctrl);
     (void)hipEventDestroy(h->ev_start);
     (void)hipEventDestroy(h->ev_stop);
+    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     delete h;
     return IPT_OK;
 }
@@ -299,6 +340,8 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     cv.base = (char *)h->ws;
     layout(cv, zb, cs, &dpart, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
 
+    Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
+    IPT_HIP(h, timer.ensure());
     IPT_HIP(h, hipEventRecord(h->ev_start, s));
     const int32_t start_prec = cold ? PREC_EXACT_FIRST : (ladder ? PREC_F32 : PREC_F64);
     IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kp, bitmap, start_prec, (int32_t)ntn, 0));
@@ -330,7 +373,9 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         const int32_t out_par = t & 1;
         double *zin = zb[(t - 1) & 1], *zout = zb[t & 1];
         if (first_exact) {
+            IPT_HIP(h, timer.mark(t, PREC_EXACT_FIRST, 0, s));
             IPT_HIP(h, launch_sweep1_dense(s, ctrl, theta, dA, ldA, cs, dpart, zout, kp, part, n, np, kp));
+            IPT_HIP(h, timer.mark(t, PREC_EXACT_FIRST, 1, s));
         } else {
             if (ladder) {
                 if (use_low) IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, lt, PREC_LOW));
@@ -338,13 +383,20 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
             }
             IPT_HIP(h, launch_diag_dense(s, ctrl, dA, ldA, zin, kp, cs, dpart, n, kp));
             if (ladder) {
-                if (use_low)
+                if (use_low) {
+                    IPT_HIP(h, timer.mark(t, PREC_LOW, 0, s));
                     IPT_HIP(h, launch_gemm_low(s, ctrl, PREC_LOW, dlo, np, zt, np, dA, ldA, zin, zout, kp, theta, cs,
                                                dpart, part, n, np, kp, t, lt));
+                    IPT_HIP(h, timer.mark(t, PREC_LOW, 1, s));
+                }
+                IPT_HIP(h, timer.mark(t, PREC_F32, 0, s));
                 IPT_HIP(h, launch_gemm_low(s, ctrl, PREC_F32, d32, np, zt, np, dA, ldA, zin, zout, kp, theta, cs,
                                            dpart, part, n, np, kp, t, LT_F32));
+                IPT_HIP(h, timer.mark(t, PREC_F32, 1, s));
             }
+            IPT_HIP(h, timer.mark(t, PREC_F64, 0, s));
             IPT_HIP(h, launch_gemm_f64(s, ctrl, dA, ldA, zin, zout, kp, theta, cs, dpart, part, n, np, kp, t));
+            IPT_HIP(h, timer.mark(t, PREC_F64, 1, s));
         }
         IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dpart, theta, part, nrt, kp, t, in_par, out_par));
         IPT_HIP(h, launch_control(s, ctrl, dopt, t));
@@ -355,7 +407,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         }
     }
     IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lambda_out, col_status, n, k, ci));
-    return finish(h, ctrl, k, info);
+    return finish(h, ctrl, k, info, &timer);
 }
 
 ipt_status ipt_solve_csr(ipt_handle h, int64_t, const double *, const int32_t *, const int32_t *, const double *,

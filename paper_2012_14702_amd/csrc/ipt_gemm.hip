@@ -169,50 +169,56 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const Ctrl *ctrl, const dou
     const int a_r = t >> 3, a_k = 2 * (t & 7);
     const int b_r = t >> 4, b_c = (t & 15) * 8;
 
-    double2 ra[4], rb[4];
-    auto gload = [&](int64_t k0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ra[q] = *(const double2 *)(Ab + (int64_t)(a_r + 32 * q) * lda + k0 + a_k);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rb[q] = *(const double2 *)(Bb + (k0 + b_r) * ldzb + b_c + 2 * q);
-    };
-    auto sstore = [&](int s) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            As[s][a_r + 32 * q][a_k] = ra[q].x;
-            As[s][a_r + 32 * q][a_k + 1] = ra[q].y;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *(double2 *)&Bs[s][b_r][b_c + 2 * q] = rb[q];
-    };
-
     d4_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
 
+    // Register staging of the next K slice: issued before the MFMAs of the current
+    // slice, written to the idle LDS stage after them (one barrier per slice).  The
+    // last iteration re-reads its own slice into the idle stage, which keeps the
+    // loop free of branches.
+    double2 ra[4], rb[4];
     const int nk = (int)(np / BK64);
-    gload(0);
-    sstore(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = *(const double2 *)(Ab + (int64_t)(a_r + 32 * q) * lda + a_k);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rb[q] = *(const double2 *)(Bb + (int64_t)b_r * ldzb + b_c + 2 * q);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        As[0][a_r + 32 * q][a_k] = ra[q].x;
+        As[0][a_r + 32 * q][a_k + 1] = ra[q].y;
+        *(double2 *)&Bs[0][b_r][b_c + 2 * q] = rb[q];
+    }
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK64);
+        const int64_t kn = (int64_t)(kt + 1 < nk ? kt + 1 : kt) * BK64;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[q] = *(const double2 *)(Ab + (int64_t)(a_r + 32 * q) * lda + kn + a_k);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rb[q] = *(const double2 *)(Bb + (kn + b_r) * ldzb + b_c + 2 * q);
 #pragma unroll
         for (int kk = 0; kk < BK64 / 4; ++kk) {
-            double a[4], b[4];
+            double fa[4], fb[4];
 #pragma unroll
-            for (int ib = 0; ib < 4; ++ib) a[ib] = As[cur][wm * 64 + 16 * ib + (lane & 15)][4 * kk + (lane >> 4)];
+            for (int ib = 0; ib < 4; ++ib) fa[ib] = As[cur][wm * 64 + 16 * ib + (lane & 15)][4 * kk + (lane >> 4)];
 #pragma unroll
-            for (int jb = 0; jb < 4; ++jb) b[jb] = Bs[cur][4 * kk + (lane >> 4)][wn * 64 + 16 * jb + (lane & 15)];
+            for (int jb = 0; jb < 4; ++jb) fb[jb] = Bs[cur][4 * kk + (lane >> 4)][wn * 64 + 16 * jb + (lane & 15)];
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb)
-                    acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ib], b[jb], acc[ib][jb], 0, 0, 0);
+                    acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[ib], fb[jb], acc[ib][jb], 0, 0, 0);
         }
-        if (kt + 1 < nk) sstore(cur ^ 1);
+        const int nx = cur ^ 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[nx][a_r + 32 * q][a_k] = ra[q].x;
+            As[nx][a_r + 32 * q][a_k + 1] = ra[q].y;
+            *(double2 *)&Bs[nx][b_r][b_c + 2 * q] = rb[q];
+        }
         __syncthreads();
     }
 
@@ -254,6 +260,31 @@ __device__ inline f4_t mfma_low<float>(const float *a, const float *b, f4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0);
 }
 
+// Staged 16-byte chunks -> LDS tile rows (row l_r + 32 q, elements l_c ..).
+template <typename T, int EPC, int LDP>
+__device__ __forceinline__ void lds_put(T (*as)[LDP], T (*bs)[LDP], const uint4 *ra, const uint4 *rb, int l_r,
+                                        int l_c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if constexpr ((LDP * sizeof(T)) % 16 == 0) {
+            *(uint4 *)&as[l_r + 32 * q][l_c] = ra[q];
+            *(uint4 *)&bs[l_r + 32 * q][l_c] = rb[q];
+        } else {
+            union {
+                uint4 u;
+                T e[EPC];
+            } ua, ub;
+            ua.u = ra[q];
+            ub.u = rb[q];
+#pragma unroll
+            for (int e2 = 0; e2 < EPC; ++e2) {
+                as[l_r + 32 * q][l_c + e2] = ua.e[e2];
+                bs[l_r + 32 * q][l_c + e2] = ub.e[e2];
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_gemm_low(const Ctrl *ctrl, int32_t want_prec, const T *__restrict__ dlo,
                                                      int64_t ldd, const T *__restrict__ zt, int64_t ldt,
@@ -283,59 +314,38 @@ __global__ __launch_bounds__(256, 2) void k_gemm_low(const Ctrl *ctrl, int32_t w
     const int l_r = t >> 3, l_c = (t & 7) * EPC;
     const T *Ab = dlo + (int64_t)tm * BM * ldd;
     const T *Bb = zt + (int64_t)tn * BN * ldt;
-    uint4 ra[4], rb[4];
-    auto gload = [&](int64_t k0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ra[q] = *(const uint4 *)(Ab + (int64_t)(l_r + 32 * q) * ldd + k0 + l_c);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rb[q] = *(const uint4 *)(Bb + (int64_t)(l_r + 32 * q) * ldt + k0 + l_c);
-    };
-    auto sstore = [&](int s) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if constexpr (C::PAD % EPC == 0) {
-                *(uint4 *)&As[s][l_r + 32 * q][l_c] = ra[q];
-                *(uint4 *)&Bs[s][l_r + 32 * q][l_c] = rb[q];
-            } else {
-                const T *pa = (const T *)&ra[q];
-                const T *pb = (const T *)&rb[q];
-#pragma unroll
-                for (int e2 = 0; e2 < EPC; ++e2) {
-                    As[s][l_r + 32 * q][l_c + e2] = pa[e2];
-                    Bs[s][l_r + 32 * q][l_c + e2] = pb[e2];
-                }
-            }
-        }
-    };
-
     f4_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
 
+    uint4 ra[4], rb[4];
     const int nk = (int)(np / BK);
-    gload(0);
-    sstore(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = *(const uint4 *)(Ab + (int64_t)(l_r + 32 * q) * ldd + l_c);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rb[q] = *(const uint4 *)(Bb + (int64_t)(l_r + 32 * q) * ldt + l_c);
+    lds_put<T, EPC, LDP>(As[0], Bs[0], ra, rb, l_r, l_c);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+        const int64_t kn = (int64_t)(kt + 1 < nk ? kt + 1 : kt) * BK;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[q] = *(const uint4 *)(Ab + (int64_t)(l_r + 32 * q) * ldd + kn + l_c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rb[q] = *(const uint4 *)(Bb + (int64_t)(l_r + 32 * q) * ldt + kn + l_c);
 #pragma unroll
         for (int kk = 0; kk < BK / C::KSTEP; ++kk) {
             const int koff = kk * C::KSTEP + C::VEC * (lane >> 4);
-            const T *a[4];
-            const T *b[4];
-#pragma unroll
-            for (int ib = 0; ib < 4; ++ib) a[ib] = &As[cur][wm * 64 + 16 * ib + (lane & 15)][koff];
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb) b[jb] = &Bs[cur][wn * 64 + 16 * jb + (lane & 15)][koff];
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-                for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = mfma_low<T>(a[ib], b[jb], acc[ib][jb]);
+                for (int jb = 0; jb < 4; ++jb)
+                    acc[ib][jb] = mfma_low<T>(&As[cur][wm * 64 + 16 * ib + (lane & 15)][koff],
+                                              &Bs[cur][wn * 64 + 16 * jb + (lane & 15)][koff], acc[ib][jb]);
         }
-        if (kt + 1 < nk) sstore(cur ^ 1);
+        lds_put<T, EPC, LDP>(As[cur ^ 1], Bs[cur ^ 1], ra, rb, l_r, l_c);
         __syncthreads();
     }
 

@@ -19,6 +19,7 @@ LOW_BF16, LOW_FP16, LOW_NONE = 0, 1, 2
 SWEEP_NAMES = {0: "exact-first", 1: "low", 2: "fp32", 3: "fp64"}
 IPT_HIST = 128
 FLAG_NO_NORM = 1
+FLAG_TIME_KERNELS = 2
 
 
 class Opts(C.Structure):
@@ -32,7 +33,8 @@ class Info(C.Structure):
                 ("diverged", C.c_int32), ("matvecs", C.c_int64), ("max_step", C.c_double), ("norm1", C.c_double),
                 ("max_resid", C.c_double), ("time_ms", C.c_float), ("hist_len", C.c_int32),
                 ("sweep_prec", C.c_int32 * IPT_HIST), ("sweep_active", C.c_int32 * IPT_HIST),
-                ("sweep_max_step", C.c_double * IPT_HIST)]
+                ("sweep_max_step", C.c_double * IPT_HIST), ("prec_ms", C.c_float * 4),
+                ("prec_sweeps", C.c_int32 * 4)]
 
     def as_dict(self):
         h = self.hist_len
@@ -40,7 +42,9 @@ class Info(C.Structure):
                 "diverged": self.diverged, "matvecs": self.matvecs, "max_step": self.max_step,
                 "norm1": self.norm1, "max_resid": self.max_resid, "time_ms": self.time_ms,
                 "sweep_prec": [SWEEP_NAMES[p] for p in self.sweep_prec[:h]],
-                "sweep_active": list(self.sweep_active[:h]), "sweep_max_step": list(self.sweep_max_step[:h])}
+                "sweep_active": list(self.sweep_active[:h]), "sweep_max_step": list(self.sweep_max_step[:h]),
+                "prec_ms": {SWEEP_NAMES[q]: self.prec_ms[q] for q in range(4)},
+                "prec_sweeps": {SWEEP_NAMES[q]: self.prec_sweeps[q] for q in range(4)}}
 
 
 class ColInfo(C.Structure):
