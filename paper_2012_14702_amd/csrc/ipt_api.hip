@@ -137,16 +137,15 @@ void fill_info(const Ctrl &c, ipt_info *info, float ms) {
     }
 }
 
-// Kernel timing: for sweep t and product slot q (0 exact-first / 1 low / 2 f32 /
-// 3 f64) a pair of events brackets the launch.  Only the launch whose precision
-// matches the sweep's does work; its time is attributed through hist_prec.
+// Kernel timing: one pair of events brackets the product launch of each sweep;
+// the time is attributed to the sweep's precision through hist_prec.
 struct Timer {
     ipt_handle h;
     bool on;
     int max_iter;
     hipError_t ensure() {
         if (!on) return hipSuccess;
-        const size_t want = (size_t)(max_iter < IPT_HIST ? max_iter : IPT_HIST) * 8;
+        const size_t want = (size_t)(max_iter < IPT_HIST ? max_iter : IPT_HIST) * 2;
         while (h->tev.size() < want) {
             hipEvent_t e;
             hipError_t err = hipEventCreate(&e);
@@ -155,9 +154,9 @@ struct Timer {
         }
         return hipSuccess;
     }
-    hipError_t mark(int32_t t, int q, int end, hipStream_t s) {
+    hipError_t mark(int32_t t, int end, hipStream_t s) {
         if (!on || t - 1 >= IPT_HIST) return hipSuccess;
-        return hipEventRecord(h->tev[((size_t)(t - 1) * 4 + q) * 2 + end], s);
+        return hipEventRecord(h->tev[(size_t)(t - 1) * 2 + end], s);
     }
     void collect(const Ctrl &c, ipt_info *info) {
         if (!on || !info) return;
@@ -165,14 +164,27 @@ struct Timer {
         for (int t = 1; t <= hl; ++t) {
             const int q = c.hist_prec[t - 1];
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, h->tev[((size_t)(t - 1) * 4 + q) * 2], h->tev[((size_t)(t - 1) * 4 + q) * 2 + 1]) ==
-                hipSuccess) {
+            if (hipEventElapsedTime(&ms, h->tev[(size_t)(t - 1) * 2], h->tev[(size_t)(t - 1) * 2 + 1]) == hipSuccess) {
                 info->prec_ms[q] += ms;
                 info->prec_sweeps[q] += 1;
             }
         }
     }
 };
+
+// Host polling of the device stop flag: after the first `first` sweeps, then every
+// `every` sweeps, and always at max_iter.  Sweeps launched after the device has
+// set its done flag return at once.
+struct PollPlan {
+    int first, every;
+    bool at(int t, int max_iter) const { return t == max_iter || t == first || (t > first && (t - first) % every == 0); }
+};
+
+PollPlan poll_plan(const ipt_opts &o, bool cold) {
+    if (o.sync_every > 0) return PollPlan{o.sync_every, o.sync_every};
+    // A cold start certifies after about four sweeps on well-separated spectra.
+    return PollPlan{cold ? 4 : 3, 1};
+}
 
 // Reads the error/done words of the control block (one small copy and a wait).
 ipt_status poll_ctrl(ipt_handle h, Ctrl *dev, int32_t &error, int32_t &done) {
@@ -302,11 +314,12 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     const bool use_low = ladder && o.low_type != IPT_LOW_NONE;
 
     // Workspace layout (sizes first, then carve).
-    auto layout = [&](Carve &cv, double **zb, ColState &cs, double **dpart, double **part, uint32_t **bitmap,
+    auto layout = [&](Carve &cv, double **zb, ColState &cs, double **dpart, double **dvec, double **part, uint32_t **bitmap,
                       double **scratch, double **dpad, void **dlo, float **d32, void **zt, Ctrl **ctrl) {
         zb[0] = cv.take<double>(np * kp);
         zb[1] = cv.take<double>(np * kp);
         *dpart = cv.take<double>(DIAG_SPLIT * kp);
+        *dvec = cv.take<double>(kp);
         *part = cv.take<double>(nrt * kp * NPART);
         cs.state = cv.take<int32_t>(kp);
         cs.sweeps = cv.take<int32_t>(kp);
@@ -319,7 +332,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         cs.lam = cv.take<double>(kp);
         cs.resid = cv.take<double>(kp);
         *bitmap = cv.take<uint32_t>((n + 31) / 32);
-        *scratch = norm ? cv.take<double>(64 * n > 2 * n ? 64 * n : 2 * n) : nullptr;
+        *scratch = norm ? cv.take<double>(((np + 255) / 256) * n) : nullptr;
         *dpad = direct ? nullptr : cv.take<double>(np * np);
         *dlo = use_low ? (void *)cv.take<uint16_t>(np * np) : nullptr;
         *d32 = ladder ? cv.take<float>(np * np) : nullptr;
@@ -328,17 +341,17 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     };
     double *zb[2];
     ColState cs;
-    double *dpart, *part, *scratch, *dpad;
+    double *dpart, *dvec, *part, *scratch, *dpad;
     uint32_t *bitmap;
     void *dlo, *zt;
     float *d32;
     Ctrl *ctrl;
     Carve sizing;
-    layout(sizing, zb, cs, &dpart, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
+    layout(sizing, zb, cs, &dpart, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
     if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
     Carve cv;
     cv.base = (char *)h->ws;
-    layout(cv, zb, cs, &dpart, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
+    layout(cv, zb, cs, &dpart, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
 
     Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
     IPT_HIP(h, timer.ensure());
@@ -346,61 +359,41 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     const int32_t start_prec = cold ? PREC_EXACT_FIRST : (ladder ? PREC_F32 : PREC_F64);
     IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kp, bitmap, start_prec, (int32_t)ntn, 0));
     IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
-    if (norm) IPT_HIP(h, launch_norm1_dense(s, ctrl, theta, delta, lda, n, scratch));
-    const double *dA = delta;
-    int64_t ldA = lda;
-    if (!direct) {
-        IPT_HIP(h, launch_copy_pad(s, delta, lda, dpad, np, n, np));
-        dA = dpad;
-        ldA = np;
-    }
-    if (ladder) {
-        if (use_low && lt == LT_F16) IPT_HIP(h, launch_absmax(s, ctrl, dA, n, n, ldA));
-        if (use_low) IPT_HIP(h, launch_cast_delta(s, ctrl, dA, ldA, dlo, np, n, np, lt));
-        IPT_HIP(h, launch_cast_delta(s, ctrl, dA, ldA, d32, np, n, np, LT_F32));
-    }
+    if (use_low && lt == LT_F16) IPT_HIP(h, launch_absmax(s, ctrl, delta, n, n, lda));
+    const double *dA = direct ? delta : dpad;
+    const int64_t ldA = direct ? lda : np;
+    if (!direct || ladder || norm)
+        IPT_HIP(h, launch_prep_delta(s, ctrl, theta, delta, lda, n, np, direct ? nullptr : dpad,
+                                     use_low ? dlo : nullptr, lt, ladder ? d32 : nullptr, norm ? scratch : nullptr));
+    const bool padded = (np != n) || (kp != k);
     if (cold) {
-        IPT_HIP(h, launch_zero_pad(s, zb[0], kp, n, np, k, kp));
+        if (padded) IPT_HIP(h, launch_zero_pad(s, zb[0], kp, n, np, k, kp));
     } else {
         IPT_HIP(h, launch_load_z0(s, ctrl, z0, ldz0, zb[0], kp, cs.idx, n, np, k, kp));
-        IPT_HIP(h, launch_zero_pad(s, zb[1], kp, n, np, k, kp));
+        if (padded) IPT_HIP(h, launch_zero_pad(s, zb[1], kp, n, np, k, kp));
     }
 
-    const int sync_every = o.sync_every > 0 ? o.sync_every : 1;
+    const PollPlan plan = poll_plan(o, cold);
     for (int32_t t = 1; t <= o.max_iter; ++t) {
         const bool first_exact = cold && t == 1;
         const int32_t in_par = first_exact ? PAR_UNIT : ((t - 1) & 1);
         const int32_t out_par = t & 1;
         double *zin = zb[(t - 1) & 1], *zout = zb[t & 1];
         if (first_exact) {
-            IPT_HIP(h, timer.mark(t, PREC_EXACT_FIRST, 0, s));
-            IPT_HIP(h, launch_sweep1_dense(s, ctrl, theta, dA, ldA, cs, dpart, zout, kp, part, n, np, kp));
-            IPT_HIP(h, timer.mark(t, PREC_EXACT_FIRST, 1, s));
+            IPT_HIP(h, timer.mark(t, 0, s));
+            IPT_HIP(h, launch_sweep1_dense(s, ctrl, theta, dA, ldA, cs, dvec, zout, kp, part, n, np, kp));
+            IPT_HIP(h, timer.mark(t, 1, s));
         } else {
-            if (ladder) {
-                if (use_low) IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, lt, PREC_LOW));
-                IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, LT_F32, PREC_F32));
-            }
-            IPT_HIP(h, launch_diag_dense(s, ctrl, dA, ldA, zin, kp, cs, dpart, n, kp));
-            if (ladder) {
-                if (use_low) {
-                    IPT_HIP(h, timer.mark(t, PREC_LOW, 0, s));
-                    IPT_HIP(h, launch_gemm_low(s, ctrl, PREC_LOW, dlo, np, zt, np, dA, ldA, zin, zout, kp, theta, cs,
-                                               dpart, part, n, np, kp, t, lt));
-                    IPT_HIP(h, timer.mark(t, PREC_LOW, 1, s));
-                }
-                IPT_HIP(h, timer.mark(t, PREC_F32, 0, s));
-                IPT_HIP(h, launch_gemm_low(s, ctrl, PREC_F32, d32, np, zt, np, dA, ldA, zin, zout, kp, theta, cs,
-                                           dpart, part, n, np, kp, t, LT_F32));
-                IPT_HIP(h, timer.mark(t, PREC_F32, 1, s));
-            }
-            IPT_HIP(h, timer.mark(t, PREC_F64, 0, s));
-            IPT_HIP(h, launch_gemm_f64(s, ctrl, dA, ldA, zin, zout, kp, theta, cs, dpart, part, n, np, kp, t));
-            IPT_HIP(h, timer.mark(t, PREC_F64, 1, s));
+            if (ladder) IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, lt));
+            IPT_HIP(h, launch_diag_dense(s, ctrl, dA, ldA, zin, kp, cs, dpart, dvec, n, kp));
+            IPT_HIP(h, timer.mark(t, 0, s));
+            IPT_HIP(h, launch_sweep_gemm(s, ctrl, dA, ldA, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, t,
+                                         lt));
+            IPT_HIP(h, timer.mark(t, 1, s));
         }
-        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dpart, theta, part, nrt, kp, t, in_par, out_par));
+        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, nrt, kp, t, in_par, out_par));
         IPT_HIP(h, launch_control(s, ctrl, dopt, t));
-        if (t % sync_every == 0 || t == o.max_iter) {
+        if (plan.at(t, o.max_iter)) {
             int32_t err, done;
             if (ipt_status st = poll_ctrl(h, ctrl, err, done)) return st;
             if (err || done) break;

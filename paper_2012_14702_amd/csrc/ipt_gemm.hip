@@ -6,7 +6,9 @@
 // kernel).  By F(Z) - Z = -G o (M Z - Z Lambda), the third sum is the squared
 // eigen-residual |M z - lambda z|^2 of the column.
 //
-// Two kernels:
+// One kernel per sweep; the precision of the sweep is read from the device control
+// block (the ladder is decided on the device, so the host never waits between
+// sweeps) and selects one of two bodies:
 //  * FP64: v_mfma_f64_16x16x4f64, 128x128 block tile, 4 waves of 64x64, BK = 16,
 //    double-buffered LDS.  Delta (padded to a multiple of 128) and Z are read in place.
 //  * low precision (BF16 / FP16 with v_mfma_f32_16x16x32_*, FP32 with
@@ -22,7 +24,6 @@ namespace ipt {
 
 namespace {
 
-constexpr int kDiagSplit = DIAG_SPLIT;
 constexpr int BM = TILE_M, BN = TILE_N;
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -48,22 +49,34 @@ __device__ inline void tile_of(int bid, int nblocks, int ntm, int ntn, int &tm, 
     tn = in / gsz;
 }
 
+// Everything a sweep GEMM needs (one struct keeps the kernel signature short).
+struct GemmArgs {
+    const double *delta;  // FP64 Delta (padded to np rows when copied), leading dimension lda
+    int64_t lda;
+    const void *dlo;      // low-precision Delta shadow (np x np, leading dimension np)
+    const float *d32;     // FP32 Delta shadow (np x np)
+    const void *zt;       // transposed shadow of Z - E (kp x np)
+    const double *zin;    // iterate Z (np x kp)
+    double *zout;         // W = F(Z)
+    const double *theta;
+    ColState cs;
+    const double *dvec;   // d_c
+    double *part;         // partial sums [row tile][column][NPART]
+    int64_t n, np, kp;
+    int32_t low_type;     // LT_BF16 or LT_F16
+};
+
+constexpr int SMEM_F64 = 2 * BM * (16 + 1) * 8 + 2 * 16 * BN * 8;
+constexpr int SMEM_LOW16 = 2 * 2 * BM * (64 + 8) * 2;
+constexpr int SMEM_LOW32 = 2 * 2 * BM * (32 + 1) * 4;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int SMEM_MAIN = cmax(SMEM_F64, cmax(SMEM_LOW16, SMEM_LOW32));
+
 // Shared epilogue.  Each lane holds 4 column blocks (jb) x 16 rows of the block
 // tile; row_of(ib, r) gives the tile row of accumulator (ib, r), which depends on
 // the MFMA family.  y_of(ib, jb, r, j, i) returns the FP64 product value.
-struct EpiCtx {
-    const double *theta;
-    const double *zin;
-    double *zout;
-    int64_t ldzb;
-    ColState cs;
-    const double *dpart;
-    double *part;
-    int64_t n, kp;
-};
-
 template <class RowOf, class YOf>
-__device__ inline void sweep_epilogue(const EpiCtx &e, int tm, int tn, int wm, int wn, int lane, RowOf row_of,
+__device__ inline void sweep_epilogue(const GemmArgs &e, int tm, int tn, int wm, int wn, int lane, RowOf row_of,
                                       YOf y_of, double (*red)[BN][NPART]) {
     int64_t cols[4];
     int32_t ii[4];
@@ -76,10 +89,9 @@ __device__ inline void sweep_epilogue(const EpiCtx &e, int tm, int tn, int wm, i
         act[jb] = e.cs.state[c] == COL_ACTIVE;
         ii[jb] = e.cs.idx[c];
         ti[jb] = e.theta[ii[jb]];
-        double d = 0.0;
-        for (int s = 0; s < kDiagSplit; ++s) d += e.dpart[(int64_t)s * e.kp + c];
-        dd[jb] = d;
+        dd[jb] = e.dvec[c];
     }
+    const int64_t ldzb = e.kp;
     double sums[4][NPART];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
@@ -96,7 +108,7 @@ __device__ inline void sweep_epilogue(const EpiCtx &e, int tm, int tn, int wm, i
             for (int jb = 0; jb < 4; ++jb) {
                 if (!act[jb]) continue;
                 const int64_t c = cols[jb];
-                const double z = e.zin[j * e.ldzb + c];
+                const double z = e.zin[j * ldzb + c];
                 double w, st, gs, de;
                 if (j == ii[jb]) {
                     w = 1.0;
@@ -111,7 +123,7 @@ __device__ inline void sweep_epilogue(const EpiCtx &e, int tm, int tn, int wm, i
                     gs = gap * st;
                     de = w;
                 }
-                e.zout[j * e.ldzb + c] = w;
+                e.zout[j * ldzb + c] = w;
                 sums[jb][0] += st * st;
                 sums[jb][1] += z * z;
                 sums[jb][2] += gs * gs;
@@ -148,24 +160,17 @@ __device__ inline void sweep_epilogue(const EpiCtx &e, int tm, int tn, int wm, i
 // ------------------------------------------------------------------- FP64
 constexpr int BK64 = 16;
 
-__global__ __launch_bounds__(256, 2) void k_gemm_f64(const Ctrl *ctrl, const double *__restrict__ delta, int64_t lda,
-                                                     const double *__restrict__ zin, double *__restrict__ zout,
-                                                     int64_t ldzb, const double *__restrict__ theta, ColState cs,
-                                                     const double *__restrict__ dpart, double *__restrict__ part,
-                                                     int64_t n, int64_t np, int64_t kp, int32_t sweep) {
-    if (ctrl->error || ctrl->done || ctrl->prec != PREC_F64) return;
-    const int ntm = (int)(np / BM), ntn = (int)(kp / BN);
-    int tm, tn;
-    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
-    if (cs.tile_stamp[tn] != sweep - 1) return;  // no active column in this column tile
-
-    __shared__ double As[2][BM][BK64 + 1];
-    __shared__ double Bs[2][BK64][BN];
-    __shared__ double red[2][BN][NPART];
+__device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPART], const GemmArgs &g, int tm,
+                                              int tn) {
+    typedef double ATile[BM][BK64 + 1];
+    typedef double BTile[BK64][BN];
+    ATile *As = (ATile *)smem;
+    BTile *Bs = (BTile *)(smem + 2 * sizeof(ATile));
 
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
-    const double *Ab = delta + (int64_t)tm * BM * lda;
-    const double *Bb = zin + (int64_t)tn * BN;
+    const int64_t lda = g.lda, ldzb = g.kp;
+    const double *Ab = g.delta + (int64_t)tm * BM * lda;
+    const double *Bb = g.zin + (int64_t)tn * BN;
     const int a_r = t >> 3, a_k = 2 * (t & 7);
     const int b_r = t >> 4, b_c = (t & 15) * 8;
 
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const Ctrl *ctrl, const dou
     // last iteration re-reads its own slice into the idle stage, which keeps the
     // loop free of branches.
     double2 ra[4], rb[4];
-    const int nk = (int)(np / BK64);
+    const int nk = (int)(g.np / BK64);
 #pragma unroll
     for (int q = 0; q < 4; ++q) ra[q] = *(const double2 *)(Ab + (int64_t)(a_r + 32 * q) * lda + a_k);
 #pragma unroll
@@ -222,11 +227,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const Ctrl *ctrl, const dou
         __syncthreads();
     }
 
-    EpiCtx e{theta, zin, zout, ldzb, cs, dpart, part, n, kp};
     // v_mfma_f64_16x16x4f64: lane l, register r holds row 4r + l/16, column l%16.
     auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * r + (l >> 4); };
     auto y_of = [&](int ib, int jb, int r, int64_t, int32_t) { return acc[ib][jb][r]; };
-    sweep_epilogue(e, tm, tn, wm, wn, lane, row_of, y_of, red);
+    sweep_epilogue(g, tm, tn, wm, wn, lane, row_of, y_of, red);
 }
 
 // ------------------------------------------------------------ low precision
@@ -286,34 +290,23 @@ __device__ __forceinline__ void lds_put(T (*as)[LDP], T (*bs)[LDP], const uint4 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_gemm_low(const Ctrl *ctrl, int32_t want_prec, const T *__restrict__ dlo,
-                                                     int64_t ldd, const T *__restrict__ zt, int64_t ldt,
-                                                     const double *__restrict__ delta, int64_t lda,
-                                                     const double *__restrict__ zin, double *__restrict__ zout,
-                                                     int64_t ldzb, const double *__restrict__ theta, ColState cs,
-                                                     const double *__restrict__ dpart, double *__restrict__ part,
-                                                     int64_t n, int64_t np, int64_t kp, int32_t sweep,
-                                                     bool scaled) {
-    if (ctrl->error || ctrl->done || ctrl->prec != want_prec) return;
-    const double unscale = scaled ? 1.0 / (ctrl->dscale * ctrl->zscale) : 1.0;
+__device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPART], const GemmArgs &g, const T *dlo,
+                                              double unscale, int tm, int tn) {
     using C = LowCfg<T>;
     constexpr int BK = C::BK, LDP = C::BK + C::PAD;
-    const int ntm = (int)(np / BM), ntn = (int)(kp / BN);
-    int tm, tn;
-    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
-    if (cs.tile_stamp[tn] != sweep - 1) return;
-
-    __shared__ __attribute__((aligned(16))) T As[2][BM][LDP];
-    __shared__ __attribute__((aligned(16))) T Bs[2][BN][LDP];
-    __shared__ double red[2][BN][NPART];
+    typedef T Tile[BM][LDP];
+    Tile *As = (Tile *)smem;
+    Tile *Bs = (Tile *)(smem + 2 * sizeof(Tile));
 
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
     // Each block row of BK elements is 128 bytes = 8 chunks of 16 bytes; 256 threads
-    // move 4 rows' worth of chunks per pass, 4 passes cover 128 rows.
+    // move 32 rows' worth of chunks per pass, 4 passes cover 128 rows.
     constexpr int EPC = 16 / sizeof(T);  // elements per 16-byte chunk
     const int l_r = t >> 3, l_c = (t & 7) * EPC;
+    const int64_t ldd = g.np, ldt = g.np;
     const T *Ab = dlo + (int64_t)tm * BM * ldd;
-    const T *Bb = zt + (int64_t)tn * BN * ldt;
+    const T *Bb = (const T *)g.zt + (int64_t)tn * BN * ldt;
+
     f4_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -321,7 +314,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_low(const Ctrl *ctrl, int32_t w
         for (int b = 0; b < 4; ++b) acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
 
     uint4 ra[4], rb[4];
-    const int nk = (int)(np / BK);
+    const int nk = (int)(g.np / BK);
 #pragma unroll
     for (int q = 0; q < 4; ++q) ra[q] = *(const uint4 *)(Ab + (int64_t)(l_r + 32 * q) * ldd + l_c);
 #pragma unroll
@@ -349,42 +342,48 @@ __global__ __launch_bounds__(256, 2) void k_gemm_low(const Ctrl *ctrl, int32_t w
         __syncthreads();
     }
 
-    EpiCtx e{theta, zin, zout, ldzb, cs, dpart, part, n, kp};
     // f32-accumulating 16x16 MFMAs: lane l, register r holds row 4(l/16) + r, column l%16.
+    const double *delta = g.delta;
+    const int64_t lda = g.lda;
     auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * (l >> 4) + r; };
     auto y_of = [&](int ib, int jb, int r, int64_t j, int32_t i) {
         return delta[j * lda + i] + unscale * (double)acc[ib][jb][r];
     };
-    sweep_epilogue(e, tm, tn, wm, wn, lane, row_of, y_of, red);
+    sweep_epilogue(g, tm, tn, wm, wn, lane, row_of, y_of, red);
+}
+
+// One sweep's product and epilogue, in the precision the ladder chose for it.
+__global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArgs g, int32_t sweep) {
+    if (ctrl->error || ctrl->done) return;
+    const int32_t prec = ctrl->prec;
+    const int ntm = (int)(g.np / BM), ntn = (int)(g.kp / BN);
+    int tm, tn;
+    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
+    if (g.cs.tile_stamp[tn] != sweep - 1) return;  // no active column in this column tile
+    __shared__ __attribute__((aligned(16))) char smem[SMEM_MAIN];
+    __shared__ double red[2][BN][NPART];
+    if (prec == PREC_F64) {
+        gemm_f64_body(smem, red, g, tm, tn);
+    } else if (prec == PREC_F32) {
+        gemm_low_body<float>(smem, red, g, g.d32, 1.0, tm, tn);
+    } else if (prec == PREC_LOW) {
+        if (g.low_type == LT_F16)
+            gemm_low_body<_Float16>(smem, red, g, (const _Float16 *)g.dlo, 1.0 / (ctrl->dscale * ctrl->zscale), tm,
+                                    tn);
+        else
+            gemm_low_body<__bf16>(smem, red, g, (const __bf16 *)g.dlo, 1.0, tm, tn);
+    }
 }
 
 }  // namespace
 
-hipError_t launch_gemm_f64(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
-                           double *zout, int64_t ldzb, const double *theta, ColState cs, const double *dpart,
-                           double *part, int64_t n, int64_t np, int64_t kp, int32_t sweep) {
+hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const void *dlo,
+                             const float *d32, const void *zt, const double *zin, double *zout, const double *theta,
+                             ColState cs, const double *dvec, double *part, int64_t n, int64_t np, int64_t kp,
+                             int32_t sweep, int32_t low_type) {
+    GemmArgs g{delta, lda, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, low_type};
     const int blocks = (int)((np / BM) * (kp / BN));
-    k_gemm_f64<<<blocks, 256, 0, s>>>(ctrl, delta, lda, zin, zout, ldzb, theta, cs, dpart, part, n, np, kp, sweep);
-    return hipGetLastError();
-}
-
-hipError_t launch_gemm_low(hipStream_t s, const Ctrl *ctrl, int32_t want_prec, const void *dlo, int64_t ldd,
-                           const void *zt, int64_t ldt, const double *delta, int64_t lda, const double *zin,
-                           double *zout, int64_t ldzb, const double *theta, ColState cs, const double *dpart,
-                           double *part, int64_t n, int64_t np, int64_t kp, int32_t sweep, int32_t type) {
-    const int blocks = (int)((np / BM) * (kp / BN));
-    if (type == LT_F32)
-        k_gemm_low<float><<<blocks, 256, 0, s>>>(ctrl, want_prec, (const float *)dlo, ldd, (const float *)zt, ldt, delta,
-                                                 lda, zin, zout, ldzb, theta, cs, dpart, part, n, np, kp, sweep,
-                                                 false);
-    else if (type == LT_BF16)
-        k_gemm_low<__bf16><<<blocks, 256, 0, s>>>(ctrl, want_prec, (const __bf16 *)dlo, ldd, (const __bf16 *)zt, ldt,
-                                                  delta, lda, zin, zout, ldzb, theta, cs, dpart, part, n, np, kp, sweep,
-                                                  false);
-    else
-        k_gemm_low<_Float16><<<blocks, 256, 0, s>>>(ctrl, want_prec, (const _Float16 *)dlo, ldd, (const _Float16 *)zt,
-                                                    ldt, delta, lda, zin, zout, ldzb, theta, cs, dpart, part, n, np, kp,
-                                                    sweep, true);
+    k_sweep_gemm<<<blocks, 256, 0, s>>>(ctrl, g, sweep);
     return hipGetLastError();
 }
 

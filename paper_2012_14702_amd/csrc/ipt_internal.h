@@ -74,51 +74,47 @@ constexpr int NPART = 4;      // partial sums per (row tile, column): step^2, z^
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// Element types of the low-precision shadows.
+enum : int32_t { LT_BF16 = 0, LT_F16 = 1, LT_F32 = 2 };
+
 // -------------------------------------------------------------- launchers
-constexpr int DIAG_SPLIT = 8;  // partial sums per d_c (dpart is DIAG_SPLIT x kp)
+constexpr int DIAG_SPLIT = 64;  // max partial sums per d_c (dpart is DIAG_SPLIT x kp)
 
 // Setup and bookkeeping (ipt_setup.hip)
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp);
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
                               int64_t k);
-hipError_t launch_norm1_dense(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
-                              int64_t n, double *scratch);
+hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
+                             int64_t n, int64_t np, double *dpad, void *dlo, int32_t low_type, float *d32,
+                             double *colpart);
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
                             const int32_t *col, const double *val, int64_t n, double *scratch);
 hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld);
-hipError_t launch_copy_pad(hipStream_t s, const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n,
-                           int64_t np);
 hipError_t launch_load_z0(hipStream_t s, const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb,
                           int64_t ldzb, const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kp);
 hipError_t launch_zero_pad(hipStream_t s, double *zb, int64_t ldzb, int64_t n, int64_t np, int64_t k, int64_t kp);
 hipError_t launch_sweep1_dense(hipStream_t s, const Ctrl *ctrl, const double *theta, const double *delta,
-                               int64_t lda, ColState cs, double *dpart, double *zout, int64_t ldzb, double *part,
+                               int64_t lda, ColState cs, double *dvec, double *zout, int64_t ldzb, double *part,
                                int64_t n, int64_t np, int64_t kp);
 hipError_t launch_diag_dense(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
-                             int64_t ldzb, ColState cs, double *dpart, int64_t n, int64_t kp);
-hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, const double *dpart,
+                             int64_t ldzb, ColState cs, double *dpart, double *dvec, int64_t n, int64_t kp);
+hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, const double *dvec,
                            const double *theta, const double *part, int64_t nrt, int64_t kp, int32_t sweep,
                            int32_t in_par, int32_t out_par);
 hipError_t launch_control(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep);
 hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
                           int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
                           int64_t n, int64_t k, const ipt_colinfo *ci);
-hipError_t launch_cast_delta(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, void *dst,
-                             int64_t ldd, int64_t n, int64_t np, int32_t type);
 hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
-                         int64_t ldt, int64_t np, int64_t kp, int32_t type, int32_t want_prec);
+                         int64_t ldt, int64_t np, int64_t kp, int32_t low_type);
 
-// GEMM sweeps (ipt_gemm.hip).  Each returns at once unless ctrl->prec is its precision.
-hipError_t launch_gemm_f64(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
-                           double *zout, int64_t ldzb, const double *theta, ColState cs, const double *dpart,
-                           double *part, int64_t n, int64_t np, int64_t kp, int32_t sweep);
-hipError_t launch_gemm_low(hipStream_t s, const Ctrl *ctrl, int32_t want_prec, const void *dlo, int64_t ldd,
-                           const void *zt, int64_t ldt, const double *delta, int64_t lda, const double *zin,
-                           double *zout, int64_t ldzb, const double *theta, ColState cs, const double *dpart,
-                           double *part, int64_t n, int64_t np, int64_t kp, int32_t sweep, int32_t type);
+// The product and fused epilogue of one sweep (ipt_gemm.hip), in the precision the
+// device-side ladder chose (ctrl->prec).
+hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const void *dlo,
+                             const float *d32, const void *zt, const double *zin, double *zout, const double *theta,
+                             ColState cs, const double *dvec, double *part, int64_t n, int64_t np, int64_t kp,
+                             int32_t sweep, int32_t low_type);
 
-// Element types of the low-precision shadows.
-enum : int32_t { LT_BF16 = 0, LT_F16 = 1, LT_F32 = 2 };
 
 }  // namespace ipt

@@ -12,7 +12,6 @@ namespace ipt {
 
 namespace {
 
-constexpr int kDiagSplit = DIAG_SPLIT;  // partial sums of each d_c (see the diagonal kernel)
 
 __device__ inline uint64_t dbits(double x) {
     // Bit pattern of a non-negative double (NaN mapped to +inf) so that unsigned
@@ -24,13 +23,17 @@ __device__ inline uint64_t dbits(double x) {
 __device__ inline double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
 
 __global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k) {
-    Ctrl c = {};
-    c.prec = start_prec;
-    c.active = (int32_t)k;
-    c.prev_maxstep = INFINITY;
-    c.dscale = 1.0;
-    c.zscale = 1.0;
-    *ctrl = c;
+    uint32_t *w = (uint32_t *)ctrl;
+    constexpr int words = (int)(sizeof(Ctrl) / sizeof(uint32_t));
+    for (int q = threadIdx.x; q < words; q += blockDim.x) w[q] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctrl->prec = start_prec;
+        ctrl->active = (int32_t)k;
+        ctrl->prev_maxstep = INFINITY;
+        ctrl->dscale = 1.0;
+        ctrl->zscale = 1.0;
+    }
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t v) {
@@ -89,29 +92,54 @@ __global__ void k_check_theta(Ctrl *ctrl, const double *theta, const int32_t *id
     if (degen) atomicMax(&ctrl->error, (int32_t)IPT_EDEGENERATE);
 }
 
-// |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Stage 1: column sums over
-// row chunks (coalesced: consecutive threads take consecutive columns).
-__global__ void k_norm1_dense_part(const double *theta, const double *delta, int64_t lda, int64_t n, int64_t rows,
-                                   double *scratch) {
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    const int64_t r0 = (int64_t)blockIdx.y * rows;
-    int64_t r1 = r0 + rows;
-    if (r1 > n) r1 = n;
+// Conversions to the shadow element types (round to nearest even).
+template <typename T>
+__device__ inline T to_low(double x);
+template <>
+__device__ inline float to_low<float>(double x) { return (float)x; }
+template <>
+__device__ inline __bf16 to_low<__bf16>(double x) { return (__bf16)(float)x; }
+template <>
+__device__ inline _Float16 to_low<_Float16>(double x) { return (_Float16)(float)x; }
+
+// One pass over Delta for everything the solve needs from it before the sweeps:
+// a zero-padded FP64 copy (when Delta is not tile aligned), the low-precision and
+// FP32 shadows of the ladder, and per-chunk partial column sums of |M| for
+// |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Block: 64 columns x
+// PREP_ROWS rows; thread (cx, ry) walks rows ry, ry + 4, ...
+constexpr int PREP_ROWS = 256;
+
+template <typename TL>
+__global__ __launch_bounds__(256) void k_prep_delta(const Ctrl *ctrl, const double *theta, const double *delta,
+                                                    int64_t lda, int64_t n, int64_t np, double *dpad, TL *dlo,
+                                                    float *d32, double *colpart) {
+    __shared__ double sh[4][64];
+    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + cx;
+    const int64_t r0 = (int64_t)blockIdx.y * PREP_ROWS;
+    const double dscale = ctrl->dscale;
     double acc = 0.0;
-    for (int64_t j = r0; j < r1; ++j) {
-        double m = delta[j * lda + c];
-        if (j == c) m += theta[c];
-        acc += fabs(m);
+    for (int q = 0; q < PREP_ROWS / 4; ++q) {
+        const int64_t j = r0 + ry + 4 * q;
+        if (j >= np) break;
+        const bool in = (j < n) && (c < n);
+        const double v = in ? delta[j * lda + c] : 0.0;
+        if (dpad) dpad[j * np + c] = v;
+        if (dlo) dlo[j * np + c] = to_low<TL>(v * dscale);
+        if (d32) d32[j * np + c] = (float)v;
+        if (in) acc += fabs(j == c ? v + theta[c] : v);
     }
-    scratch[(int64_t)blockIdx.y * n + c] = acc;
+    if (!colpart) return;
+    sh[ry][cx] = acc;
+    __syncthreads();
+    if (ry == 0 && c < n) colpart[(int64_t)blockIdx.y * n + c] = ((sh[0][cx] + sh[1][cx]) + sh[2][cx]) + sh[3][cx];
 }
 
-__global__ void k_norm1_reduce(Ctrl *ctrl, const double *scratch, int64_t n, int64_t chunks) {
+__global__ void k_norm1_reduce(Ctrl *ctrl, const double *colpart, int64_t n, int64_t chunks) {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= n) return;
     double acc = 0.0;
-    for (int64_t q = 0; q < chunks; ++q) acc += scratch[q * n + c];
+    for (int64_t q = 0; q < chunks; ++q) acc += colpart[q * n + c];
     atomicMax((unsigned long long *)&ctrl->norm1_bits, (unsigned long long)dbits(acc));
 }
 
@@ -140,14 +168,6 @@ __global__ void k_norm1_csr_reduce(Ctrl *ctrl, const double *theta, const double
 __global__ void k_zero_f64(double *p, int64_t count) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
         p[t] = 0.0;
-}
-
-// dst (np x np, ldd) <- src (n x n, lds) with zero padding.
-__global__ void k_copy_pad(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, int64_t np) {
-    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t j = blockIdx.y;
-    if (l >= np) return;
-    dst[j * ldd + l] = (j < n && l < n) ? src[j * lds + l] : 0.0;
 }
 
 // Warm start: Z <- z0 with Z[idx[c], c] = 1 (chart U_i); padding zero.
@@ -192,7 +212,7 @@ __device__ inline void store_col_partials(double (*sh)[4][64], const double v[NP
 // W_ic = 1, d_c = Delta_ii (eq. dyn at Z = I; the first-order RS term of
 // eq. ARS-alpha).  Block: one row tile of TILE_M rows x 64 columns.
 __global__ __launch_bounds__(256) void k_sweep1_dense(const Ctrl *ctrl, const double *theta, const double *delta,
-                                                      int64_t lda, ColState cs, double *dpart, double *zout,
+                                                      int64_t lda, ColState cs, double *dvec, double *zout,
                                                       int64_t ldzb, double *part, int64_t n, int64_t kp) {
     if (ctrl->error || ctrl->done) return;
     __shared__ double sh[4][4][64];
@@ -221,22 +241,21 @@ __global__ __launch_bounds__(256) void k_sweep1_dense(const Ctrl *ctrl, const do
         }
         zout[j * ldzb + c] = w;
     }
-    if (colok && rt == (int64_t)(i / TILE_M) && ry == 0) {
-        dpart[c] = delta[(int64_t)i * lda + i];
-        for (int s = 1; s < kDiagSplit; ++s) dpart[(int64_t)s * kp + c] = 0.0;
-    }
+    if (colok && rt == (int64_t)(i / TILE_M) && ry == 0) dvec[c] = delta[(int64_t)i * lda + i];
     store_col_partials(sh, v, cx, ry, part, rt, kp, c);
 }
 
 // d_c = (Delta Z)_{i,c} = sum_l Delta_il Z_lc in FP64 for the active columns.
-// Block: 64 columns x one of kDiagSplit contiguous ranges of l; the ranges' sums
-// are added in a fixed order by the consumers (GEMM epilogue and finalize).
+// Block: 64 columns x one of kDiagSplit contiguous ranges of l, walked in chunks
+// of 64: the 64 x 64 slices of the rows Delta[idx[c], :] and of Z are read with
+// 16-byte loads and met in LDS.  Each range's sum goes to dpart[range][c]; the
+// consumers add the ranges in a fixed order (k_diag_sum).
 __global__ __launch_bounds__(256) void k_diag_dense(const Ctrl *ctrl, const double *delta, int64_t lda,
                                                     const double *zin, int64_t ldzb, ColState cs, double *dpart,
-                                                    int64_t n, int64_t kp) {
+                                                    int64_t n, int64_t kp, int64_t span) {
     if (ctrl->error || ctrl->done) return;
     __shared__ double dt[64][65];
-    __shared__ double zt[64][65];
+    __shared__ double zt[64][66];
     __shared__ double red[4][64];
     __shared__ int32_t any;
     const int t = threadIdx.x;
@@ -246,95 +265,155 @@ __global__ __launch_bounds__(256) void k_diag_dense(const Ctrl *ctrl, const doub
     if (t < 64 && cs.state[c0 + t] == COL_ACTIVE) any = 1;
     __syncthreads();
     if (!any) return;
-    const int64_t span = (n + kDiagSplit - 1) / kDiagSplit;
     const int64_t lbeg = (int64_t)blockIdx.y * span;
     int64_t lend = lbeg + span;
     if (lend > n) lend = n;
     const int cx = t & 63, p = t >> 6;
-    double acc = 0.0;
     const int lr = t >> 2, lq = (t & 3) * 16;  // loader: row lr, 16 consecutive entries from lq
-    const int32_t irow = cs.idx[c0 + lr];
+    const double *drow = delta + (int64_t)cs.idx[c0 + lr] * lda;
+    double acc = 0.0;
     for (int64_t l0 = lbeg; l0 < lend; l0 += 64) {
-        // dt[cc][ll] = Delta[idx[c0 + cc], l0 + ll];  zt[ll][cc] = Z[l0 + ll, c0 + cc]
+        if (l0 + 64 <= lend && ((lda | l0) & 1) == 0) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int64_t l = l0 + lq + e;
-            dt[lr][lq + e] = (l < lend) ? delta[(int64_t)irow * lda + l] : 0.0;
+            for (int e = 0; e < 16; e += 2) {
+                const double2 v = *(const double2 *)(drow + l0 + lq + e);
+                dt[lr][lq + e] = v.x;
+                dt[lr][lq + e + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dt[lr][lq + e] = (l0 + lq + e < lend) ? drow[l0 + lq + e] : 0.0;
         }
         const bool rowok = (l0 + lr) < lend;
+        const double *zr = zin + (l0 + lr) * ldzb + c0 + lq;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) zt[lr][lq + e] = rowok ? zin[(l0 + lr) * ldzb + c0 + lq + e] : 0.0;
+        for (int e = 0; e < 16; e += 2) {
+            const double2 v = rowok ? *(const double2 *)(zr + e) : double2{0.0, 0.0};
+            zt[lr][lq + e] = v.x;
+            zt[lr][lq + e + 1] = v.y;
+        }
         __syncthreads();
+#pragma unroll
         for (int e = 0; e < 16; ++e) acc += dt[cx][16 * p + e] * zt[16 * p + e][cx];
         __syncthreads();
     }
     red[p][cx] = acc;
     __syncthreads();
-    if (p == 0) {
-        const double s = ((red[0][cx] + red[1][cx]) + red[2][cx]) + red[3][cx];
-        dpart[(int64_t)blockIdx.y * kp + c0 + cx] = s;
+    if (p == 0) dpart[(int64_t)blockIdx.y * kp + c0 + cx] = ((red[0][cx] + red[1][cx]) + red[2][cx]) + red[3][cx];
+}
+
+// d_c = sum of the kDiagSplit range sums, in range order.
+__global__ void k_diag_sum(const Ctrl *ctrl, const double *dpart, double *d, int64_t kp, int32_t splits) {
+    if (ctrl->error || ctrl->done) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= kp) return;
+    double s = 0.0;
+    for (int q = 0; q < splits; ++q) s += dpart[(int64_t)q * kp + c];
+    d[c] = s;
+}
+
+__device__ inline uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = (uint64_t)__shfl_xor((unsigned long long)v, off);
+        v = o > v ? o : v;
     }
+    return v;
+}
+
+// Adds the number of lanes with pred set to *p with one atomic per wave.
+__device__ inline void wave_count(int32_t *p, bool pred) {
+    const uint64_t m = __ballot(pred);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(p, (int32_t)__popcll(m));
+}
+
+__device__ inline void wave_atomic_max(uint64_t *p, uint64_t v) {
+    v = wave_max_u64(v);
+    if ((threadIdx.x & 63) == 0 && v) atomicMax((unsigned long long *)p, (unsigned long long)v);
 }
 
 // Finalize sweep t for every active column: reduce the partial sums over row
-// tiles in order, form s_c = |W_c - Z_c| / |Z_c| (Alg. 1 loop test, Euclidean
-// norms), and decide.  Only an exact sweep (FP64 product, or the product-free
-// first sweep) may certify a column; a certified column keeps its input iterate
-// and lambda_c = theta_i + d_c of this sweep (Alg. 1/2 return steps).
-__global__ void k_finalize(Ctrl *ctrl, DevOpts o, ColState cs, const double *dpart, const double *theta,
-                           const double *part, int64_t nrt, int64_t kp, int32_t sweep, int32_t in_par,
-                           int32_t out_par) {
+// tiles in a fixed order, form s_c = |W_c - Z_c| / |Z_c| (Alg. 1 loop test,
+// Euclidean norms), and decide.  Only an exact sweep (FP64 product, or the
+// product-free first sweep) may certify a column; a certified column keeps its
+// input iterate and lambda_c = theta_i + d_c of this sweep (Alg. 1/2 return steps).
+// Block: 64 columns; thread (cx, g) sums row tiles g, g + 4, ...; wave 0 decides.
+__global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColState cs, const double *dvec,
+                                                  const double *theta, const double *part, int64_t nrt, int64_t kp,
+                                                  int32_t sweep, int32_t in_par, int32_t out_par) {
     if (ctrl->error || ctrl->done) return;
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= kp || cs.state[c] != COL_ACTIVE) return;
+    __shared__ double sh[4][NPART][64];
+    const int cx = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + cx;
+    const bool act = cs.state[c] == COL_ACTIVE;
     double p[NPART] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t rt = 0; rt < nrt; ++rt)
-        for (int q = 0; q < NPART; ++q) p[q] += part[(rt * kp + c) * NPART + q];
-    double d = 0.0;
-    for (int s = 0; s < kDiagSplit; ++s) d += dpart[(int64_t)s * kp + c];
-    const double s = sqrt(p[0]) / sqrt(p[1]);
-    const int32_t prec = ctrl->prec;
-    const bool exact = (prec == PREC_F64) || (prec == PREC_EXACT_FIRST);
-    const double nrm = bitsd(ctrl->norm1_bits);
-    const double resid = sqrt(p[2]) / (nrm > 0.0 ? nrm : 1.0) / sqrt(p[1]);
-    const int32_t i = cs.idx[c];
-    atomicMax((unsigned long long *)&ctrl->acc_maxstep, (unsigned long long)dbits(s));
-    int32_t decided = -1, par = 0;
-    if (exact && s <= o.tol) {
-        decided = COL_CONVERGED;
-        par = in_par;
-        atomicMax((unsigned long long *)&ctrl->acc_maxres, (unsigned long long)dbits(resid));
-    } else {
-        const bool bad = !isfinite(s) || !(sqrt(p[3]) <= o.div_norm);
-        int32_t grow = cs.grow[c];
-        if (exact) {
-            grow = (s > cs.prev[c]) ? grow + 1 : 0;
-            cs.prev[c] = s;
-            cs.grow[c] = grow;
-        }
-        if (bad || grow >= o.div_growth) {
-            decided = COL_DIVERGED;
-            par = out_par;
-        } else if (sweep >= o.max_iter) {
-            decided = COL_NOT_CONVERGED;
-            par = out_par;
+    if (act) {
+        for (int64_t rt = g; rt < nrt; rt += 4) {
+            const double4 v = *(const double4 *)&part[(rt * kp + c) * NPART];
+            p[0] += v.x;
+            p[1] += v.y;
+            p[2] += v.z;
+            p[3] += v.w;
         }
     }
-    if (decided >= 0) {
-        cs.state[c] = decided;
-        cs.par[c] = par;
-        cs.sweeps[c] = sweep;
-        cs.step[c] = s;
-        cs.lam[c] = theta[i] + d;
-        cs.resid[c] = resid;
-        atomicAdd(decided == COL_CONVERGED ? &ctrl->n_conv : decided == COL_DIVERGED ? &ctrl->n_div : &ctrl->n_notconv,
-                  1);
-        atomicMax((unsigned long long *)&ctrl->dec_maxstep, (unsigned long long)dbits(s));
-    } else {
-        atomicAdd(&ctrl->acc_active, 1);
-        atomicMax((unsigned long long *)&ctrl->acc_maxdist, (unsigned long long)dbits(sqrt(p[3])));
-        cs.tile_stamp[c / TILE_N] = sweep;
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) sh[g][q][cx] = p[q];
+    __syncthreads();
+    if (g != 0) return;
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) p[q] = ((sh[0][q][cx] + sh[1][q][cx]) + sh[2][q][cx]) + sh[3][q][cx];
+    int32_t decided = -1;
+    double s = 0.0;
+    uint64_t res_bits = 0;
+    if (act) {
+        const double d = dvec[c];
+        s = sqrt(p[0]) / sqrt(p[1]);
+        const int32_t prec = ctrl->prec;
+        const bool exact = (prec == PREC_F64) || (prec == PREC_EXACT_FIRST);
+        const double nrm = bitsd(ctrl->norm1_bits);
+        const double resid = sqrt(p[2]) / (nrm > 0.0 ? nrm : 1.0) / sqrt(p[1]);
+        const int32_t i = cs.idx[c];
+        int32_t par = 0;
+        if (exact && s <= o.tol) {
+            decided = COL_CONVERGED;
+            par = in_par;
+            res_bits = dbits(resid);
+        } else {
+            const bool bad = !isfinite(s) || !(sqrt(p[3]) <= o.div_norm);
+            int32_t grow = cs.grow[c];
+            if (exact) {
+                grow = (s > cs.prev[c]) ? grow + 1 : 0;
+                cs.prev[c] = s;
+                cs.grow[c] = grow;
+            }
+            if (bad || grow >= o.div_growth) {
+                decided = COL_DIVERGED;
+                par = out_par;
+            } else if (sweep >= o.max_iter) {
+                decided = COL_NOT_CONVERGED;
+                par = out_par;
+            }
+        }
+        if (decided >= 0) {
+            cs.state[c] = decided;
+            cs.par[c] = par;
+            cs.sweeps[c] = sweep;
+            cs.step[c] = s;
+            cs.lam[c] = theta[i] + d;
+            cs.resid[c] = resid;
+        } else {
+            cs.tile_stamp[c / TILE_N] = sweep;
+        }
     }
+    const bool still = act && decided < 0;
+    wave_atomic_max(&ctrl->acc_maxstep, act ? dbits(s) : 0);
+    wave_atomic_max(&ctrl->acc_maxdist, still ? dbits(sqrt(p[3])) : 0);
+    wave_atomic_max(&ctrl->acc_maxres, res_bits);
+    wave_atomic_max(&ctrl->dec_maxstep, decided >= 0 ? dbits(s) : 0);
+    wave_count(&ctrl->acc_active, still);
+    wave_count(&ctrl->n_conv, decided == COL_CONVERGED);
+    wave_count(&ctrl->n_div, decided == COL_DIVERGED);
+    wave_count(&ctrl->n_notconv, decided == COL_NOT_CONVERGED);
 }
 
 // Bookkeeping after sweep t and the precision of sweep t+1 (the ladder): leave the
@@ -417,37 +496,27 @@ __global__ void k_copyout(const Ctrl *ctrl, ColState cs, const double *buf0, con
     }
 }
 
-// Low-precision shadows (precision ladder).  Delta_lo = lowp(scale * Delta),
-// np x np with zero padding.
+// Transposed shadow of the split iterate for a low-precision or FP32 sweep:
+// zt[c][j] = lowp(scale * (Z_jc - [j == i])).  Only Z - E goes through low
+// precision; Delta E is added back exactly in FP64 by the GEMM epilogue.  The
+// element type follows the precision the ladder chose for this sweep (nothing is
+// done for an FP64 sweep).  64 x 64 tiles transposed through LDS.
 template <typename T>
-__device__ inline T to_low(double x);
-template <>
-__device__ inline float to_low<float>(double x) { return (float)x; }
-template <>
-__device__ inline __bf16 to_low<__bf16>(double x) { return (__bf16)(float)x; }
-template <>
-__device__ inline _Float16 to_low<_Float16>(double x) { return (_Float16)(float)x; }
-
-template <typename T>
-__global__ void k_cast_delta(const Ctrl *ctrl, const double *delta, int64_t lda, T *dst, int64_t ldd, int64_t n,
-                             int64_t np, bool scaled) {
-    if (ctrl->error) return;
-    const double scale = scaled ? ctrl->dscale : 1.0;
-    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t j = blockIdx.y;
-    if (l >= np) return;
-    const double v = (j < n && l < n) ? delta[j * lda + l] * scale : 0.0;
-    dst[j * ldd + l] = to_low<T>(v);
+__device__ __forceinline__ void cast_z_tile(double (*tile)[65], T *zt, int64_t ldt, int64_t c0, int64_t j0) {
+    const int t = threadIdx.x;
+    for (int q = 0; q < 16; ++q) {
+        const int cc = (t >> 6) + 4 * q, r = t & 63;
+        zt[(c0 + cc) * ldt + j0 + r] = to_low<T>(tile[r][cc]);
+    }
 }
 
-// Transposed shadow of the split iterate: zt[c][j] = lowp(scale * (Z_jc - [j == i])).
-// Only Z - E goes through low precision; Delta E is added back exactly in FP64
-// by the GEMM epilogue.  64 x 64 tiles transposed through LDS.
-template <typename T>
 __global__ __launch_bounds__(256) void k_cast_z(const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs,
-                                                T *zt, int64_t ldt, bool scaled, int32_t want_prec) {
-    if (ctrl->error || ctrl->done || ctrl->prec != want_prec) return;
-    const double scale = scaled ? ctrl->zscale : 1.0;
+                                                void *zt, int64_t ldt, int32_t low_type) {
+    if (ctrl->error || ctrl->done) return;
+    const int32_t prec = ctrl->prec;
+    if (prec != PREC_LOW && prec != PREC_F32) return;
+    const bool f16 = prec == PREC_LOW && low_type == LT_F16;
+    const double scale = f16 ? ctrl->zscale : 1.0;
     __shared__ double tile[64][65];
     const int64_t j0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
     const int t = threadIdx.x;
@@ -459,10 +528,9 @@ __global__ __launch_bounds__(256) void k_cast_z(const Ctrl *ctrl, const double *
         tile[r][cc] = v * scale;
     }
     __syncthreads();
-    for (int q = 0; q < 16; ++q) {
-        const int cc = (t >> 6) + 4 * q, r = t & 63;
-        zt[(c0 + cc) * ldt + j0 + r] = to_low<T>(tile[r][cc]);
-    }
+    if (prec == PREC_F32) cast_z_tile<float>(tile, (float *)zt, ldt, c0, j0);
+    else if (f16) cast_z_tile<_Float16>(tile, (_Float16 *)zt, ldt, c0, j0);
+    else cast_z_tile<__bf16>(tile, (__bf16 *)zt, ldt, c0, j0);
 }
 
 inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) / per); }
@@ -473,7 +541,7 @@ inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) /
 
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp) {
-    k_ctrl_init<<<1, 1, 0, s>>>(ctrl, start_prec, k);
+    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k);
     const int64_t words = (n + 31) / 32;
     k_fill_u32<<<blocks_for(words, 256) < 1024 ? blocks_for(words, 256) : 1024, 256, 0, s>>>(bitmap, words, 0u);
     const int64_t m = kp > ntiles_n ? kp : ntiles_n;
@@ -488,16 +556,16 @@ hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, co
     return hipGetLastError();
 }
 
-hipError_t launch_norm1_dense(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
-                              int64_t n, double *scratch) {
-    int64_t chunks = n / 64;
-    if (chunks < 1) chunks = 1;
-    if (chunks > 64) chunks = 64;
-    const int64_t rows = (n + chunks - 1) / chunks;
-    chunks = (n + rows - 1) / rows;
-    dim3 g(blocks_for(n, 256), (unsigned)chunks);
-    k_norm1_dense_part<<<g, 256, 0, s>>>(theta, delta, lda, n, rows, scratch);
-    k_norm1_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, scratch, n, chunks);
+hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
+                             int64_t n, int64_t np, double *dpad, void *dlo, int32_t low_type, float *d32,
+                             double *colpart) {
+    const int64_t chunks = (np + PREP_ROWS - 1) / PREP_ROWS;
+    dim3 g((unsigned)(np / 64), (unsigned)chunks);
+    if (low_type == LT_F16)
+        k_prep_delta<_Float16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, (_Float16 *)dlo, d32, colpart);
+    else
+        k_prep_delta<__bf16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, (__bf16 *)dlo, d32, colpart);
+    if (colpart) k_norm1_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, colpart, n, chunks);
     return hipGetLastError();
 }
 
@@ -506,13 +574,6 @@ hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, cons
     k_zero_f64<<<blocks_for(2 * n, 256) < 2048 ? blocks_for(2 * n, 256) : 2048, 256, 0, s>>>(scratch, 2 * n);
     k_norm1_csr_part<<<blocks_for(n, 256), 256, 0, s>>>(row_ptr, col, val, n, scratch);
     k_norm1_csr_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, theta, scratch, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy_pad(hipStream_t s, const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n,
-                           int64_t np) {
-    dim3 g(blocks_for(np, 256), (unsigned)np);
-    k_copy_pad<<<g, 256, 0, s>>>(src, lds, dst, ldd, n, np);
     return hipGetLastError();
 }
 
@@ -530,24 +591,32 @@ hipError_t launch_zero_pad(hipStream_t s, double *zb, int64_t ldzb, int64_t n, i
 }
 
 hipError_t launch_sweep1_dense(hipStream_t s, const Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
-                               ColState cs, double *dpart, double *zout, int64_t ldzb, double *part, int64_t n,
+                               ColState cs, double *dvec, double *zout, int64_t ldzb, double *part, int64_t n,
                                int64_t np, int64_t kp) {
     dim3 g((unsigned)(kp / 64), (unsigned)(np / TILE_M));
-    k_sweep1_dense<<<g, 256, 0, s>>>(ctrl, theta, delta, lda, cs, dpart, zout, ldzb, part, n, kp);
+    k_sweep1_dense<<<g, 256, 0, s>>>(ctrl, theta, delta, lda, cs, dvec, zout, ldzb, part, n, kp);
     return hipGetLastError();
 }
 
 hipError_t launch_diag_dense(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
-                             int64_t ldzb, ColState cs, double *dpart, int64_t n, int64_t kp) {
-    dim3 g((unsigned)(kp / 64), kDiagSplit);
-    k_diag_dense<<<g, 256, 0, s>>>(ctrl, delta, lda, zin, ldzb, cs, dpart, n, kp);
+                             int64_t ldzb, ColState cs, double *dpart, double *dvec, int64_t n, int64_t kp) {
+    // about 64-256 entries of l per block, at most DIAG_SPLIT ranges
+    int64_t splits = (n + 255) / 256;
+    if (splits > DIAG_SPLIT) splits = DIAG_SPLIT;
+    if (splits < 1) splits = 1;
+    int64_t span = (n + splits - 1) / splits;
+    span = (span + 63) / 64 * 64;
+    splits = (n + span - 1) / span;
+    dim3 g((unsigned)(kp / 64), (unsigned)splits);
+    k_diag_dense<<<g, 256, 0, s>>>(ctrl, delta, lda, zin, ldzb, cs, dpart, n, kp, span);
+    k_diag_sum<<<blocks_for(kp, 256), 256, 0, s>>>(ctrl, dpart, dvec, kp, (int32_t)splits);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, const double *dpart,
+hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, const double *dvec,
                            const double *theta, const double *part, int64_t nrt, int64_t kp, int32_t sweep,
                            int32_t in_par, int32_t out_par) {
-    k_finalize<<<blocks_for(kp, 256), 256, 0, s>>>(ctrl, o, cs, dpart, theta, part, nrt, kp, sweep, in_par, out_par);
+    k_finalize<<<(unsigned)(kp / 64), 256, 0, s>>>(ctrl, o, cs, dvec, theta, part, nrt, kp, sweep, in_par, out_par);
     return hipGetLastError();
 }
 
@@ -565,15 +634,6 @@ hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const do
     return hipGetLastError();
 }
 
-hipError_t launch_cast_delta(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, void *dst, int64_t ldd,
-                             int64_t n, int64_t np, int32_t type) {
-    dim3 g(blocks_for(np, 256), (unsigned)np);
-    if (type == LT_F32) k_cast_delta<float><<<g, 256, 0, s>>>(ctrl, delta, lda, (float *)dst, ldd, n, np, false);
-    else if (type == LT_BF16) k_cast_delta<__bf16><<<g, 256, 0, s>>>(ctrl, delta, lda, (__bf16 *)dst, ldd, n, np, false);
-    else k_cast_delta<_Float16><<<g, 256, 0, s>>>(ctrl, delta, lda, (_Float16 *)dst, ldd, n, np, true);
-    return hipGetLastError();
-}
-
 hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld) {
     int b = blocks_for(rows * cols, 256);
     if (b > 4096) b = 4096;
@@ -583,11 +643,9 @@ hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t row
 }
 
 hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
-                         int64_t ldt, int64_t np, int64_t kp, int32_t type, int32_t want_prec) {
+                         int64_t ldt, int64_t np, int64_t kp, int32_t low_type) {
     dim3 g((unsigned)(kp / 64), (unsigned)(np / 64));
-    if (type == LT_F32) k_cast_z<float><<<g, 256, 0, s>>>(ctrl, zin, ldzb, cs, (float *)zt, ldt, false, want_prec);
-    else if (type == LT_BF16) k_cast_z<__bf16><<<g, 256, 0, s>>>(ctrl, zin, ldzb, cs, (__bf16 *)zt, ldt, false, want_prec);
-    else k_cast_z<_Float16><<<g, 256, 0, s>>>(ctrl, zin, ldzb, cs, (_Float16 *)zt, ldt, true, want_prec);
+    k_cast_z<<<g, 256, 0, s>>>(ctrl, zin, ldzb, cs, zt, ldt, low_type);
     return hipGetLastError();
 }
 
