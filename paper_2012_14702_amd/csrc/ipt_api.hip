@@ -106,6 +106,7 @@ DevOpts dev_opts(const ipt_opts &o) {
     d.div_growth = o.div_growth;
     d.ladder = o.precision == IPT_PREC_LADDER;
     d.low_type = o.low_type;
+    d.first_product = 0;
     return d;
 }
 
@@ -403,10 +404,110 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     return finish(h, ctrl, k, info, &timer);
 }
 
-ipt_status ipt_solve_csr(ipt_handle h, int64_t, const double *, const int32_t *, const int32_t *, const double *,
-                         int64_t, int64_t, const int32_t *, const double *, int64_t, const ipt_opts *, double *, int64_t,
-                         double *, int32_t *, ipt_info *, const ipt_colinfo *) {
-    return fail(h, IPT_EINVAL, "sparse path not built yet");
+ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int32_t *row_ptr, const int32_t *col,
+                         const double *val, int64_t nnz, int64_t k, const int32_t *idx, const double *z0, int64_t ldz0,
+                         const ipt_opts *opts, double *z_out, int64_t ldz, double *lambda_out, int32_t *col_status,
+                         ipt_info *info, const ipt_colinfo *ci) {
+    if (!h) return IPT_EINVAL;
+    h->last_error.clear();
+    if (n < 1 || n > (int64_t(1) << 30)) return fail(h, IPT_EINVAL, "n must be in [1, 2^30]");
+    if (k < 1 || k > n) return fail(h, IPT_EINVAL, "k must be in [1, n]");
+    if (nnz < 0 || nnz > INT32_MAX) return fail(h, IPT_EINVAL, "nnz must be in [0, 2^31)");
+    if (ldz < k) return fail(h, IPT_EINVAL, "ldz must be >= k");
+    if (z0 && ldz0 < k) return fail(h, IPT_EINVAL, "ldz0 must be >= k");
+    if (!theta || !row_ptr || (nnz > 0 && (!col || !val)) || !z_out || !lambda_out || !col_status)
+        return fail(h, IPT_EINVAL, "theta, row_ptr, col, val, z_out, lambda_out and col_status must be non-NULL");
+    ipt_opts o;
+    if (ipt_status st = check_opts(h, opts, o)) return st;
+    DevOpts dopt = dev_opts(o);
+    dopt.low_type = IPT_LOW_NONE;  // the sparse ladder runs FP32 then FP64 sweeps
+    dopt.first_product = 1;
+    const bool ladder = dopt.ladder;
+    const bool cold = (z0 == nullptr);
+    const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
+    DeviceGuard guard(h->device);
+    hipStream_t s = h->stream;
+
+    const int64_t kpc = round_up(k, 64);   // column-state and partial-sum layout
+    const int64_t ldzb = round_up(k, 2);   // Z buffers: n x ldzb
+    const int64_t nrt = spmm_row_tiles(n);
+    auto layout = [&](Carve &cv, double **zb, float **zlo, ColState &cs, double **dvec, double **part,
+                      uint32_t **bitmap, double **scratch, float **val32, Ctrl **ctrl) {
+        zb[0] = cv.take<double>(n * ldzb);
+        zb[1] = cv.take<double>(n * ldzb);
+        zlo[0] = ladder ? cv.take<float>(n * ldzb) : nullptr;
+        zlo[1] = ladder ? cv.take<float>(n * ldzb) : nullptr;
+        *dvec = cv.take<double>(kpc);
+        *part = cv.take<double>(nrt * kpc * NPART);
+        cs.state = cv.take<int32_t>(kpc);
+        cs.sweeps = cv.take<int32_t>(kpc);
+        cs.grow = cv.take<int32_t>(kpc);
+        cs.par = cv.take<int32_t>(kpc);
+        cs.idx = cv.take<int32_t>(kpc);
+        cs.tile_stamp = cv.take<int32_t>(kpc / TILE_N + 1);
+        cs.prev = cv.take<double>(kpc);
+        cs.step = cv.take<double>(kpc);
+        cs.lam = cv.take<double>(kpc);
+        cs.resid = cv.take<double>(kpc);
+        *bitmap = cv.take<uint32_t>((n + 31) / 32);
+        *scratch = norm ? cv.take<double>(2 * n) : nullptr;
+        *val32 = (ladder && nnz > 0) ? cv.take<float>(nnz) : nullptr;
+        *ctrl = cv.take<Ctrl>(1);
+    };
+    double *zb[2], *dvec, *part, *scratch;
+    float *zlo[2], *val32;
+    ColState cs;
+    uint32_t *bitmap;
+    Ctrl *ctrl;
+    Carve sizing;
+    layout(sizing, zb, zlo, cs, &dvec, &part, &bitmap, &scratch, &val32, &ctrl);
+    if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
+    Carve cv;
+    cv.base = (char *)h->ws;
+    layout(cv, zb, zlo, cs, &dvec, &part, &bitmap, &scratch, &val32, &ctrl);
+
+    Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
+    IPT_HIP(h, timer.ensure());
+    IPT_HIP(h, hipEventRecord(h->ev_start, s));
+    // A cold start's first sweep multiplies Delta by E, which is exact in every
+    // precision (the low-precision part Z - E is zero), so it may certify.
+    const int32_t start_prec = cold ? PREC_EXACT_FIRST : (ladder ? PREC_F32 : PREC_F64);
+    IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kpc, bitmap, start_prec, (int32_t)(kpc / TILE_N + 1), 0));
+    IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
+    IPT_HIP(h, launch_check_csr(s, ctrl, row_ptr, col, n, nnz));
+    if (norm) IPT_HIP(h, launch_norm1_csr(s, ctrl, theta, row_ptr, col, val, n, scratch));
+    if (ladder && nnz > 0) IPT_HIP(h, launch_val32(s, val, val32, nnz));
+    IPT_HIP(h, launch_load_z0(s, ctrl, z0, ldz0, zb[0], ldzb, cs.idx, n, n, k, ldzb));
+    if (ladder) {
+        if (cold) IPT_HIP(h, launch_fill_f32(s, zlo[0], n * ldzb));
+        else IPT_HIP(h, launch_zlo_init(s, zb[0], zlo[0], ldzb, cs.idx, n, k));
+    }
+    if (ldzb != k) {  // padding column of the second buffer
+        IPT_HIP(h, launch_load_z0(s, ctrl, nullptr, 0, zb[1], ldzb, cs.idx, n, n, k, ldzb));
+        if (ladder) IPT_HIP(h, launch_fill_f32(s, zlo[1], n * ldzb));
+    }
+
+    PollPlan plan = poll_plan(o, cold);
+    if (o.sync_every <= 0) plan.first = cold ? 3 : 2;  // sparse near-diagonal solves take few sweeps
+    for (int32_t t = 1; t <= o.max_iter; ++t) {
+        const int32_t in_par = (t - 1) & 1, out_par = t & 1;
+        double *zin = zb[(t - 1) & 1], *zout = zb[t & 1];
+        IPT_HIP(h, launch_diag_csr(s, ctrl, row_ptr, col, val, zin, ldzb, cs, dvec, k));
+        IPT_HIP(h, timer.mark(t, 0, s));
+        IPT_HIP(h, launch_spmm_sweep(s, ctrl, row_ptr, col, val, val32, theta, zin, zout,
+                                     ladder ? zlo[(t - 1) & 1] : nullptr, ladder ? zlo[t & 1] : nullptr, cs, dvec,
+                                     part, n, k, ldzb, kpc));
+        IPT_HIP(h, timer.mark(t, 1, s));
+        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, nrt, kpc, t, in_par, out_par));
+        IPT_HIP(h, launch_control(s, ctrl, dopt, t));
+        if (plan.at(t, o.max_iter)) {
+            int32_t err, done;
+            if (ipt_status st = poll_ctrl(h, ctrl, err, done)) return st;
+            if (err || done) break;
+        }
+    }
+    IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], ldzb, z_out, ldz, lambda_out, col_status, n, k, ci));
+    return finish(h, ctrl, k, info, &timer);
 }
 
 ipt_status ipt_solve_batched(ipt_handle h, int32_t, const int32_t *, const int64_t *, const int64_t *, const int64_t *,

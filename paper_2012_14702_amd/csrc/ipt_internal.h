@@ -52,6 +52,7 @@ struct Ctrl {
 struct DevOpts {
     double tol, tau_low, tau_32, div_norm;
     int32_t max_iter, div_growth, ladder, low_type;
+    int32_t first_product;  // the first sweep of a cold start multiplies by Delta (sparse path)
 };
 
 // Per-column state arrays (length kp).
@@ -108,6 +109,22 @@ hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const do
                           int64_t n, int64_t k, const ipt_colinfo *ci);
 hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
                          int64_t ldt, int64_t np, int64_t kp, int32_t low_type);
+
+hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count);  // zero fill
+
+// Sparse sweeps (ipt_spmm.hip)
+int64_t spmm_row_tiles(int64_t n);
+hipError_t launch_spmm_sweep(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
+                             const double *val, const float *val32, const double *theta, const double *zin,
+                             double *zout, const float *zlo_in, float *zlo_out, ColState cs, const double *dvec,
+                             double *part, int64_t n, int64_t k, int64_t ldz, int64_t kpc);
+hipError_t launch_diag_csr(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
+                           const double *val, const double *zin, int64_t ldz, ColState cs, double *dvec, int64_t k);
+hipError_t launch_check_csr(hipStream_t s, Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, int64_t n,
+                            int64_t nnz);
+hipError_t launch_val32(hipStream_t s, const double *val, float *val32, int64_t nnz);
+hipError_t launch_zlo_init(hipStream_t s, const double *zb, float *zlo, int64_t ldz, const int32_t *idx, int64_t n,
+                           int64_t k);
 
 // The product and fused epilogue of one sweep (ipt_gemm.hip), in the precision the
 // device-side ladder chose (ctrl->prec).

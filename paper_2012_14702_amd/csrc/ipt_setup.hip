@@ -147,8 +147,9 @@ __global__ void k_norm1_reduce(Ctrl *ctrl, const double *colpart, int64_t n, int
 // Delta to scratch[n + c] (added to theta_c before taking the modulus).  Double
 // atomics: the norm is a diagnostic (it scales the reported eigen-residual) and
 // takes no part in any decision.
-__global__ void k_norm1_csr_part(const int32_t *row_ptr, const int32_t *col, const double *val, int64_t n,
-                                 double *scratch) {
+__global__ void k_norm1_csr_part(const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, const double *val,
+                                 int64_t n, double *scratch) {
+    if (ctrl->error) return;  // the structure checks ran first; never walk a malformed matrix
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= n) return;
     for (int32_t p = row_ptr[j]; p < row_ptr[j + 1]; ++p) {
@@ -170,24 +171,27 @@ __global__ void k_zero_f64(double *p, int64_t count) {
         p[t] = 0.0;
 }
 
-// Warm start: Z <- z0 with Z[idx[c], c] = 1 (chart U_i); padding zero.
+// Z <- z0 with Z[idx[c], c] = 1 (chart U_i), or Z <- E when z0 is NULL; padding zero.
+// Writes columns [0, kw) of rows [0, np) (grid-stride over the np x kw elements).
 __global__ void k_load_z0(const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
-                          const int32_t *idx, int64_t n, int64_t k, int64_t kp) {
+                          const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kw) {
     if (ctrl->error) return;
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t j = blockIdx.y;
-    if (c >= kp) return;
-    double v = 0.0;
-    if (j < n && c < k) v = (j == idx[c]) ? 1.0 : z0[j * ldz0 + c];
-    zb[j * ldzb + c] = v;
+    const int64_t total = np * kw;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / kw, c = e - j * kw;
+        double v = 0.0;
+        if (j < n && c < k) v = (j == idx[c]) ? 1.0 : (z0 ? z0[j * ldz0 + c] : 0.0);
+        zb[j * ldzb + c] = v;
+    }
 }
 
 // Zero the padding rows [n, np) and padding columns [k, kp) of a Z buffer.
 __global__ void k_zero_pad(double *zb, int64_t ldzb, int64_t n, int64_t np, int64_t k, int64_t kp) {
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t j = blockIdx.y;
-    if (c >= kp) return;
-    if (j >= n || c >= k) zb[j * ldzb + c] = 0.0;
+    const int64_t total = np * kp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / kp, c = e - j * kp;
+        if (j >= n || c >= k) zb[j * ldzb + c] = 0.0;
+    }
 }
 
 // Block-wide reduction of per-thread column partials laid out as 4 row groups of
@@ -428,7 +432,7 @@ __global__ void k_control(Ctrl *ctrl, DevOpts o, int32_t sweep) {
         ctrl->hist_active[sweep - 1] = ctrl->active;
         ctrl->hist_step[sweep - 1] = ms;
     }
-    if (prec != PREC_EXACT_FIRST) ctrl->matvecs += ctrl->active;
+    if (prec != PREC_EXACT_FIRST || o.first_product) ctrl->matvecs += ctrl->active;
     ctrl->active = ctrl->acc_active;
     ctrl->acc_active = 0;
     ctrl->acc_maxstep = 0;
@@ -483,9 +487,11 @@ __global__ void k_copyout(const Ctrl *ctrl, ColState cs, const double *buf0, con
     const int32_t par = cs.par[c];
     const int32_t i = cs.idx[c];
     const double *src = (par == PAR_BUF1) ? buf1 : buf0;
-    int64_t j1 = j0 + 64;
-    if (j1 > n) j1 = n;
-    for (int64_t j = j0; j < j1; ++j) z_out[j * ldz + c] = (par == PAR_UNIT) ? (j == i ? 1.0 : 0.0) : src[j * ldzb + c];
+    for (int64_t jb = j0; jb < n; jb += (int64_t)gridDim.y * 64) {
+        int64_t j1 = jb + 64;
+        if (j1 > n) j1 = n;
+        for (int64_t j = jb; j < j1; ++j) z_out[j * ldz + c] = (par == PAR_UNIT) ? (j == i ? 1.0 : 0.0) : src[j * ldzb + c];
+    }
     if (blockIdx.y == 0) {
         lambda_out[c] = cs.lam[c];
         const int32_t st = cs.state[c];
@@ -569,24 +575,31 @@ hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, con
     return hipGetLastError();
 }
 
+hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count) {
+    k_fill_u32<<<blocks_for(count, 256) < 4096 ? blocks_for(count, 256) : 4096, 256, 0, s>>>((uint32_t *)p, count, 0u);
+    return hipGetLastError();
+}
+
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
                             const int32_t *col, const double *val, int64_t n, double *scratch) {
     k_zero_f64<<<blocks_for(2 * n, 256) < 2048 ? blocks_for(2 * n, 256) : 2048, 256, 0, s>>>(scratch, 2 * n);
-    k_norm1_csr_part<<<blocks_for(n, 256), 256, 0, s>>>(row_ptr, col, val, n, scratch);
+    k_norm1_csr_part<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, row_ptr, col, val, n, scratch);
     k_norm1_csr_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, theta, scratch, n);
     return hipGetLastError();
 }
 
 hipError_t launch_load_z0(hipStream_t s, const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
                           const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kp) {
-    dim3 g(blocks_for(kp, 256), (unsigned)np);
-    k_load_z0<<<g, 256, 0, s>>>(ctrl, z0, ldz0, zb, ldzb, idx, n, k, kp);
+    int b = blocks_for(np * kp, 256);
+    if (b > 8192) b = 8192;
+    k_load_z0<<<b, 256, 0, s>>>(ctrl, z0, ldz0, zb, ldzb, idx, n, np, k, kp);
     return hipGetLastError();
 }
 
 hipError_t launch_zero_pad(hipStream_t s, double *zb, int64_t ldzb, int64_t n, int64_t np, int64_t k, int64_t kp) {
-    dim3 g(blocks_for(kp, 256), (unsigned)np);
-    k_zero_pad<<<g, 256, 0, s>>>(zb, ldzb, n, np, k, kp);
+    int b = blocks_for(np * kp, 256);
+    if (b > 8192) b = 8192;
+    k_zero_pad<<<b, 256, 0, s>>>(zb, ldzb, n, np, k, kp);
     return hipGetLastError();
 }
 
@@ -628,7 +641,8 @@ hipError_t launch_control(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t s
 hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
                           int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out, int64_t n,
                           int64_t k, const ipt_colinfo *ci) {
-    dim3 g(blocks_for(k, 256), blocks_for(n, 64));
+    const int gy = blocks_for(n, 64) < 65535 ? blocks_for(n, 64) : 65535;
+    dim3 g(blocks_for(k, 256), gy);
     k_copyout<<<g, 256, 0, s>>>(ctrl, cs, buf0, buf1, ldzb, z_out, ldz, lambda_out, status_out, n, k,
                                 ci ? ci->sweeps : nullptr, ci ? ci->step : nullptr, ci ? ci->resid : nullptr);
     return hipGetLastError();

@@ -1,0 +1,220 @@
+// Sparse sweep: Y = Delta Z with Delta in CSR form (few eigenpairs of a sparse
+// near-diagonal M), with the IPT update fused into the same kernel:
+//   W_jc = (Z_jc d_c - Y_jc) / (theta_j - theta_i)  (j != i),  W_ic = 1      (eq. dyn)
+// and the per-column partial sums of |W - Z|^2, |Z|^2, |(theta_j - theta_i)(W - Z)|^2 and
+// |W - e_i|^2 over each block of rows.
+//
+// Layout: Z is row-major n x ldz (ldz = k rounded up to 2), so the k entries of a
+// gathered row Z[col[p], :] are contiguous.  kg lanes serve one row (kg = k rounded
+// up to a power of two, at most 64); a wave walks 64/kg rows at a time, each lane
+// owning one column (columns c, c + 64, ... when k > 64).  The col/val entries of a
+// row are broadcast to its kg lanes.
+//
+// FP32 sweeps of the precision ladder read an FP32 copy of val and the FP32 shadow
+// of Z - E; Delta E is added exactly in FP64 (the lane meets entry (j, idx[c]) while
+// walking row j).  Every sweep writes the FP32 shadow of W - E for the next one.
+#include <math.h>
+
+#include "ipt_internal.h"
+
+namespace ipt {
+
+namespace {
+
+constexpr int SP_ROWS = 512;  // rows per block (one partial-sum row tile)
+
+struct SpArgs {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+    const float *val32;   // FP32 copy of val (ladder only)
+    const double *theta;
+    const double *zin;
+    double *zout;
+    const float *zlo_in;  // FP32 shadow of Z - E (ladder only)
+    float *zlo_out;       // FP32 shadow of W - E (ladder only)
+    ColState cs;
+    const double *dvec;
+    double *part;
+    int64_t n, k, ldz, kpc;
+    int32_t kg;           // lanes per row
+};
+
+__global__ __launch_bounds__(256) void k_spmm_sweep(const Ctrl *ctrl, SpArgs a) {
+    if (ctrl->error || ctrl->done) return;
+    const bool f32 = ctrl->prec == PREC_F32;
+    __shared__ double red[4][64][NPART];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int kg = a.kg;
+    const int rows_per_pass = 64 / kg;
+    const int sub = lane / kg;     // which row of the pass this lane serves
+    const int cl = lane % kg;      // column slot
+    const int64_t r0 = (int64_t)blockIdx.x * SP_ROWS;
+    int64_t r1 = r0 + SP_ROWS;
+    if (r1 > a.n) r1 = a.n;
+    // columns handled by this lane: cl, cl + 64, ... (kg == 64 when k > 64)
+    for (int64_t c0 = 0; c0 < a.k; c0 += 64) {
+        const int64_t c = c0 + cl;
+        const bool colok = c < a.k && a.cs.state[c] == COL_ACTIVE;
+        const int32_t i = colok ? a.cs.idx[c] : 0;
+        const double ti = a.theta[i];
+        const double d = colok ? a.dvec[c] : 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        // waves take interleaved passes of rows_per_pass rows
+        for (int64_t jb = r0 + (int64_t)wv * rows_per_pass; jb < r1; jb += 4 * rows_per_pass) {
+            const int64_t j = jb + sub;
+            if (j >= r1 || !colok) continue;
+            const int32_t pb = a.row_ptr[j], pe = a.row_ptr[j + 1];
+            double y = 0.0, ye = 0.0;
+            float y32 = 0.f;
+            if (!f32) {
+                for (int32_t p = pb; p < pe; ++p) y += a.val[p] * a.zin[(int64_t)a.col[p] * a.ldz + c];
+            } else {
+                for (int32_t p = pb; p < pe; ++p) {
+                    const int32_t cp = a.col[p];
+                    y32 += a.val32[p] * a.zlo_in[(int64_t)cp * a.ldz + c];
+                    if (cp == i) ye += a.val[p];
+                }
+                y = ye + (double)y32;
+            }
+            const double z = a.zin[j * a.ldz + c];
+            double w, st, gs, de;
+            if (j == i) {
+                w = 1.0;
+                st = w - z;
+                gs = 0.0;
+                de = 0.0;
+            } else {
+                const double gap = a.theta[j] - ti;
+                w = (z * d - y) / gap;
+                st = w - z;
+                gs = gap * st;
+                de = w;
+            }
+            a.zout[j * a.ldz + c] = w;
+            if (a.zlo_out) a.zlo_out[j * a.ldz + c] = (float)(j == i ? 0.0 : w);
+            s0 += st * st;
+            s1 += z * z;
+            s2 += gs * gs;
+            s3 += de * de;
+        }
+        // reduce the rows_per_pass lanes of each column (fixed xor pattern), then the
+        // 4 waves in order
+        for (int off = kg; off < 64; off <<= 1) {
+            s0 += __shfl_xor(s0, off);
+            s1 += __shfl_xor(s1, off);
+            s2 += __shfl_xor(s2, off);
+            s3 += __shfl_xor(s3, off);
+        }
+        if (lane < kg) {
+            red[wv][lane][0] = s0;
+            red[wv][lane][1] = s1;
+            red[wv][lane][2] = s2;
+            red[wv][lane][3] = s3;
+        }
+        __syncthreads();
+        if (threadIdx.x < kg) {
+            const int t = threadIdx.x;
+            const int64_t cc = c0 + t;
+            if (cc < a.kpc) {
+#pragma unroll
+                for (int q = 0; q < NPART; ++q)
+                    a.part[((int64_t)blockIdx.x * a.kpc + cc) * NPART + q] =
+                        ((red[0][t][q] + red[1][t][q]) + red[2][t][q]) + red[3][t][q];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// d_c = (Delta Z)_{i,c} = sum over row i of val[p] Z[col[p], c], FP64, one wave per
+// column: lane-strided partial sums then a fixed xor tree.
+__global__ void k_diag_csr(const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, const double *val,
+                           const double *zin, int64_t ldz, ColState cs, double *dvec, int64_t k) {
+    if (ctrl->error || ctrl->done) return;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= k || cs.state[c] != COL_ACTIVE) return;
+    const int32_t i = cs.idx[c];
+    double acc = 0.0;
+    for (int32_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += 64) acc += val[p] * zin[(int64_t)col[p] * ldz + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) dvec[c] = acc;
+}
+
+// CSR structure checks: row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, and
+// every column index in [0, n).
+__global__ void k_check_csr(Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (t == 0) bad |= row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz;
+    if (t < n) bad |= row_ptr[t + 1] < row_ptr[t];
+    for (int64_t p = t; p < nnz; p += (int64_t)gridDim.x * blockDim.x) bad |= col[p] < 0 || (int64_t)col[p] >= n;
+    if (bad) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
+}
+
+__global__ void k_val32(const double *val, float *val32, int64_t nnz) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+        val32[p] = (float)val[p];
+}
+
+// FP32 shadow of Z0 - E for a warm start (zero elsewhere).
+__global__ void k_zlo_init(const double *zb, float *zlo, int64_t ldz, const int32_t *idx, int64_t n, int64_t k) {
+    const int64_t total = n * ldz;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / ldz, c = e - j * ldz;
+        const double v = (c < k) ? zb[e] - (j == idx[c] ? 1.0 : 0.0) : 0.0;
+        zlo[e] = (float)v;
+    }
+}
+
+inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) / per); }
+
+}  // namespace
+
+int64_t spmm_row_tiles(int64_t n) { return (n + SP_ROWS - 1) / SP_ROWS; }
+
+hipError_t launch_spmm_sweep(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
+                             const double *val, const float *val32, const double *theta, const double *zin,
+                             double *zout, const float *zlo_in, float *zlo_out, ColState cs, const double *dvec,
+                             double *part, int64_t n, int64_t k, int64_t ldz, int64_t kpc) {
+    int kg = 1;
+    while (kg < k && kg < 64) kg <<= 1;
+    SpArgs a{row_ptr, col, val, val32, theta, zin, zout, zlo_in, zlo_out, cs, dvec, part, n, k, ldz, kpc, kg};
+    k_spmm_sweep<<<(unsigned)spmm_row_tiles(n), 256, 0, s>>>(ctrl, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_csr(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
+                           const double *val, const double *zin, int64_t ldz, ColState cs, double *dvec, int64_t k) {
+    k_diag_csr<<<(unsigned)((k + 3) / 4), 256, 0, s>>>(ctrl, row_ptr, col, val, zin, ldz, cs, dvec, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_csr(hipStream_t s, Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, int64_t n,
+                            int64_t nnz) {
+    int b = blocks_for(n + 1 > nnz ? n + 1 : nnz, 256);
+    if (b > 4096) b = 4096;
+    if (b < blocks_for(n, 256)) b = blocks_for(n, 256);
+    k_check_csr<<<b, 256, 0, s>>>(ctrl, row_ptr, col, n, nnz);
+    return hipGetLastError();
+}
+
+hipError_t launch_val32(hipStream_t s, const double *val, float *val32, int64_t nnz) {
+    int b = blocks_for(nnz, 256);
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    k_val32<<<b, 256, 0, s>>>(val, val32, nnz);
+    return hipGetLastError();
+}
+
+hipError_t launch_zlo_init(hipStream_t s, const double *zb, float *zlo, int64_t ldz, const int32_t *idx, int64_t n,
+                           int64_t k) {
+    int b = blocks_for(n * ldz, 256);
+    if (b > 8192) b = 8192;
+    k_zlo_init<<<b, 256, 0, s>>>(zb, zlo, ldz, idx, n, k);
+    return hipGetLastError();
+}
+
+}  // namespace ipt
