@@ -5,6 +5,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,7 @@ struct ipt_context {
     Ctrl *host_ctrl = nullptr;  // pinned copy of the control block
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     std::vector<hipEvent_t> tev;  // kernel-timing events (IPT_FLAG_TIME_KERNELS), reused across solves
+    int batch_tile_split = 192;    // batched solves: problems with n <= this use 64 x 64 tiles
     std::string last_error;
 };
 
@@ -510,10 +512,163 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     return finish(h, ctrl, k, info, &timer);
 }
 
-ipt_status ipt_solve_batched(ipt_handle h, int32_t, const int32_t *, const int64_t *, const int64_t *, const int64_t *,
-                             const double *, const double *, const ipt_opts *, double *, double *, int32_t *,
-                             ipt_info *) {
-    return fail(h, IPT_EINVAL, "batched path not built yet");
+ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
+                             const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
+                             const double *delta_pool, const ipt_opts *opts, double *z_pool, double *lambda_pool,
+                             int32_t *status_pool, ipt_info *info) {
+    if (!h) return IPT_EINVAL;
+    h->last_error.clear();
+    if (count < 1) return fail(h, IPT_EINVAL, "count must be >= 1");
+    if (!ns || !theta_off || !delta_off || !z_off || !theta_pool || !delta_pool || !z_pool || !lambda_pool ||
+        !status_pool)
+        return fail(h, IPT_EINVAL, "NULL argument");
+    ipt_opts o;
+    if (ipt_status st = check_opts(h, opts, o)) return st;
+    DevOpts dopt = dev_opts(o);
+    dopt.low_type = IPT_LOW_NONE;  // batched ladder: FP32 split-form sweeps, then FP64
+    const bool ladder = dopt.ladder;
+    const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
+    DeviceGuard guard(h->device);
+    hipStream_t s = h->stream;
+
+    // Host plan: per-problem layout, tile size per size bucket, work lists (largest
+    // problems first so the persistent GEMM ends with small items).
+    const int tile_split = h->batch_tile_split;
+    std::vector<BatchMeta> meta(count);
+    int64_t offz = 0, offc = 0, offp = 0, offf = 0, maxn = 0;
+    for (int32_t b = 0; b < count; ++b) {
+        const int64_t n = ns[b];
+        if (n < 1 || n > 4096) return fail(h, IPT_EINVAL, "every problem size must be in [1, 4096]");
+        if (theta_off[b] < 0 || delta_off[b] < 0 || z_off[b] < 0) return fail(h, IPT_EINVAL, "negative offset");
+        BatchMeta &m = meta[b];
+        m.n = (int32_t)n;
+        m.T = n <= tile_split ? 64 : 128;
+        m.offd = delta_off[b];
+        m.offt = theta_off[b];
+        m.offz = offz;
+        m.offc = offc;
+        m.offp = offp;
+        m.offf = offf;
+        const int64_t nt = (n + m.T - 1) / m.T;
+        offz += n * n;
+        offc += n;
+        offp += nt * n * NPART;
+        offf += nt;
+        if (n > maxn) maxn = n;
+    }
+    std::vector<int32_t> order(count);
+    for (int32_t b = 0; b < count; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return meta[x].n > meta[y].n; });
+    std::vector<int4> it64, it128, it_s1, it_dg;
+    for (int32_t b : order) {
+        const BatchMeta &m = meta[b];
+        const int nt = (m.n + m.T - 1) / m.T, ncb = (m.n + 63) / 64;
+        std::vector<int4> &dst = m.T == 64 ? it64 : it128;
+        for (int tn = 0; tn < nt; ++tn)
+            for (int tm = 0; tm < nt; ++tm) dst.push_back(make_int4(b, tm, tn, 0));
+        for (int tm = 0; tm < nt; ++tm)
+            for (int cb = 0; cb < ncb; ++cb) it_s1.push_back(make_int4(b, tm, cb, 0));
+        for (int cb = 0; cb < ncb; ++cb) it_dg.push_back(make_int4(b, 0, cb, 0));
+    }
+    const int64_t total_cols = offc, total_tiles = offf;
+    const int64_t n64 = (int64_t)it64.size(), n128 = (int64_t)it128.size();
+
+    auto layout = [&](Carve &cv, BatchMeta **dmeta, int4 **d64, int4 **d128, int4 **ds1, int4 **ddg, int64_t **dzoff,
+                      double **z0, double **z1, BatchCols &col, double **part, uint32_t **tflag, int32_t **tickets,
+                      double **maxres, Ctrl **ctrl) {
+        *dmeta = cv.take<BatchMeta>(count);
+        *d64 = cv.take<int4>(n64 + 1);
+        *d128 = cv.take<int4>(n128 + 1);
+        *ds1 = cv.take<int4>(it_s1.size());
+        *ddg = cv.take<int4>(it_dg.size());
+        *dzoff = cv.take<int64_t>(count);
+        *z0 = cv.take<double>(offz);
+        *z1 = cv.take<double>(offz);
+        col.state = cv.take<int32_t>(total_cols);
+        col.sweeps = cv.take<int32_t>(total_cols);
+        col.grow = cv.take<int32_t>(total_cols);
+        col.par = cv.take<int32_t>(total_cols);
+        col.prob = cv.take<int32_t>(total_cols);
+        col.prev = cv.take<double>(total_cols);
+        col.step = cv.take<double>(total_cols);
+        col.lam = cv.take<double>(total_cols);
+        col.resid = cv.take<double>(total_cols);
+        col.d = cv.take<double>(total_cols);
+        col.norm_bits = cv.take<uint64_t>(count);
+        *part = cv.take<double>(offp);
+        *tflag = cv.take<uint32_t>(2 * total_tiles);
+        *tickets = cv.take<int32_t>(2);
+        *maxres = cv.take<double>(1);
+        *ctrl = cv.take<Ctrl>(1);
+    };
+    BatchMeta *dmeta;
+    int4 *d64, *d128, *ds1, *ddg;
+    int64_t *dzoff;
+    double *z0, *z1, *part, *maxres;
+    BatchCols col;
+    uint32_t *tflag;
+    int32_t *tickets;
+    Ctrl *ctrl;
+    Carve sizing;
+    layout(sizing, &dmeta, &d64, &d128, &ds1, &ddg, &dzoff, &z0, &z1, col, &part, &tflag, &tickets, &maxres, &ctrl);
+    if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
+    Carve cv;
+    cv.base = (char *)h->ws;
+    layout(cv, &dmeta, &d64, &d128, &ds1, &ddg, &dzoff, &z0, &z1, col, &part, &tflag, &tickets, &maxres, &ctrl);
+
+    // Upload the plan (host-to-device copies ordered on the stream; the host
+    // vectors stay alive until the stream is synchronised below).
+    IPT_HIP(h, hipMemcpyAsync(dmeta, meta.data(), sizeof(BatchMeta) * count, hipMemcpyHostToDevice, s));
+    if (n64) IPT_HIP(h, hipMemcpyAsync(d64, it64.data(), sizeof(int4) * n64, hipMemcpyHostToDevice, s));
+    if (n128) IPT_HIP(h, hipMemcpyAsync(d128, it128.data(), sizeof(int4) * n128, hipMemcpyHostToDevice, s));
+    IPT_HIP(h, hipMemcpyAsync(ds1, it_s1.data(), sizeof(int4) * it_s1.size(), hipMemcpyHostToDevice, s));
+    IPT_HIP(h, hipMemcpyAsync(ddg, it_dg.data(), sizeof(int4) * it_dg.size(), hipMemcpyHostToDevice, s));
+    IPT_HIP(h, hipMemcpyAsync(dzoff, z_off, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
+    IPT_HIP(h, hipStreamSynchronize(s));
+
+    const BatchLaunch L = make_batch_launch(dmeta, theta_pool, delta_pool, z0, z1, col, part, tflag, total_tiles);
+    Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
+    IPT_HIP(h, timer.ensure());
+    IPT_HIP(h, hipEventRecord(h->ev_start, s));
+    IPT_HIP(h, launch_ctrl_init(s, ctrl, PREC_EXACT_FIRST, total_cols));
+    IPT_HIP(h, launch_fill_f32(s, (float *)tickets, 2));
+    IPT_HIP(h, launch_fill_f32(s, (float *)maxres, 2));
+    IPT_HIP(h, launch_binit(s, ctrl, L, count, ladder ? PREC_F32 : PREC_F64));
+    if (norm) IPT_HIP(h, launch_bnorm(s, ctrl, L, count));
+    const int grid64 = bgemm_grid(64), grid128 = bgemm_grid(128);
+
+    PollPlan plan = poll_plan(o, true);
+    if (o.sync_every <= 0) plan = PollPlan{5, 2};
+    for (int32_t t = 1; t <= o.max_iter; ++t) {
+        const int32_t in_buf = (t - 1) & 1;
+        const int32_t in_par = t == 1 ? PAR_UNIT : in_buf;
+        const int32_t out_par = t & 1;
+        IPT_HIP(h, timer.mark(t, 0, s));
+        if (t == 1) {
+            IPT_HIP(h, launch_bsweep1(s, ctrl, L, ds1, (int64_t)it_s1.size()));
+        } else {
+            IPT_HIP(h, launch_bdiag(s, ctrl, L, ddg, (int64_t)it_dg.size(), in_buf));
+            IPT_HIP(h, launch_bgemm(s, ctrl, L, 128, d128, n128, t, in_buf, tickets + 1, grid128));
+            IPT_HIP(h, launch_bgemm(s, ctrl, L, 64, d64, n64, t, in_buf, tickets, grid64));
+        }
+        IPT_HIP(h, timer.mark(t, 1, s));
+        IPT_HIP(h, launch_bfinalize(s, ctrl, dopt, L, total_cols, t, in_par, out_par));
+        IPT_HIP(h, launch_bcontrol(s, ctrl, dopt, t, tickets));
+        if (plan.at(t, o.max_iter)) {
+            int32_t err, done;
+            if (ipt_status st = poll_ctrl(h, ctrl, err, done)) return st;
+            if (err || done) break;
+        }
+    }
+    IPT_HIP(h, launch_bcopyout(s, ctrl, L, dzoff, z_pool, lambda_pool, status_pool, total_cols, maxres));
+    ipt_status st = finish(h, ctrl, total_cols, info, &timer);
+    if (info && (st == IPT_OK || st == IPT_ENOTCONV)) {
+        double mr = 0.0;
+        IPT_HIP(h, hipMemcpy(&mr, maxres, sizeof(double), hipMemcpyDeviceToHost));
+        info->max_resid = mr;
+        info->norm1 = 0.0;
+    }
+    return st;
 }
 
 }  // extern "C"

@@ -84,6 +84,7 @@ constexpr int DIAG_SPLIT = 64;  // max partial sums per d_c (dpart is DIAG_SPLIT
 // Setup and bookkeeping (ipt_setup.hip)
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp);
+hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active);
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
                               int64_t k);
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
@@ -125,6 +126,44 @@ hipError_t launch_check_csr(hipStream_t s, Ctrl *ctrl, const int32_t *row_ptr, c
 hipError_t launch_val32(hipStream_t s, const double *val, float *val32, int64_t nnz);
 hipError_t launch_zlo_init(hipStream_t s, const double *zb, float *zlo, int64_t ldz, const int32_t *idx, int64_t n,
                            int64_t k);
+
+// Batched solves (ipt_batched.hip).  Problem b: size n, tile size T, offsets of its
+// Delta (caller pool), theta (caller pool), iterate buffers, columns, partial sums
+// and column-tile flags.
+struct BatchMeta {
+    int32_t n, T;
+    int64_t offd, offt, offz, offc, offp, offf;
+};
+struct BatchCols {  // per column of all problems, concatenated
+    int32_t *state, *sweeps, *grow, *par, *prob;
+    double *prev, *step, *lam, *resid, *d;
+    uint64_t *norm_bits;  // per problem: |M_b|_1 (bits)
+};
+struct BatchLaunch {
+    const BatchMeta *meta;
+    const double *theta, *delta;
+    double *z0, *z1;
+    BatchCols col;
+    double *part;
+    uint32_t *tflag;  // [2][total column tiles]: (sweep << 2) | precision
+    int64_t total_tiles;
+};
+BatchLaunch make_batch_launch(const BatchMeta *meta, const double *theta, const double *delta, double *z0, double *z1,
+                              BatchCols col, double *part, uint32_t *tflag, int64_t total_tiles);
+hipError_t launch_binit(hipStream_t s, Ctrl *ctrl, const BatchLaunch &L, int32_t count, int32_t start_prec);
+hipError_t launch_bnorm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, int32_t count);
+hipError_t launch_bsweep1(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems);
+hipError_t launch_bdiag(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
+                        int32_t in_buf);
+hipError_t launch_bgemm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, int tile, const int4 *items,
+                        int64_t nitems, int32_t sweep, int32_t in_buf, int32_t *ticket, int grid);
+hipError_t launch_bfinalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
+                            int32_t sweep, int32_t in_par, int32_t out_par);
+hipError_t launch_bcontrol(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, int32_t *tickets);
+hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int64_t *z_off,
+                           double *z_pool, double *lambda_pool, int32_t *status_pool, int64_t total_cols,
+                           double *max_resid_out);
+int bgemm_grid(int tile);  // persistent grid size (CUs x resident blocks)
 
 // The product and fused epilogue of one sweep (ipt_gemm.hip), in the precision the
 // device-side ladder chose (ctrl->prec).

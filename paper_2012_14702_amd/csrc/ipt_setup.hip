@@ -555,6 +555,11 @@ hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *id
     return hipGetLastError();
 }
 
+hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active) {
+    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, active);
+    return hipGetLastError();
+}
+
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
                               int64_t k) {
     dim3 g(blocks_for(n, 256), blocks_for(k, 256));
