@@ -98,6 +98,84 @@ def cpu_baseline(theta, delta, seconds):
                       "plain C FP64, OpenMP over columns); %.1f s" % (cols - 1, n, dt)}
 
 
+def _time(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, r
+
+
+def bench_sparse(ipt, handle, args):
+    """Sparse extremal workload: n = 200000, theta_i = i, about 12 symmetric
+    off-diagonal entries per row with values U(-0.05, 0.05), the 16 lowest eigenpairs,
+    tol 1e-10; FP64 SpMM sweeps and the FP32-SpMM + FP64-finish ladder."""
+    import torch
+    import workloads
+    n, k = 200000, 16
+    th, rp, col, val = workloads.sparse_sym_uniform(n, seed=0)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(a).to(dev)
+    thd, rpd, cold, vald = T(th), T(rp), T(col), T(val)
+    idx = T(workloads.lowest_indices(th, k))
+    nnz = int(val.shape[0])
+    res = {}
+    for name, prec in (("fp64", ipt.PREC_FP64), ("ladder", ipt.PREC_LADDER)):
+        o = ipt.default_opts(tol=1e-10, precision=prec, flags=ipt.FLAG_TIME_KERNELS)
+        run = lambda: ipt.ipt_solve_csr(thd, rpd, cold, vald, idx, opts=o, handle=handle, colinfo=False)
+        _time(run, 3)
+        sec, r = _time(run, max(5, args.steps))
+        inf = r.info
+        # algorithmic bytes of one SpMM sweep: CSR arrays, row pointers, one read of
+        # the gathered rows of Z, one read of Z and one write of W in the epilogue
+        zb = 8 if name == "fp64" else 4
+        per = 12.0 * nnz + 4.0 * (n + 1) + zb * n * k + 2 * 8.0 * n * k
+        ms = sum(inf["prec_ms"].values())
+        nl = sum(inf["prec_sweeps"].values())
+        res[name] = {"eigenpairs_per_s": round(int(inf["converged"]) / sec, 1), "ms_per_solve": round(sec * 1e3, 4),
+                     "converged": inf["converged"], "sweeps": inf["sweeps"], "sweep_prec": inf["sweep_prec"],
+                     "spmm_avg_launch_ms": round(ms / max(nl, 1), 5),
+                     "spmm_GBps": round(per / (ms / max(nl, 1) * 1e-3) / 1e9, 1),
+                     "spmm_frac_of_hbm": round(per / (ms / max(nl, 1) * 1e-3) / 1e9 / HBM_PEAK, 4)}
+        log("sparse %s: %.3f ms/solve, sweeps %s" % (name, sec * 1e3, inf["sweep_prec"]))
+    return {"workload": "sparse n=200000, ~12 sym off-diagonals/row U(-0.05,0.05), k=16 lowest, tol 1e-10",
+            "nnz": nnz, "modes": res}
+
+
+def bench_batched(ipt, handle, args):
+    """Batched workload: problems with n ~ U{32..512}, theta sorted U(0, n),
+    Delta = 0.02 (R + R^T)/2, R iid N(0, 1/n), full spectra, tol 1e-10, max 64 sweeps;
+    FP32 split-form sweeps + FP64 finish vs plain FP64."""
+    import torch
+    import workloads
+    B = args.batch
+    t0 = time.perf_counter()
+    ns, th, de, th_off, de_off = workloads.batched_sym_gaussian(B, 32, 512, 0.02, seed=0)
+    log("batched inputs generated in %.1f s (%d problems, %.2f GB)" % (time.perf_counter() - t0, B, de.nbytes / 1e9))
+    dev = torch.device("cuda:0")
+    thd = torch.from_numpy(th).to(dev)
+    ded = torch.from_numpy(de).to(dev)
+    del de
+    res = {}
+    for name, prec in (("ladder", ipt.PREC_LADDER), ("fp64", ipt.PREC_FP64)):
+        o = ipt.default_opts(tol=1e-10, precision=prec, max_iter=64)
+        run = lambda: ipt.ipt_solve_batched(ns, thd, ded, th_off, de_off, opts=o, handle=handle)
+        _time(run, 1)
+        sec, r = _time(run, 3)
+        inf = r.info
+        res[name] = {"eigenpairs_per_s": round(int(inf["converged"]) / sec, 1), "ms_per_solve": round(sec * 1e3, 3),
+                     "converged": inf["converged"], "not_converged": inf["not_converged"],
+                     "diverged": inf["diverged"], "sweeps": inf["sweeps"],
+                     "converged_fraction": round(inf["converged"] / float(ns.sum()), 5)}
+        log("batched %s: %.2f ms/solve, %d/%d converged, %d sweeps" % (name, sec * 1e3, inf["converged"],
+                                                                     int(ns.sum()), inf["sweeps"]))
+        del r
+    return {"workload": "batched %d problems n~U{32..512}, theta=sort(U(0,n)), Delta=0.02*sym N(0,1/n), "
+                        "full spectra, tol 1e-10, max 64 sweeps" % B, "eigenpairs": int(ns.sum()), "modes": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,7 +186,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "ladder", "fp64"], default="all",
-                    help="restrict to one mode (for profiler runs)")
+                    help="restrict the dense workload to one mode (for profiler runs)")
+    ap.add_argument("--extra", default="sparse,batched",
+                    help="comma list of secondary workloads to time: sparse, batched ('' for none)")
+    ap.add_argument("--batch", type=int, default=4096, help="problems in the batched workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -205,6 +286,11 @@ def main():
     }
     if ("fp64" in modes) and ("ladder" in modes):
         out["ladder_speedup_vs_fp64"] = round(results[(args.eps, "fp64")]["sec"] / results[(args.eps, "ladder")]["sec"], 3)
+    extras = [e for e in args.extra.split(",") if e]
+    if "sparse" in extras:
+        out["sparse"] = bench_sparse(ipt, handle, args)
+    if "batched" in extras:
+        out["batched"] = bench_batched(ipt, handle, args)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
         th, de = host[args.eps]

@@ -500,7 +500,8 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
                                      ladder ? zlo[(t - 1) & 1] : nullptr, ladder ? zlo[t & 1] : nullptr, cs, dvec,
                                      part, n, k, ldzb, kpc));
         IPT_HIP(h, timer.mark(t, 1, s));
-        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, nrt, kpc, t, in_par, out_par));
+        IPT_HIP(h, launch_reduce_parts(s, ctrl, cs, part, nrt, kpc));
+        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, 1, kpc, t, in_par, out_par));
         IPT_HIP(h, launch_control(s, ctrl, dopt, t));
         if (plan.at(t, o.max_iter)) {
             int32_t err, done;

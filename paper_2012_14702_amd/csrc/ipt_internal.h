@@ -115,6 +115,7 @@ hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count);  // zero fil
 
 // Sparse sweeps (ipt_spmm.hip)
 int64_t spmm_row_tiles(int64_t n);
+hipError_t launch_reduce_parts(hipStream_t s, const Ctrl *ctrl, ColState cs, double *part, int64_t nblk, int64_t kpc);
 hipError_t launch_spmm_sweep(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
                              const double *val, const float *val32, const double *theta, const double *zin,
                              double *zout, const float *zlo_in, float *zlo_out, ColState cs, const double *dvec,

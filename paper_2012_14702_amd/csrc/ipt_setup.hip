@@ -440,13 +440,19 @@ __global__ void k_control(Ctrl *ctrl, DevOpts o, int32_t sweep) {
     if (ctrl->active == 0 || sweep >= o.max_iter) ctrl->done = 1;
     int32_t next = PREC_F64;
     if (o.ladder) {
+        // Leave a rung when its step is below the rung's threshold, when it stopped
+        // falling (the rung's rounding floor), or when the next exact sweep is
+        // predicted to certify: with the observed contraction ratio q = s_t / s_{t-1},
+        // the next step is about q s_t.
         const bool stalled = !(ms < ctrl->prev_maxstep);
+        const double predicted = ms * (ms / ctrl->prev_maxstep);
+        const bool certify_next = isfinite(predicted) && predicted <= o.tol;
         if (prec == PREC_EXACT_FIRST) {
             next = (ms <= o.tau_32) ? PREC_F64 : (ms <= o.tau_low || o.low_type == IPT_LOW_NONE) ? PREC_F32 : PREC_LOW;
         } else if (prec == PREC_LOW) {
             next = (ms <= o.tau_32) ? PREC_F64 : (ms <= o.tau_low || stalled) ? PREC_F32 : PREC_LOW;
         } else if (prec == PREC_F32) {
-            next = (ms <= o.tau_32 || stalled) ? PREC_F64 : PREC_F32;
+            next = (ms <= o.tau_32 || stalled || certify_next) ? PREC_F64 : PREC_F32;
         }
     }
     ctrl->prec = next;

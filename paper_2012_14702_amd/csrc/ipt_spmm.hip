@@ -21,7 +21,7 @@ namespace ipt {
 
 namespace {
 
-constexpr int SP_ROWS = 512;  // rows per block (one partial-sum row tile)
+constexpr int SP_ROWS = 64;  // rows per block (one partial-sum row tile before the block reduction)
 
 struct SpArgs {
     const int32_t *row_ptr;
@@ -67,10 +67,42 @@ __global__ __launch_bounds__(256) void k_spmm_sweep(const Ctrl *ctrl, SpArgs a) 
             const int32_t pb = a.row_ptr[j], pe = a.row_ptr[j + 1];
             double y = 0.0, ye = 0.0;
             float y32 = 0.f;
+            // Entries are taken four at a time so that four gathers of Z rows are in
+            // flight per lane; the sum still runs in storage order.
+            int32_t p = pb;
             if (!f32) {
-                for (int32_t p = pb; p < pe; ++p) y += a.val[p] * a.zin[(int64_t)a.col[p] * a.ldz + c];
+                for (; p + 4 <= pe; p += 4) {
+                    int32_t cq[4];
+                    double vq[4], zq[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        cq[u] = a.col[p + u];
+                        vq[u] = a.val[p + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) zq[u] = a.zin[(int64_t)cq[u] * a.ldz + c];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) y += vq[u] * zq[u];
+                }
+                for (; p < pe; ++p) y += a.val[p] * a.zin[(int64_t)a.col[p] * a.ldz + c];
             } else {
-                for (int32_t p = pb; p < pe; ++p) {
+                for (; p + 4 <= pe; p += 4) {
+                    int32_t cq[4];
+                    float vq[4], zq[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        cq[u] = a.col[p + u];
+                        vq[u] = a.val32[p + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) zq[u] = a.zlo_in[(int64_t)cq[u] * a.ldz + c];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        y32 += vq[u] * zq[u];
+                        if (cq[u] == i) ye += a.val[p + u];
+                    }
+                }
+                for (; p < pe; ++p) {
                     const int32_t cp = a.col[p];
                     y32 += a.val32[p] * a.zlo_in[(int64_t)cp * a.ldz + c];
                     if (cp == i) ye += a.val[p];
@@ -127,6 +159,27 @@ __global__ __launch_bounds__(256) void k_spmm_sweep(const Ctrl *ctrl, SpArgs a) 
     }
 }
 
+// Second level of the per-column reduction: part[0][c][q] <- sum over all row blocks
+// of part[blk][c][q].  Block per (column, quantity); thread t adds blocks t, t + 256,
+// ... in order, then a fixed tree over the 256 threads.
+__global__ __launch_bounds__(256) void k_reduce_parts(const Ctrl *ctrl, const ColState cs, double *part, int64_t nblk,
+                                                      int64_t kpc) {
+    if (ctrl->error || ctrl->done) return;
+    __shared__ double sh[256];
+    const int64_t c = blockIdx.x >> 2;
+    const int q = blockIdx.x & 3;
+    if (cs.state[c] != COL_ACTIVE) return;
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nblk; b += 256) acc += part[(b * kpc + c) * NPART + q];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[c * NPART + q] = sh[0];
+}
+
 // d_c = (Delta Z)_{i,c} = sum over row i of val[p] Z[col[p], c], FP64, one wave per
 // column: lane-strided partial sums then a fixed xor tree.
 __global__ void k_diag_csr(const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, const double *val,
@@ -174,6 +227,11 @@ inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) /
 }  // namespace
 
 int64_t spmm_row_tiles(int64_t n) { return (n + SP_ROWS - 1) / SP_ROWS; }
+
+hipError_t launch_reduce_parts(hipStream_t s, const Ctrl *ctrl, ColState cs, double *part, int64_t nblk, int64_t kpc) {
+    k_reduce_parts<<<(unsigned)(kpc * 4), 256, 0, s>>>(ctrl, cs, part, nblk, kpc);
+    return hipGetLastError();
+}
 
 hipError_t launch_spmm_sweep(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
                              const double *val, const float *val32, const double *theta, const double *zin,
