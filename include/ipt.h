@@ -178,6 +178,56 @@ ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, con
                              const double *delta_pool, const ipt_opts *opts, double *z_pool, double *lambda_pool,
                              int32_t *status_pool, ipt_info *info);
 
+/*
+ * Learned warm start: a small MLP x -> [Linear -> tanh] x depth -> Linear -> y, trained
+ * and evaluated with the library's own kernels (BF16 MFMA GEMMs with FP32
+ * accumulation, MSE loss, Adam on FP32 master weights with a BF16 compute copy).  It
+ * predicts Z0 for a parametrised family M(eps) = D + eps R (initial guesses, Sec. 7);
+ * the solve it warm-starts still certifies every column with FP64 sweeps, so the
+ * network can change the cost of a solve but not its answer.
+ * Parameters are stored layer by layer as W_l (out_l x in_l, row-major) then b_l.
+ * All arrays are device pointers; x is batch x in_dim and y / targets batch x out_dim,
+ * row-major FP32.  The MLP runs on its handle's stream; destroy it before the handle.
+ */
+typedef struct ipt_mlp_context *ipt_mlp;
+
+/* hidden >= 1, depth >= 1 hidden layers, in_dim/out_dim >= 1; weights drawn from
+ * Glorot-uniform with a 64-bit seed, biases zero.  Errors: IPT_EINVAL, IPT_ENOMEM, IPT_EHIP. */
+ipt_status ipt_mlp_create(ipt_handle h, int32_t in_dim, int32_t hidden, int32_t depth, int32_t out_dim, uint64_t seed,
+                          ipt_mlp *out);
+ipt_status ipt_mlp_destroy(ipt_mlp m);
+/* Number of FP32 parameters (the length of the get/set/grad buffers); -1 for NULL. */
+int64_t ipt_mlp_num_params(ipt_mlp m);
+ipt_status ipt_mlp_get_params(ipt_mlp m, float *dst);
+ipt_status ipt_mlp_set_params(ipt_mlp m, const float *src);
+/* y = network(x) with the BF16 weight copy. */
+ipt_status ipt_mlp_forward(ipt_mlp m, const float *x, int32_t batch, float *y);
+/* Mean squared error of network(x) against targets and its gradient with respect to
+ * every parameter (no update).  loss: host float. */
+ipt_status ipt_mlp_loss_grad(ipt_mlp m, const float *x, const float *targets, int32_t batch, float *loss,
+                             float *grad);
+/* `steps` full-batch Adam steps (beta 0.9/0.999, eps 1e-8) at learning rate lr;
+ * *loss (host) receives the loss before the last update. */
+ipt_status ipt_mlp_train(ipt_mlp m, const float *x, const float *targets, int32_t batch, int32_t steps, float lr,
+                         float *loss);
+/* Warm starts for `batch` problems: y = network(x), then for problem p
+ * Z0_p[j, c] = 1 if j == idx[c], else scale[p] (mu[q] + sigma[q] y[p, q]) with q = j k + c
+ * (out_dim must equal n k).  z0 of problem p starts at z0 + p * pstride (leading
+ * dimension ldz0 >= k). */
+ipt_status ipt_mlp_predict_z0(ipt_mlp m, const float *x, int32_t batch, const float *mu, const float *sigma,
+                              const double *scale, int64_t n, int64_t k, const int32_t *idx, double *z0, int64_t ldz0,
+                              int64_t pstride);
+
+/* Standardised training targets for the warm-start network.  For problem p and output
+ * q = j k + c: r_pq = (Z_p[j, c] - [j == idx[c]]) / scale[p]; mu_q and sigma_q are the mean
+ * and standard deviation of r_.q over the batch, summed in problem order (sigma_q = 1
+ * where it would be below 1e-300); targets[p, q] = (r_pq - mu_q) / sigma_q.  Z_p starts at
+ * z + p * pstride with leading dimension ldz; targets is batch x (n k) FP32; mu and sigma
+ * are (n k) FP32.  Runs on the handle's stream and returns when done. */
+ipt_status ipt_mlp_targets(ipt_handle h, const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz,
+                           int64_t pstride, const int32_t *idx, const double *scale, float *targets, float *mu,
+                           float *sigma);
+
 /* Static description of a status code. */
 const char *ipt_status_string(ipt_status s);
 /* Message of the last failing call on h ("" if none); valid until the next call on h. */

@@ -673,3 +673,262 @@ ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, con
 }
 
 }  // extern "C"
+
+// ======================================================================= MLP
+struct ipt_mlp_context {
+    ipt_handle h = nullptr;
+    int in = 0, hid = 0, depth = 0, out = 0;
+    int64_t nparam = 0;
+    std::vector<int64_t> woff, boff;  // per linear layer (depth + 1 layers)
+    std::vector<int> lin, lout;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    __bf16 *wb = nullptr;
+    float *act = nullptr;  // activations H_1..H_depth (batch x hid each)
+    float *dpre = nullptr, *dpre2 = nullptr;  // gradient scratch (batch x hid)
+    float *y = nullptr, *gy = nullptr;        // output and its gradient (batch x out)
+    double *partial = nullptr;
+    float *loss_dev = nullptr;
+    int cap_batch = 0;
+    int adam_step = 0;
+};
+
+namespace {
+
+ipt_status mlp_fail(ipt_mlp m, ipt_status st, const std::string &msg) { return fail(m ? m->h : nullptr, st, msg); }
+
+#define IPT_MHIP(m, expr)                                                                                      \
+    do {                                                                                                       \
+        hipError_t e_ = (expr);                                                                                \
+        if (e_ != hipSuccess) return mlp_fail((m), IPT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void mlp_free_batch(ipt_mlp m) {
+    for (void *p : {(void *)m->act, (void *)m->dpre, (void *)m->dpre2, (void *)m->y, (void *)m->gy, (void *)m->partial})
+        if (p) (void)hipFree(p);
+    m->act = m->dpre = m->dpre2 = m->y = m->gy = nullptr;
+    m->partial = nullptr;
+    m->cap_batch = 0;
+}
+
+ipt_status mlp_ensure_batch(ipt_mlp m, int batch) {
+    if (batch <= m->cap_batch) return IPT_OK;
+    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    mlp_free_batch(m);
+    const size_t nb = (size_t)batch;
+    if (hipMalloc(&m->act, sizeof(float) * nb * m->hid * m->depth) != hipSuccess ||
+        hipMalloc(&m->dpre, sizeof(float) * nb * m->hid) != hipSuccess ||
+        hipMalloc(&m->dpre2, sizeof(float) * nb * m->hid) != hipSuccess ||
+        hipMalloc(&m->y, sizeof(float) * nb * m->out) != hipSuccess ||
+        hipMalloc(&m->gy, sizeof(float) * nb * m->out) != hipSuccess ||
+        hipMalloc(&m->partial, sizeof(double) * 4096) != hipSuccess) {
+        (void)hipGetLastError();
+        mlp_free_batch(m);
+        return mlp_fail(m, IPT_ENOMEM, "MLP activation buffers");
+    }
+    m->cap_batch = batch;
+    return IPT_OK;
+}
+
+// Forward pass: activations into m->act, output into y.
+ipt_status mlp_forward_impl(ipt_mlp m, const float *x, int batch, float *y) {
+    hipStream_t s = m->h->stream;
+    const float *hin = x;
+    for (int l = 0; l <= m->depth; ++l) {
+        const bool last = l == m->depth;
+        float *dst = last ? y : m->act + (size_t)l * batch * m->hid;
+        IPT_MHIP(m, mlp_gemm(s, hin, false, m->lin[l], true, m->wb + m->woff[l], true, m->lin[l], true, dst,
+                             m->lout[l], m->w + m->boff[l], nullptr, 0, batch, m->lout[l], m->lin[l],
+                             last ? 0 : 1));
+        hin = dst;
+    }
+    return IPT_OK;
+}
+
+// Loss and gradient of every parameter into m->g (forward included).
+ipt_status mlp_backward_impl(ipt_mlp m, const float *x, const float *tg, int batch) {
+    hipStream_t s = m->h->stream;
+    if (ipt_status st = mlp_forward_impl(m, x, batch, m->y)) return st;
+    IPT_MHIP(m, mlp_mse(s, m->y, tg, m->gy, (int64_t)batch * m->out, m->partial, m->loss_dev));
+    const float *dcur = m->gy;  // gradient of the current layer's pre-activation
+    float *bufs[2] = {m->dpre, m->dpre2};
+    for (int l = m->depth; l >= 0; --l) {
+        const float *hin = l == 0 ? x : m->act + (size_t)(l - 1) * batch * m->hid;
+        // dW_l = dPre_l^T H_{l-1}: M = out_l, N = in_l, K = batch (both operands r-contiguous)
+        IPT_MHIP(m, mlp_gemm(s, dcur, false, m->lout[l], false, hin, false, m->lin[l], false, m->g + m->woff[l],
+                             m->lin[l], nullptr, nullptr, 0, m->lout[l], m->lin[l], batch, 0));
+        IPT_MHIP(m, mlp_colsum(s, dcur, batch, m->lout[l], m->g + m->boff[l]));
+        if (l > 0) {
+            // dPre_{l-1} = (dPre_l W_l) o (1 - H_{l-1}^2): M = batch, N = in_l, K = out_l
+            float *dnext = bufs[l & 1];
+            IPT_MHIP(m, mlp_gemm(s, dcur, false, m->lout[l], true, m->wb + m->woff[l], true, m->lin[l], false, dnext,
+                                 m->lin[l], nullptr, hin, m->lin[l], batch, m->lin[l], m->lout[l], 2));
+            dcur = dnext;
+        }
+    }
+    return IPT_OK;
+}
+
+uint64_t splitmix64(uint64_t &x) {
+    uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+ipt_status ipt_mlp_create(ipt_handle h, int32_t in_dim, int32_t hidden, int32_t depth, int32_t out_dim, uint64_t seed,
+                          ipt_mlp *out) {
+    if (!h || !out) return IPT_EINVAL;
+    *out = nullptr;
+    if (in_dim < 1 || hidden < 1 || depth < 1 || depth > 16 || out_dim < 1)
+        return fail(h, IPT_EINVAL, "MLP sizes must be >= 1 (depth <= 16)");
+    DeviceGuard guard(h->device);
+    ipt_mlp m = new (std::nothrow) ipt_mlp_context();
+    if (!m) return IPT_ENOMEM;
+    m->h = h;
+    m->in = in_dim;
+    m->hid = hidden;
+    m->depth = depth;
+    m->out = out_dim;
+    int64_t off = 0;
+    for (int l = 0; l <= depth; ++l) {
+        const int li = l == 0 ? in_dim : hidden, lo = l == depth ? out_dim : hidden;
+        m->lin.push_back(li);
+        m->lout.push_back(lo);
+        m->woff.push_back(off);
+        off += (int64_t)li * lo;
+        m->boff.push_back(off);
+        off += lo;
+    }
+    m->nparam = off;
+    std::vector<float> host(off, 0.f);
+    uint64_t st = seed;
+    for (int l = 0; l <= depth; ++l) {
+        const double a = sqrt(6.0 / (double)(m->lin[l] + m->lout[l]));  // Glorot uniform
+        for (int64_t e = 0; e < (int64_t)m->lin[l] * m->lout[l]; ++e) {
+            const double u = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0);
+            host[m->woff[l] + e] = (float)((2.0 * u - 1.0) * a);
+        }
+    }
+    const size_t bytes = sizeof(float) * off;
+    if (hipMalloc(&m->w, bytes) != hipSuccess || hipMalloc(&m->g, bytes) != hipSuccess ||
+        hipMalloc(&m->m, bytes) != hipSuccess || hipMalloc(&m->v, bytes) != hipSuccess ||
+        hipMalloc(&m->wb, sizeof(__bf16) * off) != hipSuccess || hipMalloc(&m->loss_dev, sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        ipt_mlp_destroy(m);
+        return fail(h, IPT_ENOMEM, "MLP parameter buffers");
+    }
+    hipStream_t s = h->stream;
+    if (hipMemcpyAsync(m->w, host.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemsetAsync(m->m, 0, bytes, s) != hipSuccess || hipMemsetAsync(m->v, 0, bytes, s) != hipSuccess ||
+        mlp_to_bf16(s, m->w, m->wb, off) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        ipt_mlp_destroy(m);
+        return fail(h, IPT_EHIP, "MLP initialisation");
+    }
+    *out = m;
+    return IPT_OK;
+}
+
+ipt_status ipt_mlp_destroy(ipt_mlp m) {
+    if (!m) return IPT_EINVAL;
+    DeviceGuard guard(m->h->device);
+    (void)hipStreamSynchronize(m->h->stream);
+    mlp_free_batch(m);
+    for (void *p : {(void *)m->w, (void *)m->g, (void *)m->m, (void *)m->v, (void *)m->wb, (void *)m->loss_dev})
+        if (p) (void)hipFree(p);
+    delete m;
+    return IPT_OK;
+}
+
+int64_t ipt_mlp_num_params(ipt_mlp m) { return m ? m->nparam : -1; }
+
+ipt_status ipt_mlp_get_params(ipt_mlp m, float *dst) {
+    if (!m || !dst) return IPT_EINVAL;
+    DeviceGuard guard(m->h->device);
+    IPT_MHIP(m, hipMemcpyAsync(dst, m->w, sizeof(float) * m->nparam, hipMemcpyDeviceToDevice, m->h->stream));
+    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    return IPT_OK;
+}
+
+ipt_status ipt_mlp_set_params(ipt_mlp m, const float *src) {
+    if (!m || !src) return IPT_EINVAL;
+    DeviceGuard guard(m->h->device);
+    IPT_MHIP(m, hipMemcpyAsync(m->w, src, sizeof(float) * m->nparam, hipMemcpyDeviceToDevice, m->h->stream));
+    IPT_MHIP(m, mlp_to_bf16(m->h->stream, m->w, m->wb, m->nparam));
+    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    return IPT_OK;
+}
+
+ipt_status ipt_mlp_forward(ipt_mlp m, const float *x, int32_t batch, float *y) {
+    if (!m || !x || !y || batch < 1) return m ? mlp_fail(m, IPT_EINVAL, "bad MLP forward arguments") : IPT_EINVAL;
+    DeviceGuard guard(m->h->device);
+    if (ipt_status st = mlp_ensure_batch(m, batch)) return st;
+    if (ipt_status st = mlp_forward_impl(m, x, batch, y)) return st;
+    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    return IPT_OK;
+}
+
+ipt_status ipt_mlp_loss_grad(ipt_mlp m, const float *x, const float *targets, int32_t batch, float *loss,
+                             float *grad) {
+    if (!m || !x || !targets || batch < 1) return m ? mlp_fail(m, IPT_EINVAL, "bad MLP arguments") : IPT_EINVAL;
+    DeviceGuard guard(m->h->device);
+    if (ipt_status st = mlp_ensure_batch(m, batch)) return st;
+    if (ipt_status st = mlp_backward_impl(m, x, targets, batch)) return st;
+    if (grad)
+        IPT_MHIP(m, hipMemcpyAsync(grad, m->g, sizeof(float) * m->nparam, hipMemcpyDeviceToDevice, m->h->stream));
+    float l = 0.f;
+    IPT_MHIP(m, hipMemcpyAsync(&l, m->loss_dev, sizeof(float), hipMemcpyDeviceToHost, m->h->stream));
+    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    if (loss) *loss = l;
+    return IPT_OK;
+}
+
+ipt_status ipt_mlp_train(ipt_mlp m, const float *x, const float *targets, int32_t batch, int32_t steps, float lr,
+                         float *loss) {
+    if (!m || !x || !targets || batch < 1 || steps < 0 || !(lr > 0.f))
+        return m ? mlp_fail(m, IPT_EINVAL, "bad MLP training arguments") : IPT_EINVAL;
+    DeviceGuard guard(m->h->device);
+    if (ipt_status st = mlp_ensure_batch(m, batch)) return st;
+    for (int32_t it = 0; it < steps; ++it) {
+        if (ipt_status st = mlp_backward_impl(m, x, targets, batch)) return st;
+        m->adam_step += 1;
+        IPT_MHIP(m, mlp_adam(m->h->stream, m->w, m->wb, m->g, m->m, m->v, m->nparam, lr, m->adam_step));
+    }
+    float l = 0.f;
+    IPT_MHIP(m, hipMemcpyAsync(&l, m->loss_dev, sizeof(float), hipMemcpyDeviceToHost, m->h->stream));
+    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    if (loss) *loss = l;
+    return IPT_OK;
+}
+
+ipt_status ipt_mlp_predict_z0(ipt_mlp m, const float *x, int32_t batch, const float *mu, const float *sigma,
+                              const double *scale, int64_t n, int64_t k, const int32_t *idx, double *z0, int64_t ldz0,
+                              int64_t pstride) {
+    if (!m || !x || !mu || !sigma || !scale || !idx || !z0 || batch < 1 || n < 1 || k < 1 || k > n || ldz0 < k ||
+        n * k != m->out || pstride < (n - 1) * ldz0 + k)
+        return m ? mlp_fail(m, IPT_EINVAL, "bad warm-start arguments (out_dim must be n k)") : IPT_EINVAL;
+    DeviceGuard guard(m->h->device);
+    if (ipt_status st = mlp_ensure_batch(m, batch)) return st;
+    if (ipt_status st = mlp_forward_impl(m, x, batch, m->y)) return st;
+    IPT_MHIP(m, mlp_warm_start(m->h->stream, m->y, m->out, mu, sigma, scale, n, k, idx, z0, ldz0, pstride, batch));
+    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    return IPT_OK;
+}
+
+ipt_status ipt_mlp_targets(ipt_handle h, const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz,
+                           int64_t pstride, const int32_t *idx, const double *scale, float *targets, float *mu,
+                           float *sigma) {
+    if (!h) return IPT_EINVAL;
+    if (!z || !idx || !scale || !targets || !mu || !sigma || batch < 1 || n < 1 || k < 1 || k > n || ldz < k ||
+        pstride < (n - 1) * ldz + k)
+        return fail(h, IPT_EINVAL, "bad target arguments");
+    DeviceGuard guard(h->device);
+    IPT_HIP(h, mlp_targets(h->stream, z, batch, n, k, ldz, pstride, idx, scale, targets, mu, sigma));
+    IPT_HIP(h, hipStreamSynchronize(h->stream));
+    return IPT_OK;
+}
+
+}  // extern "C"

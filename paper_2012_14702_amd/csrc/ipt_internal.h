@@ -166,6 +166,23 @@ hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L
                            double *max_resid_out);
 int bgemm_grid(int tile);  // persistent grid size (CUs x resident blocks)
 
+// MLP kernels (ipt_mlp.hip)
+hipError_t mlp_gemm(hipStream_t s, const void *A, bool a_bf16, int64_t lda, bool a_kcontig, const void *B,
+                    bool b_bf16, int64_t ldb, bool b_kcontig, float *C, int64_t ldc, const float *bias, const float *h,
+                    int64_t ldh, int M, int N, int K, int epi);
+hipError_t mlp_mse(hipStream_t s, const float *y, const float *tg, float *g, int64_t count, double *partial,
+                   float *loss_dev);
+hipError_t mlp_colsum(hipStream_t s, const float *g, int B, int N, float *db);
+hipError_t mlp_adam(hipStream_t s, float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t count, float lr,
+                    int step);
+hipError_t mlp_to_bf16(hipStream_t s, const float *w, __bf16 *wb, int64_t count);
+hipError_t mlp_targets(hipStream_t s, const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz,
+                       int64_t pstride, const int32_t *idx, const double *scale, float *targets, float *mu,
+                       float *sigma);
+hipError_t mlp_warm_start(hipStream_t s, const float *y, int64_t ldy, const float *mu, const float *sigma,
+                          const double *scale, int64_t n, int64_t k, const int32_t *idx, double *z0, int64_t ldz0,
+                          int64_t pstride, int32_t count);
+
 // The product and fused epilogue of one sweep (ipt_gemm.hip), in the precision the
 // device-side ladder chose (ctrl->prec).
 hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const void *dlo,

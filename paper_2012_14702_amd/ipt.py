@@ -301,3 +301,124 @@ def ipt_solve_batched(ns, theta_pool, delta_pool, theta_off=None, delta_off=None
                                _ptr(theta_pool), _ptr(delta_pool), C.byref(o), _ptr(z), _ptr(lam), _ptr(status),
                                C.byref(info))
     return _finish(lib, h, st, z, lam, status, info, None)
+
+
+# ------------------------------------------------------------------ learned warm start
+_mlp_bound = False
+
+
+def _bind_mlp(lib):
+    global _mlp_bound
+    if _mlp_bound:
+        return
+    p, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.ipt_mlp_create.argtypes = [p, i32, i32, i32, i32, C.c_uint64, C.POINTER(p)]
+    lib.ipt_mlp_destroy.argtypes = [p]
+    lib.ipt_mlp_num_params.argtypes = [p]
+    lib.ipt_mlp_num_params.restype = i64
+    lib.ipt_mlp_get_params.argtypes = [p, p]
+    lib.ipt_mlp_set_params.argtypes = [p, p]
+    lib.ipt_mlp_forward.argtypes = [p, p, i32, p]
+    lib.ipt_mlp_loss_grad.argtypes = [p, p, p, i32, C.POINTER(C.c_float), p]
+    lib.ipt_mlp_train.argtypes = [p, p, p, i32, i32, C.c_float, C.POINTER(C.c_float)]
+    lib.ipt_mlp_predict_z0.argtypes = [p, p, i32, p, p, p, i64, i64, p, p, i64, i64]
+    lib.ipt_mlp_targets.argtypes = [p, p, i32, i64, i64, i64, i64, p, p, p, p, p]
+    for fn in ("ipt_mlp_create", "ipt_mlp_destroy", "ipt_mlp_get_params", "ipt_mlp_set_params", "ipt_mlp_forward",
+               "ipt_mlp_loss_grad", "ipt_mlp_train", "ipt_mlp_predict_z0", "ipt_mlp_targets"):
+        getattr(lib, fn).restype = C.c_int
+    _mlp_bound = True
+
+
+class MLP:
+    """ipt_mlp: x -> [Linear -> tanh] x depth -> Linear -> y with BF16 weights and FP32
+    accumulation, trained by the library's own kernels (ipt_mlp_train)."""
+
+    def __init__(self, in_dim, hidden, depth, out_dim, seed=0, handle=None):
+        lib = load_library()
+        _bind_mlp(lib)
+        self._lib = lib
+        self._handle = _handle(handle)
+        self._m = C.c_void_p()
+        st = lib.ipt_mlp_create(self._handle.ptr, in_dim, hidden, depth, out_dim, seed, C.byref(self._m))
+        if st != IPT_OK:
+            raise IPTError(st, "ipt_mlp_create: " + self._handle.last_error())
+        self.in_dim, self.hidden, self.depth, self.out_dim = in_dim, hidden, depth, out_dim
+
+    def _chk(self, st, what):
+        if st != IPT_OK:
+            raise IPTError(st, what + ": " + self._handle.last_error())
+
+    @property
+    def num_params(self):
+        return int(self._lib.ipt_mlp_num_params(self._m))
+
+    def get_params(self):
+        import torch
+        out = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
+        self._chk(self._lib.ipt_mlp_get_params(self._m, _ptr(out)), "ipt_mlp_get_params")
+        return out
+
+    def set_params(self, params):
+        _check(params, __import__("torch").float32, "params")
+        self._chk(self._lib.ipt_mlp_set_params(self._m, _ptr(params.contiguous())), "ipt_mlp_set_params")
+
+    def forward(self, x):
+        import torch
+        x = x.contiguous()
+        y = torch.empty((x.shape[0], self.out_dim), dtype=torch.float32, device=x.device)
+        self._chk(self._lib.ipt_mlp_forward(self._m, _ptr(x), x.shape[0], _ptr(y)), "ipt_mlp_forward")
+        return y
+
+    def loss_grad(self, x, targets):
+        import torch
+        g = torch.empty(self.num_params, dtype=torch.float32, device=x.device)
+        loss = C.c_float()
+        self._chk(self._lib.ipt_mlp_loss_grad(self._m, _ptr(x.contiguous()), _ptr(targets.contiguous()), x.shape[0],
+                                              C.byref(loss), _ptr(g)), "ipt_mlp_loss_grad")
+        return float(loss.value), g
+
+    def train(self, x, targets, steps, lr=1e-3):
+        loss = C.c_float()
+        self._chk(self._lib.ipt_mlp_train(self._m, _ptr(x.contiguous()), _ptr(targets.contiguous()), x.shape[0],
+                                          int(steps), float(lr), C.byref(loss)), "ipt_mlp_train")
+        return float(loss.value)
+
+    def predict_z0(self, x, mu, sigma, scale, n, k, idx):
+        """Warm starts Z0 [batch, n, k] (FP64) for the inputs x [batch, in_dim]."""
+        import torch
+        b = x.shape[0]
+        z0 = torch.empty((b, n, k), dtype=torch.float64, device=x.device)
+        self._chk(self._lib.ipt_mlp_predict_z0(self._m, _ptr(x.contiguous()), b, _ptr(mu.contiguous()),
+                                               _ptr(sigma.contiguous()), _ptr(scale.contiguous()), n, k,
+                                               _ptr(idx.contiguous()), _ptr(z0), k, n * k), "ipt_mlp_predict_z0")
+        return z0
+
+    def close(self):
+        if self._m:
+            self._lib.ipt_mlp_destroy(self._m)
+            self._m = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ipt_mlp_targets(z, idx, scale, handle=None):
+    """Standardised targets (ipt_mlp_targets) from solutions z [batch, n, k] (FP64):
+    returns (targets [batch, n k], mu [n k], sigma [n k]) as FP32 GPU tensors."""
+    import torch
+    lib = load_library()
+    _bind_mlp(lib)
+    h = _handle(handle)
+    z = z.contiguous()
+    b, n, k = z.shape
+    tg = torch.empty((b, n * k), dtype=torch.float32, device=z.device)
+    mu = torch.empty(n * k, dtype=torch.float32, device=z.device)
+    sd = torch.empty(n * k, dtype=torch.float32, device=z.device)
+    st = lib.ipt_mlp_targets(h.ptr, _ptr(z), b, n, k, k, n * k, _ptr(idx.contiguous()), _ptr(scale.contiguous()),
+                             _ptr(tg), _ptr(mu), _ptr(sd))
+    if st != IPT_OK:
+        raise IPTError(st, "ipt_mlp_targets: " + h.last_error())
+    return tg, mu, sd

@@ -1,0 +1,93 @@
+"""GPU tests of the learned warm start: HIP gradients against the FP64 reference of
+the same network, training, and warm-started solves that keep the oracle's answers."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import dev, say, t
+from oracle import mlp as ref_mlp
+from parity import angles, check
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ipt():
+    from paper_2012_14702_amd import ipt as mod
+    mod.load_library()
+    dev()
+    return mod
+
+
+def test_gradients_match_fp64_reference(ipt):
+    """ipt_mlp_loss_grad against the FP64 chain rule on the same (BF16-rounded)
+    weights: BF16 rounding of the GEMM inputs bounds the agreement to about 1e-2
+    relative per layer."""
+    import torch
+    say("mlp gradient check")
+    dims = (2, 64, 2, 300)
+    net = ipt.MLP(*dims, seed=3)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((37, 2)).astype(np.float32)
+    tg = rng.standard_normal((37, 300)).astype(np.float32)
+    loss, g = net.loss_grad(t(x), t(tg))
+    p = net.get_params().cpu().numpy().astype(np.float64)
+    rloss, rg = ref_mlp.loss_grad(p, x, tg, dims, round_bf16=True)
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss - rloss) <= 1e-2 * rloss
+    off = 0
+    for li, lo in ref_mlp.layer_sizes(*dims):
+        for size in (li * lo, lo):
+            a, b = g[off:off + size], rg[off:off + size]
+            off += size
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            assert rel <= 3e-2, rel
+            assert np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300) >= 0.999
+    # forward matches too
+    y = net.forward(t(x)).cpu().numpy()
+    ry = ref_mlp.forward(p, x, dims, round_bf16=True)[-1]
+    assert np.max(np.abs(y - ry)) <= 2e-2 * np.max(np.abs(ry))
+
+
+def test_training_reduces_loss(ipt):
+    import torch
+    say("mlp training")
+    dims = (2, 64, 2, 50)
+    net = ipt.MLP(*dims, seed=0)
+    e = np.linspace(0, 1, 64)
+    x = np.stack([e, e * e], 1).astype(np.float32)
+    tg = np.sin(3 * e[:, None] + np.arange(50)[None, :] * 0.1).astype(np.float32)
+    l0, _ = net.loss_grad(t(x), t(tg))
+    l1 = net.train(t(x), t(tg), 400, 3e-3)
+    assert l1 < 0.05 * l0
+
+
+def test_warm_start_keeps_answers_and_saves_sweeps(ipt):
+    """Family diag(1..256) + eps R, k = 16 lowest: a network trained on 96 solutions
+    warm-starts 12 new eps; every column matches the oracle and the cold solve, and the
+    mean sweep count drops."""
+    import torch
+    from paper_2012_14702_amd import warmstart
+    say("mlp warm start n=256")
+    n, k = 256, 16
+    th, base = W.family_base(n, 0)
+    thd, based = t(th), t(base)
+    idx = t(W.lowest_indices(th, k))
+    eps_tr = W.family_eps(96, 0.0, 0.08, seed=1)
+    eps_te = W.family_eps(12, 0.0, 0.08, seed=2)
+    ztr, _, st_tr, _, _ = warmstart.solve_family(thd, based, eps_tr, idx, tol=1e-12)
+    assert int((st_tr != 0).sum()) == 0
+    ws = warmstart.WarmStarter(n, k, hidden=128, depth=2, seed=0)
+    loss, _ = ws.fit(ztr, eps_tr, idx, steps=600, lr=2e-3)
+    assert loss < 0.05
+    z0 = ws.predict(eps_te, idx)
+    zc, lc, sc, swc, _ = warmstart.solve_family(thd, based, eps_te, idx, tol=1e-10)
+    zw, lw, sw, sww, _ = warmstart.solve_family(thd, based, eps_te, idx, z0=z0, tol=1e-10)
+    assert np.all(sc.cpu().numpy() == 0) and np.all(sw.cpu().numpy() == 0)
+    assert sww.mean() < swc.mean()
+    for p, e in enumerate(eps_te):
+        de = e * base
+        ref = oracle.ipt_dense(th, de, idx=W.lowest_indices(th, k), tol=1e-10)
+        check(zw[p].cpu().numpy(), lw[p].cpu().numpy(), sw[p].cpu().numpy(), ref, oracle.norm1(th, de), 1e-10)
+        assert np.max(angles(zw[p].cpu().numpy(), zc[p].cpu().numpy())) <= 1e-8
