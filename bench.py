@@ -176,6 +176,69 @@ def bench_batched(ipt, handle, args):
                         "full spectra, tol 1e-10, max 64 sweeps" % B, "eigenpairs": int(ns.sum()), "modes": res}
 
 
+def bench_learned(ipt, handle, args):
+    """Learned warm start: M(eps) = diag(1..1024) + eps R, R = (R'+R'^T)/2, R' iid N(0,1/n)
+    seed 0, k = 32 lowest; the network is trained on 512 eps ~ U[0, 0.08] (seed 1) and
+    tested on 128 new eps (seed 2).  Cold start (Z0 = I, whose first sweep is the free
+    first-order start F(I)) vs MLP warm start (inference time included) vs linear
+    interpolation between the two neighbouring training solutions; FP64 sweeps,
+    tol 1e-10; every warm answer is compared with the cold one."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2012_14702_amd import warmstart
+    n, k = 1024, 32
+    th, base = workloads.family_base(n, 0)
+    dev = torch.device("cuda:0")
+    thd, based = torch.from_numpy(th).to(dev), torch.from_numpy(base).to(dev)
+    idx = torch.from_numpy(workloads.lowest_indices(th, k)).to(dev)
+    eps_tr = workloads.family_eps(512, 0.0, 0.08, seed=1)
+    eps_te = workloads.family_eps(128, 0.0, 0.08, seed=2)
+    ztr, _, _, _, t_train_solves = warmstart.solve_family(thd, based, eps_tr, idx, handle=handle, tol=1e-12)
+    ws = warmstart.WarmStarter(n, k, hidden=256, depth=2, seed=0, handle=handle)
+    loss, t_fit = ws.fit(ztr, eps_tr, idx, steps=args.train_steps, lr=1e-3)
+    log("learned: trained %d steps in %.1f s, loss %.3g" % (args.train_steps, t_fit, loss))
+    # cold
+    zc, lc, sc, swc, t_cold = warmstart.solve_family(thd, based, eps_te, idx, handle=handle, tol=1e-10)
+    # learned: inference for all 128 eps, then the warm-started solves
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    z0 = ws.predict(eps_te, idx)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    zw, lw, sw, sww, t_warm = warmstart.solve_family(thd, based, eps_te, idx, z0=z0, handle=handle, tol=1e-10)
+    # control: linear interpolation between neighbouring training solutions
+    order = np.argsort(eps_tr)
+    es = eps_tr[order]
+    zs = ztr[torch.from_numpy(order).to(dev)]
+    zi = torch.empty_like(z0)
+    for p, e in enumerate(eps_te):
+        q = int(np.clip(np.searchsorted(es, e), 1, len(es) - 1))
+        w = (e - es[q - 1]) / (es[q] - es[q - 1])
+        zi[p] = (1 - w) * zs[q - 1] + w * zs[q]
+    _, _, si, swi, t_interp = warmstart.solve_family(thd, based, eps_te, idx, z0=zi, handle=handle, tol=1e-10)
+    conv_c = int((sc == 0).sum())
+    conv_w = int((sw == 0).sum())
+    za, zb = zw.cpu().numpy(), zc.cpu().numpy()
+    an = za / np.linalg.norm(za, axis=1, keepdims=True)
+    bn = zb / np.linalg.norm(zb, axis=1, keepdims=True)
+    max_angle = float(np.max(2 * np.arcsin(np.minimum(1.0, np.linalg.norm(an - bn, axis=1) / 2))))
+    max_dlam = float((lw - lc).abs().max())
+    log("learned: sweeps cold %.2f warm %.2f interp %.2f" % (swc.mean(), sww.mean(), swi.mean()))
+    return {"workload": "family diag(1..1024)+eps*R, k=32 lowest, train 512 eps~U[0,0.08], test 128 new eps, "
+                        "FP64 sweeps, tol 1e-10",
+            "network": "2 -> 256 -> 256 -> 32768 tanh MLP, BF16 weights / FP32 accumulation, Adam, %d steps"
+                       % args.train_steps,
+            "train_loss": loss, "train_seconds": round(t_fit, 3), "train_solves_seconds": round(t_train_solves, 3),
+            "mean_sweeps": {"cold": float(swc.mean()), "mlp": float(sww.mean()), "interp_control": float(swi.mean())},
+            "eigenpairs_per_s": {"cold": round(conv_c / t_cold, 1),
+                                 "mlp_incl_inference": round(conv_w / (t_warm + t_inf), 1),
+                                 "interp_control": round(int((si == 0).sum()) / t_interp, 1)},
+            "mlp_inference_ms_for_128": round(t_inf * 1e3, 3),
+            "converged": {"cold": conv_c, "mlp": conv_w, "of": 128 * k},
+            "warm_vs_cold": {"max_angle": max_angle, "max_abs_dlambda": max_dlam}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,8 +250,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "ladder", "fp64"], default="all",
                     help="restrict the dense workload to one mode (for profiler runs)")
-    ap.add_argument("--extra", default="sparse,batched",
-                    help="comma list of secondary workloads to time: sparse, batched ('' for none)")
+    ap.add_argument("--extra", default="sparse,batched,learned",
+                    help="comma list of secondary workloads to time: sparse, batched, learned ('' for none)")
+    ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the warm-start network")
     ap.add_argument("--batch", type=int, default=4096, help="problems in the batched workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -291,6 +355,8 @@ def main():
         out["sparse"] = bench_sparse(ipt, handle, args)
     if "batched" in extras:
         out["batched"] = bench_batched(ipt, handle, args)
+    if "learned" in extras:
+        out["learned"] = bench_learned(ipt, handle, args)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
         th, de = host[args.eps]
