@@ -161,20 +161,37 @@ def bench_batched(ipt, handle, args):
     thd = torch.from_numpy(th).to(dev)
     ded = torch.from_numpy(de).to(dev)
     del de
+    t0 = time.perf_counter()
+    tiles = ipt.ipt_batched_tune(ns, thd, ded, th_off, de_off, handle=handle)
+    t_tune = time.perf_counter() - t0
+    buckets = sorted(set(int(x) for x in (ns - 1) // 64))
+    log("batched tile table (tuned in %.2f s): %s" % (t_tune, {64 * (q + 1): tiles[q] for q in buckets}))
+    z_out = torch.empty_like(ded)
+    lam_out = torch.empty_like(thd)
+    st_out = torch.empty(thd.shape[0], dtype=torch.int32, device=dev)
     res = {}
-    for name, prec in (("ladder", ipt.PREC_LADDER), ("fp64", ipt.PREC_FP64)):
-        o = ipt.default_opts(tol=1e-10, precision=prec, max_iter=64)
-        run = lambda: ipt.ipt_solve_batched(ns, thd, ded, th_off, de_off, opts=o, handle=handle)
+    modes = (("ladder", ipt.PREC_LADDER, 0), ("ladder_no_graph", ipt.PREC_LADDER, ipt.FLAG_NO_GRAPH),
+             ("fp64", ipt.PREC_FP64, 0))
+    for name, prec, flags in modes:
+        if args.batched_modes and name not in args.batched_modes.split(","):
+            continue
+        o = ipt.default_opts(tol=1e-10, precision=prec, max_iter=64, flags=flags)
+        run = lambda: ipt.ipt_solve_batched(ns, thd, ded, th_off, de_off, opts=o, handle=handle, z_out=z_out,
+                                            lam_out=lam_out, status_out=st_out)
         _time(run, 1)
         sec, r = _time(run, 3)
         inf = r.info
         res[name] = {"eigenpairs_per_s": round(int(inf["converged"]) / sec, 1), "ms_per_solve": round(sec * 1e3, 3),
+                     "device_ms": round(inf["time_ms"], 3),
                      "converged": inf["converged"], "not_converged": inf["not_converged"],
                      "diverged": inf["diverged"], "sweeps": inf["sweeps"],
+                     "sweep_equivalents": round(inf["matvecs"] / float(ns.sum()), 3),
                      "converged_fraction": round(inf["converged"] / float(ns.sum()), 5)}
-        log("batched %s: %.2f ms/solve, %d/%d converged, %d sweeps" % (name, sec * 1e3, inf["converged"],
-                                                                     int(ns.sum()), inf["sweeps"]))
+        log("batched %s: %.2f ms/solve, %d/%d converged, %d sweeps, %.2f sweep-equivalents" % (
+            name, sec * 1e3, inf["converged"], int(ns.sum()), inf["sweeps"], inf["matvecs"] / float(ns.sum())))
         del r
+    res["tiles"] = {"bucket_upper_n": [64 * (q + 1) for q in buckets], "tile": [tiles[q] for q in buckets],
+                    "tune_s": round(t_tune, 3)}
     return {"workload": "batched %d problems n~U{32..512}, theta=sort(U(0,n)), Delta=0.02*sym N(0,1/n), "
                         "full spectra, tol 1e-10, max 64 sweeps" % B, "eigenpairs": int(ns.sum()), "modes": res}
 
@@ -256,9 +273,11 @@ def main():
     ap.add_argument("--extra", default="sparse,batched,learned",
                     help="comma list of secondary workloads to time: sparse, batched, learned ('' for none)")
     ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the warm-start network")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense workload (profiling of the others)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to scale HBM counters) and exit")
     ap.add_argument("--batch", type=int, default=4096, help="problems in the batched workload")
+    ap.add_argument("--batched-modes", default="", help="comma list of batched modes to time (default: all)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -286,6 +305,14 @@ def main():
     torch.cuda.set_device(dev)
     n = args.n
     handle = ipt.Handle()
+    if args.no_dense:
+        extras = [e for e in args.extra.split(",") if e]
+        out = {}
+        for name, fn in (("sparse", bench_sparse), ("batched", bench_batched), ("learned", bench_learned)):
+            if name in extras:
+                out[name] = fn(ipt, handle, args)
+        print(json.dumps(out), flush=True)
+        return
 
     def prep(eps):
         th, de = workloads.dense_sym_gaussian(n, eps, 0)

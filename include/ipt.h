@@ -82,6 +82,9 @@ typedef struct ipt_opts {
 /* Bracket every product kernel launch with HIP events on the handle's stream and
  * report the device time per sweep precision in ipt_info.prec_ms. */
 #define IPT_FLAG_TIME_KERNELS 2
+/* Batched solves: launch every sweep from the host instead of replaying the captured
+ * hipGraph of a chunk of sweeps (the results are the same, bit for bit). */
+#define IPT_FLAG_NO_GRAPH 4
 #define IPT_HIST 128
 
 /* Host struct filled by a solve (may be NULL). */
@@ -163,20 +166,53 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
                          int32_t *col_status, ipt_info *info, const ipt_colinfo *ci);
 
 /*
- * Batched full-spectrum solve of `count` independent dense problems of uneven size.
+ * Batched full-spectrum solve of `count` independent dense problems of uneven size
+ * (Alg. 2 applied to each M_b = D_b + Delta_b; the columns of all problems are
+ * independent, so one sweep advances every active column of the batch).
  *   ns, theta_off, delta_off, z_off   HOST arrays [count]: size n_b (1 <= n_b <= 4096) and the
  *                                     element offsets of problem b in the pools
  *   theta_pool   FP64 device pool; theta of problem b at theta_pool + theta_off[b] ([n_b])
  *   delta_pool   FP64 device pool; row-major n_b x n_b Delta at delta_pool + delta_off[b]
- *   z_pool       FP64 device pool; row-major n_b x n_b output at z_pool + z_off[b]
+ *   z_pool       FP64 device pool; row-major n_b x n_b output at z_pool + z_off[b].  It is
+ *                also one of the two iterate buffers of the solve, so the problems'
+ *                regions must not overlap each other or the input pools
  *   lambda_pool, status_pool   outputs at + theta_off[b] ([n_b] each)
  * Every problem is solved for its full spectrum with the same options; info
- * aggregates over the whole batch.
+ * aggregates over the whole batch.  The first sweep is product-free and also yields
+ * |M_b|_1, by which each column's resid is normalised (IPT_FLAG_NO_NORM is ignored).
+ * The ladder runs FP32 split-form sweeps, then FP64 sweeps, chosen per column tile;
+ * opts.low_type is ignored.  Sweeps after the first are replayed as a captured
+ * hipGraph of opts.sync_every sweeps (4 when 0) unless IPT_FLAG_NO_GRAPH or
+ * IPT_FLAG_TIME_KERNELS is set.  Problems use the tile size of their size bucket
+ * (ipt_batched_tune / ipt_batched_set_tiles).
+ * Errors: IPT_EINVAL, IPT_EDEGENERATE (theta_j equal within a problem), IPT_ENOTCONV,
+ * IPT_EHIP, IPT_ENOMEM.
  */
 ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
                              const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
                              const double *delta_pool, const ipt_opts *opts, double *z_pool, double *lambda_pool,
                              int32_t *status_pool, ipt_info *info);
+
+/* Size buckets of the batched tile table: bucket q holds the problems with
+ * 64 q < n_b <= 64 (q + 1). */
+#define IPT_TILE_BUCKETS 64
+
+/*
+ * Autotune the batched tile table of handle h on a batch laid out as for
+ * ipt_solve_batched: for every size bucket present (up to 512 of its problems), time
+ * two FP32 and two FP64 sweeps with 32 x 32, 64 x 64 and 128 x 128 tiles and keep the
+ * fastest.  z_pool, lambda_pool and status_pool serve as scratch (their contents are
+ * undefined afterwards).  tiles_out [IPT_TILE_BUCKETS] (host, may be NULL) receives
+ * the table.  Buckets with no problem keep their previous entry.
+ */
+ipt_status ipt_batched_tune(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
+                            const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
+                            const double *delta_pool, double *z_pool, double *lambda_pool, int32_t *status_pool,
+                            int32_t *tiles_out);
+/* Read or replace the handle's tile table (host arrays of IPT_TILE_BUCKETS entries,
+ * each 32, 64 or 128), e.g. to reuse a table tuned earlier.  IPT_EINVAL otherwise. */
+ipt_status ipt_batched_get_tiles(ipt_handle h, int32_t *tiles);
+ipt_status ipt_batched_set_tiles(ipt_handle h, const int32_t *tiles);
 
 /*
  * Learned warm start: a small MLP x -> [Linear -> tanh] x depth -> Linear -> y, trained

@@ -21,7 +21,16 @@ struct ipt_context {
     Ctrl *host_ctrl = nullptr;  // pinned copy of the control block
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     std::vector<hipEvent_t> tev;  // kernel-timing events (IPT_FLAG_TIME_KERNELS), reused across solves
-    int batch_tile_split = 192;    // batched solves: problems with n <= this use 64 x 64 tiles
+    // batched solves: tile size per size bucket (bucket q holds 64q < n <= 64(q + 1))
+    int32_t batch_tile[IPT_TILE_BUCKETS];
+    hipStream_t cap_stream = nullptr;          // capture-only stream for the batched sweep graph
+    hipGraphExec_t bgraph = nullptr;           // instantiated chunk of batched sweeps
+    std::vector<unsigned char> bgraph_key;     // the launch arguments it was captured with
+    int32_t *poll_host = nullptr;              // pinned [2][2]: error/done words of two polls in flight
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    ipt_context() {
+        for (int q = 0; q < IPT_TILE_BUCKETS; ++q) batch_tile[q] = q < 3 ? 64 : 128;
+    }
     std::string last_error;
 };
 
@@ -100,6 +109,7 @@ ipt_status check_opts(ipt_handle h, const ipt_opts *in, ipt_opts &o) {
 
 DevOpts dev_opts(const ipt_opts &o) {
     DevOpts d;
+    memset(&d, 0, sizeof(d));  // padding too: batched graphs are keyed on the argument bytes
     d.tol = o.tol;
     d.tau_low = o.tau_low;
     d.tau_32 = o.tau_32;
@@ -215,6 +225,252 @@ ipt_status finish(ipt_handle h, Ctrl *dev, int64_t k, ipt_info *info, Timer *tim
     return IPT_ENOTCONV;
 }
 
+// ------------------------------------------------------------- batched
+ipt_status ensure_poll(ipt_handle h) {
+    if (h->poll_host) return IPT_OK;
+    IPT_HIP(h, hipEventCreateWithFlags(&h->poll_ev[0], hipEventDisableTiming));
+    IPT_HIP(h, hipEventCreateWithFlags(&h->poll_ev[1], hipEventDisableTiming));
+    IPT_HIP(h, hipHostMalloc((void **)&h->poll_host, 4 * sizeof(int32_t), hipHostMallocDefault));
+    return IPT_OK;
+}
+
+// Everything a captured chunk of batched sweeps depends on; the graph is reused
+// while these bytes are unchanged.
+struct BatchGraphKey {
+    BatchLaunch L;
+    BatchLists lists;
+    DevOpts dopt;
+    Ctrl *ctrl;
+    int64_t total_cols;
+    int32_t grid[3], has[3], chunk;
+};
+
+template <typename F>
+ipt_status ensure_batch_graph(ipt_handle h, const BatchGraphKey &key, F capture) {
+    const unsigned char *kb = (const unsigned char *)&key;
+    std::vector<unsigned char> want(kb, kb + sizeof(key));
+    if (h->bgraph && h->bgraph_key == want) return IPT_OK;
+    if (h->bgraph) {
+        IPT_HIP(h, hipGraphExecDestroy(h->bgraph));
+        h->bgraph = nullptr;
+    }
+    if (!h->cap_stream) IPT_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    IPT_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+    const hipError_t e1 = capture(h->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(h, IPT_EHIP, std::string("capture of the batched sweep graph failed: ") +
+                                     hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    }
+    const hipError_t e3 = hipGraphInstantiate(&h->bgraph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+        h->bgraph = nullptr;
+        return fail(h, IPT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    }
+    h->bgraph_key = want;
+    return IPT_OK;
+}
+
+// The batched solve; force_T != 0 gives every problem that tile size (autotuner).
+ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
+                       const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
+                       const double *delta_pool, const ipt_opts &o, double *z_pool, double *lambda_pool,
+                       int32_t *status_pool, ipt_info *info, int force_T) {
+    if (count < 1) return fail(h, IPT_EINVAL, "count must be >= 1");
+    if (!ns || !theta_off || !delta_off || !z_off || !theta_pool || !delta_pool || !z_pool || !lambda_pool ||
+        !status_pool)
+        return fail(h, IPT_EINVAL, "NULL argument");
+    DevOpts dopt = dev_opts(o);
+    dopt.low_type = IPT_LOW_NONE;  // batched ladder: FP32 split-form sweeps, then FP64
+    const bool ladder = dopt.ladder;
+    DeviceGuard guard(h->device);
+    hipStream_t s = h->stream;
+
+    // Host plan: problems laid out largest first (so the work lists the finalize
+    // appends run roughly largest first), tile size per size bucket.
+    std::vector<int32_t> order(count);
+    for (int32_t b = 0; b < count; ++b) {
+        if (ns[b] < 1 || ns[b] > 4096) return fail(h, IPT_EINVAL, "every problem size must be in [1, 4096]");
+        if (theta_off[b] < 0 || delta_off[b] < 0 || z_off[b] < 0) return fail(h, IPT_EINVAL, "negative offset");
+        order[b] = b;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return ns[x] > ns[y]; });
+    std::vector<BatchMeta> meta(count);
+    std::vector<int4> it_s1;
+    int64_t offz = 0, offc = 0, offp = 0, offq = 0, offf = 0, cap[3] = {0, 0, 0};
+    for (int32_t b : order) {
+        const int64_t n = ns[b];
+        const int T = force_T ? force_T : h->batch_tile[(n - 1) / 64];
+        const int64_t np = round_up(n, T), nt = np / T, ncb = (np + 63) / 64;
+        BatchMeta &m = meta[b];
+        m.n = (int32_t)n;
+        m.T = T;
+        m.np = (int32_t)np;
+        m.offd = delta_off[b];
+        m.offt = theta_off[b];
+        m.offo = z_off[b];
+        m.offz = offz;
+        m.offc = offc;
+        m.offp = offp;
+        m.offq = offq;
+        m.offf = offf;
+        offz += np * np;
+        offc += n;
+        offp += nt * n * NPART;
+        offq += nt * n;
+        offf += nt;
+        cap[T == 32 ? 0 : (T == 64 ? 1 : 2)] += nt * nt;
+        for (int tm = 0; tm < nt; ++tm)
+            for (int cb = 0; cb < ncb; ++cb) it_s1.push_back(make_int4(b, tm, cb, 0));
+    }
+    const int64_t total_cols = offc, total_tiles = offf, total_q = offq;
+    if (total_cols > INT32_MAX / 2 || cap[0] > INT32_MAX / 2 || cap[1] > INT32_MAX / 2 || cap[2] > INT32_MAX / 2)
+        return fail(h, IPT_EINVAL, "batch too large");
+
+    BatchLaunch L;
+    memset(&L, 0, sizeof(L));
+    BatchLists lists;
+    memset(&lists, 0, sizeof(lists));
+    BatchMeta *dmeta;
+    int4 *ds1;
+    double *maxres;
+    int32_t *cnt;
+    Ctrl *ctrl;
+    auto layout = [&](Carve &cv) {
+        dmeta = cv.take<BatchMeta>(count);
+        ds1 = cv.take<int4>(it_s1.size());
+        L.dpad = cv.take<double>(offz);
+        L.z0 = cv.take<double>(offz);
+        L.z1 = cv.take<double>(offz);
+        L.d32 = cv.take<float>(ladder ? offz : 1);
+        L.zlo0 = cv.take<float>(ladder ? offz : 1);
+        L.zlo1 = cv.take<float>(ladder ? offz : 1);
+        L.bpart = cv.take<uint64_t>((size_t)bfinalize_blocks(total_cols) * 8);
+        L.col.state = cv.take<int32_t>(total_cols);
+        L.col.sweeps = cv.take<int32_t>(total_cols);
+        L.col.grow = cv.take<int32_t>(total_cols);
+        L.col.par = cv.take<int32_t>(total_cols);
+        L.col.prob = cv.take<int32_t>(total_cols);
+        L.col.prev = cv.take<double>(total_cols);
+        L.col.step = cv.take<double>(total_cols);
+        L.col.lam = cv.take<double>(total_cols);
+        L.col.resid = cv.take<double>(total_cols);
+        L.col.d = cv.take<double>(total_cols);
+        L.col.norm_bits = cv.take<uint64_t>(count);
+        L.part = cv.take<double>(offp);
+        L.dpart = cv.take<double>(total_q);
+        L.normpart = cv.take<double>(total_q);
+        L.tflag = cv.take<uint32_t>(2 * total_tiles);
+        for (int c = 0; c < 3; ++c)
+            for (int p = 0; p < 2; ++p) lists.l[c][p] = cv.take<int4>(cap[c] + 1);
+        cnt = cv.take<int32_t>(9);
+        maxres = cv.take<double>(1);
+        ctrl = cv.take<Ctrl>(1);
+    };
+    Carve sizing;
+    layout(sizing);
+    if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
+    if (ipt_status st = ensure_poll(h)) return st;
+    Carve cv;
+    cv.base = (char *)h->ws;
+    layout(cv);
+    lists.counts = cnt;
+    lists.tickets = cnt + 6;
+    L.meta = dmeta;
+    L.theta = theta_pool;
+    L.delta = delta_pool;
+    L.total_tiles = total_tiles;
+    L.total_q = total_q;
+
+    // Upload the plan (ordered on the stream; the host vectors live until the
+    // synchronisation below).
+    IPT_HIP(h, hipMemcpyAsync(dmeta, meta.data(), sizeof(BatchMeta) * count, hipMemcpyHostToDevice, s));
+    IPT_HIP(h, hipMemcpyAsync(ds1, it_s1.data(), sizeof(int4) * it_s1.size(), hipMemcpyHostToDevice, s));
+    IPT_HIP(h, hipStreamSynchronize(s));
+
+    const int tsize[3] = {32, 64, 128};
+    BatchGraphKey key;
+    memset(&key, 0, sizeof(key));
+    key.L = L;
+    key.lists = lists;
+    key.dopt = dopt;
+    key.ctrl = ctrl;
+    key.total_cols = total_cols;
+    key.chunk = o.sync_every > 0 ? o.sync_every : 4;
+    for (int c = 0; c < 3; ++c) {
+        key.has[c] = cap[c] > 0;
+        key.grid[c] = cap[c] > 0 ? (int32_t)std::min<int64_t>(bgemm_grid(tsize[c]), cap[c]) : 0;
+    }
+    // One sweep after the first: the GEMM per tile class (largest tiles first), the
+    // finalize, the control kernel.
+    Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
+    auto sweep = [&](hipStream_t st, int32_t t_host) -> hipError_t {
+        hipError_t e = timer.mark(t_host, 0, st);
+        for (int c = 2; c >= 0 && e == hipSuccess; --c)
+            if (key.has[c]) e = launch_bgemm(st, ctrl, L, lists, tsize[c], key.grid[c]);
+        if (e == hipSuccess) e = timer.mark(t_host, 1, st);
+        if (e == hipSuccess) e = launch_bfinalize(st, ctrl, dopt, L, total_cols, lists);
+        if (e == hipSuccess) e = launch_bcontrol(st, ctrl, dopt, L, total_cols, lists);
+        return e;
+    };
+    const bool use_graph = !(o.flags & (IPT_FLAG_NO_GRAPH | IPT_FLAG_TIME_KERNELS));
+    if (use_graph) {
+        if (ipt_status st = ensure_batch_graph(h, key, [&](hipStream_t cs) -> hipError_t {
+                for (int q = 0; q < key.chunk; ++q)
+                    if (hipError_t e = sweep(cs, 0)) return e;
+                return hipSuccess;
+            }))
+            return st;
+    }
+
+    IPT_HIP(h, timer.ensure());
+    IPT_HIP(h, hipEventRecord(h->ev_start, s));
+    IPT_HIP(h, launch_ctrl_init(s, ctrl, PREC_EXACT_FIRST, total_cols));
+    IPT_HIP(h, launch_fill_f32(s, (float *)cnt, 9));
+    IPT_HIP(h, launch_fill_f32(s, (float *)maxres, 2));
+    IPT_HIP(h, launch_binit(s, ctrl, L, count, ladder ? PREC_F32 : PREC_F64));
+    // sweep 1: product-free
+    IPT_HIP(h, timer.mark(1, 0, s));
+    IPT_HIP(h, launch_bsweep1(s, ctrl, L, ds1, (int64_t)it_s1.size(), ladder ? 1 : 0));
+    IPT_HIP(h, timer.mark(1, 1, s));
+    IPT_HIP(h, launch_bfinalize(s, ctrl, dopt, L, total_cols, lists));
+    IPT_HIP(h, launch_bcontrol(s, ctrl, dopt, L, total_cols, lists));
+    // Later sweeps in chunks; the host reads the stop words of chunk i while chunk
+    // i + 1 runs (sweeps launched after the device stopped return at once).
+    int32_t launched = 1;
+    int pend = -1, slot = 0;
+    while (launched < o.max_iter) {
+        if (use_graph) {
+            IPT_HIP(h, hipGraphLaunch(h->bgraph, s));
+            launched += key.chunk;
+        } else {
+            const int32_t m = std::min<int32_t>(key.chunk, o.max_iter - launched);
+            for (int32_t q = 0; q < m; ++q) IPT_HIP(h, sweep(s, launched + q + 1));
+            launched += m;
+        }
+        IPT_HIP(h, hipMemcpyAsync(h->poll_host + 2 * slot, ctrl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        IPT_HIP(h, hipEventRecord(h->poll_ev[slot], s));
+        if (pend >= 0) {
+            IPT_HIP(h, hipEventSynchronize(h->poll_ev[pend]));
+            if (h->poll_host[2 * pend] || h->poll_host[2 * pend + 1]) break;
+        }
+        pend = slot;
+        slot ^= 1;
+    }
+    IPT_HIP(h, launch_bcopyout(s, ctrl, L, ds1, (int64_t)it_s1.size(), z_pool, lambda_pool, status_pool, maxres));
+    ipt_status st = finish(h, ctrl, total_cols, info, &timer);
+    if (info && (st == IPT_OK || st == IPT_ENOTCONV)) {
+        double mr = 0.0;
+        IPT_HIP(h, hipMemcpy(&mr, maxres, sizeof(double), hipMemcpyDeviceToHost));
+        info->max_resid = mr;
+        info->norm1 = 0.0;
+    }
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -264,6 +520,11 @@ ipt_status ipt_destroy(ipt_handle h) {
     (void)hipEventDestroy(h->ev_start);
     (void)hipEventDestroy(h->ev_stop);
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
+    if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->poll_host) (void)hipHostFree(h->poll_host);
+    for (hipEvent_t e : h->poll_ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     return IPT_OK;
 }
@@ -519,157 +780,92 @@ ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, con
                              int32_t *status_pool, ipt_info *info) {
     if (!h) return IPT_EINVAL;
     h->last_error.clear();
-    if (count < 1) return fail(h, IPT_EINVAL, "count must be >= 1");
-    if (!ns || !theta_off || !delta_off || !z_off || !theta_pool || !delta_pool || !z_pool || !lambda_pool ||
-        !status_pool)
-        return fail(h, IPT_EINVAL, "NULL argument");
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
-    DevOpts dopt = dev_opts(o);
-    dopt.low_type = IPT_LOW_NONE;  // batched ladder: FP32 split-form sweeps, then FP64
-    const bool ladder = dopt.ladder;
-    const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
-    DeviceGuard guard(h->device);
-    hipStream_t s = h->stream;
+    return batched_run(h, count, ns, theta_off, delta_off, z_off, theta_pool, delta_pool, o, z_pool, lambda_pool,
+                       status_pool, info, 0);
+}
 
-    // Host plan: per-problem layout, tile size per size bucket, work lists (largest
-    // problems first so the persistent GEMM ends with small items).
-    const int tile_split = h->batch_tile_split;
-    std::vector<BatchMeta> meta(count);
-    int64_t offz = 0, offc = 0, offp = 0, offf = 0, maxn = 0;
+ipt_status ipt_batched_tune(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
+                            const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
+                            const double *delta_pool, double *z_pool, double *lambda_pool, int32_t *status_pool,
+                            int32_t *tiles_out) {
+    if (!h) return IPT_EINVAL;
+    h->last_error.clear();
+    if (count < 1 || !ns || !theta_off || !delta_off || !z_off) return fail(h, IPT_EINVAL, "bad batch description");
+    // Per size bucket: time two FP32 and two FP64 GEMM sweeps of (up to 512 of) its
+    // problems with each tile size and keep the fastest sum.  tol = 0 keeps every
+    // column active, so each sweep multiplies whole problems.
+    std::vector<std::vector<int32_t>> members(IPT_TILE_BUCKETS);
     for (int32_t b = 0; b < count; ++b) {
-        const int64_t n = ns[b];
-        if (n < 1 || n > 4096) return fail(h, IPT_EINVAL, "every problem size must be in [1, 4096]");
-        if (theta_off[b] < 0 || delta_off[b] < 0 || z_off[b] < 0) return fail(h, IPT_EINVAL, "negative offset");
-        BatchMeta &m = meta[b];
-        m.n = (int32_t)n;
-        m.T = n <= tile_split ? 64 : 128;
-        m.offd = delta_off[b];
-        m.offt = theta_off[b];
-        m.offz = offz;
-        m.offc = offc;
-        m.offp = offp;
-        m.offf = offf;
-        const int64_t nt = (n + m.T - 1) / m.T;
-        offz += n * n;
-        offc += n;
-        offp += nt * n * NPART;
-        offf += nt;
-        if (n > maxn) maxn = n;
+        if (ns[b] < 1 || ns[b] > 4096) return fail(h, IPT_EINVAL, "every problem size must be in [1, 4096]");
+        std::vector<int32_t> &v = members[(ns[b] - 1) / 64];
+        if (v.size() < 512) v.push_back(b);
     }
-    std::vector<int32_t> order(count);
-    for (int32_t b = 0; b < count; ++b) order[b] = b;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return meta[x].n > meta[y].n; });
-    std::vector<int4> it64, it128, it_s1, it_dg;
-    for (int32_t b : order) {
-        const BatchMeta &m = meta[b];
-        const int nt = (m.n + m.T - 1) / m.T, ncb = (m.n + 63) / 64;
-        std::vector<int4> &dst = m.T == 64 ? it64 : it128;
-        for (int tn = 0; tn < nt; ++tn)
-            for (int tm = 0; tm < nt; ++tm) dst.push_back(make_int4(b, tm, tn, 0));
-        for (int tm = 0; tm < nt; ++tm)
-            for (int cb = 0; cb < ncb; ++cb) it_s1.push_back(make_int4(b, tm, cb, 0));
-        for (int cb = 0; cb < ncb; ++cb) it_dg.push_back(make_int4(b, 0, cb, 0));
-    }
-    const int64_t total_cols = offc, total_tiles = offf;
-    const int64_t n64 = (int64_t)it64.size(), n128 = (int64_t)it128.size();
-
-    auto layout = [&](Carve &cv, BatchMeta **dmeta, int4 **d64, int4 **d128, int4 **ds1, int4 **ddg, int64_t **dzoff,
-                      double **z0, double **z1, BatchCols &col, double **part, uint32_t **tflag, int32_t **tickets,
-                      double **maxres, Ctrl **ctrl) {
-        *dmeta = cv.take<BatchMeta>(count);
-        *d64 = cv.take<int4>(n64 + 1);
-        *d128 = cv.take<int4>(n128 + 1);
-        *ds1 = cv.take<int4>(it_s1.size());
-        *ddg = cv.take<int4>(it_dg.size());
-        *dzoff = cv.take<int64_t>(count);
-        *z0 = cv.take<double>(offz);
-        *z1 = cv.take<double>(offz);
-        col.state = cv.take<int32_t>(total_cols);
-        col.sweeps = cv.take<int32_t>(total_cols);
-        col.grow = cv.take<int32_t>(total_cols);
-        col.par = cv.take<int32_t>(total_cols);
-        col.prob = cv.take<int32_t>(total_cols);
-        col.prev = cv.take<double>(total_cols);
-        col.step = cv.take<double>(total_cols);
-        col.lam = cv.take<double>(total_cols);
-        col.resid = cv.take<double>(total_cols);
-        col.d = cv.take<double>(total_cols);
-        col.norm_bits = cv.take<uint64_t>(count);
-        *part = cv.take<double>(offp);
-        *tflag = cv.take<uint32_t>(2 * total_tiles);
-        *tickets = cv.take<int32_t>(2);
-        *maxres = cv.take<double>(1);
-        *ctrl = cv.take<Ctrl>(1);
-    };
-    BatchMeta *dmeta;
-    int4 *d64, *d128, *ds1, *ddg;
-    int64_t *dzoff;
-    double *z0, *z1, *part, *maxres;
-    BatchCols col;
-    uint32_t *tflag;
-    int32_t *tickets;
-    Ctrl *ctrl;
-    Carve sizing;
-    layout(sizing, &dmeta, &d64, &d128, &ds1, &ddg, &dzoff, &z0, &z1, col, &part, &tflag, &tickets, &maxres, &ctrl);
-    if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
-    Carve cv;
-    cv.base = (char *)h->ws;
-    layout(cv, &dmeta, &d64, &d128, &ds1, &ddg, &dzoff, &z0, &z1, col, &part, &tflag, &tickets, &maxres, &ctrl);
-
-    // Upload the plan (host-to-device copies ordered on the stream; the host
-    // vectors stay alive until the stream is synchronised below).
-    IPT_HIP(h, hipMemcpyAsync(dmeta, meta.data(), sizeof(BatchMeta) * count, hipMemcpyHostToDevice, s));
-    if (n64) IPT_HIP(h, hipMemcpyAsync(d64, it64.data(), sizeof(int4) * n64, hipMemcpyHostToDevice, s));
-    if (n128) IPT_HIP(h, hipMemcpyAsync(d128, it128.data(), sizeof(int4) * n128, hipMemcpyHostToDevice, s));
-    IPT_HIP(h, hipMemcpyAsync(ds1, it_s1.data(), sizeof(int4) * it_s1.size(), hipMemcpyHostToDevice, s));
-    IPT_HIP(h, hipMemcpyAsync(ddg, it_dg.data(), sizeof(int4) * it_dg.size(), hipMemcpyHostToDevice, s));
-    IPT_HIP(h, hipMemcpyAsync(dzoff, z_off, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
-    IPT_HIP(h, hipStreamSynchronize(s));
-
-    const BatchLaunch L = make_batch_launch(dmeta, theta_pool, delta_pool, z0, z1, col, part, tflag, total_tiles);
-    Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
-    IPT_HIP(h, timer.ensure());
-    IPT_HIP(h, hipEventRecord(h->ev_start, s));
-    IPT_HIP(h, launch_ctrl_init(s, ctrl, PREC_EXACT_FIRST, total_cols));
-    IPT_HIP(h, launch_fill_f32(s, (float *)tickets, 2));
-    IPT_HIP(h, launch_fill_f32(s, (float *)maxres, 2));
-    IPT_HIP(h, launch_binit(s, ctrl, L, count, ladder ? PREC_F32 : PREC_F64));
-    if (norm) IPT_HIP(h, launch_bnorm(s, ctrl, L, count));
-    const int grid64 = bgemm_grid(64), grid128 = bgemm_grid(128);
-
-    PollPlan plan = poll_plan(o, true);
-    if (o.sync_every <= 0) plan = PollPlan{5, 2};
-    for (int32_t t = 1; t <= o.max_iter; ++t) {
-        const int32_t in_buf = (t - 1) & 1;
-        const int32_t in_par = t == 1 ? PAR_UNIT : in_buf;
-        const int32_t out_par = t & 1;
-        IPT_HIP(h, timer.mark(t, 0, s));
-        if (t == 1) {
-            IPT_HIP(h, launch_bsweep1(s, ctrl, L, ds1, (int64_t)it_s1.size()));
-        } else {
-            IPT_HIP(h, launch_bdiag(s, ctrl, L, ddg, (int64_t)it_dg.size(), in_buf));
-            IPT_HIP(h, launch_bgemm(s, ctrl, L, 128, d128, n128, t, in_buf, tickets + 1, grid128));
-            IPT_HIP(h, launch_bgemm(s, ctrl, L, 64, d64, n64, t, in_buf, tickets, grid64));
+    int32_t tiles[IPT_TILE_BUCKETS];
+    memcpy(tiles, h->batch_tile, sizeof(tiles));
+    for (int q = 0; q < IPT_TILE_BUCKETS; ++q) {
+        const std::vector<int32_t> &v = members[q];
+        if (v.empty()) continue;
+        std::vector<int32_t> sn(v.size());
+        std::vector<int64_t> sto(v.size()), sdo(v.size()), szo(v.size());
+        for (size_t u = 0; u < v.size(); ++u) {
+            sn[u] = ns[v[u]];
+            sto[u] = theta_off[v[u]];
+            sdo[u] = delta_off[v[u]];
+            szo[u] = z_off[v[u]];
         }
-        IPT_HIP(h, timer.mark(t, 1, s));
-        IPT_HIP(h, launch_bfinalize(s, ctrl, dopt, L, total_cols, t, in_par, out_par));
-        IPT_HIP(h, launch_bcontrol(s, ctrl, dopt, t, tickets));
-        if (plan.at(t, o.max_iter)) {
-            int32_t err, done;
-            if (ipt_status st = poll_ctrl(h, ctrl, err, done)) return st;
-            if (err || done) break;
+        float best = INFINITY;
+        int best_t = tiles[q];
+        for (int T : {32, 64, 128}) {
+            if (q == 0 && T == 128) continue;  // n <= 64: a 128 tile is mostly padding
+            float total = 0.f;
+            for (int prec : {IPT_PREC_LADDER, IPT_PREC_FP64}) {
+                ipt_opts o;
+                ipt_opts_default(&o);
+                o.tol = 0.0;
+                o.max_iter = 3;
+                o.precision = prec;
+                o.tau_32 = 0.0;
+                o.sync_every = 3;
+                o.flags = IPT_FLAG_TIME_KERNELS | IPT_FLAG_NO_GRAPH;
+                float run_best = INFINITY;
+                for (int rep = 0; rep < 2; ++rep) {
+                    ipt_info inf;
+                    ipt_status st = batched_run(h, (int32_t)v.size(), sn.data(), sto.data(), sdo.data(), szo.data(),
+                                                theta_pool, delta_pool, o, z_pool, lambda_pool, status_pool, &inf, T);
+                    if (st != IPT_OK && st != IPT_ENOTCONV) return st;
+                    const float ms = inf.prec_ms[IPT_SWEEP_FP32] + inf.prec_ms[IPT_SWEEP_FP64];
+                    run_best = ms < run_best ? ms : run_best;
+                }
+                total += run_best;
+            }
+            if (total < best) {
+                best = total;
+                best_t = T;
+            }
         }
+        tiles[q] = best_t;
     }
-    IPT_HIP(h, launch_bcopyout(s, ctrl, L, dzoff, z_pool, lambda_pool, status_pool, total_cols, maxres));
-    ipt_status st = finish(h, ctrl, total_cols, info, &timer);
-    if (info && (st == IPT_OK || st == IPT_ENOTCONV)) {
-        double mr = 0.0;
-        IPT_HIP(h, hipMemcpy(&mr, maxres, sizeof(double), hipMemcpyDeviceToHost));
-        info->max_resid = mr;
-        info->norm1 = 0.0;
-    }
-    return st;
+    h->last_error.clear();
+    memcpy(h->batch_tile, tiles, sizeof(tiles));
+    if (tiles_out) memcpy(tiles_out, tiles, sizeof(tiles));
+    return IPT_OK;
+}
+
+ipt_status ipt_batched_get_tiles(ipt_handle h, int32_t *tiles) {
+    if (!h || !tiles) return IPT_EINVAL;
+    memcpy(tiles, h->batch_tile, sizeof(h->batch_tile));
+    return IPT_OK;
+}
+
+ipt_status ipt_batched_set_tiles(ipt_handle h, const int32_t *tiles) {
+    if (!h || !tiles) return IPT_EINVAL;
+    for (int q = 0; q < IPT_TILE_BUCKETS; ++q)
+        if (tiles[q] != 32 && tiles[q] != 64 && tiles[q] != 128)
+            return fail(h, IPT_EINVAL, "tile sizes must be 32, 64 or 128");
+    memcpy(h->batch_tile, tiles, sizeof(h->batch_tile));
+    return IPT_OK;
 }
 
 }  // extern "C"

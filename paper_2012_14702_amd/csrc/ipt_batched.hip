@@ -1,17 +1,31 @@
 // Batched full-spectrum IPT: many independent dense problems M_b = D_b + Delta_b of
 // uneven size n_b, all advanced by the same few launches per sweep.
 //
-// Every matrix is cut into T x T tiles (T = 64 or 128, chosen per size bucket); the
-// work list holds one item (b, row tile, column tile) per tile, largest matrices
-// first.  The sweep GEMM is persistent: a fixed grid of workgroups takes items from
-// an atomic ticket until the list is drained, and skips column tiles with no active
-// column.  Each column tile carries its own precision for the sweep (a stamped
-// word: sweep << 2 | precision), chosen by the finalize kernel from the columns'
-// steps: FP32 split-form sweeps (only Z - E in FP32, Delta E exact in FP64) until a
-// column's step reaches tau_32 or stalls, then FP64 sweeps, which alone may certify.
+// Every problem is cut into T x T tiles, T in {32, 64, 128} chosen per size bucket
+// (by the autotuner in ipt_api.hip), and padded to np_b = round_up(n_b, T) so that
+// the GEMM reads aligned 16-byte chunks with no bounds checks.  A sweep is one
+// persistent GEMM launch per tile size over a compacted work list of (problem, row
+// tile, column tile) items -- only the column tiles that still hold an active column
+// -- then a finalize over all columns and a control kernel.  The finalize of sweep t
+// builds the lists of sweep t + 1.  The sweep number lives in the device control
+// block, so every sweep's launches are the same and a chunk of sweeps is captured
+// once in a hipGraph and replayed.
 //
-// Layouts (all row-major, leading dimension n_b): Delta_b in the caller's pool, the
-// two iterate buffers in a packed pool, columns of all problems concatenated.
+// Each column tile carries its own precision for the next sweep (a stamped word:
+// sweep << 2 | precision), chosen by the finalize kernel from the columns' steps:
+// FP32 split-form sweeps (Delta_32 (Z - E)_32 on the matrix cores, Delta E added
+// exactly in FP64) until a column's step reaches tau_32 or stalls, then FP64 sweeps,
+// which alone may certify.  FP32 tiles also write the FP32 shadow of W - E that the
+// next FP32 sweep multiplies.
+//
+// d_c = (Delta Z)_{cc} of sweep t + 1 is summed by the epilogues of sweep t from the W
+// they produce (per row tile, the sum over its rows l of Delta_cl W_lc) and reduced
+// in row-tile order by the finalize, so no separate pass over Delta and Z is needed.
+//
+// Workspace layouts (row-major, leading dimension np_b, problems packed largest
+// first): padded Delta (FP64, and its FP32 shadow for the ladder), two FP64 iterate
+// buffers and their two FP32 (Z - E) shadows.  The caller's Delta is read only by
+// the first sweep, which also builds the padded copies.
 #include <math.h>
 
 #include <type_traits>
@@ -33,8 +47,37 @@ __device__ inline double bitsd(uint64_t b) { return __longlong_as_double((long l
 
 typedef BatchLaunch BArgs;
 
-__device__ inline uint32_t flag_word(uint32_t *tflag, int64_t total, int32_t parity, int64_t tile) {
-    return tflag[(int64_t)parity * total + tile];
+__device__ inline int32_t cur_sweep(const Ctrl *ctrl) { return ctrl->sweeps + 1; }
+
+template <int T>
+constexpr int tile_class() {
+    return T == 32 ? 0 : (T == 64 ? 1 : 2);
+}
+__device__ inline int tile_class_of(int T) { return T == 32 ? 0 : (T == 64 ? 1 : 2); }
+
+// Segmented inclusive max over a wave.  Lanes with equal keys must be contiguous;
+// the segment maximum ends up in the segment's last lane, which gets leader = true.
+__device__ inline uint64_t seg_max(int64_t key, uint64_t v, bool &leader) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t ov = (uint64_t)__shfl_up((unsigned long long)v, off);
+        const int64_t ok = (int64_t)__shfl_up((long long)key, off);
+        if (lane >= off && ok == key) v = ov > v ? ov : v;
+    }
+    const int64_t nk = (int64_t)__shfl_down((long long)key, 1);
+    leader = (lane == 63) || (nk != key);
+    return v;
+}
+
+__device__ inline int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(v, off);
+        if (lane >= off) v += o;
+    }
+    return v;
 }
 
 // ----------------------------------------------------------------- setup
@@ -64,161 +107,179 @@ __global__ __launch_bounds__(256) void k_binit(Ctrl *ctrl, BArgs a, int32_t star
         a.col.step[c] = INFINITY;
         a.col.lam[c] = 0.0;
         a.col.resid[c] = 0.0;
+        a.col.d[c] = 0.0;
     }
     if (bad_nan) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
     if (degen) atomicMax(&ctrl->error, (int32_t)IPT_EDEGENERATE);
-    const int ntn = (m.n + m.T - 1) / m.T;
+    const int ntn = m.np / m.T;
     for (int q = threadIdx.x; q < ntn; q += blockDim.x) {
-        a.tflag[m.offf + q] = (0u << 2) | (uint32_t)start_prec;                   // sweep 1 (stamp 0)
+        a.tflag[m.offf + q] = (0u << 2) | (uint32_t)start_prec;
         a.tflag[a.total_tiles + m.offf + q] = (0u << 2) | (uint32_t)start_prec;
     }
     if (threadIdx.x == 0) a.col.norm_bits[b] = 0;
 }
 
-// |M_b|_1 per problem (max column sum of |D_b + Delta_b|), block per problem.
-__global__ __launch_bounds__(256) void k_bnorm(const Ctrl *ctrl, BArgs a) {
-    if (ctrl->error) return;
-    const int b = blockIdx.x;
-    const BatchMeta m = a.meta[b];
-    const double *db = a.delta + m.offd;
-    const double *tb = a.theta + m.offt;
-    double best = 0.0;
-    for (int c = threadIdx.x; c < m.n; c += blockDim.x) {
-        double s = 0.0;
-        for (int j = 0; j < m.n; ++j) {
-            const double v = db[(int64_t)j * m.n + c] + (j == c ? tb[c] : 0.0);
-            s += fabs(v);
-        }
-        best = fmax(best, s);
-    }
-    atomicMax((unsigned long long *)&a.col.norm_bits[b], (unsigned long long)dbits(best));
-}
-
-// Product-free first sweep of a cold start: W = I - G o Delta (eq. dyn at Z = I),
-// d_c = Delta_cc.  Item = (problem, row tile, 64 columns); same partial layout as the
-// GEMM epilogue.
-__global__ __launch_bounds__(256) void k_bsweep1(const Ctrl *ctrl, BArgs a, const int4 *items, int64_t nitems) {
+// Product-free first sweep of a cold start, W = I - G o Delta (eq. 2 at Z = I), with
+// d_c = Delta_cc for this sweep.  It also writes the padded copies of Delta (FP64 and,
+// for the ladder, FP32), zeroes the padding of both iterate buffers and shadows, and
+// stores the row-tile partials of the next sweep's d (sum_l Delta_cl W_lc, the
+// transposed Delta block staged through LDS) and of the column sums of |M_b| (for
+// |M_b|_1).  Item = (problem, row tile, 64 columns of the padded width).
+__global__ __launch_bounds__(256) void k_bsweep1(const Ctrl *ctrl, BArgs a, const int4 *items, int64_t nitems,
+                                                 int32_t ladder) {
     if (ctrl->error || ctrl->done) return;
-    __shared__ double sh[4][NPART][64];
+    __shared__ double tt[32][64 + 1];            // Delta[c0 + ci][j0 + jj] at tt[jj][ci]
+    __shared__ double sh[4][NPART + 2][64];
+    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
         const BatchMeta m = a.meta[w.x];
-        const int tm = w.y, cb = w.z;
-        const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
-        const int c = cb * 64 + cx;
-        const bool colok = c < m.n;
+        const int n = m.n, np = m.np, tm = w.y;
+        const int c0 = w.z * 64, c = c0 + cx;
+        const bool colok = c < n;
         const double *db = a.delta + m.offd;
         const double *tb = a.theta + m.offt;
-        double *zout = a.z1 + m.offz;
-        double v[NPART] = {0.0, 0.0, 0.0, 0.0};
         const double ti = colok ? tb[c] : 0.0;
-        for (int r = ry; r < m.T; r += 4) {
-            const int j = tm * m.T + r;
-            if (!colok || j >= m.n) continue;
-            double wv;
-            if (j == c) {
-                wv = 1.0;
-                v[1] += 1.0;
-            } else {
-                const double gap = tb[j] - ti;
-                wv = -db[(int64_t)j * m.n + c] / gap;
-                v[0] += wv * wv;
-                v[2] += (gap * wv) * (gap * wv);
-                v[3] += wv * wv;
-            }
-            zout[(int64_t)j * m.n + c] = wv;
-        }
-        if (colok && tm == c / m.T && ry == 0) a.col.d[m.offc + c] = db[(int64_t)c * m.n + c];
+        // partials: step^2, |z|^2, gap^2 step^2, |w - e|^2 (as the GEMM epilogue), next d,
+        // |M| column sum
+        double v[NPART + 2] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int j0 = tm * m.T; j0 < tm * m.T + m.T; j0 += 32) {
+            {   // transposed block: thread loads 8 consecutive j of row c0 + t / 4
+                const int ci = threadIdx.x >> 2, jb = (threadIdx.x & 3) * 8;
+                const int cc = c0 + ci;
 #pragma unroll
-        for (int q = 0; q < NPART; ++q) sh[ry][q][cx] = v[q];
+                for (int e = 0; e < 8; ++e) {
+                    const int jj = j0 + jb + e;
+                    tt[jb + e][ci] = (cc < n && jj < n) ? db[(int64_t)cc * n + jj] : 0.0;
+                }
+            }
+            __syncthreads();
+#pragma unroll 2
+            for (int i = 0; i < 8; ++i) {
+                const int jj = ry + 4 * i, j = j0 + jj;
+                if (c >= np) continue;
+                const bool in = colok && j < n;
+                const double djc = in ? db[(int64_t)j * n + c] : 0.0;
+                const int64_t e = m.offz + (int64_t)j * np + c;
+                a.dpad[e] = djc;
+                double wv = 0.0;
+                if (in) {
+                    if (j == c) {
+                        wv = 1.0;
+                        v[1] += 1.0;
+                        v[5] += fabs(djc + ti);
+                    } else {
+                        const double gap = tb[j] - ti;
+                        wv = -djc / gap;
+                        v[0] += wv * wv;
+                        v[2] += (gap * wv) * (gap * wv);
+                        v[3] += wv * wv;
+                        v[5] += fabs(djc);
+                    }
+                    v[4] += tt[jj][cx] * wv;
+                }
+                a.z1[e] = wv;
+                if (!in) a.z0[e] = 0.0;
+                if (ladder) {
+                    a.d32[e] = (float)djc;
+                    a.zlo1[e] = (float)(wv - (in && j == c ? 1.0 : 0.0));
+                    if (!in) a.zlo0[e] = 0.f;
+                }
+            }
+            __syncthreads();
+        }
+        if (colok && tm == c / m.T && ry == 0) a.col.d[m.offc + c] = db[(int64_t)c * n + c];
+#pragma unroll
+        for (int q = 0; q < NPART + 2; ++q) sh[ry][q][cx] = v[q];
         __syncthreads();
         if (ry == 0 && colok) {
+            double r6[NPART + 2];
 #pragma unroll
-            for (int q = 0; q < NPART; ++q)
-                a.part[m.offp + ((int64_t)tm * m.n + c) * NPART + q] =
-                    ((sh[0][q][cx] + sh[1][q][cx]) + sh[2][q][cx]) + sh[3][q][cx];
+            for (int q = 0; q < NPART + 2; ++q) r6[q] = ((sh[0][q][cx] + sh[1][q][cx]) + sh[2][q][cx]) + sh[3][q][cx];
+#pragma unroll
+            for (int q = 0; q < NPART; ++q) a.part[m.offp + ((int64_t)tm * n + c) * NPART + q] = r6[q];
+            a.dpart[m.offq + (int64_t)tm * n + c] = r6[4];
+            a.normpart[m.offq + (int64_t)tm * n + c] = r6[5];
         }
-        __syncthreads();
-    }
-}
-
-// d_c = sum_l Delta_cl Z_lc (FP64) for the active columns.  Item = (problem, 64
-// columns); 4 lane groups split l and are added in order.
-__global__ __launch_bounds__(256) void k_bdiag(const Ctrl *ctrl, BArgs a, const int4 *items, int64_t nitems,
-                                               int32_t in_buf) {
-    if (ctrl->error || ctrl->done) return;
-    __shared__ double red[4][64];
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const int4 w = items[it];
-        const BatchMeta m = a.meta[w.x];
-        const int cx = threadIdx.x & 63, g = threadIdx.x >> 6;
-        const int c = w.z * 64 + cx;
-        const bool act = c < m.n && a.col.state[m.offc + c] == COL_ACTIVE;
-        const double *db = a.delta + m.offd + (int64_t)(act ? c : 0) * m.n;
-        const double *zb = (in_buf ? a.z1 : a.z0) + m.offz;
-        const int span = (m.n + 3) / 4;
-        double acc = 0.0;
-        if (act) {
-            const int l1 = min(m.n, (g + 1) * span);
-            for (int l = g * span; l < l1; ++l) acc += db[l] * zb[(int64_t)l * m.n + c];
-        }
-        red[g][cx] = acc;
-        __syncthreads();
-        if (g == 0 && act) a.col.d[m.offc + c] = ((red[0][cx] + red[1][cx]) + red[2][cx]) + red[3][cx];
         __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------ GEMM
 // One T x T tile of W = F(Z) for problem b: Y = Delta_b Z_b on the matrix cores
-// (FP64, or FP32 on the split iterate), bounds-checked loads (n_b need not be a
-// multiple of T), fused IPT epilogue and per-column partial sums.
-template <int T>
-struct BCfg {
-    static constexpr int MI = T / 32;  // 16x16 MFMA blocks per wave and dimension (waves are 2 x 2)
-    static constexpr int BK = 16;
-    static constexpr int PA = T * BK / 256;  // A elements staged per thread per K slice
+// (FP64, or FP32 on the shadows), fused IPT epilogue, per-column partial sums and
+// the partial of the next sweep's d.  All operands are padded and 16-byte aligned.
+template <int T, bool F64>
+struct BT {
+    typedef typename std::conditional<F64, double, float>::type E;
+    static constexpr int BK = F64 ? 16 : 32;
+    static constexpr int VE = 16 / (int)sizeof(E);  // elements per 16-byte chunk
+    static constexpr int CPA = BK / VE;              // chunks per A row (8)
+    static constexpr int RPA = 256 / CPA;            // A rows per pass (32)
+    static constexpr int PA = T / RPA;               // A passes per thread
+    static constexpr int TPB = 256 / BK;             // threads per B row
+    static constexpr int PB = (T / VE) / TPB;        // B chunks per thread
+    static constexpr int LDA = BK + 1;               // A row pitch in LDS (odd: no bank aliasing)
+    static constexpr int SMEM = 2 * T * LDA * (int)sizeof(E) + 2 * BK * T * (int)sizeof(E);
+    static_assert(PA >= 1 && PB >= 1, "tile too small for the loader");
 };
 
+template <int T>
+constexpr int bsmem() {
+    return BT<T, true>::SMEM > BT<T, false>::SMEM ? BT<T, true>::SMEM : BT<T, false>::SMEM;
+}
+
 template <int T, bool F64>
-__device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART], const BArgs &a, const BatchMeta &m, int tm,
-                                      int tn, int32_t in_buf) {
-    using C = BCfg<T>;
-    constexpr int MI = C::MI, BK = C::BK, PA = C::PA;
-    typedef typename std::conditional<F64, double, float>::type E;
-    typedef E ATile[T][BK + 1];
+__device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], const BArgs &a, const BatchMeta &m,
+                                      int tm, int tn, int32_t t) {
+    typedef BT<T, F64> C;
+    typedef typename C::E E;
+    constexpr int BK = C::BK, VE = C::VE, CPA = C::CPA, RPA = C::RPA, PA = C::PA, TPB = C::TPB, PB = C::PB,
+                  LDA = C::LDA;
+    constexpr int MI = T / 32;  // 16 x 16 MFMA blocks per wave and dimension (waves are 2 x 2)
+    typedef E ATile[T][LDA];
     typedef E BTile[BK][T];
     ATile *As = (ATile *)smem;
     BTile *Bs = (BTile *)(smem + 2 * sizeof(ATile));
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
-    const int n = m.n;
-    const double *Ab = a.delta + m.offd;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
+    const int n = m.n, np = m.np;
+    const int32_t in_buf = (t - 1) & 1;
+    const double *Ad = a.dpad + m.offz;
     const double *zin = (in_buf ? a.z1 : a.z0) + m.offz;
     double *zout = (in_buf ? a.z0 : a.z1) + m.offz;
+    const E *Ag, *Bg;
+    if constexpr (F64) {
+        Ag = Ad;
+        Bg = zin;
+    } else {
+        Ag = a.d32 + m.offz;
+        Bg = (in_buf ? a.zlo1 : a.zlo0) + m.offz;
+    }
     const int r0 = tm * T, c0 = tn * T;
-    // loader mapping: A slice T x BK, thread t loads rows (t / BK) + (256 / BK) q, column t % BK;
-    //                 B slice BK x T, thread t loads row t / T + (256 / T) q, column t % T
-    const int a_r = t / BK, a_k = t % BK;
-    const int b_r = t / T, b_c = t % T;
-    constexpr int AR = 256 / BK, BR = 256 / T;
-    E ra[PA], rb[PA];
-#define IPT_BLOAD(K0)                                                                          \
-    do {                                                                                       \
-        _Pragma("unroll") for (int q = 0; q < PA; ++q) {                                       \
-            const int row = r0 + a_r + AR * q, kk = (K0) + a_k;                                \
-            ra[q] = (E)((row < n && kk < n) ? Ab[(int64_t)row * n + kk] : 0.0);                \
-        }                                                                                      \
-        _Pragma("unroll") for (int q = 0; q < PA; ++q) {                                       \
-            const int kk = (K0) + b_r + BR * q, cc = c0 + b_c;                                 \
-            double v = (kk < n && cc < n) ? zin[(int64_t)kk * n + cc] : 0.0;                   \
-            if (!F64 && kk == cc && kk < n) v -= 1.0; /* split iterate Z - E */                \
-            rb[q] = (E)v;                                                                      \
-        }                                                                                      \
+    const E *Ab = Ag + (int64_t)r0 * np;
+    const E *Bb = Bg + c0;
+    const int a_r = tid / CPA, a_c = (tid % CPA) * VE;
+    const int b_r = tid / TPB, b_c = (tid % TPB) * PB * VE;
+    uint4 ra[PA], rb[PB];
+    union Chunk {
+        uint4 u;
+        E e[VE];
+    };
+#define IPT_BLOAD(K0)                                                                                   \
+    do {                                                                                                \
+        _Pragma("unroll") for (int q = 0; q < PA; ++q) ra[q] =                                          \
+            *(const uint4 *)(Ab + (int64_t)(a_r + RPA * q) * np + (K0) + a_c);                          \
+        _Pragma("unroll") for (int q = 0; q < PB; ++q) rb[q] =                                          \
+            *(const uint4 *)(Bb + (int64_t)((K0) + b_r) * np + b_c + VE * q);                           \
     } while (0)
-#define IPT_BSTORE(S)                                                                          \
-    do {                                                                                       \
-        _Pragma("unroll") for (int q = 0; q < PA; ++q) As[S][a_r + AR * q][a_k] = ra[q];       \
-        _Pragma("unroll") for (int q = 0; q < PA; ++q) Bs[S][b_r + BR * q][b_c] = rb[q];       \
+#define IPT_BSTORE(S)                                                                                   \
+    do {                                                                                                \
+        _Pragma("unroll") for (int q = 0; q < PA; ++q) {                                                \
+            Chunk ch;                                                                                   \
+            ch.u = ra[q];                                                                               \
+            _Pragma("unroll") for (int e2 = 0; e2 < VE; ++e2) As[S][a_r + RPA * q][a_c + e2] = ch.e[e2]; \
+        }                                                                                               \
+        _Pragma("unroll") for (int q = 0; q < PB; ++q) * (uint4 *)&Bs[S][b_r][b_c + VE * q] = rb[q];    \
     } while (0)
     typedef typename std::conditional<F64, d4_t, f4_t>::type ACC;
     ACC acc[MI][MI];
@@ -226,7 +287,7 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART], const
     for (int x = 0; x < MI; ++x)
 #pragma unroll
         for (int y = 0; y < MI; ++y) acc[x][y] = ACC{0, 0, 0, 0};
-    const int nk = (n + BK - 1) / BK;
+    const int nk = np / BK;
     IPT_BLOAD(0);
     IPT_BSTORE(0);
     __syncthreads();
@@ -255,327 +316,436 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART], const
     }
 #undef IPT_BLOAD
 #undef IPT_BSTORE
-    // epilogue (idx = identity: column c continues e_c)
+    // epilogue (column c continues e_c), in groups of YB column blocks so that only
+    // their partial sums are live at once
     const double *tb = a.theta + m.offt;
-    int cols[MI];
-    bool act[MI];
-    double ti[MI], dd[MI];
+    float *zlo_out = F64 ? nullptr : (in_buf ? a.zlo0 : a.zlo1) + m.offz;
+    constexpr int YB = MI > 2 ? 2 : MI;
 #pragma unroll
-    for (int y = 0; y < MI; ++y) {
-        const int c = c0 + wn * (T / 2) + 16 * y + (lane & 15);
-        cols[y] = c;
-        act[y] = c < n && a.col.state[m.offc + c] == COL_ACTIVE;
-        ti[y] = c < n ? tb[c] : 0.0;
-        dd[y] = c < n ? a.col.d[m.offc + c] : 0.0;
-    }
-    double sums[MI][NPART];
+    for (int y0 = 0; y0 < MI; y0 += YB) {
+        int cols[YB];
+        bool act[YB];
+        double ti[YB], dd[YB];
+        double sums[YB][NPART + 1];
 #pragma unroll
-    for (int y = 0; y < MI; ++y)
+        for (int u = 0; u < YB; ++u) {
+            const int c = c0 + wn * (T / 2) + 16 * (y0 + u) + (lane & 15);
+            cols[u] = c;
+            act[u] = c < n && a.col.state[m.offc + c] == COL_ACTIVE;
+            ti[u] = c < n ? tb[c] : 0.0;
+            dd[u] = act[u] ? a.col.d[m.offc + c] : 0.0;
 #pragma unroll
-        for (int q = 0; q < NPART; ++q) sums[y][q] = 0.0;
+            for (int q = 0; q < NPART + 1; ++q) sums[u][q] = 0.0;
+        }
 #pragma unroll
-    for (int x = 0; x < MI; ++x)
+        for (int x = 0; x < MI; ++x)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            // f64 MFMA: row 4r + l/16; f32 MFMA: row 4(l/16) + r
-            const int lr = F64 ? (16 * x + 4 * r + (lane >> 4)) : (16 * x + 4 * (lane >> 4) + r);
-            const int j = r0 + wm * (T / 2) + lr;
-            if (j >= n) continue;
-            const double tj = tb[j];
+            for (int r = 0; r < 4; ++r) {
+                // f64 MFMA: row 4r + l/16; f32 MFMA: row 4(l/16) + r
+                const int lr = F64 ? (16 * x + 4 * r + (lane >> 4)) : (16 * x + 4 * (lane >> 4) + r);
+                const int j = r0 + wm * (T / 2) + lr;
+                if (j >= n) continue;
+                const double tj = tb[j];
 #pragma unroll
-            for (int y = 0; y < MI; ++y) {
-                if (!act[y]) continue;
-                const int c = cols[y];
-                const double z = zin[(int64_t)j * n + c];
-                double wv, st, gs, de;
-                if (j == c) {
-                    wv = 1.0;
-                    st = wv - z;
-                    gs = 0.0;
-                    de = 0.0;
-                } else {
-                    const double yv = F64 ? (double)acc[x][y][r] : Ab[(int64_t)j * n + c] + (double)acc[x][y][r];
-                    const double gap = tj - ti[y];
-                    wv = (z * dd[y] - yv) / gap;
-                    st = wv - z;
-                    gs = gap * st;
-                    de = wv;
+                for (int u = 0; u < YB; ++u) {
+                    if (!act[u]) continue;
+                    const int c = cols[u];
+                    const int64_t e = (int64_t)j * np + c;
+                    const double z = zin[e];
+                    double wvv, st, gs, de;
+                    if (j == c) {
+                        wvv = 1.0;
+                        st = wvv - z;
+                        gs = 0.0;
+                        de = 0.0;
+                    } else {
+                        const double acv = (double)acc[x][y0 + u][r];
+                        const double yv = F64 ? acv : Ad[e] + acv;  // split form: Delta E exact
+                        const double gap = tj - ti[u];
+                        wvv = (z * dd[u] - yv) / gap;
+                        st = wvv - z;
+                        gs = gap * st;
+                        de = wvv;
+                    }
+                    zout[e] = wvv;
+                    if constexpr (!F64) zlo_out[e] = (float)(j == c ? 0.0 : wvv);
+                    sums[u][0] += st * st;
+                    sums[u][1] += z * z;
+                    sums[u][2] += gs * gs;
+                    sums[u][3] += de * de;
+                    sums[u][4] += Ad[(int64_t)c * np + j] * wvv;  // next sweep's d_c
                 }
-                zout[(int64_t)j * n + c] = wv;
-                sums[y][0] += st * st;
-                sums[y][1] += z * z;
-                sums[y][2] += gs * gs;
-                sums[y][3] += de * de;
             }
-        }
 #pragma unroll
-    for (int y = 0; y < MI; ++y)
+        for (int u = 0; u < YB; ++u)
 #pragma unroll
-        for (int q = 0; q < NPART; ++q) {
-            double v = sums[y][q];
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
-            sums[y][q] = v;
-        }
-    if (lane < 16) {
-#pragma unroll
-        for (int y = 0; y < MI; ++y)
-#pragma unroll
-            for (int q = 0; q < NPART; ++q) red[wm][wn * (T / 2) + 16 * y + lane][q] = sums[y][q];
+            for (int q = 0; q < NPART + 1; ++q) {
+                double v = sums[u][q];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (lane < 16) red[wm][wn * (T / 2) + 16 * (y0 + u) + lane][q] = v;
+            }
     }
     __syncthreads();
-    if (t < T) {
-        const int c = c0 + t;
+    if (tid < T) {
+        const int c = c0 + tid;
         if (c < n) {
 #pragma unroll
             for (int q = 0; q < NPART; ++q)
-                a.part[m.offp + ((int64_t)tm * n + c) * NPART + q] = red[0][t][q] + red[1][t][q];
+                a.part[m.offp + ((int64_t)tm * n + c) * NPART + q] = red[0][tid][q] + red[1][tid][q];
+            a.dpart[m.offq + (int64_t)tm * n + c] = red[0][tid][NPART] + red[1][tid][NPART];
         }
     }
     __syncthreads();
 }
 
 template <int T>
-__global__ __launch_bounds__(256, (T == 64 ? 3 : 2)) void k_bgemm(const Ctrl *ctrl, BArgs a, const int4 *items, int64_t nitems,
-                                               int32_t sweep, int32_t in_buf, int32_t *ticket) {
+__global__ __launch_bounds__(256, (T == 128 ? 2 : (T == 64 ? 4 : 5))) void k_bgemm(const Ctrl *ctrl, BArgs a,
+                                                                                   BatchLists lists) {
     if (ctrl->error || ctrl->done) return;
-    constexpr int SM = 2 * T * (16 + 1) * 8 + 2 * 16 * T * 8;
-    __shared__ __attribute__((aligned(16))) char smem[SM];
-    __shared__ double red[2][T][NPART];
-    __shared__ int64_t cur_item;
-    const int32_t par = (sweep - 1) & 1;  // tile flags of this sweep were written by the previous finalize
+    constexpr int C = tile_class<T>();
+    const int32_t t = cur_sweep(ctrl);
+    const int4 *items = lists.l[C][t & 1];
+    const int32_t nitems = lists.counts[2 * C + (t & 1)];
+    __shared__ __attribute__((aligned(16))) char smem[bsmem<T>()];
+    __shared__ double red[2][T][NPART + 1];
+    __shared__ int32_t cur_item;
     for (;;) {
-        if (threadIdx.x == 0) cur_item = atomicAdd(ticket, 1);
+        if (threadIdx.x == 0) cur_item = atomicAdd(&lists.tickets[C], 1);
         __syncthreads();
-        const int64_t it = cur_item;
+        const int32_t it = cur_item;
         __syncthreads();
         if (it >= nitems) break;
         const int4 w = items[it];
         const BatchMeta m = a.meta[w.x];
-        const uint32_t f = flag_word(a.tflag, a.total_tiles, par, m.offf + w.z);
-        if ((int32_t)(f >> 2) != sweep - 1) continue;  // no active column in this column tile
-        if ((f & 3u) == (uint32_t)PREC_F64) btile<T, true>(smem, red, a, m, w.y, w.z, in_buf);
-        else btile<T, false>(smem, red, a, m, w.y, w.z, in_buf);
+        const uint32_t f = a.tflag[(int64_t)((t - 1) & 1) * a.total_tiles + m.offf + w.z];
+        if ((f & 3u) == (uint32_t)PREC_F64) btile<T, true>(smem, red, a, m, w.y, w.z, t);
+        else btile<T, false>(smem, red, a, m, w.y, w.z, t);
     }
 }
 
 // --------------------------------------------------------------- finalize
-// Per column of every problem: reduce the partials of its problem's row tiles in
-// order, form s_c, decide (only an FP64 or product-free sweep certifies), and stamp
-// the column tile's flag for the next sweep with the precision it needs.
+// Per column of every problem: reduce its problem's row-tile partials in order, form
+// s_c, decide (only an FP64 or product-free sweep certifies); a column that stays
+// active gets its next d (the epilogue partials, in row-tile order) and stamps its
+// column tile with the precision it needs next.  The first stamp of a tile in a sweep
+// enqueues the tile's row tiles for the next sweep (one list append per block and
+// tile class).  Batch counters go to per-block partials, reduced by the control
+// kernel in block order.
+enum { BP_MAXSTEP, BP_DECSTEP, BP_STILL, BP_CONV, BP_DIV, BP_NC, BP_F32, BP_WORDS = 8 };
+
 __global__ __launch_bounds__(256) void k_bfinalize(Ctrl *ctrl, DevOpts o, BArgs a, int64_t total_cols,
-                                                   int32_t sweep, int32_t in_par, int32_t out_par) {
+                                                   BatchLists lists) {
     if (ctrl->error || ctrl->done) return;
+    const int32_t t = cur_sweep(ctrl);
     const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int32_t decided = -1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool inb = gc < total_cols;
+    int32_t decided = -1, prec = 0;
     double s = 0.0;
     bool act = false, still = false;
-    uint64_t res_bits = 0;
-    double dist = 0.0;
-    if (gc < total_cols && a.col.state[gc] == COL_ACTIVE) {
-        act = true;
+    uint32_t want = 0;
+    int64_t tile_key = -1, prob_key = -1;
+    uint64_t norm_v = 0;
+    BatchMeta m{};
+    int c = 0;
+    if (inb) {
         const int b = a.col.prob[gc];
-        const BatchMeta m = a.meta[b];
-        const int c = (int)(gc - m.offc);
-        const int nrt = (m.n + m.T - 1) / m.T;
-        double p[NPART] = {0.0, 0.0, 0.0, 0.0};
-        for (int rt = 0; rt < nrt; ++rt) {
-            const double4 v = *(const double4 *)&a.part[m.offp + ((int64_t)rt * m.n + c) * NPART];
-            p[0] += v.x;
-            p[1] += v.y;
-            p[2] += v.z;
-            p[3] += v.w;
+        m = a.meta[b];
+        c = (int)(gc - m.offc);
+        tile_key = m.offf + c / m.T;
+        prob_key = b;
+        const int nt = m.np / m.T;
+        if (t == 1) {  // |M_b|_1 from the first sweep's column sums
+            double cs = 0.0;
+            for (int q = 0; q < nt; ++q) cs += a.normpart[m.offq + (int64_t)q * m.n + c];
+            norm_v = dbits(cs);
         }
-        s = sqrt(p[0]) / sqrt(p[1]);
-        dist = sqrt(p[3]);
-        const uint32_t f = flag_word(a.tflag, a.total_tiles, (sweep - 1) & 1, m.offf + c / m.T);
-        const int32_t prec = (sweep == 1 && in_par == PAR_UNIT) ? PREC_EXACT_FIRST : (int32_t)(f & 3u);
-        const bool exact = prec == PREC_F64 || prec == PREC_EXACT_FIRST;
-        const double resid = sqrt(p[2]) / sqrt(p[1]);  // normalised by |M_b|_1 at copy-out
-        if (exact && s <= o.tol) {
-            decided = COL_CONVERGED;
-            a.col.par[gc] = in_par;
-            res_bits = 1;
-        } else {
-            const bool bad = !isfinite(s) || !(dist <= o.div_norm);
-            int32_t grow = a.col.grow[gc];
-            if (exact) {
-                grow = (s > a.col.prev[gc]) ? grow + 1 : 0;
-                a.col.grow[gc] = grow;
+        act = a.col.state[gc] == COL_ACTIVE;
+        if (act) {
+            double p[NPART] = {0.0, 0.0, 0.0, 0.0};
+            for (int rt = 0; rt < nt; ++rt) {
+                const double4 v = *(const double4 *)&a.part[m.offp + ((int64_t)rt * m.n + c) * NPART];
+                p[0] += v.x;
+                p[1] += v.y;
+                p[2] += v.z;
+                p[3] += v.w;
             }
-            if (bad || grow >= o.div_growth) {
-                decided = COL_DIVERGED;
-                a.col.par[gc] = out_par;
-            } else if (sweep >= o.max_iter) {
-                decided = COL_NOT_CONVERGED;
-                a.col.par[gc] = out_par;
+            s = sqrt(p[0]) / sqrt(p[1]);
+            const double dist = sqrt(p[3]);
+            const uint32_t f = a.tflag[(int64_t)((t - 1) & 1) * a.total_tiles + tile_key];
+            prec = (t == 1) ? PREC_EXACT_FIRST : (int32_t)(f & 3u);
+            const bool exact = prec == PREC_F64 || prec == PREC_EXACT_FIRST;
+            const double resid = sqrt(p[2]) / sqrt(p[1]);  // normalised by |M_b|_1 at copy-out
+            const int32_t in_par = (t == 1) ? PAR_UNIT : ((t - 1) & 1);
+            const int32_t out_par = t & 1;
+            const double prev = a.col.prev[gc];
+            if (exact && s <= o.tol) {
+                decided = COL_CONVERGED;
+                a.col.par[gc] = in_par;
+            } else {
+                const bool bad = !isfinite(s) || !(dist <= o.div_norm);
+                int32_t grow = a.col.grow[gc];
+                if (exact) {
+                    grow = (s > prev) ? grow + 1 : 0;
+                    a.col.grow[gc] = grow;
+                }
+                if (bad || grow >= o.div_growth) {
+                    decided = COL_DIVERGED;
+                    a.col.par[gc] = out_par;
+                } else if (t >= o.max_iter) {
+                    decided = COL_NOT_CONVERGED;
+                    a.col.par[gc] = out_par;
+                }
             }
-        }
-        const double prev = a.col.prev[gc];
-        a.col.prev[gc] = s;
-        if (decided >= 0) {
-            a.col.state[gc] = decided;
-            a.col.sweeps[gc] = sweep;
-            a.col.step[gc] = s;
-            a.col.lam[gc] = a.theta[m.offt + c] + a.col.d[gc];
-            a.col.resid[gc] = resid;
-        } else {
-            still = true;
-            // precision this column asks of its tile next sweep
-            int32_t want = PREC_F64;
-            if (o.ladder && prec != PREC_F64) want = (s <= o.tau_32 || !(s < prev)) ? PREC_F64 : PREC_F32;
-            atomicMax(&a.tflag[(int64_t)(sweep & 1) * a.total_tiles + m.offf + c / m.T],
-                      ((uint32_t)sweep << 2) | (uint32_t)want);
+            a.col.prev[gc] = s;
+            if (decided >= 0) {
+                a.col.state[gc] = decided;
+                a.col.sweeps[gc] = t;
+                a.col.step[gc] = s;
+                a.col.lam[gc] = a.theta[m.offt + c] + a.col.d[gc];
+                a.col.resid[gc] = resid;
+            } else {
+                still = true;
+                double dn = 0.0;
+                for (int q = 0; q < nt; ++q) dn += a.dpart[m.offq + (int64_t)q * m.n + c];
+                a.col.d[gc] = dn;
+                want = PREC_F64;
+                if (o.ladder && prec != PREC_F64) want = (s <= o.tau_32 || !(s < prev)) ? PREC_F64 : PREC_F32;
+            }
         }
     }
-    // wave-aggregated bookkeeping
+    // column-tile stamps: one atomic per tile segment of the wave
+    bool leader;
+    const uint64_t tw = seg_max(tile_key, still ? (uint64_t)(((uint32_t)t << 2) | want) : 0ull, leader);
+    int my_cls = -1, my_cnt = 0;
+    if (leader && tw) {
+        const uint32_t old = atomicMax(&a.tflag[(int64_t)(t & 1) * a.total_tiles + tile_key], (uint32_t)tw);
+        if ((int32_t)(old >> 2) != t) {  // first stamp of this tile in this sweep
+            my_cls = tile_class_of(m.T);
+            my_cnt = m.np / m.T;
+        }
+    }
+    // list appends: wave scans per tile class, one atomicAdd per class and block
+    __shared__ int s_tot[4][3];
+    __shared__ int s_base[3];
+    int my_excl = 0;
+#pragma unroll
+    for (int cl = 0; cl < 3; ++cl) {
+        const int v = (my_cls == cl) ? my_cnt : 0;
+        const int inc = wave_incl_scan(v);
+        if (my_cls == cl) my_excl = inc - v;
+        if (lane == 63) s_tot[wave][cl] = inc;
+    }
+    __syncthreads();
+    const int nx = (t + 1) & 1;
+    if (threadIdx.x < 3) {
+        const int cl = threadIdx.x;
+        const int tot = s_tot[0][cl] + s_tot[1][cl] + s_tot[2][cl] + s_tot[3][cl];
+        s_base[cl] = tot ? atomicAdd(&lists.counts[2 * cl + nx], tot) : 0;
+    }
+    __syncthreads();
+    if (my_cnt) {
+        int pos = s_base[my_cls] + my_excl;
+        for (int w2 = 0; w2 < wave; ++w2) pos += s_tot[w2][my_cls];
+        int4 *lst = lists.l[my_cls][nx];
+        const int tn = c / m.T;
+        for (int q = 0; q < my_cnt; ++q) lst[pos + q] = make_int4((int)prob_key, q, tn, 0);
+    }
+    if (t == 1) {
+        bool nl;
+        const uint64_t nv = seg_max(prob_key, norm_v, nl);
+        if (nl && inb) atomicMax((unsigned long long *)&a.col.norm_bits[prob_key], (unsigned long long)nv);
+    }
+    // batch counters: wave reductions, then a per-block partial
     uint64_t v = act ? dbits(s) : 0;
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t q = (uint64_t)__shfl_xor((unsigned long long)v, off);
-        v = q > v ? q : v;
-    }
     uint64_t dv = decided >= 0 ? dbits(s) : 0;
+#pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t q = (uint64_t)__shfl_xor((unsigned long long)dv, off);
-        dv = q > dv ? q : dv;
+        const uint64_t q1 = (uint64_t)__shfl_xor((unsigned long long)v, off);
+        const uint64_t q2 = (uint64_t)__shfl_xor((unsigned long long)dv, off);
+        v = q1 > v ? q1 : v;
+        dv = q2 > dv ? q2 : dv;
+    }
+    __shared__ uint64_t s_w[4][BP_WORDS];
+    if (lane == 0) {
+        s_w[wave][BP_MAXSTEP] = v;
+        s_w[wave][BP_DECSTEP] = dv;
     }
     const uint64_t m_still = __ballot(still), m_conv = __ballot(decided == COL_CONVERGED),
-                   m_div = __ballot(decided == COL_DIVERGED), m_nc = __ballot(decided == COL_NOT_CONVERGED);
-    (void)res_bits;
-    (void)dist;
-    if ((threadIdx.x & 63) == 0) {
-        if (v) atomicMax((unsigned long long *)&ctrl->acc_maxstep, (unsigned long long)v);
-        if (dv) atomicMax((unsigned long long *)&ctrl->dec_maxstep, (unsigned long long)dv);
-        if (m_still) atomicAdd(&ctrl->acc_active, (int32_t)__popcll(m_still));
-        if (m_conv) atomicAdd(&ctrl->n_conv, (int32_t)__popcll(m_conv));
-        if (m_div) atomicAdd(&ctrl->n_div, (int32_t)__popcll(m_div));
-        if (m_nc) atomicAdd(&ctrl->n_notconv, (int32_t)__popcll(m_nc));
+                   m_div = __ballot(decided == COL_DIVERGED), m_nc = __ballot(decided == COL_NOT_CONVERGED),
+                   m_f32 = __ballot(act && prec == PREC_F32);
+    if (lane == 0) {
+        s_w[wave][BP_STILL] = __popcll(m_still);
+        s_w[wave][BP_CONV] = __popcll(m_conv);
+        s_w[wave][BP_DIV] = __popcll(m_div);
+        s_w[wave][BP_NC] = __popcll(m_nc);
+        s_w[wave][BP_F32] = m_f32 ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < BP_WORDS) {
+        const int q = threadIdx.x;
+        uint64_t r;
+        if (q <= BP_DECSTEP || q == BP_F32) {
+            r = s_w[0][q];
+            for (int w2 = 1; w2 < 4; ++w2) r = s_w[w2][q] > r ? s_w[w2][q] : r;
+        } else {
+            r = s_w[0][q] + s_w[1][q] + s_w[2][q] + s_w[3][q];
+        }
+        if (q == BP_WORDS - 1) r = 0;
+        a.bpart[(int64_t)blockIdx.x * BP_WORDS + q] = r;
     }
 }
 
-// Sweep bookkeeping of the batch (history, done flag) and ticket reset.
-__global__ void k_bcontrol(Ctrl *ctrl, DevOpts o, int32_t sweep, int32_t *tickets) {
+// Sweep bookkeeping of the batch: reduce the finalize blocks' partials in block
+// order, then history, done flag, device sweep counter, and reset of the work-list
+// counters and tickets this sweep consumed.  One block.
+__global__ __launch_bounds__(256) void k_bcontrol(Ctrl *ctrl, DevOpts o, BArgs a, int32_t nblk, BatchLists lists) {
     if (ctrl->error || ctrl->done) return;
-    const double ms = bitsd(ctrl->acc_maxstep);
-    if (sweep - 1 < IPT_HIST) {
-        ctrl->hist_prec[sweep - 1] = ctrl->prec;
-        ctrl->hist_active[sweep - 1] = ctrl->active;
-        ctrl->hist_step[sweep - 1] = ms;
+    __shared__ uint64_t r[256][BP_WORDS];
+    uint64_t acc[BP_WORDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int bi = threadIdx.x; bi < nblk; bi += 256) {
+        const uint64_t *p = a.bpart + (int64_t)bi * BP_WORDS;
+#pragma unroll
+        for (int q = 0; q < BP_WORDS; ++q) {
+            const uint64_t x = p[q];
+            if (q <= BP_DECSTEP || q == BP_F32) acc[q] = x > acc[q] ? x : acc[q];
+            else acc[q] += x;
+        }
     }
-    ctrl->matvecs += (sweep == 1 && ctrl->prec == PREC_EXACT_FIRST) ? 0 : ctrl->active;
-    ctrl->active = ctrl->acc_active;
-    ctrl->acc_active = 0;
-    ctrl->acc_maxstep = 0;
-    ctrl->sweeps = sweep;
-    if (ctrl->active == 0 || sweep >= o.max_iter) ctrl->done = 1;
-    // the batch records FP64 once any tile runs in FP64, else FP32 (tile precisions vary)
-    ctrl->prec = o.ladder ? PREC_F32 : PREC_F64;
-    tickets[0] = 0;
-    tickets[1] = 0;
+#pragma unroll
+    for (int q = 0; q < BP_WORDS; ++q) r[threadIdx.x][q] = acc[q];
+    __syncthreads();
+    for (int half = 128; half > 0; half >>= 1) {
+        if (threadIdx.x < half) {
+#pragma unroll
+            for (int q = 0; q < BP_WORDS; ++q) {
+                const uint64_t x = r[threadIdx.x + half][q], y = r[threadIdx.x][q];
+                r[threadIdx.x][q] = (q <= BP_DECSTEP || q == BP_F32) ? (x > y ? x : y) : x + y;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const int32_t t = cur_sweep(ctrl);
+    const double ms = bitsd(r[0][BP_MAXSTEP]);
+    if (r[0][BP_DECSTEP] > ctrl->dec_maxstep) ctrl->dec_maxstep = r[0][BP_DECSTEP];
+    ctrl->n_conv += (int32_t)r[0][BP_CONV];
+    ctrl->n_div += (int32_t)r[0][BP_DIV];
+    ctrl->n_notconv += (int32_t)r[0][BP_NC];
+    // a sweep counts as FP32 when any of its tiles ran in FP32
+    const int32_t prec = (t == 1) ? PREC_EXACT_FIRST : (r[0][BP_F32] ? PREC_F32 : PREC_F64);
+    if (t - 1 < IPT_HIST) {
+        ctrl->hist_prec[t - 1] = prec;
+        ctrl->hist_active[t - 1] = ctrl->active;
+        ctrl->hist_step[t - 1] = ms;
+    }
+    if (t > 1) ctrl->matvecs += ctrl->active;
+    ctrl->active = (int32_t)r[0][BP_STILL];
+    ctrl->sweeps = t;
+    if (ctrl->active == 0 || t >= o.max_iter) ctrl->done = 1;
+    for (int cl = 0; cl < 3; ++cl) {
+        lists.counts[2 * cl + (t & 1)] = 0;
+        lists.tickets[cl] = 0;
+    }
 }
 
-// Outputs: z_pool[b] <- final iterate of each column, lambda, status; the
-// eigen-residual is normalised by |M_b|_1 here.
-__global__ void k_bcopyout(const Ctrl *ctrl, BArgs a, const int64_t *z_off, double *z_pool, double *lambda_pool,
-                           int32_t *status_pool, int64_t total_cols, double *max_resid_out) {
+// Outputs: the final iterate of each column into z_pool (row-major, leading dimension
+// n_b), lambda, status; the eigen-residual is normalised by |M_b|_1 here.  Item =
+// (problem, row tile, 64 columns), as for the first sweep.
+__global__ __launch_bounds__(256) void k_bcopyout(const Ctrl *ctrl, BArgs a, const int4 *items, int64_t nitems,
+                                                  double *z_pool, double *lambda_pool, int32_t *status_pool,
+                                                  double *max_resid_out) {
     if (ctrl->error) return;
-    const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (gc >= total_cols) return;
-    const int b = a.col.prob[gc];
-    const BatchMeta m = a.meta[b];
-    const int c = (int)(gc - m.offc);
-    const int32_t par = a.col.par[gc];
-    const double *src = (par == PAR_BUF1 ? a.z1 : a.z0) + m.offz;
-    double *dst = z_pool + z_off[b];
-    for (int j = 0; j < m.n; ++j) dst[(int64_t)j * m.n + c] = (par == PAR_UNIT) ? (j == c ? 1.0 : 0.0) : src[(int64_t)j * m.n + c];
-    lambda_pool[m.offt + c] = a.col.lam[gc];
-    const int32_t st = a.col.state[gc];
-    status_pool[m.offt + c] = st == COL_ACTIVE ? IPT_NOT_CONVERGED : st;
-    const double nrm = bitsd(a.col.norm_bits[b]);
-    const double r = a.col.resid[gc] / (nrm > 0.0 ? nrm : 1.0);
-    a.col.resid[gc] = r;
-    if (st == COL_CONVERGED)
-        atomicMax((unsigned long long *)max_resid_out, (unsigned long long)dbits(r));
+    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        const BatchMeta m = a.meta[w.x];
+        const int n = m.n, np = m.np, tm = w.y;
+        const int c = w.z * 64 + cx;
+        const bool ok = c < n;
+        const int64_t gc = m.offc + c;
+        if (ok) {
+            const int32_t par = a.col.par[gc];
+            const double *src = (par == PAR_BUF1 ? a.z1 : a.z0) + m.offz;
+            double *dst = z_pool + m.offo;
+            const int j1 = min(n, tm * m.T + m.T);
+            for (int j = tm * m.T + ry; j < j1; j += 4)
+                dst[(int64_t)j * n + c] = (par == PAR_UNIT) ? (j == c ? 1.0 : 0.0) : src[(int64_t)j * np + c];
+        }
+        if (tm == 0 && ry == 0) {  // one wave per item: per-column outputs
+            uint64_t rb = 0;
+            if (ok) {
+                lambda_pool[m.offt + c] = a.col.lam[gc];
+                const int32_t st = a.col.state[gc];
+                status_pool[m.offt + c] = st == COL_ACTIVE ? IPT_NOT_CONVERGED : st;
+                const double nrm = bitsd(a.col.norm_bits[w.x]);
+                const double r = a.col.resid[gc] / (nrm > 0.0 ? nrm : 1.0);
+                a.col.resid[gc] = r;
+                if (st == COL_CONVERGED) rb = dbits(r);
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint64_t q = (uint64_t)__shfl_xor((unsigned long long)rb, off);
+                rb = q > rb ? q : rb;
+            }
+            if (cx == 0 && rb) atomicMax((unsigned long long *)max_resid_out, (unsigned long long)rb);
+        }
+    }
 }
 
 }  // namespace
 
 // ------------------------------------------------------------- launchers
-BatchLaunch make_batch_launch(const BatchMeta *meta, const double *theta, const double *delta, double *z0, double *z1,
-                              BatchCols col, double *part, uint32_t *tflag, int64_t total_tiles) {
-    BatchLaunch L;
-    L.meta = meta;
-    L.theta = theta;
-    L.delta = delta;
-    L.z0 = z0;
-    L.z1 = z1;
-    L.col = col;
-    L.part = part;
-    L.tflag = tflag;
-    L.total_tiles = total_tiles;
-    return L;
-}
-
-static const BArgs &to_args(const BatchLaunch &L) { return L; }
-
 int bgemm_grid(int tile) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 512;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    hipError_t e = tile == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bgemm<64>, 256, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bgemm<128>, 256, 0);
+    hipError_t e = tile == 32   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bgemm<32>, 256, 0)
+                   : tile == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bgemm<64>, 256, 0)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bgemm<128>, 256, 0);
     if (e != hipSuccess || per <= 0) per = 1;
     return cus * per;
 }
 
+int bfinalize_blocks(int64_t total_cols) { return (int)((total_cols + 255) / 256); }
+
 hipError_t launch_binit(hipStream_t s, Ctrl *ctrl, const BatchLaunch &L, int32_t count, int32_t start_prec) {
-    k_binit<<<count, 256, 0, s>>>(ctrl, to_args(L), start_prec);
+    k_binit<<<count, 256, 0, s>>>(ctrl, L, start_prec);
     return hipGetLastError();
 }
 
-hipError_t launch_bnorm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, int32_t count) {
-    k_bnorm<<<count, 256, 0, s>>>(ctrl, to_args(L));
-    return hipGetLastError();
-}
-
-hipError_t launch_bsweep1(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems) {
+hipError_t launch_bsweep1(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
+                          int32_t ladder) {
     const int g = nitems < 8192 ? (int)nitems : 8192;
-    k_bsweep1<<<g > 0 ? g : 1, 256, 0, s>>>(ctrl, to_args(L), items, nitems);
+    k_bsweep1<<<g > 0 ? g : 1, 256, 0, s>>>(ctrl, L, items, nitems, ladder);
     return hipGetLastError();
 }
 
-hipError_t launch_bdiag(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
-                        int32_t in_buf) {
-    const int g = nitems < 8192 ? (int)nitems : 8192;
-    k_bdiag<<<g > 0 ? g : 1, 256, 0, s>>>(ctrl, to_args(L), items, nitems, in_buf);
-    return hipGetLastError();
-}
-
-hipError_t launch_bgemm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, int tile, const int4 *items,
-                        int64_t nitems, int32_t sweep, int32_t in_buf, int32_t *ticket, int grid) {
-    if (nitems == 0) return hipSuccess;
-    if (tile == 64) k_bgemm<64><<<grid, 256, 0, s>>>(ctrl, to_args(L), items, nitems, sweep, in_buf, ticket);
-    else k_bgemm<128><<<grid, 256, 0, s>>>(ctrl, to_args(L), items, nitems, sweep, in_buf, ticket);
+hipError_t launch_bgemm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int tile,
+                        int grid) {
+    if (tile == 32) k_bgemm<32><<<grid, 256, 0, s>>>(ctrl, L, lists);
+    else if (tile == 64) k_bgemm<64><<<grid, 256, 0, s>>>(ctrl, L, lists);
+    else k_bgemm<128><<<grid, 256, 0, s>>>(ctrl, L, lists);
     return hipGetLastError();
 }
 
 hipError_t launch_bfinalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
-                            int32_t sweep, int32_t in_par, int32_t out_par) {
-    k_bfinalize<<<(unsigned)((total_cols + 255) / 256), 256, 0, s>>>(ctrl, o, to_args(L), total_cols, sweep, in_par,
-                                                                      out_par);
+                            const BatchLists &lists) {
+    k_bfinalize<<<bfinalize_blocks(total_cols), 256, 0, s>>>(ctrl, o, L, total_cols, lists);
     return hipGetLastError();
 }
 
-hipError_t launch_bcontrol(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, int32_t *tickets) {
-    k_bcontrol<<<1, 1, 0, s>>>(ctrl, o, sweep, tickets);
+hipError_t launch_bcontrol(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
+                           const BatchLists &lists) {
+    k_bcontrol<<<1, 256, 0, s>>>(ctrl, o, L, bfinalize_blocks(total_cols), lists);
     return hipGetLastError();
 }
 
-hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int64_t *z_off,
-                           double *z_pool, double *lambda_pool, int32_t *status_pool, int64_t total_cols,
-                           double *max_resid_out) {
-    k_bcopyout<<<(unsigned)((total_cols + 255) / 256), 256, 0, s>>>(ctrl, to_args(L), z_off, z_pool, lambda_pool,
-                                                                     status_pool, total_cols, max_resid_out);
+hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
+                           double *z_pool, double *lambda_pool, int32_t *status_pool, double *max_resid_out) {
+    const int g = nitems < 8192 ? (int)nitems : 8192;
+    k_bcopyout<<<g > 0 ? g : 1, 256, 0, s>>>(ctrl, L, items, nitems, z_pool, lambda_pool, status_pool, max_resid_out);
     return hipGetLastError();
 }
 

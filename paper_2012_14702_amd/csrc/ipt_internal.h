@@ -32,7 +32,7 @@ struct Ctrl {
     int32_t active;      // active columns entering the next sweep
     int32_t acc_active;  // finalize accumulator: columns still active after this sweep
     int32_t n_conv, n_notconv, n_div;
-    int32_t pad0;
+    int32_t prec_mask;  // batched: bit PREC_F32 set when a tile of this sweep ran in FP32
     uint64_t acc_maxstep;  // finalize accumulator: max s_c (bit pattern of a non-negative double)
     uint64_t acc_maxres;   // max normalised eigen-residual over converged columns (bits)
     uint64_t dec_maxstep;  // max deciding step over decided columns (bits)
@@ -128,12 +128,15 @@ hipError_t launch_val32(hipStream_t s, const double *val, float *val32, int64_t 
 hipError_t launch_zlo_init(hipStream_t s, const double *zb, float *zlo, int64_t ldz, const int32_t *idx, int64_t n,
                            int64_t k);
 
-// Batched solves (ipt_batched.hip).  Problem b: size n, tile size T, offsets of its
-// Delta (caller pool), theta (caller pool), iterate buffers, columns, partial sums
-// and column-tile flags.
+// Batched solves (ipt_batched.hip).  Problem b: size n, tile size T (32, 64 or
+// 128), padded size np = round_up(n, T); offsets of its Delta and theta (caller
+// pools), of its output in z_pool (offo), of its padded np x np blocks in the
+// workspace arrays (offz: padded Delta, both iterate buffers and their shadows), of
+// its columns, its partial sums (offp, NPART per row tile and column), its
+// per-row-tile d and norm partials (offq) and its column-tile flags (offf).
 struct BatchMeta {
-    int32_t n, T;
-    int64_t offd, offt, offz, offc, offp, offf;
+    int32_t n, T, np, pad_;
+    int64_t offd, offt, offo, offz, offc, offp, offq, offf;
 };
 struct BatchCols {  // per column of all problems, concatenated
     int32_t *state, *sweeps, *grow, *par, *prob;
@@ -142,28 +145,38 @@ struct BatchCols {  // per column of all problems, concatenated
 };
 struct BatchLaunch {
     const BatchMeta *meta;
-    const double *theta, *delta;
-    double *z0, *z1;
+    const double *theta, *delta;  // caller pools
+    double *dpad;                 // padded FP64 Delta
+    float *d32;                   // padded FP32 Delta (ladder)
+    double *z0, *z1;              // iterate buffers
+    float *zlo0, *zlo1;           // FP32 shadows of Z - E (ladder)
     BatchCols col;
     double *part;
-    uint32_t *tflag;  // [2][total column tiles]: (sweep << 2) | precision
-    int64_t total_tiles;
+    double *dpart;     // [total_q] next sweep's d, one partial per (row tile, column)
+    double *normpart;  // [total_q] column sums of |M_b| per row tile (first sweep)
+    uint64_t *bpart;   // [finalize blocks][8] per-block batch counters
+    uint32_t *tflag;   // [2][total column tiles]: (sweep << 2) | precision
+    int64_t total_tiles, total_q;
 };
-BatchLaunch make_batch_launch(const BatchMeta *meta, const double *theta, const double *delta, double *z0, double *z1,
-                              BatchCols col, double *part, uint32_t *tflag, int64_t total_tiles);
+// Work lists of (problem, row tile, column tile, 0) items per tile class (T = 32, 64,
+// 128) and sweep parity, filled by the finalize of the previous sweep.
+struct BatchLists {
+    int4 *l[3][2];
+    int32_t *counts;   // [3][2] items in each list
+    int32_t *tickets;  // [3] next item of the running sweep, per class
+};
+int bfinalize_blocks(int64_t total_cols);
 hipError_t launch_binit(hipStream_t s, Ctrl *ctrl, const BatchLaunch &L, int32_t count, int32_t start_prec);
-hipError_t launch_bnorm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, int32_t count);
-hipError_t launch_bsweep1(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems);
-hipError_t launch_bdiag(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
-                        int32_t in_buf);
-hipError_t launch_bgemm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, int tile, const int4 *items,
-                        int64_t nitems, int32_t sweep, int32_t in_buf, int32_t *ticket, int grid);
+hipError_t launch_bsweep1(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
+                          int32_t ladder);
+hipError_t launch_bgemm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int tile,
+                        int grid);
 hipError_t launch_bfinalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
-                            int32_t sweep, int32_t in_par, int32_t out_par);
-hipError_t launch_bcontrol(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, int32_t *tickets);
-hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int64_t *z_off,
-                           double *z_pool, double *lambda_pool, int32_t *status_pool, int64_t total_cols,
-                           double *max_resid_out);
+                            const BatchLists &lists);
+hipError_t launch_bcontrol(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
+                           const BatchLists &lists);
+hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
+                           double *z_pool, double *lambda_pool, int32_t *status_pool, double *max_resid_out);
 int bgemm_grid(int tile);  // persistent grid size (CUs x resident blocks)
 
 // MLP kernels (ipt_mlp.hip)

@@ -20,6 +20,8 @@ SWEEP_NAMES = {0: "exact-first", 1: "low", 2: "fp32", 3: "fp64"}
 IPT_HIST = 128
 FLAG_NO_NORM = 1
 FLAG_TIME_KERNELS = 2
+FLAG_NO_GRAPH = 4
+TILE_BUCKETS = 64  # batched tile table: bucket q holds 64 q < n <= 64 (q + 1)
 
 
 class Opts(C.Structure):
@@ -100,12 +102,15 @@ def load_library():
     lib.ipt_solve_csr.argtypes = [p, i64, p, p, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
                                   C.POINTER(Info), C.POINTER(ColInfo)]
     lib.ipt_solve_batched.argtypes = [p, i32, p, p, p, p, p, p, C.POINTER(Opts), p, p, p, C.POINTER(Info)]
+    lib.ipt_batched_tune.argtypes = [p, i32, p, p, p, p, p, p, p, p, p, p]
+    lib.ipt_batched_get_tiles.argtypes = [p, p]
+    lib.ipt_batched_set_tiles.argtypes = [p, p]
     lib.ipt_status_string.argtypes = [C.c_int]
     lib.ipt_status_string.restype = C.c_char_p
     lib.ipt_last_error.argtypes = [p]
     lib.ipt_last_error.restype = C.c_char_p
     for fn in ("ipt_create", "ipt_destroy", "ipt_set_stream", "ipt_solve_dense", "ipt_solve_csr",
-               "ipt_solve_batched"):
+               "ipt_solve_batched", "ipt_batched_tune", "ipt_batched_get_tiles", "ipt_batched_set_tiles"):
         getattr(lib, fn).restype = C.c_int
     _lib = lib
     return lib
@@ -275,25 +280,36 @@ def ipt_solve_csr(theta, row_ptr, col, val, idx, z0=None, opts=None, handle=None
     return _finish(lib, h, st, z, lam, status, info, extra)
 
 
-def ipt_solve_batched(ns, theta_pool, delta_pool, theta_off=None, delta_off=None, opts=None, handle=None, **kw):
-    """Batched full-spectrum IPT (ipt_solve_batched).  ns: host int sequence of sizes;
-    pools are GPU f64 tensors; offsets default to the packed layout.  Returns z_pool
-    (same layout as delta_pool), lam_pool and status_pool (same layout as theta_pool)."""
-    import torch
-    lib = load_library()
-    h = _handle(handle)
+def _batch_layout(ns, theta_off, delta_off):
     ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
     if theta_off is None:
         theta_off = np.concatenate([[0], np.cumsum(ns.astype(np.int64))[:-1]]).astype(np.int64)
     if delta_off is None:
         delta_off = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
-    theta_off = np.ascontiguousarray(theta_off, dtype=np.int64)
-    delta_off = np.ascontiguousarray(delta_off, dtype=np.int64)
+    return (ns, np.ascontiguousarray(theta_off, dtype=np.int64), np.ascontiguousarray(delta_off, dtype=np.int64))
+
+
+def ipt_solve_batched(ns, theta_pool, delta_pool, theta_off=None, delta_off=None, opts=None, handle=None,
+                      z_out=None, lam_out=None, status_out=None, **kw):
+    """Batched full-spectrum IPT (ipt_solve_batched).  ns: host int sequence of sizes;
+    pools are GPU f64 tensors; offsets default to the packed layout.  Returns z_pool
+    (same layout as delta_pool), lam_pool and status_pool (same layout as theta_pool);
+    z_out / lam_out / status_out may be given to reuse output tensors."""
+    import torch
+    lib = load_library()
+    h = _handle(handle)
+    ns, theta_off, delta_off = _batch_layout(ns, theta_off, delta_off)
     _check(theta_pool, torch.float64, "theta_pool")
     _check(delta_pool, torch.float64, "delta_pool")
-    z = torch.empty_like(delta_pool)
-    lam = torch.empty_like(theta_pool)
-    status = torch.empty(theta_pool.shape[0], dtype=torch.int32, device=theta_pool.device)
+    z = torch.empty_like(delta_pool) if z_out is None else z_out
+    lam = torch.empty_like(theta_pool) if lam_out is None else lam_out
+    status = (torch.empty(theta_pool.shape[0], dtype=torch.int32, device=theta_pool.device)
+              if status_out is None else status_out)
+    _check(z, torch.float64, "z_out")
+    _check(lam, torch.float64, "lam_out")
+    _check(status, torch.int32, "status_out")
+    if z.numel() < delta_pool.numel() or lam.numel() < theta_pool.numel() or status.numel() < theta_pool.numel():
+        raise ValueError("output tensors smaller than the pools")
     o = _opts(opts, kw)
     info = Info()
     hp = lambda a: a.ctypes.data_as(C.c_void_p)
@@ -301,6 +317,51 @@ def ipt_solve_batched(ns, theta_pool, delta_pool, theta_off=None, delta_off=None
                                _ptr(theta_pool), _ptr(delta_pool), C.byref(o), _ptr(z), _ptr(lam), _ptr(status),
                                C.byref(info))
     return _finish(lib, h, st, z, lam, status, info, None)
+
+
+def ipt_batched_tune(ns, theta_pool, delta_pool, theta_off=None, delta_off=None, handle=None):
+    """Autotune the handle's batched tile table on this batch (ipt_batched_tune);
+    returns the table (TILE_BUCKETS tile sizes)."""
+    import torch
+    lib = load_library()
+    h = _handle(handle)
+    ns, theta_off, delta_off = _batch_layout(ns, theta_off, delta_off)
+    _check(theta_pool, torch.float64, "theta_pool")
+    _check(delta_pool, torch.float64, "delta_pool")
+    z = torch.empty_like(delta_pool)
+    lam = torch.empty_like(theta_pool)
+    status = torch.empty(theta_pool.shape[0], dtype=torch.int32, device=theta_pool.device)
+    tiles = np.zeros(TILE_BUCKETS, dtype=np.int32)
+    hp = lambda a: a.ctypes.data_as(C.c_void_p)
+    st = lib.ipt_batched_tune(h.ptr, ns.shape[0], hp(ns), hp(theta_off), hp(delta_off), hp(delta_off),
+                              _ptr(theta_pool), _ptr(delta_pool), _ptr(z), _ptr(lam), _ptr(status), hp(tiles))
+    if st != IPT_OK:
+        raise IPTError(st, h.last_error())
+    return [int(t) for t in tiles]
+
+
+def ipt_batched_get_tiles(handle=None):
+    """The handle's batched tile table (ipt_batched_get_tiles)."""
+    lib = load_library()
+    h = _handle(handle)
+    tiles = np.zeros(TILE_BUCKETS, dtype=np.int32)
+    st = lib.ipt_batched_get_tiles(h.ptr, tiles.ctypes.data_as(C.c_void_p))
+    if st != IPT_OK:
+        raise IPTError(st, h.last_error())
+    return [int(t) for t in tiles]
+
+
+def ipt_batched_set_tiles(tiles, handle=None):
+    """Replace the handle's batched tile table (ipt_batched_set_tiles), e.g. with a
+    table tuned earlier and stored as JSON."""
+    lib = load_library()
+    h = _handle(handle)
+    arr = np.ascontiguousarray(np.asarray(tiles, dtype=np.int32))
+    if arr.shape != (TILE_BUCKETS,):
+        raise ValueError("tile table must have %d entries" % TILE_BUCKETS)
+    st = lib.ipt_batched_set_tiles(h.ptr, arr.ctypes.data_as(C.c_void_p))
+    if st != IPT_OK:
+        raise IPTError(st, h.last_error())
 
 
 # ------------------------------------------------------------------ learned warm start

@@ -4,8 +4,12 @@ Columns both sides mark CONVERGED are compared: |lambda_gpu - lambda_oracle| <=
 lam_tol * |M|_1 and eigenvector angle 2 asin(|a/|a| - b/|b||/2) <= ang_tol (both
 columns have entry idx[c] equal to +1, so there is no sign ambiguity).  Statuses
 must agree, except for columns whose oracle deciding step lies within a factor 4 of
-the tolerance (rounding can move that decision by one sweep); sweep counts may
-differ by one."""
+the tolerance (rounding can move that decision by one sweep), and, when max_iter is
+given, for columns the oracle leaves undecided until the last sweep: there the
+divergence rule's growth count on that sweep decides between DIVERGED and
+NOT_CONVERGED, and on a trajectory that never converges that count depends on the
+rounding order, so either failure status is accepted (never CONVERGED).  Sweep
+counts may differ by one."""
 import numpy as np
 
 LAM_TOL = 1e-10
@@ -19,7 +23,7 @@ def angles(a, b):
 
 
 def check(gpu_z, gpu_lam, gpu_status, ref, norm1, tol, gpu_sweeps=None, lam_tol=LAM_TOL, ang_tol=ANG_TOL,
-          sweep_slack=1, cols=None):
+          sweep_slack=1, cols=None, max_iter=None):
     """gpu_* are numpy arrays restricted to the same columns as ref (an oracle
     Result).  Returns a dict of the worst errors; raises AssertionError on a
     violation."""
@@ -27,6 +31,9 @@ def check(gpu_z, gpu_lam, gpu_status, ref, norm1, tol, gpu_sweeps=None, lam_tol=
     rst = np.asarray(ref.status)
     edge = (ref.step >= tol / 4) & (ref.step <= 4 * tol)
     bad_status = (gst != rst) & ~edge
+    if max_iter is not None:
+        last = (np.asarray(ref.sweeps) >= max_iter) & (rst != 0) & (gst != 0)
+        bad_status &= ~last
     assert not bad_status.any(), "status mismatch in columns %s: gpu %s oracle %s" % (
         np.where(bad_status)[0][:10], gst[bad_status][:10], rst[bad_status][:10])
     both = (gst == 0) & (rst == 0)

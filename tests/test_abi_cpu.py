@@ -53,6 +53,8 @@ def test_null_handle_is_rejected(lib):
     assert l.ipt_create(None, None) == ipt.IPT_EINVAL
     assert l.ipt_solve_dense(None, 4, None, None, 4, 4, None, None, 0, None, None, 4, None, None, None,
                              None) == ipt.IPT_EINVAL
+    assert l.ipt_batched_get_tiles(None, None) == ipt.IPT_EINVAL
+    assert l.ipt_batched_set_tiles(None, None) == ipt.IPT_EINVAL
 
 
 def test_product_path_has_no_oracle_dependency():

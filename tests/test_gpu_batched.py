@@ -45,8 +45,7 @@ def test_batched_small_batch_parity(ipt, prec):
         thb, deb = th[th_off[b]:th_off[b] + n], de[de_off[b]:de_off[b] + n * n].reshape(n, n)
         rr = oracle.ipt_dense(thb, deb, tol=1e-10, max_iter=64)   # per-column steps for the status rule
         np.testing.assert_array_equal(rr.status, rs)
-        out = check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-10,
-                    gpu_sweeps=None)
+        out = check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-10, max_iter=64)
         compared += out["compared"]
     assert compared >= 0.95 * int(ns.sum())
     assert info["converged"] == int((st == 0).sum())
@@ -88,3 +87,110 @@ def test_batched_invalid(ipt):
     with pytest.raises(ipt.IPTError) as e:
         _run(ipt, bad, th, de)
     assert e.value.status == ipt.IPT_EINVAL
+
+
+def _edge_batch(sizes, seed0):
+    th_parts, de_parts = [], []
+    for q, n in enumerate(sizes):
+        thb, deb = W.dense_sym_gaussian(n, 0.01, seed0 + q)
+        th_parts.append(thb)
+        de_parts.append(deb.ravel())
+    ns = np.array(sizes, dtype=np.int32)
+    th_off = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    de_off = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
+    return ns, np.concatenate(th_parts), np.concatenate(de_parts), th_off, de_off
+
+
+def _same(a, b):
+    for x, y in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(x, y)
+    for key in ("sweeps", "converged", "diverged", "not_converged", "matvecs", "max_step", "max_resid",
+                "sweep_prec", "sweep_active", "sweep_max_step"):
+        assert a[3][key] == b[3][key], key
+
+
+def test_batched_graph_replays_match_eager(ipt):
+    """The captured chunk of sweeps, replayed many times per solve and reused across
+    solves, gives the same bits as launching every sweep from the host; a second
+    batch in between forces a new capture."""
+    say("batched graph vs eager")
+    ns, th, de, th_off, de_off = W.batched_sym_gaussian(40, 1, 300, 0.02, seed=5)
+    kw = dict(tol=1e-10, precision=ipt.PREC_LADDER, max_iter=60)
+    eager = _run(ipt, ns, th, de, flags=ipt.FLAG_NO_GRAPH, **kw)
+    g1 = _run(ipt, ns, th, de, **kw)
+    g2 = _run(ipt, ns, th, de, **kw)
+    ns2, th2, de2, _, _ = W.batched_sym_gaussian(7, 100, 200, 0.02, seed=6)
+    _run(ipt, ns2, th2, de2, **kw)
+    g3 = _run(ipt, ns, th, de, **kw)
+    g4 = _run(ipt, ns, th, de, sync_every=3, **kw)
+    e4 = _run(ipt, ns, th, de, sync_every=3, flags=ipt.FLAG_NO_GRAPH, **kw)
+    for g in (g1, g2, g3, g4, e4):
+        _same(eager, g)
+    assert eager[3]["sweeps"] > 4  # several chunks were replayed
+
+
+@pytest.mark.parametrize("tile", [32, 64, 128])
+def test_batched_tile_sizes_parity(ipt, tile):
+    """Every problem forced to one tile size (ragged edges at each) matches the oracle."""
+    say("batched tile %d" % tile)
+    sizes = [1, 3, 31, 32, 33, 64, 65, 96, 129, 200, 257, 333]
+    ns, th, de, th_off, de_off = _edge_batch(sizes, 300)
+    saved = ipt.ipt_batched_get_tiles()
+    try:
+        ipt.ipt_batched_set_tiles([tile] * ipt.TILE_BUCKETS)
+        assert ipt.ipt_batched_get_tiles() == [tile] * ipt.TILE_BUCKETS
+        for prec in (ipt.PREC_LADDER, ipt.PREC_FP64):
+            z, lam, st, info = _run(ipt, ns, th, de, tol=1e-11, precision=prec)
+            assert np.all(st == 0)
+            for b, n in enumerate(sizes):
+                gz, gl, gs = _per_problem(ns, th_off, de_off, z, lam, st, b)
+                thb = th[th_off[b]:th_off[b] + n]
+                deb = de[de_off[b]:de_off[b] + n * n].reshape(n, n)
+                rr = oracle.ipt_dense(thb, deb, tol=1e-11)
+                check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-11)
+    finally:
+        ipt.ipt_batched_set_tiles(saved)
+
+
+def test_batched_max_iter_outputs(ipt):
+    """max_iter = 3: the undecided columns are NOT_CONVERGED and return the last
+    iterate F(Z) with lambda from the input Z of the last sweep, as the oracle does."""
+    say("batched max_iter 3")
+    sizes = [5, 40, 70, 130]
+    ns, th, de, th_off, de_off = _edge_batch(sizes, 400)
+    z, lam, st, info = _run(ipt, ns, th, de, tol=1e-14, max_iter=3)
+    assert info["sweeps"] == 3
+    for b, n in enumerate(sizes):
+        gz, gl, gs = _per_problem(ns, th_off, de_off, z, lam, st, b)
+        thb = th[th_off[b]:th_off[b] + n]
+        deb = de[de_off[b]:de_off[b] + n * n].reshape(n, n)
+        rr = oracle.ipt_dense(thb, deb, tol=1e-14, max_iter=3)
+        np.testing.assert_array_equal(gs, rr.status)
+        nc = rr.status == 1
+        if nc.any():
+            np.testing.assert_allclose(gz[:, nc], rr.z[:, nc], rtol=0, atol=1e-13)
+            np.testing.assert_allclose(gl[nc], rr.lam[nc], rtol=0, atol=1e-13)
+
+
+def test_batched_tune_table(ipt):
+    """The autotuner returns one of 32/64/128 per bucket, installs it, and a solve
+    with the tuned table matches the oracle."""
+    say("batched tune")
+    ns, th, de, th_off, de_off = W.batched_sym_gaussian(24, 1, 400, 0.02, seed=8)
+    saved = ipt.ipt_batched_get_tiles()
+    try:
+        tiles = ipt.ipt_batched_tune(ns, t(th), t(de))
+        assert len(tiles) == ipt.TILE_BUCKETS and set(tiles) <= {32, 64, 128}
+        assert ipt.ipt_batched_get_tiles() == tiles
+        z, lam, st, info = _run(ipt, ns, th, de, tol=1e-10)
+        for b in range(len(ns)):
+            n = int(ns[b])
+            gz, gl, gs = _per_problem(ns, th_off, de_off, z, lam, st, b)
+            thb = th[th_off[b]:th_off[b] + n]
+            deb = de[de_off[b]:de_off[b] + n * n].reshape(n, n)
+            rr = oracle.ipt_dense(thb, deb, tol=1e-10, max_iter=100)
+            check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-10, max_iter=100)
+        with pytest.raises(ipt.IPTError):
+            ipt.ipt_batched_set_tiles([48] * ipt.TILE_BUCKETS)
+    finally:
+        ipt.ipt_batched_set_tiles(saved)
