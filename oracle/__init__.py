@@ -63,6 +63,8 @@ def _load():
                                          p, i64, p, p, p, p, p]
         lib.oracle_ipt_csr.argtypes = [i64, p, p, p, p, i64, p, p, i64, d, C.c_int, d, C.c_int,
                                        p, i64, p, p, p, p, p]
+        lib.oracle_ipt_dense_acx.argtypes = lib.oracle_ipt_dense.argtypes
+        lib.oracle_ipt_csr_acx.argtypes = lib.oracle_ipt_csr.argtypes
         lib.oracle_ipt_trace.argtypes = [i64, p, p, i64, i64, p, C.c_int, p]
         lib.oracle_ipt_map.argtypes = [i64, p, p, i64, i64, p, p]
         lib.oracle_ipt_map.restype = d
@@ -105,11 +107,19 @@ def _finish(rc, z, lam, st, sw, stp, res):
     return Result(z=z, lam=lam, status=st, sweeps=sw, step=stp, resid=res)
 
 
+def _fn(name, accel):
+    if accel not in ("picard", "acx"):
+        raise ValueError("accel must be 'picard' or 'acx'")
+    return getattr(_load(), name + ("_acx" if accel == "acx" else ""))
+
+
 def ipt_dense(theta, delta, idx=None, z0=None, tol=1e-12, max_iter=DEFAULT_MAX_ITER,
-              div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, resid=True) -> Result:
+              div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, resid=True, accel="picard") -> Result:
     """IPT (Alg. 1 per requested column; Alg. 2 when idx covers every index) on a
     dense Delta.  Returns the certified iterate z (entry idx[c] of column c is 1),
-    lambda = theta_i + (Delta z)_i, and the per-column status."""
+    lambda = theta_i + (Delta z)_i, and the per-column status.  accel="acx" replaces
+    the plain update by alternating cyclic extrapolation (Alg. 3); sweeps then
+    counts applications of F."""
     theta = np.ascontiguousarray(theta, dtype=np.float64)
     delta = np.ascontiguousarray(delta, dtype=np.float64)
     n = theta.shape[0]
@@ -123,15 +133,16 @@ def ipt_dense(theta, delta, idx=None, z0=None, tol=1e-12, max_iter=DEFAULT_MAX_I
         assert z0.shape == (n, k)
     z = np.empty((n, k)); lam = np.empty(k); st = np.empty(k, np.int32); sw = np.empty(k, np.int32)
     stp = np.empty(k); res = np.empty(k) if resid else None
-    rc = _load().oracle_ipt_dense(n, _ptr(theta), _ptr(delta), n, k, _ptr(idx), _ptr(z0), k, tol, max_iter,
+    rc = _fn("oracle_ipt_dense", accel)(n, _ptr(theta), _ptr(delta), n, k, _ptr(idx), _ptr(z0), k, tol, max_iter,
                                   div_norm, div_growth, _ptr(z), k, _ptr(lam), _ptr(st), _ptr(sw), _ptr(stp),
                                   _ptr(res))
     return _finish(rc, z, lam, st, sw, stp, res)
 
 
 def ipt_csr(theta, row_ptr, col, val, idx, z0=None, tol=1e-10, max_iter=DEFAULT_MAX_ITER,
-            div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, resid=True) -> Result:
-    """IPT on a CSR Delta for the requested columns (Alg. 1 per column)."""
+            div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, resid=True, accel="picard") -> Result:
+    """IPT on a CSR Delta for the requested columns (Alg. 1 per column; accel as for
+    ipt_dense)."""
     theta = np.ascontiguousarray(theta, dtype=np.float64)
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col = np.ascontiguousarray(col, dtype=np.int32)
@@ -144,7 +155,7 @@ def ipt_csr(theta, row_ptr, col, val, idx, z0=None, tol=1e-10, max_iter=DEFAULT_
         assert z0.shape == (n, k)
     z = np.empty((n, k)); lam = np.empty(k); st = np.empty(k, np.int32); sw = np.empty(k, np.int32)
     stp = np.empty(k); res = np.empty(k) if resid else None
-    rc = _load().oracle_ipt_csr(n, _ptr(theta), _ptr(row_ptr), _ptr(col), _ptr(val), k, _ptr(idx), _ptr(z0), k,
+    rc = _fn("oracle_ipt_csr", accel)(n, _ptr(theta), _ptr(row_ptr), _ptr(col), _ptr(val), k, _ptr(idx), _ptr(z0), k,
                                 tol, max_iter, div_norm, div_growth, _ptr(z), k, _ptr(lam), _ptr(st), _ptr(sw),
                                 _ptr(stp), _ptr(res))
     return _finish(rc, z, lam, st, sw, stp, res)
@@ -174,9 +185,19 @@ def ipt_map(theta, delta, i, z):
 
 
 def ipt_batched(ns, theta_pool, delta_pool, theta_off, delta_off, tol=1e-10, max_iter=64,
-                div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH):
+                div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, accel="picard"):
     """Independent dense full-spectrum IPT solves over a packed batch.  z of problem
     b is returned row-major at z_pool[delta_off[b]:][:n_b*n_b]."""
+    if accel != "picard":
+        ns = np.asarray(ns)
+        z = np.empty(np.asarray(delta_pool).shape[0]); lam = np.empty(np.asarray(theta_pool).shape[0])
+        st = np.empty(lam.shape[0], np.int32); sw = np.empty(lam.shape[0], np.int32)
+        for b in range(ns.shape[0]):
+            n, to, do = int(ns[b]), int(theta_off[b]), int(delta_off[b])
+            r = ipt_dense(theta_pool[to:to + n], np.asarray(delta_pool[do:do + n * n]).reshape(n, n), tol=tol,
+                          max_iter=max_iter, div_norm=div_norm, div_growth=div_growth, resid=False, accel=accel)
+            z[do:do + n * n] = r.z.ravel(); lam[to:to + n] = r.lam; st[to:to + n] = r.status; sw[to:to + n] = r.sweeps
+        return Result(z=z, lam=lam, status=st, sweeps=sw, step=None, resid=None)
     ns = np.ascontiguousarray(ns, dtype=np.int32)
     theta_off = np.ascontiguousarray(theta_off, dtype=np.int64)
     delta_off = np.ascontiguousarray(delta_off, dtype=np.int64)

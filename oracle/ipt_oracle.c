@@ -149,6 +149,100 @@ static void solve_column(const op_t *A, const double *theta, int64_t i, double t
     *step = s;
 }
 
+/* IPT-ACX for one column: Alg. 1 with its update replaced by alternating cyclic
+ * extrapolation (Alg. 3), orders 3, 2, 3, 2, ...  Each extrapolation cycle of order
+ * p takes F(z), ..., F^p(z) and moves to
+ *     z + sum_{q=1..p} binom(p, q) sigma^q D^q,
+ *     D^q = q-th forward difference (D^1 = F(z) - z, D^2 = F^2(z) - 2F(z) + z,
+ *           D^3 = F^3(z) - 3F^2(z) + 3F(z) - z),
+ *     sigma = |<D^p, D^(p-1)>| / |D^p|^2.
+ * Readings of the printed listing (whose update line omits the leading z term and
+ * whose sigma has an unsquared norm): with these, sigma = 1 gives F^p(z) and an
+ * affine map x -> r x + b with r < 1 reaches its fixed point in one cycle.  When
+ * |D^p| = 0, sigma = 1.  The stopping and divergence tests of Alg. 1 are made on
+ * the first application of each cycle (the listing's loop test), with growth
+ * counted from cycle to cycle; max_iter bounds the applications of F, and a cycle
+ * that the remaining budget cannot finish ends the column as NOT_CONVERGED with
+ * F(z) returned.  Returned values otherwise as in solve_column. */
+static void solve_column_acx(const op_t *A, const double *theta, int64_t i, double tol, int max_iter,
+                             double div_norm, int div_growth, double *z, double *g, double *y, double *f1,
+                             double *f2, double *f3, double *lambda, int32_t *status, int32_t *sweeps,
+                             double *step) {
+    const int64_t n = A->n;
+    inverse_gaps(n, theta, i, g);
+    z[i] = 1.0;
+    double prev_s = INFINITY, s = INFINITY, d = 0.0;
+    int grow = 0, used = 0;
+    for (int cycle = 0;; ++cycle) {
+        const int p = (cycle % 2 == 0) ? 3 : 2;
+        d = map_once(A, theta, i, g, z, y, f1);
+        ++used;
+        double num = 0.0, den = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double e = f1[j] - z[j];
+            num += e * e;
+            den += z[j] * z[j];
+        }
+        s = sqrt(num) / sqrt(den);
+        if (s <= tol) {
+            *lambda = theta[i] + d;
+            *status = OR_CONVERGED;
+            *sweeps = used;
+            *step = s;
+            return;
+        }
+        int finite = isfinite(s);
+        double dist2 = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double e = f1[j] - (j == i ? 1.0 : 0.0);
+            if (!isfinite(f1[j])) finite = 0;
+            dist2 += e * e;
+        }
+        grow = (s > prev_s) ? grow + 1 : 0;
+        prev_s = s;
+        const int diverged = !finite || !(sqrt(dist2) <= div_norm) || grow >= div_growth;
+        if (diverged || used + (p - 1) > max_iter) {
+            memcpy(z, f1, (size_t)n * sizeof(double));
+            *lambda = theta[i] + d;
+            *status = diverged ? OR_DIVERGED : OR_NOT_CONVERGED;
+            *sweeps = used;
+            *step = s;
+            return;
+        }
+        map_once(A, theta, i, g, f1, y, f2);
+        ++used;
+        if (p == 3) {
+            map_once(A, theta, i, g, f2, y, f3);
+            ++used;
+        }
+        /* sigma from the two highest differences, summed in ascending j */
+        double dot = 0.0, nrm = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double d1 = f1[j] - z[j];
+            const double d2 = (f2[j] - 2.0 * f1[j]) + z[j];
+            if (p == 2) {
+                dot += d2 * d1;
+                nrm += d2 * d2;
+            } else {
+                const double d3 = ((f3[j] - 3.0 * f2[j]) + 3.0 * f1[j]) - z[j];
+                dot += d3 * d2;
+                nrm += d3 * d3;
+            }
+        }
+        const double sg = (nrm > 0.0) ? fabs(dot) / nrm : 1.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double d1 = f1[j] - z[j];
+            const double d2 = (f2[j] - 2.0 * f1[j]) + z[j];
+            if (p == 2) {
+                z[j] = (z[j] + 2.0 * sg * d1) + (sg * sg) * d2;
+            } else {
+                const double d3 = ((f3[j] - 3.0 * f2[j]) + 3.0 * f1[j]) - z[j];
+                z[j] = ((z[j] + 3.0 * sg * d1) + 3.0 * (sg * sg) * d2) + (sg * sg * sg) * d3;
+            }
+        }
+    }
+}
+
 /* rho = |M z - lambda z|_2 / |z|_2 with M z = theta o z + Delta z (plain definition). */
 static double eigen_residual(const op_t *A, const double *theta, const double *z, double lambda, double *y) {
     const int64_t n = A->n;
@@ -165,24 +259,29 @@ static double eigen_residual(const op_t *A, const double *theta, const double *z
 static int solve_columns(const op_t *A, const double *theta, int64_t k, const int32_t *idx,
                          const double *z0, int64_t ldz0, double tol, int max_iter, double div_norm,
                          int div_growth, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
-                         int32_t *sweeps_out, double *step_out, double *resid_out) {
+                         int32_t *sweeps_out, double *step_out, double *resid_out, int acx) {
     const int64_t n = A->n;
     int fail = 0;
 #pragma omp parallel
     {
-        double *buf = (double *)malloc((size_t)n * 4 * sizeof(double));
+        double *buf = (double *)malloc((size_t)n * 6 * sizeof(double));
         if (!buf) {
 #pragma omp atomic write
             fail = 1;
         } else {
-            double *z = buf, *g = buf + n, *y = buf + 2 * n, *w = buf + 3 * n;
+            double *z = buf, *g = buf + n, *y = buf + 2 * n, *w = buf + 3 * n, *w2 = buf + 4 * n, *w3 = buf + 5 * n;
 #pragma omp for schedule(dynamic, 1)
             for (int64_t c = 0; c < k; ++c) {
                 const int64_t i = idx ? idx[c] : c;
                 for (int64_t j = 0; j < n; ++j) z[j] = z0 ? z0[j * ldz0 + c] : (j == i ? 1.0 : 0.0);
                 double lam, st;
                 int32_t stat, sw;
-                solve_column(A, theta, i, tol, max_iter, div_norm, div_growth, z, g, y, w, &lam, &stat, &sw, &st);
+                if (acx)
+                    solve_column_acx(A, theta, i, tol, max_iter, div_norm, div_growth, z, g, y, w, w2, w3, &lam,
+                                     &stat, &sw, &st);
+                else
+                    solve_column(A, theta, i, tol, max_iter, div_norm, div_growth, z, g, y, w, &lam, &stat, &sw,
+                                 &st);
                 for (int64_t j = 0; j < n; ++j) z_out[j * ldz + c] = z[j];
                 lambda_out[c] = lam;
                 status_out[c] = stat;
@@ -224,7 +323,18 @@ int oracle_ipt_dense(int64_t n, const double *theta, const double *delta, int64_
                      int32_t *status_out, int32_t *sweeps_out, double *step_out, double *resid_out) {
     op_t A = {n, delta, lda, NULL, NULL, NULL};
     return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
-                         lambda_out, status_out, sweeps_out, step_out, resid_out);
+                         lambda_out, status_out, sweeps_out, step_out, resid_out, 0);
+}
+
+/* IPT-ACX (Alg. 3 in place of the plain update), otherwise as oracle_ipt_dense;
+ * sweeps_out counts applications of F. */
+int oracle_ipt_dense_acx(int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                         const int32_t *idx, const double *z0, int64_t ldz0, double tol, int max_iter,
+                         double div_norm, int div_growth, double *z_out, int64_t ldz, double *lambda_out,
+                         int32_t *status_out, int32_t *sweeps_out, double *step_out, double *resid_out) {
+    op_t A = {n, delta, lda, NULL, NULL, NULL};
+    return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
+                         lambda_out, status_out, sweeps_out, step_out, resid_out, 1);
 }
 
 /* Same with a CSR Delta (row_ptr[n+1], col[nnz], val[nnz]). */
@@ -235,7 +345,18 @@ int oracle_ipt_csr(int64_t n, const double *theta, const int32_t *row_ptr, const
                    double *resid_out) {
     op_t A = {n, NULL, 0, row_ptr, col, val};
     return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
-                         lambda_out, status_out, sweeps_out, step_out, resid_out);
+                         lambda_out, status_out, sweeps_out, step_out, resid_out, 0);
+}
+
+/* IPT-ACX with a CSR Delta. */
+int oracle_ipt_csr_acx(int64_t n, const double *theta, const int32_t *row_ptr, const int32_t *col,
+                       const double *val, int64_t k, const int32_t *idx, const double *z0, int64_t ldz0,
+                       double tol, int max_iter, double div_norm, int div_growth, double *z_out, int64_t ldz,
+                       double *lambda_out, int32_t *status_out, int32_t *sweeps_out, double *step_out,
+                       double *resid_out) {
+    op_t A = {n, NULL, 0, row_ptr, col, val};
+    return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
+                         lambda_out, status_out, sweeps_out, step_out, resid_out, 1);
 }
 
 /* The iterates z^(0..t) of f_i from a start z (no stopping test): out is

@@ -24,6 +24,14 @@ MUTANTS = {
     "lambda_without_theta": ("*lambda = theta[i] + d;\n            *status = OR_CONVERGED;",
                              "*lambda = d;\n            *status = OR_CONVERGED;"),
     "step_not_relative": ("s = sqrt(num) / sqrt(den);", "s = sqrt(num);"),
+    # IPT-ACX (Alg. 3)
+    "acx_sigma_unsquared": ("fabs(dot) / nrm : 1.0", "fabs(dot) / sqrt(nrm) : 1.0"),
+    "acx_orders_swapped": ("(cycle % 2 == 0) ? 3 : 2", "(cycle % 2 == 0) ? 2 : 3"),
+    "acx_order2_without_z": ("z[j] = (z[j] + 2.0 * sg * d1) + (sg * sg) * d2;",
+                             "z[j] = (2.0 * sg * d1) + (sg * sg) * d2;"),
+    "acx_order3_binomial": ("3.0 * (sg * sg) * d2) + (sg * sg * sg) * d3", "(sg * sg) * d2) + (sg * sg * sg) * d3"),
+    "acx_second_difference": ("const double d2 = (f2[j] - 2.0 * f1[j]) + z[j];\n            if (p == 2) {\n                dot",
+                              "const double d2 = (f2[j] - f1[j]) + z[j];\n            if (p == 2) {\n                dot"),
 }
 
 
@@ -64,6 +72,18 @@ def _pins_pass():
     tr = oracle.ipt_trace(th, de, 0, t)
     want = np.linalg.norm(tr[t] - tr[t - 1]) / np.linalg.norm(tr[t - 1])
     ok &= bool(r.status[0] == oracle.CONVERGED and abs(r.step[0] - want) <= 1e-12 * want)
+    # IPT-ACX on affine maps (closed forms of the extrapolation, see test_oracle_acx)
+    from test_oracle_acx import affine_case
+    th, de, zs = affine_case(0.95)
+    r = oracle.ipt_dense(th, de, idx=np.array([0], np.int32), tol=1e-10, max_iter=100, accel="acx")
+    ok &= bool(r.status[0] == oracle.CONVERGED and r.sweeps[0] == 4 and np.max(np.abs(r.z[:, 0] - zs)) < 2e-11)
+    th, de, zs = affine_case(1.5)
+    e0 = 1e-3 * np.random.default_rng(1).standard_normal(6)
+    e0[0] = 0.0
+    for mi, fac in ((4, 12.0), (6, 48.0)):
+        r = oracle.ipt_dense(th, de, idx=np.array([0], np.int32), z0=(zs + e0).reshape(6, 1), tol=1e-12,
+                             max_iter=mi, accel="acx")
+        ok &= bool(r.sweeps[0] == mi and np.max(np.abs(r.z[:, 0] - (zs + fac * e0))) < 1e-12)
     return ok
 
 
