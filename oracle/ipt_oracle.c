@@ -161,9 +161,11 @@ static void solve_column(const op_t *A, const double *theta, int64_t i, double t
  * affine map x -> r x + b with r < 1 reaches its fixed point in one cycle.  When
  * |D^p| = 0, sigma = 1.  The stopping and divergence tests of Alg. 1 are made on
  * the first application of each cycle (the listing's loop test), with growth
- * counted from cycle to cycle; max_iter bounds the applications of F, and a cycle
- * that the remaining budget cannot finish ends the column as NOT_CONVERGED with
- * F(z) returned.  Returned values otherwise as in solve_column. */
+ * counted from cycle to cycle.  max_iter bounds the applications of F: a test at
+ * application u whose cycle could not be followed by another test within the
+ * budget (u + p > max_iter) ends the column as NOT_CONVERGED with F(z) returned --
+ * for p = 1 this is the plain rule u = max_iter.  Returned values otherwise as in
+ * solve_column. */
 static void solve_column_acx(const op_t *A, const double *theta, int64_t i, double tol, int max_iter,
                              double div_norm, int div_growth, double *z, double *g, double *y, double *f1,
                              double *f2, double *f3, double *lambda, int32_t *status, int32_t *sweeps,
@@ -201,7 +203,7 @@ static void solve_column_acx(const op_t *A, const double *theta, int64_t i, doub
         grow = (s > prev_s) ? grow + 1 : 0;
         prev_s = s;
         const int diverged = !finite || !(sqrt(dist2) <= div_norm) || grow >= div_growth;
-        if (diverged || used + (p - 1) > max_iter) {
+        if (diverged || used + p > max_iter) {
             memcpy(z, f1, (size_t)n * sizeof(double));
             *lambda = theta[i] + d;
             *status = diverged ? OR_DIVERGED : OR_NOT_CONVERGED;

@@ -50,20 +50,22 @@ def test_acx_solves_a_contracting_affine_map_in_one_cycle():
     assert p.status[0] == oracle.NOT_CONVERGED
 
 
-@pytest.mark.parametrize("max_iter,factor", [(4, 8 * 1.5), (6, 8 * 4 * 1.5)])
-def test_acx_cycle_factors_on_a_repelling_affine_map(max_iter, factor):
+@pytest.mark.parametrize("max_iter,factor,used", [(4, 8 * 1.5, 4), (5, 8 * 1.5, 4), (6, 32 * 1.5, 6),
+                                                  (8, 32 * 1.5, 6), (9, 256 * 1.5, 9)])
+def test_acx_cycle_factors_on_a_repelling_affine_map(max_iter, factor, used):
     """For x -> r x + b with r > 1, sigma = 1/(r - 1) and a cycle of order p maps the
     error e to (1 + 1)^p e: 8 e for p = 3, 4 e for p = 2.  From z* + e0 the orders run
-    3, 2, 3: after 4 applications the budget cannot finish the order-2 cycle, so the
-    column ends NOT_CONVERGED returning F(z* + 8 e0) = z* + 12 e0; after 6 it returns
-    F(z* + 32 e0) = z* + 48 e0."""
+    3, 2, 3, 2 with tests at applications 1, 4, 6, 9.  A test whose cycle could not be
+    followed by another test within max_iter ends the column NOT_CONVERGED with F(z):
+    F(z* + 8 e0) = z* + 12 e0 at application 4 (max_iter 4 or 5), F(z* + 32 e0) at 6
+    (max_iter 6 to 8), F(z* + 256 e0) at 9; no application runs past max_iter."""
     th, de, zs = affine_case(1.5)
     rng = np.random.default_rng(1)
     e0 = 1e-3 * rng.standard_normal(6)
     e0[0] = 0.0
     z0 = (zs + e0).reshape(6, 1)
     r = oracle.ipt_dense(th, de, idx=np.array([0], np.int32), z0=z0, tol=1e-12, max_iter=max_iter, accel="acx")
-    assert r.status[0] == oracle.NOT_CONVERGED and r.sweeps[0] == max_iter
+    assert r.status[0] == oracle.NOT_CONVERGED and r.sweeps[0] == used
     np.testing.assert_allclose(r.z[:, 0], zs + factor * e0, rtol=0, atol=1e-12)
 
 
