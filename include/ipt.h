@@ -85,6 +85,16 @@ typedef struct ipt_opts {
 /* Batched solves: launch every sweep from the host instead of replaying the captured
  * hipGraph of a chunk of sweeps (the results are the same, bit for bit). */
 #define IPT_FLAG_NO_GRAPH 4
+/* IPT-ACX (Sec. 5, Alg. 3): replace the plain update by alternating cyclic
+ * extrapolation with orders 3, 2, 3, 2, ...: a cycle of order p applies F p times
+ * (F(z), ..., F^p(z)) and moves each active column to
+ *   z + sum_{q=1..p} binom(p, q) sigma^q D^q,  sigma = |<D^p, D^(p-1)>| / |D^p|^2,
+ * D^q the q-th forward difference of the iterates (sigma = 1 when D^p = 0).  The
+ * stopping and divergence tests run on the first application of each cycle; a
+ * test whose cycle could not be followed by another test within max_iter ends the
+ * column NOT_CONVERGED.  Sweeps then count applications of F.  Requires
+ * precision = IPT_PREC_FP64 (every application is an FP64 sweep). */
+#define IPT_FLAG_ACX 8
 #define IPT_HIST 128
 
 /* Host struct filled by a solve (may be NULL). */

@@ -104,6 +104,8 @@ ipt_status check_opts(ipt_handle h, const ipt_opts *in, ipt_opts &o) {
     if (!(o.div_norm > 0.0)) return fail(h, IPT_EINVAL, "opts.div_norm must be > 0");
     if (o.div_growth < 1) return fail(h, IPT_EINVAL, "opts.div_growth must be >= 1");
     if (!(o.tau_low >= 0.0) || !(o.tau_32 >= 0.0)) return fail(h, IPT_EINVAL, "opts.tau_low/tau_32 must be >= 0");
+    if ((o.flags & IPT_FLAG_ACX) && o.precision != IPT_PREC_FP64)
+        return fail(h, IPT_EINVAL, "IPT_FLAG_ACX runs FP64 sweeps: set precision = IPT_PREC_FP64");
     return IPT_OK;
 }
 
@@ -119,6 +121,7 @@ DevOpts dev_opts(const ipt_opts &o) {
     d.ladder = o.precision == IPT_PREC_LADDER;
     d.low_type = o.low_type;
     d.first_product = 0;
+    d.acx = (o.flags & IPT_FLAG_ACX) ? 1 : 0;
     return d;
 }
 
@@ -578,10 +581,16 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     const bool use_low = ladder && o.low_type != IPT_LOW_NONE;
 
     // Workspace layout (sizes first, then carve).
+    const bool acx = dopt.acx != 0;
+    double *acx_part = nullptr, *acx_sigma = nullptr;
     auto layout = [&](Carve &cv, double **zb, ColState &cs, double **dpart, double **dvec, double **part, uint32_t **bitmap,
                       double **scratch, double **dpad, void **dlo, float **d32, void **zt, Ctrl **ctrl) {
         zb[0] = cv.take<double>(np * kp);
         zb[1] = cv.take<double>(np * kp);
+        zb[2] = acx ? cv.take<double>(np * kp) : nullptr;
+        zb[3] = acx ? cv.take<double>(np * kp) : nullptr;
+        acx_part = acx ? cv.take<double>((size_t)acx_splits(n) * kp * 2) : nullptr;
+        acx_sigma = acx ? cv.take<double>(kp) : nullptr;
         *dpart = cv.take<double>(DIAG_SPLIT * kp);
         *dvec = cv.take<double>(kp);
         *part = cv.take<double>(nrt * kp * NPART);
@@ -603,7 +612,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         *zt = ladder ? (void *)cv.take<float>(kp * np) : nullptr;
         *ctrl = cv.take<Ctrl>(1);
     };
-    double *zb[2];
+    double *zb[4];
     ColState cs;
     double *dpart, *dvec, *part, *scratch, *dpad;
     uint32_t *bitmap;
@@ -630,19 +639,25 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         IPT_HIP(h, launch_prep_delta(s, ctrl, theta, delta, lda, n, np, direct ? nullptr : dpad,
                                      use_low ? dlo : nullptr, lt, ladder ? d32 : nullptr, norm ? scratch : nullptr));
     const bool padded = (np != n) || (kp != k);
-    if (cold) {
+    if (cold && !acx) {
         if (padded) IPT_HIP(h, launch_zero_pad(s, zb[0], kp, n, np, k, kp));
     } else {
+        // warm start, or the base iterate E of the first ACX cycle
         IPT_HIP(h, launch_load_z0(s, ctrl, z0, ldz0, zb[0], kp, cs.idx, n, np, k, kp));
-        if (padded) IPT_HIP(h, launch_zero_pad(s, zb[1], kp, n, np, k, kp));
+        if (padded)
+            for (int q = 1; q < (acx ? 4 : 2); ++q) IPT_HIP(h, launch_zero_pad(s, zb[q], kp, n, np, k, kp));
     }
 
     const PollPlan plan = poll_plan(o, cold);
     for (int32_t t = 1; t <= o.max_iter; ++t) {
         const bool first_exact = cold && t == 1;
-        const int32_t in_par = first_exact ? PAR_UNIT : ((t - 1) & 1);
-        const int32_t out_par = t & 1;
-        double *zin = zb[(t - 1) & 1], *zout = zb[t & 1];
+        // Plain sweeps ping-pong between two buffers; an ACX cycle runs slot q -> q + 1
+        // from its base iterate in slot 0 and extrapolates back into slot 0.
+        int32_t q, pc;
+        acx_phase(dopt.acx, t, q, pc);
+        const int32_t in_par = first_exact ? PAR_UNIT : (acx ? PAR_BUF0 : ((t - 1) & 1));
+        const int32_t out_par = acx ? PAR_BUF1 : (t & 1);
+        double *zin = acx ? zb[q] : zb[(t - 1) & 1], *zout = acx ? zb[q + 1] : zb[t & 1];
         if (first_exact) {
             IPT_HIP(h, timer.mark(t, 0, s));
             IPT_HIP(h, launch_sweep1_dense(s, ctrl, theta, dA, ldA, cs, dvec, zout, kp, part, n, np, kp));
@@ -657,6 +672,8 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         }
         IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, nrt, kp, t, in_par, out_par));
         IPT_HIP(h, launch_control(s, ctrl, dopt, t));
+        if (acx && q == pc - 1)
+            IPT_HIP(h, launch_acx(s, ctrl, cs.state, zb[0], zb[1], zb[2], zb[3], kp, n, kp, pc, acx_part, acx_sigma));
         if (plan.at(t, o.max_iter)) {
             int32_t err, done;
             if (ipt_status st = poll_ctrl(h, ctrl, err, done)) return st;
@@ -694,10 +711,16 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     const int64_t kpc = round_up(k, 64);   // column-state and partial-sum layout
     const int64_t ldzb = round_up(k, 2);   // Z buffers: n x ldzb
     const int64_t nrt = spmm_row_tiles(n);
+    const bool acx = dopt.acx != 0;
+    double *acx_part = nullptr, *acx_sigma = nullptr;
     auto layout = [&](Carve &cv, double **zb, float **zlo, ColState &cs, double **dvec, double **part,
                       uint32_t **bitmap, double **scratch, float **val32, Ctrl **ctrl) {
         zb[0] = cv.take<double>(n * ldzb);
         zb[1] = cv.take<double>(n * ldzb);
+        zb[2] = acx ? cv.take<double>(n * ldzb) : nullptr;
+        zb[3] = acx ? cv.take<double>(n * ldzb) : nullptr;
+        acx_part = acx ? cv.take<double>((size_t)acx_splits(n) * kpc * 2) : nullptr;
+        acx_sigma = acx ? cv.take<double>(kpc) : nullptr;
         zlo[0] = ladder ? cv.take<float>(n * ldzb) : nullptr;
         zlo[1] = ladder ? cv.take<float>(n * ldzb) : nullptr;
         *dvec = cv.take<double>(kpc);
@@ -717,7 +740,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         *val32 = (ladder && nnz > 0) ? cv.take<float>(nnz) : nullptr;
         *ctrl = cv.take<Ctrl>(1);
     };
-    double *zb[2], *dvec, *part, *scratch;
+    double *zb[4], *dvec, *part, *scratch;
     float *zlo[2], *val32;
     ColState cs;
     uint32_t *bitmap;
@@ -745,16 +768,19 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         if (cold) IPT_HIP(h, launch_fill_f32(s, zlo[0], n * ldzb));
         else IPT_HIP(h, launch_zlo_init(s, zb[0], zlo[0], ldzb, cs.idx, n, k));
     }
-    if (ldzb != k) {  // padding column of the second buffer
-        IPT_HIP(h, launch_load_z0(s, ctrl, nullptr, 0, zb[1], ldzb, cs.idx, n, n, k, ldzb));
+    if (ldzb != k) {  // padding column of the other buffers
+        for (int q = 1; q < (acx ? 4 : 2); ++q)
+            IPT_HIP(h, launch_load_z0(s, ctrl, nullptr, 0, zb[q], ldzb, cs.idx, n, n, k, ldzb));
         if (ladder) IPT_HIP(h, launch_fill_f32(s, zlo[1], n * ldzb));
     }
 
     PollPlan plan = poll_plan(o, cold);
     if (o.sync_every <= 0) plan.first = cold ? 3 : 2;  // sparse near-diagonal solves take few sweeps
     for (int32_t t = 1; t <= o.max_iter; ++t) {
-        const int32_t in_par = (t - 1) & 1, out_par = t & 1;
-        double *zin = zb[(t - 1) & 1], *zout = zb[t & 1];
+        int32_t q, pc;
+        acx_phase(dopt.acx, t, q, pc);
+        const int32_t in_par = acx ? PAR_BUF0 : ((t - 1) & 1), out_par = acx ? PAR_BUF1 : (t & 1);
+        double *zin = acx ? zb[q] : zb[(t - 1) & 1], *zout = acx ? zb[q + 1] : zb[t & 1];
         IPT_HIP(h, launch_diag_csr(s, ctrl, row_ptr, col, val, zin, ldzb, cs, dvec, k));
         IPT_HIP(h, timer.mark(t, 0, s));
         IPT_HIP(h, launch_spmm_sweep(s, ctrl, row_ptr, col, val, val32, theta, zin, zout,
@@ -764,6 +790,8 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         IPT_HIP(h, launch_reduce_parts(s, ctrl, cs, part, nrt, kpc));
         IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, 1, kpc, t, in_par, out_par));
         IPT_HIP(h, launch_control(s, ctrl, dopt, t));
+        if (acx && q == pc - 1)
+            IPT_HIP(h, launch_acx(s, ctrl, cs.state, zb[0], zb[1], zb[2], zb[3], ldzb, n, k, pc, acx_part, acx_sigma));
         if (plan.at(t, o.max_iter)) {
             int32_t err, done;
             if (ipt_status st = poll_ctrl(h, ctrl, err, done)) return st;

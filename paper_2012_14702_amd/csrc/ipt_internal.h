@@ -53,7 +53,22 @@ struct DevOpts {
     double tol, tau_low, tau_32, div_norm;
     int32_t max_iter, div_growth, ladder, low_type;
     int32_t first_product;  // the first sweep of a cold start multiplies by Delta (sparse path)
+    int32_t acx;            // IPT-ACX cycles (orders 3, 2, 3, 2, ...)
 };
+
+// IPT-ACX schedule: sweep t (1-based) is application q (0-based) of a cycle of
+// order p; the orders alternate 3, 2, so the pattern repeats every 5 sweeps.
+// Without ACX every sweep is a cycle of order 1.
+__host__ __device__ inline void acx_phase(int32_t acx, int32_t t, int32_t &q, int32_t &p) {
+    if (!acx) {
+        q = 0;
+        p = 1;
+        return;
+    }
+    const int32_t r = (t - 1) % 5;
+    q = r < 3 ? r : r - 3;
+    p = r < 3 ? 3 : 2;
+}
 
 // Per-column state arrays (length kp).
 struct ColState {
@@ -195,6 +210,15 @@ hipError_t mlp_targets(hipStream_t s, const double *z, int32_t batch, int64_t n,
 hipError_t mlp_warm_start(hipStream_t s, const float *y, int64_t ldy, const float *mu, const float *sigma,
                           const double *scale, int64_t n, int64_t k, const int32_t *idx, double *z0, int64_t ldz0,
                           int64_t pstride, int32_t count);
+
+// IPT-ACX extrapolation over row-major iterate slots z, f1, f2, f3 (n rows, leading
+// dimension ld, kc columns with states `state`) after a cycle of order p
+// (ipt_acx.hip): per-column dot and squared norm of the two highest differences in
+// row-range partials, sigma, and the in-place update of z for the active columns.
+int acx_splits(int64_t n);
+hipError_t launch_acx(hipStream_t s, const Ctrl *ctrl, const int32_t *state, double *z, const double *f1,
+                      const double *f2, const double *f3, int64_t ld, int64_t n, int64_t kc, int32_t p, double *part,
+                      double *sigma);
 
 // The product and fused epilogue of one sweep (ipt_gemm.hip), in the precision the
 // device-side ladder chose (ctrl->prec).

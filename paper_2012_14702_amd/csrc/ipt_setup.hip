@@ -369,7 +369,15 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
     int32_t decided = -1;
     double s = 0.0;
     uint64_t res_bits = 0;
-    if (act) {
+    // IPT-ACX: only the first application of a cycle is tested; the budget rule ends
+    // a column whose cycle could not be followed by another test within max_iter
+    // (with plain sweeps, p = 1: the last sweep).
+    int32_t q, pc;
+    acx_phase(o.acx, sweep, q, pc);
+    if (act && q != 0) {
+        s = sqrt(p[0]) / sqrt(p[1]);
+        cs.tile_stamp[c / TILE_N] = sweep;
+    } else if (act) {
         const double d = dvec[c];
         s = sqrt(p[0]) / sqrt(p[1]);
         const int32_t prec = ctrl->prec;
@@ -393,7 +401,7 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
             if (bad || grow >= o.div_growth) {
                 decided = COL_DIVERGED;
                 par = out_par;
-            } else if (sweep >= o.max_iter) {
+            } else if (sweep + pc > o.max_iter) {
                 decided = COL_NOT_CONVERGED;
                 par = out_par;
             }

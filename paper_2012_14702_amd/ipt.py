@@ -21,6 +21,7 @@ IPT_HIST = 128
 FLAG_NO_NORM = 1
 FLAG_TIME_KERNELS = 2
 FLAG_NO_GRAPH = 4
+FLAG_ACX = 8
 TILE_BUCKETS = 64  # batched tile table: bucket q holds 64 q < n <= 64 (q + 1)
 
 
