@@ -171,7 +171,7 @@ def bench_batched(ipt, handle, args):
     st_out = torch.empty(thd.shape[0], dtype=torch.int32, device=dev)
     res = {}
     modes = (("ladder", ipt.PREC_LADDER, 0), ("ladder_no_graph", ipt.PREC_LADDER, ipt.FLAG_NO_GRAPH),
-             ("fp64", ipt.PREC_FP64, 0))
+             ("fp64", ipt.PREC_FP64, 0), ("acx", ipt.PREC_FP64, ipt.FLAG_ACX))
     for name, prec, flags in modes:
         if args.batched_modes and name not in args.batched_modes.split(","):
             continue
@@ -194,6 +194,34 @@ def bench_batched(ipt, handle, args):
                     "tune_s": round(t_tune, 3)}
     return {"workload": "batched %d problems n~U{32..512}, theta=sort(U(0,n)), Delta=0.02*sym N(0,1/n), "
                         "full spectra, tol 1e-10, max 64 sweeps" % B, "eigenpairs": int(ns.sum()), "modes": res}
+
+
+def bench_morgan(ipt, handle, args):
+    """Morgan's tridiagonal matrix (n = 5000, theta_i = i, off-diagonals 0.5; Sec. 6.1),
+    the k lowest eigenpairs for k = 1 and 50, tol 1e-12: plain IPT vs IPT-ACX on the
+    sparse path (FP64 SpMM sweeps)."""
+    import numpy as np
+    import torch
+    import workloads
+    dev = torch.device("cuda:0")
+    th, rp, col, val = workloads.morgan_tridiagonal(5000, 0.5)
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    thd, rpd, cold, vald = tt(th), tt(rp), tt(col), tt(val)
+    res = {}
+    for k in (1, 50):
+        idx = tt(np.arange(k, dtype=np.int32))
+        for name, flags in (("plain", 0), ("acx", ipt.FLAG_ACX)):
+            o = ipt.default_opts(tol=1e-12, precision=ipt.PREC_FP64, max_iter=2000, flags=flags)
+            run = lambda: ipt.ipt_solve_csr(thd, rpd, cold, vald, idx, opts=o, handle=handle)
+            _time(run, 1)
+            sec, r = _time(run, 5)
+            inf = r.info
+            res["k%d_%s" % (k, name)] = {"ms_per_solve": round(sec * 1e3, 3), "converged": inf["converged"],
+                                         "sweeps": inf["sweeps"], "matvecs": inf["matvecs"],
+                                         "eigenpairs_per_s": round(inf["converged"] / sec, 1)}
+            log("morgan k=%d %s: %.3f ms/solve, %d/%d converged, %d sweeps, %d matvecs" % (
+                k, name, sec * 1e3, inf["converged"], k, inf["sweeps"], inf["matvecs"]))
+    return {"workload": "Morgan tridiagonal n=5000, off-diagonal 0.5, k lowest, tol 1e-12", "modes": res}
 
 
 def bench_learned(ipt, handle, args):
@@ -270,7 +298,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "ladder", "fp64"], default="all",
                     help="restrict the dense workload to one mode (for profiler runs)")
-    ap.add_argument("--extra", default="sparse,batched,learned",
+    ap.add_argument("--extra", default="sparse,morgan,batched,learned",
                     help="comma list of secondary workloads to time: sparse, batched, learned ('' for none)")
     ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the warm-start network")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense workload (profiling of the others)")
@@ -308,7 +336,8 @@ def main():
     if args.no_dense:
         extras = [e for e in args.extra.split(",") if e]
         out = {}
-        for name, fn in (("sparse", bench_sparse), ("batched", bench_batched), ("learned", bench_learned)):
+        for name, fn in (("sparse", bench_sparse), ("morgan", bench_morgan), ("batched", bench_batched),
+                         ("learned", bench_learned)):
             if name in extras:
                 out[name] = fn(ipt, handle, args)
         print(json.dumps(out), flush=True)
@@ -400,6 +429,8 @@ def main():
     extras = [e for e in args.extra.split(",") if e]
     if "sparse" in extras:
         out["sparse"] = bench_sparse(ipt, handle, args)
+    if "morgan" in extras:
+        out["morgan"] = bench_morgan(ipt, handle, args)
     if "batched" in extras:
         out["batched"] = bench_batched(ipt, handle, args)
     if "learned" in extras:

@@ -288,7 +288,7 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
         return fail(h, IPT_EINVAL, "NULL argument");
     DevOpts dopt = dev_opts(o);
     dopt.low_type = IPT_LOW_NONE;  // batched ladder: FP32 split-form sweeps, then FP64
-    const bool ladder = dopt.ladder;
+    const bool ladder = dopt.ladder, acx = dopt.acx != 0;
     DeviceGuard guard(h->device);
     hipStream_t s = h->stream;
 
@@ -346,8 +346,12 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
         dmeta = cv.take<BatchMeta>(count);
         ds1 = cv.take<int4>(it_s1.size());
         L.dpad = cv.take<double>(offz);
-        L.z0 = cv.take<double>(offz);
-        L.z1 = cv.take<double>(offz);
+        for (int q = 0; q < 4; ++q) L.zs[q] = (q < 2 || acx) ? cv.take<double>(offz) : nullptr;
+        L.col.dslot = cv.take<double>(acx ? 4 * total_cols : 1);
+        L.col.alist = cv.take<int32_t>(total_cols);
+        L.col.cprec = cv.take<int32_t>(total_cols);
+        L.col.want = cv.take<int32_t>(total_cols);
+        L.col.kact = cv.take<int32_t>(count);
         L.d32 = cv.take<float>(ladder ? offz : 1);
         L.zlo0 = cv.take<float>(ladder ? offz : 1);
         L.zlo1 = cv.take<float>(ladder ? offz : 1);
@@ -413,10 +417,12 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
     auto sweep = [&](hipStream_t st, int32_t t_host) -> hipError_t {
         hipError_t e = timer.mark(t_host, 0, st);
         for (int c = 2; c >= 0 && e == hipSuccess; --c)
-            if (key.has[c]) e = launch_bgemm(st, ctrl, L, lists, tsize[c], key.grid[c]);
+            if (key.has[c]) e = launch_bgemm(st, ctrl, L, lists, tsize[c], key.grid[c], dopt.acx);
         if (e == hipSuccess) e = timer.mark(t_host, 1, st);
         if (e == hipSuccess) e = launch_bfinalize(st, ctrl, dopt, L, total_cols, lists);
+        if (e == hipSuccess) e = launch_bplan(st, ctrl, L, lists, count);
         if (e == hipSuccess) e = launch_bcontrol(st, ctrl, dopt, L, total_cols, lists);
+        if (e == hipSuccess && acx) e = launch_bacx(st, ctrl, L, lists, total_cols);
         return e;
     };
     const bool use_graph = !(o.flags & (IPT_FLAG_NO_GRAPH | IPT_FLAG_TIME_KERNELS));
@@ -437,10 +443,12 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
     IPT_HIP(h, launch_binit(s, ctrl, L, count, ladder ? PREC_F32 : PREC_F64));
     // sweep 1: product-free
     IPT_HIP(h, timer.mark(1, 0, s));
-    IPT_HIP(h, launch_bsweep1(s, ctrl, L, ds1, (int64_t)it_s1.size(), ladder ? 1 : 0));
+    IPT_HIP(h, launch_bsweep1(s, ctrl, L, ds1, (int64_t)it_s1.size(), ladder ? 1 : 0, dopt.acx));
     IPT_HIP(h, timer.mark(1, 1, s));
     IPT_HIP(h, launch_bfinalize(s, ctrl, dopt, L, total_cols, lists));
+    IPT_HIP(h, launch_bplan(s, ctrl, L, lists, count));
     IPT_HIP(h, launch_bcontrol(s, ctrl, dopt, L, total_cols, lists));
+    if (acx) IPT_HIP(h, launch_bacx(s, ctrl, L, lists, total_cols));
     // Later sweeps in chunks; the host reads the stop words of chunk i while chunk
     // i + 1 runs (sweeps launched after the device stopped return at once).
     int32_t launched = 1;

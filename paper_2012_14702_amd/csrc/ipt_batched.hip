@@ -3,17 +3,19 @@
 //
 // Every problem is cut into T x T tiles, T in {32, 64, 128} chosen per size bucket
 // (by the autotuner in ipt_api.hip), and padded to np_b = round_up(n_b, T) so that
-// the GEMM reads aligned 16-byte chunks with no bounds checks.  A sweep is one
-// persistent GEMM launch per tile size over a compacted work list of (problem, row
-// tile, column tile) items -- only the column tiles that still hold an active column
-// -- then a finalize over all columns and a control kernel.  The finalize of sweep t
-// builds the lists of sweep t + 1.  The sweep number lives in the device control
-// block, so every sweep's launches are the same and a chunk of sweeps is captured
-// once in a hipGraph and replayed.
+// the Delta operand is read in aligned 16-byte chunks with no bounds checks.  The
+// active columns of each problem are packed: after every sweep a plan kernel lists
+// them in ascending order, and the GEMM tiles run over packed column positions,
+// gathering their iterate columns, so frozen columns cost nothing (the iterates
+// keep their natural layout).  A sweep is one persistent GEMM launch per tile size
+// over the work list of (problem, row tile, packed column tile) items, a finalize
+// over all columns, the plan kernel (one block per problem: packed columns, tile
+// precisions, work items of the next sweep) and a control kernel.  The sweep number
+// lives in the device control block, so every sweep's launches are the same and a
+// chunk of sweeps is captured once in a hipGraph and replayed.
 //
-// Each column tile carries its own precision for the next sweep (a stamped word:
-// sweep << 2 | precision), chosen by the finalize kernel from the columns' steps:
-// FP32 split-form sweeps (Delta_32 (Z - E)_32 on the matrix cores, Delta E added
+// Each packed column tile carries its own precision, the highest its columns ask
+// for (from their steps, in the finalize): FP32 split-form sweeps (Delta_32 (Z - E)_32 on the matrix cores, Delta E added
 // exactly in FP64) until a column's step reaches tau_32 or stalls, then FP64 sweeps,
 // which alone may certify.  FP32 tiles also write the FP32 shadow of W - E that the
 // next FP32 sweep multiplies.
@@ -111,12 +113,11 @@ __global__ __launch_bounds__(256) void k_binit(Ctrl *ctrl, BArgs a, int32_t star
     }
     if (bad_nan) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
     if (degen) atomicMax(&ctrl->error, (int32_t)IPT_EDEGENERATE);
-    const int ntn = m.np / m.T;
-    for (int q = threadIdx.x; q < ntn; q += blockDim.x) {
-        a.tflag[m.offf + q] = (0u << 2) | (uint32_t)start_prec;
-        a.tflag[a.total_tiles + m.offf + q] = (0u << 2) | (uint32_t)start_prec;
+    (void)start_prec;
+    if (threadIdx.x == 0) {
+        a.col.norm_bits[b] = 0;
+        a.col.kact[b] = 0;
     }
-    if (threadIdx.x == 0) a.col.norm_bits[b] = 0;
 }
 
 // Product-free first sweep of a cold start, W = I - G o Delta (eq. 2 at Z = I), with
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(256) void k_binit(Ctrl *ctrl, BArgs a, int32_t star
 // transposed Delta block staged through LDS) and of the column sums of |M_b| (for
 // |M_b|_1).  Item = (problem, row tile, 64 columns of the padded width).
 __global__ __launch_bounds__(256) void k_bsweep1(const Ctrl *ctrl, BArgs a, const int4 *items, int64_t nitems,
-                                                 int32_t ladder) {
+                                                 int32_t ladder, int32_t acx) {
     if (ctrl->error || ctrl->done) return;
     __shared__ double tt[32][64 + 1];            // Delta[c0 + ci][j0 + jj] at tt[jj][ci]
     __shared__ double sh[4][NPART + 2][64];
@@ -178,8 +179,14 @@ __global__ __launch_bounds__(256) void k_bsweep1(const Ctrl *ctrl, BArgs a, cons
                     }
                     v[4] += tt[jj][cx] * wv;
                 }
-                a.z1[e] = wv;
-                if (!in) a.z0[e] = 0.0;
+                a.zs[1][e] = wv;
+                // slot 0: padding zeroed; with ACX it holds E, the base iterate of the first cycle
+                if (acx) a.zs[0][e] = (in && j == c) ? 1.0 : 0.0;
+                else if (!in) a.zs[0][e] = 0.0;
+                if (acx && !in) {
+                    a.zs[2][e] = 0.0;
+                    a.zs[3][e] = 0.0;
+                }
                 if (ladder) {
                     a.d32[e] = (float)djc;
                     a.zlo1[e] = (float)(wv - (in && j == c ? 1.0 : 0.0));
@@ -230,12 +237,11 @@ constexpr int bsmem() {
 }
 
 template <int T, bool F64>
-__device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], const BArgs &a, const BatchMeta &m,
-                                      int tm, int tn, int32_t t) {
+__device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], int32_t *scol, const BArgs &a,
+                                      const BatchMeta &m, int b, int tm, int tn, int32_t t, int32_t acx) {
     typedef BT<T, F64> C;
     typedef typename C::E E;
-    constexpr int BK = C::BK, VE = C::VE, CPA = C::CPA, RPA = C::RPA, PA = C::PA, TPB = C::TPB, PB = C::PB,
-                  LDA = C::LDA;
+    constexpr int BK = C::BK, VE = C::VE, CPA = C::CPA, RPA = C::RPA, PA = C::PA, LDA = C::LDA;
     constexpr int MI = T / 32;  // 16 x 16 MFMA blocks per wave and dimension (waves are 2 x 2)
     typedef E ATile[T][LDA];
     typedef E BTile[BK][T];
@@ -243,10 +249,12 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], c
     BTile *Bs = (BTile *)(smem + 2 * sizeof(ATile));
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
     const int n = m.n, np = m.np;
-    const int32_t in_buf = (t - 1) & 1;
+    int32_t q, pc;
+    acx_phase(acx, t, q, pc);
+    const int32_t in_buf = acx ? q : (t - 1) & 1, out_buf = acx ? q + 1 : in_buf ^ 1;
     const double *Ad = a.dpad + m.offz;
-    const double *zin = (in_buf ? a.z1 : a.z0) + m.offz;
-    double *zout = (in_buf ? a.z0 : a.z1) + m.offz;
+    const double *zin = a.zs[in_buf] + m.offz;
+    double *zout = a.zs[out_buf] + m.offz;
     const E *Ag, *Bg;
     if constexpr (F64) {
         Ag = Ad;
@@ -255,12 +263,22 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], c
         Ag = a.d32 + m.offz;
         Bg = (in_buf ? a.zlo1 : a.zlo0) + m.offz;
     }
-    const int r0 = tm * T, c0 = tn * T;
+    // packed column positions p0 .. p0 + T - 1 of the problem's active list
+    const int r0 = tm * T, p0 = tn * T;
+    const int32_t *al = a.col.alist + m.offc;
+    const int kact = a.col.kact[b];
     const E *Ab = Ag + (int64_t)r0 * np;
-    const E *Bb = Bg + c0;
     const int a_r = tid / CPA, a_c = (tid % CPA) * VE;
-    const int b_r = tid / TPB, b_c = (tid % TPB) * PB * VE;
-    uint4 ra[PA], rb[PB];
+    // The tile's gathered iterate columns (-1 past the active list).  B loader: each
+    // thread owns one column (lanes run over consecutive packed columns) and RB-strided
+    // rows of the K slice.
+    for (int i = tid; i < T; i += 256) scol[i] = p0 + i < kact ? al[p0 + i] : -1;
+    __syncthreads();
+    constexpr int RB = 256 / T, NB = BK / RB;  // row stride and rows per thread of the B slice
+    const int b_c = tid % T, b_r = tid / T;
+    const int cg = scol[b_c];
+    uint4 ra[PA];
+    E rb[NB];
     union Chunk {
         uint4 u;
         E e[VE];
@@ -269,8 +287,8 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], c
     do {                                                                                                \
         _Pragma("unroll") for (int q = 0; q < PA; ++q) ra[q] =                                          \
             *(const uint4 *)(Ab + (int64_t)(a_r + RPA * q) * np + (K0) + a_c);                          \
-        _Pragma("unroll") for (int q = 0; q < PB; ++q) rb[q] =                                          \
-            *(const uint4 *)(Bb + (int64_t)((K0) + b_r) * np + b_c + VE * q);                           \
+        const E *bcol = Bg + (int64_t)((K0) + b_r) * np + (cg >= 0 ? cg : 0);                           \
+        _Pragma("unroll") for (int q = 0; q < NB; ++q) rb[q] = cg >= 0 ? bcol[(int64_t)RB * q * np] : (E)0; \
     } while (0)
 #define IPT_BSTORE(S)                                                                                   \
     do {                                                                                                \
@@ -279,7 +297,7 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], c
             ch.u = ra[q];                                                                               \
             _Pragma("unroll") for (int e2 = 0; e2 < VE; ++e2) As[S][a_r + RPA * q][a_c + e2] = ch.e[e2]; \
         }                                                                                               \
-        _Pragma("unroll") for (int q = 0; q < PB; ++q) * (uint4 *)&Bs[S][b_r][b_c + VE * q] = rb[q];    \
+        _Pragma("unroll") for (int q = 0; q < NB; ++q) Bs[S][b_r + RB * q][b_c] = rb[q];                \
     } while (0)
     typedef typename std::conditional<F64, d4_t, f4_t>::type ACC;
     ACC acc[MI][MI];
@@ -329,10 +347,11 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], c
         double sums[YB][NPART + 1];
 #pragma unroll
         for (int u = 0; u < YB; ++u) {
-            const int c = c0 + wn * (T / 2) + 16 * (y0 + u) + (lane & 15);
+            const int pi = p0 + wn * (T / 2) + 16 * (y0 + u) + (lane & 15);
+            const int c = pi < kact ? al[pi] : -1;
             cols[u] = c;
-            act[u] = c < n && a.col.state[m.offc + c] == COL_ACTIVE;
-            ti[u] = c < n ? tb[c] : 0.0;
+            act[u] = c >= 0 && a.col.state[m.offc + c] == COL_ACTIVE;
+            ti[u] = act[u] ? tb[c] : 0.0;
             dd[u] = act[u] ? a.col.d[m.offc + c] : 0.0;
 #pragma unroll
             for (int q = 0; q < NPART + 1; ++q) sums[u][q] = 0.0;
@@ -388,8 +407,9 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], c
     }
     __syncthreads();
     if (tid < T) {
-        const int c = c0 + tid;
-        if (c < n) {
+        const int pi = p0 + tid;
+        const int c = pi < kact ? al[pi] : -1;
+        if (c >= 0) {
 #pragma unroll
             for (int q = 0; q < NPART; ++q)
                 a.part[m.offp + ((int64_t)tm * n + c) * NPART + q] = red[0][tid][q] + red[1][tid][q];
@@ -401,7 +421,7 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], c
 
 template <int T>
 __global__ __launch_bounds__(256, (T == 128 ? 2 : (T == 64 ? 4 : 5))) void k_bgemm(const Ctrl *ctrl, BArgs a,
-                                                                                   BatchLists lists) {
+                                                                                   BatchLists lists, int32_t acx) {
     if (ctrl->error || ctrl->done) return;
     constexpr int C = tile_class<T>();
     const int32_t t = cur_sweep(ctrl);
@@ -409,6 +429,7 @@ __global__ __launch_bounds__(256, (T == 128 ? 2 : (T == 64 ? 4 : 5))) void k_bge
     const int32_t nitems = lists.counts[2 * C + (t & 1)];
     __shared__ __attribute__((aligned(16))) char smem[bsmem<T>()];
     __shared__ double red[2][T][NPART + 1];
+    __shared__ int32_t scol[T];
     __shared__ int32_t cur_item;
     for (;;) {
         if (threadIdx.x == 0) cur_item = atomicAdd(&lists.tickets[C], 1);
@@ -418,9 +439,8 @@ __global__ __launch_bounds__(256, (T == 128 ? 2 : (T == 64 ? 4 : 5))) void k_bge
         if (it >= nitems) break;
         const int4 w = items[it];
         const BatchMeta m = a.meta[w.x];
-        const uint32_t f = a.tflag[(int64_t)((t - 1) & 1) * a.total_tiles + m.offf + w.z];
-        if ((f & 3u) == (uint32_t)PREC_F64) btile<T, true>(smem, red, a, m, w.y, w.z, t);
-        else btile<T, false>(smem, red, a, m, w.y, w.z, t);
+        if (a.tflag[m.offf + w.z] == (uint32_t)PREC_F64) btile<T, true>(smem, red, scol, a, m, w.x, w.y, w.z, t, acx);
+        else btile<T, false>(smem, red, scol, a, m, w.x, w.y, w.z, t, acx);
     }
 }
 
@@ -434,8 +454,7 @@ __global__ __launch_bounds__(256, (T == 128 ? 2 : (T == 64 ? 4 : 5))) void k_bge
 // kernel in block order.
 enum { BP_MAXSTEP, BP_DECSTEP, BP_STILL, BP_CONV, BP_DIV, BP_NC, BP_F32, BP_WORDS = 8 };
 
-__global__ __launch_bounds__(256) void k_bfinalize(Ctrl *ctrl, DevOpts o, BArgs a, int64_t total_cols,
-                                                   BatchLists lists) {
+__global__ __launch_bounds__(256) void k_bfinalize(Ctrl *ctrl, DevOpts o, BArgs a, int64_t total_cols) {
     if (ctrl->error || ctrl->done) return;
     const int32_t t = cur_sweep(ctrl);
     const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -445,7 +464,7 @@ __global__ __launch_bounds__(256) void k_bfinalize(Ctrl *ctrl, DevOpts o, BArgs 
     double s = 0.0;
     bool act = false, still = false;
     uint32_t want = 0;
-    int64_t tile_key = -1, prob_key = -1;
+    int64_t prob_key = -1;
     uint64_t norm_v = 0;
     BatchMeta m{};
     int c = 0;
@@ -453,7 +472,6 @@ __global__ __launch_bounds__(256) void k_bfinalize(Ctrl *ctrl, DevOpts o, BArgs 
         const int b = a.col.prob[gc];
         m = a.meta[b];
         c = (int)(gc - m.offc);
-        tile_key = m.offf + c / m.T;
         prob_key = b;
         const int nt = m.np / m.T;
         if (t == 1) {  // |M_b|_1 from the first sweep's column sums
@@ -473,14 +491,18 @@ __global__ __launch_bounds__(256) void k_bfinalize(Ctrl *ctrl, DevOpts o, BArgs 
             }
             s = sqrt(p[0]) / sqrt(p[1]);
             const double dist = sqrt(p[3]);
-            const uint32_t f = a.tflag[(int64_t)((t - 1) & 1) * a.total_tiles + tile_key];
-            prec = (t == 1) ? PREC_EXACT_FIRST : (int32_t)(f & 3u);
+            prec = (t == 1) ? PREC_EXACT_FIRST : a.col.cprec[gc];
             const bool exact = prec == PREC_F64 || prec == PREC_EXACT_FIRST;
             const double resid = sqrt(p[2]) / sqrt(p[1]);  // normalised by |M_b|_1 at copy-out
-            const int32_t in_par = (t == 1) ? PAR_UNIT : ((t - 1) & 1);
-            const int32_t out_par = t & 1;
+            // IPT-ACX: only the first application of a cycle is tested (slot 0 -> 1)
+            int32_t q, pc;
+            acx_phase(o.acx, t, q, pc);
+            const int32_t in_par = (t == 1) ? PAR_UNIT : (o.acx ? PAR_BUF0 : ((t - 1) & 1));
+            const int32_t out_par = o.acx ? PAR_BUF1 : (t & 1);
             const double prev = a.col.prev[gc];
-            if (exact && s <= o.tol) {
+            if (q != 0) {
+                // mid-cycle application: no decision
+            } else if (exact && s <= o.tol) {
                 decided = COL_CONVERGED;
                 a.col.par[gc] = in_par;
             } else {
@@ -493,12 +515,12 @@ __global__ __launch_bounds__(256) void k_bfinalize(Ctrl *ctrl, DevOpts o, BArgs 
                 if (bad || grow >= o.div_growth) {
                     decided = COL_DIVERGED;
                     a.col.par[gc] = out_par;
-                } else if (t >= o.max_iter) {
+                } else if (t + pc > o.max_iter) {
                     decided = COL_NOT_CONVERGED;
                     a.col.par[gc] = out_par;
                 }
             }
-            a.col.prev[gc] = s;
+            if (q == 0) a.col.prev[gc] = s;
             if (decided >= 0) {
                 a.col.state[gc] = decided;
                 a.col.sweeps[gc] = t;
@@ -508,49 +530,17 @@ __global__ __launch_bounds__(256) void k_bfinalize(Ctrl *ctrl, DevOpts o, BArgs 
             } else {
                 still = true;
                 double dn = 0.0;
-                for (int q = 0; q < nt; ++q) dn += a.dpart[m.offq + (int64_t)q * m.n + c];
+                for (int r2 = 0; r2 < nt; ++r2) dn += a.dpart[m.offq + (int64_t)r2 * m.n + c];
+                if (o.acx) {  // d of every slot of the cycle, for the extrapolated iterate's d
+                    if (q == 0) a.col.dslot[gc] = a.col.d[gc];
+                    a.col.dslot[(int64_t)(q + 1) * total_cols + gc] = dn;
+                }
                 a.col.d[gc] = dn;
                 want = PREC_F64;
                 if (o.ladder && prec != PREC_F64) want = (s <= o.tau_32 || !(s < prev)) ? PREC_F64 : PREC_F32;
+                a.col.want[gc] = (int32_t)want;
             }
         }
-    }
-    // column-tile stamps: one atomic per tile segment of the wave
-    bool leader;
-    const uint64_t tw = seg_max(tile_key, still ? (uint64_t)(((uint32_t)t << 2) | want) : 0ull, leader);
-    int my_cls = -1, my_cnt = 0;
-    if (leader && tw) {
-        const uint32_t old = atomicMax(&a.tflag[(int64_t)(t & 1) * a.total_tiles + tile_key], (uint32_t)tw);
-        if ((int32_t)(old >> 2) != t) {  // first stamp of this tile in this sweep
-            my_cls = tile_class_of(m.T);
-            my_cnt = m.np / m.T;
-        }
-    }
-    // list appends: wave scans per tile class, one atomicAdd per class and block
-    __shared__ int s_tot[4][3];
-    __shared__ int s_base[3];
-    int my_excl = 0;
-#pragma unroll
-    for (int cl = 0; cl < 3; ++cl) {
-        const int v = (my_cls == cl) ? my_cnt : 0;
-        const int inc = wave_incl_scan(v);
-        if (my_cls == cl) my_excl = inc - v;
-        if (lane == 63) s_tot[wave][cl] = inc;
-    }
-    __syncthreads();
-    const int nx = (t + 1) & 1;
-    if (threadIdx.x < 3) {
-        const int cl = threadIdx.x;
-        const int tot = s_tot[0][cl] + s_tot[1][cl] + s_tot[2][cl] + s_tot[3][cl];
-        s_base[cl] = tot ? atomicAdd(&lists.counts[2 * cl + nx], tot) : 0;
-    }
-    __syncthreads();
-    if (my_cnt) {
-        int pos = s_base[my_cls] + my_excl;
-        for (int w2 = 0; w2 < wave; ++w2) pos += s_tot[w2][my_cls];
-        int4 *lst = lists.l[my_cls][nx];
-        const int tn = c / m.T;
-        for (int q = 0; q < my_cnt; ++q) lst[pos + q] = make_int4((int)prob_key, q, tn, 0);
     }
     if (t == 1) {
         bool nl;
@@ -595,6 +585,53 @@ __global__ __launch_bounds__(256) void k_bfinalize(Ctrl *ctrl, DevOpts o, BArgs 
         if (q == BP_WORDS - 1) r = 0;
         a.bpart[(int64_t)blockIdx.x * BP_WORDS + q] = r;
     }
+}
+
+// Plan of the next sweep, one block per problem: the still-active columns in
+// ascending order (packed positions), the precision of each packed column tile (the
+// highest its columns ask for), each column's precision, and the work items (row
+// tile, packed column tile) appended to the next sweep's list of its tile class.
+__global__ __launch_bounds__(256) void k_bplan(const Ctrl *ctrl, BArgs a, BatchLists lists) {
+    if (ctrl->error || ctrl->done) return;
+    const int32_t t = cur_sweep(ctrl);  // the sweep just finalized
+    const int b = blockIdx.x;
+    const BatchMeta m = a.meta[b];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ int s_w[4];
+    __shared__ int s_base, s_items;
+    __shared__ uint32_t s_tprec[128];  // n <= 4096, T >= 32
+    for (int i = threadIdx.x; i < 128; i += 256) s_tprec[i] = 0;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    int32_t *al = a.col.alist + m.offc;
+    for (int c0 = 0; c0 < m.n; c0 += 256) {
+        const int c = c0 + threadIdx.x;
+        const bool act = c < m.n && a.col.state[m.offc + c] == COL_ACTIVE;
+        const int inc = wave_incl_scan(act ? 1 : 0);
+        if (lane == 63) s_w[wave] = inc;
+        __syncthreads();
+        int pos = s_base + inc - (act ? 1 : 0);
+        for (int w2 = 0; w2 < wave; ++w2) pos += s_w[w2];
+        if (act) {
+            al[pos] = c;
+            atomicMax(&s_tprec[pos / m.T], (uint32_t)a.col.want[m.offc + c]);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_base += s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
+    }
+    const int kact = s_base;
+    const int tiles = (kact + m.T - 1) / m.T, nt = m.np / m.T;
+    for (int pos = threadIdx.x; pos < kact; pos += 256) a.col.cprec[m.offc + al[pos]] = (int32_t)s_tprec[pos / m.T];
+    for (int tn = threadIdx.x; tn < tiles; tn += 256) a.tflag[m.offf + tn] = s_tprec[tn];
+    const int cl = tile_class_of(m.T), nx = (t + 1) & 1;
+    if (threadIdx.x == 0) {
+        a.col.kact[b] = kact;
+        s_items = tiles ? atomicAdd(&lists.counts[2 * cl + nx], tiles * nt) : 0;
+    }
+    __syncthreads();
+    int4 *lst = lists.l[cl][nx];
+    for (int e = threadIdx.x; e < tiles * nt; e += 256) lst[s_items + e] = make_int4(b, e % nt, e / nt, 0);
 }
 
 // Sweep bookkeeping of the batch: reduce the finalize blocks' partials in block
@@ -667,7 +704,7 @@ __global__ __launch_bounds__(256) void k_bcopyout(const Ctrl *ctrl, BArgs a, con
         const int64_t gc = m.offc + c;
         if (ok) {
             const int32_t par = a.col.par[gc];
-            const double *src = (par == PAR_BUF1 ? a.z1 : a.z0) + m.offz;
+            const double *src = a.zs[par == PAR_BUF1 ? 1 : 0] + m.offz;
             double *dst = z_pool + m.offo;
             const int j1 = min(n, tm * m.T + m.T);
             for (int j = tm * m.T + ry; j < j1; j += 4)
@@ -694,6 +731,128 @@ __global__ __launch_bounds__(256) void k_bcopyout(const Ctrl *ctrl, BArgs a, con
     }
 }
 
+// ------------------------------------------------------------------ IPT-ACX
+// After the last application of a cycle of order p (sweep t = ctrl->sweeps), every
+// active column moves to z + sum_q binom(p, q) sigma^q D^q (D^q the forward
+// differences of its slots z, F(z), ..., F^p(z); sigma = |<D^p, D^(p-1)>| / |D^p|^2,
+// 1 when D^p = 0), and its d follows by linearity from the d of the slots.  The
+// tiles are those of the next sweep's work lists (every tile holding an active
+// column); a tile's partial sums go to the per-row-tile arrays dpart (dot) and
+// normpart (squared norm), free at this point of the sweep.
+__device__ inline bool acx_cycle_end(const Ctrl *ctrl, int32_t &t, int32_t &pc) {
+    if (ctrl->error || ctrl->done) return false;
+    t = ctrl->sweeps;
+    int32_t q;
+    acx_phase(1, t, q, pc);
+    return q == pc - 1;
+}
+
+__device__ inline bool acx_item(const BatchLists &lists, int32_t t, int64_t it, int4 &w) {
+    const int nx = (t + 1) & 1;
+    int64_t base = 0;
+    for (int cl = 0; cl < 3; ++cl) {
+        const int64_t cnt = lists.counts[2 * cl + nx];
+        if (it < base + cnt) {
+            w = lists.l[cl][nx][it - base];
+            return true;
+        }
+        base += cnt;
+    }
+    return false;
+}
+
+__device__ inline void acx_diffs(int32_t p, double z, double a1, double a2, double a3, double &d1, double &d2,
+                                 double &d3) {
+    d1 = a1 - z;
+    d2 = (a2 - 2.0 * a1) + z;
+    d3 = p == 3 ? ((a3 - 3.0 * a2) + 3.0 * a1) - z : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_bacx_dots(const Ctrl *ctrl, BArgs a, BatchLists lists) {
+    int32_t t, pc;
+    if (!acx_cycle_end(ctrl, t, pc)) return;
+    __shared__ double sh[2][256];
+    const int64_t total = (int64_t)lists.counts[(t + 1) & 1] + lists.counts[2 + ((t + 1) & 1)] +
+                          lists.counts[4 + ((t + 1) & 1)];
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        int4 w;
+        acx_item(lists, t, it, w);
+        const BatchMeta m = a.meta[w.x];
+        const int T = m.T, n = m.n, np = m.np;
+        const int cc = threadIdx.x % T, rg = threadIdx.x / T, ngr = 256 / T;
+        const int pi = w.z * T + cc;
+        const int c = pi < a.col.kact[w.x] ? a.col.alist[m.offc + pi] : -1;
+        const bool act = c >= 0 && a.col.state[m.offc + c] == COL_ACTIVE;
+        double dot = 0.0, nrm = 0.0;
+        if (act) {
+            const int j1 = min(n, w.y * T + T);
+            for (int j = w.y * T + rg; j < j1; j += ngr) {
+                const int64_t e = m.offz + (int64_t)j * np + c;
+                double d1, d2, d3;
+                acx_diffs(pc, a.zs[0][e], a.zs[1][e], a.zs[2][e], pc == 3 ? a.zs[3][e] : 0.0, d1, d2, d3);
+                const double hi = pc == 3 ? d3 : d2, lo = pc == 3 ? d2 : d1;
+                dot += hi * lo;
+                nrm += hi * hi;
+            }
+        }
+        sh[0][threadIdx.x] = dot;
+        sh[1][threadIdx.x] = nrm;
+        __syncthreads();
+        if (rg == 0 && act) {
+            double sd = 0.0, sn = 0.0;
+            for (int g = 0; g < ngr; ++g) {
+                sd += sh[0][g * T + cc];
+                sn += sh[1][g * T + cc];
+            }
+            a.dpart[m.offq + (int64_t)w.y * n + c] = sd;
+            a.normpart[m.offq + (int64_t)w.y * n + c] = sn;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bacx_update(const Ctrl *ctrl, BArgs a, BatchLists lists, int64_t total_cols) {
+    int32_t t, pc;
+    if (!acx_cycle_end(ctrl, t, pc)) return;
+    const int64_t total = (int64_t)lists.counts[(t + 1) & 1] + lists.counts[2 + ((t + 1) & 1)] +
+                          lists.counts[4 + ((t + 1) & 1)];
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        int4 w;
+        acx_item(lists, t, it, w);
+        const BatchMeta m = a.meta[w.x];
+        const int T = m.T, n = m.n, np = m.np, nt = np / T;
+        const int cc = threadIdx.x % T, rg = threadIdx.x / T, ngr = 256 / T;
+        const int pi = w.z * T + cc;
+        const int c = pi < a.col.kact[w.x] ? a.col.alist[m.offc + pi] : -1;
+        if (c < 0 || a.col.state[m.offc + c] != COL_ACTIVE) continue;
+        double sd = 0.0, sn = 0.0;
+        for (int r = 0; r < nt; ++r) {
+            sd += a.dpart[m.offq + (int64_t)r * n + c];
+            sn += a.normpart[m.offq + (int64_t)r * n + c];
+        }
+        const double sg = sn > 0.0 ? fabs(sd) / sn : 1.0;
+        const int j1 = min(n, w.y * T + T);
+        for (int j = w.y * T + rg; j < j1; j += ngr) {
+            const int64_t e = m.offz + (int64_t)j * np + c;
+            const double z = a.zs[0][e];
+            double d1, d2, d3;
+            acx_diffs(pc, z, a.zs[1][e], a.zs[2][e], pc == 3 ? a.zs[3][e] : 0.0, d1, d2, d3);
+            a.zs[0][e] = pc == 3 ? ((z + 3.0 * sg * d1) + 3.0 * (sg * sg) * d2) + (sg * sg * sg) * d3
+                                 : (z + 2.0 * sg * d1) + (sg * sg) * d2;
+        }
+        if (w.y == 0 && rg == 0) {
+            const int64_t gc = m.offc + c;
+            const double *ds = a.col.dslot;
+            double d1, d2, d3;
+            const double d0 = ds[gc];
+            acx_diffs(pc, d0, ds[total_cols + gc], ds[2 * total_cols + gc], pc == 3 ? ds[3 * total_cols + gc] : 0.0,
+                      d1, d2, d3);
+            a.col.d[gc] = pc == 3 ? ((d0 + 3.0 * sg * d1) + 3.0 * (sg * sg) * d2) + (sg * sg * sg) * d3
+                                  : (d0 + 2.0 * sg * d1) + (sg * sg) * d2;
+        }
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers
@@ -716,23 +875,36 @@ hipError_t launch_binit(hipStream_t s, Ctrl *ctrl, const BatchLaunch &L, int32_t
 }
 
 hipError_t launch_bsweep1(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
-                          int32_t ladder) {
+                          int32_t ladder, int32_t acx) {
     const int g = nitems < 8192 ? (int)nitems : 8192;
-    k_bsweep1<<<g > 0 ? g : 1, 256, 0, s>>>(ctrl, L, items, nitems, ladder);
+    k_bsweep1<<<g > 0 ? g : 1, 256, 0, s>>>(ctrl, L, items, nitems, ladder, acx);
     return hipGetLastError();
 }
 
 hipError_t launch_bgemm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int tile,
-                        int grid) {
-    if (tile == 32) k_bgemm<32><<<grid, 256, 0, s>>>(ctrl, L, lists);
-    else if (tile == 64) k_bgemm<64><<<grid, 256, 0, s>>>(ctrl, L, lists);
-    else k_bgemm<128><<<grid, 256, 0, s>>>(ctrl, L, lists);
+                        int grid, int32_t acx) {
+    if (tile == 32) k_bgemm<32><<<grid, 256, 0, s>>>(ctrl, L, lists, acx);
+    else if (tile == 64) k_bgemm<64><<<grid, 256, 0, s>>>(ctrl, L, lists, acx);
+    else k_bgemm<128><<<grid, 256, 0, s>>>(ctrl, L, lists, acx);
+    return hipGetLastError();
+}
+
+hipError_t launch_bacx(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists,
+                       int64_t total_cols) {
+    k_bacx_dots<<<4096, 256, 0, s>>>(ctrl, L, lists);
+    k_bacx_update<<<4096, 256, 0, s>>>(ctrl, L, lists, total_cols);
     return hipGetLastError();
 }
 
 hipError_t launch_bfinalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
                             const BatchLists &lists) {
-    k_bfinalize<<<bfinalize_blocks(total_cols), 256, 0, s>>>(ctrl, o, L, total_cols, lists);
+    (void)lists;
+    k_bfinalize<<<bfinalize_blocks(total_cols), 256, 0, s>>>(ctrl, o, L, total_cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_bplan(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int32_t count) {
+    k_bplan<<<count, 256, 0, s>>>(ctrl, L, lists);
     return hipGetLastError();
 }
 

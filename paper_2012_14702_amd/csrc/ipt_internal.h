@@ -156,6 +156,11 @@ struct BatchMeta {
 struct BatchCols {  // per column of all problems, concatenated
     int32_t *state, *sweeps, *grow, *par, *prob;
     double *prev, *step, *lam, *resid, *d;
+    double *dslot;        // IPT-ACX: [4][columns] d of each iterate slot of the running cycle
+    int32_t *alist;       // per problem, its active columns in ascending order (packed positions)
+    int32_t *cprec;       // precision of the tile that computes the column in the running sweep
+    int32_t *want;        // precision the column asks for in the next sweep
+    int32_t *kact;        // per problem: active columns (length of its alist)
     uint64_t *norm_bits;  // per problem: |M_b|_1 (bits)
 };
 struct BatchLaunch {
@@ -163,14 +168,14 @@ struct BatchLaunch {
     const double *theta, *delta;  // caller pools
     double *dpad;                 // padded FP64 Delta
     float *d32;                   // padded FP32 Delta (ladder)
-    double *z0, *z1;              // iterate buffers
+    double *zs[4];                // iterate slots: ping-pong in 0/1; IPT-ACX cycles use 0..3
     float *zlo0, *zlo1;           // FP32 shadows of Z - E (ladder)
     BatchCols col;
     double *part;
     double *dpart;     // [total_q] next sweep's d, one partial per (row tile, column)
     double *normpart;  // [total_q] column sums of |M_b| per row tile (first sweep)
     uint64_t *bpart;   // [finalize blocks][8] per-block batch counters
-    uint32_t *tflag;   // [2][total column tiles]: (sweep << 2) | precision
+    uint32_t *tflag;   // [total column tiles] precision of each packed column tile of the next sweep
     int64_t total_tiles, total_q;
 };
 // Work lists of (problem, row tile, column tile, 0) items per tile class (T = 32, 64,
@@ -183,13 +188,16 @@ struct BatchLists {
 int bfinalize_blocks(int64_t total_cols);
 hipError_t launch_binit(hipStream_t s, Ctrl *ctrl, const BatchLaunch &L, int32_t count, int32_t start_prec);
 hipError_t launch_bsweep1(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
-                          int32_t ladder);
+                          int32_t ladder, int32_t acx);
+hipError_t launch_bacx(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists,
+                       int64_t total_cols);
 hipError_t launch_bgemm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int tile,
-                        int grid);
+                        int grid, int32_t acx);
 hipError_t launch_bfinalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
                             const BatchLists &lists);
 hipError_t launch_bcontrol(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
                            const BatchLists &lists);
+hipError_t launch_bplan(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int32_t count);
 hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
                            double *z_pool, double *lambda_pool, int32_t *status_pool, double *max_resid_out);
 int bgemm_grid(int tile);  // persistent grid size (CUs x resident blocks)

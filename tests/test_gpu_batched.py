@@ -194,3 +194,45 @@ def test_batched_tune_table(ipt):
             ipt.ipt_batched_set_tiles([48] * ipt.TILE_BUCKETS)
     finally:
         ipt.ipt_batched_set_tiles(saved)
+
+
+def test_batched_acx_parity_and_graph(ipt):
+    """IPT-ACX over a batch (sizes 1..400, three tile sizes by the default table):
+    every problem matches the ACX oracle, and the captured graph replays give the
+    same bits as host-launched sweeps."""
+    say("batched acx")
+    ns, th, de, th_off, de_off = W.batched_sym_gaussian(32, 1, 400, 0.02, seed=9)
+    kw = dict(tol=1e-10, max_iter=64, flags=ipt.FLAG_ACX)
+    g = _run(ipt, ns, th, de, **kw)
+    e = _run(ipt, ns, th, de, tol=1e-10, max_iter=64, flags=ipt.FLAG_ACX | ipt.FLAG_NO_GRAPH)
+    _same(g, e)
+    z, lam, st, info = g
+    for b in range(len(ns)):
+        n = int(ns[b])
+        gz, gl, gs = _per_problem(ns, th_off, de_off, z, lam, st, b)
+        thb = th[th_off[b]:th_off[b] + n]
+        deb = de[de_off[b]:de_off[b] + n * n].reshape(n, n)
+        rr = oracle.ipt_dense(thb, deb, tol=1e-10, max_iter=64, accel="acx")
+        check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-10, max_iter=64)
+    assert info["converged"] == int((st == 0).sum())
+
+
+@pytest.mark.parametrize("tile", [32, 128])
+def test_batched_acx_tiles(ipt, tile):
+    """ACX with every problem on one tile size, ragged sizes."""
+    say("batched acx tile %d" % tile)
+    sizes = [1, 3, 33, 64, 100, 129, 250]
+    ns, th, de, th_off, de_off = _edge_batch(sizes, 500)
+    saved = ipt.ipt_batched_get_tiles()
+    try:
+        ipt.ipt_batched_set_tiles([tile] * ipt.TILE_BUCKETS)
+        z, lam, st, info = _run(ipt, ns, th, de, tol=1e-11, flags=ipt.FLAG_ACX)
+        for b, n in enumerate(sizes):
+            gz, gl, gs = _per_problem(ns, th_off, de_off, z, lam, st, b)
+            thb = th[th_off[b]:th_off[b] + n]
+            deb = de[de_off[b]:de_off[b] + n * n].reshape(n, n)
+            rr = oracle.ipt_dense(thb, deb, tol=1e-11, accel="acx")
+            check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-11, max_iter=100)
+        assert np.all(st == 0)
+    finally:
+        ipt.ipt_batched_set_tiles(saved)
