@@ -352,6 +352,7 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
         L.col.cprec = cv.take<int32_t>(total_cols);
         L.col.want = cv.take<int32_t>(total_cols);
         L.col.kact = cv.take<int32_t>(count);
+        L.col.asym = cv.take<int32_t>(count);
         L.d32 = cv.take<float>(ladder ? offz : 1);
         L.zlo0 = cv.take<float>(ladder ? offz : 1);
         L.zlo1 = cv.take<float>(ladder ? offz : 1);

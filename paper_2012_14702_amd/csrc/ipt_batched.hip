@@ -117,6 +117,7 @@ __global__ __launch_bounds__(256) void k_binit(Ctrl *ctrl, BArgs a, int32_t star
     if (threadIdx.x == 0) {
         a.col.norm_bits[b] = 0;
         a.col.kact[b] = 0;
+        a.col.asym[b] = 0;
     }
 }
 
@@ -179,6 +180,7 @@ __global__ __launch_bounds__(256) void k_bsweep1(const Ctrl *ctrl, BArgs a, cons
                     }
                     v[4] += tt[jj][cx] * wv;
                 }
+                if (in && djc != tt[jj][cx]) a.col.asym[w.x] = 1;  // Delta_jc vs Delta_cj
                 a.zs[1][e] = wv;
                 // slot 0: padding zeroed; with ACX it holds E, the base iterate of the first cycle
                 if (acx) a.zs[0][e] = (in && j == c) ? 1.0 : 0.0;
@@ -226,9 +228,13 @@ struct BT {
     static constexpr int PA = T / RPA;               // A passes per thread
     static constexpr int TPB = 256 / BK;             // threads per B row
     static constexpr int PB = (T / VE) / TPB;        // B chunks per thread
-    static constexpr int LDA = BK + 1;               // A row pitch in LDS (odd: no bank aliasing)
-    static constexpr int SMEM = 2 * T * LDA * (int)sizeof(E) + 2 * BK * T * (int)sizeof(E);
+    // LDS pitches (elements) chosen so that the MFMA operand reads -- 16 rows x 4 k of A,
+    // 4 k rows x 16 columns of B per wave -- fall on distinct banks
+    static constexpr int LDA = F64 ? BK + 2 : BK + 4;
+    static constexpr int LDB = T + 16;
+    static constexpr int SMEM = 2 * T * LDA * (int)sizeof(E) + 2 * BK * LDB * (int)sizeof(E);
     static_assert(PA >= 1 && PB >= 1, "tile too small for the loader");
+    static_assert(SMEM >= 2 * T * (NPART + 1) * 8, "epilogue reduction must fit in the operand LDS");
 };
 
 template <int T>
@@ -237,14 +243,15 @@ constexpr int bsmem() {
 }
 
 template <int T, bool F64>
-__device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], int32_t *scol, const BArgs &a,
-                                      const BatchMeta &m, int b, int tm, int tn, int32_t t, int32_t acx) {
+__device__ __forceinline__ void btile(char *smem, int32_t *scol, const BArgs &a, const BatchMeta &m, int b, int tm,
+                                      int tn, int32_t t, int32_t acx) {
     typedef BT<T, F64> C;
     typedef typename C::E E;
-    constexpr int BK = C::BK, VE = C::VE, CPA = C::CPA, RPA = C::RPA, PA = C::PA, LDA = C::LDA;
+    constexpr int BK = C::BK, VE = C::VE, CPA = C::CPA, RPA = C::RPA, PA = C::PA, LDA = C::LDA, LDB = C::LDB;
     constexpr int MI = T / 32;  // 16 x 16 MFMA blocks per wave and dimension (waves are 2 x 2)
     typedef E ATile[T][LDA];
-    typedef E BTile[BK][T];
+    typedef E BTile[BK][LDB];
+    double(*red)[T][NPART + 1] = (double(*)[T][NPART + 1])smem;  // epilogue reuse of the operand LDS
     ATile *As = (ATile *)smem;
     BTile *Bs = (BTile *)(smem + 2 * sizeof(ATile));
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
@@ -338,6 +345,8 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], i
     // their partial sums are live at once
     const double *tb = a.theta + m.offt;
     float *zlo_out = F64 ? nullptr : (in_buf ? a.zlo0 : a.zlo1) + m.offz;
+    // Delta_cj of the next d: for an exactly symmetric Delta_b it is the coalesced Delta_jc
+    const bool sym = a.col.asym[b] == 0;
     constexpr int YB = MI > 2 ? 2 : MI;
 #pragma unroll
     for (int y0 = 0; y0 < MI; y0 += YB) {
@@ -371,6 +380,7 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], i
                     const int c = cols[u];
                     const int64_t e = (int64_t)j * np + c;
                     const double z = zin[e];
+                    const double adj = (!F64 || sym) ? Ad[e] : 0.0;
                     double wvv, st, gs, de;
                     if (j == c) {
                         wvv = 1.0;
@@ -379,7 +389,7 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], i
                         de = 0.0;
                     } else {
                         const double acv = (double)acc[x][y0 + u][r];
-                        const double yv = F64 ? acv : Ad[e] + acv;  // split form: Delta E exact
+                        const double yv = F64 ? acv : adj + acv;  // split form: Delta E exact
                         const double gap = tj - ti[u];
                         wvv = (z * dd[u] - yv) / gap;
                         st = wvv - z;
@@ -392,7 +402,7 @@ __device__ __forceinline__ void btile(char *smem, double (*red)[T][NPART + 1], i
                     sums[u][1] += z * z;
                     sums[u][2] += gs * gs;
                     sums[u][3] += de * de;
-                    sums[u][4] += Ad[(int64_t)c * np + j] * wvv;  // next sweep's d_c
+                    sums[u][4] += (sym ? adj : Ad[(int64_t)c * np + j]) * wvv;  // next sweep's d_c
                 }
             }
 #pragma unroll
@@ -428,7 +438,6 @@ __global__ __launch_bounds__(256, (T == 128 ? 2 : (T == 64 ? 4 : 5))) void k_bge
     const int4 *items = lists.l[C][t & 1];
     const int32_t nitems = lists.counts[2 * C + (t & 1)];
     __shared__ __attribute__((aligned(16))) char smem[bsmem<T>()];
-    __shared__ double red[2][T][NPART + 1];
     __shared__ int32_t scol[T];
     __shared__ int32_t cur_item;
     for (;;) {
@@ -439,8 +448,8 @@ __global__ __launch_bounds__(256, (T == 128 ? 2 : (T == 64 ? 4 : 5))) void k_bge
         if (it >= nitems) break;
         const int4 w = items[it];
         const BatchMeta m = a.meta[w.x];
-        if (a.tflag[m.offf + w.z] == (uint32_t)PREC_F64) btile<T, true>(smem, red, scol, a, m, w.x, w.y, w.z, t, acx);
-        else btile<T, false>(smem, red, scol, a, m, w.x, w.y, w.z, t, acx);
+        if (a.tflag[m.offf + w.z] == (uint32_t)PREC_F64) btile<T, true>(smem, scol, a, m, w.x, w.y, w.z, t, acx);
+        else btile<T, false>(smem, scol, a, m, w.x, w.y, w.z, t, acx);
     }
 }
 

@@ -161,6 +161,7 @@ struct BatchCols {  // per column of all problems, concatenated
     int32_t *cprec;       // precision of the tile that computes the column in the running sweep
     int32_t *want;        // precision the column asks for in the next sweep
     int32_t *kact;        // per problem: active columns (length of its alist)
+    int32_t *asym;        // per problem: nonzero when Delta_b is not exactly symmetric
     uint64_t *norm_bits;  // per problem: |M_b|_1 (bits)
 };
 struct BatchLaunch {

@@ -236,3 +236,28 @@ def test_batched_acx_tiles(ipt, tile):
         assert np.all(st == 0)
     finally:
         ipt.ipt_batched_set_tiles(saved)
+
+
+@pytest.mark.parametrize("flags", [0, 8])
+def test_batched_nonsymmetric(ipt, flags):
+    """Non-symmetric problems (the paper's diag(1..n) + eps R, R iid U[0,1], Sec. 6.2)
+    next to symmetric ones in one batch: the next sweep's d uses Delta_cj, which the
+    solve reads as Delta_jc only for exactly symmetric problems."""
+    say("batched nonsym flags=%d" % flags)
+    sizes = [5, 70, 130, 200, 64]
+    th_parts, de_parts = [], []
+    for q, n in enumerate(sizes):
+        thb, deb = (W.dense_uniform_nonsym(n, 1e-3, 700 + q) if q % 2 == 0 else W.dense_sym_gaussian(n, 0.01, 700 + q))
+        th_parts.append(thb)
+        de_parts.append(deb.ravel())
+    ns = np.array(sizes, dtype=np.int32)
+    th, de = np.concatenate(th_parts), np.concatenate(de_parts)
+    th_off = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    de_off = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
+    z, lam, st, info = _run(ipt, ns, th, de, tol=1e-11, flags=flags)
+    for b, n in enumerate(sizes):
+        gz, gl, gs = _per_problem(ns, th_off, de_off, z, lam, st, b)
+        thb, deb = th_parts[b], de_parts[b].reshape(n, n)
+        rr = oracle.ipt_dense(thb, deb, tol=1e-11, accel="acx" if flags else "picard")
+        check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-11, max_iter=100)
+    assert np.all(st == 0)
