@@ -19,7 +19,6 @@ namespace ipt {
 
 namespace {
 
-constexpr int ACX_ROWS = 256;  // rows per split
 constexpr int ACX_MAX_SPLITS = 64;
 
 __device__ inline void diffs(int32_t p, double z, double a, double b, double c, double &d1, double &d2,
@@ -29,21 +28,23 @@ __device__ inline void diffs(int32_t p, double z, double a, double b, double c, 
     d3 = p == 3 ? ((c - 3.0 * b) + 3.0 * a) - z : 0.0;
 }
 
-// Block: 64 columns x 4 row groups of one split; partial (dot, norm) per split and
-// column.
+// Block: cw columns x (256 / cw) row groups of one row split (cw = 64, or the
+// next power of two >= kc for narrow solves, so that few columns still fill the
+// block); partial (dot, norm) per split and column, row groups added in order.
 __global__ __launch_bounds__(256) void k_acx_dots(const Ctrl *ctrl, const int32_t *state, const double *z,
                                                   const double *f1, const double *f2, const double *f3, int64_t ld,
-                                                  int64_t n, int64_t kc, int32_t p, int64_t rows_per, double *part) {
+                                                  int64_t n, int64_t kc, int32_t p, int32_t cw, int64_t rows_per,
+                                                  double *part) {
     if (ctrl->error || ctrl->done) return;
-    __shared__ double sh[4][2][64];
-    const int cx = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int64_t c = (int64_t)blockIdx.x * 64 + cx;
+    __shared__ double sh[2][256];
+    const int cx = threadIdx.x % cw, g = threadIdx.x / cw, ng = 256 / cw;
+    const int64_t c = (int64_t)blockIdx.x * cw + cx;
     const bool act = c < kc && state[c] == COL_ACTIVE;
     double dot = 0.0, nrm = 0.0;
     if (act) {
         const int64_t r0 = (int64_t)blockIdx.y * rows_per;
         const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
-        for (int64_t j = r0 + g; j < r1; j += 4) {
+        for (int64_t j = r0 + g; j < r1; j += ng) {
             const int64_t e = j * ld + c;
             double d1, d2, d3;
             diffs(p, z[e], f1[e], f2[e], p == 3 ? f3[e] : 0.0, d1, d2, d3);
@@ -52,12 +53,17 @@ __global__ __launch_bounds__(256) void k_acx_dots(const Ctrl *ctrl, const int32_
             nrm += hi * hi;
         }
     }
-    sh[g][0][cx] = dot;
-    sh[g][1][cx] = nrm;
+    sh[0][threadIdx.x] = dot;
+    sh[1][threadIdx.x] = nrm;
     __syncthreads();
     if (g == 0 && c < kc) {
-        part[((int64_t)blockIdx.y * kc + c) * 2] = ((sh[0][0][cx] + sh[1][0][cx]) + sh[2][0][cx]) + sh[3][0][cx];
-        part[((int64_t)blockIdx.y * kc + c) * 2 + 1] = ((sh[0][1][cx] + sh[1][1][cx]) + sh[2][1][cx]) + sh[3][1][cx];
+        double sd = 0.0, sn = 0.0;
+        for (int q = 0; q < ng; ++q) {
+            sd += sh[0][q * cw + cx];
+            sn += sh[1][q * cw + cx];
+        }
+        part[((int64_t)blockIdx.y * kc + c) * 2] = sd;
+        part[((int64_t)blockIdx.y * kc + c) * 2 + 1] = sn;
     }
 }
 
@@ -93,18 +99,30 @@ __global__ void k_acx_update(const Ctrl *ctrl, const int32_t *state, double *z, 
 
 }  // namespace
 
-int acx_splits(int64_t n) {
-    const int64_t s = (n + ACX_ROWS - 1) / ACX_ROWS;
-    return (int)(s < 1 ? 1 : (s > ACX_MAX_SPLITS ? ACX_MAX_SPLITS : s));
+static int acx_cw(int64_t kc) {
+    int cw = 1;
+    while (cw < kc && cw < 64) cw <<= 1;
+    return cw;
+}
+
+// Row splits: enough blocks to fill the chip (about 1024), at least 64 rows each.
+int acx_splits(int64_t n, int64_t kc) {
+    const int64_t col_blocks = (kc + acx_cw(kc) - 1) / acx_cw(kc);
+    int64_t s = (1024 + col_blocks - 1) / col_blocks;
+    const int64_t by_rows = (n + 63) / 64;
+    if (s > by_rows) s = by_rows;
+    if (s > ACX_MAX_SPLITS) s = ACX_MAX_SPLITS;
+    return (int)(s < 1 ? 1 : s);
 }
 
 hipError_t launch_acx(hipStream_t s, const Ctrl *ctrl, const int32_t *state, double *z, const double *f1,
                       const double *f2, const double *f3, int64_t ld, int64_t n, int64_t kc, int32_t p, double *part,
                       double *sigma) {
-    const int splits = acx_splits(n);
+    const int splits = acx_splits(n, kc);
     const int64_t rows_per = (n + splits - 1) / splits;
-    dim3 g1((unsigned)((kc + 63) / 64), (unsigned)splits);
-    k_acx_dots<<<g1, 256, 0, s>>>(ctrl, state, z, f1, f2, f3, ld, n, kc, p, rows_per, part);
+    const int cw = acx_cw(kc);
+    dim3 g1((unsigned)((kc + cw - 1) / cw), (unsigned)splits);
+    k_acx_dots<<<g1, 256, 0, s>>>(ctrl, state, z, f1, f2, f3, ld, n, kc, p, cw, rows_per, part);
     k_acx_sigma<<<(unsigned)((kc + 255) / 256), 256, 0, s>>>(ctrl, state, part, splits, kc, sigma);
     const int64_t total = n * kc;
     int64_t blocks = (total + 255) / 256;

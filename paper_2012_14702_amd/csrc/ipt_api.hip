@@ -202,15 +202,6 @@ PollPlan poll_plan(const ipt_opts &o, bool cold) {
     return PollPlan{cold ? 4 : 3, 1};
 }
 
-// Reads the error/done words of the control block (one small copy and a wait).
-ipt_status poll_ctrl(ipt_handle h, Ctrl *dev, int32_t &error, int32_t &done) {
-    IPT_HIP(h, hipMemcpyAsync(h->host_ctrl, dev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-    IPT_HIP(h, hipStreamSynchronize(h->stream));
-    error = h->host_ctrl->error;
-    done = h->host_ctrl->done;
-    return IPT_OK;
-}
-
 ipt_status finish(ipt_handle h, Ctrl *dev, int64_t k, ipt_info *info, Timer *timer) {
     IPT_HIP(h, hipEventRecord(h->ev_stop, h->stream));
     IPT_HIP(h, hipMemcpyAsync(h->host_ctrl, dev, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
@@ -236,6 +227,31 @@ ipt_status ensure_poll(ipt_handle h) {
     IPT_HIP(h, hipHostMalloc((void **)&h->poll_host, 4 * sizeof(int32_t), hipHostMallocDefault));
     return IPT_OK;
 }
+
+// Look-ahead polling of the device stop words: each poll enqueues a copy of them
+// and then waits for the previous poll's copy, so the sweeps launched in between
+// keep the device busy (sweeps launched after the device stopped return at once).
+// The first poll, placed where the solve is expected to stop, waits for itself.
+struct LookaheadPoll {
+    ipt_handle h;
+    const Ctrl *ctrl;
+    int pend = -1, slot = 0;
+    bool first = true;
+    ipt_status push(bool &stop) {
+        stop = false;
+        IPT_HIP(h, hipMemcpyAsync(h->poll_host + 2 * slot, ctrl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        IPT_HIP(h, hipEventRecord(h->poll_ev[slot], h->stream));
+        const int wait = first ? slot : pend;
+        first = false;
+        if (wait >= 0) {
+            IPT_HIP(h, hipEventSynchronize(h->poll_ev[wait]));
+            stop = h->poll_host[2 * wait] != 0 || h->poll_host[2 * wait + 1] != 0;
+        }
+        pend = (wait == slot) ? -1 : slot;
+        slot ^= 1;
+        return IPT_OK;
+    }
+};
 
 // Everything a captured chunk of batched sweeps depends on; the graph is reused
 // while these bytes are unchanged.
@@ -453,7 +469,7 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
     // Later sweeps in chunks; the host reads the stop words of chunk i while chunk
     // i + 1 runs (sweeps launched after the device stopped return at once).
     int32_t launched = 1;
-    int pend = -1, slot = 0;
+    LookaheadPoll poll{h, ctrl};
     while (launched < o.max_iter) {
         if (use_graph) {
             IPT_HIP(h, hipGraphLaunch(h->bgraph, s));
@@ -463,14 +479,9 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
             for (int32_t q = 0; q < m; ++q) IPT_HIP(h, sweep(s, launched + q + 1));
             launched += m;
         }
-        IPT_HIP(h, hipMemcpyAsync(h->poll_host + 2 * slot, ctrl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        IPT_HIP(h, hipEventRecord(h->poll_ev[slot], s));
-        if (pend >= 0) {
-            IPT_HIP(h, hipEventSynchronize(h->poll_ev[pend]));
-            if (h->poll_host[2 * pend] || h->poll_host[2 * pend + 1]) break;
-        }
-        pend = slot;
-        slot ^= 1;
+        bool stop;
+        if (ipt_status st = poll.push(stop)) return st;
+        if (stop) break;
     }
     IPT_HIP(h, launch_bcopyout(s, ctrl, L, ds1, (int64_t)it_s1.size(), z_pool, lambda_pool, status_pool, maxres));
     ipt_status st = finish(h, ctrl, total_cols, info, &timer);
@@ -598,7 +609,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         zb[1] = cv.take<double>(np * kp);
         zb[2] = acx ? cv.take<double>(np * kp) : nullptr;
         zb[3] = acx ? cv.take<double>(np * kp) : nullptr;
-        acx_part = acx ? cv.take<double>((size_t)acx_splits(n) * kp * 2) : nullptr;
+        acx_part = acx ? cv.take<double>((size_t)acx_splits(n, kp) * kp * 2) : nullptr;
         acx_sigma = acx ? cv.take<double>(kp) : nullptr;
         *dpart = cv.take<double>(DIAG_SPLIT * kp);
         *dvec = cv.take<double>(kp);
@@ -658,6 +669,8 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     }
 
     const PollPlan plan = poll_plan(o, cold);
+    if (ipt_status st = ensure_poll(h)) return st;
+    LookaheadPoll poll{h, ctrl};
     for (int32_t t = 1; t <= o.max_iter; ++t) {
         const bool first_exact = cold && t == 1;
         // Plain sweeps ping-pong between two buffers; an ACX cycle runs slot q -> q + 1
@@ -684,9 +697,9 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         if (acx && q == pc - 1)
             IPT_HIP(h, launch_acx(s, ctrl, cs.state, zb[0], zb[1], zb[2], zb[3], kp, n, kp, pc, acx_part, acx_sigma));
         if (plan.at(t, o.max_iter)) {
-            int32_t err, done;
-            if (ipt_status st = poll_ctrl(h, ctrl, err, done)) return st;
-            if (err || done) break;
+            bool stop;
+            if (ipt_status st = poll.push(stop)) return st;
+            if (stop) break;
         }
     }
     IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lambda_out, col_status, n, k, ci));
@@ -728,7 +741,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         zb[1] = cv.take<double>(n * ldzb);
         zb[2] = acx ? cv.take<double>(n * ldzb) : nullptr;
         zb[3] = acx ? cv.take<double>(n * ldzb) : nullptr;
-        acx_part = acx ? cv.take<double>((size_t)acx_splits(n) * kpc * 2) : nullptr;
+        acx_part = acx ? cv.take<double>((size_t)acx_splits(n, k) * kpc * 2) : nullptr;
         acx_sigma = acx ? cv.take<double>(kpc) : nullptr;
         zlo[0] = ladder ? cv.take<float>(n * ldzb) : nullptr;
         zlo[1] = ladder ? cv.take<float>(n * ldzb) : nullptr;
@@ -785,6 +798,8 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
 
     PollPlan plan = poll_plan(o, cold);
     if (o.sync_every <= 0) plan.first = cold ? 3 : 2;  // sparse near-diagonal solves take few sweeps
+    if (ipt_status st = ensure_poll(h)) return st;
+    LookaheadPoll poll{h, ctrl};
     for (int32_t t = 1; t <= o.max_iter; ++t) {
         int32_t q, pc;
         acx_phase(dopt.acx, t, q, pc);
@@ -802,9 +817,9 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         if (acx && q == pc - 1)
             IPT_HIP(h, launch_acx(s, ctrl, cs.state, zb[0], zb[1], zb[2], zb[3], ldzb, n, k, pc, acx_part, acx_sigma));
         if (plan.at(t, o.max_iter)) {
-            int32_t err, done;
-            if (ipt_status st = poll_ctrl(h, ctrl, err, done)) return st;
-            if (err || done) break;
+            bool stop;
+            if (ipt_status st = poll.push(stop)) return st;
+            if (stop) break;
         }
     }
     IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], ldzb, z_out, ldz, lambda_out, col_status, n, k, ci));

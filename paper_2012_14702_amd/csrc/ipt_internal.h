@@ -224,7 +224,7 @@ hipError_t mlp_warm_start(hipStream_t s, const float *y, int64_t ldy, const floa
 // dimension ld, kc columns with states `state`) after a cycle of order p
 // (ipt_acx.hip): per-column dot and squared norm of the two highest differences in
 // row-range partials, sigma, and the in-place update of z for the active columns.
-int acx_splits(int64_t n);
+int acx_splits(int64_t n, int64_t kc);  // row splits of the partial sums (workspace: splits x kc x 2)
 hipError_t launch_acx(hipStream_t s, const Ctrl *ctrl, const int32_t *state, double *z, const double *f1,
                       const double *f2, const double *f3, int64_t ld, int64_t n, int64_t kc, int32_t p, double *part,
                       double *sigma);
