@@ -602,7 +602,12 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
 
     // Workspace layout (sizes first, then carve).
     const bool acx = dopt.acx != 0;
-    double *acx_part = nullptr, *acx_sigma = nullptr;
+    double *acx_part = nullptr, *acx_sigma = nullptr, *ypart = nullptr;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
+        cus = 256;
+    const int nblk = 2 * cus;  // the sweep GEMM keeps two 256-thread blocks per CU
+    const SplitBounds sb = split_bounds(np, kp, nblk);
     auto layout = [&](Carve &cv, double **zb, ColState &cs, double **dpart, double **dvec, double **part, uint32_t **bitmap,
                       double **scratch, double **dpad, void **dlo, float **d32, void **zt, Ctrl **ctrl) {
         zb[0] = cv.take<double>(np * kp);
@@ -611,6 +616,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         zb[3] = acx ? cv.take<double>(np * kp) : nullptr;
         acx_part = acx ? cv.take<double>((size_t)acx_splits(n, kp) * kp * 2) : nullptr;
         acx_sigma = acx ? cv.take<double>(kp) : nullptr;
+        ypart = sb.ypart_tiles ? cv.take<double>((size_t)sb.ypart_tiles * TILE_M * TILE_N) : nullptr;
         *dpart = cv.take<double>(DIAG_SPLIT * kp);
         *dvec = cv.take<double>(kp);
         *part = cv.take<double>(nrt * kp * NPART);
@@ -620,6 +626,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         cs.par = cv.take<int32_t>(kp);
         cs.idx = cv.take<int32_t>(kp);
         cs.tile_stamp = cv.take<int32_t>(ntn < kp ? kp : ntn);
+        cs.alist = cv.take<int32_t>(kp);
         cs.prev = cv.take<double>(kp);
         cs.step = cv.take<double>(kp);
         cs.lam = cv.take<double>(kp);
@@ -652,6 +659,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     const int32_t start_prec = cold ? PREC_EXACT_FIRST : (ladder ? PREC_F32 : PREC_F64);
     IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kp, bitmap, start_prec, (int32_t)ntn, 0));
     IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
+    IPT_HIP(h, launch_plan_dense(s, ctrl, cs, kp));
     if (use_low && lt == LT_F16) IPT_HIP(h, launch_absmax(s, ctrl, delta, n, n, lda));
     const double *dA = direct ? delta : dpad;
     const int64_t ldA = direct ? lda : np;
@@ -689,11 +697,11 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
             IPT_HIP(h, launch_diag_dense(s, ctrl, dA, ldA, zin, kp, cs, dpart, dvec, n, kp));
             IPT_HIP(h, timer.mark(t, 0, s));
             IPT_HIP(h, launch_sweep_gemm(s, ctrl, dA, ldA, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, t,
-                                         lt));
+                                         lt, ypart, nblk));
             IPT_HIP(h, timer.mark(t, 1, s));
         }
         IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, nrt, kp, t, in_par, out_par));
-        IPT_HIP(h, launch_control(s, ctrl, dopt, t));
+        IPT_HIP(h, launch_control_plan(s, ctrl, dopt, t, cs, kp));
         if (acx && q == pc - 1)
             IPT_HIP(h, launch_acx(s, ctrl, cs.state, zb[0], zb[1], zb[2], zb[3], kp, n, kp, pc, acx_part, acx_sigma));
         if (plan.at(t, o.max_iter)) {
@@ -753,6 +761,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         cs.par = cv.take<int32_t>(kpc);
         cs.idx = cv.take<int32_t>(kpc);
         cs.tile_stamp = cv.take<int32_t>(kpc / TILE_N + 1);
+        cs.alist = nullptr;
         cs.prev = cv.take<double>(kpc);
         cs.step = cv.take<double>(kpc);
         cs.lam = cv.take<double>(kpc);

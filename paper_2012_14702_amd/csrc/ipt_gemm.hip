@@ -6,6 +6,9 @@
 // kernel).  By F(Z) - Z = -G o (M Z - Z Lambda), the third sum is the squared
 // eigen-residual |M z - lambda z|^2 of the column.
 //
+// Column tiles run over the packed active columns (ColState::alist, rebuilt after
+// every finalize), so frozen columns cost nothing; the B operand gathers them.
+//
 // One kernel per sweep; the precision of the sweep is read from the device control
 // block (the ladder is decided on the device, so the host never waits between
 // sweeps) and selects one of two bodies:
@@ -64,6 +67,34 @@ struct GemmArgs {
     double *part;         // partial sums [row tile][column][NPART]
     int64_t n, np, kp;
     int32_t low_type;     // LT_BF16 or LT_F16
+    double *ypart;        // split-K partial products of narrow sweeps
+    int32_t nblk;         // blocks that fill the chip (2 per CU)
+};
+
+// Narrow sweeps: when the packed active columns give fewer tiles than nblk, the K
+// range is split S ways (S >= 2); each split writes its FP64 partial tile and a
+// separate kernel sums the partials in split order and runs the epilogue.
+constexpr int SPLIT_MAX = 16;
+struct SplitPlan {
+    int nct, S;
+};
+__host__ __device__ inline SplitPlan split_plan(int64_t kact, int ntm, int64_t np, int nblk) {
+    SplitPlan sp;
+    sp.nct = (int)((kact + BN - 1) / BN);
+    const int64_t reg = (int64_t)ntm * sp.nct;
+    int64_t S = reg > 0 && reg < nblk ? (nblk + reg - 1) / reg : 1;
+    if (S > SPLIT_MAX) S = SPLIT_MAX;
+    if (S > np / 64) S = np / 64;
+    sp.S = S >= 2 ? (int)S : 1;
+    return sp;
+}
+
+// The packed columns of one column tile: position i (< BN) holds column cols[i] when
+// i < lim, no column otherwise.
+struct PackedCols {
+    const int32_t *cols;
+    int32_t lim;
+    __device__ int32_t operator[](int i) const { return i < lim ? cols[i] : -1; }
 };
 
 constexpr int SMEM_F64 = 2 * BM * (16 + 1) * 8 + 2 * 16 * BN * 8;
@@ -76,20 +107,20 @@ constexpr int SMEM_MAIN = cmax(SMEM_F64, cmax(SMEM_LOW16, SMEM_LOW32));
 // tile; row_of(ib, r) gives the tile row of accumulator (ib, r), which depends on
 // the MFMA family.  y_of(ib, jb, r, j, i) returns the FP64 product value.
 template <class RowOf, class YOf>
-__device__ inline void sweep_epilogue(const GemmArgs &e, int tm, int tn, int wm, int wn, int lane, RowOf row_of,
-                                      YOf y_of, double (*red)[BN][NPART]) {
+__device__ inline void sweep_epilogue(const GemmArgs &e, const PackedCols scol, int tm, int wm, int wn, int lane,
+                                      RowOf row_of, YOf y_of, double (*red)[BN][NPART]) {
     int64_t cols[4];
     int32_t ii[4];
     double ti[4], dd[4];
     bool act[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
-        const int64_t c = (int64_t)tn * BN + wn * 64 + 16 * jb + (lane & 15);
+        const int32_t c = scol[wn * 64 + 16 * jb + (lane & 15)];  // packed position -> column
         cols[jb] = c;
-        act[jb] = e.cs.state[c] == COL_ACTIVE;
-        ii[jb] = e.cs.idx[c];
-        ti[jb] = e.theta[ii[jb]];
-        dd[jb] = e.dvec[c];
+        act[jb] = c >= 0 && e.cs.state[c] == COL_ACTIVE;
+        ii[jb] = act[jb] ? e.cs.idx[c] : 0;
+        ti[jb] = act[jb] ? e.theta[ii[jb]] : 0.0;
+        dd[jb] = act[jb] ? e.dvec[c] : 0.0;
     }
     const int64_t ldzb = e.kp;
     double sums[4][NPART];
@@ -151,17 +182,21 @@ __device__ inline void sweep_epilogue(const GemmArgs &e, int tm, int tn, int wm,
     __syncthreads();
     const int t = threadIdx.x;
     if (t < BN) {
-        const int64_t c = (int64_t)tn * BN + t;
+        const int32_t c = scol[t];
+        if (c >= 0) {
 #pragma unroll
-        for (int q = 0; q < NPART; ++q) e.part[((int64_t)tm * e.kp + c) * NPART + q] = red[0][t][q] + red[1][t][q];
+            for (int q = 0; q < NPART; ++q)
+                e.part[((int64_t)tm * e.kp + c) * NPART + q] = red[0][t][q] + red[1][t][q];
+        }
     }
 }
 
 // ------------------------------------------------------------------- FP64
 constexpr int BK64 = 16;
 
-__device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPART], const GemmArgs &g, int tm,
-                                              int tn) {
+template <bool SPLIT>
+__device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPART], const PackedCols scol,
+                                              const GemmArgs &g, int tm, int64_t k0, int64_t k1, double *yp) {
     typedef double ATile[BM][BK64 + 1];
     typedef double BTile[BK64][BN];
     ATile *As = (ATile *)smem;
@@ -170,9 +205,16 @@ __device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPAR
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
     const int64_t lda = g.lda, ldzb = g.kp;
     const double *Ab = g.delta + (int64_t)tm * BM * lda;
-    const double *Bb = g.zin + (int64_t)tn * BN;
+    // B loader.  Contiguous packed columns (every column of the tile active, the usual
+    // case): thread -> column pair 2cp, 2cp + 1 and rows rg + 4q, 16-byte loads.
+    // Otherwise one gathered column per thread, rows b_r + 2q.
     const int a_r = t >> 3, a_k = 2 * (t & 7);
-    const int b_r = t >> 4, b_c = (t & 15) * 8;
+    const int b_c = t & (BN - 1), b_r = t >> 7;
+    const int cp = t & 63, rg = t >> 6;
+    const int32_t c_first = scol[0];
+    const bool contig = scol.lim >= BN && scol[BN - 1] == c_first + BN - 1;
+    const int32_t cg = contig ? c_first + 2 * cp : scol[b_c];
+    const double *Bc = g.zin + (cg >= 0 ? cg : 0);
 
     d4_t acc[4][4];
 #pragma unroll
@@ -184,26 +226,47 @@ __device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPAR
     // slice, written to the idle LDS stage after them (one barrier per slice).  The
     // last iteration re-reads its own slice into the idle stage, which keeps the
     // loop free of branches.
-    double2 ra[4], rb[4];
-    const int nk = (int)(g.np / BK64);
+    double2 ra[4];
+    double rb[8];
+    const int nk = (int)((k1 - k0) / BK64);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ra[q] = *(const double2 *)(Ab + (int64_t)(a_r + 32 * q) * lda + a_k);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) rb[q] = *(const double2 *)(Bb + (int64_t)b_r * ldzb + b_c + 2 * q);
+    for (int q = 0; q < 4; ++q) ra[q] = *(const double2 *)(Ab + (int64_t)(a_r + 32 * q) * lda + k0 + a_k);
+#define IPT_F64_BLOAD(K)                                                                        \
+    do {                                                                                        \
+        if (contig) {                                                                           \
+            _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                     \
+                const double2 v = *(const double2 *)(Bc + ((K) + rg + 4 * q) * ldzb);          \
+                rb[2 * q] = v.x;                                                                \
+                rb[2 * q + 1] = v.y;                                                            \
+            }                                                                                   \
+        } else {                                                                                \
+            _Pragma("unroll") for (int q = 0; q < 8; ++q) rb[q] =                               \
+                cg >= 0 ? Bc[((K) + b_r + 2 * q) * ldzb] : 0.0;                                 \
+        }                                                                                       \
+    } while (0)
+#define IPT_F64_BSTORE(S)                                                                       \
+    do {                                                                                        \
+        if (contig) {                                                                           \
+            _Pragma("unroll") for (int q = 0; q < 4; ++q)                                       \
+                *(double2 *)&Bs[S][rg + 4 * q][2 * cp] = double2{rb[2 * q], rb[2 * q + 1]};     \
+        } else {                                                                                \
+            _Pragma("unroll") for (int q = 0; q < 8; ++q) Bs[S][b_r + 2 * q][b_c] = rb[q];      \
+        }                                                                                       \
+    } while (0)
+    IPT_F64_BLOAD(k0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         As[0][a_r + 32 * q][a_k] = ra[q].x;
         As[0][a_r + 32 * q][a_k + 1] = ra[q].y;
-        *(double2 *)&Bs[0][b_r][b_c + 2 * q] = rb[q];
     }
+    IPT_F64_BSTORE(0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        const int64_t kn = (int64_t)(kt + 1 < nk ? kt + 1 : kt) * BK64;
+        const int64_t kn = k0 + (int64_t)(kt + 1 < nk ? kt + 1 : kt) * BK64;
 #pragma unroll
         for (int q = 0; q < 4; ++q) ra[q] = *(const double2 *)(Ab + (int64_t)(a_r + 32 * q) * lda + kn + a_k);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rb[q] = *(const double2 *)(Bb + (kn + b_r) * ldzb + b_c + 2 * q);
+        IPT_F64_BLOAD(kn);
 #pragma unroll
         for (int kk = 0; kk < BK64 / 4; ++kk) {
             double fa[4], fb[4];
@@ -222,15 +285,27 @@ __device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPAR
         for (int q = 0; q < 4; ++q) {
             As[nx][a_r + 32 * q][a_k] = ra[q].x;
             As[nx][a_r + 32 * q][a_k + 1] = ra[q].y;
-            *(double2 *)&Bs[nx][b_r][b_c + 2 * q] = rb[q];
         }
+        IPT_F64_BSTORE(nx);
         __syncthreads();
     }
+#undef IPT_F64_BLOAD
+#undef IPT_F64_BSTORE
 
     // v_mfma_f64_16x16x4f64: lane l, register r holds row 4r + l/16, column l%16.
     auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * r + (l >> 4); };
-    auto y_of = [&](int ib, int jb, int r, int64_t, int32_t) { return acc[ib][jb][r]; };
-    sweep_epilogue(g, tm, tn, wm, wn, lane, row_of, y_of, red);
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    yp[(int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15)] = acc[ib][jb][r];
+    } else {
+        auto y_of = [&](int ib, int jb, int r, int64_t, int32_t) { return acc[ib][jb][r]; };
+        sweep_epilogue(g, scol, tm, wm, wn, lane, row_of, y_of, red);
+    }
 }
 
 // ------------------------------------------------------------ low precision
@@ -289,9 +364,10 @@ __device__ __forceinline__ void lds_put(T (*as)[LDP], T (*bs)[LDP], const uint4 
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPART], const GemmArgs &g, const T *dlo,
-                                              double unscale, int tm, int tn) {
+template <typename T, bool SPLIT>
+__device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPART], const PackedCols scol,
+                                              const GemmArgs &g, const T *dlo, double unscale, int tm, int64_t k0,
+                                              int64_t k1, double *yp) {
     using C = LowCfg<T>;
     constexpr int BK = C::BK, LDP = C::BK + C::PAD;
     typedef T Tile[BM][LDP];
@@ -305,7 +381,14 @@ __device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPAR
     const int l_r = t >> 3, l_c = (t & 7) * EPC;
     const int64_t ldd = g.np, ldt = g.np;
     const T *Ab = dlo + (int64_t)tm * BM * ldd;
-    const T *Bb = (const T *)g.zt + (int64_t)tn * BN * ldt;
+    // B rows are the transposed shadows of the tile's packed columns (-1: zeros)
+    const T *zt = (const T *)g.zt;
+    int64_t boff[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int32_t cg = scol[l_r + 32 * q];
+        boff[q] = cg >= 0 ? (int64_t)cg * ldt + l_c : -1;
+    }
 
     f4_t acc[4][4];
 #pragma unroll
@@ -314,20 +397,22 @@ __device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPAR
         for (int b = 0; b < 4; ++b) acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
 
     uint4 ra[4], rb[4];
-    const int nk = (int)(g.np / BK);
+    const int nk = (int)((k1 - k0) / BK);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ra[q] = *(const uint4 *)(Ab + (int64_t)(l_r + 32 * q) * ldd + l_c);
+    for (int q = 0; q < 4; ++q) ra[q] = *(const uint4 *)(Ab + (int64_t)(l_r + 32 * q) * ldd + k0 + l_c);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) rb[q] = *(const uint4 *)(Bb + (int64_t)(l_r + 32 * q) * ldt + l_c);
+    for (int q = 0; q < 4; ++q)
+        rb[q] = boff[q] >= 0 ? *(const uint4 *)(zt + boff[q] + k0) : uint4{0u, 0u, 0u, 0u};
     lds_put<T, EPC, LDP>(As[0], Bs[0], ra, rb, l_r, l_c);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        const int64_t kn = (int64_t)(kt + 1 < nk ? kt + 1 : kt) * BK;
+        const int64_t kn = k0 + (int64_t)(kt + 1 < nk ? kt + 1 : kt) * BK;
 #pragma unroll
         for (int q = 0; q < 4; ++q) ra[q] = *(const uint4 *)(Ab + (int64_t)(l_r + 32 * q) * ldd + kn + l_c);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rb[q] = *(const uint4 *)(Bb + (int64_t)(l_r + 32 * q) * ldt + kn + l_c);
+        for (int q = 0; q < 4; ++q)
+            rb[q] = boff[q] >= 0 ? *(const uint4 *)(zt + boff[q] + kn) : uint4{0u, 0u, 0u, 0u};
 #pragma unroll
         for (int kk = 0; kk < BK / C::KSTEP; ++kk) {
             const int koff = kk * C::KSTEP + C::VEC * (lane >> 4);
@@ -346,32 +431,99 @@ __device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPAR
     const double *delta = g.delta;
     const int64_t lda = g.lda;
     auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * (l >> 4) + r; };
-    auto y_of = [&](int ib, int jb, int r, int64_t j, int32_t i) {
-        return delta[j * lda + i] + unscale * (double)acc[ib][jb][r];
-    };
-    sweep_epilogue(g, tm, tn, wm, wn, lane, row_of, y_of, red);
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    yp[(int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15)] =
+                        unscale * (double)acc[ib][jb][r];
+    } else {
+        auto y_of = [&](int ib, int jb, int r, int64_t j, int32_t i) {
+            return delta[j * lda + i] + unscale * (double)acc[ib][jb][r];
+        };
+        sweep_epilogue(g, scol, tm, wm, wn, lane, row_of, y_of, red);
+    }
 }
 
-// One sweep's product and epilogue, in the precision the ladder chose for it.
-__global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArgs g, int32_t sweep) {
-    if (ctrl->error || ctrl->done) return;
+// The sweep's product over the K range [k0, k1), in the precision the ladder chose;
+// SPLIT writes the partial tile instead of running the epilogue.
+template <bool SPLIT>
+__device__ __forceinline__ void sweep_tile(const Ctrl *ctrl, const GemmArgs &g, char *smem, double (*red)[BN][NPART],
+                                           const PackedCols scol, int tm, int64_t k0, int64_t k1, double *yp) {
     const int32_t prec = ctrl->prec;
-    const int ntm = (int)(g.np / BM), ntn = (int)(g.kp / BN);
-    int tm, tn;
-    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
-    if (g.cs.tile_stamp[tn] != sweep - 1) return;  // no active column in this column tile
-    __shared__ __attribute__((aligned(16))) char smem[SMEM_MAIN];
-    __shared__ double red[2][BN][NPART];
     if (prec == PREC_F64) {
-        gemm_f64_body(smem, red, g, tm, tn);
+        gemm_f64_body<SPLIT>(smem, red, scol, g, tm, k0, k1, yp);
     } else if (prec == PREC_F32) {
-        gemm_low_body<float>(smem, red, g, g.d32, 1.0, tm, tn);
+        gemm_low_body<float, SPLIT>(smem, red, scol, g, g.d32, 1.0, tm, k0, k1, yp);
     } else if (prec == PREC_LOW) {
         if (g.low_type == LT_F16)
-            gemm_low_body<_Float16>(smem, red, g, (const _Float16 *)g.dlo, 1.0 / (ctrl->dscale * ctrl->zscale), tm,
-                                    tn);
+            gemm_low_body<_Float16, SPLIT>(smem, red, scol, g, (const _Float16 *)g.dlo,
+                                           1.0 / (ctrl->dscale * ctrl->zscale), tm, k0, k1, yp);
         else
-            gemm_low_body<__bf16>(smem, red, g, (const __bf16 *)g.dlo, 1.0, tm, tn);
+            gemm_low_body<__bf16, SPLIT>(smem, red, scol, g, (const __bf16 *)g.dlo, 1.0, tm, k0, k1, yp);
+    }
+}
+
+// One sweep's product.  Sweeps with enough tiles: block -> (row tile, packed column
+// tile), whole K range, fused epilogue.  Narrow sweeps: block -> (split s, packed
+// column tile, row tile) over a K range, partial tile written for k_sweep_split_epi.
+__global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArgs g, int32_t regular_blocks) {
+    if (ctrl->error || ctrl->done) return;
+    const int ntm = (int)(g.np / BM), ntn = (int)(g.kp / BN);
+    const int32_t kact = ctrl->kact;
+    const SplitPlan sp = split_plan(kact, ntm, g.np, g.nblk);
+    __shared__ __attribute__((aligned(16))) char smem[SMEM_MAIN];
+    __shared__ double red[2][BN][NPART];
+    if (sp.S < 2) {
+        if ((int)blockIdx.x >= regular_blocks) return;
+        int tm, tn;
+        tile_of(blockIdx.x, regular_blocks, ntm, ntn, tm, tn);
+        // column tiles run over the packed active columns; tiles past them have no work
+        if ((int64_t)tn * BN >= kact) return;
+        const PackedCols scol{g.cs.alist + (int64_t)tn * BN, (int32_t)(kact - (int64_t)tn * BN)};
+        sweep_tile<false>(ctrl, g, smem, red, scol, tm, 0, g.np, nullptr);
+    } else {
+        const int64_t per = (int64_t)ntm * sp.nct;
+        if ((int64_t)blockIdx.x >= per * sp.S) return;
+        const int s = (int)(blockIdx.x / per), rest = (int)(blockIdx.x % per);
+        const int tn = rest / ntm, tm = rest % ntm;
+        const int64_t nk64 = g.np / 64;
+        const int64_t k0 = (int64_t)s * nk64 / sp.S * 64, k1 = (int64_t)(s + 1) * nk64 / sp.S * 64;
+        const PackedCols scol{g.cs.alist + (int64_t)tn * BN, (int32_t)(kact - (int64_t)tn * BN)};
+        double *yp = g.ypart + (((int64_t)s * sp.nct + tn) * ntm + tm) * (int64_t)(BM * BN);
+        sweep_tile<true>(ctrl, g, smem, nullptr, scol, tm, k0, k1, yp);
+    }
+}
+
+// Narrow sweep, epilogue: Y of the tile = the split partials summed in split order.
+// A small grid walks the tiles, so that sweeps with enough tiles pay little for it.
+__global__ __launch_bounds__(256, 1) void k_sweep_split_epi(const Ctrl *ctrl, GemmArgs g) {
+    if (ctrl->error || ctrl->done) return;
+    const int ntm = (int)(g.np / BM);
+    const int32_t kact = ctrl->kact;
+    const SplitPlan sp = split_plan(kact, ntm, g.np, g.nblk);
+    if (sp.S < 2) return;
+    __shared__ double red[2][BN][NPART];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+    const bool low = ctrl->prec != PREC_F64;
+    const int64_t tile = (int64_t)BM * BN, stride = (int64_t)sp.nct * ntm * tile;
+    auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * r + (l >> 4); };
+    for (int64_t bt = blockIdx.x; bt < (int64_t)ntm * sp.nct; bt += gridDim.x) {
+        const int tn = (int)(bt / ntm), tm = (int)(bt % ntm);
+        const PackedCols scol{g.cs.alist + (int64_t)tn * BN, (int32_t)(kact - (int64_t)tn * BN)};
+        const double *y0 = g.ypart + ((int64_t)tn * ntm + tm) * tile;
+        auto y_of = [&](int ib, int jb, int r, int64_t j, int32_t i) {
+            const int64_t e = (int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15);
+            double y = 0.0;
+#pragma unroll 1
+            for (int q = 0; q < sp.S; ++q) y += y0[q * stride + e];
+            return low ? g.delta[j * g.lda + i] + y : y;  // low precision: split form, Delta E exact
+        };
+        sweep_epilogue(g, scol, tm, wm, wn, lane, row_of, y_of, red);
+        __syncthreads();
     }
 }
 
@@ -380,11 +532,32 @@ __global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArg
 hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const void *dlo,
                              const float *d32, const void *zt, const double *zin, double *zout, const double *theta,
                              ColState cs, const double *dvec, double *part, int64_t n, int64_t np, int64_t kp,
-                             int32_t sweep, int32_t low_type) {
-    GemmArgs g{delta, lda, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, low_type};
+                             int32_t sweep, int32_t low_type, double *ypart, int nblk) {
+    GemmArgs g{delta, lda, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, low_type, ypart, nblk};
+    (void)sweep;
     const int blocks = (int)((np / BM) * (kp / BN));
-    k_sweep_gemm<<<blocks, 256, 0, s>>>(ctrl, g, sweep);
+    const SplitBounds b = split_bounds(np, kp, nblk);
+    const int64_t grid = b.split_blocks > blocks ? b.split_blocks : blocks;
+    k_sweep_gemm<<<(unsigned)grid, 256, 0, s>>>(ctrl, g, blocks);
+    if (b.split_blocks > 0) {
+        const int64_t eg = b.epi_blocks < nblk / 2 ? b.epi_blocks : nblk / 2;
+        k_sweep_split_epi<<<(unsigned)(eg > 0 ? eg : 1), 256, 0, s>>>(ctrl, g);
+    }
     return hipGetLastError();
+}
+
+SplitBounds split_bounds(int64_t np, int64_t kp, int nblk) {
+    SplitBounds b{0, 0, 0};
+    const int ntm = (int)(np / BM);
+    for (int64_t nct = 1; nct <= kp / BN; ++nct) {
+        const SplitPlan sp = split_plan(nct * BN, ntm, np, nblk);
+        if (sp.S < 2) continue;
+        const int64_t blocks = (int64_t)ntm * nct * sp.S;
+        if (blocks > b.split_blocks) b.split_blocks = blocks;
+        if ((int64_t)ntm * nct > b.epi_blocks) b.epi_blocks = (int64_t)ntm * nct;
+        if (blocks > b.ypart_tiles) b.ypart_tiles = blocks;
+    }
+    return b;
 }
 
 }  // namespace ipt

@@ -33,6 +33,8 @@ struct Ctrl {
     int32_t acc_active;  // finalize accumulator: columns still active after this sweep
     int32_t n_conv, n_notconv, n_div;
     int32_t prec_mask;  // batched: bit PREC_F32 set when a tile of this sweep ran in FP32
+    int32_t kact;       // dense: active columns entering the next sweep (length of ColState::alist)
+    int32_t pad1;
     uint64_t acc_maxstep;  // finalize accumulator: max s_c (bit pattern of a non-negative double)
     uint64_t acc_maxres;   // max normalised eigen-residual over converged columns (bits)
     uint64_t dec_maxstep;  // max deciding step over decided columns (bits)
@@ -82,6 +84,7 @@ struct ColState {
     double *resid;    // normalised eigen-residual of the deciding sweep
     int32_t *idx;     // requested indices (padding columns hold 0)
     int32_t *tile_stamp;  // per column tile of width TILE_N: last sweep in which it had an active column
+    int32_t *alist;       // dense: the active columns in ascending order (packed positions of the GEMM)
 };
 
 constexpr int TILE_M = 128;   // rows of Delta / Y per GEMM tile, and per partial-sum row tile
@@ -100,6 +103,10 @@ constexpr int DIAG_SPLIT = 64;  // max partial sums per d_c (dpart is DIAG_SPLIT
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp);
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active);
+// Dense: list the active columns in ascending order (ColState::alist, ctrl->kact).
+hipError_t launch_plan_dense(hipStream_t s, Ctrl *ctrl, ColState cs, int64_t kp);
+// Dense: the plan of the next sweep followed by the control step, in one launch.
+hipError_t launch_control_plan(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, ColState cs, int64_t kp);
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
                               int64_t k);
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
@@ -234,7 +241,14 @@ hipError_t launch_acx(hipStream_t s, const Ctrl *ctrl, const int32_t *state, dou
 hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const void *dlo,
                              const float *d32, const void *zt, const double *zin, double *zout, const double *theta,
                              ColState cs, const double *dvec, double *part, int64_t n, int64_t np, int64_t kp,
-                             int32_t sweep, int32_t low_type);
+                             int32_t sweep, int32_t low_type, double *ypart, int nblk);
+// Launch bounds of the split-K path of narrow sweeps (grid sizes and the tiles of
+// the partial-product workspace, each 128 x 128 FP64); all zero when no packed width
+// of this shape is narrow.
+struct SplitBounds {
+    int64_t split_blocks, epi_blocks, ypart_tiles;
+};
+SplitBounds split_bounds(int64_t np, int64_t kp, int nblk);
 
 
 }  // namespace ipt

@@ -428,11 +428,65 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
     wave_count(&ctrl->n_notconv, decided == COL_NOT_CONVERGED);
 }
 
+// The active columns in ascending order: the packed column positions of the next
+// dense sweep's GEMM (one block of 1024 threads; a block-wide scan per 1024 columns).
+__device__ void plan_dense(Ctrl *ctrl, ColState cs, int64_t kp) {
+    __shared__ int32_t s_w[16];
+    __shared__ int32_t s_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < kp; c0 += 1024) {
+        const int64_t c = c0 + threadIdx.x;
+        const int act = (c < kp && cs.state[c] == COL_ACTIVE) ? 1 : 0;
+        int inc = act;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(inc, off);
+            if (lane >= off) inc += o;
+        }
+        if (lane == 63) s_w[wave] = inc;
+        __syncthreads();
+        int pos = s_base + inc - act;
+        for (int w2 = 0; w2 < wave; ++w2) pos += s_w[w2];
+        if (act) cs.alist[pos] = (int32_t)c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w2 = 0; w2 < 16; ++w2) tot += s_w[w2];
+            s_base += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctrl->kact = s_base;
+}
+
+__global__ __launch_bounds__(1024) void k_plan_dense(Ctrl *ctrl, ColState cs, int64_t kp) {
+    if (ctrl->error || ctrl->done) return;
+    plan_dense(ctrl, cs, kp);
+}
+
 // Bookkeeping after sweep t and the precision of sweep t+1 (the ladder): leave the
 // low rung when the max step is <= tau_low or stops falling, leave FP32 when it is
 // <= tau_32 or stops falling; FP64 is final.
+__device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep);
+
 __global__ void k_control(Ctrl *ctrl, DevOpts o, int32_t sweep) {
     if (ctrl->error || ctrl->done) return;
+    control_step(ctrl, o, sweep);
+}
+
+// Dense sweeps: the plan of the next sweep (packed active columns), then the control.
+__global__ __launch_bounds__(1024) void k_control_plan(Ctrl *ctrl, DevOpts o, int32_t sweep, ColState cs,
+                                                       int64_t kp) {
+    if (ctrl->error || ctrl->done) return;
+    // the packed list only changes when a column left the active set in this sweep
+    if (ctrl->acc_active != ctrl->active) plan_dense(ctrl, cs, kp);
+    __syncthreads();
+    if (threadIdx.x == 0) control_step(ctrl, o, sweep);
+}
+
+__device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep) {
     const double ms = bitsd(ctrl->acc_maxstep);
     const int32_t prec = ctrl->prec;
     if (sweep - 1 < IPT_HIST) {
@@ -569,6 +623,11 @@ hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *id
     return hipGetLastError();
 }
 
+hipError_t launch_plan_dense(hipStream_t s, Ctrl *ctrl, ColState cs, int64_t kp) {
+    k_plan_dense<<<1, 1024, 0, s>>>(ctrl, cs, kp);
+    return hipGetLastError();
+}
+
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active) {
     k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, active);
     return hipGetLastError();
@@ -649,6 +708,11 @@ hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState
                            const double *theta, const double *part, int64_t nrt, int64_t kp, int32_t sweep,
                            int32_t in_par, int32_t out_par) {
     k_finalize<<<(unsigned)(kp / 64), 256, 0, s>>>(ctrl, o, cs, dvec, theta, part, nrt, kp, sweep, in_par, out_par);
+    return hipGetLastError();
+}
+
+hipError_t launch_control_plan(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, ColState cs, int64_t kp) {
+    k_control_plan<<<1, 1024, 0, s>>>(ctrl, o, sweep, cs, kp);
     return hipGetLastError();
 }
 
