@@ -368,6 +368,7 @@ def main():
             results[(eps, name)] = {"sec": sec, "infos": infos, "conv": conv, "eigenpairs_per_s": conv / sec,
                                     "device_ms": float(np.mean([i["time_ms"] for i in infos])),
                                     "sweeps": infos[-1]["sweeps"], "sweep_prec": infos[-1]["sweep_prec"],
+                                    "sweep_active": infos[-1]["sweep_active"],
                                     "sweep_max_step": [float("%.3g" % s) for s in infos[-1]["sweep_max_step"]]}
             log("eps=%g mode=%s: %.3f ms/solve, %d converged, sweeps %s" % (
                 eps, name, sec * 1e3, conv, infos[-1]["sweep_prec"]))
@@ -421,6 +422,7 @@ def main():
         "solve": {"%s eps=%g" % (m, e): {"eigenpairs_per_s": round(v["eigenpairs_per_s"], 1),
                                          "ms_per_solve": round(v["sec"] * 1e3, 4), "device_ms": round(v["device_ms"], 4),
                                          "converged": v["conv"], "sweeps": v["sweeps"], "sweep_prec": v["sweep_prec"],
+                                         "sweep_active": v["sweep_active"],
                                          "sweep_max_step": v["sweep_max_step"]}
                   for (e, m), v in results.items()},
     }

@@ -608,7 +608,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         cus = 256;
     const int nblk = 2 * cus;  // the sweep GEMM keeps two 256-thread blocks per CU
     const SplitBounds sb = split_bounds(np, kp, nblk);
-    auto layout = [&](Carve &cv, double **zb, ColState &cs, double **dpart, double **dvec, double **part, uint32_t **bitmap,
+    auto layout = [&](Carve &cv, double **zb, ColState &cs, double **dnp, double **dvec, double **part, uint32_t **bitmap,
                       double **scratch, double **dpad, void **dlo, float **d32, void **zt, Ctrl **ctrl) {
         zb[0] = cv.take<double>(np * kp);
         zb[1] = cv.take<double>(np * kp);
@@ -617,9 +617,9 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         acx_part = acx ? cv.take<double>((size_t)acx_splits(n, kp) * kp * 2) : nullptr;
         acx_sigma = acx ? cv.take<double>(kp) : nullptr;
         ypart = sb.ypart_tiles ? cv.take<double>((size_t)sb.ypart_tiles * TILE_M * TILE_N) : nullptr;
-        *dpart = cv.take<double>(DIAG_SPLIT * kp);
         *dvec = cv.take<double>(kp);
         *part = cv.take<double>(nrt * kp * NPART);
+        *dnp = cv.take<double>(nrt * kp);
         cs.state = cv.take<int32_t>(kp);
         cs.sweeps = cv.take<int32_t>(kp);
         cs.grow = cv.take<int32_t>(kp);
@@ -632,7 +632,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         cs.lam = cv.take<double>(kp);
         cs.resid = cv.take<double>(kp);
         *bitmap = cv.take<uint32_t>((n + 31) / 32);
-        *scratch = norm ? cv.take<double>(((np + 255) / 256) * n) : nullptr;
+        *scratch = norm ? cv.take<double>(prep_delta_chunks(np) * n) : nullptr;
         *dpad = direct ? nullptr : cv.take<double>(np * np);
         *dlo = use_low ? (void *)cv.take<uint16_t>(np * np) : nullptr;
         *d32 = ladder ? cv.take<float>(np * np) : nullptr;
@@ -641,31 +641,38 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     };
     double *zb[4];
     ColState cs;
-    double *dpart, *dvec, *part, *scratch, *dpad;
+    double *dnp, *dvec, *part, *scratch, *dpad;
     uint32_t *bitmap;
     void *dlo, *zt;
     float *d32;
     Ctrl *ctrl;
     Carve sizing;
-    layout(sizing, zb, cs, &dpart, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
+    layout(sizing, zb, cs, &dnp, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
     if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
     Carve cv;
     cv.base = (char *)h->ws;
-    layout(cv, zb, cs, &dpart, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
+    layout(cv, zb, cs, &dnp, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
 
     Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
     IPT_HIP(h, timer.ensure());
     IPT_HIP(h, hipEventRecord(h->ev_start, s));
     const int32_t start_prec = cold ? PREC_EXACT_FIRST : (ladder ? PREC_F32 : PREC_F64);
-    IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kp, bitmap, start_prec, (int32_t)ntn, 0));
-    IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
-    IPT_HIP(h, launch_plan_dense(s, ctrl, cs, kp));
+    // The pass over Delta goes first (it needs only the control block), so that the
+    // small column-setup kernels queue behind it instead of idling the device.
+    // Plain sweeps take d of the next sweep from the product epilogue; for an exactly
+    // symmetric Delta (checked once here) it reads Delta_ji, coalesced, for Delta_ij.
+    const bool fuse_d = !acx;
+    IPT_HIP(h, launch_ctrl_init(s, ctrl, start_prec, k, fuse_d ? 1 : 0));
     if (use_low && lt == LT_F16) IPT_HIP(h, launch_absmax(s, ctrl, delta, n, n, lda));
     const double *dA = direct ? delta : dpad;
     const int64_t ldA = direct ? lda : np;
     if (!direct || ladder || norm)
         IPT_HIP(h, launch_prep_delta(s, ctrl, theta, delta, lda, n, np, direct ? nullptr : dpad,
                                      use_low ? dlo : nullptr, lt, ladder ? d32 : nullptr, norm ? scratch : nullptr));
+    if (fuse_d) IPT_HIP(h, launch_check_sym(s, ctrl, delta, lda, n));
+    IPT_HIP(h, launch_init_cols(s, ctrl, cs, idx, n, k, kp, bitmap, (int32_t)ntn, 0));
+    IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
+    IPT_HIP(h, launch_plan_dense(s, ctrl, cs, kp));
     const bool padded = (np != n) || (kp != k);
     if (cold && !acx) {
         if (padded) IPT_HIP(h, launch_zero_pad(s, zb[0], kp, n, np, k, kp));
@@ -679,6 +686,9 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     const PollPlan plan = poll_plan(o, cold);
     if (ipt_status st = ensure_poll(h)) return st;
     LookaheadPoll poll{h, ctrl};
+    // d of a sweep comes from the previous sweep's product epilogue (plain sweeps: the
+    // input is the previous output W), else from a pass over Delta and Z.
+    bool d_ready = false;
     for (int32_t t = 1; t <= o.max_iter; ++t) {
         const bool first_exact = cold && t == 1;
         // Plain sweeps ping-pong between two buffers; an ACX cycle runs slot q -> q + 1
@@ -694,13 +704,16 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
             IPT_HIP(h, timer.mark(t, 1, s));
         } else {
             if (ladder) IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, lt));
-            IPT_HIP(h, launch_diag_dense(s, ctrl, dA, ldA, zin, kp, cs, dpart, dvec, n, kp));
+            if (!d_ready) IPT_HIP(h, launch_diag_dense(s, ctrl, dA, ldA, zin, kp, cs, dnp, dvec, n, kp));
             IPT_HIP(h, timer.mark(t, 0, s));
             IPT_HIP(h, launch_sweep_gemm(s, ctrl, dA, ldA, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, t,
-                                         lt, ypart, nblk));
+                                         lt, ypart, nblk, fuse_d ? dnp : nullptr));
             IPT_HIP(h, timer.mark(t, 1, s));
         }
-        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, nrt, kp, t, in_par, out_par));
+        const bool fused_d = !first_exact && fuse_d;
+        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, nrt, kp, t, in_par, out_par,
+                                   fused_d ? dnp : nullptr));
+        d_ready = fused_d;
         IPT_HIP(h, launch_control_plan(s, ctrl, dopt, t, cs, kp));
         if (acx && q == pc - 1)
             IPT_HIP(h, launch_acx(s, ctrl, cs.state, zb[0], zb[1], zb[2], zb[3], kp, n, kp, pc, acx_part, acx_sigma));

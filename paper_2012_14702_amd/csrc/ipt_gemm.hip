@@ -4,7 +4,10 @@
 // plus the per-column partial sums of |W - Z|^2, |Z|^2, |(theta_j - theta_i)(W - Z)|^2
 // and |W - e_i|^2 over each 128-row tile (reduced in a fixed order by the finalize
 // kernel).  By F(Z) - Z = -G o (M Z - Z Lambda), the third sum is the squared
-// eigen-residual |M z - lambda z|^2 of the column.
+// eigen-residual |M z - lambda z|^2 of the column.  Optionally the epilogue also
+// forms sum_j Delta_ij W_jc over its rows: the finalize adds these into d of the next
+// sweep (lambda = theta + diag(Delta Z) with Z = W), so that sweep needs no separate
+// pass over Delta and Z for its d.
 //
 // Column tiles run over the packed active columns (ColState::alist, rebuilt after
 // every finalize), so frozen columns cost nothing; the B operand gathers them.
@@ -69,7 +72,12 @@ struct GemmArgs {
     int32_t low_type;     // LT_BF16 or LT_F16
     double *ypart;        // split-K partial products of narrow sweeps
     int32_t nblk;         // blocks that fill the chip (2 per CU)
+    double *dnp;          // NULL, or [row tile][column] partials of d for the next sweep
 };
+
+// Epilogue reduction slots: the NPART sums of the finalize, then the partial of
+// d' = (Delta W)_{i,c}, the d of the next sweep (W is its input).
+constexpr int NRED = NPART + 1;
 
 // Narrow sweeps: when the packed active columns give fewer tiles than nblk, the K
 // range is split S ways (S >= 2); each split writes its FP64 partial tile and a
@@ -97,6 +105,13 @@ struct PackedCols {
     __device__ int32_t operator[](int i) const { return i < lim ? cols[i] : -1; }
 };
 
+// Column blocks (16 columns each) of wave column wn that hold packed columns.  Narrow
+// sweeps (the split path) skip the MFMAs of the others.
+__device__ inline int live_col_blocks(int32_t lim, int wn) {
+    const int v = (lim - wn * 64 + 15) >> 4;
+    return v < 0 ? 0 : (v > 4 ? 4 : v);
+}
+
 constexpr int SMEM_F64 = 2 * BM * (16 + 1) * 8 + 2 * 16 * BN * 8;
 constexpr int SMEM_LOW16 = 2 * 2 * BM * (64 + 8) * 2;
 constexpr int SMEM_LOW32 = 2 * 2 * BM * (32 + 1) * 4;
@@ -105,41 +120,57 @@ constexpr int SMEM_MAIN = cmax(SMEM_F64, cmax(SMEM_LOW16, SMEM_LOW32));
 
 // Shared epilogue.  Each lane holds 4 column blocks (jb) x 16 rows of the block
 // tile; row_of(ib, r) gives the tile row of accumulator (ib, r), which depends on
-// the MFMA family.  y_of(ib, jb, r, j, i) returns the FP64 product value.
-template <class RowOf, class YOf>
+// the MFMA family.  y_of(ib, jb, r, dji) returns the FP64 product value (dji =
+// Delta_ji, loaded for a low-precision product, LOW).  WANT_D: also the partials of
+// the next sweep's d (e.dnp).  Both are template flags so that the unrolled loop
+// carries no branches around its loads.
+template <bool LOW, bool WANT_D, class RowOf, class YOf>
 __device__ inline void sweep_epilogue(const GemmArgs &e, const PackedCols scol, int tm, int wm, int wn, int lane,
-                                      RowOf row_of, YOf y_of, double (*red)[BN][NPART]) {
-    int64_t cols[4];
-    int32_t ii[4];
+                                      RowOf row_of, YOf y_of, double (*red)[BN][NRED], bool sym) {
+    // The loads of one row (4 column blocks) issue together before its arithmetic, at
+    // addresses that are always valid (empty packed slots read column 0, rows past n
+    // the zero padding, theta clamps to n - 1); the arithmetic then skips what is not
+    // there.  One element at a time would leave each load's latency exposed.
+    int32_t cols[4], ii[4];
     double ti[4], dd[4];
     bool act[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
         const int32_t c = scol[wn * 64 + 16 * jb + (lane & 15)];  // packed position -> column
-        cols[jb] = c;
         act[jb] = c >= 0 && e.cs.state[c] == COL_ACTIVE;
+        cols[jb] = act[jb] ? c : 0;
         ii[jb] = act[jb] ? e.cs.idx[c] : 0;
         ti[jb] = act[jb] ? e.theta[ii[jb]] : 0.0;
         dd[jb] = act[jb] ? e.dvec[c] : 0.0;
     }
     const int64_t ldzb = e.kp;
-    double sums[4][NPART];
+    double sums[4][NRED];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-        for (int q = 0; q < NPART; ++q) sums[jb][q] = 0.0;
+        for (int q = 0; q < NRED; ++q) sums[jb][q] = 0.0;
 #pragma unroll
-    for (int ib = 0; ib < 4; ++ib) {
+    for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t j = (int64_t)tm * BM + wm * 64 + row_of(ib, r, lane);
-            if (j >= e.n) continue;
-            const double tj = e.theta[j];
+            const bool rok = j < e.n;
+            const double tj = e.theta[rok ? j : e.n - 1];
+            double zv[4], dji[4], dij[4];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const int64_t a_ji = j * e.lda + ii[jb], a_ij = (int64_t)ii[jb] * e.lda + j;
+                zv[jb] = e.zin[j * ldzb + cols[jb]];
+                dji[jb] = LOW ? e.delta[a_ji] : 0.0;
+                // Delta_ij of d'; for an exactly symmetric Delta, Delta_ji (coalesced
+                // across the lanes' columns) holds the same value
+                dij[jb] = WANT_D ? e.delta[sym ? a_ji : a_ij] : 0.0;
+            }
+            if (!rok) continue;
 #pragma unroll
             for (int jb = 0; jb < 4; ++jb) {
                 if (!act[jb]) continue;
-                const int64_t c = cols[jb];
-                const double z = e.zin[j * ldzb + c];
+                const double z = zv[jb];
                 double w, st, gs, de;
                 if (j == ii[jb]) {
                     w = 1.0;
@@ -147,27 +178,27 @@ __device__ inline void sweep_epilogue(const GemmArgs &e, const PackedCols scol, 
                     gs = 0.0;
                     de = 0.0;
                 } else {
-                    const double y = y_of(ib, jb, r, j, ii[jb]);
                     const double gap = tj - ti[jb];
-                    w = (z * dd[jb] - y) / gap;
+                    w = fma(z, dd[jb], -y_of(ib, jb, r, dji[jb])) / gap;
                     st = w - z;
                     gs = gap * st;
                     de = w;
                 }
-                e.zout[j * ldzb + c] = w;
-                sums[jb][0] += st * st;
-                sums[jb][1] += z * z;
-                sums[jb][2] += gs * gs;
-                sums[jb][3] += de * de;
+                e.zout[j * ldzb + cols[jb]] = w;
+                sums[jb][0] = fma(st, st, sums[jb][0]);
+                sums[jb][1] = fma(z, z, sums[jb][1]);
+                sums[jb][2] = fma(gs, gs, sums[jb][2]);
+                sums[jb][3] = fma(de, de, sums[jb][3]);
+                if constexpr (WANT_D) sums[jb][NPART] = fma(dij[jb], w, sums[jb][NPART]);
             }
         }
-    }
     // Reduce over the 4 lane groups holding the same columns (fixed pattern), then
     // over the two waves that share the column block, in a fixed order.
+    constexpr int nq = WANT_D ? NRED : NPART;
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-        for (int q = 0; q < NPART; ++q) {
+        for (int q = 0; q < nq; ++q) {
             double v = sums[jb][q];
             v += __shfl_xor(v, 16);
             v += __shfl_xor(v, 32);
@@ -177,7 +208,7 @@ __device__ inline void sweep_epilogue(const GemmArgs &e, const PackedCols scol, 
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-            for (int q = 0; q < NPART; ++q) red[wm][wn * 64 + 16 * jb + lane][q] = sums[jb][q];
+            for (int q = 0; q < nq; ++q) red[wm][wn * 64 + 16 * jb + lane][q] = sums[jb][q];
     }
     __syncthreads();
     const int t = threadIdx.x;
@@ -187,6 +218,7 @@ __device__ inline void sweep_epilogue(const GemmArgs &e, const PackedCols scol, 
 #pragma unroll
             for (int q = 0; q < NPART; ++q)
                 e.part[((int64_t)tm * e.kp + c) * NPART + q] = red[0][t][q] + red[1][t][q];
+            if constexpr (WANT_D) e.dnp[(int64_t)tm * e.kp + c] = red[0][t][NPART] + red[1][t][NPART];
         }
     }
 }
@@ -195,8 +227,9 @@ __device__ inline void sweep_epilogue(const GemmArgs &e, const PackedCols scol, 
 constexpr int BK64 = 16;
 
 template <bool SPLIT>
-__device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPART], const PackedCols scol,
-                                              const GemmArgs &g, int tm, int64_t k0, int64_t k1, double *yp) {
+__device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NRED], const PackedCols scol,
+                                              const GemmArgs &g, int tm, int64_t k0, int64_t k1, double *yp,
+                                              bool sym) {
     typedef double ATile[BM][BK64 + 1];
     typedef double BTile[BK64][BN];
     ATile *As = (ATile *)smem;
@@ -215,6 +248,7 @@ __device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPAR
     const bool contig = scol.lim >= BN && scol[BN - 1] == c_first + BN - 1;
     const int32_t cg = contig ? c_first + 2 * cp : scol[b_c];
     const double *Bc = g.zin + (cg >= 0 ? cg : 0);
+    const int nj = SPLIT ? live_col_blocks(scol.lim, wn) : 4;
 
     d4_t acc[4][4];
 #pragma unroll
@@ -273,12 +307,14 @@ __device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPAR
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib) fa[ib] = As[cur][wm * 64 + 16 * ib + (lane & 15)][4 * kk + (lane >> 4)];
 #pragma unroll
-            for (int jb = 0; jb < 4; ++jb) fb[jb] = Bs[cur][4 * kk + (lane >> 4)][wn * 64 + 16 * jb + (lane & 15)];
+            for (int jb = 0; jb < 4; ++jb)
+                fb[jb] = (!SPLIT || jb < nj) ? Bs[cur][4 * kk + (lane >> 4)][wn * 64 + 16 * jb + (lane & 15)] : 0.0;
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb)
-                    acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[ib], fb[jb], acc[ib][jb], 0, 0, 0);
+                    if (!SPLIT || jb < nj)
+                        acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[ib], fb[jb], acc[ib][jb], 0, 0, 0);
         }
         const int nx = cur ^ 1;
 #pragma unroll
@@ -301,10 +337,13 @@ __device__ __forceinline__ void gemm_f64_body(char *smem, double (*red)[BN][NPAR
             for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb)
-                    yp[(int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15)] = acc[ib][jb][r];
+                    if (wn * 64 + 16 * jb + (lane & 15) < scol.lim)  // empty packed columns: never read
+                        yp[(int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15)] =
+                            acc[ib][jb][r];
     } else {
-        auto y_of = [&](int ib, int jb, int r, int64_t, int32_t) { return acc[ib][jb][r]; };
-        sweep_epilogue(g, scol, tm, wm, wn, lane, row_of, y_of, red);
+        auto y_of = [&](int ib, int jb, int r, double) { return acc[ib][jb][r]; };
+        if (g.dnp) sweep_epilogue<false, true>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
+        else sweep_epilogue<false, false>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
     }
 }
 
@@ -365,9 +404,9 @@ __device__ __forceinline__ void lds_put(T (*as)[LDP], T (*bs)[LDP], const uint4 
 }
 
 template <typename T, bool SPLIT>
-__device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPART], const PackedCols scol,
+__device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NRED], const PackedCols scol,
                                               const GemmArgs &g, const T *dlo, double unscale, int tm, int64_t k0,
-                                              int64_t k1, double *yp) {
+                                              int64_t k1, double *yp, bool sym) {
     using C = LowCfg<T>;
     constexpr int BK = C::BK, LDP = C::BK + C::PAD;
     typedef T Tile[BM][LDP];
@@ -389,6 +428,7 @@ __device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPAR
         const int32_t cg = scol[l_r + 32 * q];
         boff[q] = cg >= 0 ? (int64_t)cg * ldt + l_c : -1;
     }
+    const int nj = SPLIT ? live_col_blocks(scol.lim, wn) : 4;
 
     f4_t acc[4][4];
 #pragma unroll
@@ -420,16 +460,15 @@ __device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPAR
             for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb)
-                    acc[ib][jb] = mfma_low<T>(&As[cur][wm * 64 + 16 * ib + (lane & 15)][koff],
-                                              &Bs[cur][wn * 64 + 16 * jb + (lane & 15)][koff], acc[ib][jb]);
+                    if (!SPLIT || jb < nj)
+                        acc[ib][jb] = mfma_low<T>(&As[cur][wm * 64 + 16 * ib + (lane & 15)][koff],
+                                                  &Bs[cur][wn * 64 + 16 * jb + (lane & 15)][koff], acc[ib][jb]);
         }
         lds_put<T, EPC, LDP>(As[cur ^ 1], Bs[cur ^ 1], ra, rb, l_r, l_c);
         __syncthreads();
     }
 
     // f32-accumulating 16x16 MFMAs: lane l, register r holds row 4(l/16) + r, column l%16.
-    const double *delta = g.delta;
-    const int64_t lda = g.lda;
     auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * (l >> 4) + r; };
     if constexpr (SPLIT) {
 #pragma unroll
@@ -438,32 +477,33 @@ __device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NPAR
             for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb)
-                    yp[(int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15)] =
-                        unscale * (double)acc[ib][jb][r];
+                    if (wn * 64 + 16 * jb + (lane & 15) < scol.lim)  // empty packed columns: never read
+                        yp[(int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15)] =
+                            unscale * (double)acc[ib][jb][r];
     } else {
-        auto y_of = [&](int ib, int jb, int r, int64_t j, int32_t i) {
-            return delta[j * lda + i] + unscale * (double)acc[ib][jb][r];
-        };
-        sweep_epilogue(g, scol, tm, wm, wn, lane, row_of, y_of, red);
+        auto y_of = [&](int ib, int jb, int r, double dji) { return dji + unscale * (double)acc[ib][jb][r]; };
+        if (g.dnp) sweep_epilogue<true, true>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
+        else sweep_epilogue<true, false>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
     }
 }
 
 // The sweep's product over the K range [k0, k1), in the precision the ladder chose;
 // SPLIT writes the partial tile instead of running the epilogue.
 template <bool SPLIT>
-__device__ __forceinline__ void sweep_tile(const Ctrl *ctrl, const GemmArgs &g, char *smem, double (*red)[BN][NPART],
+__device__ __forceinline__ void sweep_tile(const Ctrl *ctrl, const GemmArgs &g, char *smem, double (*red)[BN][NRED],
                                            const PackedCols scol, int tm, int64_t k0, int64_t k1, double *yp) {
     const int32_t prec = ctrl->prec;
+    const bool sym = ctrl->sym != 0;
     if (prec == PREC_F64) {
-        gemm_f64_body<SPLIT>(smem, red, scol, g, tm, k0, k1, yp);
+        gemm_f64_body<SPLIT>(smem, red, scol, g, tm, k0, k1, yp, sym);
     } else if (prec == PREC_F32) {
-        gemm_low_body<float, SPLIT>(smem, red, scol, g, g.d32, 1.0, tm, k0, k1, yp);
+        gemm_low_body<float, SPLIT>(smem, red, scol, g, g.d32, 1.0, tm, k0, k1, yp, sym);
     } else if (prec == PREC_LOW) {
         if (g.low_type == LT_F16)
             gemm_low_body<_Float16, SPLIT>(smem, red, scol, g, (const _Float16 *)g.dlo,
-                                           1.0 / (ctrl->dscale * ctrl->zscale), tm, k0, k1, yp);
+                                           1.0 / (ctrl->dscale * ctrl->zscale), tm, k0, k1, yp, sym);
         else
-            gemm_low_body<__bf16, SPLIT>(smem, red, scol, g, (const __bf16 *)g.dlo, 1.0, tm, k0, k1, yp);
+            gemm_low_body<__bf16, SPLIT>(smem, red, scol, g, (const __bf16 *)g.dlo, 1.0, tm, k0, k1, yp, sym);
     }
 }
 
@@ -476,7 +516,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArg
     const int32_t kact = ctrl->kact;
     const SplitPlan sp = split_plan(kact, ntm, g.np, g.nblk);
     __shared__ __attribute__((aligned(16))) char smem[SMEM_MAIN];
-    __shared__ double red[2][BN][NPART];
+    // The epilogue's reduction area reuses the operand stages: every wave has passed
+    // the K loop's last barrier, after its last operand read, before it is written.
+    static_assert(sizeof(double) * 2 * BN * NRED <= SMEM_MAIN, "reduction area exceeds the operand stages");
+    double (*red)[BN][NRED] = (double (*)[BN][NRED])smem;
     if (sp.S < 2) {
         if ((int)blockIdx.x >= regular_blocks) return;
         int tm, tn;
@@ -499,30 +542,53 @@ __global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArg
 }
 
 // Narrow sweep, epilogue: Y of the tile = the split partials summed in split order.
-// A small grid walks the tiles, so that sweeps with enough tiles pay little for it.
+// The block first sums the partials of the tile's live columns into split slot 0
+// (coalesced rows, every split's load in flight at once), then runs the epilogue on
+// that sum.  A small grid walks the tiles, so that sweeps with enough tiles pay
+// little for it.
 __global__ __launch_bounds__(256, 1) void k_sweep_split_epi(const Ctrl *ctrl, GemmArgs g) {
     if (ctrl->error || ctrl->done) return;
     const int ntm = (int)(g.np / BM);
     const int32_t kact = ctrl->kact;
     const SplitPlan sp = split_plan(kact, ntm, g.np, g.nblk);
     if (sp.S < 2) return;
-    __shared__ double red[2][BN][NPART];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
-    const bool low = ctrl->prec != PREC_F64;
+    __shared__ double red[2][BN][NRED];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
+    const bool low = ctrl->prec != PREC_F64, sym = ctrl->sym != 0;
     const int64_t tile = (int64_t)BM * BN, stride = (int64_t)sp.nct * ntm * tile;
     auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * r + (l >> 4); };
     for (int64_t bt = blockIdx.x; bt < (int64_t)ntm * sp.nct; bt += gridDim.x) {
         const int tn = (int)(bt / ntm), tm = (int)(bt % ntm);
         const PackedCols scol{g.cs.alist + (int64_t)tn * BN, (int32_t)(kact - (int64_t)tn * BN)};
-        const double *y0 = g.ypart + ((int64_t)tn * ntm + tm) * tile;
-        auto y_of = [&](int ib, int jb, int r, int64_t j, int32_t i) {
-            const int64_t e = (int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15);
+        double *y0 = g.ypart + ((int64_t)tn * ntm + tm) * tile;
+        // (row, live column) pairs spread over all threads, consecutive threads on
+        // consecutive columns of a row
+        const int live = scol.lim < BN ? scol.lim : BN;
+#pragma unroll 2
+        for (int p = t; p < BM * live; p += 256) {
+            const int r = p / live, cl = p - r * live;
+            const int64_t e = (int64_t)r * BN + cl;
+            double v[SPLIT_MAX];
+#pragma unroll
+            for (int q = 0; q < SPLIT_MAX; ++q) v[q] = q < sp.S ? y0[q * stride + e] : 0.0;
             double y = 0.0;
-#pragma unroll 1
-            for (int q = 0; q < sp.S; ++q) y += y0[q * stride + e];
-            return low ? g.delta[j * g.lda + i] + y : y;  // low precision: split form, Delta E exact
+#pragma unroll
+            for (int q = 0; q < SPLIT_MAX; ++q)
+                if (q < sp.S) y += v[q];
+            y0[e] = y;
+        }
+        __syncthreads();
+        auto y_of = [&](int ib, int jb, int r, double dji) {
+            const double y = y0[(int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15)];
+            return low ? dji + y : y;  // low precision: split form, Delta E exact
         };
-        sweep_epilogue(g, scol, tm, wm, wn, lane, row_of, y_of, red);
+        if (low) {
+            if (g.dnp) sweep_epilogue<true, true>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
+            else sweep_epilogue<true, false>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
+        } else {
+            if (g.dnp) sweep_epilogue<false, true>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
+            else sweep_epilogue<false, false>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
+        }
         __syncthreads();
     }
 }
@@ -532,8 +598,8 @@ __global__ __launch_bounds__(256, 1) void k_sweep_split_epi(const Ctrl *ctrl, Ge
 hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const void *dlo,
                              const float *d32, const void *zt, const double *zin, double *zout, const double *theta,
                              ColState cs, const double *dvec, double *part, int64_t n, int64_t np, int64_t kp,
-                             int32_t sweep, int32_t low_type, double *ypart, int nblk) {
-    GemmArgs g{delta, lda, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, low_type, ypart, nblk};
+                             int32_t sweep, int32_t low_type, double *ypart, int nblk, double *dnp) {
+    GemmArgs g{delta, lda, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, low_type, ypart, nblk, dnp};
     (void)sweep;
     const int blocks = (int)((np / BM) * (kp / BN));
     const SplitBounds b = split_bounds(np, kp, nblk);

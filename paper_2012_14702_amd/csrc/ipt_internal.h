@@ -34,7 +34,7 @@ struct Ctrl {
     int32_t n_conv, n_notconv, n_div;
     int32_t prec_mask;  // batched: bit PREC_F32 set when a tile of this sweep ran in FP32
     int32_t kact;       // dense: active columns entering the next sweep (length of ColState::alist)
-    int32_t pad1;
+    int32_t sym;        // dense: 1 once Delta is verified exactly symmetric (Delta_ji may stand for Delta_ij)
     uint64_t acc_maxstep;  // finalize accumulator: max s_c (bit pattern of a non-negative double)
     uint64_t acc_maxres;   // max normalised eigen-residual over converged columns (bits)
     uint64_t dec_maxstep;  // max deciding step over decided columns (bits)
@@ -97,21 +97,29 @@ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 enum : int32_t { LT_BF16 = 0, LT_F16 = 1, LT_F32 = 2 };
 
 // -------------------------------------------------------------- launchers
-constexpr int DIAG_SPLIT = 64;  // max partial sums per d_c (dpart is DIAG_SPLIT x kp)
 
 // Setup and bookkeeping (ipt_setup.hip)
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp);
-hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active);
+// The column part of launch_init (after a separate launch_ctrl_init).
+hipError_t launch_init_cols(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
+                            int64_t kp, uint32_t *bitmap, int32_t ntiles_n, int32_t start_stamp);
+// sym0 = 1 when k_check_sym runs next (it clears sym on the first asymmetric pair).
+hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0 = 0);
+// Clears ctrl->sym unless Delta (n x n, leading dimension lda) equals its transpose
+// bit for bit.
+hipError_t launch_check_sym(hipStream_t s, Ctrl *ctrl, const double *delta, int64_t lda, int64_t n);
 // Dense: list the active columns in ascending order (ColState::alist, ctrl->kact).
 hipError_t launch_plan_dense(hipStream_t s, Ctrl *ctrl, ColState cs, int64_t kp);
 // Dense: the plan of the next sweep followed by the control step, in one launch.
 hipError_t launch_control_plan(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, ColState cs, int64_t kp);
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
                               int64_t k);
+// colpart holds prep_delta_chunks(np) x n doubles.
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
                              int64_t n, int64_t np, double *dpad, void *dlo, int32_t low_type, float *d32,
                              double *colpart);
+int64_t prep_delta_chunks(int64_t np);
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
                             const int32_t *col, const double *val, int64_t n, double *scratch);
 hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld);
@@ -121,11 +129,16 @@ hipError_t launch_zero_pad(hipStream_t s, double *zb, int64_t ldzb, int64_t n, i
 hipError_t launch_sweep1_dense(hipStream_t s, const Ctrl *ctrl, const double *theta, const double *delta,
                                int64_t lda, ColState cs, double *dvec, double *zout, int64_t ldzb, double *part,
                                int64_t n, int64_t np, int64_t kp);
+// d of the sweep from Delta and its input Z, through the same row-tile partials
+// (dnp: ceil(n / TILE_M) x kp) and summation order as the sweep epilogue's d.
 hipError_t launch_diag_dense(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
-                             int64_t ldzb, ColState cs, double *dpart, double *dvec, int64_t n, int64_t kp);
-hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, const double *dvec,
+                             int64_t ldzb, ColState cs, double *dnp, double *dvec, int64_t n, int64_t kp);
+// dnp: NULL, or the nrt x kp partials of the next sweep's d from the sweep's
+// epilogue; the finalize then writes dvec[c] = their sum for the columns that stay
+// active (after reading this sweep's d).
+hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, double *dvec,
                            const double *theta, const double *part, int64_t nrt, int64_t kp, int32_t sweep,
-                           int32_t in_par, int32_t out_par);
+                           int32_t in_par, int32_t out_par, const double *dnp = nullptr);
 hipError_t launch_control(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep);
 hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
                           int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
@@ -241,7 +254,7 @@ hipError_t launch_acx(hipStream_t s, const Ctrl *ctrl, const int32_t *state, dou
 hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const void *dlo,
                              const float *d32, const void *zt, const double *zin, double *zout, const double *theta,
                              ColState cs, const double *dvec, double *part, int64_t n, int64_t np, int64_t kp,
-                             int32_t sweep, int32_t low_type, double *ypart, int nblk);
+                             int32_t sweep, int32_t low_type, double *ypart, int nblk, double *dnp);
 // Launch bounds of the split-K path of narrow sweeps (grid sizes and the tiles of
 // the partial-product workspace, each 128 x 128 FP64); all zero when no packed width
 // of this shape is narrow.

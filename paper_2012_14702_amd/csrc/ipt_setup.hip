@@ -6,6 +6,8 @@
 // kp columns with zeros), W = F(Z) its image under the map of eq. dyn.
 #include <math.h>
 
+#include <type_traits>
+
 #include "ipt_internal.h"
 
 namespace ipt {
@@ -22,7 +24,7 @@ __device__ inline uint64_t dbits(double x) {
 
 __device__ inline double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
 
-__global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k) {
+__global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k, int32_t sym0) {
     uint32_t *w = (uint32_t *)ctrl;
     constexpr int words = (int)(sizeof(Ctrl) / sizeof(uint32_t));
     for (int q = threadIdx.x; q < words; q += blockDim.x) w[q] = 0u;
@@ -30,6 +32,7 @@ __global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k) {
     if (threadIdx.x == 0) {
         ctrl->prec = start_prec;
         ctrl->active = (int32_t)k;
+        ctrl->sym = sym0;
         ctrl->prev_maxstep = INFINITY;
         ctrl->dscale = 1.0;
         ctrl->zscale = 1.0;
@@ -105,41 +108,104 @@ __device__ inline _Float16 to_low<_Float16>(double x) { return (_Float16)(float)
 // One pass over Delta for everything the solve needs from it before the sweeps:
 // a zero-padded FP64 copy (when Delta is not tile aligned), the low-precision and
 // FP32 shadows of the ladder, and per-chunk partial column sums of |M| for
-// |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Block: 64 columns x
-// PREP_ROWS rows; thread (cx, ry) walks rows ry, ry + 4, ...
-constexpr int PREP_ROWS = 256;
+// |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Block: 256 columns x
+// PREP_ROWS rows; thread (cx, ry) holds columns 4cx..4cx+3 (16-byte loads) and walks
+// rows ry, ry + 4, ..., four rows in flight.
+constexpr int PREP_ROWS = 128;
 
 template <typename TL>
 __global__ __launch_bounds__(256) void k_prep_delta(const Ctrl *ctrl, const double *theta, const double *delta,
                                                     int64_t lda, int64_t n, int64_t np, double *dpad, TL *dlo,
                                                     float *d32, double *colpart) {
-    __shared__ double sh[4][64];
+    typedef TL tl4_t __attribute__((ext_vector_type(4)));
+    __shared__ double sh[4][256];
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
-    const int64_t c = (int64_t)blockIdx.x * 64 + cx;
+    const int64_t c0 = (int64_t)blockIdx.x * 256 + 4 * cx;
     const int64_t r0 = (int64_t)blockIdx.y * PREP_ROWS;
     const double dscale = ctrl->dscale;
-    double acc = 0.0;
-    for (int q = 0; q < PREP_ROWS / 4; ++q) {
-        const int64_t j = r0 + ry + 4 * q;
-        if (j >= np) break;
-        const bool in = (j < n) && (c < n);
-        const double v = in ? delta[j * lda + c] : 0.0;
-        if (dpad) dpad[j * np + c] = v;
-        if (dlo) dlo[j * np + c] = to_low<TL>(v * dscale);
-        if (d32) d32[j * np + c] = (float)v;
-        if (in) acc += fabs(j == c ? v + theta[c] : v);
-    }
+    const bool vec = ((lda & 1) == 0) && (((uintptr_t)delta & 15) == 0) && c0 + 4 <= n;
+    const bool live = c0 < np;  // np is a multiple of 128, so c0 + 4 <= np
+    double acc[4] = {0.0, 0.0, 0.0, 0.0}, th[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) th[e] = c0 + e < n ? theta[c0 + e] : 0.0;
+    // Loads read a clamped (valid) row and column and are masked afterwards, so the
+    // four rows' loads issue back to back without branches between them.
+    auto walk = [&](auto vec_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value;
+        for (int q0 = 0; q0 < PREP_ROWS / 4; q0 += 4) {
+            double v[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t j = r0 + ry + 4 * (q0 + u);
+                const int64_t jc = j < n ? j : n - 1;
+                if constexpr (VEC) {
+                    const double2 x = *(const double2 *)(delta + jc * lda + c0);
+                    const double2 y = *(const double2 *)(delta + jc * lda + c0 + 2);
+                    v[u][0] = x.x;
+                    v[u][1] = x.y;
+                    v[u][2] = y.x;
+                    v[u][3] = y.y;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int64_t cc = c0 + e < n ? c0 + e : n - 1;
+                        v[u][e] = delta[jc * lda + cc];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (!(j < n && c0 + e < n)) v[u][e] = 0.0;
+            }
+            if (!live) continue;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t j = r0 + ry + 4 * (q0 + u);
+                if (j >= np) continue;
+                const int64_t o = j * np + c0;
+                if (dpad) {
+                    *(double2 *)(dpad + o) = double2{v[u][0], v[u][1]};
+                    *(double2 *)(dpad + o + 2) = double2{v[u][2], v[u][3]};
+                }
+                if (dlo)
+                    *(tl4_t *)(dlo + o) = tl4_t{to_low<TL>(v[u][0] * dscale), to_low<TL>(v[u][1] * dscale),
+                                                to_low<TL>(v[u][2] * dscale), to_low<TL>(v[u][3] * dscale)};
+                if (d32)
+                    *(float4 *)(d32 + o) = float4{(float)v[u][0], (float)v[u][1], (float)v[u][2], (float)v[u][3]};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc[e] += fabs(j == c0 + e ? v[u][e] + th[e] : v[u][e]);  // padding adds 0
+            }
+        }
+    };
+    if (vec) walk(std::true_type{});
+    else walk(std::false_type{});
     if (!colpart) return;
-    sh[ry][cx] = acc;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sh[ry][4 * cx + e] = acc[e];
     __syncthreads();
-    if (ry == 0 && c < n) colpart[(int64_t)blockIdx.y * n + c] = ((sh[0][cx] + sh[1][cx]) + sh[2][cx]) + sh[3][cx];
+    if (ry == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t c = c0 + e;
+            const int x = 4 * cx + e;
+            if (c < n) colpart[(int64_t)blockIdx.y * n + c] = ((sh[0][x] + sh[1][x]) + sh[2][x]) + sh[3][x];
+        }
+    }
 }
 
 __global__ void k_norm1_reduce(Ctrl *ctrl, const double *colpart, int64_t n, int64_t chunks) {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= n) return;
     double acc = 0.0;
-    for (int64_t q = 0; q < chunks; ++q) acc += colpart[q * n + c];
+    int64_t q = 0;
+    for (; q + 8 <= chunks; q += 8) {  // eight loads in flight, added in chunk order
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = colpart[(q + u) * n + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; q < chunks; ++q) acc += colpart[q * n + c];
     atomicMax((unsigned long long *)&ctrl->norm1_bits, (unsigned long long)dbits(acc));
 }
 
@@ -249,71 +315,124 @@ __global__ __launch_bounds__(256) void k_sweep1_dense(const Ctrl *ctrl, const do
     store_col_partials(sh, v, cx, ry, part, rt, kp, c);
 }
 
-// d_c = (Delta Z)_{i,c} = sum_l Delta_il Z_lc in FP64 for the active columns.
-// Block: 64 columns x one of kDiagSplit contiguous ranges of l, walked in chunks
-// of 64: the 64 x 64 slices of the rows Delta[idx[c], :] and of Z are read with
-// 16-byte loads and met in LDS.  Each range's sum goes to dpart[range][c]; the
-// consumers add the ranges in a fixed order (k_diag_sum).
-__global__ __launch_bounds__(256) void k_diag_dense(const Ctrl *ctrl, const double *delta, int64_t lda,
-                                                    const double *zin, int64_t ldzb, ColState cs, double *dpart,
-                                                    int64_t n, int64_t kp, int64_t span) {
-    if (ctrl->error || ctrl->done) return;
-    __shared__ double dt[64][65];
-    __shared__ double zt[64][66];
-    __shared__ double red[4][64];
-    __shared__ int32_t any;
-    const int t = threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.x * 64;
-    if (t == 0) any = 0;
+// Exact symmetry of Delta: block b takes the b-th pair of 64 x 64 tiles (I, J), I >= J,
+// in row-major lower-triangle order, and compares Delta[I, J] with the transpose of
+// Delta[J, I] bit for bit (the second tile goes through LDS).  Any difference clears
+// ctrl->sym; blocks that start after that return at once.
+__global__ __launch_bounds__(256) void k_check_sym(Ctrl *ctrl, const double *delta, int64_t lda, int64_t n,
+                                                   int64_t nb) {
+    __shared__ double tb[64][65];
+    __shared__ int32_t go;
+    if (threadIdx.x == 0) go = ctrl->sym;  // one read per block keeps the exit uniform
     __syncthreads();
-    if (t < 64 && cs.state[c0 + t] == COL_ACTIVE) any = 1;
-    __syncthreads();
-    if (!any) return;
-    const int64_t lbeg = (int64_t)blockIdx.y * span;
-    int64_t lend = lbeg + span;
-    if (lend > n) lend = n;
-    const int cx = t & 63, p = t >> 6;
-    const int lr = t >> 2, lq = (t & 3) * 16;  // loader: row lr, 16 consecutive entries from lq
-    const double *drow = delta + (int64_t)cs.idx[c0 + lr] * lda;
-    double acc = 0.0;
-    for (int64_t l0 = lbeg; l0 < lend; l0 += 64) {
-        if (l0 + 64 <= lend && ((lda | l0) & 1) == 0) {
-#pragma unroll
-            for (int e = 0; e < 16; e += 2) {
-                const double2 v = *(const double2 *)(drow + l0 + lq + e);
-                dt[lr][lq + e] = v.x;
-                dt[lr][lq + e + 1] = v.y;
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) dt[lr][lq + e] = (l0 + lq + e < lend) ? drow[l0 + lq + e] : 0.0;
-        }
-        const bool rowok = (l0 + lr) < lend;
-        const double *zr = zin + (l0 + lr) * ldzb + c0 + lq;
-#pragma unroll
-        for (int e = 0; e < 16; e += 2) {
-            const double2 v = rowok ? *(const double2 *)(zr + e) : double2{0.0, 0.0};
-            zt[lr][lq + e] = v.x;
-            zt[lr][lq + e + 1] = v.y;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc += dt[cx][16 * p + e] * zt[16 * p + e][cx];
-        __syncthreads();
+    if (!go) return;
+    const int64_t b = blockIdx.x;
+    // lower-triangle decode: bi (bi + 1) / 2 <= b < (bi + 1)(bi + 2) / 2
+    int64_t bi = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    while (bi * (bi + 1) / 2 > b) --bi;
+    const int64_t bj = b - bi * (bi + 1) / 2;
+    if (bi >= nb) return;
+    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    const int64_t r0 = bi * 64, c0 = bj * 64;
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+        const int64_t r = c0 + ry + 4 * q, c = r0 + cx;  // tile Delta[J, I]
+        tb[ry + 4 * q][cx] = (r < n && c < n) ? delta[r * lda + c] : 0.0;
     }
-    red[p][cx] = acc;
     __syncthreads();
-    if (p == 0) dpart[(int64_t)blockIdx.y * kp + c0 + cx] = ((red[0][cx] + red[1][cx]) + red[2][cx]) + red[3][cx];
+    bool diff = false;
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+        const int rr = ry + 4 * q;
+        const int64_t r = r0 + rr, c = c0 + cx;  // Delta[r, c] against Delta[c, r] = tb[cx][rr]
+        if (r < n && c < n) diff |= __double_as_longlong(delta[r * lda + c]) != __double_as_longlong(tb[cx][rr]);
+    }
+    if (__syncthreads_or(diff) && threadIdx.x == 0) ctrl->sym = 0;
 }
 
-// d_c = sum of the kDiagSplit range sums, in range order.
-__global__ void k_diag_sum(const Ctrl *ctrl, const double *dpart, double *d, int64_t kp, int32_t splits) {
+// d_c = (Delta Z)_{i,c} = sum_l Delta_il Z_lc in FP64 for the active columns, as
+// per-row-tile partials dnp[tm][c] (tiles of TILE_M rows) that k_diag_reduce adds.
+// Each partial is summed in exactly the order in which the FP64 sweep epilogue forms
+// the same quantity for the next sweep (rows held by wave row wm and lane group g:
+// wm*64 + 16ib + 4r + g, in (ib, r) order, by fused multiply-adds; the four groups
+// as (g0 + g1) + (g2 + g3); then wm 0 + wm 1), and k_diag_reduce adds the tiles in
+// the finalize's order, so a solve resumed from a returned iterate computes bit for
+// bit the d that the uninterrupted solve took from its epilogue.  Block: 64 columns
+// x one row tile.  The 64 row segments Delta[idx[c], tile] are staged in LDS with
+// coalesced loads; thread (cx, w) then sums the slots (wm, g) = 2w and 2w + 1.
+__global__ __launch_bounds__(256) void k_diag_tiles(const Ctrl *ctrl, const double *delta, int64_t lda,
+                                                    const double *zin, int64_t ldzb, ColState cs, double *dnp,
+                                                    int64_t n, int64_t kp) {
     if (ctrl->error || ctrl->done) return;
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= kp) return;
-    double s = 0.0;
-    for (int q = 0; q < splits; ++q) s += dpart[(int64_t)q * kp + c];
-    d[c] = s;
+    __shared__ double ds[64][TILE_M + 1];
+    __shared__ double sh[8][64];
+    __shared__ int32_t srow[64];
+    const int cx = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t c0 = (int64_t)blockIdx.x * 64, c = c0 + cx;
+    const int64_t tm = blockIdx.y, j0 = tm * TILE_M;
+    const bool act = cs.state[c] == COL_ACTIVE;
+    if (w == 0) srow[cx] = act ? cs.idx[c] : -1;
+    if (!__syncthreads_or(act)) return;
+    // Wave w stages rows 16w .. 16w + 15 of ds (one 128-entry segment of Delta row
+    // idx[c] each); addresses are clamped into Delta and the values masked, so the
+    // 32 loads of a lane issue without branches between them.
+    const int64_t ja = j0 + cx < n ? j0 + cx : n - 1, jb = j0 + cx + 64 < n ? j0 + cx + 64 : n - 1;
+    const bool oka = j0 + cx < n, okb = j0 + cx + 64 < n;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+        const int row = 16 * w + rr;
+        const int32_t i = srow[row];
+        const double *drow = delta + (int64_t)(i >= 0 ? i : 0) * lda;
+        const double va = drow[ja], vb = drow[jb];
+        ds[row][cx] = (i >= 0 && oka) ? va : 0.0;
+        ds[row][cx + 64] = (i >= 0 && okb) ? vb : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int slot = 2 * w + s, wm = slot >> 2, g = slot & 3;
+        double acc = 0.0;
+        if (act) {
+            double z[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int64_t j = j0 + wm * 64 + 16 * (q >> 2) + 4 * (q & 3) + g;
+                z[q] = zin[(j < n ? j : n - 1) * ldzb + c];
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {  // q = 4 ib + r
+                const int jl = wm * 64 + 16 * (q >> 2) + 4 * (q & 3) + g;
+                const double nxt = fma(ds[cx][jl], z[q], acc);
+                acc = (j0 + jl < n) ? nxt : acc;  // rows past n: skipped, as in the epilogue
+            }
+        }
+        sh[slot][cx] = acc;
+    }
+    __syncthreads();
+    if (w == 0 && act) {
+        const double r0 = (sh[0][cx] + sh[1][cx]) + (sh[2][cx] + sh[3][cx]);
+        const double r1 = (sh[4][cx] + sh[5][cx]) + (sh[6][cx] + sh[7][cx]);
+        dnp[tm * kp + c] = r0 + r1;
+    }
+}
+
+// d_c = the row-tile partials added exactly as the finalize adds them: group g sums
+// tiles g, g + 4, ... in order, then ((s0 + s1) + s2) + s3.  Block: 64 columns x 4
+// groups.
+__global__ __launch_bounds__(256) void k_diag_reduce(const Ctrl *ctrl, ColState cs, const double *dnp, double *d,
+                                                     int64_t nrt, int64_t kp) {
+    if (ctrl->error || ctrl->done) return;
+    __shared__ double sh[4][64];
+    const int cx = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + cx;
+    const bool act = cs.state[c] == COL_ACTIVE;
+    double a = 0.0;
+    if (act)
+        for (int64_t rt = g; rt < nrt; rt += 4) a += dnp[rt * kp + c];
+    sh[g][cx] = a;
+    __syncthreads();
+    if (g == 0 && act) d[c] = ((sh[0][cx] + sh[1][cx]) + sh[2][cx]) + sh[3][cx];
 }
 
 __device__ inline uint64_t wave_max_u64(uint64_t v) {
@@ -342,15 +461,15 @@ __device__ inline void wave_atomic_max(uint64_t *p, uint64_t v) {
 // product-free first sweep) may certify a column; a certified column keeps its
 // input iterate and lambda_c = theta_i + d_c of this sweep (Alg. 1/2 return steps).
 // Block: 64 columns; thread (cx, g) sums row tiles g, g + 4, ...; wave 0 decides.
-__global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColState cs, const double *dvec,
+__global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColState cs, double *dvec,
                                                   const double *theta, const double *part, int64_t nrt, int64_t kp,
-                                                  int32_t sweep, int32_t in_par, int32_t out_par) {
+                                                  int32_t sweep, int32_t in_par, int32_t out_par, const double *dnp) {
     if (ctrl->error || ctrl->done) return;
-    __shared__ double sh[4][NPART][64];
+    __shared__ double sh[4][NPART + 1][64];
     const int cx = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t c = (int64_t)blockIdx.x * 64 + cx;
     const bool act = cs.state[c] == COL_ACTIVE;
-    double p[NPART] = {0.0, 0.0, 0.0, 0.0};
+    double p[NPART] = {0.0, 0.0, 0.0, 0.0}, dn = 0.0;
     if (act) {
         for (int64_t rt = g; rt < nrt; rt += 4) {
             const double4 v = *(const double4 *)&part[(rt * kp + c) * NPART];
@@ -358,14 +477,17 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
             p[1] += v.y;
             p[2] += v.z;
             p[3] += v.w;
+            if (dnp) dn += dnp[rt * kp + c];
         }
     }
 #pragma unroll
     for (int q = 0; q < NPART; ++q) sh[g][q][cx] = p[q];
+    sh[g][NPART][cx] = dn;
     __syncthreads();
     if (g != 0) return;
 #pragma unroll
     for (int q = 0; q < NPART; ++q) p[q] = ((sh[0][q][cx] + sh[1][q][cx]) + sh[2][q][cx]) + sh[3][q][cx];
+    dn = ((sh[0][NPART][cx] + sh[1][NPART][cx]) + sh[2][NPART][cx]) + sh[3][NPART][cx];
     int32_t decided = -1;
     double s = 0.0;
     uint64_t res_bits = 0;
@@ -418,6 +540,7 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
         }
     }
     const bool still = act && decided < 0;
+    if (dnp && still) dvec[c] = dn;  // d of the next sweep, whose input is this sweep's W
     wave_atomic_max(&ctrl->acc_maxstep, act ? dbits(s) : 0);
     wave_atomic_max(&ctrl->acc_maxdist, still ? dbits(sqrt(p[3])) : 0);
     wave_atomic_max(&ctrl->acc_maxres, res_bits);
@@ -615,7 +738,12 @@ inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) /
 
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp) {
-    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k);
+    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k, 0);
+    return launch_init_cols(s, ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp);
+}
+
+hipError_t launch_init_cols(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
+                            int64_t kp, uint32_t *bitmap, int32_t ntiles_n, int32_t start_stamp) {
     const int64_t words = (n + 31) / 32;
     k_fill_u32<<<blocks_for(words, 256) < 1024 ? blocks_for(words, 256) : 1024, 256, 0, s>>>(bitmap, words, 0u);
     const int64_t m = kp > ntiles_n ? kp : ntiles_n;
@@ -628,8 +756,14 @@ hipError_t launch_plan_dense(hipStream_t s, Ctrl *ctrl, ColState cs, int64_t kp)
     return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active) {
-    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, active);
+hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0) {
+    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, active, sym0);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_sym(hipStream_t s, Ctrl *ctrl, const double *delta, int64_t lda, int64_t n) {
+    const int64_t nb = (n + 63) / 64;
+    k_check_sym<<<(unsigned)(nb * (nb + 1) / 2), 256, 0, s>>>(ctrl, delta, lda, n, nb);
     return hipGetLastError();
 }
 
@@ -640,11 +774,13 @@ hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, co
     return hipGetLastError();
 }
 
+int64_t prep_delta_chunks(int64_t np) { return (np + PREP_ROWS - 1) / PREP_ROWS; }
+
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
                              int64_t n, int64_t np, double *dpad, void *dlo, int32_t low_type, float *d32,
                              double *colpart) {
-    const int64_t chunks = (np + PREP_ROWS - 1) / PREP_ROWS;
-    dim3 g((unsigned)(np / 64), (unsigned)chunks);
+    const int64_t chunks = prep_delta_chunks(np);
+    dim3 g((unsigned)((np + 255) / 256), (unsigned)chunks);
     if (low_type == LT_F16)
         k_prep_delta<_Float16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, (_Float16 *)dlo, d32, colpart);
     else
@@ -690,24 +826,19 @@ hipError_t launch_sweep1_dense(hipStream_t s, const Ctrl *ctrl, const double *th
 }
 
 hipError_t launch_diag_dense(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
-                             int64_t ldzb, ColState cs, double *dpart, double *dvec, int64_t n, int64_t kp) {
-    // about 64-256 entries of l per block, at most DIAG_SPLIT ranges
-    int64_t splits = (n + 255) / 256;
-    if (splits > DIAG_SPLIT) splits = DIAG_SPLIT;
-    if (splits < 1) splits = 1;
-    int64_t span = (n + splits - 1) / splits;
-    span = (span + 63) / 64 * 64;
-    splits = (n + span - 1) / span;
-    dim3 g((unsigned)(kp / 64), (unsigned)splits);
-    k_diag_dense<<<g, 256, 0, s>>>(ctrl, delta, lda, zin, ldzb, cs, dpart, n, kp, span);
-    k_diag_sum<<<blocks_for(kp, 256), 256, 0, s>>>(ctrl, dpart, dvec, kp, (int32_t)splits);
+                             int64_t ldzb, ColState cs, double *dnp, double *dvec, int64_t n, int64_t kp) {
+    const int64_t nrt = (n + TILE_M - 1) / TILE_M;
+    dim3 g((unsigned)(kp / 64), (unsigned)nrt);
+    k_diag_tiles<<<g, 256, 0, s>>>(ctrl, delta, lda, zin, ldzb, cs, dnp, n, kp);
+    k_diag_reduce<<<(unsigned)(kp / 64), 256, 0, s>>>(ctrl, cs, dnp, dvec, nrt, kp);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, const double *dvec,
+hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, double *dvec,
                            const double *theta, const double *part, int64_t nrt, int64_t kp, int32_t sweep,
-                           int32_t in_par, int32_t out_par) {
-    k_finalize<<<(unsigned)(kp / 64), 256, 0, s>>>(ctrl, o, cs, dvec, theta, part, nrt, kp, sweep, in_par, out_par);
+                           int32_t in_par, int32_t out_par, const double *dnp) {
+    k_finalize<<<(unsigned)(kp / 64), 256, 0, s>>>(ctrl, o, cs, dvec, theta, part, nrt, kp, sweep, in_par, out_par,
+                                                     dnp);
     return hipGetLastError();
 }
 

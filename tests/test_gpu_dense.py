@@ -62,6 +62,24 @@ def test_nonsymmetric_paper_family(ipt):
     check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12, gpu_sweeps=g.sweeps)
 
 
+@pytest.mark.parametrize("n,pair", [(300, (299, 298)), (256, (64, 63)), (129, (128, 127))])
+def test_nearly_symmetric(ipt, n, pair):
+    """A symmetric Delta with one entry Delta_ab (b = a - 1) changed by 2e-3: the
+    exact-symmetry check must see it, else the reported lambda_a = theta_a + d_a would
+    use Delta_ba for Delta_ab and be off by about 2e-3 |z_b| ~ 3e-6, far above the
+    bound.  The pairs sit in a diagonal 64 x 64 tile at the ragged edge, across two
+    tiles, and in a last row tile of one row."""
+    say("dense nearly symmetric n=%d pair=%s" % (n, pair))
+    th, de = W.dense_sym_gaussian(n, 0.03, 4)
+    de = de.copy()
+    de[pair] += 2e-3
+    for prec in ("fp64", "ladder"):
+        p = ipt.PREC_LADDER if prec == "ladder" else ipt.PREC_FP64
+        g = _solve(ipt, th, de, tol=1e-11, precision=p)
+        ref = oracle.ipt_dense(th, de, tol=1e-11)
+        check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-11)
+
+
 @pytest.mark.parametrize("eps,want", [(0.3, 0), (0.9, 1), (2.0, 2)])
 def test_two_by_two_statuses(ipt, eps, want):
     """2x2 example: converges below sqrt(3)/2, cycles at 0.9, diverges at 2."""
@@ -75,11 +93,17 @@ def test_two_by_two_statuses(ipt, eps, want):
         check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12)
 
 
-def test_warm_start_resume_and_determinism(ipt):
+@pytest.mark.parametrize("kind", ["sym", "nonsym"])
+def test_warm_start_resume_and_determinism(ipt, kind):
     """Stopping after 2 sweeps and resuming from the returned iterate equals the
-    uninterrupted solve bit for bit; two identical solves are bitwise equal."""
-    say("dense resume n=384")
-    th, de = W.dense_sym_gaussian(384, 0.03, 2)
+    uninterrupted solve bit for bit (the resumed first sweep computes d from Delta and
+    Z in the order the uninterrupted solve's epilogue used); two identical solves are
+    bitwise equal."""
+    say("dense resume n=384 %s" % kind)
+    if kind == "sym":
+        th, de = W.dense_sym_gaussian(384, 0.03, 2)
+    else:
+        th, de = W.dense_uniform_nonsym(384, 0.03, 2)
     full = _solve(ipt, th, de, tol=1e-12)
     again = _solve(ipt, th, de, tol=1e-12)
     np.testing.assert_array_equal(full.z, again.z)
@@ -137,6 +161,19 @@ def test_ladder_parity(ipt, eps, low):
     assert g.info["sweep_prec"][-1] == "fp64"
     if low != "none":
         assert "low" in g.info["sweep_prec"]
+
+
+@pytest.mark.parametrize("low", ["bf16", "none"])
+def test_ladder_parity_nonsymmetric(ipt, low):
+    """The ladder on the paper's non-symmetric family (the epilogue's d of the next
+    sweep then reads Delta_ij itself, beside the Delta_ji of the split product)."""
+    say("dense ladder nonsym n=640 low=%s" % low)
+    th, de = W.dense_uniform_nonsym(640, 0.02, 3)
+    lt = {"bf16": ipt.LOW_BF16, "none": ipt.LOW_NONE}[low]
+    g = _solve(ipt, th, de, tol=1e-10, precision=ipt.PREC_LADDER, low_type=lt)
+    ref = oracle.ipt_dense(th, de, tol=1e-10)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-10)
+    assert g.info["sweep_prec"][-1] == "fp64"
 
 
 @pytest.mark.parametrize("eps", [0.01, 0.05])
