@@ -56,7 +56,7 @@ enum { IPT_CONVERGED = 0, IPT_NOT_CONVERGED = 1, IPT_DIVERGED = 2 };
 /* Arithmetic of the product Delta x Z in a sweep. */
 enum {
     IPT_PREC_FP64 = 0,   /* every product in FP64 (plain IPT) */
-    IPT_PREC_LADDER = 1  /* low precision -> FP32 -> FP64; only FP64 sweeps may certify */
+    IPT_PREC_LADDER = 1  /* low precision -> FP32 class -> FP64; only FP64 sweeps may certify */
 };
 /* Low rung of the ladder. */
 enum { IPT_LOW_BF16 = 0, IPT_LOW_FP16 = 1, IPT_LOW_NONE = 2 /* start the ladder at FP32 */ };
@@ -95,6 +95,13 @@ typedef struct ipt_opts {
  * column NOT_CONVERGED.  Sweeps then count applications of F.  Requires
  * precision = IPT_PREC_FP64 (every application is an FP64 sweep). */
 #define IPT_FLAG_ACX 8
+/* Dense ladder: compute the FP32-class rung's correction product Delta (Z - E) on
+ * the FP32 matrix cores.  By default it is formed from three FP16 products: A =
+ * s_d Delta and B = s_z (Z - E), scaled by powers of two into the FP16 range, are
+ * split into hi + lo halves and A B ~ Ah Bh + Ah Bl + Al Bh accumulated in FP32,
+ * about 2^-22 relative against FP32's 2^-24, at FP16 matrix-core speed.  Either way
+ * only FP64 sweeps certify a column.  (The sparse and batched ladders always use FP32.) */
+#define IPT_FLAG_MID_FP32 16
 #define IPT_HIST 128
 
 /* Host struct filled by a solve (may be NULL). */

@@ -122,6 +122,7 @@ DevOpts dev_opts(const ipt_opts &o) {
     d.low_type = o.low_type;
     d.first_product = 0;
     d.acx = (o.flags & IPT_FLAG_ACX) ? 1 : 0;
+    d.mid_x3 = (d.ladder && !(o.flags & IPT_FLAG_MID_FP32)) ? 1 : 0;  // the dense GEMM's FP32-class rung
     return d;
 }
 
@@ -304,6 +305,7 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
         return fail(h, IPT_EINVAL, "NULL argument");
     DevOpts dopt = dev_opts(o);
     dopt.low_type = IPT_LOW_NONE;  // batched ladder: FP32 split-form sweeps, then FP64
+    dopt.mid_x3 = 0;
     const bool ladder = dopt.ladder, acx = dopt.acx != 0;
     DeviceGuard guard(h->device);
     hipStream_t s = h->stream;
@@ -663,12 +665,15 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     // symmetric Delta (checked once here) it reads Delta_ji, coalesced, for Delta_ij.
     const bool fuse_d = !acx;
     IPT_HIP(h, launch_ctrl_init(s, ctrl, start_prec, k, fuse_d ? 1 : 0));
-    if (use_low && lt == LT_F16) IPT_HIP(h, launch_absmax(s, ctrl, delta, n, n, lda));
+    // FP16 shadows of Delta (low rung, three-product rung) need its power-of-two scale
+    const bool mid_x3 = dopt.mid_x3 != 0;
+    if ((use_low && lt == LT_F16) || mid_x3) IPT_HIP(h, launch_absmax(s, ctrl, delta, n, n, lda));
     const double *dA = direct ? delta : dpad;
     const int64_t ldA = direct ? lda : np;
     if (!direct || ladder || norm)
         IPT_HIP(h, launch_prep_delta(s, ctrl, theta, delta, lda, n, np, direct ? nullptr : dpad,
-                                     use_low ? dlo : nullptr, lt, ladder ? d32 : nullptr, norm ? scratch : nullptr));
+                                     use_low ? dlo : nullptr, lt, (ladder && !mid_x3) ? d32 : nullptr,
+                                     norm ? scratch : nullptr, mid_x3 ? (_Float16 *)d32 : nullptr));
     if (fuse_d) IPT_HIP(h, launch_check_sym(s, ctrl, delta, lda, n));
     IPT_HIP(h, launch_init_cols(s, ctrl, cs, idx, n, k, kp, bitmap, (int32_t)ntn, 0));
     IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
@@ -678,7 +683,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         if (padded) IPT_HIP(h, launch_zero_pad(s, zb[0], kp, n, np, k, kp));
     } else {
         // warm start, or the base iterate E of the first ACX cycle
-        IPT_HIP(h, launch_load_z0(s, ctrl, z0, ldz0, zb[0], kp, cs.idx, n, np, k, kp));
+        IPT_HIP(h, launch_load_z0(s, ctrl, z0, ldz0, zb[0], kp, cs.idx, n, np, k, kp, mid_x3 ? 1 : 0));
         if (padded)
             for (int q = 1; q < (acx ? 4 : 2); ++q) IPT_HIP(h, launch_zero_pad(s, zb[q], kp, n, np, k, kp));
     }
@@ -703,11 +708,11 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
             IPT_HIP(h, launch_sweep1_dense(s, ctrl, theta, dA, ldA, cs, dvec, zout, kp, part, n, np, kp));
             IPT_HIP(h, timer.mark(t, 1, s));
         } else {
-            if (ladder) IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, lt));
+            if (ladder) IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, lt, dopt.mid_x3));
             if (!d_ready) IPT_HIP(h, launch_diag_dense(s, ctrl, dA, ldA, zin, kp, cs, dnp, dvec, n, kp));
             IPT_HIP(h, timer.mark(t, 0, s));
             IPT_HIP(h, launch_sweep_gemm(s, ctrl, dA, ldA, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, t,
-                                         lt, ypart, nblk, fuse_d ? dnp : nullptr));
+                                         lt, ypart, nblk, fuse_d ? dnp : nullptr, dopt.mid_x3));
             IPT_HIP(h, timer.mark(t, 1, s));
         }
         const bool fused_d = !first_exact && fuse_d;
@@ -744,6 +749,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     if (ipt_status st = check_opts(h, opts, o)) return st;
     DevOpts dopt = dev_opts(o);
     dopt.low_type = IPT_LOW_NONE;  // the sparse ladder runs FP32 then FP64 sweeps
+    dopt.mid_x3 = 0;
     dopt.first_product = 1;
     const bool ladder = dopt.ladder;
     const bool cold = (z0 == nullptr);

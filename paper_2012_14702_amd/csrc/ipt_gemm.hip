@@ -73,6 +73,10 @@ struct GemmArgs {
     double *ypart;        // split-K partial products of narrow sweeps
     int32_t nblk;         // blocks that fill the chip (2 per CU)
     double *dnp;          // NULL, or [row tile][column] partials of d for the next sweep
+    // FP32-class rung as three FP16 products (mid_x3): hi/lo FP16 shadows of the scaled
+    // Delta (np x np each) and of the scaled transposed Z - E (kp x np each)
+    const _Float16 *dmh, *dml, *zth, *ztl;
+    int32_t mid_x3;
 };
 
 // Epilogue reduction slots: the NPART sums of the finalize, then the partial of
@@ -115,8 +119,10 @@ __device__ inline int live_col_blocks(int32_t lim, int wn) {
 constexpr int SMEM_F64 = 2 * BM * (16 + 1) * 8 + 2 * 16 * BN * 8;
 constexpr int SMEM_LOW16 = 2 * 2 * BM * (64 + 8) * 2;
 constexpr int SMEM_LOW32 = 2 * 2 * BM * (32 + 1) * 4;
+constexpr int X3_BK = 32, X3_LDP = X3_BK + 8;
+constexpr int SMEM_X3 = 2 * 4 * BM * X3_LDP * 2;  // two stages of A hi/lo and B hi/lo
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int SMEM_MAIN = cmax(SMEM_F64, cmax(SMEM_LOW16, SMEM_LOW32));
+constexpr int SMEM_MAIN = cmax(cmax(SMEM_F64, SMEM_X3), cmax(SMEM_LOW16, SMEM_LOW32));
 
 // Shared epilogue.  Each lane holds 4 column blocks (jb) x 16 rows of the block
 // tile; row_of(ib, r) gives the tile row of accumulator (ib, r), which depends on
@@ -487,6 +493,105 @@ __device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NRED
     }
 }
 
+// ------------------------------------------------ FP32-class rung, 3 x FP16
+// The correction product (Delta)(Z - E) of an FP32-class sweep from FP16 matrix-core
+// products: with A = s_d Delta and B = s_z (Z - E) scaled by powers of two, each split
+// into FP16 hi + lo (lo = the rounding remainder, so hi + lo carries about 22 bits),
+// A B ~ Ah Bh + Ah Bl + Al Bh accumulated in FP32 (the dropped Al Bl is 2^-22
+// relative).  v_mfma_f32_16x16x32_f16 runs 16 times the FP32 matrix rate, so the three
+// products cost less than a fifth of one FP32 product.  BK = 32; each 16-byte chunk
+// holds 8 elements, 4 chunks per tile row, 256 threads cover 64 rows per pass.
+template <bool SPLIT>
+__device__ __forceinline__ void gemm_x3_body(char *smem, double (*red)[BN][NRED], const PackedCols scol,
+                                             const GemmArgs &g, double unscale, int tm, int64_t k0, int64_t k1,
+                                             double *yp, bool sym) {
+    typedef _Float16 Tile[BM][X3_LDP];
+    Tile *S = (Tile *)smem;  // stage s: S[4 s + 0..3] = A hi, A lo, B hi, B lo
+
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
+    const int l_r = t >> 2, l_c = (t & 3) * 8;
+    const int64_t ldd = g.np, ldt = g.np;
+    const _Float16 *Ah = g.dmh + (int64_t)tm * BM * ldd, *Al = g.dml + (int64_t)tm * BM * ldd;
+    int64_t boff[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int32_t cg = scol[l_r + 64 * q];
+        boff[q] = cg >= 0 ? (int64_t)cg * ldt + l_c : -1;
+    }
+    const int nj = SPLIT ? live_col_blocks(scol.lim, wn) : 4;
+
+    f4_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    uint4 st[4][2];  // staged chunks: A hi, A lo, B hi, B lo x two rows
+    auto load = [&](int64_t k) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int64_t ao = (int64_t)(l_r + 64 * q) * ldd + k + l_c;
+            st[0][q] = *(const uint4 *)(Ah + ao);
+            st[1][q] = *(const uint4 *)(Al + ao);
+            st[2][q] = boff[q] >= 0 ? *(const uint4 *)(g.zth + boff[q] + k) : uint4{0u, 0u, 0u, 0u};
+            st[3][q] = boff[q] >= 0 ? *(const uint4 *)(g.ztl + boff[q] + k) : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto put = [&](int stage) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) *(uint4 *)&S[4 * stage + m][l_r + 64 * q][l_c] = st[m][q];
+    };
+    const int nk = (int)((k1 - k0) / X3_BK);
+    load(k0);
+    put(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        load(k0 + (int64_t)(kt + 1 < nk ? kt + 1 : kt) * X3_BK);
+        const int koff = 8 * (lane >> 4);
+        h8_t ah[4], al[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            ah[ib] = *(const h8_t *)&S[4 * cur + 0][wm * 64 + 16 * ib + (lane & 15)][koff];
+            al[ib] = *(const h8_t *)&S[4 * cur + 1][wm * 64 + 16 * ib + (lane & 15)][koff];
+        }
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            if (SPLIT && jb >= nj) continue;
+            const h8_t bh = *(const h8_t *)&S[4 * cur + 2][wn * 64 + 16 * jb + (lane & 15)][koff];
+            const h8_t bl = *(const h8_t *)&S[4 * cur + 3][wn * 64 + 16 * jb + (lane & 15)][koff];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[ib], bh, acc[ib][jb], 0, 0, 0);
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[ib], bl, acc[ib][jb], 0, 0, 0);
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[ib], bh, acc[ib][jb], 0, 0, 0);
+            }
+        }
+        put(cur ^ 1);
+        __syncthreads();
+    }
+
+    // f32-accumulating 16x16 MFMAs: lane l, register r holds row 4(l/16) + r, column l%16.
+    auto row_of = [](int ib, int r, int l) { return 16 * ib + 4 * (l >> 4) + r; };
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    if (wn * 64 + 16 * jb + (lane & 15) < scol.lim)  // empty packed columns: never read
+                        yp[(int64_t)(wm * 64 + row_of(ib, r, lane)) * BN + wn * 64 + 16 * jb + (lane & 15)] =
+                            unscale * (double)acc[ib][jb][r];
+    } else {
+        auto y_of = [&](int ib, int jb, int r, double dji) { return dji + unscale * (double)acc[ib][jb][r]; };
+        if (g.dnp) sweep_epilogue<true, true>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
+        else sweep_epilogue<true, false>(g, scol, tm, wm, wn, lane, row_of, y_of, red, sym);
+    }
+}
+
 // The sweep's product over the K range [k0, k1), in the precision the ladder chose;
 // SPLIT writes the partial tile instead of running the epilogue.
 template <bool SPLIT>
@@ -497,7 +602,8 @@ __device__ __forceinline__ void sweep_tile(const Ctrl *ctrl, const GemmArgs &g, 
     if (prec == PREC_F64) {
         gemm_f64_body<SPLIT>(smem, red, scol, g, tm, k0, k1, yp, sym);
     } else if (prec == PREC_F32) {
-        gemm_low_body<float, SPLIT>(smem, red, scol, g, g.d32, 1.0, tm, k0, k1, yp, sym);
+        if (g.mid_x3) gemm_x3_body<SPLIT>(smem, red, scol, g, 1.0 / (ctrl->dscale * ctrl->zscale), tm, k0, k1, yp, sym);
+        else gemm_low_body<float, SPLIT>(smem, red, scol, g, g.d32, 1.0, tm, k0, k1, yp, sym);
     } else if (prec == PREC_LOW) {
         if (g.low_type == LT_F16)
             gemm_low_body<_Float16, SPLIT>(smem, red, scol, g, (const _Float16 *)g.dlo,
@@ -598,8 +704,12 @@ __global__ __launch_bounds__(256, 1) void k_sweep_split_epi(const Ctrl *ctrl, Ge
 hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const void *dlo,
                              const float *d32, const void *zt, const double *zin, double *zout, const double *theta,
                              ColState cs, const double *dvec, double *part, int64_t n, int64_t np, int64_t kp,
-                             int32_t sweep, int32_t low_type, double *ypart, int nblk, double *dnp) {
-    GemmArgs g{delta, lda, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, low_type, ypart, nblk, dnp};
+                             int32_t sweep, int32_t low_type, double *ypart, int nblk, double *dnp, int32_t mid_x3) {
+    // three-product rung: the FP16 hi/lo shadows live where the FP32 shadows would
+    const _Float16 *dmh = (const _Float16 *)d32, *dml = dmh ? dmh + np * np : nullptr;
+    const _Float16 *zth = (const _Float16 *)zt, *ztl = zth ? zth + kp * np : nullptr;
+    GemmArgs g{delta, lda, dlo, d32, zt, zin, zout, theta, cs, dvec, part, n, np, kp, low_type, ypart, nblk, dnp,
+               dmh, dml, zth, ztl, mid_x3};
     (void)sweep;
     const int blocks = (int)((np / BM) * (kp / BN));
     const SplitBounds b = split_bounds(np, kp, nblk);

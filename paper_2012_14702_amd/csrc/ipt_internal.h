@@ -56,6 +56,7 @@ struct DevOpts {
     int32_t max_iter, div_growth, ladder, low_type;
     int32_t first_product;  // the first sweep of a cold start multiplies by Delta (sparse path)
     int32_t acx;            // IPT-ACX cycles (orders 3, 2, 3, 2, ...)
+    int32_t mid_x3;         // dense ladder: FP32-class rung as three FP16 products
 };
 
 // IPT-ACX schedule: sweep t (1-based) is application q (0-based) of a cycle of
@@ -118,13 +119,15 @@ hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, co
 // colpart holds prep_delta_chunks(np) x n doubles.
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
                              int64_t n, int64_t np, double *dpad, void *dlo, int32_t low_type, float *d32,
-                             double *colpart);
+                             double *colpart, _Float16 *dmh = nullptr);
 int64_t prep_delta_chunks(int64_t np);
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
                             const int32_t *col, const double *val, int64_t n, double *scratch);
 hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld);
-hipError_t launch_load_z0(hipStream_t s, const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb,
-                          int64_t ldzb, const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kp);
+// set_zscale: also the power-of-two scale of the FP16 shadow of Z - E from max |Z - E|
+// (a warm-started ladder whose first sweep is on an FP16-shadowed rung).
+hipError_t launch_load_z0(hipStream_t s, Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
+                          const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kp, int32_t set_zscale = 0);
 hipError_t launch_zero_pad(hipStream_t s, double *zb, int64_t ldzb, int64_t n, int64_t np, int64_t k, int64_t kp);
 hipError_t launch_sweep1_dense(hipStream_t s, const Ctrl *ctrl, const double *theta, const double *delta,
                                int64_t lda, ColState cs, double *dvec, double *zout, int64_t ldzb, double *part,
@@ -144,7 +147,7 @@ hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const do
                           int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
                           int64_t n, int64_t k, const ipt_colinfo *ci);
 hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
-                         int64_t ldt, int64_t np, int64_t kp, int32_t low_type);
+                         int64_t ldt, int64_t np, int64_t kp, int32_t low_type, int32_t mid_x3 = 0);
 
 hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count);  // zero fill
 
@@ -254,7 +257,7 @@ hipError_t launch_acx(hipStream_t s, const Ctrl *ctrl, const int32_t *state, dou
 hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const void *dlo,
                              const float *d32, const void *zt, const double *zin, double *zout, const double *theta,
                              ColState cs, const double *dvec, double *part, int64_t n, int64_t np, int64_t kp,
-                             int32_t sweep, int32_t low_type, double *ypart, int nblk, double *dnp);
+                             int32_t sweep, int32_t low_type, double *ypart, int nblk, double *dnp, int32_t mid_x3);
 // Launch bounds of the split-K path of narrow sweeps (grid sizes and the tiles of
 // the partial-product workspace, each 128 x 128 FP64); all zero when no packed width
 // of this shape is narrow.

@@ -116,13 +116,18 @@ constexpr int PREP_ROWS = 128;
 template <typename TL>
 __global__ __launch_bounds__(256) void k_prep_delta(const Ctrl *ctrl, const double *theta, const double *delta,
                                                     int64_t lda, int64_t n, int64_t np, double *dpad, TL *dlo,
-                                                    float *d32, double *colpart) {
+                                                    float *d32, double *colpart, _Float16 *dmh) {
     typedef TL tl4_t __attribute__((ext_vector_type(4)));
+    typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
     __shared__ double sh[4][256];
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * 256 + 4 * cx;
     const int64_t r0 = (int64_t)blockIdx.y * PREP_ROWS;
+    // the FP16 shadows (low rung, hi/lo of the three-product rung) carry the power-of-two
+    // scale of Delta; a BF16 low shadow needs none
     const double dscale = ctrl->dscale;
+    const double lscale = std::is_same<TL, _Float16>::value ? dscale : 1.0;
+    _Float16 *dml = dmh ? dmh + np * np : nullptr;
     const bool vec = ((lda & 1) == 0) && (((uintptr_t)delta & 15) == 0) && c0 + 4 <= n;
     const bool live = c0 < np;  // np is a multiple of 128, so c0 + 4 <= np
     double acc[4] = {0.0, 0.0, 0.0, 0.0}, th[4];
@@ -167,8 +172,19 @@ __global__ __launch_bounds__(256) void k_prep_delta(const Ctrl *ctrl, const doub
                     *(double2 *)(dpad + o + 2) = double2{v[u][2], v[u][3]};
                 }
                 if (dlo)
-                    *(tl4_t *)(dlo + o) = tl4_t{to_low<TL>(v[u][0] * dscale), to_low<TL>(v[u][1] * dscale),
-                                                to_low<TL>(v[u][2] * dscale), to_low<TL>(v[u][3] * dscale)};
+                    *(tl4_t *)(dlo + o) = tl4_t{to_low<TL>(v[u][0] * lscale), to_low<TL>(v[u][1] * lscale),
+                                                to_low<TL>(v[u][2] * lscale), to_low<TL>(v[u][3] * lscale)};
+                if (dmh) {
+                    h4_t hi, lo;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double x = v[u][e] * dscale;
+                        hi[e] = to_low<_Float16>(x);
+                        lo[e] = to_low<_Float16>(x - (double)hi[e]);
+                    }
+                    *(h4_t *)(dmh + o) = hi;
+                    *(h4_t *)(dml + o) = lo;
+                }
                 if (d32)
                     *(float4 *)(d32 + o) = float4{(float)v[u][0], (float)v[u][1], (float)v[u][2], (float)v[u][3]};
 #pragma unroll
@@ -239,16 +255,29 @@ __global__ void k_zero_f64(double *p, int64_t count) {
 
 // Z <- z0 with Z[idx[c], c] = 1 (chart U_i), or Z <- E when z0 is NULL; padding zero.
 // Writes columns [0, kw) of rows [0, np) (grid-stride over the np x kw elements).
-__global__ void k_load_z0(const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
-                          const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kw) {
+__device__ inline void wave_atomic_max(uint64_t *p, uint64_t v);
+
+// Also records max |Z - E| in ctrl->acc_maxdist (when want_max), from which
+// k_set_zscale scales the FP16 shadow of Z - E for a first sweep on that rung.
+__global__ void k_load_z0(Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb, const int32_t *idx,
+                          int64_t n, int64_t np, int64_t k, int64_t kw, int32_t want_max) {
     if (ctrl->error) return;
     const int64_t total = np * kw;
+    double m = 0.0;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = e / kw, c = e - j * kw;
         double v = 0.0;
         if (j < n && c < k) v = (j == idx[c]) ? 1.0 : (z0 ? z0[j * ldz0 + c] : 0.0);
         zb[j * ldzb + c] = v;
+        if (j < n && c < k && j != idx[c]) m = fmax(m, fabs(v));
     }
+    if (want_max) wave_atomic_max(&ctrl->acc_maxdist, dbits(isfinite(m) ? m : 0.0));
+}
+
+__global__ void k_set_zscale(Ctrl *ctrl) {
+    const double md = bitsd(ctrl->acc_maxdist);
+    ctrl->zscale = (md > 0.0 && isfinite(md)) ? exp2(floor(log2(8192.0 / md))) : 1.0;
+    ctrl->acc_maxdist = 0;
 }
 
 // Zero the padding rows [n, np) and padding columns [k, kp) of a Z buffer.
@@ -642,9 +671,10 @@ __device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep) {
     }
     ctrl->prec = next;
     ctrl->prev_maxstep = ms;
-    // FP16 rung: scale Z - E by a power of two so that its largest entry (bounded
-    // by max_c |W_c - e_i|) lands near 2^13, well inside the FP16 range.
-    if (o.ladder && o.low_type == IPT_LOW_FP16) {
+    // FP16 shadows (FP16 low rung, three-product rung): scale Z - E by a power of two
+    // so that its largest entry (bounded by max_c |W_c - e_i|) lands near 2^13, well
+    // inside the FP16 range.
+    if (o.ladder && (o.low_type == IPT_LOW_FP16 || o.mid_x3)) {
         const double md = bitsd(ctrl->acc_maxdist);
         ctrl->zscale = (md > 0.0 && isfinite(md)) ? exp2(floor(log2(8192.0 / md))) : 1.0;
     }
@@ -653,12 +683,30 @@ __device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep) {
 
 // max |x_jl| over a rows x cols matrix (leading dimension ld) -> ctrl->dmax_bits;
 // then the FP16 scale of the Delta shadow.
-__global__ void k_absmax(Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld) {
+// Block: 256 columns x 128 rows; thread (cx, ry) reads columns 4cx..4cx+3 of rows
+// ry, ry + 4, ... (16-byte loads when the rows allow), one atomic per wave.
+__global__ __launch_bounds__(256) void k_absmax(Ctrl *ctrl, const double *x, int64_t rows, int64_t cols,
+                                                int64_t ld) {
+    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    const int64_t c0 = (int64_t)blockIdx.x * 256 + 4 * cx, r0 = (int64_t)blockIdx.y * 128;
+    const bool vec = ((ld & 1) == 0) && (((uintptr_t)x & 15) == 0) && c0 + 4 <= cols;
     double m = 0.0;
-    const int64_t count = rows * cols;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
-        m = fmax(m, fabs(x[(t / cols) * ld + t % cols]));
-    atomicMax((unsigned long long *)&ctrl->dmax_bits, (unsigned long long)dbits(m));
+    if (c0 < cols) {
+#pragma unroll 4
+        for (int q = 0; q < 32; ++q) {
+            const int64_t r = r0 + ry + 4 * q;
+            if (r >= rows) break;
+            const double *p = x + r * ld + c0;
+            if (vec) {
+                const double2 a = *(const double2 *)p, b = *(const double2 *)(p + 2);
+                m = fmax(m, fmax(fmax(fabs(a.x), fabs(a.y)), fmax(fabs(b.x), fabs(b.y))));
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (c0 + e < cols) m = fmax(m, fabs(p[e]));
+            }
+        }
+    }
+    wave_atomic_max(&ctrl->dmax_bits, dbits(m));
 }
 
 __global__ void k_set_dscale(Ctrl *ctrl) {
@@ -708,11 +756,12 @@ __device__ __forceinline__ void cast_z_tile(double (*tile)[65], T *zt, int64_t l
 }
 
 __global__ __launch_bounds__(256) void k_cast_z(const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs,
-                                                void *zt, int64_t ldt, int32_t low_type) {
+                                                void *zt, int64_t ldt, int64_t kp, int32_t low_type, int32_t mid_x3) {
     if (ctrl->error || ctrl->done) return;
     const int32_t prec = ctrl->prec;
     if (prec != PREC_LOW && prec != PREC_F32) return;
-    const bool f16 = prec == PREC_LOW && low_type == LT_F16;
+    const bool x3 = prec == PREC_F32 && mid_x3;
+    const bool f16 = (prec == PREC_LOW && low_type == LT_F16) || x3;
     const double scale = f16 ? ctrl->zscale : 1.0;
     __shared__ double tile[64][65];
     const int64_t j0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
@@ -725,7 +774,17 @@ __global__ __launch_bounds__(256) void k_cast_z(const Ctrl *ctrl, const double *
         tile[r][cc] = v * scale;
     }
     __syncthreads();
-    if (prec == PREC_F32) cast_z_tile<float>(tile, (float *)zt, ldt, c0, j0);
+    if (x3) {  // hi/lo FP16 halves (kp x ldt each)
+        _Float16 *zh = (_Float16 *)zt, *zl = zh + kp * ldt;
+        const int t2 = threadIdx.x;
+        for (int q = 0; q < 16; ++q) {
+            const int cc = (t2 >> 6) + 4 * q, r = t2 & 63;
+            const double x = tile[r][cc];
+            const _Float16 hi = to_low<_Float16>(x);
+            zh[(c0 + cc) * ldt + j0 + r] = hi;
+            zl[(c0 + cc) * ldt + j0 + r] = to_low<_Float16>(x - (double)hi);
+        }
+    } else if (prec == PREC_F32) cast_z_tile<float>(tile, (float *)zt, ldt, c0, j0);
     else if (f16) cast_z_tile<_Float16>(tile, (_Float16 *)zt, ldt, c0, j0);
     else cast_z_tile<__bf16>(tile, (__bf16 *)zt, ldt, c0, j0);
 }
@@ -778,13 +837,14 @@ int64_t prep_delta_chunks(int64_t np) { return (np + PREP_ROWS - 1) / PREP_ROWS;
 
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
                              int64_t n, int64_t np, double *dpad, void *dlo, int32_t low_type, float *d32,
-                             double *colpart) {
+                             double *colpart, _Float16 *dmh) {
     const int64_t chunks = prep_delta_chunks(np);
     dim3 g((unsigned)((np + 255) / 256), (unsigned)chunks);
     if (low_type == LT_F16)
-        k_prep_delta<_Float16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, (_Float16 *)dlo, d32, colpart);
+        k_prep_delta<_Float16>
+            <<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, (_Float16 *)dlo, d32, colpart, dmh);
     else
-        k_prep_delta<__bf16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, (__bf16 *)dlo, d32, colpart);
+        k_prep_delta<__bf16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, (__bf16 *)dlo, d32, colpart, dmh);
     if (colpart) k_norm1_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, colpart, n, chunks);
     return hipGetLastError();
 }
@@ -802,11 +862,12 @@ hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, cons
     return hipGetLastError();
 }
 
-hipError_t launch_load_z0(hipStream_t s, const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
-                          const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kp) {
+hipError_t launch_load_z0(hipStream_t s, Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
+                          const int32_t *idx, int64_t n, int64_t np, int64_t k, int64_t kp, int32_t set_zscale) {
     int b = blocks_for(np * kp, 256);
     if (b > 8192) b = 8192;
-    k_load_z0<<<b, 256, 0, s>>>(ctrl, z0, ldz0, zb, ldzb, idx, n, np, k, kp);
+    k_load_z0<<<b, 256, 0, s>>>(ctrl, z0, ldz0, zb, ldzb, idx, n, np, k, kp, set_zscale);
+    if (set_zscale) k_set_zscale<<<1, 1, 0, s>>>(ctrl);
     return hipGetLastError();
 }
 
@@ -863,17 +924,16 @@ hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const do
 }
 
 hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld) {
-    int b = blocks_for(rows * cols, 256);
-    if (b > 4096) b = 4096;
-    k_absmax<<<b, 256, 0, s>>>(ctrl, x, rows, cols, ld);
+    dim3 g((unsigned)((cols + 255) / 256), (unsigned)((rows + 127) / 128));
+    k_absmax<<<g, 256, 0, s>>>(ctrl, x, rows, cols, ld);
     k_set_dscale<<<1, 1, 0, s>>>(ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
-                         int64_t ldt, int64_t np, int64_t kp, int32_t low_type) {
+                         int64_t ldt, int64_t np, int64_t kp, int32_t low_type, int32_t mid_x3) {
     dim3 g((unsigned)(kp / 64), (unsigned)(np / 64));
-    k_cast_z<<<g, 256, 0, s>>>(ctrl, zin, ldzb, cs, zt, ldt, low_type);
+    k_cast_z<<<g, 256, 0, s>>>(ctrl, zin, ldzb, cs, zt, ldt, kp, low_type, mid_x3);
     return hipGetLastError();
 }
 

@@ -163,6 +163,40 @@ def test_ladder_parity(ipt, eps, low):
         assert "low" in g.info["sweep_prec"]
 
 
+@pytest.mark.parametrize("eps", [0.01, 0.05])
+def test_ladder_mid_rung_three_fp16_vs_fp32(ipt, eps):
+    """The FP32-class rung from three FP16 products (default) against FP32 matrix
+    cores (FLAG_MID_FP32): both certify at FP64 parity, and the three-product rung
+    needs no more sweeps."""
+    say("dense ladder mid rung n=1024 eps=%g" % eps)
+    th, de = W.dense_sym_gaussian(1024, eps, 1)
+    ref = oracle.ipt_dense(th, de, tol=1e-10)
+    x3 = _solve(ipt, th, de, tol=1e-10, precision=ipt.PREC_LADDER)
+    f32 = _solve(ipt, th, de, tol=1e-10, precision=ipt.PREC_LADDER, flags=ipt.FLAG_MID_FP32)
+    for g in (x3, f32):
+        check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-10)
+        assert "fp32" in g.info["sweep_prec"]
+    assert x3.info["sweeps"] <= f32.info["sweeps"]
+
+
+@pytest.mark.parametrize("n,k", [(640, 40), (1000, 1000)])
+def test_ladder_warm_start_and_narrow(ipt, n, k):
+    """A warm-started ladder begins on the FP32-class rung (its FP16 shadow of Z - E is
+    scaled from the loaded iterate); k = 40 columns make every product narrow (split
+    K); both against the oracle from the same start."""
+    say("dense ladder warm n=%d k=%d" % (n, k))
+    th, de = W.dense_sym_gaussian(n, 0.03, 5)
+    idx = None if k == n else np.arange(k, dtype=np.int32)
+    part = _solve(ipt, th, de, idx=idx, tol=1e-12, max_iter=2)
+    g = _solve(ipt, th, de, idx=idx, z0=part.z, tol=1e-10, precision=ipt.PREC_LADDER)
+    assert g.info["sweep_prec"][0] == "fp32"
+    ref = oracle.ipt_dense(th, de, idx=idx, z0=part.z, tol=1e-10)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-10)
+    c = _solve(ipt, th, de, idx=idx, tol=1e-10, precision=ipt.PREC_LADDER)
+    ref = oracle.ipt_dense(th, de, idx=idx, tol=1e-10)
+    check(c.z, c.lam, c.status, ref, oracle.norm1(th, de), 1e-10)
+
+
 @pytest.mark.parametrize("low", ["bf16", "none"])
 def test_ladder_parity_nonsymmetric(ipt, low):
     """The ladder on the paper's non-symmetric family (the epilogue's d of the next
