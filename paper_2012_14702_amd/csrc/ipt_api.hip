@@ -665,16 +665,20 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     // symmetric Delta (checked once here) it reads Delta_ji, coalesced, for Delta_ij.
     const bool fuse_d = !acx;
     IPT_HIP(h, launch_ctrl_init(s, ctrl, start_prec, k, fuse_d ? 1 : 0));
-    // FP16 shadows of Delta (low rung, three-product rung) need its power-of-two scale
+    // Row-major pass over Delta (copy, BF16/FP32 shadows, |M|_1, max |Delta|), then the
+    // tile-pair pass (symmetry, FP16 shadows at the power-of-two scale from that max)
     const bool mid_x3 = dopt.mid_x3 != 0;
-    if ((use_low && lt == LT_F16) || mid_x3) IPT_HIP(h, launch_absmax(s, ctrl, delta, n, n, lda));
+    const bool low16 = use_low && lt == LT_F16;
+    const bool want_max = low16 || mid_x3;
     const double *dA = direct ? delta : dpad;
     const int64_t ldA = direct ? lda : np;
     if (!direct || ladder || norm)
         IPT_HIP(h, launch_prep_delta(s, ctrl, theta, delta, lda, n, np, direct ? nullptr : dpad,
-                                     use_low ? dlo : nullptr, lt, (ladder && !mid_x3) ? d32 : nullptr,
-                                     norm ? scratch : nullptr, mid_x3 ? (_Float16 *)d32 : nullptr));
-    if (fuse_d) IPT_HIP(h, launch_check_sym(s, ctrl, delta, lda, n));
+                                     (use_low && !low16) ? (__bf16 *)dlo : nullptr, (ladder && !mid_x3) ? d32 : nullptr,
+                                     norm ? scratch : nullptr, want_max));
+    if (fuse_d || want_max)
+        IPT_HIP(h, launch_scan_delta(s, ctrl, delta, lda, n, np, fuse_d, low16 ? (_Float16 *)dlo : nullptr,
+                                     mid_x3 ? (_Float16 *)d32 : nullptr));
     IPT_HIP(h, launch_init_cols(s, ctrl, cs, idx, n, k, kp, bitmap, (int32_t)ntn, 0));
     IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
     IPT_HIP(h, launch_plan_dense(s, ctrl, cs, kp));
@@ -705,7 +709,8 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         double *zin = acx ? zb[q] : zb[(t - 1) & 1], *zout = acx ? zb[q + 1] : zb[t & 1];
         if (first_exact) {
             IPT_HIP(h, timer.mark(t, 0, s));
-            IPT_HIP(h, launch_sweep1_dense(s, ctrl, theta, dA, ldA, cs, dvec, zout, kp, part, n, np, kp));
+            IPT_HIP(h, launch_sweep1_dense(s, ctrl, theta, dA, ldA, cs, dvec, zout, kp, part, n, np, kp,
+                                           fuse_d ? dnp : nullptr));
             IPT_HIP(h, timer.mark(t, 1, s));
         } else {
             if (ladder) IPT_HIP(h, launch_cast_z(s, ctrl, zin, kp, cs, zt, np, np, kp, lt, dopt.mid_x3));
@@ -715,7 +720,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
                                          lt, ypart, nblk, fuse_d ? dnp : nullptr, dopt.mid_x3));
             IPT_HIP(h, timer.mark(t, 1, s));
         }
-        const bool fused_d = !first_exact && fuse_d;
+        const bool fused_d = fuse_d;  // every plain sweep (the product-free first one too) forms the next d
         IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, nrt, kp, t, in_par, out_par,
                                    fused_d ? dnp : nullptr));
         d_ready = fused_d;

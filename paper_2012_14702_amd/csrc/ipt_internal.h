@@ -105,25 +105,27 @@ hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *id
 // The column part of launch_init (after a separate launch_ctrl_init).
 hipError_t launch_init_cols(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                             int64_t kp, uint32_t *bitmap, int32_t ntiles_n, int32_t start_stamp);
-// sym0 = 1 when k_check_sym runs next (it clears sym on the first asymmetric pair).
+// sym0 = 1 when the symmetry scan runs next (it clears sym on the first asymmetric pair).
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0 = 0);
-// Clears ctrl->sym unless Delta (n x n, leading dimension lda) equals its transpose
-// bit for bit.
-hipError_t launch_check_sym(hipStream_t s, Ctrl *ctrl, const double *delta, int64_t lda, int64_t n);
+// Tile pairs of Delta over the padded np x np, after launch_prep_delta: want_sym
+// clears ctrl->sym unless Delta equals its transpose bit for bit; f16 (the FP16 low
+// rung) and hi (hi/lo of the three-product rung, lo = hi + np^2) receive the FP16
+// shadows scaled by ctrl->dscale.
+hipError_t launch_scan_delta(hipStream_t s, Ctrl *ctrl, const double *delta, int64_t lda, int64_t n, int64_t np,
+                             int32_t want_sym, _Float16 *f16, _Float16 *hi);
 // Dense: list the active columns in ascending order (ColState::alist, ctrl->kact).
 hipError_t launch_plan_dense(hipStream_t s, Ctrl *ctrl, ColState cs, int64_t kp);
 // Dense: the plan of the next sweep followed by the control step, in one launch.
 hipError_t launch_control_plan(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, ColState cs, int64_t kp);
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
                               int64_t k);
-// colpart holds prep_delta_chunks(np) x n doubles.
+// colpart holds prep_delta_chunks(np) x n doubles; want_max also sets ctrl->dscale.
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
-                             int64_t n, int64_t np, double *dpad, void *dlo, int32_t low_type, float *d32,
-                             double *colpart, _Float16 *dmh = nullptr);
+                             int64_t n, int64_t np, double *dpad, __bf16 *dlo, float *d32, double *colpart,
+                             int32_t want_max);
 int64_t prep_delta_chunks(int64_t np);
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
                             const int32_t *col, const double *val, int64_t n, double *scratch);
-hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld);
 // set_zscale: also the power-of-two scale of the FP16 shadow of Z - E from max |Z - E|
 // (a warm-started ladder whose first sweep is on an FP16-shadowed rung).
 hipError_t launch_load_z0(hipStream_t s, Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
@@ -131,7 +133,7 @@ hipError_t launch_load_z0(hipStream_t s, Ctrl *ctrl, const double *z0, int64_t l
 hipError_t launch_zero_pad(hipStream_t s, double *zb, int64_t ldzb, int64_t n, int64_t np, int64_t k, int64_t kp);
 hipError_t launch_sweep1_dense(hipStream_t s, const Ctrl *ctrl, const double *theta, const double *delta,
                                int64_t lda, ColState cs, double *dvec, double *zout, int64_t ldzb, double *part,
-                               int64_t n, int64_t np, int64_t kp);
+                               int64_t n, int64_t np, int64_t kp, double *dnp = nullptr);
 // d of the sweep from Delta and its input Z, through the same row-tile partials
 // (dnp: ceil(n / TILE_M) x kp) and summation order as the sweep epilogue's d.
 hipError_t launch_diag_dense(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,

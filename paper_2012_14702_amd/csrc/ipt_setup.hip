@@ -105,32 +105,28 @@ __device__ inline __bf16 to_low<__bf16>(double x) { return (__bf16)(float)x; }
 template <>
 __device__ inline _Float16 to_low<_Float16>(double x) { return (_Float16)(float)x; }
 
-// One pass over Delta for everything the solve needs from it before the sweeps:
-// a zero-padded FP64 copy (when Delta is not tile aligned), the low-precision and
-// FP32 shadows of the ladder, and per-chunk partial column sums of |M| for
-// |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Block: 256 columns x
+__device__ inline void wave_atomic_max(uint64_t *p, uint64_t v);  // one atomic max per wave (below)
+
+// Row-major pass over Delta: a zero-padded FP64 copy (when Delta is not tile
+// aligned), the BF16 and FP32 shadows of the ladder, max |Delta_jl| (for the scale
+// of the FP16 shadows, which k_scan_delta writes), and per-chunk partial column sums
+// of |M| for |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Block: 256 columns x
 // PREP_ROWS rows; thread (cx, ry) holds columns 4cx..4cx+3 (16-byte loads) and walks
 // rows ry, ry + 4, ..., four rows in flight.
 constexpr int PREP_ROWS = 128;
 
 template <typename TL>
-__global__ __launch_bounds__(256) void k_prep_delta(const Ctrl *ctrl, const double *theta, const double *delta,
+__global__ __launch_bounds__(256) void k_prep_delta(Ctrl *ctrl, const double *theta, const double *delta,
                                                     int64_t lda, int64_t n, int64_t np, double *dpad, TL *dlo,
-                                                    float *d32, double *colpart, _Float16 *dmh) {
+                                                    float *d32, double *colpart, int32_t want_max) {
     typedef TL tl4_t __attribute__((ext_vector_type(4)));
-    typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
     __shared__ double sh[4][256];
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * 256 + 4 * cx;
     const int64_t r0 = (int64_t)blockIdx.y * PREP_ROWS;
-    // the FP16 shadows (low rung, hi/lo of the three-product rung) carry the power-of-two
-    // scale of Delta; a BF16 low shadow needs none
-    const double dscale = ctrl->dscale;
-    const double lscale = std::is_same<TL, _Float16>::value ? dscale : 1.0;
-    _Float16 *dml = dmh ? dmh + np * np : nullptr;
     const bool vec = ((lda & 1) == 0) && (((uintptr_t)delta & 15) == 0) && c0 + 4 <= n;
     const bool live = c0 < np;  // np is a multiple of 128, so c0 + 4 <= np
-    double acc[4] = {0.0, 0.0, 0.0, 0.0}, th[4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0}, th[4], vmax = 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) th[e] = c0 + e < n ? theta[c0 + e] : 0.0;
     // Loads read a clamped (valid) row and column and are masked afterwards, so the
@@ -172,19 +168,10 @@ __global__ __launch_bounds__(256) void k_prep_delta(const Ctrl *ctrl, const doub
                     *(double2 *)(dpad + o + 2) = double2{v[u][2], v[u][3]};
                 }
                 if (dlo)
-                    *(tl4_t *)(dlo + o) = tl4_t{to_low<TL>(v[u][0] * lscale), to_low<TL>(v[u][1] * lscale),
-                                                to_low<TL>(v[u][2] * lscale), to_low<TL>(v[u][3] * lscale)};
-                if (dmh) {
-                    h4_t hi, lo;
+                    *(tl4_t *)(dlo + o) = tl4_t{to_low<TL>(v[u][0]), to_low<TL>(v[u][1]), to_low<TL>(v[u][2]),
+                                                to_low<TL>(v[u][3])};
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const double x = v[u][e] * dscale;
-                        hi[e] = to_low<_Float16>(x);
-                        lo[e] = to_low<_Float16>(x - (double)hi[e]);
-                    }
-                    *(h4_t *)(dmh + o) = hi;
-                    *(h4_t *)(dml + o) = lo;
-                }
+                for (int e = 0; e < 4; ++e) vmax = fmax(vmax, fabs(v[u][e]));
                 if (d32)
                     *(float4 *)(d32 + o) = float4{(float)v[u][0], (float)v[u][1], (float)v[u][2], (float)v[u][3]};
 #pragma unroll
@@ -195,6 +182,7 @@ __global__ __launch_bounds__(256) void k_prep_delta(const Ctrl *ctrl, const doub
     };
     if (vec) walk(std::true_type{});
     else walk(std::false_type{});
+    if (want_max) wave_atomic_max(&ctrl->dmax_bits, dbits(vmax));
     if (!colpart) return;
 #pragma unroll
     for (int e = 0; e < 4; ++e) sh[ry][4 * cx + e] = acc[e];
@@ -255,8 +243,6 @@ __global__ void k_zero_f64(double *p, int64_t count) {
 
 // Z <- z0 with Z[idx[c], c] = 1 (chart U_i), or Z <- E when z0 is NULL; padding zero.
 // Writes columns [0, kw) of rows [0, np) (grid-stride over the np x kw elements).
-__device__ inline void wave_atomic_max(uint64_t *p, uint64_t v);
-
 // Also records max |Z - E| in ctrl->acc_maxdist (when want_max), from which
 // k_set_zscale scales the FP16 shadow of Z - E for a first sweep on that rung.
 __global__ void k_load_z0(Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb, const int32_t *idx,
@@ -312,49 +298,75 @@ __device__ inline void store_col_partials(double (*sh)[4][64], const double v[NP
 // eq. ARS-alpha).  Block: one row tile of TILE_M rows x 64 columns.
 __global__ __launch_bounds__(256) void k_sweep1_dense(const Ctrl *ctrl, const double *theta, const double *delta,
                                                       int64_t lda, ColState cs, double *dvec, double *zout,
-                                                      int64_t ldzb, double *part, int64_t n, int64_t kp) {
+                                                      int64_t ldzb, double *part, int64_t n, int64_t kp, double *dnp) {
     if (ctrl->error || ctrl->done) return;
     __shared__ double sh[4][4][64];
+    __shared__ double sdn[2][4][64];
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     const int64_t rt = blockIdx.y;
     const int64_t c = (int64_t)blockIdx.x * 64 + cx;
     const bool colok = cs.state[c] == COL_ACTIVE;
     const int32_t i = cs.idx[c];
     const double ti = theta[i];
+    const bool sym = ctrl->sym != 0;
     double v[NPART] = {0.0, 0.0, 0.0, 0.0};
+    // Partials of the next sweep's d = sum_j Delta_ij W_jc, in the FP64 sweep
+    // epilogue's order: rows ry + 4q for q < 16 (q >= 16) are that epilogue's rows of
+    // lane group ry in wave row 0 (1), in the same order.
+    double dn[2] = {0.0, 0.0};
     for (int q = 0; q < TILE_M / 4; ++q) {
         const int64_t j = rt * TILE_M + ry + 4 * q;
         double w = 0.0;
         if (colok && j < n) {
+            const double dji = delta[j * lda + i];
             if (j == i) {
                 w = 1.0;
                 v[1] += 1.0;  // z_ii^2
             } else {
                 const double gap = theta[j] - ti;
-                w = -delta[j * lda + i] / gap;
+                w = -dji / gap;
                 const double st = w;  // z_jc = 0
                 v[0] += st * st;
                 v[2] += (gap * st) * (gap * st);
                 v[3] += w * w;
             }
+            if (dnp) {
+                const double dij = sym ? dji : delta[(int64_t)i * lda + j];
+                dn[q >> 4] = fma(dij, w, dn[q >> 4]);
+            }
         }
         zout[j * ldzb + c] = w;
     }
     if (colok && rt == (int64_t)(i / TILE_M) && ry == 0) dvec[c] = delta[(int64_t)i * lda + i];
-    store_col_partials(sh, v, cx, ry, part, rt, kp, c);
+    if (dnp) {
+        sdn[0][ry][cx] = dn[0];
+        sdn[1][ry][cx] = dn[1];
+    }
+    store_col_partials(sh, v, cx, ry, part, rt, kp, c);  // synchronizes the block first
+    if (dnp && ry == 0 && colok) {
+        const double r0 = (sdn[0][0][cx] + sdn[0][1][cx]) + (sdn[0][2][cx] + sdn[0][3][cx]);
+        const double r1 = (sdn[1][0][cx] + sdn[1][1][cx]) + (sdn[1][2][cx] + sdn[1][3][cx]);
+        dnp[rt * kp + c] = r0 + r1;
+    }
 }
 
-// Exact symmetry of Delta: block b takes the b-th pair of 64 x 64 tiles (I, J), I >= J,
-// in row-major lower-triangle order, and compares Delta[I, J] with the transpose of
-// Delta[J, I] bit for bit (the second tile goes through LDS).  Any difference clears
-// ctrl->sym; blocks that start after that return at once.
-__global__ __launch_bounds__(256) void k_check_sym(Ctrl *ctrl, const double *delta, int64_t lda, int64_t n,
-                                                   int64_t nb) {
+// Pairs of 64 x 64 tiles of Delta: block b takes the b-th pair (I, J), I >= J, in
+// row-major lower-triangle order over the padded np x np (entries outside Delta are
+// 0), compares Delta[I, J] with the transpose of Delta[J, I] bit for bit (the second
+// tile goes through LDS; any difference clears ctrl->sym), and writes both tiles'
+// FP16 shadows with the power-of-two scale ctrl->dscale: f16 = the FP16 low rung's
+// shadow, hi (lo = hi + np^2) = the split of the three-product rung.  It runs right
+// after the row-major pass over Delta, whose reads leave Delta in the last-level
+// cache for these transposed ones.
+__global__ __launch_bounds__(256) void k_scan_delta(Ctrl *ctrl, const double *delta, int64_t lda, int64_t n,
+                                                    int64_t np, int64_t nb, int32_t want_sym, _Float16 *f16,
+                                                    _Float16 *hi) {
     __shared__ double tb[64][65];
     __shared__ int32_t go;
-    if (threadIdx.x == 0) go = ctrl->sym;  // one read per block keeps the exit uniform
+    if (threadIdx.x == 0) go = want_sym && ctrl->sym;  // one read per block keeps the branch uniform
     __syncthreads();
-    if (!go) return;
+    const bool cmp = go != 0;
+    if (!cmp && !f16 && !hi) return;
     const int64_t b = blockIdx.x;
     // lower-triangle decode: bi (bi + 1) / 2 <= b < (bi + 1)(bi + 2) / 2
     int64_t bi = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
@@ -362,20 +374,73 @@ __global__ __launch_bounds__(256) void k_check_sym(Ctrl *ctrl, const double *del
     while (bi * (bi + 1) / 2 > b) --bi;
     const int64_t bj = b - bi * (bi + 1) / 2;
     if (bi >= nb) return;
-    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    // thread -> column pair 2 cp, 2 cp + 1 of rows ry + 8 q: both tiles' 16 loads issue
+    // before any of them is used.  Entries outside Delta count as 0; their loads read a
+    // valid address instead.  16-byte loads need an even n (a pair is then wholly
+    // inside or outside Delta), an even lda and an aligned Delta.
+    const int cp = threadIdx.x & 31, ry = threadIdx.x >> 5;
     const int64_t r0 = bi * 64, c0 = bj * 64;
-#pragma unroll 4
-    for (int q = 0; q < 16; ++q) {
-        const int64_t r = c0 + ry + 4 * q, c = r0 + cx;  // tile Delta[J, I]
-        tb[ry + 4 * q][cx] = (r < n && c < n) ? delta[r * lda + c] : 0.0;
+    const bool pair = ((n & 1) == 0) && ((lda & 1) == 0) && (((uintptr_t)delta & 15) == 0);
+    double2 va[8], vb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int rr = ry + 8 * q;
+        const int64_t ra = r0 + rr, ca = c0 + 2 * cp;  // Delta[I, J]
+        const int64_t rb = c0 + rr, cb = r0 + 2 * cp;  // Delta[J, I]
+        if (pair) {
+            const bool oka = ra < n && ca < n, okb = rb < n && cb < n;
+            const double2 x = *(const double2 *)(delta + (oka ? ra * lda + ca : 0));
+            const double2 y = *(const double2 *)(delta + (okb ? rb * lda + cb : 0));
+            va[q] = oka ? x : double2{0.0, 0.0};
+            vb[q] = okb ? y : double2{0.0, 0.0};
+        } else {
+            double e[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t r = u < 2 ? ra : rb, c = (u < 2 ? ca : cb) + (u & 1);
+                const bool ok = r < n && c < n;
+                const double v = delta[ok ? r * lda + c : 0];
+                e[u] = ok ? v : 0.0;
+            }
+            va[q] = double2{e[0], e[1]};
+            vb[q] = double2{e[2], e[3]};
+        }
+    }
+    if (f16 || hi) {
+        typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+        const double ds = ctrl->dscale;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int rr = ry + 8 * q;
+#pragma unroll
+            for (int t2 = 0; t2 < 2; ++t2) {
+                if (t2 == 1 && bi == bj) break;  // a diagonal tile is its own mirror
+                const double2 v = t2 ? vb[q] : va[q];
+                const int64_t o = t2 ? (c0 + rr) * np + r0 + 2 * cp : (r0 + rr) * np + c0 + 2 * cp;
+                const double x0 = v.x * ds, x1 = v.y * ds;
+                const h2_t h{to_low<_Float16>(x0), to_low<_Float16>(x1)};
+                if (f16) *(h2_t *)(f16 + o) = h;
+                if (hi) {
+                    *(h2_t *)(hi + o) = h;
+                    *(h2_t *)(hi + np * np + o) =
+                        h2_t{to_low<_Float16>(x0 - (double)h[0]), to_low<_Float16>(x1 - (double)h[1])};
+                }
+            }
+        }
+    }
+    if (!cmp) return;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        tb[ry + 8 * q][2 * cp] = vb[q].x;
+        tb[ry + 8 * q][2 * cp + 1] = vb[q].y;
     }
     __syncthreads();
     bool diff = false;
-#pragma unroll 4
-    for (int q = 0; q < 16; ++q) {
-        const int rr = ry + 4 * q;
-        const int64_t r = r0 + rr, c = c0 + cx;  // Delta[r, c] against Delta[c, r] = tb[cx][rr]
-        if (r < n && c < n) diff |= __double_as_longlong(delta[r * lda + c]) != __double_as_longlong(tb[cx][rr]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int rr = ry + 8 * q;  // Delta[r0 + rr, c0 + 2cp + e] against Delta[c0 + 2cp + e, r0 + rr]
+        diff |= __double_as_longlong(va[q].x) != __double_as_longlong(tb[2 * cp][rr]);
+        diff |= __double_as_longlong(va[q].y) != __double_as_longlong(tb[2 * cp + 1][rr]);
     }
     if (__syncthreads_or(diff) && threadIdx.x == 0) ctrl->sym = 0;
 }
@@ -681,34 +746,8 @@ __device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep) {
     ctrl->acc_maxdist = 0;
 }
 
-// max |x_jl| over a rows x cols matrix (leading dimension ld) -> ctrl->dmax_bits;
-// then the FP16 scale of the Delta shadow.
-// Block: 256 columns x 128 rows; thread (cx, ry) reads columns 4cx..4cx+3 of rows
-// ry, ry + 4, ... (16-byte loads when the rows allow), one atomic per wave.
-__global__ __launch_bounds__(256) void k_absmax(Ctrl *ctrl, const double *x, int64_t rows, int64_t cols,
-                                                int64_t ld) {
-    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
-    const int64_t c0 = (int64_t)blockIdx.x * 256 + 4 * cx, r0 = (int64_t)blockIdx.y * 128;
-    const bool vec = ((ld & 1) == 0) && (((uintptr_t)x & 15) == 0) && c0 + 4 <= cols;
-    double m = 0.0;
-    if (c0 < cols) {
-#pragma unroll 4
-        for (int q = 0; q < 32; ++q) {
-            const int64_t r = r0 + ry + 4 * q;
-            if (r >= rows) break;
-            const double *p = x + r * ld + c0;
-            if (vec) {
-                const double2 a = *(const double2 *)p, b = *(const double2 *)(p + 2);
-                m = fmax(m, fmax(fmax(fabs(a.x), fabs(a.y)), fmax(fabs(b.x), fabs(b.y))));
-            } else {
-                for (int e = 0; e < 4; ++e)
-                    if (c0 + e < cols) m = fmax(m, fabs(p[e]));
-            }
-        }
-    }
-    wave_atomic_max(&ctrl->dmax_bits, dbits(m));
-}
-
+// The FP16 scale of the Delta shadows from max |Delta_jl| (ctrl->dmax_bits): a power
+// of two that brings the largest entry near 2^13.
 __global__ void k_set_dscale(Ctrl *ctrl) {
     const double md = bitsd(ctrl->dmax_bits);
     ctrl->dscale = (md > 0.0 && isfinite(md)) ? exp2(floor(log2(8192.0 / md))) : 1.0;
@@ -820,9 +859,10 @@ hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64
     return hipGetLastError();
 }
 
-hipError_t launch_check_sym(hipStream_t s, Ctrl *ctrl, const double *delta, int64_t lda, int64_t n) {
-    const int64_t nb = (n + 63) / 64;
-    k_check_sym<<<(unsigned)(nb * (nb + 1) / 2), 256, 0, s>>>(ctrl, delta, lda, n, nb);
+hipError_t launch_scan_delta(hipStream_t s, Ctrl *ctrl, const double *delta, int64_t lda, int64_t n, int64_t np,
+                             int32_t want_sym, _Float16 *f16, _Float16 *hi) {
+    const int64_t nb = np / 64;
+    k_scan_delta<<<(unsigned)(nb * (nb + 1) / 2), 256, 0, s>>>(ctrl, delta, lda, n, np, nb, want_sym, f16, hi);
     return hipGetLastError();
 }
 
@@ -836,16 +876,13 @@ hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, co
 int64_t prep_delta_chunks(int64_t np) { return (np + PREP_ROWS - 1) / PREP_ROWS; }
 
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
-                             int64_t n, int64_t np, double *dpad, void *dlo, int32_t low_type, float *d32,
-                             double *colpart, _Float16 *dmh) {
+                             int64_t n, int64_t np, double *dpad, __bf16 *dlo, float *d32, double *colpart,
+                             int32_t want_max) {
     const int64_t chunks = prep_delta_chunks(np);
     dim3 g((unsigned)((np + 255) / 256), (unsigned)chunks);
-    if (low_type == LT_F16)
-        k_prep_delta<_Float16>
-            <<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, (_Float16 *)dlo, d32, colpart, dmh);
-    else
-        k_prep_delta<__bf16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, (__bf16 *)dlo, d32, colpart, dmh);
+    k_prep_delta<__bf16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, dlo, d32, colpart, want_max);
     if (colpart) k_norm1_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, colpart, n, chunks);
+    if (want_max) k_set_dscale<<<1, 1, 0, s>>>(ctrl);
     return hipGetLastError();
 }
 
@@ -880,9 +917,9 @@ hipError_t launch_zero_pad(hipStream_t s, double *zb, int64_t ldzb, int64_t n, i
 
 hipError_t launch_sweep1_dense(hipStream_t s, const Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
                                ColState cs, double *dvec, double *zout, int64_t ldzb, double *part, int64_t n,
-                               int64_t np, int64_t kp) {
+                               int64_t np, int64_t kp, double *dnp) {
     dim3 g((unsigned)(kp / 64), (unsigned)(np / TILE_M));
-    k_sweep1_dense<<<g, 256, 0, s>>>(ctrl, theta, delta, lda, cs, dvec, zout, ldzb, part, n, kp);
+    k_sweep1_dense<<<g, 256, 0, s>>>(ctrl, theta, delta, lda, cs, dvec, zout, ldzb, part, n, kp, dnp);
     return hipGetLastError();
 }
 
@@ -923,12 +960,6 @@ hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const do
     return hipGetLastError();
 }
 
-hipError_t launch_absmax(hipStream_t s, Ctrl *ctrl, const double *x, int64_t rows, int64_t cols, int64_t ld) {
-    dim3 g((unsigned)((cols + 255) / 256), (unsigned)((rows + 127) / 128));
-    k_absmax<<<g, 256, 0, s>>>(ctrl, x, rows, cols, ld);
-    k_set_dscale<<<1, 1, 0, s>>>(ctrl);
-    return hipGetLastError();
-}
 
 hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
                          int64_t ldt, int64_t np, int64_t kp, int32_t low_type, int32_t mid_x3) {

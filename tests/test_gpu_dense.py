@@ -93,13 +93,14 @@ def test_two_by_two_statuses(ipt, eps, want):
         check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12)
 
 
+@pytest.mark.parametrize("stop", [1, 2])
 @pytest.mark.parametrize("kind", ["sym", "nonsym"])
-def test_warm_start_resume_and_determinism(ipt, kind):
-    """Stopping after 2 sweeps and resuming from the returned iterate equals the
+def test_warm_start_resume_and_determinism(ipt, kind, stop):
+    """Stopping after 1 or 2 sweeps and resuming from the returned iterate equals the
     uninterrupted solve bit for bit (the resumed first sweep computes d from Delta and
-    Z in the order the uninterrupted solve's epilogue used); two identical solves are
-    bitwise equal."""
-    say("dense resume n=384 %s" % kind)
+    Z in the order in which the uninterrupted solve's previous sweep formed it); two
+    identical solves are bitwise equal."""
+    say("dense resume n=384 %s stop=%d" % (kind, stop))
     if kind == "sym":
         th, de = W.dense_sym_gaussian(384, 0.03, 2)
     else:
@@ -108,12 +109,12 @@ def test_warm_start_resume_and_determinism(ipt, kind):
     again = _solve(ipt, th, de, tol=1e-12)
     np.testing.assert_array_equal(full.z, again.z)
     np.testing.assert_array_equal(full.lam, again.lam)
-    part = _solve(ipt, th, de, tol=1e-12, max_iter=2)
+    part = _solve(ipt, th, de, tol=1e-12, max_iter=stop)
     assert np.all(part.status == 1)
     res = _solve(ipt, th, de, z0=part.z, tol=1e-12)
     np.testing.assert_array_equal(res.z, full.z)
     np.testing.assert_array_equal(res.lam, full.lam)
-    np.testing.assert_array_equal(res.sweeps + 2, full.sweeps)
+    np.testing.assert_array_equal(res.sweeps + stop, full.sweeps)
     ref = oracle.ipt_dense(th, de, z0=part.z, tol=1e-12)
     check(res.z, res.lam, res.status, ref, oracle.norm1(th, de), 1e-12)
 
