@@ -296,7 +296,7 @@ def main():
     ap.add_argument("--eps", type=float, default=0.01)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "ladder", "fp64"], default="all",
+    ap.add_argument("--only", choices=["all", "ladder", "ladder_fp32_mma", "fp64"], default="all",
                     help="restrict the dense workload to one mode (for profiler runs)")
     ap.add_argument("--extra", default="sparse,morgan,batched,learned",
                     help="comma list of secondary workloads to time: sparse, batched, learned ('' for none)")
@@ -348,7 +348,10 @@ def main():
         return th, de, torch.from_numpy(th).to(dev), torch.from_numpy(de).to(dev)
 
     zbuf = torch.empty((n, n), dtype=torch.float64, device=dev)
+    # "ladder": BF16 -> FP32-class rung as three FP16 products (the default) -> FP64;
+    # "ladder_fp32_mma": the same ladder with the FP32 rung on FP32 matrix cores
     modes = {"ladder": dict(precision=ipt.PREC_LADDER, low_type=ipt.LOW_BF16),
+             "ladder_fp32_mma": dict(precision=ipt.PREC_LADDER, low_type=ipt.LOW_BF16, flags=ipt.FLAG_MID_FP32),
              "fp64": dict(precision=ipt.PREC_FP64)}
     if args.only != "all":
         modes = {args.only: modes[args.only]}
@@ -358,7 +361,8 @@ def main():
         th, de, thd, ded = prep(eps)
         host[eps] = (th, de)
         for name, kw in modes.items():
-            o = ipt.default_opts(tol=1e-10, flags=ipt.FLAG_TIME_KERNELS, **kw)
+            kw2 = dict(kw)
+            o = ipt.default_opts(tol=1e-10, flags=ipt.FLAG_TIME_KERNELS | kw2.pop("flags", 0), **kw2)
             log("eps=%g mode=%s warmup %d" % (eps, name, args.warmup))
             solve_many(ipt, handle, thd, ded, zbuf, o, args.warmup)
             steps = args.steps if eps == args.eps else max(3, args.steps // 4)
@@ -374,7 +378,7 @@ def main():
                 eps, name, sec * 1e3, conv, infos[-1]["sweep_prec"]))
         del thd, ded
 
-    head_mode = "ladder" if "ladder" in modes else "fp64"
+    head_mode = "ladder" if "ladder" in modes else ("ladder_fp32_mma" if "ladder_fp32_mma" in modes else "fp64")
     head = results[(args.eps, head_mode)]
     # Roofline of the dominant kernel, the sweep GEMM in its FP64 body.  One kernel
     # (k_sweep_gemm) serves every precision, so it is measured in the plain FP64 run,
@@ -418,8 +422,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16 -> fp32-class (3 x fp16 split products) -> f64 ladder (f64 certifies)"
-                 if head_mode == "ladder" else "f64",
+        "dtype": {"ladder": "bf16 -> fp32-class (3 x fp16 split products) -> f64 ladder (f64 certifies)",
+                  "ladder_fp32_mma": "bf16 -> f32 -> f64 ladder (f64 certifies)"}.get(head_mode, "f64"),
         "data": "synthetic",
         "config": {"workload": "dense full spectrum n=%d, D=diag(1..n), Delta=eps*(R+R^T)/2, R iid N(0,1/n) "
                                "seed 0, eps=%g, k=n, tol 1e-10 (per-column relative step)" % (n, args.eps),
@@ -435,6 +439,9 @@ def main():
     }
     if ("fp64" in modes) and ("ladder" in modes):
         out["ladder_speedup_vs_fp64"] = round(results[(args.eps, "fp64")]["sec"] / results[(args.eps, "ladder")]["sec"], 3)
+    if ("fp64" in modes) and ("ladder_fp32_mma" in modes):
+        out["ladder_fp32_mma_speedup_vs_fp64"] = round(
+            results[(args.eps, "fp64")]["sec"] / results[(args.eps, "ladder_fp32_mma")]["sec"], 3)
     extras = [e for e in args.extra.split(",") if e]
     if "sparse" in extras:
         out["sparse"] = bench_sparse(ipt, handle, args)

@@ -119,7 +119,7 @@ __device__ inline int live_col_blocks(int32_t lim, int wn) {
 constexpr int SMEM_F64 = 2 * BM * (16 + 1) * 8 + 2 * 16 * BN * 8;
 constexpr int SMEM_LOW16 = 2 * 2 * BM * (64 + 8) * 2;
 constexpr int SMEM_LOW32 = 2 * 2 * BM * (32 + 1) * 4;
-constexpr int X3_BK = 32, X3_LDP = X3_BK + 8;
+constexpr int X3_BK = 32, X3_LDP = X3_BK;  // unpadded rows; 16-byte chunks XOR-swizzled by row
 constexpr int SMEM_X3 = 2 * 4 * BM * X3_LDP * 2;  // two stages of A hi/lo and B hi/lo
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int SMEM_MAIN = cmax(cmax(SMEM_F64, SMEM_X3), cmax(SMEM_LOW16, SMEM_LOW32));
@@ -500,7 +500,9 @@ __device__ __forceinline__ void gemm_low_body(char *smem, double (*red)[BN][NRED
 // A B ~ Ah Bh + Ah Bl + Al Bh accumulated in FP32 (the dropped Al Bl is 2^-22
 // relative).  v_mfma_f32_16x16x32_f16 runs 16 times the FP32 matrix rate, so the three
 // products cost less than a fifth of one FP32 product.  BK = 32; each 16-byte chunk
-// holds 8 elements, 4 chunks per tile row, 256 threads cover 64 rows per pass.
+// holds 8 elements, 4 chunks per 64-byte tile row, 256 threads cover 64 rows per pass.
+// Chunk c of row r sits at position c ^ ((r >> 2) & 3), so the eight rows that one
+// 16-byte fragment read serves per cycle fall on distinct banks without padding.
 template <bool SPLIT>
 __device__ __forceinline__ void gemm_x3_body(char *smem, double (*red)[BN][NRED], const PackedCols scol,
                                              const GemmArgs &g, double unscale, int tm, int64_t k0, int64_t k1,
@@ -537,11 +539,13 @@ __device__ __forceinline__ void gemm_x3_body(char *smem, double (*red)[BN][NRED]
             st[3][q] = boff[q] >= 0 ? *(const uint4 *)(g.ztl + boff[q] + k) : uint4{0u, 0u, 0u, 0u};
         }
     };
+    auto swz = [](int r, int chunk) { return 8 * (chunk ^ ((r >> 2) & 3)); };
     auto put = [&](int stage) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) *(uint4 *)&S[4 * stage + m][l_r + 64 * q][l_c] = st[m][q];
+            for (int q = 0; q < 2; ++q)
+                *(uint4 *)&S[4 * stage + m][l_r + 64 * q][swz(l_r + 64 * q, l_c >> 3)] = st[m][q];
     };
     const int nk = (int)((k1 - k0) / X3_BK);
     load(k0);
@@ -550,18 +554,20 @@ __device__ __forceinline__ void gemm_x3_body(char *smem, double (*red)[BN][NRED]
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         load(k0 + (int64_t)(kt + 1 < nk ? kt + 1 : kt) * X3_BK);
-        const int koff = 8 * (lane >> 4);
+        const int kc = lane >> 4;  // this lane's 16-byte chunk of the K slice
         h8_t ah[4], al[4];
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib) {
-            ah[ib] = *(const h8_t *)&S[4 * cur + 0][wm * 64 + 16 * ib + (lane & 15)][koff];
-            al[ib] = *(const h8_t *)&S[4 * cur + 1][wm * 64 + 16 * ib + (lane & 15)][koff];
+            const int r = wm * 64 + 16 * ib + (lane & 15);
+            ah[ib] = *(const h8_t *)&S[4 * cur + 0][r][swz(r, kc)];
+            al[ib] = *(const h8_t *)&S[4 * cur + 1][r][swz(r, kc)];
         }
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) {
             if (SPLIT && jb >= nj) continue;
-            const h8_t bh = *(const h8_t *)&S[4 * cur + 2][wn * 64 + 16 * jb + (lane & 15)][koff];
-            const h8_t bl = *(const h8_t *)&S[4 * cur + 3][wn * 64 + 16 * jb + (lane & 15)][koff];
+            const int r = wn * 64 + 16 * jb + (lane & 15);
+            const h8_t bh = *(const h8_t *)&S[4 * cur + 2][r][swz(r, kc)];
+            const h8_t bl = *(const h8_t *)&S[4 * cur + 3][r][swz(r, kc)];
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib) {
                 acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[ib], bh, acc[ib][jb], 0, 0, 0);
