@@ -17,6 +17,10 @@ Contents
 * ``acx_dense``: IPT with Alternating Cyclic Extrapolation (Alg. ACX) per column,
   in NumPy.
 * ``norm1`` / ``eigen_residual``: the plain definitions used by the parity bounds.
+* ``pair_partners`` / ``pair_rotation`` / ``pair_back_rotate``: the choice of D per
+  near-degenerate pair (the concluding section's suggestion of choosing D to widen
+  the convergence domain), as 2x2 Jacobi rotations of M, in NumPy; ``ipt_batched``
+  applies them with ``pair_tau``.
 
 Every function cites the passage it follows; the readings taken where the paper
 is silent are stated in ``ipt_oracle.c``.
@@ -185,18 +189,24 @@ def ipt_map(theta, delta, i, z):
 
 
 def ipt_batched(ns, theta_pool, delta_pool, theta_off, delta_off, tol=1e-10, max_iter=64,
-                div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, accel="picard"):
+                div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, accel="picard", pair_tau=None):
     """Independent dense full-spectrum IPT solves over a packed batch.  z of problem
-    b is returned row-major at z_pool[delta_off[b]:][:n_b*n_b]."""
-    if accel != "picard":
+    b is returned row-major at z_pool[delta_off[b]:][:n_b*n_b].  With pair_tau, each
+    problem is first rotated by ``pair_rotation`` and its eigenvectors rotated back
+    (``pair_back_rotate``)."""
+    if accel != "picard" or pair_tau is not None:
         ns = np.asarray(ns)
         z = np.empty(np.asarray(delta_pool).shape[0]); lam = np.empty(np.asarray(theta_pool).shape[0])
         st = np.empty(lam.shape[0], np.int32); sw = np.empty(lam.shape[0], np.int32)
         for b in range(ns.shape[0]):
             n, to, do = int(ns[b]), int(theta_off[b]), int(delta_off[b])
-            r = ipt_dense(theta_pool[to:to + n], np.asarray(delta_pool[do:do + n * n]).reshape(n, n), tol=tol,
-                          max_iter=max_iter, div_norm=div_norm, div_growth=div_growth, resid=False, accel=accel)
-            z[do:do + n * n] = r.z.ravel(); lam[to:to + n] = r.lam; st[to:to + n] = r.status; sw[to:to + n] = r.sweeps
+            th = np.asarray(theta_pool[to:to + n]); de = np.asarray(delta_pool[do:do + n * n]).reshape(n, n)
+            if pair_tau is not None:
+                th, de, partner, cs = pair_rotation(th, de, pair_tau)
+            r = ipt_dense(th, de, tol=tol, max_iter=max_iter, div_norm=div_norm, div_growth=div_growth, resid=False,
+                          accel=accel)
+            zb = r.z if pair_tau is None else pair_back_rotate(r.z, partner, cs)
+            z[do:do + n * n] = zb.ravel(); lam[to:to + n] = r.lam; st[to:to + n] = r.status; sw[to:to + n] = r.sweeps
         return Result(z=z, lam=lam, status=st, sweeps=sw, step=None, resid=None)
     ns = np.ascontiguousarray(ns, dtype=np.int32)
     theta_off = np.ascontiguousarray(theta_off, dtype=np.int64)
@@ -212,6 +222,93 @@ def ipt_batched(ns, theta_pool, delta_pool, theta_off, delta_off, tol=1e-10, max
 
 
 # ------------------------------------------------------------------ NumPy parts
+
+def pair_partners(theta, delta, tau):
+    """Near-degenerate pairs (reading: the concluding section's freedom in choosing D,
+    applied to pairs).  The coupling of i and k relative to their gap is
+    r_ik = |Delta_ik| / |theta_i - theta_k| (k != i).  i and j = argmax_k r_ik (the
+    first index on ties) form a pair when i is also the argmax for j, r_ij > tau, and
+    Delta_ij == Delta_ji exactly (the 2x2 block is then symmetric).  Returns partner[i]
+    (-1 when unpaired) and the row maxima of r."""
+    theta = np.asarray(theta, dtype=np.float64)
+    delta = np.asarray(delta, dtype=np.float64)
+    n = theta.shape[0]
+    partner = np.full(n, -1, dtype=np.int64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.abs(delta) / np.abs(theta[:, None] - theta[None, :])
+    np.fill_diagonal(r, -1.0)
+    best = np.argmax(r, axis=1)  # the first index among equal maxima
+    rmax = r[np.arange(n), best]
+    for i in range(n):
+        j = best[i]
+        if n > 1 and best[j] == i and rmax[i] > tau and delta[i, j] == delta[j, i]:
+            partner[i] = j
+    return partner, rmax
+
+
+def jacobi_cs(a, b, d):
+    """The rotation J = [[c, s], [-s, c]] with J^T [[a, b], [b, d]] J diagonal (the
+    symmetric Schur decomposition of a 2x2 block: t = tan of the angle, |angle| <=
+    pi/4)."""
+    if b == 0.0:
+        return 1.0, 0.0
+    zeta = (d - a) / (2.0 * b)
+    t = (1.0 if zeta >= 0.0 else -1.0) / (abs(zeta) + np.sqrt(1.0 + zeta * zeta))
+    c = 1.0 / np.sqrt(1.0 + t * t)
+    return c, t * c
+
+
+def pair_rotation(theta, delta, tau):
+    """M = diag(theta) + Delta -> M' = R^T M R with R the product of the pairs' 2x2
+    rotations (R_ii = R_jj = c, R_ij = s, R_ji = -s for the pair i < j).  The new
+    partition keeps every unpaired theta_k and Delta_kk; a pair's theta'_i, theta'_j
+    are the diagonal of its rotated 2x2 block, whose entries leave Delta' (the
+    pair's coupling is gone).  M' has the eigenvalues of M, and an eigenvector z' of
+    M' is R^T z for the eigenvector z of M.  Returns (theta', Delta', partner, cs)
+    with cs[i] = (c, s) for both members of a pair."""
+    theta = np.asarray(theta, dtype=np.float64)
+    delta = np.asarray(delta, dtype=np.float64)
+    n = theta.shape[0]
+    partner, _ = pair_partners(theta, delta, tau)
+    M = np.diag(theta) + delta
+    R = np.eye(n)
+    cs = np.zeros((n, 2))
+    cs[:, 0] = 1.0
+    for i in range(n):
+        j = partner[i]
+        if j > i:
+            c, s = jacobi_cs(M[i, i], M[i, j], M[j, j])
+            R[i, i] = R[j, j] = c
+            R[i, j], R[j, i] = s, -s
+            cs[i] = cs[j] = (c, s)
+    Mr = R.T @ M @ R
+    th2 = theta.copy()
+    de2 = delta.copy()
+    paired = partner >= 0
+    for i in range(n):
+        for k in range(n):
+            if paired[i] or paired[k]:
+                de2[i, k] = Mr[i, k]
+    for i in np.where(paired)[0]:
+        j = partner[i]
+        th2[i] = Mr[i, i]
+        de2[i, i] = 0.0
+        de2[i, j] = 0.0
+    return th2, de2, partner, cs
+
+
+def pair_back_rotate(z, partner, cs):
+    """Eigenvectors of M from those of M': z = R z' (rows i and j of a pair mix)."""
+    z = np.array(z, dtype=np.float64, copy=True)
+    out = z.copy()
+    for i in range(z.shape[0]):
+        j = partner[i]
+        if j > i:
+            c, s = cs[i]
+            out[i] = c * z[i] + s * z[j]
+            out[j] = -s * z[i] + c * z[j]
+    return out
+
 
 def inverse_gaps(theta):
     """G_jk = 1/(theta_j - theta_k) for j != k, G_jj = 0 (Sec. 3, inverse gaps matrix)."""
