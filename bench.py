@@ -171,7 +171,9 @@ def bench_batched(ipt, handle, args):
     st_out = torch.empty(thd.shape[0], dtype=torch.int32, device=dev)
     res = {}
     modes = (("ladder", ipt.PREC_LADDER, 0), ("ladder_no_graph", ipt.PREC_LADDER, ipt.FLAG_NO_GRAPH),
-             ("fp64", ipt.PREC_FP64, 0), ("acx", ipt.PREC_FP64, ipt.FLAG_ACX))
+             ("fp64", ipt.PREC_FP64, 0), ("acx", ipt.PREC_FP64, ipt.FLAG_ACX),
+             ("ladder_pairs", ipt.PREC_LADDER, ipt.FLAG_PAIR_ROTATE), ("acx_pairs", ipt.PREC_FP64,
+                                                                       ipt.FLAG_ACX | ipt.FLAG_PAIR_ROTATE))
     for name, prec, flags in modes:
         if args.batched_modes and name not in args.batched_modes.split(","):
             continue

@@ -18,6 +18,8 @@ struct ipt_context {
     hipStream_t stream = nullptr;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    void *pws = nullptr;  // near-degenerate pair rotation: rotated copies of the inputs
+    size_t pws_bytes = 0;
     Ctrl *host_ctrl = nullptr;  // pinned copy of the control block
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     std::vector<hipEvent_t> tev;  // kernel-timing events (IPT_FLAG_TIME_KERNELS), reused across solves
@@ -71,26 +73,28 @@ struct Carve {
     }
 };
 
-ipt_status ensure_ws(ipt_handle h, size_t bytes) {
-    if (bytes <= h->ws_bytes) return IPT_OK;
+ipt_status ensure_buf(ipt_handle h, void *&buf, size_t &have, size_t bytes) {
+    if (bytes <= have) return IPT_OK;
     IPT_HIP(h, hipStreamSynchronize(h->stream));
-    if (h->ws) IPT_HIP(h, hipFree(h->ws));
-    h->ws = nullptr;
-    h->ws_bytes = 0;
+    if (buf) IPT_HIP(h, hipFree(buf));
+    buf = nullptr;
+    have = 0;
     size_t want = bytes + bytes / 8;  // head-room for slightly larger follow-up solves
-    hipError_t e = hipMalloc(&h->ws, want);
+    hipError_t e = hipMalloc(&buf, want);
     if (e != hipSuccess) {
         want = bytes;
-        e = hipMalloc(&h->ws, want);
+        e = hipMalloc(&buf, want);
     }
     if (e != hipSuccess) {
-        h->ws = nullptr;
+        buf = nullptr;
         (void)hipGetLastError();
         return fail(h, IPT_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
     }
-    h->ws_bytes = want;
+    have = want;
     return IPT_OK;
 }
+
+ipt_status ensure_ws(ipt_handle h, size_t bytes) { return ensure_buf(h, h->ws, h->ws_bytes, bytes); }
 
 ipt_status check_opts(ipt_handle h, const ipt_opts *in, ipt_opts &o) {
     ipt_opts_default(&o);
@@ -541,6 +545,7 @@ ipt_status ipt_destroy(ipt_handle h) {
     DeviceGuard g(h->device);
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
+    if (h->pws) (void)hipFree(h->pws);
     if (h->host_ctrl) (void)hipHostFree(h->host_ctrl);
     (void)hipEventDestroy(h->ev_start);
     (void)hipEventDestroy(h->ev_stop);
@@ -859,6 +864,72 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     return finish(h, ctrl, k, info, &timer);
 }
 
+namespace {
+
+// IPT_FLAG_PAIR_ROTATE on a batch: copies of the pools (at the caller's offsets) get
+// each problem's near-degenerate pairs rotated out, the batch is solved on them, and
+// the eigenvectors are rotated back in z_pool.
+ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
+                         const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
+                         const double *delta_pool, const ipt_opts &o, double *z_pool, double *lambda_pool,
+                         int32_t *status_pool, ipt_info *info) {
+    if (count < 1 || !ns || !theta_off || !delta_off || !z_off || !theta_pool || !delta_pool || !z_pool)
+        return fail(h, IPT_EINVAL, "bad batch description");
+    int64_t tlo = INT64_MAX, thi = 0, dlo = INT64_MAX, dhi = 0;
+    int32_t max_n = 0;
+    for (int32_t b = 0; b < count; ++b) {
+        const int64_t n = ns[b];
+        if (n < 1 || n > 4096) return fail(h, IPT_EINVAL, "every problem size must be in [1, 4096]");
+        if (theta_off[b] < 0 || delta_off[b] < 0 || z_off[b] < 0) return fail(h, IPT_EINVAL, "negative pool offset");
+        tlo = std::min(tlo, theta_off[b]);
+        thi = std::max(thi, theta_off[b] + n);
+        dlo = std::min(dlo, delta_off[b]);
+        dhi = std::max(dhi, delta_off[b] + n * n);
+        max_n = std::max(max_n, (int32_t)n);
+    }
+    // scratch: theta' [thi], Delta' [dhi], best [thi], partner [thi], rmax [thi], cs [2 thi],
+    // then the per-problem n, ld = n, offsets
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t o_dp = up(thi * 8), o_best = o_dp + up(dhi * 8), o_part = o_best + up(thi * 4),
+                 o_rmax = o_part + up(thi * 4), o_cs = o_rmax + up(thi * 8), o_meta = o_cs + up(thi * 16);
+    const size_t meta_bytes = (size_t)count * (4 + 4 + 8 * 4);
+    if (ipt_status st = ensure_buf(h, h->pws, h->pws_bytes, o_meta + meta_bytes)) return st;
+    char *base = (char *)h->pws;
+    double *tp = (double *)base, *dp = (double *)(base + o_dp), *rmax = (double *)(base + o_rmax);
+    double *cs = (double *)(base + o_cs);
+    int32_t *best = (int32_t *)(base + o_best), *partner = (int32_t *)(base + o_part);
+    std::vector<unsigned char> meta(meta_bytes);
+    int32_t *hn = (int32_t *)meta.data(), *hk = hn + count;
+    int64_t *hto = (int64_t *)(hk + count), *hdo = hto + count, *hzo = hdo + count, *hld = hzo + count;
+    for (int32_t b = 0; b < count; ++b) {
+        hn[b] = hk[b] = ns[b];
+        hto[b] = theta_off[b];
+        hdo[b] = delta_off[b];
+        hzo[b] = z_off[b];
+        hld[b] = ns[b];
+    }
+    char *dm = base + o_meta;
+    int32_t *dn = (int32_t *)dm, *dk = dn + count;
+    int64_t *dto = (int64_t *)(dk + count), *ddo = dto + count, *dzo = ddo + count, *dld = dzo + count;
+    hipStream_t s = h->stream;
+    IPT_HIP(h, hipMemcpyAsync(dm, meta.data(), meta_bytes, hipMemcpyHostToDevice, s));
+    IPT_HIP(h, hipMemcpyAsync(tp + tlo, theta_pool + tlo, (size_t)(thi - tlo) * 8, hipMemcpyDeviceToDevice, s));
+    IPT_HIP(h, hipMemcpyAsync(dp + dlo, delta_pool + dlo, (size_t)(dhi - dlo) * 8, hipMemcpyDeviceToDevice, s));
+    IPT_HIP(h, hipStreamSynchronize(s));  // the host copy of the metadata is released below
+    IPT_HIP(h, launch_pair_rotate(s, count, max_n, dn, dto, ddo, theta_pool, delta_pool, tp, dp, best, rmax, partner,
+                                  cs, IPT_PAIR_TAU));
+    ipt_opts o2 = o;
+    o2.flags &= ~IPT_FLAG_PAIR_ROTATE;
+    const ipt_status st = batched_run(h, count, ns, theta_off, delta_off, z_off, tp, dp, o2, z_pool, lambda_pool,
+                                      status_pool, info, 0);
+    if (st != IPT_OK && st != IPT_ENOTCONV) return st;
+    IPT_HIP(h, launch_pair_rows(s, count, dn, dto, dzo, dld, dk, z_pool, partner, cs, 0));
+    IPT_HIP(h, hipStreamSynchronize(s));
+    return st;
+}
+
+}  // namespace
+
 ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
                              const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
                              const double *delta_pool, const ipt_opts *opts, double *z_pool, double *lambda_pool,
@@ -867,6 +938,11 @@ ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, con
     h->last_error.clear();
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
+    if (o.flags & IPT_FLAG_PAIR_ROTATE) {
+        DeviceGuard guard(h->device);
+        return batched_pairs(h, count, ns, theta_off, delta_off, z_off, theta_pool, delta_pool, o, z_pool,
+                             lambda_pool, status_pool, info);
+    }
     return batched_run(h, count, ns, theta_off, delta_off, z_off, theta_pool, delta_pool, o, z_pool, lambda_pool,
                        status_pool, info, 0);
 }

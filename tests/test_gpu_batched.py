@@ -261,3 +261,65 @@ def test_batched_nonsymmetric(ipt, flags):
         rr = oracle.ipt_dense(thb, deb, tol=1e-11, accel="acx" if flags else "picard")
         check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-11, max_iter=100)
     assert np.all(st == 0)
+
+
+def _planted_pairs(n, pairs, seed, strength=1.5):
+    """theta = 1..n, a small symmetric background, and pairs (i, j) moved to a gap of
+    0.02 with coupling strength * gap (beyond the 2x2 convergence bound for 1.5)."""
+    rng = np.random.default_rng(seed)
+    th = np.arange(1.0, n + 1.0)
+    r = rng.standard_normal((n, n)) * 0.01 / np.sqrt(n)
+    de = (r + r.T) / 2.0
+    for i, j in pairs:
+        th[j] = th[i] + 0.02
+        de[i, j] = de[j, i] = strength * 0.02
+    return th, de
+
+
+@pytest.mark.parametrize("prec", ["fp64", "ladder"])
+def test_batched_pair_rotation_parity(ipt, prec):
+    """IPT_FLAG_PAIR_ROTATE: 20 problems of the batched workload plus three with pairs
+    planted beyond the 2x2 bound (one at a 64-row tile edge, one at the end of a ragged
+    size), every problem against the oracle's rotated solve column by column (the same
+    pairing, rotation and chart); the planted problems converge on every column, which
+    the plain solve does not."""
+    say("batched pair rotation %s" % prec)
+    ns0, th0, de0, _, _ = W.batched_sym_gaussian(20, 32, 384, 0.02, seed=5)
+    parts_th, parts_de = [], []
+    o0 = np.concatenate([[0], np.cumsum(ns0)[:-1]])
+    p0 = np.concatenate([[0], np.cumsum(ns0.astype(np.int64) ** 2)[:-1]])
+    for b in range(20):
+        n = int(ns0[b])
+        parts_th.append(th0[o0[b]:o0[b] + n])
+        parts_de.append(de0[p0[b]:p0[b] + n * n])
+    planted = [(96, [(10, 11), (63, 64)]), (131, [(5, 6), (129, 130)]), (40, [(0, 1), (20, 21), (38, 39)])]
+    for q, (n, pairs) in enumerate(planted):
+        thb, deb = _planted_pairs(n, pairs, 50 + q)
+        parts_th.append(thb)
+        parts_de.append(deb.ravel())
+    ns = np.array([len(x) for x in parts_th], dtype=np.int32)
+    th = np.concatenate(parts_th)
+    de = np.concatenate(parts_de)
+    th_off = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    de_off = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
+    p = ipt.PREC_LADDER if prec == "ladder" else ipt.PREC_FP64
+    z, lam, st, info = _run(ipt, ns, th, de, tol=1e-10, precision=p, max_iter=64, flags=ipt.FLAG_PAIR_ROTATE)
+    _, _, st_plain, _ = _run(ipt, ns, th, de, tol=1e-10, precision=p, max_iter=64)
+    compared = 0
+    for b in range(len(ns)):
+        n = int(ns[b])
+        gz, gl, gs = _per_problem(ns, th_off, de_off, z, lam, st, b)
+        thb, deb = th[th_off[b]:th_off[b] + n], de[de_off[b]:de_off[b] + n * n].reshape(n, n)
+        th2, de2, partner, cs = oracle.pair_rotation(thb, deb, ipt.PAIR_TAU)
+        rr = oracle.ipt_dense(th2, de2, tol=1e-10, max_iter=64)
+        rr["z"] = oracle.pair_back_rotate(rr.z, partner, cs)
+        out = check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-10, max_iter=64)
+        compared += out["compared"]
+    assert compared >= 0.95 * int(ns.sum())
+    for q in range(3):
+        b = 20 + q
+        s_rot = st[th_off[b]:th_off[b] + ns[b]]
+        s_pl = st_plain[th_off[b]:th_off[b] + ns[b]]
+        assert np.all(s_rot == 0)
+        assert np.any(s_pl != 0)
+    assert info["converged"] == int((st == 0).sum())
