@@ -17,10 +17,11 @@ Contents
 * ``acx_dense``: IPT with Alternating Cyclic Extrapolation (Alg. ACX) per column,
   in NumPy.
 * ``norm1`` / ``eigen_residual``: the plain definitions used by the parity bounds.
-* ``pair_partners`` / ``pair_rotation`` / ``pair_back_rotate``: the choice of D per
-  near-degenerate pair (the concluding section's suggestion of choosing D to widen
-  the convergence domain), as 2x2 Jacobi rotations of M, in NumPy; ``ipt_batched``
-  applies them with ``pair_tau``.
+* ``pair_partners`` / ``pair_rotation`` / ``choose_d`` / ``pair_back_rotate``: a
+  choice of D (the concluding section's suggestion of choosing D to widen the
+  convergence domain): near-degenerate pairs rotated out by 2x2 Jacobi rotations of
+  M, then the first- and second-order level shifts moved into D, in NumPy;
+  ``ipt_batched`` applies it with ``pair_tau``.
 
 Every function cites the passage it follows; the readings taken where the paper
 is silent are stated in ``ipt_oracle.c``.
@@ -192,7 +193,7 @@ def ipt_batched(ns, theta_pool, delta_pool, theta_off, delta_off, tol=1e-10, max
                 div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, accel="picard", pair_tau=None):
     """Independent dense full-spectrum IPT solves over a packed batch.  z of problem
     b is returned row-major at z_pool[delta_off[b]:][:n_b*n_b].  With pair_tau, each
-    problem is first rotated by ``pair_rotation`` and its eigenvectors rotated back
+    problem is first re-partitioned by ``choose_d`` and its eigenvectors rotated back
     (``pair_back_rotate``)."""
     if accel != "picard" or pair_tau is not None:
         ns = np.asarray(ns)
@@ -202,7 +203,7 @@ def ipt_batched(ns, theta_pool, delta_pool, theta_off, delta_off, tol=1e-10, max
             n, to, do = int(ns[b]), int(theta_off[b]), int(delta_off[b])
             th = np.asarray(theta_pool[to:to + n]); de = np.asarray(delta_pool[do:do + n * n]).reshape(n, n)
             if pair_tau is not None:
-                th, de, partner, cs = pair_rotation(th, de, pair_tau)
+                th, de, partner, cs = choose_d(th, de, pair_tau)
             r = ipt_dense(th, de, tol=tol, max_iter=max_iter, div_norm=div_norm, div_growth=div_growth, resid=False,
                           accel=accel)
             zb = r.z if pair_tau is None else pair_back_rotate(r.z, partner, cs)
@@ -295,6 +296,33 @@ def pair_rotation(theta, delta, tau):
         de2[i, i] = 0.0
         de2[i, j] = 0.0
     return th2, de2, partner, cs
+
+
+def choose_d(theta, delta, tau):
+    """The partition M = D' + Delta' used with the choice of D: the near-degenerate
+    pairs rotated out (``pair_rotation``), then the level shifts moved into D, to
+    first order (diag Delta) and second order (the RS energy shift
+    s_i = sum_{k != i} Delta_ik Delta_ki / (theta_i - theta_k), on the folded theta;
+    terms with Delta_ik Delta_ki = 0 are 0):
+      theta'_i = (theta_i + Delta_ii) + s_i,  Delta'_ii = -s_i,  Delta'_ik = Delta_ik.
+    The matrix is the rotated M (up to the rounding of theta'); the gaps of G become
+    those of the shifted levels, so a level shift comparable to a small gap no longer
+    makes the fixed point repelling.  Returns (theta', Delta', partner, cs)."""
+    th1, de1, partner, cs = pair_rotation(theta, delta, tau)
+    n = th1.shape[0]
+    th2 = th1 + np.diag(de1)
+    off = de1 - np.diag(np.diag(de1))
+    prod = off * off.T
+    with np.errstate(divide="ignore", invalid="ignore"):
+        terms = np.where(prod != 0.0, prod / (th2[:, None] - th2[None, :]), 0.0)
+    np.fill_diagonal(terms, 0.0)
+    shift = np.zeros(n)
+    for i in range(n):  # in index order
+        acc = 0.0
+        for k in range(n):
+            acc += terms[i, k]
+        shift[i] = acc
+    return th2 + shift, off - np.diag(shift), partner, cs
 
 
 def pair_back_rotate(z, partner, cs):

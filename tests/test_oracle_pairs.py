@@ -131,3 +131,46 @@ def test_batched_workload_failures_recovered():
         lam = rot.lam[to:to + n]
         res = np.linalg.norm(M @ Z[:, ok] - Z[:, ok] * lam[ok], axis=0) / np.linalg.norm(Z[:, ok], axis=0)
         assert res.max() <= 1e-9 * np.abs(M).sum(0).max()
+
+
+def test_choose_d_partition():
+    """choose_d keeps the matrix (to the rounding of theta'): same spectrum as M; the
+    diagonal of Delta' is minus the second-order shift; the shift is the RS
+    second-order energy of the folded partition (checked against rs_eigenvalues at
+    order 2 for a matrix with no pairs)."""
+    th, de = _planted(20, [(4, 5)], 3)
+    de = de + np.diag(np.linspace(-0.01, 0.01, 20))
+    t3, d3, partner, cs = oracle.choose_d(th, de, 0.05)
+    M = np.diag(th) + de
+    np.testing.assert_allclose(np.linalg.eigvalsh(np.diag(t3) + d3), np.linalg.eigvalsh(M), rtol=0, atol=1e-13)
+    # no pairs: theta' is the second-order RS eigenvalue estimate of (theta + diag, offdiag)
+    th2, de2 = _planted(16, [], 4)
+    t3b, d3b, p2, _ = oracle.choose_d(th2, de2, 0.05)
+    assert np.all(p2 < 0)
+    off = de2 - np.diag(np.diag(de2))
+    rs = oracle.rs_eigenvalues(th2 + np.diag(de2), off, 2)  # per-order terms lambda^[0..2]
+    np.testing.assert_allclose(t3b, rs[0] + rs[1] + rs[2], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(np.diag(d3b), -(t3b - (th2 + np.diag(de2))), rtol=0, atol=1e-14)
+
+
+def test_choose_d_recovers_level_shift_failures():
+    """A pair with a small coupling but a gap smaller than the difference of the two
+    levels' shifts: plain IPT diverges on it; with the shifts in D every column
+    converges, and the eigenpairs match a textbook eigensolver."""
+    n = 24
+    rng = np.random.default_rng(9)
+    th = np.arange(1.0, n + 1.0)
+    r = rng.standard_normal((n, n)) * 0.01 / np.sqrt(n)
+    de = (r + r.T) / 2.0
+    th[11] = th[10] + 2e-4
+    de[10, 10], de[11, 11] = 1.5e-3, -1.5e-3   # shift difference 3e-3 >> gap 2e-4
+    de[10, 11] = de[11, 10] = 1e-6
+    ns = np.array([n], np.int32); off = np.array([0], np.int64)
+    plain = oracle.ipt_batched(ns, th, de.ravel(), off, off, tol=1e-12, max_iter=200)
+    assert np.any(plain.status[[10, 11]] != 0)
+    got = oracle.ipt_batched(ns, th, de.ravel(), off, off, tol=1e-12, max_iter=200, pair_tau=0.05)
+    assert np.all(got.status == 0)
+    M = np.diag(th) + de
+    Z = got.z.reshape(n, n)
+    np.testing.assert_allclose(np.sort(got.lam), np.linalg.eigvalsh(M), rtol=0, atol=1e-11)
+    assert np.abs(M @ Z - Z * got.lam).max() <= 1e-10 * np.abs(Z).max()
