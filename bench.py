@@ -172,8 +172,8 @@ def bench_batched(ipt, handle, args):
     res = {}
     modes = (("ladder", ipt.PREC_LADDER, 0), ("ladder_no_graph", ipt.PREC_LADDER, ipt.FLAG_NO_GRAPH),
              ("fp64", ipt.PREC_FP64, 0), ("acx", ipt.PREC_FP64, ipt.FLAG_ACX),
-             ("ladder_pairs", ipt.PREC_LADDER, ipt.FLAG_PAIR_ROTATE), ("acx_pairs", ipt.PREC_FP64,
-                                                                       ipt.FLAG_ACX | ipt.FLAG_PAIR_ROTATE))
+             ("ladder_choose_d", ipt.PREC_LADDER, ipt.FLAG_CHOOSE_D),
+             ("acx_choose_d", ipt.PREC_FP64, ipt.FLAG_ACX | ipt.FLAG_CHOOSE_D))
     for name, prec, flags in modes:
         if args.batched_modes and name not in args.batched_modes.split(","):
             continue

@@ -102,16 +102,21 @@ typedef struct ipt_opts {
  * about 2^-22 relative against FP32's 2^-24, at FP16 matrix-core speed.  Either way
  * only FP64 sweeps certify a column.  (The sparse and batched ladders always use FP32.) */
 #define IPT_FLAG_MID_FP32 16
-/* Near-degenerate pairs (the concluding section's use of the freedom in choosing D):
- * before solving, each problem's pairs i, j that are each other's strongest coupling
- * relative to the gap, r_ij = |Delta_ij| / |theta_i - theta_j| > IPT_PAIR_TAU, with
- * Delta_ij == Delta_ji, are rotated out: M' = R^T M R with the 2x2 Jacobi rotation
- * [[c, s], [-s, c]] that diagonalizes the pair's block of M = diag(theta) + Delta;
- * the pair takes the rotated block's diagonal as theta' and loses its coupling.  IPT
- * runs on M' (same eigenvalues) and z = R z' is returned.  A paired column c is then
- * normalized by (R^T z)_c = 1 instead of z_c = 1.  Batched solves only; the rotated
+/* A choice of D (the concluding section's use of the freedom in choosing D to widen
+ * the convergence domain), batched solves only.  Before solving, each problem is
+ * re-partitioned, M unchanged:
+ *  1. Near-degenerate pairs: i, j that are each other's strongest coupling relative
+ *     to the gap, r_ij = |Delta_ij| / |theta_i - theta_j| > IPT_PAIR_TAU, with
+ *     Delta_ij == Delta_ji, are rotated out: M' = R^T M R with the 2x2 Jacobi rotation
+ *     [[c, s], [-s, c]] that diagonalizes the pair's block of M = diag(theta) + Delta;
+ *     the pair takes the rotated block's diagonal as theta and loses its coupling.
+ *  2. Level shifts: theta' = theta + Delta_ii + s_i with the second-order shift
+ *     s_i = sum_{k != i} Delta_ik Delta_ki / ((theta + Delta_ii)_i - (theta + Delta_kk)_k),
+ *     Delta'_ii = -s_i.
+ * IPT runs on (theta', Delta') (same eigenvalues) and z = R z' is returned, so a paired
+ * column c is normalized by (R^T z)_c = 1 instead of z_c = 1.  The re-partitioned
  * copies of the pools take a second workspace of their size. */
-#define IPT_FLAG_PAIR_ROTATE 32
+#define IPT_FLAG_CHOOSE_D 32
 #define IPT_PAIR_TAU 0.05
 #define IPT_HIST 128
 

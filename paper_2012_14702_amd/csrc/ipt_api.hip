@@ -866,9 +866,9 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
 
 namespace {
 
-// IPT_FLAG_PAIR_ROTATE on a batch: copies of the pools (at the caller's offsets) get
-// each problem's near-degenerate pairs rotated out, the batch is solved on them, and
-// the eigenvectors are rotated back in z_pool.
+// IPT_FLAG_CHOOSE_D on a batch: copies of the pools (at the caller's offsets) are
+// re-partitioned (near-degenerate pairs rotated out, level shifts moved into D), the
+// batch is solved on them, and the eigenvectors are rotated back in z_pool.
 ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
                          const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
                          const double *delta_pool, const ipt_opts &o, double *z_pool, double *lambda_pool,
@@ -887,16 +887,17 @@ ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const i
         dhi = std::max(dhi, delta_off[b] + n * n);
         max_n = std::max(max_n, (int32_t)n);
     }
-    // scratch: theta' [thi], Delta' [dhi], best [thi], partner [thi], rmax [thi], cs [2 thi],
+    // scratch: theta' [thi], Delta' [dhi], best [thi], partner [thi], rmax [thi], cs [2 thi], th2 [thi],
     // then the per-problem n, ld = n, offsets
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t o_dp = up(thi * 8), o_best = o_dp + up(dhi * 8), o_part = o_best + up(thi * 4),
-                 o_rmax = o_part + up(thi * 4), o_cs = o_rmax + up(thi * 8), o_meta = o_cs + up(thi * 16);
+                 o_rmax = o_part + up(thi * 4), o_cs = o_rmax + up(thi * 8), o_th2 = o_cs + up(thi * 16),
+                 o_meta = o_th2 + up(thi * 8);
     const size_t meta_bytes = (size_t)count * (4 + 4 + 8 * 4);
     if (ipt_status st = ensure_buf(h, h->pws, h->pws_bytes, o_meta + meta_bytes)) return st;
     char *base = (char *)h->pws;
     double *tp = (double *)base, *dp = (double *)(base + o_dp), *rmax = (double *)(base + o_rmax);
-    double *cs = (double *)(base + o_cs);
+    double *cs = (double *)(base + o_cs), *th2 = (double *)(base + o_th2);
     int32_t *best = (int32_t *)(base + o_best), *partner = (int32_t *)(base + o_part);
     std::vector<unsigned char> meta(meta_bytes);
     int32_t *hn = (int32_t *)meta.data(), *hk = hn + count;
@@ -917,9 +918,9 @@ ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const i
     IPT_HIP(h, hipMemcpyAsync(dp + dlo, delta_pool + dlo, (size_t)(dhi - dlo) * 8, hipMemcpyDeviceToDevice, s));
     IPT_HIP(h, hipStreamSynchronize(s));  // the host copy of the metadata is released below
     IPT_HIP(h, launch_pair_rotate(s, count, max_n, dn, dto, ddo, theta_pool, delta_pool, tp, dp, best, rmax, partner,
-                                  cs, IPT_PAIR_TAU));
+                                  cs, IPT_PAIR_TAU, th2));
     ipt_opts o2 = o;
-    o2.flags &= ~IPT_FLAG_PAIR_ROTATE;
+    o2.flags &= ~IPT_FLAG_CHOOSE_D;
     const ipt_status st = batched_run(h, count, ns, theta_off, delta_off, z_off, tp, dp, o2, z_pool, lambda_pool,
                                       status_pool, info, 0);
     if (st != IPT_OK && st != IPT_ENOTCONV) return st;
@@ -938,7 +939,7 @@ ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, con
     h->last_error.clear();
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
-    if (o.flags & IPT_FLAG_PAIR_ROTATE) {
+    if (o.flags & IPT_FLAG_CHOOSE_D) {
         DeviceGuard guard(h->device);
         return batched_pairs(h, count, ns, theta_off, delta_off, z_off, theta_pool, delta_pool, o, z_pool,
                              lambda_pool, status_pool, info);

@@ -258,12 +258,13 @@ hipError_t launch_acx(hipStream_t s, const Ctrl *ctrl, const int32_t *state, dou
 // < count (n[b] <= 4096, theta at toff[b], row-major Delta at doff[b]), pairs
 // (partner[toff + r]), their rotations (cs[2 (toff + r) + 0/1]) and the rotated
 // partition written over tp/dp, which hold copies of theta/Delta at the same offsets
-// on entry; best/rmax are scratch of the same length as tp.  launch_pair_rows: rows
+// on entry, then the level shifts moved into theta' (first and second order); best,
+// rmax and th2 are scratch of the same length as tp.  launch_pair_rows: rows
 // of each pair in z (ncols[b] columns, leading dimension ldz[b], at zoff[b]) rotated
 // back (z = R z', forward = 0) or forward (z' = R^T z, forward = 1).
 hipError_t launch_pair_rotate(hipStream_t s, int32_t count, int32_t max_n, const int32_t *n, const int64_t *toff,
                               const int64_t *doff, const double *theta, const double *delta, double *tp, double *dp,
-                              int32_t *best, double *rmax, int32_t *partner, double *cs, double tau);
+                              int32_t *best, double *rmax, int32_t *partner, double *cs, double tau, double *th2);
 hipError_t launch_pair_rows(hipStream_t s, int32_t count, const int32_t *n, const int64_t *toff, const int64_t *zoff,
                             const int64_t *ldz, const int32_t *ncols, double *z, const int32_t *partner,
                             const double *cs, int32_t forward);

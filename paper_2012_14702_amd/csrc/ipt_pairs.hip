@@ -9,7 +9,11 @@
 // is the product of the pairs' rotations and M' = R^T M R.  The new partition keeps
 // every unpaired theta_k and Delta_kk; a pair takes the diagonal of its rotated block
 // as theta', and its coupling leaves Delta'.  IPT then runs on (theta', Delta'), whose
-// near-degenerate pairs are gone, and its eigenvectors map back as z = R z'.
+// near-degenerate pairs are gone, and its eigenvectors map back as z = R z'.  The
+// level shifts then move into D as well: first order (diag Delta) and second order
+// (the RS energy shift), so that two levels whose shifts differ by more than their gap
+// no longer make the fixed point repelling; the matrix is unchanged (theta' + Delta'
+// on the diagonal is the rotated M's, to the rounding of theta').
 #include <math.h>
 
 #include "ipt_internal.h"
@@ -76,9 +80,11 @@ __device__ inline void jacobi_cs(double a, double b, double d, double &c, double
 // One block per problem: pairs, rotation coefficients, then M' = R^T M R on the copy
 // (dp = Delta' at doff[b], tp = theta' at toff[b]; both hold the input on entry):
 // columns first, then rows; pairs are disjoint, so their rotations commute within
-// each pass.  partner[toff + r] = j or -1; cs[2 (toff + r) + 0/1] = c, s.
+// each pass; then the level shifts.  partner[toff + r] = j or -1;
+// cs[2 (toff + r) + 0/1] = c, s.
 __global__ __launch_bounds__(256) void k_pair_rotate(PairMeta m, double *tp, double *dp, const int32_t *best,
-                                                     const double *rmax, int32_t *partner, double *cs, double tau) {
+                                                     const double *rmax, int32_t *partner, double *cs, double tau,
+                                                     double *th2) {
     __shared__ int32_t list[2048];
     __shared__ int32_t count;
     const int b = blockIdx.x;
@@ -140,6 +146,56 @@ __global__ __launch_bounds__(256) void k_pair_rotate(PairMeta m, double *tp, dou
         D[(int64_t)i * n + j] = 0.0;
         D[(int64_t)j * n + i] = 0.0;
     }
+    __syncthreads();
+    // first-order level shift into D: theta2 = theta + diag(Delta) (k_level_shift adds
+    // the second order)
+    for (int k = threadIdx.x; k < n; k += blockDim.x) th2[to + k] = th[k] + D[(int64_t)k * n + k];
+}
+
+// Second-order level shift into D, one block per 32-row tile I of problem blockIdx.y:
+// s_i = sum_{k != i} Delta_ik Delta_ki / (theta2_i - theta2_k) over the rotated Delta
+// (terms with a zero product are 0), then theta'_i = theta2_i + s_i, Delta'_ii = -s_i.
+// The products pair D[I, K] with D[K, I]: both 32 x 32 tiles come in row by row
+// through LDS.  Only this block touches its rows' theta' and diagonal entries; every
+// block reads theta2, and the diagonal entries only for terms it skips.
+__global__ __launch_bounds__(256) void k_level_shift(PairMeta m, double *tp, double *dp, const double *th2) {
+    __shared__ double ta[32][33], tb[32][33];
+    const int b = blockIdx.y;
+    const int n = m.n[b];
+    const int i0 = blockIdx.x * 32;
+    if (i0 >= n) return;
+    const int64_t to = m.toff[b];
+    double *D = dp + m.doff[b];
+    const double *t2 = th2 + to;
+    const int tr = threadIdx.x >> 3, tk = (threadIdx.x & 7) * 4;  // row of the tile, 4 columns
+    const int i = i0 + tr;
+    const double ti = i < n ? t2[i] : 0.0;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < n; k0 += 32) {
+        for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+            const int a = e >> 5, c = e & 31;
+            ta[a][c] = (i0 + a < n && k0 + c < n) ? D[(int64_t)(i0 + a) * n + k0 + c] : 0.0;  // D[I, K]
+            tb[a][c] = (k0 + a < n && i0 + c < n) ? D[(int64_t)(k0 + a) * n + i0 + c] : 0.0;  // D[K, I]
+        }
+        __syncthreads();
+        if (i < n) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + tk + u;
+                const double p = ta[tr][tk + u] * tb[tk + u][tr];
+                if (k < n && k != i && p != 0.0) acc += p / (ti - t2[k]);
+            }
+        }
+        __syncthreads();
+    }
+    // the 8 threads of a row are consecutive lanes
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    if ((threadIdx.x & 7) == 0 && i < n) {
+        tp[to + i] = ti + acc;
+        D[(int64_t)i * n + i] = -acc;
+    }
 }
 
 // Rows i < j of each pair of problem blockIdx.x in z (ncols[b] columns, leading
@@ -169,11 +225,12 @@ __global__ __launch_bounds__(256) void k_pair_rows(PairMeta m, const int64_t *zo
 
 hipError_t launch_pair_rotate(hipStream_t s, int32_t count, int32_t max_n, const int32_t *n, const int64_t *toff,
                               const int64_t *doff, const double *theta, const double *delta, double *tp, double *dp,
-                              int32_t *best, double *rmax, int32_t *partner, double *cs, double tau) {
+                              int32_t *best, double *rmax, int32_t *partner, double *cs, double tau, double *th2) {
     const PairMeta m{n, toff, doff};
     dim3 g((unsigned)((max_n + 3) / 4), (unsigned)count);
     k_pair_best<<<g, 256, 0, s>>>(m, theta, delta, best, rmax);
-    k_pair_rotate<<<(unsigned)count, 256, 0, s>>>(m, tp, dp, best, rmax, partner, cs, tau);
+    k_pair_rotate<<<(unsigned)count, 256, 0, s>>>(m, tp, dp, best, rmax, partner, cs, tau, th2);
+    k_level_shift<<<dim3((unsigned)((max_n + 31) / 32), (unsigned)count), 256, 0, s>>>(m, tp, dp, th2);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ FLAG_TIME_KERNELS = 2
 FLAG_NO_GRAPH = 4
 FLAG_ACX = 8
 FLAG_MID_FP32 = 16
-FLAG_PAIR_ROTATE = 32
+FLAG_CHOOSE_D = 32
 PAIR_TAU = 0.05
 TILE_BUCKETS = 64  # batched tile table: bucket q holds 64 q < n <= 64 (q + 1)
 

@@ -278,7 +278,7 @@ def _planted_pairs(n, pairs, seed, strength=1.5):
 
 @pytest.mark.parametrize("prec", ["fp64", "ladder"])
 def test_batched_pair_rotation_parity(ipt, prec):
-    """IPT_FLAG_PAIR_ROTATE: 20 problems of the batched workload plus three with pairs
+    """IPT_FLAG_CHOOSE_D: 20 problems of the batched workload plus three with pairs
     planted beyond the 2x2 bound (one at a 64-row tile edge, one at the end of a ragged
     size), every problem against the oracle's rotated solve column by column (the same
     pairing, rotation and chart); the planted problems converge on every column, which
@@ -303,14 +303,14 @@ def test_batched_pair_rotation_parity(ipt, prec):
     th_off = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
     de_off = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
     p = ipt.PREC_LADDER if prec == "ladder" else ipt.PREC_FP64
-    z, lam, st, info = _run(ipt, ns, th, de, tol=1e-10, precision=p, max_iter=64, flags=ipt.FLAG_PAIR_ROTATE)
+    z, lam, st, info = _run(ipt, ns, th, de, tol=1e-10, precision=p, max_iter=64, flags=ipt.FLAG_CHOOSE_D)
     _, _, st_plain, _ = _run(ipt, ns, th, de, tol=1e-10, precision=p, max_iter=64)
     compared = 0
     for b in range(len(ns)):
         n = int(ns[b])
         gz, gl, gs = _per_problem(ns, th_off, de_off, z, lam, st, b)
         thb, deb = th[th_off[b]:th_off[b] + n], de[de_off[b]:de_off[b] + n * n].reshape(n, n)
-        th2, de2, partner, cs = oracle.pair_rotation(thb, deb, ipt.PAIR_TAU)
+        th2, de2, partner, cs = oracle.choose_d(thb, deb, ipt.PAIR_TAU)
         rr = oracle.ipt_dense(th2, de2, tol=1e-10, max_iter=64)
         rr["z"] = oracle.pair_back_rotate(rr.z, partner, cs)
         out = check(gz, gl, gs, rr, oracle.norm1(thb, deb), 1e-10, max_iter=64)
