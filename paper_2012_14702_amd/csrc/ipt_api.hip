@@ -875,7 +875,7 @@ ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const i
                          int32_t *status_pool, ipt_info *info) {
     if (count < 1 || !ns || !theta_off || !delta_off || !z_off || !theta_pool || !delta_pool || !z_pool)
         return fail(h, IPT_EINVAL, "bad batch description");
-    int64_t tlo = INT64_MAX, thi = 0, dlo = INT64_MAX, dhi = 0;
+    int64_t tlo = INT64_MAX, thi = 0, dhi = 0;
     int32_t max_n = 0;
     for (int32_t b = 0; b < count; ++b) {
         const int64_t n = ns[b];
@@ -883,7 +883,6 @@ ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const i
         if (theta_off[b] < 0 || delta_off[b] < 0 || z_off[b] < 0) return fail(h, IPT_EINVAL, "negative pool offset");
         tlo = std::min(tlo, theta_off[b]);
         thi = std::max(thi, theta_off[b] + n);
-        dlo = std::min(dlo, delta_off[b]);
         dhi = std::max(dhi, delta_off[b] + n * n);
         max_n = std::max(max_n, (int32_t)n);
     }
@@ -915,7 +914,6 @@ ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const i
     hipStream_t s = h->stream;
     IPT_HIP(h, hipMemcpyAsync(dm, meta.data(), meta_bytes, hipMemcpyHostToDevice, s));
     IPT_HIP(h, hipMemcpyAsync(tp + tlo, theta_pool + tlo, (size_t)(thi - tlo) * 8, hipMemcpyDeviceToDevice, s));
-    IPT_HIP(h, hipMemcpyAsync(dp + dlo, delta_pool + dlo, (size_t)(dhi - dlo) * 8, hipMemcpyDeviceToDevice, s));
     IPT_HIP(h, hipStreamSynchronize(s));  // the host copy of the metadata is released below
     IPT_HIP(h, launch_pair_rotate(s, count, max_n, dn, dto, ddo, theta_pool, delta_pool, tp, dp, best, rmax, partner,
                                   cs, IPT_PAIR_TAU, th2));

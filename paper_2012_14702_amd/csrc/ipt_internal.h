@@ -257,8 +257,9 @@ hipError_t launch_acx(hipStream_t s, const Ctrl *ctrl, const int32_t *state, dou
 // Near-degenerate pair rotation (ipt_pairs.hip).  launch_pair_rotate: for problems b
 // < count (n[b] <= 4096, theta at toff[b], row-major Delta at doff[b]), pairs
 // (partner[toff + r]), their rotations (cs[2 (toff + r) + 0/1]) and the rotated
-// partition written over tp/dp, which hold copies of theta/Delta at the same offsets
-// on entry, then the level shifts moved into theta' (first and second order); best,
+// partition in tp/dp (tp holds a copy of theta on entry; Delta is copied to dp at the
+// same offsets as it is searched), then the level shifts moved into theta' (first and
+// second order); best,
 // rmax and th2 are scratch of the same length as tp.  launch_pair_rows: rows
 // of each pair in z (ncols[b] columns, leading dimension ldz[b], at zoff[b]) rotated
 // back (z = R z', forward = 0) or forward (z' = R^T z, forward = 1).

@@ -29,9 +29,10 @@ struct PairMeta {
 };
 
 // One wave per row r of problem blockIdx.y: best[toff + r] = argmax_k r_rk (first on
-// ties), rmax[toff + r] = its ratio (-1 when n = 1).
+// ties), rmax[toff + r] = its ratio (-1 when n = 1); the row is also copied to dp (the
+// copy that k_pair_rotate re-partitions), at the same offset.
 __global__ __launch_bounds__(256) void k_pair_best(PairMeta m, const double *theta, const double *delta,
-                                                   int32_t *best, double *rmax) {
+                                                   int32_t *best, double *rmax, double *dp) {
     const int b = blockIdx.y;
     const int n = m.n[b];
     const int lane = threadIdx.x & 63;
@@ -39,12 +40,15 @@ __global__ __launch_bounds__(256) void k_pair_best(PairMeta m, const double *the
     if (r >= n) return;
     const double *th = theta + m.toff[b];
     const double *row = delta + m.doff[b] + (int64_t)r * n;
+    double *out = dp + m.doff[b] + (int64_t)r * n;
     const double tr = th[r];
     double bv = -1.0;
     int bk = r;
     for (int k = lane; k < n; k += 64) {
+        const double x = row[k];
+        out[k] = x;
         if (k == r) continue;
-        const double v = fabs(row[k]) / fabs(tr - th[k]);
+        const double v = fabs(x) / fabs(tr - th[k]);
         if (v > bv) {  // k rises: the first index among equal values stays
             bv = v;
             bk = k;
@@ -228,7 +232,7 @@ hipError_t launch_pair_rotate(hipStream_t s, int32_t count, int32_t max_n, const
                               int32_t *best, double *rmax, int32_t *partner, double *cs, double tau, double *th2) {
     const PairMeta m{n, toff, doff};
     dim3 g((unsigned)((max_n + 3) / 4), (unsigned)count);
-    k_pair_best<<<g, 256, 0, s>>>(m, theta, delta, best, rmax);
+    k_pair_best<<<g, 256, 0, s>>>(m, theta, delta, best, rmax, dp);
     k_pair_rotate<<<(unsigned)count, 256, 0, s>>>(m, tp, dp, best, rmax, partner, cs, tau, th2);
     k_level_shift<<<dim3((unsigned)((max_n + 31) / 32), (unsigned)count), 256, 0, s>>>(m, tp, dp, th2);
     return hipGetLastError();
