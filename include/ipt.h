@@ -71,7 +71,9 @@ typedef struct ipt_opts {
     int32_t low_type;   /* IPT_LOW_BF16 (default), IPT_LOW_FP16 or IPT_LOW_NONE */
     int32_t sync_every; /* sweeps launched between host checks of the device stop flag; 0 = auto */
     double tau_low;     /* ladder: leave the low rung once max step <= tau_low; default 1e-5 */
-    double tau_32;      /* ladder: leave FP32 once max step <= tau_32; default 1e-9 */
+    double tau_32;      /* ladder: leave FP32 once max step <= tau_32; default 1e-9.  A rung
+                         * is also left early once the next sweeps are predicted to certify
+                         * (IPT_CERTIFY_SLACK) */
     double div_norm;    /* DIVERGED when |f_i(z) - e_i|_2 > div_norm; default 1e3 */
     int32_t div_growth; /* DIVERGED when s grew on this many consecutive FP64 sweeps; default 8 */
     int32_t flags;      /* IPT_FLAG_* bits */
@@ -118,6 +120,14 @@ typedef struct ipt_opts {
  * copies of the pools take a second workspace of their size. */
 #define IPT_FLAG_CHOOSE_D 32
 #define IPT_PAIR_TAU 0.05
+/* Ladder rule (dense and sparse): the precision of the next sweep follows the steps
+ * seen so far.  After sweep t the largest column step s_t and the ratio q = s_t /
+ * s_(t-1) predict the next step q s_t; after the exact first sweep of a cold start
+ * q ~ s_1 (the first-order correction), so s_1^2 and s_1^3 are the steps one and two
+ * sweeps on.  A rung moves to FP64 (or a cold start skips the low rung) when that
+ * prediction is <= IPT_CERTIFY_SLACK * tol: only the prediction is relaxed, a column
+ * still certifies only on an FP64 step <= tol. */
+#define IPT_CERTIFY_SLACK 2.0
 #define IPT_HIST 128
 
 /* Host struct filled by a solve (may be NULL). */

@@ -722,12 +722,22 @@ __device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep) {
         // Leave a rung when its step is below the rung's threshold, when it stopped
         // falling (the rung's rounding floor), or when the next exact sweep is
         // predicted to certify: with the observed contraction ratio q = s_t / s_{t-1},
-        // the next step is about q s_t.
+        // the next step is about q s_t.  "Certify" allows IPT_CERTIFY_SLACK: the
+        // prediction is for the largest column step, and the few columns left above
+        // tol cost one narrow FP64 sweep, far less than another full sweep of a rung.
+        const double slack_tol = IPT_CERTIFY_SLACK * o.tol;
         const bool stalled = !(ms < ctrl->prev_maxstep);
         const double predicted = ms * (ms / ctrl->prev_maxstep);
-        const bool certify_next = isfinite(predicted) && predicted <= o.tol;
+        const bool certify_next = isfinite(predicted) && predicted <= slack_tol;
         if (prec == PREC_EXACT_FIRST) {
-            next = (ms <= o.tau_32) ? PREC_F64 : (ms <= o.tau_low || o.low_type == IPT_LOW_NONE) ? PREC_F32 : PREC_LOW;
+            // From Z = E the first step is the first-order correction |G o Delta e_i|,
+            // which also estimates the contraction ratio: q ~ s_1, so the step after
+            // one more sweep is ~ s_1^2 and after two ~ s_1^3.  Go straight to FP64
+            // when the next sweep should certify, and skip the low rung when an
+            // FP32-class sweep followed by the certifying FP64 sweep should do.
+            const bool f64_next = ms <= o.tau_32 || ms * ms <= slack_tol;
+            const bool f32_next = ms <= o.tau_low || o.low_type == IPT_LOW_NONE || ms * ms * ms <= slack_tol;
+            next = f64_next ? PREC_F64 : f32_next ? PREC_F32 : PREC_LOW;
         } else if (prec == PREC_LOW) {
             next = (ms <= o.tau_32) ? PREC_F64 : (ms <= o.tau_low || stalled) ? PREC_F32 : PREC_LOW;
         } else if (prec == PREC_F32) {

@@ -25,6 +25,7 @@ FLAG_ACX = 8
 FLAG_MID_FP32 = 16
 FLAG_CHOOSE_D = 32
 PAIR_TAU = 0.05
+CERTIFY_SLACK = 2.0
 TILE_BUCKETS = 64  # batched tile table: bucket q holds 64 q < n <= 64 (q + 1)
 
 

@@ -148,7 +148,7 @@ def test_invalid_arguments(ipt):
     assert e.value.status == ipt.IPT_EINVAL
 
 
-@pytest.mark.parametrize("eps", [0.01, 0.05])
+@pytest.mark.parametrize("eps", [0.005, 0.01, 0.05])
 @pytest.mark.parametrize("low", ["bf16", "fp16", "none"])
 def test_ladder_parity(ipt, eps, low):
     """Precision ladder: low -> FP32 -> FP64; only FP64 sweeps certify, so the
@@ -160,8 +160,16 @@ def test_ladder_parity(ipt, eps, low):
     ref = oracle.ipt_dense(th, de, tol=1e-10)
     check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-10)
     assert g.info["sweep_prec"][-1] == "fp64"
-    if low != "none":
-        assert "low" in g.info["sweep_prec"]
+    # the rung after the exact first sweep follows its step s1 (~ the contraction
+    # ratio of a cold start): the low rung unless s1^3 predicts certification within
+    # the slack (eps = 0.005 here), or the FP32-class rung first when there is none
+    s1 = g.info["sweep_max_step"][0]
+    slack_tol = ipt.CERTIFY_SLACK * 1e-10
+    skip_low = low == "none" or s1 ** 3 <= slack_tol or s1 <= 1e-5
+    assert ("low" in g.info["sweep_prec"]) == (not skip_low), (s1, g.info["sweep_prec"])
+    assert skip_low == (eps == 0.005 or low == "none")
+    if skip_low and s1 ** 2 > slack_tol:
+        assert g.info["sweep_prec"][1] == "fp32"
 
 
 @pytest.mark.parametrize("eps", [0.01, 0.05])
