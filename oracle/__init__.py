@@ -16,6 +16,8 @@ Contents
   (App. B, eq. RS-recursion), in NumPy.
 * ``acx_dense``: IPT with Alternating Cyclic Extrapolation (Alg. ACX) per column,
   in NumPy.
+* ``ipt_dense_cont``: the non-autonomous continuation of the concluding discussion
+  (the perturbation scaled by 1 - alpha^t at sweep t), in the C oracle.
 * ``norm1`` / ``eigen_residual``: the plain definitions used by the parity bounds.
 * ``pair_partners`` / ``pair_rotation`` / ``choose_d`` / ``pair_back_rotate``: a
   choice of D (the concluding section's suggestion of choosing D to widen the
@@ -69,6 +71,8 @@ def _load():
         lib.oracle_ipt_csr.argtypes = [i64, p, p, p, p, i64, p, p, i64, d, C.c_int, d, C.c_int,
                                        p, i64, p, p, p, p, p]
         lib.oracle_ipt_dense_acx.argtypes = lib.oracle_ipt_dense.argtypes
+        lib.oracle_ipt_dense_cont.argtypes = [i64, p, p, i64, i64, p, p, i64, d, d, C.c_int, d, C.c_int,
+                                              p, i64, p, p, p, p, p]
         lib.oracle_ipt_csr_acx.argtypes = lib.oracle_ipt_csr.argtypes
         lib.oracle_ipt_trace.argtypes = [i64, p, p, i64, i64, p, C.c_int, p]
         lib.oracle_ipt_map.argtypes = [i64, p, p, i64, i64, p, p]
@@ -141,6 +145,33 @@ def ipt_dense(theta, delta, idx=None, z0=None, tol=1e-12, max_iter=DEFAULT_MAX_I
     rc = _fn("oracle_ipt_dense", accel)(n, _ptr(theta), _ptr(delta), n, k, _ptr(idx), _ptr(z0), k, tol, max_iter,
                                   div_norm, div_growth, _ptr(z), k, _ptr(lam), _ptr(st), _ptr(sw), _ptr(stp),
                                   _ptr(res))
+    return _finish(rc, z, lam, st, sw, stp, res)
+
+
+def ipt_dense_cont(theta, delta, alpha, idx=None, z0=None, tol=1e-12, max_iter=DEFAULT_MAX_ITER,
+                   div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, resid=True) -> Result:
+    """IPT with the non-autonomous continuation of the concluding discussion (the
+    3 x 3 example): sweep t applies f_i to the partition D + (1 - alpha^t) Delta, so
+    the map tends to the autonomous one; a column is certified only on a sweep whose
+    scale has reached exactly 1 in FP64.  0 < alpha < 1; otherwise as ipt_dense."""
+    if not (0.0 < alpha < 1.0):
+        raise ValueError("alpha must be in (0, 1)")
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    delta = np.ascontiguousarray(delta, dtype=np.float64)
+    n = theta.shape[0]
+    assert delta.shape == (n, n)
+    if idx is None:
+        idx = np.arange(n, dtype=np.int32)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    k = idx.shape[0]
+    if z0 is not None:
+        z0 = np.ascontiguousarray(z0, dtype=np.float64)
+        assert z0.shape == (n, k)
+    z = np.empty((n, k)); lam = np.empty(k); st = np.empty(k, np.int32); sw = np.empty(k, np.int32)
+    stp = np.empty(k); res = np.empty(k) if resid else None
+    rc = _load().oracle_ipt_dense_cont(n, _ptr(theta), _ptr(delta), n, k, _ptr(idx), _ptr(z0), k, float(alpha), tol,
+                                       max_iter, div_norm, div_growth, _ptr(z), k, _ptr(lam), _ptr(st), _ptr(sw),
+                                       _ptr(stp), _ptr(res))
     return _finish(rc, z, lam, st, sw, stp, res)
 
 

@@ -30,6 +30,10 @@
  *     In both cases the last computed iterate f_i(z) is returned, with lambda from
  *     the (Delta z)_i of that sweep.
  *   - a warm start has its entry i overwritten with 1 (chart z_i = 1).
+ *   - non-autonomous continuation: the paper's sequence of scales 1 - alpha^k
+ *     starts at k = 0 (scale 0, the identity map); here sweep t uses 1 - alpha^t,
+ *     the same iterates one sweep earlier.  The paper leaves the stopping rule
+ *     open; here a column certifies only once the scale is exactly 1.
  *
  * Arithmetic: FP64, every dot product summed in ascending index order, compiled
  * with -ffp-contract=off so no fused multiply-add changes the rounding.  OpenMP
@@ -134,6 +138,73 @@ static void solve_column(const op_t *A, const double *theta, int64_t i, double t
         }
         grow = (s > prev_s) ? grow + 1 : 0;
         prev_s = s;
+        memcpy(z, w, (size_t)n * sizeof(double));
+        if (!finite || !(sqrt(dist2) <= div_norm) || grow >= div_growth) {
+            *lambda = theta[i] + d;
+            *status = OR_DIVERGED;
+            *sweeps = t;
+            *step = s;
+            return;
+        }
+    }
+    *lambda = theta[i] + d;
+    *status = OR_NOT_CONVERGED;
+    *sweeps = max_iter;
+    *step = s;
+}
+
+/* Non-autonomous continuation (concluding discussion of the 3 x 3 example): sweep t
+ * applies f_i with the perturbation scaled by 1 - alpha^t, alpha^t formed by
+ * repeated multiplication in FP64, so that the scale tends to 1 and reaches it
+ * exactly once alpha^t drops below half an ulp of 1.  (The paper counts from a
+ * scale of 1 - alpha^0 = 0, the identity map; that sweep is not counted here.)  A
+ * column can pass the stopping test only on a sweep whose scale is exactly 1; while
+ * the scale is below 1 only the non-finite and div_norm rules apply and the growth
+ * count restarts.  lambda = theta_i + (scale Delta z)_i of the last sweep. */
+static void solve_column_cont(const op_t *A, const double *theta, int64_t i, double alpha, double tol,
+                              int max_iter, double div_norm, int div_growth, double *z, double *g, double *y,
+                              double *w, double *lambda, int32_t *status, int32_t *sweeps, double *step) {
+    const int64_t n = A->n;
+    inverse_gaps(n, theta, i, g);
+    z[i] = 1.0;
+    double prev_s = INFINITY, apow = 1.0;
+    int grow = 0;
+    double d = 0.0, s = INFINITY;
+    for (int t = 1; t <= max_iter; ++t) {
+        apow *= alpha;
+        const double scale = 1.0 - apow;
+        op_apply(A, z, y);
+        for (int64_t j = 0; j < n; ++j) y[j] *= scale; /* (scale Delta) z */
+        d = y[i];
+        for (int64_t j = 0; j < n; ++j) w[j] = (j == i) ? 1.0 : g[j] * (z[j] * d - y[j]);
+        double num = 0.0, den = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double e = w[j] - z[j];
+            num += e * e;
+            den += z[j] * z[j];
+        }
+        s = sqrt(num) / sqrt(den);
+        if (scale == 1.0 && s <= tol) {
+            *lambda = theta[i] + d;
+            *status = OR_CONVERGED;
+            *sweeps = t;
+            *step = s;
+            return;
+        }
+        int finite = isfinite(s);
+        double dist2 = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double e = w[j] - (j == i ? 1.0 : 0.0);
+            if (!isfinite(w[j])) finite = 0;
+            dist2 += e * e;
+        }
+        if (scale == 1.0) {
+            grow = (s > prev_s) ? grow + 1 : 0;
+            prev_s = s;
+        } else {
+            grow = 0;
+            prev_s = INFINITY;
+        }
         memcpy(z, w, (size_t)n * sizeof(double));
         if (!finite || !(sqrt(dist2) <= div_norm) || grow >= div_growth) {
             *lambda = theta[i] + d;
@@ -261,7 +332,7 @@ static double eigen_residual(const op_t *A, const double *theta, const double *z
 static int solve_columns(const op_t *A, const double *theta, int64_t k, const int32_t *idx,
                          const double *z0, int64_t ldz0, double tol, int max_iter, double div_norm,
                          int div_growth, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
-                         int32_t *sweeps_out, double *step_out, double *resid_out, int acx) {
+                         int32_t *sweeps_out, double *step_out, double *resid_out, int acx, double alpha) {
     const int64_t n = A->n;
     int fail = 0;
 #pragma omp parallel
@@ -278,7 +349,10 @@ static int solve_columns(const op_t *A, const double *theta, int64_t k, const in
                 for (int64_t j = 0; j < n; ++j) z[j] = z0 ? z0[j * ldz0 + c] : (j == i ? 1.0 : 0.0);
                 double lam, st;
                 int32_t stat, sw;
-                if (acx)
+                if (alpha > 0.0)
+                    solve_column_cont(A, theta, i, alpha, tol, max_iter, div_norm, div_growth, z, g, y, w, &lam,
+                                      &stat, &sw, &st);
+                else if (acx)
                     solve_column_acx(A, theta, i, tol, max_iter, div_norm, div_growth, z, g, y, w, w2, w3, &lam,
                                      &stat, &sw, &st);
                 else
@@ -325,7 +399,20 @@ int oracle_ipt_dense(int64_t n, const double *theta, const double *delta, int64_
                      int32_t *status_out, int32_t *sweeps_out, double *step_out, double *resid_out) {
     op_t A = {n, delta, lda, NULL, NULL, NULL};
     return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
-                         lambda_out, status_out, sweeps_out, step_out, resid_out, 0);
+                         lambda_out, status_out, sweeps_out, step_out, resid_out, 0, 0.0);
+}
+
+/* Non-autonomous continuation (solve_column_cont) with 0 < alpha < 1, otherwise as
+ * oracle_ipt_dense. */
+int oracle_ipt_dense_cont(int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                          const int32_t *idx, const double *z0, int64_t ldz0, double alpha, double tol,
+                          int max_iter, double div_norm, int div_growth, double *z_out, int64_t ldz,
+                          double *lambda_out, int32_t *status_out, int32_t *sweeps_out, double *step_out,
+                          double *resid_out) {
+    if (!(alpha > 0.0 && alpha < 1.0)) return -2;
+    op_t A = {n, delta, lda, NULL, NULL, NULL};
+    return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
+                         lambda_out, status_out, sweeps_out, step_out, resid_out, 0, alpha);
 }
 
 /* IPT-ACX (Alg. 3 in place of the plain update), otherwise as oracle_ipt_dense;
@@ -336,7 +423,7 @@ int oracle_ipt_dense_acx(int64_t n, const double *theta, const double *delta, in
                          int32_t *status_out, int32_t *sweeps_out, double *step_out, double *resid_out) {
     op_t A = {n, delta, lda, NULL, NULL, NULL};
     return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
-                         lambda_out, status_out, sweeps_out, step_out, resid_out, 1);
+                         lambda_out, status_out, sweeps_out, step_out, resid_out, 1, 0.0);
 }
 
 /* Same with a CSR Delta (row_ptr[n+1], col[nnz], val[nnz]). */
@@ -347,7 +434,7 @@ int oracle_ipt_csr(int64_t n, const double *theta, const int32_t *row_ptr, const
                    double *resid_out) {
     op_t A = {n, NULL, 0, row_ptr, col, val};
     return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
-                         lambda_out, status_out, sweeps_out, step_out, resid_out, 0);
+                         lambda_out, status_out, sweeps_out, step_out, resid_out, 0, 0.0);
 }
 
 /* IPT-ACX with a CSR Delta. */
@@ -358,7 +445,7 @@ int oracle_ipt_csr_acx(int64_t n, const double *theta, const int32_t *row_ptr, c
                        double *resid_out) {
     op_t A = {n, NULL, 0, row_ptr, col, val};
     return solve_columns(&A, theta, k, idx, z0, ldz0, tol, max_iter, div_norm, div_growth, z_out, ldz,
-                         lambda_out, status_out, sweeps_out, step_out, resid_out, 1);
+                         lambda_out, status_out, sweeps_out, step_out, resid_out, 1, 0.0);
 }
 
 /* The iterates z^(0..t) of f_i from a start z (no stopping test): out is

@@ -87,8 +87,43 @@ def _pins_pass():
     return ok
 
 
+# Non-autonomous continuation: mistakes caught by the pins of test_oracle_cont
+CONT_MUTANTS = {
+    "cont_schedule_from_zero": ("const double scale = 1.0 - apow;", "const double scale = 1.0 - apow / alpha;"),
+    "cont_certify_while_scaled": ("if (scale == 1.0 && s <= tol) {", "if (s <= tol) {"),
+    "cont_unscaled_d": ("for (int64_t j = 0; j < n; ++j) y[j] *= scale; /* (scale Delta) z */\n        d = y[i];",
+                        "d = y[i];\n        for (int64_t j = 0; j < n; ++j) y[j] *= scale; /* (scale Delta) z */"),
+    "cont_unscaled_map": ("for (int64_t j = 0; j < n; ++j) y[j] *= scale; /* (scale Delta) z */",
+                          "/* scale dropped */"),
+}
+
+
 def test_unmodified_oracle_passes():
     assert _pins_pass()
+    from test_oracle_cont import cont_pins_pass
+    assert cont_pins_pass()
+
+
+def _build_mutant(tmp_path, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, old
+    path = tmp_path / "mut.c"
+    path.write_text(src.replace(old, new))
+    so = str(tmp_path / "libmut.so")
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-o", so,
+                           str(path), "-lm"])
+    return so
+
+
+@pytest.mark.parametrize("name", sorted(CONT_MUTANTS))
+def test_planted_continuation_mistake_is_caught(tmp_path, name):
+    from test_oracle_cont import cont_pins_pass
+    so = _build_mutant(tmp_path, *CONT_MUTANTS[name])
+    prev = oracle.swap_library(so)
+    try:
+        assert not cont_pins_pass(), "mistake %s went unnoticed" % name
+    finally:
+        oracle.swap_library(prev)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
