@@ -77,6 +77,18 @@ typedef struct ipt_opts {
     double div_norm;    /* DIVERGED when |f_i(z) - e_i|_2 > div_norm; default 1e3 */
     int32_t div_growth; /* DIVERGED when s grew on this many consecutive FP64 sweeps; default 8 */
     int32_t flags;      /* IPT_FLAG_* bits */
+    double cont_alpha;  /* 0 (default): the autonomous map.  0 < cont_alpha < 1: the
+                         * non-autonomous continuation of the concluding discussion (its
+                         * 3 x 3 example): sweep t applies the map of the partition
+                         * D + (1 - cont_alpha^t) Delta, cont_alpha^t formed by repeated
+                         * multiplication in FP64, so the scale reaches exactly 1 once
+                         * cont_alpha^t drops below half an ulp of 1 (t = 54 for 1/2).  A
+                         * column certifies only on a sweep of scale 1; before that only
+                         * the non-finite and div_norm rules (on the scaled iterate) end a
+                         * column, and the growth rule restarts.  It moves the start e_i
+                         * (or z0) along with the fixed point as the perturbation grows.
+                         * Dense solves with precision = IPT_PREC_FP64 and without
+                         * IPT_FLAG_ACX only; elsewhere IPT_EINVAL */
 } ipt_opts;
 
 /* Skip |M|_1 (one extra pass over Delta) and report resid unnormalised. */

@@ -110,6 +110,10 @@ ipt_status check_opts(ipt_handle h, const ipt_opts *in, ipt_opts &o) {
     if (!(o.tau_low >= 0.0) || !(o.tau_32 >= 0.0)) return fail(h, IPT_EINVAL, "opts.tau_low/tau_32 must be >= 0");
     if ((o.flags & IPT_FLAG_ACX) && o.precision != IPT_PREC_FP64)
         return fail(h, IPT_EINVAL, "IPT_FLAG_ACX runs FP64 sweeps: set precision = IPT_PREC_FP64");
+    if (!(o.cont_alpha >= 0.0 && o.cont_alpha < 1.0))
+        return fail(h, IPT_EINVAL, "opts.cont_alpha must be in [0, 1)");
+    if (o.cont_alpha > 0.0 && (o.precision != IPT_PREC_FP64 || (o.flags & IPT_FLAG_ACX)))
+        return fail(h, IPT_EINVAL, "opts.cont_alpha needs precision = IPT_PREC_FP64 and no IPT_FLAG_ACX");
     return IPT_OK;
 }
 
@@ -120,6 +124,7 @@ DevOpts dev_opts(const ipt_opts &o) {
     d.tau_low = o.tau_low;
     d.tau_32 = o.tau_32;
     d.div_norm = o.div_norm;
+    d.cont_alpha = o.cont_alpha;
     d.max_iter = o.max_iter;
     d.div_growth = o.div_growth;
     d.ladder = o.precision == IPT_PREC_LADDER;
@@ -668,8 +673,10 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     // small column-setup kernels queue behind it instead of idling the device.
     // Plain sweeps take d of the next sweep from the product epilogue; for an exactly
     // symmetric Delta (checked once here) it reads Delta_ji, coalesced, for Delta_ij.
-    const bool fuse_d = !acx;
-    IPT_HIP(h, launch_ctrl_init(s, ctrl, start_prec, k, fuse_d ? 1 : 0));
+    // continuation sweeps rescale W after the product, so d comes from the pass over Delta
+    const bool cont = o.cont_alpha > 0.0;
+    const bool fuse_d = !acx && !cont;
+    IPT_HIP(h, launch_ctrl_init(s, ctrl, start_prec, k, fuse_d ? 1 : 0, o.cont_alpha));
     // Row-major pass over Delta (copy, BF16/FP32 shadows, |M|_1, max |Delta|), then the
     // tile-pair pass (symmetry, FP16 shadows at the power-of-two scale from that max)
     const bool mid_x3 = dopt.mid_x3 != 0;
@@ -725,6 +732,7 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
                                          lt, ypart, nblk, fuse_d ? dnp : nullptr, dopt.mid_x3));
             IPT_HIP(h, timer.mark(t, 1, s));
         }
+        if (cont) IPT_HIP(h, launch_cont_blend(s, ctrl, zout, kp, cs, n, kp));
         const bool fused_d = fuse_d;  // every plain sweep (the product-free first one too) forms the next d
         IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, nrt, kp, t, in_par, out_par,
                                    fused_d ? dnp : nullptr));
@@ -757,6 +765,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         return fail(h, IPT_EINVAL, "theta, row_ptr, col, val, z_out, lambda_out and col_status must be non-NULL");
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
+    if (o.cont_alpha > 0.0) return fail(h, IPT_EINVAL, "opts.cont_alpha: continuation is for dense solves");
     DevOpts dopt = dev_opts(o);
     dopt.low_type = IPT_LOW_NONE;  // the sparse ladder runs FP32 then FP64 sweeps
     dopt.mid_x3 = 0;
@@ -937,6 +946,7 @@ ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, con
     h->last_error.clear();
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
+    if (o.cont_alpha > 0.0) return fail(h, IPT_EINVAL, "opts.cont_alpha: continuation is for dense solves");
     if (o.flags & IPT_FLAG_CHOOSE_D) {
         DeviceGuard guard(h->device);
         return batched_pairs(h, count, ns, theta_off, delta_off, z_off, theta_pool, delta_pool, o, z_pool,

@@ -43,6 +43,8 @@ struct Ctrl {
     uint64_t dmax_bits;    // max |Delta_jl| (bits), set when the FP16 rung needs a scale
     double dscale;         // power-of-two scale of the low-precision Delta shadow (1 unless FP16)
     double zscale;         // power-of-two scale of the low-precision (Z - E) shadow (1 unless FP16)
+    double apow;           // continuation: alpha^t of the next sweep t (0 without continuation)
+    double escale;         // continuation: the next sweep's perturbation scale 1 - alpha^t (1 without)
     int64_t matvecs;
     double prev_maxstep;
     int32_t hist_prec[IPT_HIST];
@@ -53,6 +55,7 @@ struct Ctrl {
 // Options as the kernels see them.
 struct DevOpts {
     double tol, tau_low, tau_32, div_norm;
+    double cont_alpha;      // non-autonomous continuation (0: off)
     int32_t max_iter, div_growth, ladder, low_type;
     int32_t first_product;  // the first sweep of a cold start multiplies by Delta (sparse path)
     int32_t acx;            // IPT-ACX cycles (orders 3, 2, 3, 2, ...)
@@ -106,7 +109,14 @@ hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *id
 hipError_t launch_init_cols(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                             int64_t kp, uint32_t *bitmap, int32_t ntiles_n, int32_t start_stamp);
 // sym0 = 1 when the symmetry scan runs next (it clears sym on the first asymmetric pair).
-hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0 = 0);
+hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0 = 0,
+                            double cont_alpha = 0.0);
+// Continuation sweep (scale s = Ctrl::escale < 1): the sweep computed W = F(Z) of the
+// unscaled partition; the continuation map is E + s (F(Z) - E), so the off-diagonal
+// entries of this sweep's active columns are multiplied by s in place.  Nothing is
+// done once s = 1.
+hipError_t launch_cont_blend(hipStream_t s, const Ctrl *ctrl, double *w, int64_t ldw, ColState cs, int64_t n,
+                             int64_t kp);
 // Tile pairs of Delta over the padded np x np, after launch_prep_delta: want_sym
 // clears ctrl->sym unless Delta equals its transpose bit for bit; f16 (the FP16 low
 // rung) and hi (hi/lo of the three-product rung, lo = hi + np^2) receive the FP16

@@ -24,7 +24,7 @@ __device__ inline uint64_t dbits(double x) {
 
 __device__ inline double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
 
-__global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k, int32_t sym0) {
+__global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k, int32_t sym0, double cont_alpha) {
     uint32_t *w = (uint32_t *)ctrl;
     constexpr int words = (int)(sizeof(Ctrl) / sizeof(uint32_t));
     for (int q = threadIdx.x; q < words; q += blockDim.x) w[q] = 0u;
@@ -36,6 +36,9 @@ __global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k, int32_t s
         ctrl->prev_maxstep = INFINITY;
         ctrl->dscale = 1.0;
         ctrl->zscale = 1.0;
+        // continuation: sweep 1 applies the map of D + (1 - alpha) Delta
+        ctrl->apow = cont_alpha;
+        ctrl->escale = 1.0 - cont_alpha;
     }
 }
 
@@ -590,6 +593,10 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
     // (with plain sweeps, p = 1: the last sweep).
     int32_t q, pc;
     acx_phase(o.acx, sweep, q, pc);
+    // continuation sweep (scale es < 1): no column certifies, the growth rule restarts,
+    // and |W - e| of the scaled iterate is es |F(Z) - e|
+    const double es = ctrl->escale;
+    const bool scaled = es < 1.0;
     if (act && q != 0) {
         s = sqrt(p[0]) / sqrt(p[1]);
         cs.tile_stamp[c / TILE_N] = sweep;
@@ -602,14 +609,18 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
         const double resid = sqrt(p[2]) / (nrm > 0.0 ? nrm : 1.0) / sqrt(p[1]);
         const int32_t i = cs.idx[c];
         int32_t par = 0;
-        if (exact && s <= o.tol) {
+        if (exact && !scaled && s <= o.tol) {
             decided = COL_CONVERGED;
             par = in_par;
             res_bits = dbits(resid);
         } else {
-            const bool bad = !isfinite(s) || !(sqrt(p[3]) <= o.div_norm);
+            const bool bad = !isfinite(s) || !((scaled ? es * sqrt(p[3]) : sqrt(p[3])) <= o.div_norm);
             int32_t grow = cs.grow[c];
-            if (exact) {
+            if (scaled) {
+                grow = 0;
+                cs.prev[c] = INFINITY;
+                cs.grow[c] = 0;
+            } else if (exact) {
                 grow = (s > cs.prev[c]) ? grow + 1 : 0;
                 cs.prev[c] = s;
                 cs.grow[c] = grow;
@@ -627,7 +638,7 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
             cs.par[c] = par;
             cs.sweeps[c] = sweep;
             cs.step[c] = s;
-            cs.lam[c] = theta[i] + d;
+            cs.lam[c] = theta[i] + (scaled ? es * d : d);
             cs.resid[c] = resid;
         } else {
             cs.tile_stamp[c / TILE_N] = sweep;
@@ -746,6 +757,11 @@ __device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep) {
     }
     ctrl->prec = next;
     ctrl->prev_maxstep = ms;
+    // continuation: the scale of sweep t + 1 is 1 - alpha^(t+1); it stays at 1 once there
+    if (o.cont_alpha > 0.0 && ctrl->escale < 1.0) {
+        ctrl->apow *= o.cont_alpha;
+        ctrl->escale = 1.0 - ctrl->apow;
+    }
     // FP16 shadows (FP16 low rung, three-product rung): scale Z - E by a power of two
     // so that its largest entry (bounded by max_c |W_c - e_i|) lands near 2^13, well
     // inside the FP16 range.
@@ -846,7 +862,7 @@ inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) /
 
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp) {
-    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k, 0);
+    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k, 0, 0.0);
     return launch_init_cols(s, ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp);
 }
 
@@ -864,8 +880,9 @@ hipError_t launch_plan_dense(hipStream_t s, Ctrl *ctrl, ColState cs, int64_t kp)
     return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0) {
-    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, active, sym0);
+hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0,
+                            double cont_alpha) {
+    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, active, sym0, cont_alpha);
     return hipGetLastError();
 }
 
@@ -970,6 +987,29 @@ hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const do
     return hipGetLastError();
 }
 
+
+// Continuation sweep: W <- E + s (W - E) on this sweep's active columns (packed list
+// of the plan that launched it), rows j != i; block = 64 columns x 4 row lanes.
+__global__ __launch_bounds__(256) void k_cont_blend(const Ctrl *ctrl, double *w, int64_t ldw, ColState cs,
+                                                    int64_t n) {
+    if (ctrl->error || ctrl->done) return;
+    const double es = ctrl->escale;
+    if (!(es < 1.0)) return;
+    const int64_t p = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (p >= ctrl->kact) return;
+    const int32_t c = cs.alist[p];
+    const int32_t i = cs.idx[c];
+    for (int64_t j = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); j < n; j += (int64_t)gridDim.y * 4)
+        if (j != i) w[j * ldw + c] *= es;
+}
+
+hipError_t launch_cont_blend(hipStream_t s, const Ctrl *ctrl, double *w, int64_t ldw, ColState cs, int64_t n,
+                             int64_t kp) {
+    const int64_t rows = (n + 3) / 4;
+    dim3 g((unsigned)((kp + 63) / 64), (unsigned)(rows < 64 ? rows : 64));
+    k_cont_blend<<<g, 256, 0, s>>>(ctrl, w, ldw, cs, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
                          int64_t ldt, int64_t np, int64_t kp, int32_t low_type, int32_t mid_x3) {

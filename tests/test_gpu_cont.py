@@ -1,0 +1,97 @@
+"""GPU parity of the non-autonomous continuation (opts.cont_alpha, dense FP64
+sweeps) against the oracle's continuation, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import dev, host, say, t
+from parity import check
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ipt():
+    from paper_2012_14702_amd import ipt as mod
+    mod.load_library()
+    dev()
+    return mod
+
+
+def _solve(ipt, theta, delta, idx=None, z0=None, **kw):
+    r = ipt.ipt_solve_dense(t(theta), t(delta), idx=None if idx is None else t(idx.astype(np.int32)),
+                            z0=None if z0 is None else t(z0), **kw)
+    return host(r)
+
+
+def test_three_by_three_rescued(ipt):
+    """The paper's 3 x 3 example at eps = -0.475: plain IPT diverges on column 2,
+    the continuation converges there (after the scale reaches 1 at sweep 54); every
+    column matches the oracle's continuation."""
+    say("continuation 3x3 eps=-0.475 alpha=0.5")
+    th, de = W.three_by_three(-0.475)
+    plain = _solve(ipt, th, de, tol=1e-12, max_iter=2000)
+    g = _solve(ipt, th, de, tol=1e-12, max_iter=2000, cont_alpha=0.5)
+    ref = oracle.ipt_dense_cont(th, de, 0.5, tol=1e-12, max_iter=2000)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12, gpu_sweeps=g.sweeps, max_iter=2000)
+    assert plain.status[1] == ipt.DIVERGED and g.status[1] == ipt.CONVERGED
+    lam = np.linalg.eigvals(np.diag(th) + de)
+    assert np.min(np.abs(lam - g.lam[1])) < 1e-10
+    assert g.sweeps[1] >= 54
+
+
+@pytest.mark.parametrize("n,k,eps,alpha", [(300, 300, 0.05, 0.5), (257, 40, 0.2, 0.7), (129, 129, 0.02, 0.5)])
+def test_random_parity(ipt, n, k, eps, alpha):
+    """Ragged sizes over several row and column tiles; every column certifies at the
+    oracle's fixed point, no earlier than the scale's switch to 1."""
+    say("continuation n=%d k=%d eps=%g alpha=%g" % (n, k, eps, alpha))
+    th, de = W.dense_sym_gaussian(n, eps, 2)
+    idx = None if k == n else np.sort(np.random.default_rng(4).choice(n, k, replace=False)).astype(np.int32)
+    g = _solve(ipt, th, de, idx=idx, tol=1e-10, max_iter=400, cont_alpha=alpha)
+    ref = oracle.ipt_dense_cont(th, de, alpha, idx=idx, tol=1e-10, max_iter=400, resid=False)
+    out = check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-10, gpu_sweeps=g.sweeps, max_iter=400)
+    assert out["compared"] == k
+    switch = int(np.ceil(54 / np.log2(1 / alpha)))  # first t with alpha^t below half an ulp of 1 (approx.)
+    assert np.all(g.sweeps >= switch - 2)
+
+
+def test_budget_ends_during_continuation(ipt):
+    """max_iter = 10 at alpha = 0.8: every column ends NOT_CONVERGED with the tenth
+    iterate of the continuation map, equal to the oracle's to rounding."""
+    say("continuation budget n=200")
+    th, de = W.dense_sym_gaussian(200, 0.05, 6)
+    g = _solve(ipt, th, de, tol=1e-10, max_iter=10, cont_alpha=0.8)
+    ref = oracle.ipt_dense_cont(th, de, 0.8, tol=1e-10, max_iter=10, resid=False)
+    assert np.all(g.status == ipt.NOT_CONVERGED) and np.all(ref.status == oracle.NOT_CONVERGED)
+    assert np.max(np.abs(g.z - ref.z)) < 1e-13
+    assert np.max(np.abs(g.lam - ref.lam)) < 1e-13 * oracle.norm1(th, de)
+
+
+def test_tiny_alpha_is_plain(ipt):
+    """cont_alpha = 1e-300: the first scale rounds to 1, so the solve is the plain
+    FP64 method (same decisions and sweep counts, same answers)."""
+    say("continuation alpha=1e-300 n=256")
+    th, de = W.dense_sym_gaussian(256, 0.03, 8)
+    p = _solve(ipt, th, de, tol=1e-12)
+    g = _solve(ipt, th, de, tol=1e-12, cont_alpha=1e-300)
+    np.testing.assert_array_equal(p.status, g.status)
+    np.testing.assert_array_equal(p.sweeps, g.sweeps)
+    assert np.max(np.abs(p.z - g.z)) < 1e-15 and np.max(np.abs(p.lam - g.lam)) < 1e-14
+
+
+def test_continuation_rejected_elsewhere(ipt):
+    th, de = W.dense_sym_gaussian(16, 0.01, 0)
+    for kw in (dict(cont_alpha=0.5, precision=ipt.PREC_LADDER), dict(cont_alpha=0.5, flags=ipt.FLAG_ACX),
+               dict(cont_alpha=1.0), dict(cont_alpha=-0.25), dict(cont_alpha=float("nan"))):
+        with pytest.raises(ipt.IPTError) as e:
+            _solve(ipt, th, de, **kw)
+        assert e.value.status == ipt.IPT_EINVAL, kw
+    th_s, rp, col, val = W.sparse_sym_uniform(64, 3, 0.05, 1)
+    with pytest.raises(ipt.IPTError) as e:
+        ipt.ipt_solve_csr(t(th_s), t(rp), t(col), t(val), t(np.arange(4, dtype=np.int32)), cont_alpha=0.5)
+    assert e.value.status == ipt.IPT_EINVAL
+    ns, thb, deb, _, _ = W.batched_sym_gaussian(3, 8, 40, 0.02, seed=1)
+    with pytest.raises(ipt.IPTError) as e:
+        ipt.ipt_solve_batched(ns, t(thb), t(deb), cont_alpha=0.5)
+    assert e.value.status == ipt.IPT_EINVAL
