@@ -226,6 +226,55 @@ def bench_morgan(ipt, handle, args):
     return {"workload": "Morgan tridiagonal n=5000, off-diagonal 0.5, k lowest, tol 1e-12", "modes": res}
 
 
+def bench_continuation(ipt, handle, args):
+    """Non-autonomous continuation (opts.cont_alpha; the concluding discussion of the
+    3 x 3 example): the paper's 3 x 3 matrix D = diag(0, 1, 3) + eps P over a grid of
+    real eps, columns converged by plain IPT and by the continuation (alpha = 1/2,
+    tol 1e-12); and its cost on the dense n = 4096 workload against plain FP64."""
+    import numpy as np
+    import torch
+    import workloads
+    dev = torch.device("cuda:0")
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    step = args.cont_grid_step
+    grid = [] if step <= 0 else [e for e in np.round(np.arange(-0.6, 0.6 + step / 2, step), 6) if e != 0.0]
+    conv = {"plain": [0, 0, 0], "continuation": [0, 0, 0]}
+    rescued = []
+    t0 = time.perf_counter()
+    for eps in grid:
+        th, de = workloads.three_by_three(float(eps))
+        st = {}
+        for name, alpha in (("plain", 0.0), ("continuation", 0.5)):
+            r = ipt.ipt_solve_dense(tt(th), tt(de), handle=handle, tol=1e-12, max_iter=1000, cont_alpha=alpha)
+            st[name] = r.status.cpu().numpy()
+            for c in range(3):
+                conv[name][c] += int(st[name][c] == ipt.CONVERGED)
+        rescued += ["eps=%g col %d" % (eps, c + 1) for c in range(3)
+                    if st["continuation"][c] == ipt.CONVERGED and st["plain"][c] != ipt.CONVERGED]
+    t_grid = time.perf_counter() - t0
+    log("continuation 3x3 grid (%d eps): converged plain %s, continuation %s; rescued: %s" % (
+        len(grid), conv["plain"], conv["continuation"], rescued))
+    th, de = workloads.dense_sym_gaussian(args.n, args.eps, 0)
+    thd, ded = tt(th), tt(de)
+    dense = {}
+    for name, alpha in (("fp64", 0.0), ("continuation", 0.5)):
+        o = ipt.default_opts(tol=1e-10, precision=ipt.PREC_FP64, max_iter=200, cont_alpha=alpha)
+        run = lambda: ipt.ipt_solve_dense(thd, ded, opts=o, handle=handle, colinfo=False)
+        _time(run, 1)
+        sec, r = _time(run, 2)
+        inf = r.info
+        dense[name] = {"ms_per_solve": round(sec * 1e3, 3), "sweeps": inf["sweeps"], "converged": inf["converged"],
+                       "eigenpairs_per_s": round(inf["converged"] / sec, 1)}
+        log("continuation dense n=%d eps=%g %s: %.2f ms/solve, %d sweeps, %d converged" % (
+            args.n, args.eps, name, sec * 1e3, inf["sweeps"], inf["converged"]))
+        del r
+    return {"workload": "3x3 D=diag(0,1,3)+eps*[[0,1,2],[1,0,3],[2,3,0]], %d real eps in [-0.6, 0.6] (step %g), "
+                        "tol 1e-12, max 1000 sweeps, alpha=0.5; dense n=%d eps=%g full spectrum, tol 1e-10" % (
+                            len(grid), step, args.n, args.eps),
+            "grid_converged_per_column": conv, "rescued": rescued, "grid_seconds": round(t_grid, 3),
+            "dense": dense}
+
+
 def bench_learned(ipt, handle, args):
     """Learned warm start: M(eps) = diag(1..1024) + eps R, R = (R'+R'^T)/2, R' iid N(0,1/n)
     seed 0, k = 32 lowest; the network is trained on 512 eps ~ U[0, 0.08] (seed 1) and
@@ -300,14 +349,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "ladder", "ladder_fp32_mma", "fp64"], default="all",
                     help="restrict the dense workload to one mode (for profiler runs)")
-    ap.add_argument("--extra", default="sparse,morgan,batched,learned",
-                    help="comma list of secondary workloads to time: sparse, batched, learned ('' for none)")
+    ap.add_argument("--extra", default="sparse,morgan,batched,learned,continuation",
+                    help="comma list of secondary workloads to time: sparse, morgan, batched, learned, "
+                         "continuation ('' for none)")
     ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the warm-start network")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense workload (profiling of the others)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to scale HBM counters) and exit")
     ap.add_argument("--batch", type=int, default=4096, help="problems in the batched workload")
     ap.add_argument("--batched-modes", default="", help="comma list of batched modes to time (default: all)")
+    ap.add_argument("--cont-grid-step", type=float, default=0.0025,
+                    help="eps step of the 3x3 continuation grid (0: skip the grid)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -339,7 +391,7 @@ def main():
         extras = [e for e in args.extra.split(",") if e]
         out = {}
         for name, fn in (("sparse", bench_sparse), ("morgan", bench_morgan), ("batched", bench_batched),
-                         ("learned", bench_learned)):
+                         ("learned", bench_learned), ("continuation", bench_continuation)):
             if name in extras:
                 out[name] = fn(ipt, handle, args)
         print(json.dumps(out), flush=True)
@@ -453,6 +505,8 @@ def main():
         out["batched"] = bench_batched(ipt, handle, args)
     if "learned" in extras:
         out["learned"] = bench_learned(ipt, handle, args)
+    if "continuation" in extras:
+        out["continuation"] = bench_continuation(ipt, handle, args)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
         th, de = host[args.eps]
