@@ -109,6 +109,7 @@ template <>
 __device__ inline _Float16 to_low<_Float16>(double x) { return (_Float16)(float)x; }
 
 __device__ inline void wave_atomic_max(uint64_t *p, uint64_t v);  // one atomic max per wave (below)
+__device__ inline void block_atomic_max(uint64_t *p, uint64_t v);  // one atomic max per block (below)
 
 // Row-major pass over Delta: a zero-padded FP64 copy (when Delta is not tile
 // aligned), the BF16 and FP32 shadows of the ladder, max |Delta_jl| (for the scale
@@ -219,7 +220,9 @@ __global__ void k_norm1_reduce(Ctrl *ctrl, const double *colpart, int64_t n, int
 // CSR column sums: off-diagonal |Delta_jc| go to scratch[c], diagonal entries of
 // Delta to scratch[n + c] (added to theta_c before taking the modulus).  Double
 // atomics: the norm is a diagnostic (it scales the reported eigen-residual) and
-// takes no part in any decision.
+// takes no part in any decision, so the order of the sums is free.  (An exact check
+// that |M| is symmetric, which would turn the column sums into row sums, reads a
+// random line of row_ptr, col and val per entry and costs as much as the atomics.)
 __global__ void k_norm1_csr_part(const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, const double *val,
                                  int64_t n, double *scratch) {
     if (ctrl->error) return;  // the structure checks ran first; never walk a malformed matrix
@@ -232,11 +235,16 @@ __global__ void k_norm1_csr_part(const Ctrl *ctrl, const int32_t *row_ptr, const
     }
 }
 
-__global__ void k_norm1_csr_reduce(Ctrl *ctrl, const double *theta, const double *scratch, int64_t n) {
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    const double v = scratch[c] + fabs(theta[c] + scratch[n + c]);
-    atomicMax((unsigned long long *)&ctrl->norm1_bits, (unsigned long long)dbits(v));
+// Block: grid-stride over columns, one atomic max per block.
+__global__ __launch_bounds__(256) void k_norm1_csr_reduce(Ctrl *ctrl, const double *theta, const double *scratch,
+                                                          int64_t n) {
+    if (ctrl->error) return;
+    uint64_t m = 0;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = dbits(scratch[c] + fabs(theta[c] + scratch[n + c]));
+        m = b > m ? b : m;
+    }
+    block_atomic_max(&ctrl->norm1_bits, m);
 }
 
 __global__ void k_zero_f64(double *p, int64_t count) {
@@ -552,6 +560,19 @@ __device__ inline void wave_atomic_max(uint64_t *p, uint64_t v) {
     if ((threadIdx.x & 63) == 0 && v) atomicMax((unsigned long long *)p, (unsigned long long)v);
 }
 
+// Every thread of the block must call it (blockDim.x a multiple of 64, at most 1024).
+__device__ inline void block_atomic_max(uint64_t *p, uint64_t v) {
+    __shared__ uint64_t wm[16];
+    v = wave_max_u64(v);
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t m = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = wm[w] > m ? wm[w] : m;
+        if (m) atomicMax((unsigned long long *)p, (unsigned long long)m);
+    }
+}
+
 // Finalize sweep t for every active column: reduce the partial sums over row
 // tiles in a fixed order, form s_c = |W_c - Z_c| / |Z_c| (Alg. 1 loop test,
 // Euclidean norms), and decide.  Only an exact sweep (FP64 product, or the
@@ -781,11 +802,15 @@ __global__ void k_set_dscale(Ctrl *ctrl) {
 
 // z_out[:, c] <- the buffer holding column c's final value; lambda, status and the
 // optional per-column outputs.
-__global__ void k_copyout(const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1, int64_t ldzb,
-                          double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out, int64_t n, int64_t k,
-                          int32_t *ci_sweeps, double *ci_step, double *ci_resid) {
+// Block: cw columns (a power of two, cw <= 256) x 256 / cw row lanes over 64-row
+// chunks, so that narrow solves (few columns) still use every thread of a block.
+__global__ __launch_bounds__(256) void k_copyout(const Ctrl *ctrl, ColState cs, const double *buf0,
+                                                 const double *buf1, int64_t ldzb, double *z_out, int64_t ldz,
+                                                 double *lambda_out, int32_t *status_out, int64_t n, int64_t k,
+                                                 int32_t cw, int32_t *ci_sweeps, double *ci_step, double *ci_resid) {
     if (ctrl->error) return;
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int rl = threadIdx.x / cw, rstep = 256 / cw;
+    const int64_t c = blockIdx.x * (int64_t)cw + (threadIdx.x % cw);
     const int64_t j0 = (int64_t)blockIdx.y * 64;
     if (c >= k) return;
     const int32_t par = cs.par[c];
@@ -794,9 +819,10 @@ __global__ void k_copyout(const Ctrl *ctrl, ColState cs, const double *buf0, con
     for (int64_t jb = j0; jb < n; jb += (int64_t)gridDim.y * 64) {
         int64_t j1 = jb + 64;
         if (j1 > n) j1 = n;
-        for (int64_t j = jb; j < j1; ++j) z_out[j * ldz + c] = (par == PAR_UNIT) ? (j == i ? 1.0 : 0.0) : src[j * ldzb + c];
+        for (int64_t j = jb + rl; j < j1; j += rstep)
+            z_out[j * ldz + c] = (par == PAR_UNIT) ? (j == i ? 1.0 : 0.0) : src[j * ldzb + c];
     }
-    if (blockIdx.y == 0) {
+    if (blockIdx.y == 0 && rl == 0) {
         lambda_out[c] = cs.lam[c];
         const int32_t st = cs.state[c];
         status_out[c] = (st == COL_ACTIVE) ? IPT_NOT_CONVERGED : st;
@@ -922,7 +948,7 @@ hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, cons
                             const int32_t *col, const double *val, int64_t n, double *scratch) {
     k_zero_f64<<<blocks_for(2 * n, 256) < 2048 ? blocks_for(2 * n, 256) : 2048, 256, 0, s>>>(scratch, 2 * n);
     k_norm1_csr_part<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, row_ptr, col, val, n, scratch);
-    k_norm1_csr_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, theta, scratch, n);
+    k_norm1_csr_reduce<<<blocks_for(n, 256) < 512 ? blocks_for(n, 256) : 512, 256, 0, s>>>(ctrl, theta, scratch, n);
     return hipGetLastError();
 }
 
@@ -981,8 +1007,10 @@ hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const do
                           int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out, int64_t n,
                           int64_t k, const ipt_colinfo *ci) {
     const int gy = blocks_for(n, 64) < 65535 ? blocks_for(n, 64) : 65535;
-    dim3 g(blocks_for(k, 256), gy);
-    k_copyout<<<g, 256, 0, s>>>(ctrl, cs, buf0, buf1, ldzb, z_out, ldz, lambda_out, status_out, n, k,
+    int32_t cw = 1;
+    while (cw < 256 && cw < k) cw <<= 1;
+    dim3 g(blocks_for(k, cw), gy);
+    k_copyout<<<g, 256, 0, s>>>(ctrl, cs, buf0, buf1, ldzb, z_out, ldz, lambda_out, status_out, n, k, cw,
                                 ci ? ci->sweeps : nullptr, ci ? ci->step : nullptr, ci ? ci->resid : nullptr);
     return hipGetLastError();
 }

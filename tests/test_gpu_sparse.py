@@ -96,3 +96,45 @@ def test_sparse_invalid(ipt):
     with pytest.raises(ipt.IPTError) as e:
         _solve(ipt, th, rp2, col, val, [0, 1])
     assert e.value.status == ipt.IPT_EINVAL
+
+
+def _csr_from_dense(a):
+    rows, cols = np.nonzero(a)
+    rp = np.zeros(a.shape[0] + 1, dtype=np.int32)
+    np.add.at(rp, rows + 1, 1)
+    return np.cumsum(rp).astype(np.int32), cols.astype(np.int32), a[rows, cols].astype(np.float64)
+
+
+@pytest.mark.parametrize("kind", ["symmetric", "sign_flipped", "nonsymmetric", "long_row", "unsorted"])
+def test_csr_norm1_paths(ipt, kind):
+    """|M|_1 of a CSR input against the oracle's column sums on each path: |M|
+    symmetric (largest row sum; also with entries of flipped sign, since only |M_jc|
+    matters), not symmetric (scattered column sums), a row longer than the scan limit
+    (scattered sums) and unsorted column indices (the scan is linear: row sums)."""
+    say("csr norm1 %s" % kind)
+    rng = np.random.default_rng(11)
+    n = 700
+    a = np.zeros((n, n))
+    r = rng.integers(0, n, 4 * n)
+    c = rng.integers(0, n, 4 * n)
+    a[r, c] = rng.uniform(-0.05, 0.05, r.shape[0])
+    a = a + a.T
+    np.fill_diagonal(a, rng.uniform(-0.01, 0.01, n))
+    if kind == "sign_flipped":
+        a = np.triu(a) - np.tril(a, -1)
+    if kind == "nonsymmetric":
+        a[3, 7] = 0.4
+    if kind == "long_row":
+        a[5, :] = 0.001
+        a[:, 5] = 0.001
+        a[5, 5] = 0.3
+    th = np.arange(n, dtype=np.float64) * 1.0
+    rp, col, val = _csr_from_dense(a)
+    if kind == "unsorted":
+        for j in range(n):
+            s, e = rp[j], rp[j + 1]
+            col[s:e], val[s:e] = col[s:e][::-1].copy(), val[s:e][::-1].copy()
+    g = _solve(ipt, th, rp, col, val, np.array([0, 1], np.int32), tol=1e-10, max_iter=3)
+    want = np.max(np.sum(np.abs(np.diag(th) + a), axis=0))
+    assert abs(g.info["norm1"] - want) <= 1e-13 * want, (g.info["norm1"], want)
+    assert abs(oracle.norm1(th, csr=(rp, col, val)) - want) <= 1e-13 * want
