@@ -16,6 +16,7 @@ Contents
   (App. B, eq. RS-recursion), in NumPy.
 * ``acx_dense``: IPT with Alternating Cyclic Extrapolation (Alg. ACX) per column,
   in NumPy.
+* ``ipt_dense_z``: IPT over C^n (complex theta, Delta, z), in the C oracle.
 * ``ipt_dense_cont``: the non-autonomous continuation of the concluding discussion
   (the perturbation scaled by 1 - alpha^t at sweep t), in the C oracle.
 * ``norm1`` / ``eigen_residual``: the plain definitions used by the parity bounds.
@@ -73,6 +74,7 @@ def _load():
         lib.oracle_ipt_dense_acx.argtypes = lib.oracle_ipt_dense.argtypes
         lib.oracle_ipt_dense_cont.argtypes = [i64, p, p, i64, i64, p, p, i64, d, d, C.c_int, d, C.c_int,
                                               p, i64, p, p, p, p, p]
+        lib.oracle_ipt_dense_z.argtypes = lib.oracle_ipt_dense.argtypes
         lib.oracle_ipt_csr_acx.argtypes = lib.oracle_ipt_csr.argtypes
         lib.oracle_ipt_trace.argtypes = [i64, p, p, i64, i64, p, C.c_int, p]
         lib.oracle_ipt_map.argtypes = [i64, p, p, i64, i64, p, p]
@@ -172,6 +174,30 @@ def ipt_dense_cont(theta, delta, alpha, idx=None, z0=None, tol=1e-12, max_iter=D
     rc = _load().oracle_ipt_dense_cont(n, _ptr(theta), _ptr(delta), n, k, _ptr(idx), _ptr(z0), k, float(alpha), tol,
                                        max_iter, div_norm, div_growth, _ptr(z), k, _ptr(lam), _ptr(st), _ptr(sw),
                                        _ptr(stp), _ptr(res))
+    return _finish(rc, z, lam, st, sw, stp, res)
+
+
+def ipt_dense_z(theta, delta, idx=None, z0=None, tol=1e-12, max_iter=DEFAULT_MAX_ITER,
+                div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, resid=True) -> Result:
+    """IPT over C^n (Sec. 2 states the method for complex M): theta, delta, z0 complex
+    (numpy complex128, stored as (re, im) pairs); z and lam are complex.  Otherwise
+    as ipt_dense (Alg. 1 per requested column)."""
+    theta = np.ascontiguousarray(theta, dtype=np.complex128)
+    delta = np.ascontiguousarray(delta, dtype=np.complex128)
+    n = theta.shape[0]
+    assert delta.shape == (n, n)
+    if idx is None:
+        idx = np.arange(n, dtype=np.int32)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    k = idx.shape[0]
+    if z0 is not None:
+        z0 = np.ascontiguousarray(z0, dtype=np.complex128)
+        assert z0.shape == (n, k)
+    z = np.empty((n, k), np.complex128); lam = np.empty(k, np.complex128); st = np.empty(k, np.int32)
+    sw = np.empty(k, np.int32); stp = np.empty(k); res = np.empty(k) if resid else None
+    rc = _load().oracle_ipt_dense_z(n, _ptr(theta), _ptr(delta), n, k, _ptr(idx), _ptr(z0), k, tol, max_iter,
+                                    div_norm, div_growth, _ptr(z), k, _ptr(lam), _ptr(st), _ptr(sw), _ptr(stp),
+                                    _ptr(res))
     return _finish(rc, z, lam, st, sw, stp, res)
 
 

@@ -371,6 +371,120 @@ static int solve_columns(const op_t *A, const double *theta, int64_t k, const in
     return fail ? -1 : 0;
 }
 
+/* ---------------------------------------------------------- complex field */
+/* The paper states IPT over C^n (Sec. 2): theta, Delta and z complex, the same map
+ * f_i(z) = e_i + g_i o (z (Delta z)_i - Delta z), g_j = 1/(theta_j - theta_i), the same
+ * stopping test on the Euclidean norm of C^n and lambda_i = theta_i + (Delta z)_i.
+ * Arithmetic written out on (re, im) pairs: products (ac - bd, ad + bc), sums in
+ * ascending index order, 1/x by Smith's method (so a real input gives the real
+ * oracle's numbers bit for bit). */
+typedef struct {
+    double re, im;
+} cplx;
+
+static cplx c_mul(cplx a, cplx b) {
+    cplx r = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return r;
+}
+
+static cplx c_sub(cplx a, cplx b) {
+    cplx r = {a.re - b.re, a.im - b.im};
+    return r;
+}
+
+static cplx c_add(cplx a, cplx b) {
+    cplx r = {a.re + b.re, a.im + b.im};
+    return r;
+}
+
+static double c_abs2(cplx a) { return a.re * a.re + a.im * a.im; }
+
+/* 1/x (Smith): divide by the larger component first. */
+static cplx c_inv(cplx x) {
+    cplx r;
+    if (fabs(x.re) >= fabs(x.im)) {
+        const double q = x.im / x.re, den = x.re + x.im * q;
+        r.re = 1.0 / den;
+        r.im = -q / den;
+    } else {
+        const double q = x.re / x.im, den = x.im + x.re * q;
+        r.re = q / den;
+        r.im = -1.0 / den;
+    }
+    return r;
+}
+
+/* One column of complex IPT (solve_column over C^n). */
+static void solve_column_z(int64_t n, const cplx *theta, const cplx *delta, int64_t lda, int64_t i, double tol,
+                           int max_iter, double div_norm, int div_growth, cplx *z, cplx *g, cplx *y, cplx *w,
+                           cplx *lambda, int32_t *status, int32_t *sweeps, double *step) {
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) {
+            g[j].re = 0.0;
+            g[j].im = 0.0;
+        } else {
+            g[j] = c_inv(c_sub(theta[j], theta[i]));
+        }
+    }
+    z[i].re = 1.0;
+    z[i].im = 0.0;
+    double prev_s = INFINITY, s = INFINITY;
+    int grow = 0;
+    cplx d = {0.0, 0.0};
+    for (int t = 1; t <= max_iter; ++t) {
+        for (int64_t j = 0; j < n; ++j) {
+            const cplx *row = delta + j * lda;
+            cplx acc = {0.0, 0.0};
+            for (int64_t l = 0; l < n; ++l) acc = c_add(acc, c_mul(row[l], z[l]));
+            y[j] = acc;
+        }
+        d = y[i];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) {
+                w[j].re = 1.0;
+                w[j].im = 0.0;
+            } else {
+                w[j] = c_mul(g[j], c_sub(c_mul(z[j], d), y[j]));
+            }
+        }
+        double num = 0.0, den = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            num += c_abs2(c_sub(w[j], z[j]));
+            den += c_abs2(z[j]);
+        }
+        s = sqrt(num) / sqrt(den);
+        if (s <= tol) {
+            *lambda = c_add(theta[i], d);
+            *status = OR_CONVERGED;
+            *sweeps = t;
+            *step = s;
+            return;
+        }
+        int finite = isfinite(s);
+        double dist2 = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            cplx e = w[j];
+            if (j == i) e.re -= 1.0;
+            if (!isfinite(w[j].re) || !isfinite(w[j].im)) finite = 0;
+            dist2 += c_abs2(e);
+        }
+        grow = (s > prev_s) ? grow + 1 : 0;
+        prev_s = s;
+        memcpy(z, w, (size_t)n * sizeof(cplx));
+        if (!finite || !(sqrt(dist2) <= div_norm) || grow >= div_growth) {
+            *lambda = c_add(theta[i], d);
+            *status = OR_DIVERGED;
+            *sweeps = t;
+            *step = s;
+            return;
+        }
+    }
+    *lambda = c_add(theta[i], d);
+    *status = OR_NOT_CONVERGED;
+    *sweeps = max_iter;
+    *step = s;
+}
+
 /* ---------------------------------------------------------------- public */
 
 void oracle_set_threads(int nthreads) {
@@ -494,4 +608,62 @@ int oracle_ipt_batched(int32_t count, const int32_t *ns, const int64_t *theta_of
         if (rc) return rc;
     }
     return 0;
+}
+
+/* Complex dense IPT (solve_column_z per requested column).  theta: n complex,
+ * Delta: n x n row-major complex (lda complex elements), z0 / z_out: n x k row-major
+ * complex; complex numbers are (re, im) pairs of doubles.  Otherwise as
+ * oracle_ipt_dense (resid_out: |M z - lambda z| / |z|). */
+int oracle_ipt_dense_z(int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                       const int32_t *idx, const double *z0, int64_t ldz0, double tol, int max_iter, double div_norm,
+                       int div_growth, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
+                       int32_t *sweeps_out, double *step_out, double *resid_out) {
+    const cplx *th = (const cplx *)theta, *A = (const cplx *)delta, *Z0 = (const cplx *)z0;
+    cplx *Zo = (cplx *)z_out, *L = (cplx *)lambda_out;
+    int fail = 0;
+#pragma omp parallel
+    {
+        cplx *buf = (cplx *)malloc((size_t)n * 4 * sizeof(cplx));
+        if (!buf) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+            cplx *z = buf, *g = buf + n, *y = buf + 2 * n, *w = buf + 3 * n;
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t c = 0; c < k; ++c) {
+                const int64_t i = idx ? idx[c] : c;
+                for (int64_t j = 0; j < n; ++j) {
+                    if (Z0) {
+                        z[j] = Z0[j * ldz0 + c];
+                    } else {
+                        z[j].re = (j == i) ? 1.0 : 0.0;
+                        z[j].im = 0.0;
+                    }
+                }
+                cplx lam;
+                int32_t stat, sw;
+                double st;
+                solve_column_z(n, th, A, lda, i, tol, max_iter, div_norm, div_growth, z, g, y, w, &lam, &stat, &sw,
+                               &st);
+                for (int64_t j = 0; j < n; ++j) Zo[j * ldz + c] = z[j];
+                L[c] = lam;
+                status_out[c] = stat;
+                if (sweeps_out) sweeps_out[c] = sw;
+                if (step_out) step_out[c] = st;
+                if (resid_out) {
+                    double r2 = 0.0, z2 = 0.0;
+                    for (int64_t j = 0; j < n; ++j) {
+                        cplx acc = {0.0, 0.0};
+                        for (int64_t l = 0; l < n; ++l) acc = c_add(acc, c_mul(A[j * lda + l], z[l]));
+                        const cplx r = c_sub(c_add(c_mul(th[j], z[j]), acc), c_mul(lam, z[j]));
+                        r2 += c_abs2(r);
+                        z2 += c_abs2(z[j]);
+                    }
+                    resid_out[c] = sqrt(r2) / sqrt(z2);
+                }
+            }
+            free(buf);
+        }
+    }
+    return fail ? -1 : 0;
 }

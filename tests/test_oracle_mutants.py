@@ -98,10 +98,33 @@ CONT_MUTANTS = {
 }
 
 
+# Complex field: mistakes caught by the pins of test_oracle_complex
+COMPLEX_MUTANTS = {
+    "complex_product_conjugated": ("cplx r = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};",
+                                   "cplx r = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};"),
+    "complex_inverse_sign": ("        r.re = 1.0 / den;\n        r.im = -q / den;", "        r.re = 1.0 / den;\n        r.im = q / den;"),
+    "complex_dropped_imaginary_product": ("acc = c_add(acc, c_mul(row[l], z[l]));",
+                                          "acc = c_add(acc, (cplx){row[l].re * z[l].re, row[l].im * z[l].im});"),
+}
+
+
 def test_unmodified_oracle_passes():
     assert _pins_pass()
     from test_oracle_cont import cont_pins_pass
     assert cont_pins_pass()
+    from test_oracle_complex import complex_pins_pass
+    assert complex_pins_pass()
+
+
+@pytest.mark.parametrize("name", sorted(COMPLEX_MUTANTS))
+def test_planted_complex_mistake_is_caught(tmp_path, name):
+    from test_oracle_complex import complex_pins_pass
+    so = _build_mutant(tmp_path, *COMPLEX_MUTANTS[name])
+    prev = oracle.swap_library(so)
+    try:
+        assert not complex_pins_pass(), "mistake %s went unnoticed" % name
+    finally:
+        oracle.swap_library(prev)
 
 
 def _build_mutant(tmp_path, old, new):
