@@ -210,6 +210,27 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
                            const ipt_colinfo *ci);
 
 /*
+ * Dense solve over C^n (Sec. 2 states IPT for complex M: the same map, the stopping
+ * test on the Euclidean norm of C^n, lambda = theta_i + (Delta z)_i).
+ *   theta      [n] complex, finite; delta n x n complex row-major (lda >= n complex elements)
+ *   z0         optional n x k complex warm start (ldz0 >= k); entry idx[c] of column c is
+ *              taken as 1 + 0i
+ *   z_out      n x k complex (ldz >= k); lambda_out [k] complex
+ * A complex number is a (re, im) pair of doubles (the layout of C99 double complex,
+ * std::complex<double> and torch.complex128); theta, delta, z0, z_out and lambda_out
+ * must be 16-byte aligned.  n, k, idx, col_status, info and ci as for ipt_solve_dense;
+ * |M|_1 and the eigen-residual use the modulus.  Every sweep is an FP64 product sweep
+ * (four real matrix-core products; the first sweep of a cold start too, Delta E
+ * being exact): opts.precision must be IPT_PREC_FP64, and IPT_FLAG_ACX,
+ * IPT_FLAG_CHOOSE_D and opts.cont_alpha are rejected with IPT_EINVAL.
+ * IPT_EDEGENERATE when theta_j == theta_i (both parts) for a requested i and j != i.
+ */
+ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda,
+                             int64_t k, const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts *opts,
+                             double *z_out, int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info,
+                             const ipt_colinfo *ci);
+
+/*
  * Sparse solve with Delta in CSR form (few eigenpairs of a sparse near-diagonal M,
  * Sec. 6.1): row_ptr [n+1] int32 (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz),
  * col [nnz] int32 in [0, n), val [nnz] FP64.  Duplicate entries are summed.  Other

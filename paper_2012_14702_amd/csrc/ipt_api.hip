@@ -750,6 +750,106 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     return finish(h, ctrl, k, info, &timer);
 }
 
+ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda,
+                             int64_t k, const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts *opts,
+                             double *z_out, int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info,
+                             const ipt_colinfo *ci) {
+    if (!h) return IPT_EINVAL;
+    h->last_error.clear();
+    if (n < 1 || n > (int64_t(1) << 20)) return fail(h, IPT_EINVAL, "n must be in [1, 2^20]");
+    if (k < 1 || k > n) return fail(h, IPT_EINVAL, "k must be in [1, n]");
+    if (lda < n) return fail(h, IPT_EINVAL, "lda must be >= n");
+    if (ldz < k) return fail(h, IPT_EINVAL, "ldz must be >= k");
+    if (z0 && ldz0 < k) return fail(h, IPT_EINVAL, "ldz0 must be >= k");
+    if (!theta || !delta || !z_out || !lambda_out || !col_status)
+        return fail(h, IPT_EINVAL, "theta, delta, z_out, lambda_out and col_status must be non-NULL");
+    if ((((uintptr_t)theta | (uintptr_t)delta | (uintptr_t)z_out | (uintptr_t)lambda_out | (uintptr_t)z0) & 15) != 0)
+        return fail(h, IPT_EINVAL, "complex arrays must be 16-byte aligned");
+    ipt_opts o;
+    if (ipt_status st = check_opts(h, opts, o)) return st;
+    if (o.precision != IPT_PREC_FP64 || (o.flags & (IPT_FLAG_ACX | IPT_FLAG_CHOOSE_D)) || o.cont_alpha > 0.0)
+        return fail(h, IPT_EINVAL, "complex solves run plain FP64 sweeps (no ladder, ACX, choice of D or continuation)");
+    const DevOpts dopt = dev_opts(o);
+    DeviceGuard guard(h->device);
+    hipStream_t s = h->stream;
+
+    const int64_t zt = zsweep_tile();
+    const int64_t np = round_up(n, zt), kp = round_up(k, TILE_N);
+    const int64_t nrt = np / zt, ntn = kp / TILE_N;
+    const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
+    auto layout = [&](Carve &cv, double **zb, ColState &cs, double **d_re, double **d_im, double **lam_im,
+                      double **th_re, double **th_im, double **part, double **part2, uint32_t **bitmap, Ctrl **ctrl) {
+        zb[0] = cv.take<double>(2 * np * kp);
+        zb[1] = cv.take<double>(2 * np * kp);
+        *d_re = cv.take<double>(kp);
+        *d_im = cv.take<double>(kp);
+        *lam_im = cv.take<double>(kp);
+        *th_re = cv.take<double>(n);
+        *th_im = cv.take<double>(n);
+        *part = cv.take<double>(nrt * kp * NPART);
+        *part2 = norm ? cv.take<double>(zsetup_part2_doubles(n)) : nullptr;
+        cs.state = cv.take<int32_t>(kp);
+        cs.sweeps = cv.take<int32_t>(kp);
+        cs.grow = cv.take<int32_t>(kp);
+        cs.par = cv.take<int32_t>(kp);
+        cs.idx = cv.take<int32_t>(kp);
+        cs.tile_stamp = cv.take<int32_t>(ntn < kp ? kp : ntn);
+        cs.alist = cv.take<int32_t>(kp);
+        cs.prev = cv.take<double>(kp);
+        cs.step = cv.take<double>(kp);
+        cs.lam = cv.take<double>(kp);
+        cs.resid = cv.take<double>(kp);
+        *bitmap = cv.take<uint32_t>((n + 31) / 32);
+        *ctrl = cv.take<Ctrl>(1);
+    };
+    double *zb[2], *d_re, *d_im, *lam_im, *th_re, *th_im, *part, *part2;
+    ColState cs;
+    uint32_t *bitmap;
+    Ctrl *ctrl;
+    Carve sizing;
+    layout(sizing, zb, cs, &d_re, &d_im, &lam_im, &th_re, &th_im, &part, &part2, &bitmap, &ctrl);
+    if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
+    Carve cv;
+    cv.base = (char *)h->ws;
+    layout(cv, zb, cs, &d_re, &d_im, &lam_im, &th_re, &th_im, &part, &part2, &bitmap, &ctrl);
+
+    Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
+    IPT_HIP(h, timer.ensure());
+    IPT_HIP(h, hipEventRecord(h->ev_start, s));
+    // every sweep, the first of a cold start included, is a product sweep (Delta E is
+    // exact in FP64)
+    IPT_HIP(h, launch_ctrl_init(s, ctrl, PREC_F64, k));
+    IPT_HIP(h, launch_zsetup(s, ctrl, theta, delta, lda, th_re, th_im, part2, n));
+    IPT_HIP(h, launch_init_cols(s, ctrl, cs, idx, n, k, kp, bitmap, (int32_t)ntn, 0));
+    IPT_HIP(h, launch_zcheck_gaps(s, ctrl, th_re, th_im, cs.idx, n, k));
+    IPT_HIP(h, launch_plan_dense(s, ctrl, cs, kp));
+    IPT_HIP(h, launch_zload(s, ctrl, z0, ldz0, zb[0], kp, cs.idx, n, np, k));
+    IPT_HIP(h, launch_zload(s, ctrl, nullptr, 0, zb[1], kp, cs.idx, n, np, k));
+
+    const PollPlan plan = poll_plan(o, false);
+    if (ipt_status st = ensure_poll(h)) return st;
+    LookaheadPoll poll{h, ctrl};
+    for (int32_t t = 1; t <= o.max_iter; ++t) {
+        const int32_t in_par = (t - 1) & 1, out_par = t & 1;
+        const double *zin = zb[(t - 1) & 1];
+        double *zout = zb[t & 1];
+        IPT_HIP(h, launch_zdiag(s, ctrl, delta, lda, zin, kp, cs, d_re, d_im, n));
+        IPT_HIP(h, timer.mark(t, 0, s));
+        IPT_HIP(h, launch_zsweep(s, ctrl, delta, lda, th_re, th_im, zin, zout, cs, d_re, d_im, part, n, np, kp));
+        IPT_HIP(h, timer.mark(t, 1, s));
+        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, d_re, th_re, part, nrt, kp, t, in_par, out_par, nullptr, th_im,
+                                   d_im, lam_im));
+        IPT_HIP(h, launch_control_plan(s, ctrl, dopt, t, cs, kp));
+        if (plan.at(t, o.max_iter)) {
+            bool stop;
+            if (ipt_status st = poll.push(stop)) return st;
+            if (stop) break;
+        }
+    }
+    IPT_HIP(h, launch_zcopyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lam_im, lambda_out, col_status, n, k, ci));
+    return finish(h, ctrl, k, info, &timer);
+}
+
 ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int32_t *row_ptr, const int32_t *col,
                          const double *val, int64_t nnz, int64_t k, const int32_t *idx, const double *z0, int64_t ldz0,
                          const ipt_opts *opts, double *z_out, int64_t ldz, double *lambda_out, int32_t *col_status,

@@ -151,9 +151,12 @@ hipError_t launch_diag_dense(hipStream_t s, const Ctrl *ctrl, const double *delt
 // dnp: NULL, or the nrt x kp partials of the next sweep's d from the sweep's
 // epilogue; the finalize then writes dvec[c] = their sum for the columns that stay
 // active (after reading this sweep's d).
+// theta_im, dvec_im, lam_im: complex solves (theta, dvec the real parts), else NULL.
 hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, double *dvec,
                            const double *theta, const double *part, int64_t nrt, int64_t kp, int32_t sweep,
-                           int32_t in_par, int32_t out_par, const double *dnp = nullptr);
+                           int32_t in_par, int32_t out_par, const double *dnp = nullptr,
+                           const double *theta_im = nullptr, const double *dvec_im = nullptr,
+                           double *lam_im = nullptr);
 hipError_t launch_control(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep);
 hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
                           int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
@@ -294,5 +297,25 @@ struct SplitBounds {
 };
 SplitBounds split_bounds(int64_t np, int64_t kp, int nblk);
 
+
+
+// ---------------------------------------------------------- complex (ipt_complex.hip)
+// Dense IPT over C^n; complex arrays are (re, im) pairs of doubles.
+hipError_t launch_zsetup(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
+                         double *th_re, double *th_im, double *part2, int64_t n);
+int64_t zsetup_part2_doubles(int64_t n);
+hipError_t launch_zcheck_gaps(hipStream_t s, Ctrl *ctrl, const double *th_re, const double *th_im, const int32_t *idx,
+                              int64_t n, int64_t k);
+hipError_t launch_zload(hipStream_t s, const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t kp,
+                        const int32_t *idx, int64_t n, int64_t np, int64_t k);
+hipError_t launch_zdiag(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
+                        int64_t kp, ColState cs, double *d_re, double *d_im, int64_t n);
+int64_t zsweep_tile();
+hipError_t launch_zsweep(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *th_re,
+                         const double *th_im, const double *zin, double *zout, ColState cs, const double *d_re,
+                         const double *d_im, double *part, int64_t n, int64_t np, int64_t kp);
+hipError_t launch_zcopyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
+                           int64_t kp, double *z_out, int64_t ldz, const double *lam_im, double *lambda_out,
+                           int32_t *status_out, int64_t n, int64_t k, const ipt_colinfo *ci);
 
 }  // namespace ipt

@@ -581,7 +581,8 @@ __device__ inline void block_atomic_max(uint64_t *p, uint64_t v) {
 // Block: 64 columns; thread (cx, g) sums row tiles g, g + 4, ...; wave 0 decides.
 __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColState cs, double *dvec,
                                                   const double *theta, const double *part, int64_t nrt, int64_t kp,
-                                                  int32_t sweep, int32_t in_par, int32_t out_par, const double *dnp) {
+                                                  int32_t sweep, int32_t in_par, int32_t out_par, const double *dnp,
+                                                  const double *theta_im, const double *dvec_im, double *lam_im) {
     if (ctrl->error || ctrl->done) return;
     __shared__ double sh[4][NPART + 1][64];
     const int cx = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -660,6 +661,7 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
             cs.sweeps[c] = sweep;
             cs.step[c] = s;
             cs.lam[c] = theta[i] + (scaled ? es * d : d);
+            if (lam_im) lam_im[c] = theta_im[i] + (scaled ? es * dvec_im[c] : dvec_im[c]);  // complex solves
             cs.resid[c] = resid;
         } else {
             cs.tile_stamp[c / TILE_N] = sweep;
@@ -987,9 +989,10 @@ hipError_t launch_diag_dense(hipStream_t s, const Ctrl *ctrl, const double *delt
 
 hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, double *dvec,
                            const double *theta, const double *part, int64_t nrt, int64_t kp, int32_t sweep,
-                           int32_t in_par, int32_t out_par, const double *dnp) {
+                           int32_t in_par, int32_t out_par, const double *dnp, const double *theta_im,
+                           const double *dvec_im, double *lam_im) {
     k_finalize<<<(unsigned)(kp / 64), 256, 0, s>>>(ctrl, o, cs, dvec, theta, part, nrt, kp, sweep, in_par, out_par,
-                                                     dnp);
+                                                     dnp, theta_im, dvec_im, lam_im);
     return hipGetLastError();
 }
 

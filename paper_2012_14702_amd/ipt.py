@@ -105,6 +105,8 @@ def load_library():
     lib.ipt_set_stream.argtypes = [p, p]
     lib.ipt_solve_dense.argtypes = [p, i64, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
                                     C.POINTER(Info), C.POINTER(ColInfo)]
+    lib.ipt_solve_dense_z.argtypes = [p, i64, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
+                                    C.POINTER(Info), C.POINTER(ColInfo)]
     lib.ipt_solve_csr.argtypes = [p, i64, p, p, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
                                   C.POINTER(Info), C.POINTER(ColInfo)]
     lib.ipt_solve_batched.argtypes = [p, i32, p, p, p, p, p, p, C.POINTER(Opts), p, p, p, C.POINTER(Info)]
@@ -115,7 +117,7 @@ def load_library():
     lib.ipt_status_string.restype = C.c_char_p
     lib.ipt_last_error.argtypes = [p]
     lib.ipt_last_error.restype = C.c_char_p
-    for fn in ("ipt_create", "ipt_destroy", "ipt_set_stream", "ipt_solve_dense", "ipt_solve_csr",
+    for fn in ("ipt_create", "ipt_destroy", "ipt_set_stream", "ipt_solve_dense", "ipt_solve_dense_z", "ipt_solve_csr",
                "ipt_solve_batched", "ipt_batched_tune", "ipt_batched_get_tiles", "ipt_batched_set_tiles"):
         getattr(lib, fn).restype = C.c_int
     _lib = lib
@@ -256,6 +258,39 @@ def ipt_solve_dense(theta, delta, idx=None, z0=None, opts=None, handle=None, col
     st = lib.ipt_solve_dense(h.ptr, n, _ptr(theta), _ptr(delta), delta.stride(0), k, _ptr(idx), _ptr(z0),
                              z0.stride(0) if z0 is not None else 0, C.byref(o), _ptr(z_out), z_out.stride(0),
                              _ptr(lam), _ptr(status), C.byref(info), C.byref(ci) if ci is not None else None)
+    return _finish(lib, h, st, z_out, lam, status, info, extra)
+
+
+def ipt_solve_dense_z(theta, delta, idx=None, z0=None, opts=None, handle=None, colinfo=True, z_out=None, **kw):
+    """Dense IPT over C^n (ipt_solve_dense_z).  theta [n], delta [n, n] (row-major,
+    row stride = lda) and z0 [n, k] complex128; idx [k] int32 or None.  Returns a
+    Result with z [n, k] and lam [k] complex128, status [k] and info."""
+    import torch
+    lib = load_library()
+    h = _handle(handle)
+    _check(theta, torch.complex128, "theta")
+    _check(delta, torch.complex128, "delta")
+    _check(idx, torch.int32, "idx")
+    _check(z0, torch.complex128, "z0")
+    n = theta.shape[0]
+    if theta.dim() != 1 or theta.stride(0) != 1:
+        raise ValueError("theta must be a contiguous vector")
+    if delta.dim() != 2 or delta.shape[0] != n or delta.shape[1] != n or delta.stride(1) != 1:
+        raise ValueError("delta must be n x n with unit column stride")
+    k = n if idx is None else idx.shape[0]
+    if z0 is not None and (z0.dim() != 2 or z0.shape[0] != n or z0.shape[1] != k or z0.stride(1) != 1):
+        raise ValueError("z0 must be n x k with unit column stride")
+    dev = theta.device
+    if z_out is None:
+        z_out = torch.empty((n, k), dtype=torch.complex128, device=dev)
+    lam = torch.empty(k, dtype=torch.complex128, device=dev)
+    status = torch.empty(k, dtype=torch.int32, device=dev)
+    o = _opts(opts, kw)
+    info = Info()
+    ci, extra = _colinfo(k, colinfo)
+    st = lib.ipt_solve_dense_z(h.ptr, n, _ptr(theta), _ptr(delta), delta.stride(0), k, _ptr(idx), _ptr(z0),
+                               z0.stride(0) if z0 is not None else 0, C.byref(o), _ptr(z_out), z_out.stride(0),
+                               _ptr(lam), _ptr(status), C.byref(info), C.byref(ci) if ci is not None else None)
     return _finish(lib, h, st, z_out, lam, status, info, extra)
 
 
