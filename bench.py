@@ -275,6 +275,38 @@ def bench_continuation(ipt, handle, args):
             "dense": dense}
 
 
+def bench_complex(ipt, handle, args):
+    """Dense IPT over C^n (ipt_solve_dense_z): M = diag(1..n) + Delta, Delta = eps (A + A^H)/2
+    with A iid complex Gaussian (variance 1/n), full spectrum, tol 1e-10, FP64 sweeps
+    (four real matrix-core products per complex product)."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    n = args.complex_n
+    rng = np.random.default_rng(0)
+    a = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    de = torch.from_numpy(args.eps * (a + a.conj().T) / 2).to(dev)
+    del a
+    th = torch.from_numpy(np.arange(1, n + 1).astype(np.complex128)).to(dev)
+    o = ipt.default_opts(tol=1e-10, precision=ipt.PREC_FP64, flags=ipt.FLAG_TIME_KERNELS)
+    run = lambda: ipt.ipt_solve_dense_z(th, de, opts=o, handle=handle, colinfo=False)
+    _time(run, 1)
+    sec, r = _time(run, 3)
+    inf = r.info
+    ms = inf["prec_ms"]["fp64"]
+    act = inf["sweep_active"]
+    flops = sum(8.0 * n * n * a_ for a_ in act)  # four real products of 2 n^2 per active column
+    tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    log("complex n=%d: %.2f ms/solve, %d sweeps, %d converged, product %.1f TFLOP/s" % (
+        n, sec * 1e3, inf["sweeps"], inf["converged"], tf))
+    return {"workload": "complex Hermitian n=%d, theta=1..n, Delta=eps*(A+A^H)/2, A iid CN(0,1/n) seed 0, eps=%g, "
+                        "full spectrum, tol 1e-10, FP64 sweeps" % (n, args.eps),
+            "ms_per_solve": round(sec * 1e3, 3), "eigenpairs_per_s": round(inf["converged"] / sec, 1),
+            "converged": inf["converged"], "sweeps": inf["sweeps"], "sweep_active": act,
+            "product_ms": round(ms, 3), "product_tflops": round(tf, 2),
+            "product_frac_of_fp64_peak": round(tf / PEAK["fp64"], 4)}
+
+
 def bench_learned(ipt, handle, args):
     """Learned warm start: M(eps) = diag(1..1024) + eps R, R = (R'+R'^T)/2, R' iid N(0,1/n)
     seed 0, k = 32 lowest; the network is trained on 512 eps ~ U[0, 0.08] (seed 1) and
@@ -349,9 +381,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "ladder", "ladder_fp32_mma", "fp64"], default="all",
                     help="restrict the dense workload to one mode (for profiler runs)")
-    ap.add_argument("--extra", default="sparse,morgan,batched,learned,continuation",
+    ap.add_argument("--extra", default="sparse,morgan,batched,learned,continuation,complex",
                     help="comma list of secondary workloads to time: sparse, morgan, batched, learned, "
-                         "continuation ('' for none)")
+                         "continuation, complex ('' for none)")
+    ap.add_argument("--complex-n", type=int, default=4096, help="size of the complex workload")
     ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the warm-start network")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense workload (profiling of the others)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -391,7 +424,8 @@ def main():
         extras = [e for e in args.extra.split(",") if e]
         out = {}
         for name, fn in (("sparse", bench_sparse), ("morgan", bench_morgan), ("batched", bench_batched),
-                         ("learned", bench_learned), ("continuation", bench_continuation)):
+                         ("learned", bench_learned), ("continuation", bench_continuation),
+                         ("complex", bench_complex)):
             if name in extras:
                 out[name] = fn(ipt, handle, args)
         print(json.dumps(out), flush=True)
@@ -507,6 +541,8 @@ def main():
         out["learned"] = bench_learned(ipt, handle, args)
     if "continuation" in extras:
         out["continuation"] = bench_continuation(ipt, handle, args)
+    if "complex" in extras:
+        out["complex"] = bench_complex(ipt, handle, args)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
         th, de = host[args.eps]

@@ -777,12 +777,14 @@ ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const
     const int64_t np = round_up(n, zt), kp = round_up(k, TILE_N);
     const int64_t nrt = np / zt, ntn = kp / TILE_N;
     const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
-    auto layout = [&](Carve &cv, double **zb, ColState &cs, double **d_re, double **d_im, double **lam_im,
-                      double **th_re, double **th_im, double **part, double **part2, uint32_t **bitmap, Ctrl **ctrl) {
+    auto layout = [&](Carve &cv, double **zb, ColState &cs, double **d_re, double **d_im, double **dpart,
+                      double **lam_im, double **th_re, double **th_im, double **part, double **part2,
+                      uint32_t **bitmap, Ctrl **ctrl) {
         zb[0] = cv.take<double>(2 * np * kp);
         zb[1] = cv.take<double>(2 * np * kp);
         *d_re = cv.take<double>(kp);
         *d_im = cv.take<double>(kp);
+        *dpart = cv.take<double>(zdiag_part_doubles(kp));
         *lam_im = cv.take<double>(kp);
         *th_re = cv.take<double>(n);
         *th_im = cv.take<double>(n);
@@ -802,16 +804,16 @@ ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const
         *bitmap = cv.take<uint32_t>((n + 31) / 32);
         *ctrl = cv.take<Ctrl>(1);
     };
-    double *zb[2], *d_re, *d_im, *lam_im, *th_re, *th_im, *part, *part2;
+    double *zb[2], *d_re, *d_im, *dpart, *lam_im, *th_re, *th_im, *part, *part2;
     ColState cs;
     uint32_t *bitmap;
     Ctrl *ctrl;
     Carve sizing;
-    layout(sizing, zb, cs, &d_re, &d_im, &lam_im, &th_re, &th_im, &part, &part2, &bitmap, &ctrl);
+    layout(sizing, zb, cs, &d_re, &d_im, &dpart, &lam_im, &th_re, &th_im, &part, &part2, &bitmap, &ctrl);
     if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
     Carve cv;
     cv.base = (char *)h->ws;
-    layout(cv, zb, cs, &d_re, &d_im, &lam_im, &th_re, &th_im, &part, &part2, &bitmap, &ctrl);
+    layout(cv, zb, cs, &d_re, &d_im, &dpart, &lam_im, &th_re, &th_im, &part, &part2, &bitmap, &ctrl);
 
     Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
     IPT_HIP(h, timer.ensure());
@@ -833,7 +835,7 @@ ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const
         const int32_t in_par = (t - 1) & 1, out_par = t & 1;
         const double *zin = zb[(t - 1) & 1];
         double *zout = zb[t & 1];
-        IPT_HIP(h, launch_zdiag(s, ctrl, delta, lda, zin, kp, cs, d_re, d_im, n));
+        IPT_HIP(h, launch_zdiag(s, ctrl, delta, lda, zin, kp, cs, dpart, d_re, d_im, n));
         IPT_HIP(h, timer.mark(t, 0, s));
         IPT_HIP(h, launch_zsweep(s, ctrl, delta, lda, th_re, th_im, zin, zout, cs, d_re, d_im, part, n, np, kp));
         IPT_HIP(h, timer.mark(t, 1, s));

@@ -223,20 +223,27 @@ __global__ __launch_bounds__(256, 2) void k_zsweep(const Ctrl *ctrl, ZArgs g) {
     }
 }
 
-// d_c = (Delta Z)_{i,c} for the active columns: block = 64 columns x 4 row lanes,
-// lane g sums rows g, g + 4, ...; the lanes are added in order.
-__global__ __launch_bounds__(256) void k_zdiag(const Ctrl *ctrl, const double2 *delta, int64_t lda,
-                                               const double2 *zin, int64_t kp, ColState cs, double *d_re,
-                                               double *d_im, int64_t n) {
+// d_c = (Delta Z)_{i,c} for the active columns, in two passes: per chunk of rows,
+// block = 64 columns x 4 row lanes (lane g sums rows g, g + 4, ... of the chunk, the
+// lanes added in order) into dpart[chunk][c]; then the chunks in order.
+constexpr int ZDCH = 16;
+
+__global__ __launch_bounds__(256) void k_zdiag_part(const Ctrl *ctrl, const double2 *delta, int64_t lda,
+                                                    const double2 *zin, int64_t kp, ColState cs, double2 *dpart,
+                                                    int64_t n) {
     if (ctrl->error || ctrl->done) return;
     __shared__ double2 sh[4][64];
     const int cx = threadIdx.x & 63, gr = threadIdx.x >> 6;
     const int64_t c = (int64_t)blockIdx.x * 64 + cx;
     const bool act = c < kp && cs.state[c] == COL_ACTIVE;
+    const int64_t per = (n + ZDCH - 1) / ZDCH;
+    const int64_t j0 = (int64_t)blockIdx.y * per;
+    int64_t j1 = j0 + per;
+    if (j1 > n) j1 = n;
     double2 acc{0.0, 0.0};
     if (act) {
         const double2 *row = delta + (int64_t)cs.idx[c] * lda;
-        for (int64_t j = gr; j < n; j += 4) {
+        for (int64_t j = j0 + gr; j < j1; j += 4) {
             const double2 p = cmul(row[j], zin[j * kp + c]);
             acc.x += p.x;
             acc.y += p.y;
@@ -244,10 +251,23 @@ __global__ __launch_bounds__(256) void k_zdiag(const Ctrl *ctrl, const double2 *
     }
     sh[gr][cx] = acc;
     __syncthreads();
-    if (gr == 0 && act) {
-        d_re[c] = ((sh[0][cx].x + sh[1][cx].x) + sh[2][cx].x) + sh[3][cx].x;
-        d_im[c] = ((sh[0][cx].y + sh[1][cx].y) + sh[2][cx].y) + sh[3][cx].y;
+    if (gr == 0 && act)
+        dpart[blockIdx.y * kp + c] = double2{((sh[0][cx].x + sh[1][cx].x) + sh[2][cx].x) + sh[3][cx].x,
+                                             ((sh[0][cx].y + sh[1][cx].y) + sh[2][cx].y) + sh[3][cx].y};
+}
+
+__global__ void k_zdiag_reduce(const Ctrl *ctrl, ColState cs, const double2 *dpart, double *d_re, double *d_im,
+                               int64_t kp) {
+    if (ctrl->error || ctrl->done) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= kp || cs.state[c] != COL_ACTIVE) return;
+    double re = 0.0, im = 0.0;
+    for (int q = 0; q < ZDCH; ++q) {
+        re += dpart[q * kp + c].x;
+        im += dpart[q * kp + c].y;
     }
+    d_re[c] = re;
+    d_im[c] = im;
 }
 
 // theta split into planes; a non-finite theta is IPT_EINVAL.
@@ -389,10 +409,13 @@ hipError_t launch_zload(hipStream_t s, const Ctrl *ctrl, const double *z0, int64
     return hipGetLastError();
 }
 
+int64_t zdiag_part_doubles(int64_t kp) { return 2 * (int64_t)ZDCH * kp; }
+
 hipError_t launch_zdiag(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
-                        int64_t kp, ColState cs, double *d_re, double *d_im, int64_t n) {
-    k_zdiag<<<zblocks(kp, 64), 256, 0, s>>>(ctrl, (const double2 *)delta, lda, (const double2 *)zin, kp, cs, d_re,
-                                              d_im, n);
+                        int64_t kp, ColState cs, double *dpart, double *d_re, double *d_im, int64_t n) {
+    k_zdiag_part<<<dim3(zblocks(kp, 64), ZDCH), 256, 0, s>>>(ctrl, (const double2 *)delta, lda,
+                                                              (const double2 *)zin, kp, cs, (double2 *)dpart, n);
+    k_zdiag_reduce<<<zblocks(kp, 256), 256, 0, s>>>(ctrl, cs, (const double2 *)dpart, d_re, d_im, kp);
     return hipGetLastError();
 }
 

@@ -308,8 +308,9 @@ hipError_t launch_zcheck_gaps(hipStream_t s, Ctrl *ctrl, const double *th_re, co
                               int64_t n, int64_t k);
 hipError_t launch_zload(hipStream_t s, const Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t kp,
                         const int32_t *idx, int64_t n, int64_t np, int64_t k);
+int64_t zdiag_part_doubles(int64_t kp);
 hipError_t launch_zdiag(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
-                        int64_t kp, ColState cs, double *d_re, double *d_im, int64_t n);
+                        int64_t kp, ColState cs, double *dpart, double *d_re, double *d_im, int64_t n);
 int64_t zsweep_tile();
 hipError_t launch_zsweep(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *th_re,
                          const double *th_im, const double *zin, double *zout, ColState cs, const double *d_re,
