@@ -1,5 +1,7 @@
 """Pins of the oracle's non-autonomous continuation (concluding discussion of the
-3 x 3 example): sweep t applies the map of the partition D + (1 - alpha^t) Delta.
+3 x 3 example): sweep t applies the map of the partition D + (1 - alpha^t) Delta;
+and of the homotopy restart (concluding section): stages D + (q/Q) Delta, each
+started from the previous stage's vectors.
 
 Each pin checks the oracle against something other than itself: closed forms of
 the first iterates, the eigen-decomposition of the paper's 3 x 3 matrix by the
@@ -135,3 +137,44 @@ def test_bad_alpha_rejected():
         except ValueError:
             continue
         raise AssertionError("alpha %r accepted" % a)
+
+
+# ---------------------------------------------------------------- homotopy restart
+
+def test_homotopy_rescues_three_by_three():
+    """The paper's 3 x 3 example at eps = -0.475, column 2: plain IPT diverges, the
+    homotopy restart with 2 stages (D + Delta/2, then D + Delta from its vectors)
+    reaches the eigenvector and eigenvalue given by the textbook decomposition."""
+    th, de, v, lam, rho = three_by_three_case()
+    idx = np.array([1], np.int32)
+    plain = oracle.ipt_dense(th, de, idx=idx, tol=1e-12, max_iter=2000, resid=False)
+    h = oracle.ipt_dense_homotopy(th, de, 2, idx=idx, tol=1e-12, max_iter=2000, resid=False)
+    assert plain.status[0] == oracle.DIVERGED and h.status[0] == oracle.CONVERGED
+    assert np.max(np.abs(h.z[:, 0] - v)) < 1e-9 and abs(h.lam[0] - lam) < 1e-10
+
+
+def test_homotopy_first_stage_is_the_scaled_problem():
+    """With 3 stages, stage 1 solves D + Delta/3: its vectors are the eigenvectors of
+    that matrix (eigh); the full restart ends at the eigenvectors of D + Delta."""
+    from jacobi_ref import cyclic_jacobi
+    th, de = W.dense_sym_gaussian(10, 0.3, 4)
+    th = th + 5.0
+    first = oracle.ipt_dense(th, de * (1.0 / 3.0), tol=1e-14, max_iter=500)
+    ev, vec = cyclic_jacobi(np.diag(th) + de / 3.0)
+    for col in range(10):
+        m = int(np.argmax(np.abs(vec[col, :])))
+        assert np.max(np.abs(first.z[:, col] - vec[:, m] / vec[col, m])) < 1e-11
+    h = oracle.ipt_dense_homotopy(th, de, 3, tol=1e-14, max_iter=500)
+    ev, vec = cyclic_jacobi(np.diag(th) + de)
+    for col in range(10):
+        m = int(np.argmax(np.abs(vec[col, :])))
+        assert np.max(np.abs(h.z[:, col] - vec[:, m] / vec[col, m])) < 1e-11
+        assert abs(h.lam[col] - ev[m]) < 1e-11
+    assert np.all(h.sweeps > oracle.ipt_dense(th, de, tol=1e-14, max_iter=500).sweeps)
+
+
+def test_homotopy_one_stage_is_plain():
+    th, de = _random_case(n=24, eps=0.2, seed=7)
+    p = oracle.ipt_dense(th, de, tol=1e-12)
+    h = oracle.ipt_dense_homotopy(th, de, 1, tol=1e-12)
+    assert np.array_equal(p.z, h.z) and np.array_equal(p.lam, h.lam) and np.array_equal(p.sweeps, h.sweeps)
