@@ -89,6 +89,13 @@ typedef struct ipt_opts {
                          * (or z0) along with the fixed point as the perturbation grows.
                          * Dense solves with precision = IPT_PREC_FP64 and without
                          * IPT_FLAG_ACX only; elsewhere IPT_EINVAL */
+    int32_t homotopy_q; /* 0 or 1 (default): one solve.  Q > 1 (at most 1000): the homotopy
+                         * restart of the concluding section, dense solves only: stages
+                         * q = 1..Q solve the partition D + (q/Q) Delta (each entry times the
+                         * FP64 number q/Q), each started from the previous stage's vectors
+                         * (the first from z0, or cold); the last stage is the problem
+                         * itself and gives the outputs and statuses.  info sums sweeps,
+                         * matvecs and time over the stages.  Not with cont_alpha */
 } ipt_opts;
 
 /* Skip |M|_1 (one extra pass over Delta) and report resid unnormalised. */

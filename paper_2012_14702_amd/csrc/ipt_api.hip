@@ -114,6 +114,9 @@ ipt_status check_opts(ipt_handle h, const ipt_opts *in, ipt_opts &o) {
         return fail(h, IPT_EINVAL, "opts.cont_alpha must be in [0, 1)");
     if (o.cont_alpha > 0.0 && (o.precision != IPT_PREC_FP64 || (o.flags & IPT_FLAG_ACX)))
         return fail(h, IPT_EINVAL, "opts.cont_alpha needs precision = IPT_PREC_FP64 and no IPT_FLAG_ACX");
+    if (o.homotopy_q < 0 || o.homotopy_q > 1000) return fail(h, IPT_EINVAL, "opts.homotopy_q must be in [0, 1000]");
+    if (o.homotopy_q > 1 && o.cont_alpha > 0.0)
+        return fail(h, IPT_EINVAL, "opts.homotopy_q and opts.cont_alpha do not combine");
     return IPT_OK;
 }
 
@@ -584,6 +587,58 @@ const char *ipt_status_string(ipt_status s) {
 
 const char *ipt_last_error(ipt_handle h) { return h ? h->last_error.c_str() : "invalid handle"; }
 
+// The homotopy restart (concluding section): stages q = 1..Q on a scaled copy of
+// Delta (the handle's second workspace), each a full dense solve started from the
+// previous stage's vectors; the last stage runs on Delta itself into the caller's
+// outputs.
+static ipt_status homotopy_dense(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                          const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts &o, double *z_out,
+                          int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info,
+                          const ipt_colinfo *ci) {
+    const int32_t Q = o.homotopy_q;
+    Carve sizing;
+    (void)sizing.take<double>(n * n);
+    (void)sizing.take<double>(n * k);
+    (void)sizing.take<double>(n * k);
+    if (ipt_status st = ensure_buf(h, h->pws, h->pws_bytes, sizing.off + 256)) return st;
+    Carve cv;
+    cv.base = (char *)h->pws;
+    double *dq = cv.take<double>(n * n);
+    double *zs[2] = {cv.take<double>(n * k), cv.take<double>(n * k)};
+    ipt_opts os = o;
+    os.homotopy_q = 0;
+    const double *zin = z0;
+    int64_t ldin = ldz0, sweeps = 0, matvecs = 0;
+    float ms = 0.f;
+    for (int32_t q = 1; q <= Q; ++q) {
+        const bool last = q == Q;
+        if (!last) {
+            DeviceGuard guard(h->device);
+            IPT_HIP(h, launch_scale_copy(h->stream, dq, delta, lda, n, (double)q / (double)Q));
+        }
+        double *zo = last ? z_out : zs[q & 1];
+        ipt_info inf;
+        const ipt_status st = ipt_solve_dense(h, n, theta, last ? delta : dq, last ? lda : n, k, idx, zin, ldin, &os,
+                                              zo, last ? ldz : k, lambda_out, col_status, &inf, last ? ci : nullptr);
+        if (st != IPT_OK && st != IPT_ENOTCONV) return st;
+        sweeps += inf.sweeps;
+        matvecs += inf.matvecs;
+        ms += inf.time_ms;
+        if (last) {
+            if (info) {
+                *info = inf;
+                info->sweeps = (int32_t)sweeps;
+                info->matvecs = matvecs;
+                info->time_ms = ms;
+            }
+            return st;
+        }
+        zin = zo;
+        ldin = k;
+    }
+    return IPT_OK;
+}
+
 ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
                            const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts *opts, double *z_out,
                            int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info,
@@ -599,6 +654,8 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         return fail(h, IPT_EINVAL, "theta, delta, z_out, lambda_out and col_status must be non-NULL");
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
+    if (o.homotopy_q > 1) return homotopy_dense(h, n, theta, delta, lda, k, idx, z0, ldz0, o, z_out, ldz, lambda_out,
+                                                col_status, info, ci);
     const DevOpts dopt = dev_opts(o);
     const bool ladder = dopt.ladder;
     const bool cold = (z0 == nullptr);
@@ -767,8 +824,10 @@ ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const
         return fail(h, IPT_EINVAL, "complex arrays must be 16-byte aligned");
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
-    if (o.precision != IPT_PREC_FP64 || (o.flags & (IPT_FLAG_ACX | IPT_FLAG_CHOOSE_D)) || o.cont_alpha > 0.0)
-        return fail(h, IPT_EINVAL, "complex solves run plain FP64 sweeps (no ladder, ACX, choice of D or continuation)");
+    if (o.precision != IPT_PREC_FP64 || (o.flags & (IPT_FLAG_ACX | IPT_FLAG_CHOOSE_D)) || o.cont_alpha > 0.0 ||
+        o.homotopy_q > 1)
+        return fail(h, IPT_EINVAL,
+                    "complex solves run plain FP64 sweeps (no ladder, ACX, choice of D, continuation or homotopy)");
     const DevOpts dopt = dev_opts(o);
     DeviceGuard guard(h->device);
     hipStream_t s = h->stream;
@@ -868,6 +927,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
     if (o.cont_alpha > 0.0) return fail(h, IPT_EINVAL, "opts.cont_alpha: continuation is for dense solves");
+    if (o.homotopy_q > 1) return fail(h, IPT_EINVAL, "opts.homotopy_q: the homotopy restart is for dense solves");
     DevOpts dopt = dev_opts(o);
     dopt.low_type = IPT_LOW_NONE;  // the sparse ladder runs FP32 then FP64 sweeps
     dopt.mid_x3 = 0;
@@ -980,7 +1040,7 @@ namespace {
 // IPT_FLAG_CHOOSE_D on a batch: copies of the pools (at the caller's offsets) are
 // re-partitioned (near-degenerate pairs rotated out, level shifts moved into D), the
 // batch is solved on them, and the eigenvectors are rotated back in z_pool.
-ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
+static ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
                          const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
                          const double *delta_pool, const ipt_opts &o, double *z_pool, double *lambda_pool,
                          int32_t *status_pool, ipt_info *info) {
@@ -1049,6 +1109,7 @@ ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, con
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
     if (o.cont_alpha > 0.0) return fail(h, IPT_EINVAL, "opts.cont_alpha: continuation is for dense solves");
+    if (o.homotopy_q > 1) return fail(h, IPT_EINVAL, "opts.homotopy_q: the homotopy restart is for dense solves");
     if (o.flags & IPT_FLAG_CHOOSE_D) {
         DeviceGuard guard(h->device);
         return batched_pairs(h, count, ns, theta_off, delta_off, z_off, theta_pool, delta_pool, o, z_pool,

@@ -115,6 +115,8 @@ hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64
 // unscaled partition; the continuation map is E + s (F(Z) - E), so the off-diagonal
 // entries of this sweep's active columns are multiplied by s in place.  Nothing is
 // done once s = 1.
+// dst = scale * Delta, n x n with leading dimension n (the homotopy restart's stages).
+hipError_t launch_scale_copy(hipStream_t s, double *dst, const double *src, int64_t lda, int64_t n, double scale);
 hipError_t launch_cont_blend(hipStream_t s, const Ctrl *ctrl, double *w, int64_t ldw, ColState cs, int64_t n,
                              int64_t kp);
 // Tile pairs of Delta over the padded np x np, after launch_prep_delta: want_sym

@@ -1042,6 +1042,22 @@ hipError_t launch_cont_blend(hipStream_t s, const Ctrl *ctrl, double *w, int64_t
     return hipGetLastError();
 }
 
+// dst = scale * Delta (n x n, leading dimension n), one product per entry.
+__global__ void k_scale_copy(double *dst, const double *src, int64_t lda, int64_t n, double scale) {
+    const int64_t total = n * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / n, l = e - j * n;
+        dst[e] = scale * src[j * lda + l];
+    }
+}
+
+hipError_t launch_scale_copy(hipStream_t s, double *dst, const double *src, int64_t lda, int64_t n, double scale) {
+    int b = blocks_for(n * n, 256);
+    if (b > 8192) b = 8192;
+    k_scale_copy<<<b, 256, 0, s>>>(dst, src, lda, n, scale);
+    return hipGetLastError();
+}
+
 hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
                          int64_t ldt, int64_t np, int64_t kp, int32_t low_type, int32_t mid_x3) {
     dim3 g((unsigned)(kp / 64), (unsigned)(np / 64));

@@ -33,7 +33,7 @@ class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("low_type", C.c_int32),
                 ("sync_every", C.c_int32), ("tau_low", C.c_double), ("tau_32", C.c_double),
                 ("div_norm", C.c_double), ("div_growth", C.c_int32), ("flags", C.c_int32),
-                ("cont_alpha", C.c_double)]
+                ("cont_alpha", C.c_double), ("homotopy_q", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -95,3 +95,58 @@ def test_continuation_rejected_elsewhere(ipt):
     with pytest.raises(ipt.IPTError) as e:
         ipt.ipt_solve_batched(ns, t(thb), t(deb), cont_alpha=0.5)
     assert e.value.status == ipt.IPT_EINVAL
+
+
+# ---------------------------------------------------------------- homotopy restart
+
+def test_homotopy_three_by_three(ipt):
+    """The homotopy restart (2 stages) on the paper's 3 x 3 example at eps = -0.475:
+    column 2, which plain IPT loses, converges; every column matches the oracle's
+    restart."""
+    say("homotopy 3x3 eps=-0.475 Q=2")
+    th, de = W.three_by_three(-0.475)
+    g = _solve(ipt, th, de, tol=1e-12, max_iter=2000, homotopy_q=2)
+    ref = oracle.ipt_dense_homotopy(th, de, 2, tol=1e-12, max_iter=2000)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12, max_iter=2000)
+    assert g.status[1] == ipt.CONVERGED
+    assert g.info["sweeps"] >= 2
+
+
+@pytest.mark.parametrize("n,k,q,prec", [(300, 300, 3, "fp64"), (257, 40, 2, "fp64"), (256, 256, 2, "ladder")])
+def test_homotopy_parity(ipt, n, k, q, prec):
+    """Stages on the scaled copies over ragged sizes, scattered columns and the
+    precision ladder inside each stage, against the oracle's restart."""
+    say("homotopy n=%d k=%d Q=%d %s" % (n, k, q, prec))
+    th, de = W.dense_sym_gaussian(n, 0.05, 3)
+    idx = None if k == n else np.sort(np.random.default_rng(5).choice(n, k, replace=False)).astype(np.int32)
+    p = ipt.PREC_LADDER if prec == "ladder" else ipt.PREC_FP64
+    g = _solve(ipt, th, de, idx=idx, tol=1e-10, precision=p, homotopy_q=q)
+    ref = oracle.ipt_dense_homotopy(th, de, q, idx=idx, tol=1e-10, resid=False)
+    out = check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-10)
+    assert out["compared"] == k
+
+
+def test_homotopy_warm_start_and_one_stage(ipt):
+    """A warm start feeds the first stage; one stage is the plain solve bit for bit."""
+    say("homotopy warm start n=200")
+    th, de = W.dense_sym_gaussian(200, 0.04, 8)
+    part = _solve(ipt, th, de, tol=1e-12, max_iter=2)
+    g = _solve(ipt, th, de, z0=part.z, tol=1e-12, homotopy_q=2)
+    ref = oracle.ipt_dense_homotopy(th, de, 2, z0=part.z, tol=1e-12, resid=False)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12)
+    p = _solve(ipt, th, de, tol=1e-12)
+    one = _solve(ipt, th, de, tol=1e-12, homotopy_q=1)
+    np.testing.assert_array_equal(p.z, one.z)
+    np.testing.assert_array_equal(p.lam, one.lam)
+
+
+def test_homotopy_rejected_elsewhere(ipt):
+    th, de = W.dense_sym_gaussian(16, 0.01, 0)
+    for kw in (dict(homotopy_q=2, cont_alpha=0.5), dict(homotopy_q=-1), dict(homotopy_q=1001)):
+        with pytest.raises(ipt.IPTError) as e:
+            _solve(ipt, th, de, **kw)
+        assert e.value.status == ipt.IPT_EINVAL, kw
+    th_s, rp, col, val = W.sparse_sym_uniform(64, 3, 0.05, 1)
+    with pytest.raises(ipt.IPTError) as e:
+        ipt.ipt_solve_csr(t(th_s), t(rp), t(col), t(val), t(np.arange(4, dtype=np.int32)), homotopy_q=2)
+    assert e.value.status == ipt.IPT_EINVAL
