@@ -228,9 +228,10 @@ def bench_morgan(ipt, handle, args):
 
 def bench_continuation(ipt, handle, args):
     """Non-autonomous continuation (opts.cont_alpha; the concluding discussion of the
-    3 x 3 example): the paper's 3 x 3 matrix D = diag(0, 1, 3) + eps P over a grid of
-    real eps, columns converged by plain IPT and by the continuation (alpha = 1/2,
-    tol 1e-12); and its cost on the dense n = 4096 workload against plain FP64."""
+    3 x 3 example) and the homotopy restart (opts.homotopy_q, concluding section): the
+    paper's 3 x 3 matrix D = diag(0, 1, 3) + eps P over a grid of real eps, columns
+    converged by plain IPT, by the continuation (alpha = 1/2) and by a 2-stage restart
+    (tol 1e-12); and their cost on the dense n = 4096 workload against plain FP64."""
     import numpy as np
     import torch
     import workloads
@@ -238,27 +239,31 @@ def bench_continuation(ipt, handle, args):
     tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     step = args.cont_grid_step
     grid = [] if step <= 0 else [e for e in np.round(np.arange(-0.6, 0.6 + step / 2, step), 6) if e != 0.0]
-    conv = {"plain": [0, 0, 0], "continuation": [0, 0, 0]}
-    rescued = []
+    conv = {"plain": [0, 0, 0], "continuation": [0, 0, 0], "homotopy_q2": [0, 0, 0]}
+    rescued, rescued_h = [], []
     t0 = time.perf_counter()
     for eps in grid:
         th, de = workloads.three_by_three(float(eps))
         st = {}
-        for name, alpha in (("plain", 0.0), ("continuation", 0.5)):
-            r = ipt.ipt_solve_dense(tt(th), tt(de), handle=handle, tol=1e-12, max_iter=1000, cont_alpha=alpha)
+        for name, alpha, q in (("plain", 0.0, 0), ("continuation", 0.5, 0), ("homotopy_q2", 0.0, 2)):
+            r = ipt.ipt_solve_dense(tt(th), tt(de), handle=handle, tol=1e-12, max_iter=1000, cont_alpha=alpha,
+                                    homotopy_q=q)
             st[name] = r.status.cpu().numpy()
             for c in range(3):
                 conv[name][c] += int(st[name][c] == ipt.CONVERGED)
         rescued += ["eps=%g col %d" % (eps, c + 1) for c in range(3)
                     if st["continuation"][c] == ipt.CONVERGED and st["plain"][c] != ipt.CONVERGED]
+        rescued_h += ["eps=%g col %d" % (eps, c + 1) for c in range(3)
+                      if st["homotopy_q2"][c] == ipt.CONVERGED and st["plain"][c] != ipt.CONVERGED]
     t_grid = time.perf_counter() - t0
-    log("continuation 3x3 grid (%d eps): converged plain %s, continuation %s; rescued: %s" % (
-        len(grid), conv["plain"], conv["continuation"], rescued))
+    log("continuation 3x3 grid (%d eps): converged plain %s, continuation %s, homotopy (2 stages) %s; "
+        "rescued by the continuation: %s; by the homotopy: %s" % (
+            len(grid), conv["plain"], conv["continuation"], conv["homotopy_q2"], rescued, rescued_h))
     th, de = workloads.dense_sym_gaussian(args.n, args.eps, 0)
     thd, ded = tt(th), tt(de)
     dense = {}
-    for name, alpha in (("fp64", 0.0), ("continuation", 0.5)):
-        o = ipt.default_opts(tol=1e-10, precision=ipt.PREC_FP64, max_iter=200, cont_alpha=alpha)
+    for name, alpha, q in (("fp64", 0.0, 0), ("continuation", 0.5, 0), ("homotopy_q2", 0.0, 2)):
+        o = ipt.default_opts(tol=1e-10, precision=ipt.PREC_FP64, max_iter=200, cont_alpha=alpha, homotopy_q=q)
         run = lambda: ipt.ipt_solve_dense(thd, ded, opts=o, handle=handle, colinfo=False)
         _time(run, 1)
         sec, r = _time(run, 2)
@@ -271,7 +276,8 @@ def bench_continuation(ipt, handle, args):
     return {"workload": "3x3 D=diag(0,1,3)+eps*[[0,1,2],[1,0,3],[2,3,0]], %d real eps in [-0.6, 0.6] (step %g), "
                         "tol 1e-12, max 1000 sweeps, alpha=0.5; dense n=%d eps=%g full spectrum, tol 1e-10" % (
                             len(grid), step, args.n, args.eps),
-            "grid_converged_per_column": conv, "rescued": rescued, "grid_seconds": round(t_grid, 3),
+            "grid_converged_per_column": conv, "rescued": rescued, "rescued_homotopy_q2": rescued_h,
+            "grid_seconds": round(t_grid, 3),
             "dense": dense}
 
 
