@@ -180,20 +180,20 @@ def ipt_dense_cont(theta, delta, alpha, idx=None, z0=None, tol=1e-12, max_iter=D
 
 
 def ipt_dense_homotopy(theta, delta, stages, idx=None, z0=None, tol=1e-12, max_iter=DEFAULT_MAX_ITER,
-                       div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, resid=True) -> Result:
+                       div_norm=DEFAULT_DIV_NORM, div_growth=DEFAULT_DIV_GROWTH, resid=True, accel="picard") -> Result:
     """The homotopy restart of the concluding section: for q = 1..stages, IPT on the
     partition D + (q/stages) Delta (each entry of Delta times the FP64 number
     q/stages), started from the previous stage's vectors (the first stage from z0,
     or e_i); the last stage is the problem itself and decides.  Reading: "the
     diagonal matrix thus obtained as initial condition" is the matrix of the previous
     stage's eigenvectors, the chart z_i = 1 kept.  Returns the last stage's result
-    with sweeps summed over the stages."""
+    with sweeps summed over the stages; accel as for ipt_dense, in every stage."""
     delta = np.ascontiguousarray(delta, dtype=np.float64)
     z, total = z0, None
     for q in range(1, stages + 1):
         scale = float(q) / float(stages)
         r = ipt_dense(theta, delta * scale if q < stages else delta, idx=idx, z0=z, tol=tol, max_iter=max_iter,
-                      div_norm=div_norm, div_growth=div_growth, resid=resid and q == stages)
+                      div_norm=div_norm, div_growth=div_growth, resid=resid and q == stages, accel=accel)
         total = r.sweeps.copy() if total is None else total + r.sweeps
         z = r.z
     r["sweeps"] = total

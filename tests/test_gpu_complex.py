@@ -125,3 +125,23 @@ def test_complex_errors(ipt):
     th3[5] = th3[3] + 1e-3j  # equal real parts only: distinct
     g = _solve(ipt, th3, de, idx=np.array([3, 5], np.int32), tol=1e-10)
     assert g.status.shape == (2,)
+
+
+def test_complex_unsorted_columns_strided_warm_start(ipt):
+    """Unsorted requested columns (k = 1 and k = 7), a warm start with a row stride
+    larger than k, and |M|_1 skipped (IPT_FLAG_NO_NORM)."""
+    say("complex n=130 unsorted idx, strided z0")
+    th, de = _general(130, 0.05, 21)
+    for idx in (np.array([77], np.int32), np.array([129, 3, 64, 0, 100, 65, 1], np.int32)):
+        g = _solve(ipt, th, de, idx=idx, tol=1e-12)
+        ref = oracle.ipt_dense_z(th, de, idx=idx, tol=1e-12)
+        check(g.z, g.lam, g.status, ref, _norm1(th, de), 1e-12, gpu_sweeps=g.sweeps)
+    idx = np.array([129, 3, 64, 0, 100, 65, 1], np.int32)
+    part = _solve(ipt, th, de, idx=idx, tol=1e-12, max_iter=2)
+    wide = np.zeros((130, 16), np.complex128)
+    wide[:, :7] = part.z
+    zt = t(wide)[:, :7]  # row stride 16 > k = 7
+    r = host(ipt.ipt_solve_dense_z(t(th.astype(np.complex128)), t(de), idx=t(idx), z0=zt, tol=1e-12,
+                                   flags=ipt.FLAG_NO_NORM))
+    ref = oracle.ipt_dense_z(th, de, idx=idx, z0=part.z, tol=1e-12)
+    check(r.z, r.lam, r.status, ref, _norm1(th, de), 1e-12, gpu_sweeps=r.sweeps)

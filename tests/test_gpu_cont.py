@@ -150,3 +150,13 @@ def test_homotopy_rejected_elsewhere(ipt):
     with pytest.raises(ipt.IPTError) as e:
         ipt.ipt_solve_csr(t(th_s), t(rp), t(col), t(val), t(np.arange(4, dtype=np.int32)), homotopy_q=2)
     assert e.value.status == ipt.IPT_EINVAL
+
+
+def test_homotopy_with_acx(ipt):
+    """IPT-ACX inside every stage of the restart, against the oracle's restart with
+    ACX stages (application counts within a cycle, as for ACX alone)."""
+    say("homotopy + ACX n=200 Q=2")
+    th, de = W.dense_sym_gaussian(200, 0.05, 12)
+    g = _solve(ipt, th, de, tol=1e-12, homotopy_q=2, flags=ipt.FLAG_ACX)
+    ref = oracle.ipt_dense_homotopy(th, de, 2, tol=1e-12, resid=False, accel="acx")
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12)
