@@ -101,6 +101,18 @@ def cpu_baseline(theta, delta, seconds):
                       "plain C FP64, OpenMP over columns); %.1f s" % (cols - 1, n, dt)}
 
 
+def dtype_of(sweep_prec, mode):
+    """The arithmetic of the headline solve's sweeps, in the order they ran (the
+    ladder's rungs follow the steps, so this is read from the solve, not the mode)."""
+    names = {"exact-first": "f64 (first sweep, no product)", "low": "bf16",
+             "fp32": "f32" if mode == "ladder_fp32_mma" else "fp32-class (3 x fp16 split products)", "fp64": "f64"}
+    seq = []
+    for p in sweep_prec:
+        if not seq or seq[-1] != names[p]:
+            seq.append(names[p])
+    return " -> ".join(seq) + (" (f64 certifies)" if len(seq) > 1 else "")
+
+
 def _time(fn, steps):
     import torch
     torch.cuda.synchronize()
@@ -516,8 +528,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"ladder": "bf16 -> fp32-class (3 x fp16 split products) -> f64 ladder (f64 certifies)",
-                  "ladder_fp32_mma": "bf16 -> f32 -> f64 ladder (f64 certifies)"}.get(head_mode, "f64"),
+        "dtype": dtype_of(head["sweep_prec"], head_mode),
         "data": "synthetic",
         "config": {"workload": "dense full spectrum n=%d, D=diag(1..n), Delta=eps*(R+R^T)/2, R iid N(0,1/n) "
                                "seed 0, eps=%g, k=n, tol 1e-10 (per-column relative step)" % (n, args.eps),
