@@ -99,13 +99,15 @@ def test_small_and_two_by_two(ipt):
         assert abs(r.z[1, 0] - x) < 1e-15 and abs(r.z[0, 1] + x) < 1e-15
 
 
-def test_large_sampled(ipt):
-    """n = 2048 Hermitian, full spectrum on the GPU; sampled columns by the oracle."""
-    say("complex n=2048 hermitian sampled")
-    th, de = _hermitian(2048, 0.01, 1)
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_large_sampled(ipt, n):
+    """Hermitian full spectra on the GPU (n = 4096 is the benchmarked size); sampled
+    columns by the oracle."""
+    say("complex n=%d hermitian sampled" % n)
+    th, de = _hermitian(n, 0.01, 1)
     g = _solve(ipt, th, de, tol=1e-10)
     assert np.all(g.status == 0)
-    cols = np.unique(np.concatenate([[0, 1, 63, 64, 1023, 2047], np.random.default_rng(3).integers(0, 2048, 10)]))
+    cols = np.unique(np.concatenate([[0, 1, 63, 64, n // 2 - 1, n - 1], np.random.default_rng(3).integers(0, n, 10)]))
     ref = oracle.ipt_dense_z(th, de, idx=cols.astype(np.int32), tol=1e-10, resid=False)
     check(g.z[:, cols], g.lam[cols], g.status[cols], ref, _norm1(th, de), 1e-10)
 

@@ -160,3 +160,21 @@ def test_homotopy_with_acx(ipt):
     g = _solve(ipt, th, de, tol=1e-12, homotopy_q=2, flags=ipt.FLAG_ACX)
     ref = oracle.ipt_dense_homotopy(th, de, 2, tol=1e-12, resid=False, accel="acx")
     check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12)
+
+
+@pytest.mark.parametrize("mode", ["continuation", "homotopy"])
+def test_full_size_sampled(ipt, mode):
+    """The benchmarked dense workload (n = 4096, eps = 0.01, full spectrum) under the
+    continuation (alpha = 1/2) and the 2-stage restart; sampled columns by the oracle."""
+    say("%s n=4096 sampled" % mode)
+    th, de = W.dense_sym_gaussian(4096, 0.01, 0)
+    kw = dict(cont_alpha=0.5) if mode == "continuation" else dict(homotopy_q=2)
+    g = _solve(ipt, th, de, tol=1e-10, max_iter=200, **kw)
+    assert np.all(g.status == 0)
+    cols = np.unique(np.concatenate([[0, 1, 127, 128, 4095], np.random.default_rng(6).integers(0, 4096, 7)]))
+    cols = cols.astype(np.int32)
+    if mode == "continuation":
+        ref = oracle.ipt_dense_cont(th, de, 0.5, idx=cols, tol=1e-10, max_iter=200, resid=False)
+    else:
+        ref = oracle.ipt_dense_homotopy(th, de, 2, idx=cols, tol=1e-10, max_iter=200, resid=False)
+    check(g.z[:, cols], g.lam[cols], g.status[cols], ref, oracle.norm1(th, de), 1e-10)
