@@ -313,7 +313,9 @@ def bench_complex(ipt, handle, args):
     inf = r.info
     ms = inf["prec_ms"]["fp64"]
     act = inf["sweep_active"]
-    flops = sum(8.0 * n * n * a_ for a_ in act)  # four real products of 2 n^2 per active column
+    # four real products of 2 n^2 per active column, in the product sweeps (the first
+    # sweep of the cold start has none)
+    flops = sum(8.0 * n * n * a_ for a_, p_ in zip(act, inf["sweep_prec"]) if p_ == "fp64")
     tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     log("complex n=%d: %.2f ms/solve, %d sweeps, %d converged, product %.1f TFLOP/s" % (
         n, sec * 1e3, inf["sweeps"], inf["converged"], tf))

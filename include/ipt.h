@@ -226,10 +226,10 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
  * A complex number is a (re, im) pair of doubles (the layout of C99 double complex,
  * std::complex<double> and torch.complex128); theta, delta, z0, z_out and lambda_out
  * must be 16-byte aligned.  n, k, idx, col_status, info and ci as for ipt_solve_dense;
- * |M|_1 and the eigen-residual use the modulus.  Every sweep is an FP64 product sweep
- * (four real matrix-core products; the first sweep of a cold start too, Delta E
- * being exact): opts.precision must be IPT_PREC_FP64, and IPT_FLAG_ACX,
- * IPT_FLAG_CHOOSE_D and opts.cont_alpha are rejected with IPT_EINVAL.
+ * |M|_1 and the eigen-residual use the modulus.  Sweeps are FP64 (four real
+ * matrix-core products per complex product; the first sweep of a cold start needs no
+ * product, as in the real solve): opts.precision must be IPT_PREC_FP64, and IPT_FLAG_ACX,
+ * IPT_FLAG_CHOOSE_D, opts.cont_alpha and opts.homotopy_q > 1 are rejected with IPT_EINVAL.
  * IPT_EDEGENERATE when theta_j == theta_i (both parts) for a requested i and j != i.
  */
 ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda,

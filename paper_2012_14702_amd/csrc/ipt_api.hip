@@ -877,9 +877,9 @@ ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const
     Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
     IPT_HIP(h, timer.ensure());
     IPT_HIP(h, hipEventRecord(h->ev_start, s));
-    // every sweep, the first of a cold start included, is a product sweep (Delta E is
-    // exact in FP64)
-    IPT_HIP(h, launch_ctrl_init(s, ctrl, PREC_F64, k));
+    // the first sweep of a cold start needs no product (Delta E is a gather)
+    const bool cold = (z0 == nullptr);
+    IPT_HIP(h, launch_ctrl_init(s, ctrl, cold ? PREC_EXACT_FIRST : PREC_F64, k));
     IPT_HIP(h, launch_zsetup(s, ctrl, theta, delta, lda, th_re, th_im, part2, n));
     IPT_HIP(h, launch_init_cols(s, ctrl, cs, idx, n, k, kp, bitmap, (int32_t)ntn, 0));
     IPT_HIP(h, launch_zcheck_gaps(s, ctrl, th_re, th_im, cs.idx, n, k));
@@ -894,10 +894,16 @@ ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const
         const int32_t in_par = (t - 1) & 1, out_par = t & 1;
         const double *zin = zb[(t - 1) & 1];
         double *zout = zb[t & 1];
-        IPT_HIP(h, launch_zdiag(s, ctrl, delta, lda, zin, kp, cs, dpart, d_re, d_im, n));
-        IPT_HIP(h, timer.mark(t, 0, s));
-        IPT_HIP(h, launch_zsweep(s, ctrl, delta, lda, th_re, th_im, zin, zout, cs, d_re, d_im, part, n, np, kp));
-        IPT_HIP(h, timer.mark(t, 1, s));
+        if (cold && t == 1) {
+            IPT_HIP(h, timer.mark(t, 0, s));
+            IPT_HIP(h, launch_zsweep1(s, ctrl, delta, lda, th_re, th_im, cs, d_re, d_im, zout, kp, part, n, np));
+            IPT_HIP(h, timer.mark(t, 1, s));
+        } else {
+            IPT_HIP(h, launch_zdiag(s, ctrl, delta, lda, zin, kp, cs, dpart, d_re, d_im, n));
+            IPT_HIP(h, timer.mark(t, 0, s));
+            IPT_HIP(h, launch_zsweep(s, ctrl, delta, lda, th_re, th_im, zin, zout, cs, d_re, d_im, part, n, np, kp));
+            IPT_HIP(h, timer.mark(t, 1, s));
+        }
         IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, d_re, th_re, part, nrt, kp, t, in_par, out_par, nullptr, th_im,
                                    d_im, lam_im));
         IPT_HIP(h, launch_control_plan(s, ctrl, dopt, t, cs, kp));

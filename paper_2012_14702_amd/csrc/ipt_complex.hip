@@ -10,7 +10,8 @@
 // fused into the epilogue like the real sweep: the complex gap is inverted by
 // Smith's method, and the per-column partial sums |W - Z|^2, |Z|^2, |gap (W - Z)|^2,
 // |W - e|^2 of each 64-row tile go to the same finalize as the real path.  d comes
-// from a separate pass over the rows idx[c] of Delta.
+// from a separate pass over the rows idx[c] of Delta.  A cold start's first sweep
+// needs no product (k_zsweep1).
 #include <math.h>
 
 #include "ipt_internal.h"
@@ -223,6 +224,53 @@ __global__ __launch_bounds__(256, 2) void k_zsweep(const Ctrl *ctrl, ZArgs g) {
     }
 }
 
+// Product-free first sweep of a cold start: from Z = E, Delta Z is the gather of
+// the columns idx[c] of Delta (exact), so W = E - G o Delta on the requested columns
+// and d_c = Delta_ii.  Block: 64 columns x 4 row lanes over one 64-row tile; the
+// per-column partial sums of the tile, lanes added in order.
+__global__ __launch_bounds__(256) void k_zsweep1(const Ctrl *ctrl, const double2 *delta, int64_t lda,
+                                                 const double *th_re, const double *th_im, ColState cs, double *d_re,
+                                                 double *d_im, double2 *zout, int64_t kp, double *part, int64_t n) {
+    if (ctrl->error || ctrl->done) return;
+    __shared__ double red[4][64][NPART];
+    const int cx = threadIdx.x & 63, gr = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + cx;
+    const int64_t tm = blockIdx.y;
+    const bool act = c < kp && cs.state[c] == COL_ACTIVE;
+    double sm[NPART] = {0.0, 0.0, 0.0, 0.0};
+    if (act) {
+        const int32_t i = cs.idx[c];
+        const double2 thi{th_re[i], th_im[i]};
+        int64_t j1 = (tm + 1) * ZT;
+        if (j1 > n) j1 = n;
+        for (int64_t j = tm * ZT + gr; j < j1; j += 4) {
+            const double2 dji = delta[j * lda + i];
+            if (j == i) {
+                zout[j * kp + c] = double2{1.0, 0.0};
+                sm[1] += 1.0;  // |Z|^2 of e_i; W - Z and W - e vanish in row i
+                d_re[c] = dji.x;
+                d_im[c] = dji.y;
+            } else {
+                const double2 gap{th_re[j] - thi.x, th_im[j] - thi.y};
+                const double2 w = cmul(cinv(gap), double2{-dji.x, -dji.y});
+                const double2 gs = cmul(gap, w);
+                zout[j * kp + c] = w;
+                sm[0] += cabs2(w);  // W - Z with Z_jc = 0
+                sm[2] += cabs2(gs);
+                sm[3] += cabs2(w);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) red[gr][cx][q] = sm[q];
+    __syncthreads();
+    if (gr == 0 && act) {
+#pragma unroll
+        for (int q = 0; q < NPART; ++q)
+            part[(tm * kp + c) * NPART + q] = ((red[0][cx][q] + red[1][cx][q]) + red[2][cx][q]) + red[3][cx][q];
+    }
+}
+
 // d_c = (Delta Z)_{i,c} for the active columns, in two passes: per chunk of rows,
 // block = 64 columns x 4 row lanes (lane g sums rows g, g + 4, ... of the chunk, the
 // lanes added in order) into dpart[chunk][c]; then the chunks in order.
@@ -420,6 +468,14 @@ hipError_t launch_zdiag(hipStream_t s, const Ctrl *ctrl, const double *delta, in
 }
 
 int64_t zsweep_tile() { return ZT; }
+
+hipError_t launch_zsweep1(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *th_re,
+                          const double *th_im, ColState cs, double *d_re, double *d_im, double *zout, int64_t kp,
+                          double *part, int64_t n, int64_t np) {
+    k_zsweep1<<<dim3(zblocks(kp, 64), (unsigned)(np / ZT)), 256, 0, s>>>(
+        ctrl, (const double2 *)delta, lda, th_re, th_im, cs, d_re, d_im, (double2 *)zout, kp, part, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_zsweep(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *th_re,
                          const double *th_im, const double *zin, double *zout, ColState cs, const double *d_re,

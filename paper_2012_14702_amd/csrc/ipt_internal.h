@@ -314,6 +314,9 @@ int64_t zdiag_part_doubles(int64_t kp);
 hipError_t launch_zdiag(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *zin,
                         int64_t kp, ColState cs, double *dpart, double *d_re, double *d_im, int64_t n);
 int64_t zsweep_tile();
+hipError_t launch_zsweep1(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *th_re,
+                          const double *th_im, ColState cs, double *d_re, double *d_im, double *zout, int64_t kp,
+                          double *part, int64_t n, int64_t np);
 hipError_t launch_zsweep(hipStream_t s, const Ctrl *ctrl, const double *delta, int64_t lda, const double *th_re,
                          const double *th_im, const double *zin, double *zout, ColState cs, const double *d_re,
                          const double *d_im, double *part, int64_t n, int64_t np, int64_t kp);
