@@ -821,8 +821,20 @@ __global__ __launch_bounds__(256) void k_copyout(const Ctrl *ctrl, ColState cs, 
     for (int64_t jb = j0; jb < n; jb += (int64_t)gridDim.y * 64) {
         int64_t j1 = jb + 64;
         if (j1 > n) j1 = n;
-        for (int64_t j = jb + rl; j < j1; j += rstep)
-            z_out[j * ldz + c] = (par == PAR_UNIT) ? (j == i ? 1.0 : 0.0) : src[j * ldzb + c];
+        // eight rows per step, their loads issued together
+        for (int64_t j = jb + rl; j < j1; j += 8 * rstep) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t jj = j + u * rstep;
+                v[u] = jj < j1 ? ((par == PAR_UNIT) ? (jj == i ? 1.0 : 0.0) : src[jj * ldzb + c]) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t jj = j + u * rstep;
+                if (jj < j1) z_out[jj * ldz + c] = v[u];
+            }
+        }
     }
     if (blockIdx.y == 0 && rl == 0) {
         lambda_out[c] = cs.lam[c];
