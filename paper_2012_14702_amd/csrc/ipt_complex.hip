@@ -413,21 +413,8 @@ __global__ __launch_bounds__(256) void k_zcopyout(const Ctrl *ctrl, ColState cs,
     for (int64_t jb = (int64_t)blockIdx.y * 64; jb < n; jb += (int64_t)gridDim.y * 64) {
         int64_t j1 = jb + 64;
         if (j1 > n) j1 = n;
-        // eight rows per step, their loads issued together
-        for (int64_t j = jb + rl; j < j1; j += 8 * rstep) {
-            double2 v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t jj = j + u * rstep;
-                v[u] = jj < j1 ? ((par == PAR_UNIT) ? double2{jj == i ? 1.0 : 0.0, 0.0} : src[jj * kp + c])
-                               : double2{0.0, 0.0};
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t jj = j + u * rstep;
-                if (jj < j1) z_out[jj * ldz + c] = v[u];
-            }
-        }
+        for (int64_t j = jb + rl; j < j1; j += rstep)
+            z_out[j * ldz + c] = (par == PAR_UNIT) ? double2{j == i ? 1.0 : 0.0, 0.0} : src[j * kp + c];
     }
     if (blockIdx.y == 0 && rl == 0) {
         lambda_out[c] = double2{cs.lam[c], lam_im[c]};
