@@ -668,6 +668,10 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
     const int32_t lt = (o.low_type == IPT_LOW_FP16) ? LT_F16 : LT_BF16;
     const bool use_low = ladder && o.low_type != IPT_LOW_NONE;
+    // FP16 shadows of Delta (the FP16 low rung, the three-product rung) need max |Delta|
+    const bool mid_x3 = dopt.mid_x3 != 0;
+    const bool low16 = use_low && lt == LT_F16;
+    const bool want_max = low16 || mid_x3;
 
     // Workspace layout (sizes first, then carve).
     const bool acx = dopt.acx != 0;
@@ -701,7 +705,8 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         cs.lam = cv.take<double>(kp);
         cs.resid = cv.take<double>(kp);
         *bitmap = cv.take<uint32_t>((n + 31) / 32);
-        *scratch = norm ? cv.take<double>(prep_delta_chunks(np) * n) : nullptr;
+        // column partials of |M|_1, then the per-block maxima of |Delta|
+        *scratch = (norm || want_max) ? cv.take<double>(prep_delta_chunks(np) * n + prep_delta_blocks(np)) : nullptr;
         *dpad = direct ? nullptr : cv.take<double>(np * np);
         *dlo = use_low ? (void *)cv.take<uint16_t>(np * np) : nullptr;
         *d32 = ladder ? cv.take<float>(np * np) : nullptr;
@@ -736,15 +741,13 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     IPT_HIP(h, launch_ctrl_init(s, ctrl, start_prec, k, fuse_d ? 1 : 0, o.cont_alpha));
     // Row-major pass over Delta (copy, BF16/FP32 shadows, |M|_1, max |Delta|), then the
     // tile-pair pass (symmetry, FP16 shadows at the power-of-two scale from that max)
-    const bool mid_x3 = dopt.mid_x3 != 0;
-    const bool low16 = use_low && lt == LT_F16;
-    const bool want_max = low16 || mid_x3;
     const double *dA = direct ? delta : dpad;
     const int64_t ldA = direct ? lda : np;
     if (!direct || ladder || norm)
         IPT_HIP(h, launch_prep_delta(s, ctrl, theta, delta, lda, n, np, direct ? nullptr : dpad,
                                      (use_low && !low16) ? (__bf16 *)dlo : nullptr, (ladder && !mid_x3) ? d32 : nullptr,
-                                     norm ? scratch : nullptr, want_max));
+                                     norm ? scratch : nullptr,
+                                     want_max ? (uint64_t *)(scratch + prep_delta_chunks(np) * n) : nullptr));
     if (fuse_d || want_max)
         IPT_HIP(h, launch_scan_delta(s, ctrl, delta, lda, n, np, fuse_d, low16 ? (_Float16 *)dlo : nullptr,
                                      mid_x3 ? (_Float16 *)d32 : nullptr));

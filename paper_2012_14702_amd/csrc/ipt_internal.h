@@ -131,11 +131,13 @@ hipError_t launch_plan_dense(hipStream_t s, Ctrl *ctrl, ColState cs, int64_t kp)
 hipError_t launch_control_plan(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, ColState cs, int64_t kp);
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
                               int64_t k);
-// colpart holds prep_delta_chunks(np) x n doubles; want_max also sets ctrl->dscale.
+// colpart holds prep_delta_chunks(np) x n doubles; bmax (prep_delta_blocks(np) words of
+// per-block maxima of |Delta|), when given, also sets ctrl->dscale.
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
                              int64_t n, int64_t np, double *dpad, __bf16 *dlo, float *d32, double *colpart,
-                             int32_t want_max);
+                             uint64_t *bmax);
 int64_t prep_delta_chunks(int64_t np);
+int64_t prep_delta_blocks(int64_t np);
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
                             const int32_t *col, const double *val, int64_t n, double *scratch);
 // set_zscale: also the power-of-two scale of the FP16 shadow of Z - E from max |Z - E|

@@ -108,13 +108,15 @@ __device__ inline __bf16 to_low<__bf16>(double x) { return (__bf16)(float)x; }
 template <>
 __device__ inline _Float16 to_low<_Float16>(double x) { return (_Float16)(float)x; }
 
+__device__ inline uint64_t wave_max_u64(uint64_t v);              // max over the wave (below)
 __device__ inline void wave_atomic_max(uint64_t *p, uint64_t v);  // one atomic max per wave (below)
 __device__ inline void block_atomic_max(uint64_t *p, uint64_t v);  // one atomic max per block (below)
 
 // Row-major pass over Delta: a zero-padded FP64 copy (when Delta is not tile
-// aligned), the BF16 and FP32 shadows of the ladder, max |Delta_jl| (for the scale
-// of the FP16 shadows, which k_scan_delta writes), and per-chunk partial column sums
-// of |M| for |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Block: 256 columns x
+// aligned), the BF16 and FP32 shadows of the ladder, per-block maxima of |Delta_jl|
+// (for the scale of the FP16 shadows, which k_scan_delta writes; reduced by
+// k_set_dscale, so no two blocks write the same word), and per-chunk partial column
+// sums of |M| for |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Block: 256 columns x
 // PREP_ROWS rows; thread (cx, ry) holds columns 4cx..4cx+3 (16-byte loads) and walks
 // rows ry, ry + 4, ..., four rows in flight.
 constexpr int PREP_ROWS = 128;
@@ -122,9 +124,10 @@ constexpr int PREP_ROWS = 128;
 template <typename TL>
 __global__ __launch_bounds__(256) void k_prep_delta(Ctrl *ctrl, const double *theta, const double *delta,
                                                     int64_t lda, int64_t n, int64_t np, double *dpad, TL *dlo,
-                                                    float *d32, double *colpart, int32_t want_max) {
+                                                    float *d32, double *colpart, uint64_t *bmax) {
     typedef TL tl4_t __attribute__((ext_vector_type(4)));
     __shared__ double sh[4][256];
+    __shared__ uint64_t wmax[4];
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * 256 + 4 * cx;
     const int64_t r0 = (int64_t)blockIdx.y * PREP_ROWS;
@@ -186,7 +189,15 @@ __global__ __launch_bounds__(256) void k_prep_delta(Ctrl *ctrl, const double *th
     };
     if (vec) walk(std::true_type{});
     else walk(std::false_type{});
-    if (want_max) wave_atomic_max(&ctrl->dmax_bits, dbits(vmax));
+    if (bmax) {
+        const uint64_t v = wave_max_u64(dbits(vmax));
+        if (cx == 0) wmax[ry] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint64_t m01 = wmax[0] > wmax[1] ? wmax[0] : wmax[1], m23 = wmax[2] > wmax[3] ? wmax[2] : wmax[3];
+            bmax[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = m01 > m23 ? m01 : m23;
+        }
+    }
     if (!colpart) return;
 #pragma unroll
     for (int e = 0; e < 4; ++e) sh[ry][4 * cx + e] = acc[e];
@@ -795,10 +806,21 @@ __device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep) {
     ctrl->acc_maxdist = 0;
 }
 
-// The FP16 scale of the Delta shadows from max |Delta_jl| (ctrl->dmax_bits): a power
-// of two that brings the largest entry near 2^13.
-__global__ void k_set_dscale(Ctrl *ctrl) {
-    const double md = bitsd(ctrl->dmax_bits);
+// The FP16 scale of the Delta shadows from max |Delta_jl| (the nb per-block maxima of
+// k_prep_delta, kept in ctrl->dmax_bits): a power of two that brings the largest entry
+// near 2^13.  One block.
+__global__ __launch_bounds__(256) void k_set_dscale(Ctrl *ctrl, const uint64_t *bmax, int64_t nb) {
+    __shared__ uint64_t wm[4];
+    uint64_t m = 0;
+    for (int64_t i = threadIdx.x; i < nb; i += 256) m = bmax[i] > m ? bmax[i] : m;
+    m = wave_max_u64(m);
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    m = wm[0];
+    for (int w = 1; w < 4; ++w) m = wm[w] > m ? wm[w] : m;
+    ctrl->dmax_bits = m;
+    const double md = bitsd(m);
     ctrl->dscale = (md > 0.0 && isfinite(md)) ? exp2(floor(log2(8192.0 / md))) : 1.0;
 }
 
@@ -941,15 +963,16 @@ hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, co
 }
 
 int64_t prep_delta_chunks(int64_t np) { return (np + PREP_ROWS - 1) / PREP_ROWS; }
+int64_t prep_delta_blocks(int64_t np) { return ((np + 255) / 256) * prep_delta_chunks(np); }
 
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
                              int64_t n, int64_t np, double *dpad, __bf16 *dlo, float *d32, double *colpart,
-                             int32_t want_max) {
+                             uint64_t *bmax) {
     const int64_t chunks = prep_delta_chunks(np);
     dim3 g((unsigned)((np + 255) / 256), (unsigned)chunks);
-    k_prep_delta<__bf16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, dlo, d32, colpart, want_max);
+    k_prep_delta<__bf16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, dlo, d32, colpart, bmax);
     if (colpart) k_norm1_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, colpart, n, chunks);
-    if (want_max) k_set_dscale<<<1, 1, 0, s>>>(ctrl);
+    if (bmax) k_set_dscale<<<1, 256, 0, s>>>(ctrl, bmax, prep_delta_blocks(np));
     return hipGetLastError();
 }
 
