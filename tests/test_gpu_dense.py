@@ -172,6 +172,26 @@ def test_ladder_parity(ipt, eps, low):
         assert g.info["sweep_prec"][1] == "fp32"
 
 
+@pytest.mark.parametrize("n,low", [(1024, "none"), (1024, "fp16"), (300, "none"), (300, "fp16")])
+def test_ladder_without_norm(ipt, n, low):
+    """IPT_FLAG_NO_NORM with the rungs that multiply FP16 shadows of Delta (the
+    three-product rung, the FP16 low rung), tile-aligned and padded: |M|_1 only
+    normalises the reported residual, so iterates, eigenvalues, statuses and sweep
+    counts equal the normed solve's bit for bit, and both match the oracle."""
+    say("dense ladder no-norm n=%d low=%s" % (n, low))
+    th, de = W.dense_sym_gaussian(n, 0.01, 3)
+    lt = {"fp16": ipt.LOW_FP16, "none": ipt.LOW_NONE}[low]
+    a = _solve(ipt, th, de, tol=1e-10, precision=ipt.PREC_LADDER, low_type=lt)
+    b = _solve(ipt, th, de, tol=1e-10, precision=ipt.PREC_LADDER, low_type=lt, flags=ipt.FLAG_NO_NORM)
+    for x, y in ((a.z, b.z), (a.lam, b.lam), (a.status, b.status), (a.sweeps, b.sweeps)):
+        np.testing.assert_array_equal(x, y)
+    assert list(a.info["sweep_prec"]) == list(b.info["sweep_prec"])
+    assert "fp32" in b.info["sweep_prec"] and b.info["norm1"] == 0.0
+    assert abs(a.info["norm1"] - oracle.norm1(th, de)) <= 1e-13 * oracle.norm1(th, de)
+    ref = oracle.ipt_dense(th, de, tol=1e-10)
+    check(b.z, b.lam, b.status, ref, oracle.norm1(th, de), 1e-10)
+
+
 @pytest.mark.parametrize("eps", [0.01, 0.05])
 def test_ladder_mid_rung_three_fp16_vs_fp32(ipt, eps):
     """The FP32-class rung from three FP16 products (default) against FP32 matrix
