@@ -770,10 +770,13 @@ __device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep) {
         // the next step is about q s_t.  "Certify" allows IPT_CERTIFY_SLACK: the
         // prediction is for the largest column step, and the few columns left above
         // tol cost one narrow FP64 sweep, far less than another full sweep of a rung.
+        // A warm start has observed no ratio after its first sweep (prev_maxstep is
+        // still +inf), so the prediction waits for a second step.
         const double slack_tol = IPT_CERTIFY_SLACK * o.tol;
         const bool stalled = !(ms < ctrl->prev_maxstep);
+        const bool have_ratio = isfinite(ctrl->prev_maxstep) && ctrl->prev_maxstep > 0.0;
         const double predicted = ms * (ms / ctrl->prev_maxstep);
-        const bool certify_next = isfinite(predicted) && predicted <= slack_tol;
+        const bool certify_next = have_ratio && isfinite(predicted) && predicted <= slack_tol;
         if (prec == PREC_EXACT_FIRST) {
             // From Z = E the first step is the first-order correction |G o Delta e_i|,
             // which also estimates the contraction ratio: q ~ s_1, so the step after

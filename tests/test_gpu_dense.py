@@ -221,6 +221,14 @@ def test_ladder_warm_start_and_narrow(ipt, n, k):
     assert g.info["sweep_prec"][0] == "fp32"
     ref = oracle.ipt_dense(th, de, idx=idx, z0=part.z, tol=1e-10)
     check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-10)
+    # a start far from tol (the first-order start F(I)): its first FP32-class step
+    # gives no contraction ratio yet, so the rung is kept for a second sweep
+    far = _solve(ipt, th, de, idx=idx, tol=1e-12, max_iter=1)
+    g = _solve(ipt, th, de, idx=idx, z0=far.z, tol=1e-10, precision=ipt.PREC_LADDER)
+    assert g.info["sweep_max_step"][0] > 1e-7
+    assert g.info["sweep_prec"][:2] == ["fp32", "fp32"], g.info["sweep_prec"]
+    ref = oracle.ipt_dense(th, de, idx=idx, z0=far.z, tol=1e-10)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-10)
     c = _solve(ipt, th, de, idx=idx, tol=1e-10, precision=ipt.PREC_LADDER)
     ref = oracle.ipt_dense(th, de, idx=idx, tol=1e-10)
     check(c.z, c.lam, c.status, ref, oracle.norm1(th, de), 1e-10)
