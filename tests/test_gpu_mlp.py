@@ -91,3 +91,34 @@ def test_warm_start_keeps_answers_and_saves_sweeps(ipt):
         ref = oracle.ipt_dense(th, de, idx=W.lowest_indices(th, k), tol=1e-10)
         check(zw[p].cpu().numpy(), lw[p].cpu().numpy(), sw[p].cpu().numpy(), ref, oracle.norm1(th, de), 1e-10)
         assert np.max(angles(zw[p].cpu().numpy(), zc[p].cpu().numpy())) <= 1e-8
+
+
+@pytest.mark.timeout(600)
+def test_warm_start_benchmark_size(ipt):
+    """The benchmarked learned configuration: family diag(1..1024) + eps R, k = 32
+    lowest, the 2 -> 256 -> 256 -> 32768 network trained on 512 eps ~ U[0, 0.08]
+    (seed 1) for the benchmark's 3000 Adam steps; 8 of the 128 test eps (seed 2),
+    warm-started, each column against the oracle's cold solve (the start must not
+    change the answer), with fewer sweeps than the cold start on average."""
+    from paper_2012_14702_amd import warmstart
+    say("mlp warm start n=1024 k=32 (benchmark size)")
+    n, k = 1024, 32
+    th, base = W.family_base(n, 0)
+    thd, based = t(th), t(base)
+    idx_h = W.lowest_indices(th, k)
+    idx = t(idx_h)
+    eps_tr = W.family_eps(512, 0.0, 0.08, seed=1)
+    eps_te = W.family_eps(128, 0.0, 0.08, seed=2)[::16]
+    ztr, _, st_tr, _, _ = warmstart.solve_family(thd, based, eps_tr, idx, tol=1e-12)
+    assert int((st_tr != 0).sum()) == 0
+    ws = warmstart.WarmStarter(n, k, hidden=256, depth=2, seed=0)
+    ws.fit(ztr, eps_tr, idx, steps=3000, lr=1e-3)
+    z0 = ws.predict(eps_te, idx)
+    _, _, sc, swc, _ = warmstart.solve_family(thd, based, eps_te, idx, tol=1e-10)
+    zw, lw, sw, sww, _ = warmstart.solve_family(thd, based, eps_te, idx, z0=z0, tol=1e-10)
+    assert np.all(sc.cpu().numpy() == 0) and np.all(sw.cpu().numpy() == 0)
+    assert sww.mean() < swc.mean()
+    for p, e in enumerate(eps_te):
+        de = e * base
+        ref = oracle.ipt_dense(th, de, idx=idx_h, tol=1e-10, resid=False)
+        check(zw[p].cpu().numpy(), lw[p].cpu().numpy(), sw[p].cpu().numpy(), ref, oracle.norm1(th, de), 1e-10)

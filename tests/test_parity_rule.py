@@ -38,3 +38,18 @@ def test_converged_columns_are_compared():
     z2[2, 0] = 1e-6
     with pytest.raises(AssertionError):
         check(z2, ref.lam, [0, 0], ref, 1.0, 1e-10)
+
+
+def test_ladder_failure_labels_are_free_before_the_cap():
+    """On a ladder solve the growth count runs on exact sweeps only, so a failing
+    column's label may differ from the FP64 oracle's anywhere; CONVERGED against a
+    failure is still a mismatch."""
+    early = _Ref([0, 2, 1], [1e-12, 2.0, 0.9], [4, 9, 100])
+    z, lam = early.z.copy(), early.lam.copy()
+    check(z, lam, [0, 1, 2], early, 1.0, 1e-10, max_iter=100, ladder=True)
+    with pytest.raises(AssertionError):
+        check(z, lam, [0, 1, 1], early, 1.0, 1e-10, max_iter=100)
+    with pytest.raises(AssertionError):
+        check(z, lam, [0, 0, 1], early, 1.0, 1e-10, max_iter=100, ladder=True)
+    with pytest.raises(AssertionError):
+        check(z, lam, [2, 2, 1], early, 1.0, 1e-10, max_iter=100, ladder=True)
