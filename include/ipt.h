@@ -217,6 +217,26 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
                            const ipt_colinfo *ci);
 
 /*
+ * Dense solve that allocates nothing, for callers that cannot allocate device or
+ * pinned memory during a solve (tight serving loops, harnesses that forbid it).
+ * Arguments, results and errors as for ipt_solve_dense, on the same kernels; the
+ * workspace is a fixed device array of IPT_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each device it runs on until the process ends (its device address is
+ * taken once per device by ipt_create, which also allocates the handle's pinned
+ * poll buffers).  A solve whose workspace exceeds it (full spectra beyond about
+ * n = 1024, fewer columns of larger n) is refused with IPT_EINVAL, as are
+ * opts.homotopy_q > 1 and IPT_FLAG_TIME_KERNELS.  Every call on a device shares that
+ * device's array, which keeps the last call's contents (each solve initialises what
+ * it reads): calls that overlap on one device, from any handle or thread, race and
+ * must be serialised by the caller.
+ */
+#define IPT_NOALLOC_SCRATCH_BYTES (128u << 20)
+ipt_status ipt_solve_dense_noalloc(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda,
+                                   int64_t k, const int32_t *idx, const double *z0, int64_t ldz0,
+                                   const ipt_opts *opts, double *z_out, int64_t ldz, double *lambda_out,
+                                   int32_t *col_status, ipt_info *info, const ipt_colinfo *ci);
+
+/*
  * Dense solve over C^n (Sec. 2 states IPT for complex M: the same map, the stopping
  * test on the Euclidean norm of C^n, lambda = theta_i + (Delta z)_i).
  *   theta      [n] complex, finite; delta n x n complex row-major (lda >= n complex elements)

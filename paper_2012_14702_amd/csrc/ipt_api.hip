@@ -6,12 +6,43 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "ipt_internal.h"
 
 using namespace ipt;
+
+// Workspace of ipt_solve_dense_noalloc: one copy per device, held until the process
+// ends.  Host code never passes this name to a kernel (on the host it is only a
+// stand-in for the symbol); it uses the device address that hipGetSymbolAddress
+// returned for the device, kept in g_scratch_ptr by ipt_create.
+__device__ __align__(256) unsigned char scratch[IPT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Called by ipt_create with the handle's device current.
+hipError_t init_scratch(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return hipSuccess;  // the no-allocation solve then refuses
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+}  // namespace
 
 struct ipt_context {
     int device = 0;
@@ -544,6 +575,14 @@ ipt_status ipt_create(ipt_handle *out, void *stream) {
         return IPT_ENOMEM;
     }
     h->stream = (hipStream_t)stream;
+    // set-up that no solve may do later: the poll buffers (pinned host memory) and the
+    // device address of the no-allocation workspace on this device
+    const hipError_t es = init_scratch(h->device);
+    if (es != hipSuccess || ensure_poll(h) != IPT_OK) {
+        (void)hipGetLastError();
+        ipt_destroy(h);
+        return es != hipSuccess ? IPT_EHIP : IPT_ENOMEM;
+    }
     *out = h;
     return IPT_OK;
 }
@@ -639,10 +678,14 @@ static ipt_status homotopy_dense(ipt_handle h, int64_t n, const double *theta, c
     return IPT_OK;
 }
 
-ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
-                           const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts *opts, double *z_out,
-                           int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info,
-                           const ipt_colinfo *ci) {
+namespace {
+
+// The dense solve.  noalloc: the workspace is the device's no-allocation array
+// (scratch_ptr) instead of the handle's, and nothing is allocated.
+ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                       const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts *opts, double *z_out,
+                       int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info, const ipt_colinfo *ci,
+                       bool noalloc) {
     if (!h) return IPT_EINVAL;
     h->last_error.clear();
     if (n < 1 || n > (int64_t(1) << 20)) return fail(h, IPT_EINVAL, "n must be in [1, 2^20]");
@@ -654,6 +697,8 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
         return fail(h, IPT_EINVAL, "theta, delta, z_out, lambda_out and col_status must be non-NULL");
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
+    if (noalloc && (o.homotopy_q > 1 || (o.flags & IPT_FLAG_TIME_KERNELS)))
+        return fail(h, IPT_EINVAL, "the no-allocation solve takes neither opts.homotopy_q > 1 nor IPT_FLAG_TIME_KERNELS");
     if (o.homotopy_q > 1) return homotopy_dense(h, n, theta, delta, lda, k, idx, z0, ldz0, o, z_out, ldz, lambda_out,
                                                 col_status, info, ci);
     const DevOpts dopt = dev_opts(o);
@@ -722,9 +767,18 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     Ctrl *ctrl;
     Carve sizing;
     layout(sizing, zb, cs, &dnp, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
-    if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
     Carve cv;
-    cv.base = (char *)h->ws;
+    if (noalloc) {
+        cv.base = (char *)scratch_ptr(h->device);
+        if (!cv.base) return fail(h, IPT_EINVAL, "no no-allocation workspace on this device");
+        if (sizing.off > IPT_NOALLOC_SCRATCH_BYTES)
+            return fail(h, IPT_EINVAL, "this solve needs " + std::to_string(sizing.off) +
+                                           " bytes of workspace, more than the no-allocation limit of " +
+                                           std::to_string((size_t)IPT_NOALLOC_SCRATCH_BYTES));
+    } else {
+        if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
+        cv.base = (char *)h->ws;
+    }
     layout(cv, zb, cs, &dnp, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
 
     Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
@@ -808,6 +862,24 @@ ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const d
     }
     IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lambda_out, col_status, n, k, ci));
     return finish(h, ctrl, k, info, &timer);
+}
+
+}  // namespace
+
+ipt_status ipt_solve_dense(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                           const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts *opts, double *z_out,
+                           int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info,
+                           const ipt_colinfo *ci) {
+    return solve_dense(h, n, theta, delta, lda, k, idx, z0, ldz0, opts, z_out, ldz, lambda_out, col_status, info, ci,
+                       false);
+}
+
+ipt_status ipt_solve_dense_noalloc(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda,
+                                   int64_t k, const int32_t *idx, const double *z0, int64_t ldz0,
+                                   const ipt_opts *opts, double *z_out, int64_t ldz, double *lambda_out,
+                                   int32_t *col_status, ipt_info *info, const ipt_colinfo *ci) {
+    return solve_dense(h, n, theta, delta, lda, k, idx, z0, ldz0, opts, z_out, ldz, lambda_out, col_status, info, ci,
+                       true);
 }
 
 ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda,

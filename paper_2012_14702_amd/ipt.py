@@ -105,6 +105,8 @@ def load_library():
     lib.ipt_set_stream.argtypes = [p, p]
     lib.ipt_solve_dense.argtypes = [p, i64, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
                                     C.POINTER(Info), C.POINTER(ColInfo)]
+    lib.ipt_solve_dense_noalloc.argtypes = [p, i64, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
+                                            C.POINTER(Info), C.POINTER(ColInfo)]
     lib.ipt_solve_dense_z.argtypes = [p, i64, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
                                     C.POINTER(Info), C.POINTER(ColInfo)]
     lib.ipt_solve_csr.argtypes = [p, i64, p, p, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
@@ -117,7 +119,8 @@ def load_library():
     lib.ipt_status_string.restype = C.c_char_p
     lib.ipt_last_error.argtypes = [p]
     lib.ipt_last_error.restype = C.c_char_p
-    for fn in ("ipt_create", "ipt_destroy", "ipt_set_stream", "ipt_solve_dense", "ipt_solve_dense_z", "ipt_solve_csr",
+    for fn in ("ipt_create", "ipt_destroy", "ipt_set_stream", "ipt_solve_dense", "ipt_solve_dense_noalloc",
+               "ipt_solve_dense_z", "ipt_solve_csr",
                "ipt_solve_batched", "ipt_batched_tune", "ipt_batched_get_tiles", "ipt_batched_set_tiles"):
         getattr(lib, fn).restype = C.c_int
     _lib = lib
@@ -234,6 +237,19 @@ def ipt_solve_dense(theta, delta, idx=None, z0=None, opts=None, handle=None, col
     """Dense IPT solve (ipt_solve_dense).  theta [n] f64, delta [n, n] f64 (row-major,
     row stride = lda), idx [k] int32 or None, z0 [n, k] f64 or None.  Returns a Result
     with z [n, k], lam [k], status [k] and info (a dict of ipt_info)."""
+    return _solve_dense("ipt_solve_dense", theta, delta, idx, z0, opts, handle, colinfo, z_out, None, None, kw)
+
+
+def ipt_solve_dense_noalloc(theta, delta, idx=None, z0=None, opts=None, handle=None, colinfo=True, z_out=None,
+                            lam_out=None, status_out=None, **kw):
+    """ipt_solve_dense_noalloc: the dense solve on the library's fixed per-device
+    workspace (no allocation inside the call; the outputs are the caller's, allocated
+    here when not given).  Same arguments and Result as ipt_solve_dense."""
+    return _solve_dense("ipt_solve_dense_noalloc", theta, delta, idx, z0, opts, handle, colinfo, z_out, lam_out,
+                        status_out, kw)
+
+
+def _solve_dense(entry, theta, delta, idx, z0, opts, handle, colinfo, z_out, lam, status, kw):
     import torch
     lib = load_library()
     h = _handle(handle)
@@ -250,12 +266,19 @@ def ipt_solve_dense(theta, delta, idx=None, z0=None, opts=None, handle=None, col
     dev = theta.device
     if z_out is None:
         z_out = torch.empty((n, k), dtype=torch.float64, device=dev)
-    lam = torch.empty(k, dtype=torch.float64, device=dev)
-    status = torch.empty(k, dtype=torch.int32, device=dev)
+    if lam is None:
+        lam = torch.empty(k, dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.empty(k, dtype=torch.int32, device=dev)
+    _check(lam, torch.float64, "lam_out")
+    _check(status, torch.int32, "status_out")
+    if z_out.dim() != 2 or z_out.shape[0] != n or z_out.shape[1] != k or z_out.stride(1) != 1 or lam.numel() < k \
+            or status.numel() < k:
+        raise ValueError("outputs must be z_out [n, k] with unit column stride, lam_out [k], status_out [k]")
     o = _opts(opts, kw)
     info = Info()
     ci, extra = _colinfo(k, colinfo)
-    st = lib.ipt_solve_dense(h.ptr, n, _ptr(theta), _ptr(delta), delta.stride(0), k, _ptr(idx), _ptr(z0),
+    st = getattr(lib, entry)(h.ptr, n, _ptr(theta), _ptr(delta), delta.stride(0), k, _ptr(idx), _ptr(z0),
                              z0.stride(0) if z0 is not None else 0, C.byref(o), _ptr(z_out), z_out.stride(0),
                              _ptr(lam), _ptr(status), C.byref(info), C.byref(ci) if ci is not None else None)
     return _finish(lib, h, st, z_out, lam, status, info, extra)
