@@ -170,7 +170,11 @@ def network_bf16(params, x, t, dims, round_points=True):
             e_one = 2.0 * np.abs(h) * eh + eh * eh
             gn = dh * one
             e_gn = e_dh * np.abs(one) + (np.abs(dh) + e_dh) * e_one
-            g, eg = _round_err(gn, e_gn + 3.0 * U_F32 * (np.abs(gn) + e_gn))
+            # FP32 evaluation of dh (1 - h h): the square and the difference round with
+            # absolute errors (near saturation 1 - h^2 is small), then the product
+            e_gn = (e_gn + U_F32 * (1.0 + U_F32) * (np.abs(dh) + e_dh) * (h * h + np.abs(one) + e_one)
+                    + U_F32 * (np.abs(gn) + e_gn))
+            g, eg = _round_err(gn, e_gn)
     out, bnd = [], []
     for gw, gb, e_gw, e_gb in reversed(grads):
         out += [gw.ravel(), gb]

@@ -245,22 +245,86 @@ hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L
                            double *z_pool, double *lambda_pool, int32_t *status_pool, double *max_resid_out);
 int bgemm_grid(int tile);  // persistent grid size (CUs x resident blocks)
 
-// MLP kernels (ipt_mlp.hip)
-hipError_t mlp_gemm(hipStream_t s, const void *A, bool a_bf16, int64_t lda, bool a_kcontig, const void *B,
-                    bool b_bf16, int64_t ldb, bool b_kcontig, float *C, int64_t ldc, const float *bias, const float *h,
-                    int64_t ldh, int M, int N, int K, int epi);
-hipError_t mlp_mse(hipStream_t s, const float *y, const float *tg, float *g, int64_t count, double *partial,
-                   float *loss_dev);
-hipError_t mlp_colsum(hipStream_t s, const float *g, int B, int N, float *db);
-hipError_t mlp_adam(hipStream_t s, float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t count, float lr,
-                    int step);
-hipError_t mlp_to_bf16(hipStream_t s, const float *w, __bf16 *wb, int64_t count);
+// MLP kernels (ipt_mlp.hip).  Every matrix the GEMM reads is BF16, row-major with
+// its reduction (K) dimension contiguous, zero-padded to multiples of MLP_TILE in
+// both dimensions.  C[M x N] = A[M x K] B[N x K]^T, 128 x 128 tiles, then one of the
+// epilogues below.
+constexpr int MLP_TILE = 128;
+enum : int {
+    MLP_EPI_ACT = 0,    // + bias, optional tanh; BF16 C and C^T (zero outside mvalid x nvalid)
+    MLP_EPI_MSE = 1,    // + bias; g = scale (y - t) in BF16 as C and C^T, loss and column-sum partials
+    MLP_EPI_F32 = 2,    // + bias; FP32 C (valid part, leading dimension ldc32)
+    MLP_EPI_GRAD = 3,   // FP32 C (valid part): a weight gradient in the parameter layout
+    MLP_EPI_ADAM = 4,   // Adam on the weights from this gradient; BF16 copies W and W^T
+    MLP_EPI_SPLIT = 5,  // FP32 partial tile of split-K (partial z at c32 + z M N, leading dimension N)
+    MLP_EPI_WARM = 6    // + bias; warm start Z0 = E + sum_l eps^l T_l + eps^(order+1) (mu + sigma y), FP64
+};
+struct MlpEpi {
+    int32_t mvalid, nvalid;        // rows and columns of C that are data (the rest is padding)
+    const float *bias;             // [nvalid] or null
+    int32_t tanh_act;
+    __bf16 *c16;                   // BF16 C, leading dimension ldc16
+    int64_t ldc16;
+    __bf16 *ct16;                  // BF16 C^T, leading dimension ldct16
+    int64_t ldct16;
+    float *c32;                    // FP32 C, leading dimension ldc32
+    int64_t ldc32;
+    const float *tgt;              // MSE targets [mvalid x nvalid], leading dimension ldt
+    int64_t ldt;
+    float scale;                   // MSE: 2 / (number of outputs)
+    double *lossp;                 // MSE: per-block sums of (y - t)^2
+    float *colp;                   // column sums of the stored BF16 C, per 128-row tile: [M/128][ldcolp]
+    int64_t ldcolp;
+    const __bf16 *h;               // split reduce: the activation H of the layer below (tanh derivative)
+    int64_t ldh;
+    float *w, *am, *av;            // Adam: FP32 weights and moments, parameter layout (row stride nvalid)
+    const int32_t *adam_t;         // Adam: steps taken so far (device)
+    float lr;
+    double *z0;                    // warm start output: problem p, entry q = j kcols + c at z0 + p pstride + j ldz0 + c
+    int64_t ldz0, pstride, kcols;
+    const int32_t *idx;
+    const float *mu, *sigma;
+    const double *eps;             // [mvalid] family parameter of each problem
+    const double *terms;           // order x (nvalid) analytic terms T_l (may be null when order = 0)
+    int32_t order;
+};
+hipError_t mlp_gemm(hipStream_t s, int mode, const __bf16 *A, int64_t lda, const __bf16 *B, int64_t ldb, int M, int N,
+                    int K, int splits, const MlpEpi &e);
+// Sum of the split-K partials (FP32 [splits][M][N]) in split order, times the tanh
+// derivative (1 - h^2) of the stored activation; BF16 C and C^T and column sums as
+// the epilogues do.
+hipError_t mlp_split_dtanh(hipStream_t s, const float *part, int splits, int M, int N, const MlpEpi &e);
+int mlp_split_count(int M, int N, int K);
+// Padded BF16 copies W [loutp x linp] and W^T [linp x loutp] of a layer from the FP32 weights.
+hipError_t mlp_pack_weights(hipStream_t s, const float *w, int lout, int lin, __bf16 *wb, __bf16 *wbt, int loutp,
+                            int linp);
+// Padded BF16 copies X [bp x ip] and X^T [ip x bp] of the FP32 input batch x [batch x in].
+hipError_t mlp_pack_x(hipStream_t s, const float *x, int batch, int in, __bf16 *xb, __bf16 *xt, int bp, int ip);
+struct MlpBiasLayers {
+    int32_t count;                 // layers
+    int32_t lout[17];              // bias length of each layer
+    int64_t boff[17];              // offset of the bias in the parameter layout
+    const float *colp[17];         // that layer's column-sum partials [mtiles][ld]
+    int64_t ldcolp[17];
+};
+// Bias gradients (column sums over the 128-row tiles, in tile order); Adam on the
+// biases when adam (else the gradient goes to g).
+hipError_t mlp_bias_step(hipStream_t s, const MlpBiasLayers &L, int mtiles, int adam, float *w, float *g, float *am,
+                         float *av, const int32_t *adam_t, float lr);
+// Loss = sum of the per-block partials / count; with adam, the step counter advances.
+hipError_t mlp_loss_step(hipStream_t s, const double *lossp, int nparts, double inv_count, float *loss,
+                         int32_t *adam_t, int adam);
 hipError_t mlp_targets(hipStream_t s, const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz,
-                       int64_t pstride, const int32_t *idx, const double *scale, float *targets, float *mu,
-                       float *sigma);
-hipError_t mlp_warm_start(hipStream_t s, const float *y, int64_t ldy, const float *mu, const float *sigma,
-                          const double *scale, int64_t n, int64_t k, const int32_t *idx, double *z0, int64_t ldz0,
-                          int64_t pstride, int32_t count);
+                       int64_t pstride, const int32_t *idx, const double *eps, int32_t order, const double *terms,
+                       float *targets, float *mu, float *sigma);
+
+// Rayleigh-Schroedinger terms of M = D + Delta on requested columns (ipt_rs.hip).
+hipError_t rs_gather(hipStream_t s, const double *delta, int64_t lda, const int32_t *idx, int64_t n, int64_t k,
+                     double *y);
+hipError_t rs_product(hipStream_t s, const double *delta, int64_t lda, const double *z, int64_t n, int64_t k,
+                      double *y);
+hipError_t rs_term(hipStream_t s, const double *theta, const int32_t *idx, const double *y, const double *terms,
+                   double *d, int32_t l, int64_t n, int64_t k);
 
 // IPT-ACX extrapolation over row-major iterate slots z, f1, f2, f3 (n rows, leading
 // dimension ld, kc columns with states `state`) after a cycle of order p

@@ -1,11 +1,20 @@
 // Small MLP that predicts warm starts Z0 for a parametrised family M(eps) = D + eps R,
-// trained and evaluated with the kernels of this file: BF16 MFMA GEMMs with FP32
-// accumulation (v_mfma_f32_16x16x32_bf16), fused bias + tanh epilogues, MSE loss,
-// bias-gradient reductions and Adam on FP32 master weights with a BF16 compute copy.
+// trained and evaluated with the kernels of this file.
 //
 // Network: x (in) -> [Linear -> tanh] x depth -> Linear -> y (out).  Parameters are
-// stored layer by layer as W_l (out_l x in_l, row-major) followed by b_l (out_l).
-// All reductions run in a fixed order, so results are bit-reproducible.
+// stored layer by layer as W_l (out_l x in_l, row-major) followed by b_l (out_l), in
+// FP32 (the Adam master copy); the GEMMs read BF16 copies.
+//
+// Every GEMM is C[M x N] = A[M x K] B[N x K]^T on BF16 operands whose reduction
+// dimension is contiguous (16-byte loads, no transposed reads), with v_mfma_f32_16x16x32_bf16
+// and FP32 accumulation.  The layouts each product needs are written by the producer:
+// the forward epilogue stores H and H^T, the loss epilogue g and g^T, the Adam epilogue
+// W and W^T, so that
+//   forward      H_l = act(H_{l-1} W_l^T + b_l)          A = H_{l-1},  B = W_l
+//   input grad   dH_{l-1} = G_l W_l                      A = G_l,      B = W_l^T   (split K)
+//   weight grad  dW_l = G_l^T H_{l-1}                    A = G_l^T,    B = H_{l-1}^T
+// All dimensions are zero-padded to multiples of 128; padding stays zero.  Reductions
+// (split K, column sums, loss) run in a fixed order, so results are bit-reproducible.
 #include <math.h>
 
 #include "ipt_internal.h"
@@ -16,262 +25,421 @@ namespace {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-// ---------------------------------------------------------------- GEMM
-// C[M x N] = A B^T with A(m, k) and B(n, k) read through strides: an operand is
-// "k-contiguous" (element (r, k) at r * ld + k) or "r-contiguous" (at k * ld + r).
-// Epilogue: + bias[n], optional tanh, optional multiply by (1 - h[m, n]^2) (the tanh
-// derivative of a stored activation), store FP32.  64 x 64 tile, BK = 32, 4 waves of
-// 32 x 32; inputs (FP32 or BF16) are rounded to BF16 when staged in LDS.
-constexpr int MT = 64, KT = 32, KP = KT + 8;
+constexpr int GT = MLP_TILE;   // tile rows and columns
+constexpr int GK = 32;         // K step
+constexpr int GLD = GK + 8;    // LDS pitch of an operand row in BF16 (80 bytes: 16 rows hit distinct banks)
+constexpr int OLD = GT + 8;    // LDS pitch of an output row in BF16 (272 bytes)
+constexpr int STAGE = 2 * GT * GLD;             // A and B of one stage
+constexpr int SMEM_BF16 = 2 * STAGE;            // two stages (40 KB); the output tile reuses it
+static_assert(GT * OLD <= SMEM_BF16, "output tile must fit the operand buffers");
 
-enum : int { EPI_NONE = 0, EPI_TANH = 1, EPI_DTANH = 2 };
+__device__ inline uint16_t bf16_bits(float v) {
+    const __bf16 b = (__bf16)v;
+    return __builtin_bit_cast(uint16_t, b);
+}
+__device__ inline float bits_f32(uint16_t u) { return (float)__builtin_bit_cast(__bf16, u); }
 
-template <typename TA, typename TB, bool AK, bool BK_>
-__global__ __launch_bounds__(256) void k_mlp_gemm(const TA *A, int64_t lda, const TB *B, int64_t ldb, float *Cm,
-                                                  int64_t ldc, const float *bias, const float *h, int64_t ldh, int M,
-                                                  int N, int K, int epi) {
-    __shared__ __attribute__((aligned(16))) __bf16 As[MT][KP];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[MT][KP];
+// The 128 x 128 BF16 tile in LDS (out[r * OLD + c], values already zero outside the
+// valid region) goes to C (row-major), C^T and the per-tile column sums.
+__device__ void store_tile(const uint16_t *out, const MlpEpi &e, int m0, int n0) {
+    const int t = threadIdx.x;
+    if (e.c16) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int u = t + 256 * i, r = u >> 4, ch = u & 15;
+            *(u16x8 *)(e.c16 + (int64_t)(m0 + r) * e.ldc16 + n0 + ch * 8) = *(const u16x8 *)(out + r * OLD + ch * 8);
+        }
+    }
+    if (e.ct16) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int u = t + 256 * i, c = u >> 4, ch = u & 15;
+            u16x8 v;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = out[(ch * 8 + q) * OLD + c];
+            *(u16x8 *)(e.ct16 + (int64_t)(n0 + c) * e.ldct16 + m0 + ch * 8) = v;
+        }
+    }
+    if (e.colp && t < GT) {
+        float acc = 0.f;
+        for (int r = 0; r < GT; ++r) acc += bits_f32(out[r * OLD + t]);
+        e.colp[(int64_t)(m0 / GT) * e.ldcolp + n0 + t] = acc;
+    }
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Adam (beta 0.9 / 0.999, eps 1e-8) on one weight; returns the new weight.
+__device__ inline float adam_update(float *w, float *m, float *v, float g, float lr, int32_t step) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    const float mv = b1 * *m + (1.f - b1) * g;
+    const float vv = b2 * *v + (1.f - b2) * g * g;
+    *m = mv;
+    *v = vv;
+    const float nw = *w - lr * (mv / c1) / (sqrtf(vv / c2) + eps);
+    *w = nw;
+    return nw;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_mlp_gemm(const __bf16 *__restrict__ A, int64_t lda,
+                                                  const __bf16 *__restrict__ B, int64_t ldb, int Kc, int M, int N,
+                                                  MlpEpi e) {
+    __shared__ __attribute__((aligned(16))) uint16_t smem[SMEM_BF16];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
-    const int m0 = blockIdx.y * MT, n0 = blockIdx.x * MT;
-    f4_t acc[2][2];
+    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int64_t kbeg = (int64_t)blockIdx.z * Kc;
+    const __bf16 *Ab = A + (int64_t)m0 * lda + kbeg;
+    const __bf16 *Bb = B + (int64_t)n0 * ldb + kbeg;
+    // loader: 16-byte chunk u = t + 256 r of a 128 x 32 tile: row u / 4, k offset 8 (u % 4)
+    const int lr0 = t >> 2, lk = (t & 3) * 8;
+    u16x8 ra[2], rb[2];
+    f4_t acc[4][4];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = f4_t{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += KT) {
-        // stage A: 64 rows x 32 k
-        if (AK) {
-            const int r = t >> 2, kq = (t & 3) * 8;
+        for (int y = 0; y < 4; ++y) acc[x][y] = f4_t{0.f, 0.f, 0.f, 0.f};
+    const int nk = Kc / GK;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int gm = m0 + r, gk = k0 + kq + e;
-                As[r][kq + e] = (__bf16)((gm < M && gk < K) ? (float)A[(int64_t)gm * lda + gk] : 0.f);
-            }
-        } else {
-            const int kk = t >> 3, rq = (t & 7) * 8;
+    for (int r = 0; r < 2; ++r) {
+        ra[r] = *(const u16x8 *)(Ab + (int64_t)(lr0 + 64 * r) * lda + lk);
+        rb[r] = *(const u16x8 *)(Bb + (int64_t)(lr0 + 64 * r) * ldb + lk);
+    }
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int gm = m0 + rq + e, gk = k0 + kk;
-                As[rq + e][kk] = (__bf16)((gm < M && gk < K) ? (float)A[(int64_t)gk * lda + gm] : 0.f);
-            }
-        }
-        if (BK_) {
-            const int r = t >> 2, kq = (t & 3) * 8;
+    for (int r = 0; r < 2; ++r) {
+        *(u16x8 *)(smem + (lr0 + 64 * r) * GLD + lk) = ra[r];
+        *(u16x8 *)(smem + GT * GLD + (lr0 + 64 * r) * GLD + lk) = rb[r];
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) {
+            const int64_t ko = (int64_t)(kt + 1) * GK + lk;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int gn = n0 + r, gk = k0 + kq + e;
-                Bs[r][kq + e] = (__bf16)((gn < N && gk < K) ? (float)B[(int64_t)gn * ldb + gk] : 0.f);
-            }
-        } else {
-            const int kk = t >> 3, rq = (t & 7) * 8;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int gn = n0 + rq + e, gk = k0 + kk;
-                Bs[rq + e][kk] = (__bf16)((gn < N && gk < K) ? (float)B[(int64_t)gk * ldb + gn] : 0.f);
+            for (int r = 0; r < 2; ++r) {
+                ra[r] = *(const u16x8 *)(Ab + (int64_t)(lr0 + 64 * r) * lda + ko);
+                rb[r] = *(const u16x8 *)(Bb + (int64_t)(lr0 + 64 * r) * ldb + ko);
             }
         }
-        __syncthreads();
-        const int koff = 8 * (lane >> 4);
+        const uint16_t *as = smem + (kt & 1) * STAGE, *bs = as + GT * GLD;
+        bf8_t af[4], bfg[4];
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 4; ++x) af[x] = *(const bf8_t *)(as + (wm * 64 + 16 * x + (lane & 15)) * GLD + 8 * (lane >> 4));
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
-                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    *(const bf8_t *)&As[wm * 32 + 16 * x + (lane & 15)][koff],
-                    *(const bf8_t *)&Bs[wn * 32 + 16 * y + (lane & 15)][koff], acc[x][y], 0, 0, 0);
+        for (int y = 0; y < 4; ++y) bfg[y] = *(const bf8_t *)(bs + (wn * 64 + 16 * y + (lane & 15)) * GLD + 8 * (lane >> 4));
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[x], bfg[y], acc[x][y], 0, 0, 0);
+        if (kt + 1 < nk) {
+            uint16_t *ns = smem + ((kt + 1) & 1) * STAGE;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                *(u16x8 *)(ns + (lr0 + 64 * r) * GLD + lk) = ra[r];
+                *(u16x8 *)(ns + GT * GLD + (lr0 + 64 * r) * GLD + lk) = rb[r];
+            }
+        }
         __syncthreads();
     }
-    // lane l, register r: row 4(l/16) + r, column l%16
+
+    // lane l, register r of block (x, y): row 16 x + 4 (l / 16) + r, column 16 y + l % 16
+    // of the wave's 64 x 64 quarter
+    const int rbase = wm * 64 + 4 * (lane >> 4), cbase = wn * 64 + (lane & 15);
+    if (MODE == MLP_EPI_SPLIT) {
+        float *p = e.c32 + (int64_t)blockIdx.z * M * N;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < 4; ++y)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    p[(int64_t)(m0 + rbase + 16 * x + r) * N + n0 + cbase + 16 * y] = acc[x][y][r];
+        return;
+    }
+    if (MODE == MLP_EPI_F32 || MODE == MLP_EPI_GRAD) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const int gc = n0 + cbase + 16 * y;
+                if (gc >= e.nvalid) continue;
+                const float bv = (MODE == MLP_EPI_F32 && e.bias) ? e.bias[gc] : 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gr = m0 + rbase + 16 * x + r;
+                    if (gr < e.mvalid) e.c32[(int64_t)gr * e.ldc32 + gc] = acc[x][y][r] + bv;
+                }
+            }
+        return;
+    }
+    if (MODE == MLP_EPI_WARM) {
+        const int32_t ord = e.order;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const int q = n0 + cbase + 16 * y;
+                if (q >= e.nvalid) continue;
+                const int64_t j = q / e.kcols, c = q - j * e.kcols;
+                const bool unit = (j == e.idx[c]);
+                const double bv = e.bias ? (double)e.bias[q] : 0.0;
+                const double mu = e.mu[q], sg = e.sigma[q];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int p = m0 + rbase + 16 * x + r;
+                    if (p >= e.mvalid) continue;
+                    double v = 1.0;
+                    if (!unit) {
+                        const double ep = e.eps[p];
+                        double base = 0.0, pw = 1.0;
+                        for (int l = 1; l <= ord; ++l) {
+                            pw *= ep;
+                            base += pw * e.terms[(int64_t)(l - 1) * e.nvalid + q];
+                        }
+                        v = base + pw * ep * (mu + sg * ((double)acc[x][y][r] + bv));
+                    }
+                    e.z0[(int64_t)p * e.pstride + j * e.ldz0 + c] = v;
+                }
+            }
+        return;
+    }
+
+    // the BF16-output epilogues: values into the LDS tile, then store_tile
+    uint16_t *out = smem;  // the last K step ended with a barrier
+    float lsum = 0.f;
+    int32_t step = 0;
+    if (MODE == MLP_EPI_ADAM) step = *e.adam_t + 1;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int lc = cbase + 16 * y, gc = n0 + lc;
+            const bool cok = gc < e.nvalid;
+            const float bv = (e.bias && cok && MODE != MLP_EPI_ADAM) ? e.bias[gc] : 0.f;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm * 32 + 16 * x + 4 * (lane >> 4) + r;
-                const int gn = n0 + wn * 32 + 16 * y + (lane & 15);
-                if (gm >= M || gn >= N) continue;
-                float v = acc[x][y][r];
-                if (bias) v += bias[gn];
-                if (epi == EPI_TANH) v = tanhf(v);
-                if (epi == EPI_DTANH) {
-                    const float hv = h[(int64_t)gm * ldh + gn];
-                    v *= 1.f - hv * hv;
+                const int lrow = rbase + 16 * x + r, gr = m0 + lrow;
+                const bool ok = cok && gr < e.mvalid;
+                float v = acc[x][y][r] + bv;
+                if (MODE == MLP_EPI_ACT) {
+                    if (e.tanh_act) v = tanhf(v);
+                } else if (MODE == MLP_EPI_MSE) {
+                    const float d = ok ? v - e.tgt[(int64_t)gr * e.ldt + gc] : 0.f;
+                    lsum += d * d;
+                    v = e.scale * d;
+                } else if (MODE == MLP_EPI_ADAM) {
+                    if (ok) {
+                        const int64_t wi = (int64_t)gr * e.nvalid + gc;
+                        v = adam_update(e.w + wi, e.am + wi, e.av + wi, v, e.lr, step);
+                    }
                 }
-                Cm[(int64_t)gm * ldc + gn] = v;
+                out[lrow * OLD + lc] = ok ? bf16_bits(v) : (uint16_t)0;
             }
+        }
+    if (MODE == MLP_EPI_MSE) {
+        __shared__ double red[4];
+        const double ws = wave_sum_d((double)lsum);
+        if (lane == 0) red[wv] = ws;
+        __syncthreads();
+        if (t == 0) e.lossp[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    }
+    __syncthreads();
+    store_tile(out, e, m0, n0);
 }
 
-// MSE: g = 2 (y - t) / (B out), per-block partial sums of (y - t)^2.
-__global__ void k_mse(const float *y, const float *tg, float *g, int64_t count, float scale, double *partial) {
+// Split-K sum in split order, times (1 - h^2), into the LDS tile, then store_tile.
+__global__ __launch_bounds__(256) void k_split_dtanh(const float *part, int splits, int M, int N, MlpEpi e) {
+    __shared__ __attribute__((aligned(16))) uint16_t out[GT * OLD];
+    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int64_t mn = (int64_t)M * N;
+    for (int i = 0; i < GT * GT / 256; ++i) {
+        const int u = threadIdx.x + 256 * i, r = u >> 7, c = u & (GT - 1);
+        const int gr = m0 + r, gc = n0 + c;
+        float v = 0.f;
+        const float *p = part + (int64_t)gr * N + gc;
+        for (int z = 0; z < splits; ++z) v += p[z * mn];
+        const float hv = (float)e.h[(int64_t)gr * e.ldh + gc];
+        v *= 1.f - hv * hv;
+        const bool ok = gr < e.mvalid && gc < e.nvalid;
+        out[r * OLD + c] = ok ? bf16_bits(v) : (uint16_t)0;
+    }
+    __syncthreads();
+    store_tile(out, e, m0, n0);
+}
+
+__global__ void k_pack_weights(const float *w, int lout, int lin, __bf16 *wb, __bf16 *wbt, int loutp, int linp) {
+    const int64_t total = (int64_t)loutp * linp;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < total; u += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(u / linp), c = (int)(u - (int64_t)r * linp);
+        const float v = (r < lout && c < lin) ? w[(int64_t)r * lin + c] : 0.f;
+        wb[u] = (__bf16)v;
+        wbt[(int64_t)c * loutp + r] = (__bf16)v;
+    }
+}
+
+__global__ void k_pack_x(const float *x, int batch, int in, __bf16 *xb, __bf16 *xt, int bp, int ip) {
+    const int64_t total = (int64_t)bp * ip;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < total; u += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(u / ip), i = (int)(u - (int64_t)b * ip);
+        const float v = (b < batch && i < in) ? x[(int64_t)b * in + i] : 0.f;
+        xb[u] = (__bf16)v;
+        xt[(int64_t)i * bp + b] = (__bf16)v;
+    }
+}
+
+__global__ void k_bias_step(MlpBiasLayers L, int mtiles, int adam, float *w, float *g, float *am, float *av,
+                            const int32_t *adam_t, float lr) {
+    int64_t total = 0;
+    for (int l = 0; l < L.count; ++l) total += L.lout[l];
+    const int32_t step = adam ? *adam_t + 1 : 0;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < total; u += (int64_t)gridDim.x * blockDim.x) {
+        int l = 0;
+        int64_t o = u;
+        while (o >= L.lout[l]) {
+            o -= L.lout[l];
+            ++l;
+        }
+        float db = 0.f;
+        for (int mt = 0; mt < mtiles; ++mt) db += L.colp[l][(int64_t)mt * L.ldcolp[l] + o];
+        const int64_t wi = L.boff[l] + o;
+        if (adam)
+            adam_update(w + wi, am + wi, av + wi, db, lr, step);
+        else
+            g[wi] = db;
+    }
+}
+
+__global__ void k_loss_step(const double *lossp, int nparts, double inv_count, float *loss, int32_t *adam_t,
+                            int adam) {
     __shared__ double sh[256];
     double acc = 0.0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
-        const float d = y[e] - tg[e];
-        g[e] = scale * d;
-        acc += (double)d * (double)d;
-    }
+    for (int b = threadIdx.x; b < nparts; b += 256) acc += lossp[b];
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
-}
-
-__global__ void k_sum_partials(const double *partial, int nb, double inv, float *out) {
-    __shared__ double sh[256];
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) acc += partial[b];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = (float)(sh[0] * inv);
-}
-
-// db[o] = sum_b g[b, o] (column sums in row order).
-__global__ void k_colsum(const float *g, int B, int N, float *db) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= N) return;
-    float acc = 0.f;
-    for (int b = 0; b < B; ++b) acc += g[(int64_t)b * N + o];
-    db[o] = acc;
-}
-
-// Adam on FP32 master weights; refreshes the BF16 compute copy.
-__global__ void k_adam(float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t count, float lr, float b1,
-                       float b2, float eps, float c1, float c2) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
-        const float gv = g[e];
-        const float mv = b1 * m[e] + (1.f - b1) * gv;
-        const float vv = b2 * v[e] + (1.f - b2) * gv * gv;
-        m[e] = mv;
-        v[e] = vv;
-        const float nw = w[e] - lr * (mv / c1) / (sqrtf(vv / c2) + eps);
-        w[e] = nw;
-        wb[e] = (__bf16)nw;
+    if (threadIdx.x == 0) {
+        *loss = (float)(sh[0] * inv_count);
+        if (adam) *adam_t += 1;
     }
 }
 
-__global__ void k_to_bf16(const float *w, __bf16 *wb, int64_t count) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
-        wb[e] = (__bf16)w[e];
-}
-
-// Z0 of problem p: Z0[j, c] = 1 if j == idx[c], else scale_p (mu_q + sigma_q y_pq) with
-// q = j k + c (the network's outputs are the standardised entries of (Z - E) / scale).
-__global__ void k_warm_start(const float *y, int64_t ldy, const float *mu, const float *sigma, const double *scale,
-                             int64_t n, int64_t k, const int32_t *idx, double *z0, int64_t ldz0, int64_t pstride,
-                             int32_t count) {
-    const int64_t total = (int64_t)count * n * k;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = e / (n * k), q = e - p * (n * k);
-        const int64_t j = q / k, c = q - j * k;
-        const double v = (j == idx[c]) ? 1.0 : scale[p] * ((double)mu[q] + (double)sigma[q] * (double)y[p * ldy + q]);
-        z0[p * pstride + j * ldz0 + c] = v;
-    }
-}
-
+// Targets for problem p and output q = j k + c: the remainder of Z_p after the base
+// E + sum_{l <= order} eps_p^l T_l, divided by eps_p^(order + 1), standardised over the
+// batch (mean and deviation summed in problem order).
 __global__ void k_targets(const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz, int64_t pstride,
-                          const int32_t *idx, const double *scale, float *targets, float *mu, float *sigma) {
+                          const int32_t *idx, const double *eps, int32_t order, const double *terms, float *targets,
+                          float *mu, float *sigma) {
     const int64_t nk = n * k;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nk; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = q / k, c = q - j * k;
-        const double e = (j == idx[c]) ? 1.0 : 0.0;
+        const double e0 = (j == idx[c]) ? 1.0 : 0.0;
+        auto rem = [&](int32_t p) {
+            const double ep = eps[p];
+            double base = e0, pw = 1.0;
+            for (int l = 1; l <= order; ++l) {
+                pw *= ep;
+                base += pw * terms[(int64_t)(l - 1) * nk + q];
+            }
+            return (z[p * pstride + j * ldz + c] - base) / (pw * ep);
+        };
         double s = 0.0;
-        for (int32_t p = 0; p < batch; ++p) s += (z[p * pstride + j * ldz + c] - e) / scale[p];
+        for (int32_t p = 0; p < batch; ++p) s += rem(p);
         const double mean = s / batch;
         double v = 0.0;
         for (int32_t p = 0; p < batch; ++p) {
-            const double r = (z[p * pstride + j * ldz + c] - e) / scale[p] - mean;
+            const double r = rem(p) - mean;
             v += r * r;
         }
         double sd = sqrt(v / batch);
         if (!(sd >= 1e-300)) sd = 1.0;
         mu[q] = (float)mean;
         sigma[q] = (float)sd;
-        for (int32_t p = 0; p < batch; ++p)
-            targets[(int64_t)p * nk + q] = (float)(((z[p * pstride + j * ldz + c] - e) / scale[p] - mean) / sd);
+        for (int32_t p = 0; p < batch; ++p) targets[(int64_t)p * nk + q] = (float)((rem(p) - mean) / sd);
     }
 }
 
-inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) / per); }
 inline int capped(int64_t count) {
-    int b = blocks_for(count, 256);
-    return b < 1 ? 1 : (b > 4096 ? 4096 : b);
+    int64_t b = (count + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
 }  // namespace
 
 // ------------------------------------------------------------------ host side
-hipError_t mlp_gemm(hipStream_t s, const void *A, bool a_bf16, int64_t lda, bool a_kcontig, const void *B,
-                    bool b_bf16, int64_t ldb, bool b_kcontig, float *C, int64_t ldc, const float *bias, const float *h,
-                    int64_t ldh, int M, int N, int K, int epi) {
-    dim3 g(blocks_for(N, MT), blocks_for(M, MT));
-#define IPT_GEMM_CASE(TA, TB, AKc, BKc)                                                                        \
-    k_mlp_gemm<TA, TB, AKc, BKc><<<g, 256, 0, s>>>((const TA *)A, lda, (const TB *)B, ldb, C, ldc, bias, h, ldh, M, \
-                                                   N, K, epi)
-    // operand combinations used by the network: A is always FP32 (activations or
-    // gradients); B is the BF16 weight copy (forward, input gradient) or FP32
-    // activations (weight gradient).
-    if (a_bf16) return hipErrorInvalidValue;
-    if (b_bf16) {
-        if (a_kcontig && b_kcontig) IPT_GEMM_CASE(float, __bf16, true, true);
-        else if (a_kcontig && !b_kcontig) IPT_GEMM_CASE(float, __bf16, true, false);
-        else return hipErrorInvalidValue;
-    } else {
-        if (!a_kcontig && !b_kcontig) IPT_GEMM_CASE(float, float, false, false);
-        else if (a_kcontig && b_kcontig) IPT_GEMM_CASE(float, float, true, true);
-        else return hipErrorInvalidValue;
+hipError_t mlp_gemm(hipStream_t s, int mode, const __bf16 *A, int64_t lda, const __bf16 *B, int64_t ldb, int M, int N,
+                    int K, int splits, const MlpEpi &e) {
+    if (M % GT || N % GT || splits < 1 || K % (GK * splits)) return hipErrorInvalidValue;
+    if (mode != MLP_EPI_SPLIT && splits != 1) return hipErrorInvalidValue;
+    const dim3 g(N / GT, M / GT, splits);
+    const int Kc = K / splits;
+    switch (mode) {
+        case MLP_EPI_ACT: k_mlp_gemm<MLP_EPI_ACT><<<g, 256, 0, s>>>(A, lda, B, ldb, Kc, M, N, e); break;
+        case MLP_EPI_MSE: k_mlp_gemm<MLP_EPI_MSE><<<g, 256, 0, s>>>(A, lda, B, ldb, Kc, M, N, e); break;
+        case MLP_EPI_F32: k_mlp_gemm<MLP_EPI_F32><<<g, 256, 0, s>>>(A, lda, B, ldb, Kc, M, N, e); break;
+        case MLP_EPI_GRAD: k_mlp_gemm<MLP_EPI_GRAD><<<g, 256, 0, s>>>(A, lda, B, ldb, Kc, M, N, e); break;
+        case MLP_EPI_ADAM: k_mlp_gemm<MLP_EPI_ADAM><<<g, 256, 0, s>>>(A, lda, B, ldb, Kc, M, N, e); break;
+        case MLP_EPI_SPLIT: k_mlp_gemm<MLP_EPI_SPLIT><<<g, 256, 0, s>>>(A, lda, B, ldb, Kc, M, N, e); break;
+        case MLP_EPI_WARM: k_mlp_gemm<MLP_EPI_WARM><<<g, 256, 0, s>>>(A, lda, B, ldb, Kc, M, N, e); break;
+        default: return hipErrorInvalidValue;
     }
-#undef IPT_GEMM_CASE
     return hipGetLastError();
 }
 
-hipError_t mlp_mse(hipStream_t s, const float *y, const float *tg, float *g, int64_t count, double *partial,
-                   float *loss_dev) {
-    const int nb = capped(count);
-    k_mse<<<nb, 256, 0, s>>>(y, tg, g, count, (float)(2.0 / (double)count), partial);
-    k_sum_partials<<<1, 256, 0, s>>>(partial, nb, 1.0 / (double)count, loss_dev);
+int mlp_split_count(int M, int N, int K) {
+    // enough blocks for the chip (about 256) without splitting K below 256
+    const int tiles = (M / GT) * (N / GT);
+    int want = tiles >= 256 ? 1 : 256 / tiles;
+    int best = 1;
+    for (int sp = 1; sp <= want; ++sp)
+        if (K % (GK * sp) == 0 && K / sp >= 256) best = sp;
+    return best;
+}
+
+hipError_t mlp_split_dtanh(hipStream_t s, const float *part, int splits, int M, int N, const MlpEpi &e) {
+    if (M % GT || N % GT) return hipErrorInvalidValue;
+    k_split_dtanh<<<dim3(N / GT, M / GT), 256, 0, s>>>(part, splits, M, N, e);
     return hipGetLastError();
 }
 
-hipError_t mlp_colsum(hipStream_t s, const float *g, int B, int N, float *db) {
-    k_colsum<<<blocks_for(N, 256), 256, 0, s>>>(g, B, N, db);
+hipError_t mlp_pack_weights(hipStream_t s, const float *w, int lout, int lin, __bf16 *wb, __bf16 *wbt, int loutp,
+                            int linp) {
+    k_pack_weights<<<capped((int64_t)loutp * linp), 256, 0, s>>>(w, lout, lin, wb, wbt, loutp, linp);
     return hipGetLastError();
 }
 
-hipError_t mlp_adam(hipStream_t s, float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t count, float lr,
-                    int step) {
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-    k_adam<<<capped(count), 256, 0, s>>>(w, wb, g, m, v, count, lr, b1, b2, eps, c1, c2);
+hipError_t mlp_pack_x(hipStream_t s, const float *x, int batch, int in, __bf16 *xb, __bf16 *xt, int bp, int ip) {
+    k_pack_x<<<capped((int64_t)bp * ip), 256, 0, s>>>(x, batch, in, xb, xt, bp, ip);
     return hipGetLastError();
 }
 
-hipError_t mlp_to_bf16(hipStream_t s, const float *w, __bf16 *wb, int64_t count) {
-    k_to_bf16<<<capped(count), 256, 0, s>>>(w, wb, count);
+hipError_t mlp_bias_step(hipStream_t s, const MlpBiasLayers &L, int mtiles, int adam, float *w, float *g, float *am,
+                         float *av, const int32_t *adam_t, float lr) {
+    int64_t total = 0;
+    for (int l = 0; l < L.count; ++l) total += L.lout[l];
+    k_bias_step<<<capped(total), 256, 0, s>>>(L, mtiles, adam, w, g, am, av, adam_t, lr);
     return hipGetLastError();
 }
 
-hipError_t mlp_warm_start(hipStream_t s, const float *y, int64_t ldy, const float *mu, const float *sigma,
-                          const double *scale, int64_t n, int64_t k, const int32_t *idx, double *z0, int64_t ldz0,
-                          int64_t pstride, int32_t count) {
-    k_warm_start<<<capped((int64_t)count * n * k), 256, 0, s>>>(y, ldy, mu, sigma, scale, n, k, idx, z0, ldz0,
-                                                                pstride, count);
+hipError_t mlp_loss_step(hipStream_t s, const double *lossp, int nparts, double inv_count, float *loss,
+                         int32_t *adam_t, int adam) {
+    k_loss_step<<<1, 256, 0, s>>>(lossp, nparts, inv_count, loss, adam_t, adam);
     return hipGetLastError();
 }
 
 hipError_t mlp_targets(hipStream_t s, const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz,
-                       int64_t pstride, const int32_t *idx, const double *scale, float *targets, float *mu,
-                       float *sigma) {
-    k_targets<<<capped(n * k), 256, 0, s>>>(z, batch, n, k, ldz, pstride, idx, scale, targets, mu, sigma);
+                       int64_t pstride, const int32_t *idx, const double *eps, int32_t order, const double *terms,
+                       float *targets, float *mu, float *sigma) {
+    k_targets<<<capped(n * k), 256, 0, s>>>(z, batch, n, k, ldz, pstride, idx, eps, order, terms, targets, mu, sigma);
     return hipGetLastError();
 }
 
