@@ -111,16 +111,19 @@ def _round_err(v, d):
     return rv, np.maximum(hi - rv, rv - lo)
 
 
-def network_bf16(params, x, t, dims, round_points=True):
+def network_bf16(params, x, t, dims, round_points=True, row_weights=None):
     """Loss, gradient (parameter layout) and output y of the network as the kernels
     define it, with exact arithmetic between the BF16 roundings, together with bounds
     on |kernel - this| for each: returns (loss, grad, y, loss_bound, grad_bound,
-    y_bound).  round_points=False skips the roundings (the plain FP64 network)."""
+    y_bound).  round_points=False skips the roundings (the plain FP64 network).
+    row_weights (one FP32 weight w_b per example) make the loss
+    sum_b w_b^2 sum_q (y_bq - t_bq)^2 / (batch out); the kernels form w (y - t) and
+    scale w (w (y - t)) in FP32."""
     global _r
     if not round_points:
         saved, _r = _r, lambda a: np.asarray(a, dtype=np.float64)
         try:
-            return network_bf16(params, x, t, dims)
+            return network_bf16(params, x, t, dims, row_weights=row_weights)
         finally:
             _r = saved
     layers = unpack(params, *dims)
@@ -144,13 +147,17 @@ def network_bf16(params, x, t, dims, round_points=True):
     y, ey = hs[-1], ehs[-1]
     count = y.size
     s = 2.0 / count
-    d = y - t
+    w = np.ones((y.shape[0], 1)) if row_weights is None else \
+        np.asarray(row_weights, dtype=np.float32).astype(np.float64).reshape(-1, 1)
+    d = w * (y - t)
     loss = float(np.sum(d * d) / count)
-    ed = ey + U_F32 * (np.abs(d) + ey)
+    # FP32: y - t, then the product with w
+    ed = w * (ey + U_F32 * (np.abs(y - t) + ey)) + U_F32 * (np.abs(d) + w * ey)
     loss_bound = float((np.sum(2.0 * np.abs(d) * ed + ed * ed) + _gamma(66) * np.sum((np.abs(d) + ed) ** 2)) / count
                        + 2.0 * U_F32 * loss)
-    gv = s * d
-    g, eg = _round_err(gv, s * ed + 2.0 * U_F32 * (np.abs(gv) + s * ed))
+    gv = s * w * d
+    # FP32: the scale (rounded once), its product with w, then with d
+    g, eg = _round_err(gv, s * w * ed + 3.0 * U_F32 * (np.abs(gv) + s * w * ed))
     grads = []
     for l in range(len(layers) - 1, -1, -1):
         wr = _r(layers[l][0])

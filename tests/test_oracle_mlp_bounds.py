@@ -17,7 +17,7 @@ def _bf(a):
     return mlp.to_bf16(np.asarray(a, dtype=np.float32)).astype(np.float32)
 
 
-def _emulate(params, x, t, dims, mistake=None):
+def _emulate(params, x, t, dims, mistake=None, row_weights=None):
     """The network at the kernels' rounding points, in FP32 arithmetic."""
     layers = mlp.unpack(params, *dims)
     f = np.float32
@@ -32,10 +32,13 @@ def _emulate(params, x, t, dims, mistake=None):
         else:
             y = pre
     t = t.astype(f)
-    d = y - t
+    w = np.ones((y.shape[0], 1), dtype=f) if row_weights is None else row_weights.astype(f).reshape(-1, 1)
+    d = (y - t) * w
     count = y.size
     loss = float(np.sum(d.astype(np.float64) ** 2) / count)
-    g = _bf(f((1.0 if mistake == "half_scale" else 2.0) / count) * d)
+    if mistake == "unweighted_gradient":
+        w = np.ones_like(w)
+    g = _bf(f((1.0 if mistake == "half_scale" else 2.0) / count) * w * d)
     grads = []
     for l in range(len(layers) - 1, -1, -1):
         wb = _bf(layers[l][0])
@@ -99,3 +102,32 @@ def test_planted_mistakes_fall_outside(mistake):
     el, eg, ey = _emulate(p, x, t, dims, mistake)
     outside = np.sum(np.abs(eg - g) > gb) + np.sum(np.abs(ey - y) > yb) + int(abs(el - loss) > lb)
     assert outside > 0, mistake
+
+
+def test_row_weights():
+    """Per-example weights: without roundings the loss is the weighted plain loss and its
+    gradient equals central finite differences; the FP32 evaluation with the weights lands
+    inside the bounds, and forgetting the weights in the gradient falls outside."""
+    dims = (2, 9, 2, 7)
+    p, x, t = _case(5, dims, 11)
+    w = np.random.default_rng(6).uniform(0.0, 1.0, 11).astype(np.float32)
+    loss, g, *_ = mlp.network_bf16(p, x, t, dims, round_points=False, row_weights=w)
+    ws = w.astype(np.float64).reshape(-1, 1)
+    y = mlp.forward(p, x, dims)[-1]
+    assert abs(loss - np.sum((ws * (y - t)) ** 2) / y.size) <= 1e-14 * loss
+    h = 1e-6
+    for q in np.random.default_rng(7).choice(p.shape[0], 25, replace=False):
+        pp, pm = p.copy(), p.copy()
+        pp[q] += h
+        pm[q] -= h
+        fd = (mlp.network_bf16(pp, x, t, dims, False, w)[0] - mlp.network_bf16(pm, x, t, dims, False, w)[0]) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-7 * max(1.0, np.abs(g).max())
+    dims = (2, 64, 2, 300)
+    p, x, t = _case(1, dims, 37)
+    w = np.random.default_rng(8).uniform(0.0, 1.0, 37).astype(np.float32)
+    loss, g, y, lb, gb, yb = mlp.network_bf16(p, x, t, dims, row_weights=w)
+    el, eg, ey = _emulate(p, x, t, dims, row_weights=w)
+    assert abs(el - loss) <= lb
+    assert np.all(np.abs(eg - g) <= gb)
+    el, eg, ey = _emulate(p, x, t, dims, mistake="unweighted_gradient", row_weights=w)
+    assert np.sum(np.abs(eg - g) > gb) > 0
