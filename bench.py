@@ -330,10 +330,12 @@ def bench_complex(ipt, handle, args):
 def bench_learned(ipt, handle, args):
     """Learned warm start: M(eps) = diag(1..1024) + eps R, R = (R'+R'^T)/2, R' iid N(0,1/n)
     seed 0, k = 32 lowest; the network is trained on 512 eps ~ U[0, 0.08] (seed 1) and
-    tested on 128 new eps (seed 2).  Cold start (Z0 = I, whose first sweep is the free
-    first-order start F(I)) vs MLP warm start (inference time included) vs linear
-    interpolation between the two neighbouring training solutions; FP64 sweeps,
-    tol 1e-10; every warm answer is compared with the cold one."""
+    tested on 128 new eps (seed 2).  Starts compared (FP64 sweeps, tol 1e-10; the cost
+    of a start is included in its eigenpairs/s): cold (Z0 = I, whose first sweep is the
+    free first-order start F(I)); the family's Rayleigh-Schroedinger partial sums of
+    orders 2, 3 and 4 (terms computed once per family); the MLP on top of the series of
+    the configured order; linear interpolation between the two neighbouring training
+    solutions.  Every warm answer is compared with the cold one."""
     import numpy as np
     import torch
     import workloads
@@ -346,47 +348,87 @@ def bench_learned(ipt, handle, args):
     eps_tr = workloads.family_eps(512, 0.0, 0.08, seed=1)
     eps_te = workloads.family_eps(128, 0.0, 0.08, seed=2)
     ztr, _, _, _, t_train_solves = warmstart.solve_family(thd, based, eps_tr, idx, handle=handle, tol=1e-12)
-    ws = warmstart.WarmStarter(n, k, hidden=256, depth=2, seed=0, handle=handle)
-    loss, t_fit = ws.fit(ztr, eps_tr, idx, steps=args.train_steps, lr=1e-3)
-    log("learned: trained %d steps in %.1f s, loss %.3g" % (args.train_steps, t_fit, loss))
-    # cold
-    zc, lc, sc, swc, t_cold = warmstart.solve_family(thd, based, eps_te, idx, handle=handle, tol=1e-10)
-    # learned: inference for all 128 eps, then the warm-started solves
+    ws = warmstart.WarmStarter(n, k, hidden=256, depth=2, seed=0, handle=handle, order=args.learned_order)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    z0 = ws.predict(eps_te, idx)
+    terms4 = ipt.ipt_rs_terms(thd, based, idx, 4, handle=handle)
+    torch.cuda.synchronize()
+    t_terms = time.perf_counter() - t0
+    ws.terms = terms4[:args.learned_order].contiguous() if args.learned_order > 0 else None
+    loss, t_fit = ws.fit(ztr, eps_tr, idx, steps=args.train_steps, lr=1e-3)
+    log("learned: trained %d steps in %.3f s (%.1f us/step), loss %.3g" % (
+        args.train_steps, t_fit, t_fit / max(args.train_steps, 1) * 1e6, loss))
+    res = {}
+    zc, lc, sc, swc, t_cold = warmstart.solve_family(thd, based, eps_te, idx, handle=handle, tol=1e-10)
+    res["cold"] = (sc, swc, t_cold, 0.0)
+    for p_ in (2, 3, 4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        z0 = warmstart.series_start(terms4[:p_].contiguous(), eps_te, idx, handle=handle)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter() - t0
+        _, _, ss, sws, t_s = warmstart.solve_family(thd, based, eps_te, idx, z0=z0, handle=handle, tol=1e-10)
+        res["series%d" % p_] = (ss, sws, t_s, t_start)
+    # learned: inference for all 128 eps (features and parameters already on the
+    # device), then the warm-started solves
+    xin, ein = ws.inputs(eps_te)
+    z0 = ws.predict_from(xin, ein, idx)  # warm-up of the inference path
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    ws.predict_from(xin, ein, idx, z0=z0)
+    ev1.record()
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
+    t_inf_dev = ev0.elapsed_time(ev1) * 1e-3
     zw, lw, sw, sww, t_warm = warmstart.solve_family(thd, based, eps_te, idx, z0=z0, handle=handle, tol=1e-10)
+    res["mlp"] = (sw, sww, t_warm, t_inf)
     # control: linear interpolation between neighbouring training solutions
     order = np.argsort(eps_tr)
     es = eps_tr[order]
     zs = ztr[torch.from_numpy(order).to(dev)]
     zi = torch.empty_like(z0)
-    for p, e in enumerate(eps_te):
+    for p_, e in enumerate(eps_te):
         q = int(np.clip(np.searchsorted(es, e), 1, len(es) - 1))
         w = (e - es[q - 1]) / (es[q] - es[q - 1])
-        zi[p] = (1 - w) * zs[q - 1] + w * zs[q]
+        zi[p_] = (1 - w) * zs[q - 1] + w * zs[q]
     _, _, si, swi, t_interp = warmstart.solve_family(thd, based, eps_te, idx, z0=zi, handle=handle, tol=1e-10)
-    conv_c = int((sc == 0).sum())
-    conv_w = int((sw == 0).sum())
+    res["interp_control"] = (si, swi, t_interp, 0.0)
     za, zb = zw.cpu().numpy(), zc.cpu().numpy()
     an = za / np.linalg.norm(za, axis=1, keepdims=True)
     bn = zb / np.linalg.norm(zb, axis=1, keepdims=True)
     max_angle = float(np.max(2 * np.arcsin(np.minimum(1.0, np.linalg.norm(an - bn, axis=1) / 2))))
     max_dlam = float((lw - lc).abs().max())
-    log("learned: sweeps cold %.2f warm %.2f interp %.2f" % (swc.mean(), sww.mean(), swi.mean()))
+    # MLP kernels: training-step flops (forward, input and weight gradients of every
+    # layer) and the inference flops, against the BF16 dense peak
+    h = 256
+    mac = 2 * h + h * h + h * n * k
+    step_flops = 3 * 2.0 * 512 * mac - 2.0 * 512 * 2 * h  # the first layer has no input gradient
+    step_s = t_fit / max(args.train_steps, 1)
+    inf_flops = 2.0 * 128 * mac
+    roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK["low"],
+            "train_step_us": round(step_s * 1e6, 2), "train_step_flops": step_flops,
+            "train_achieved": round(step_flops / step_s / 1e12, 2),
+            "train_frac": round(step_flops / step_s / 1e12 / PEAK["low"], 4),
+            "inference_us_for_128": round(t_inf * 1e6, 2), "inference_device_us_for_128": round(t_inf_dev * 1e6, 2),
+            "inference_flops": inf_flops, "inference_achieved": round(inf_flops / t_inf_dev / 1e12, 2),
+            "note": "a training step is one graph replay, host-clocked over the run; inference on the stream's "
+                    "events (the host-clocked figure adds the call's launches and synchronisation)"}
+    log("learned: mean sweeps " + ", ".join("%s %.3f" % (nm, v[1].mean()) for nm, v in res.items()))
+    total = 128 * k
     return {"workload": "family diag(1..1024)+eps*R, k=32 lowest, train 512 eps~U[0,0.08], test 128 new eps, "
                         "FP64 sweeps, tol 1e-10",
-            "network": "2 -> 256 -> 256 -> 32768 tanh MLP, BF16 weights / FP32 accumulation, Adam, %d steps"
-                       % args.train_steps,
-            "train_loss": loss, "train_seconds": round(t_fit, 3), "train_solves_seconds": round(t_train_solves, 3),
-            "mean_sweeps": {"cold": float(swc.mean()), "mlp": float(sww.mean()), "interp_control": float(swi.mean())},
-            "eigenpairs_per_s": {"cold": round(conv_c / t_cold, 1),
-                                 "mlp_incl_inference": round(conv_w / (t_warm + t_inf), 1),
-                                 "interp_control": round(int((si == 0).sum()) / t_interp, 1)},
-            "mlp_inference_ms_for_128": round(t_inf * 1e3, 3),
-            "converged": {"cold": conv_c, "mlp": conv_w, "of": 128 * k},
+            "network": "2 -> 256 -> 256 -> 32768 tanh MLP on the remainder after the order-%d series, BF16 GEMM "
+                       "operands / FP32 accumulation, Adam, %d steps" % (args.learned_order, args.train_steps),
+            "train_loss": loss, "train_seconds": round(t_fit, 4), "train_solves_seconds": round(t_train_solves, 3),
+            "series_terms_seconds": round(t_terms, 4),
+            "mean_sweeps": {nm: float(v[1].mean()) for nm, v in res.items()},
+            "eigenpairs_per_s": {nm: round(int((v[0] == 0).sum()) / (v[2] + v[3]), 1) for nm, v in res.items()},
+            "converged": {nm: int((v[0] == 0).sum()) for nm, v in res.items()}, "of": total,
+            "start_seconds": {nm: round(v[3], 6) for nm, v in res.items()},
+            "mlp_inference_ms_for_128": round(t_inf * 1e3, 4),
+            "roofline": roof,
             "warm_vs_cold": {"max_angle": max_angle, "max_abs_dlambda": max_dlam}}
 
 
@@ -406,6 +448,8 @@ def main():
                          "continuation, complex ('' for none)")
     ap.add_argument("--complex-n", type=int, default=4096, help="size of the complex workload")
     ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the warm-start network")
+    ap.add_argument("--learned-order", type=int, default=2,
+                    help="order of the series partial sum the warm-start network corrects")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense workload (profiling of the others)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to scale HBM counters) and exit")

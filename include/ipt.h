@@ -320,17 +320,21 @@ ipt_status ipt_batched_set_tiles(ipt_handle h, const int32_t *tiles);
 /*
  * Learned warm start: a small MLP x -> [Linear -> tanh] x depth -> Linear -> y, trained
  * and evaluated with the library's own kernels (BF16 MFMA GEMMs with FP32
- * accumulation, MSE loss, Adam on FP32 master weights with a BF16 compute copy).  It
- * predicts Z0 for a parametrised family M(eps) = D + eps R (initial guesses, Sec. 7);
- * the solve it warm-starts still certifies every column with FP64 sweeps, so the
- * network can change the cost of a solve but not its answer.
+ * accumulation, MSE loss, Adam on FP32 master weights with BF16 compute copies).  It
+ * predicts Z0 for a parametrised family M(eps) = D + eps R (initial guesses, Sec. 7) on
+ * top of the family's Rayleigh-Schroedinger series (ipt_rs_terms); the solve it
+ * warm-starts still certifies every column with FP64 sweeps, so the network can change
+ * the cost of a solve but not its answer.
  * Parameters are stored layer by layer as W_l (out_l x in_l, row-major) then b_l.
+ * The kernels round to BF16 (from FP32, to nearest even): the input x, the weights,
+ * each hidden activation, the output gradient 2 (y - t) / (batch out) and each hidden
+ * gradient; products accumulate in FP32.
  * All arrays are device pointers; x is batch x in_dim and y / targets batch x out_dim,
  * row-major FP32.  The MLP runs on its handle's stream; destroy it before the handle.
  */
 typedef struct ipt_mlp_context *ipt_mlp;
 
-/* hidden >= 1, depth >= 1 hidden layers, in_dim/out_dim >= 1; weights drawn from
+/* hidden >= 1, 1 <= depth <= 16 hidden layers, in_dim/out_dim >= 1; weights drawn from
  * Glorot-uniform with a 64-bit seed, biases zero.  Errors: IPT_EINVAL, IPT_ENOMEM, IPT_EHIP. */
 ipt_status ipt_mlp_create(ipt_handle h, int32_t in_dim, int32_t hidden, int32_t depth, int32_t out_dim, uint64_t seed,
                           ipt_mlp *out);
@@ -339,33 +343,57 @@ ipt_status ipt_mlp_destroy(ipt_mlp m);
 int64_t ipt_mlp_num_params(ipt_mlp m);
 ipt_status ipt_mlp_get_params(ipt_mlp m, float *dst);
 ipt_status ipt_mlp_set_params(ipt_mlp m, const float *src);
-/* y = network(x) with the BF16 weight copy. */
+/* y = network(x). */
 ipt_status ipt_mlp_forward(ipt_mlp m, const float *x, int32_t batch, float *y);
-/* Mean squared error of network(x) against targets and its gradient with respect to
- * every parameter (no update).  loss: host float. */
-ipt_status ipt_mlp_loss_grad(ipt_mlp m, const float *x, const float *targets, int32_t batch, float *loss,
-                             float *grad);
-/* `steps` full-batch Adam steps (beta 0.9/0.999, eps 1e-8) at learning rate lr;
- * *loss (host) receives the loss before the last update. */
-ipt_status ipt_mlp_train(ipt_mlp m, const float *x, const float *targets, int32_t batch, int32_t steps, float lr,
-                         float *loss);
-/* Warm starts for `batch` problems: y = network(x), then for problem p
- * Z0_p[j, c] = 1 if j == idx[c], else scale[p] (mu[q] + sigma[q] y[p, q]) with q = j k + c
- * (out_dim must equal n k).  z0 of problem p starts at z0 + p * pstride (leading
- * dimension ldz0 >= k). */
+/* Mean squared error sum_b w_b^2 sum_q (y_bq - t_bq)^2 / (batch out_dim) of network(x)
+ * against targets, with per-example weights w (FP32 [batch]; NULL: all 1), and its
+ * gradient with respect to every parameter (no update).  loss: host float. */
+ipt_status ipt_mlp_loss_grad(ipt_mlp m, const float *x, const float *targets, const float *weights, int32_t batch,
+                             float *loss, float *grad);
+/* `steps` full-batch Adam steps (beta 0.9/0.999, eps 1e-8) at learning rate lr on the
+ * weighted loss of ipt_mlp_loss_grad, each replayed from one captured graph; *loss
+ * (host) receives the loss before the last update. */
+ipt_status ipt_mlp_train(ipt_mlp m, const float *x, const float *targets, const float *weights, int32_t batch,
+                         int32_t steps, float lr, float *loss);
+/* Warm starts for `batch` family members with parameters eps[p]: y = network(x), then
+ *   Z0_p[j, c] = 1 if j == idx[c], else
+ *                sum_{l=1..order} eps_p^l T_l[j, c] + eps_p^(order+1) (mu[q] + sigma[q] y[p, q]),
+ * q = j k + c (out_dim must equal n k), T_l the terms of ipt_rs_terms (order x n x k,
+ * NULL when order = 0).  z0 of problem p starts at z0 + p * pstride (leading dimension
+ * ldz0 >= k).  0 <= order <= 16. */
 ipt_status ipt_mlp_predict_z0(ipt_mlp m, const float *x, int32_t batch, const float *mu, const float *sigma,
-                              const double *scale, int64_t n, int64_t k, const int32_t *idx, double *z0, int64_t ldz0,
-                              int64_t pstride);
+                              const double *eps, int32_t order, const double *terms, int64_t n, int64_t k,
+                              const int32_t *idx, double *z0, int64_t ldz0, int64_t pstride);
 
 /* Standardised training targets for the warm-start network.  For problem p and output
- * q = j k + c: r_pq = (Z_p[j, c] - [j == idx[c]]) / scale[p]; mu_q and sigma_q are the mean
- * and standard deviation of r_.q over the batch, summed in problem order (sigma_q = 1
- * where it would be below 1e-300); targets[p, q] = (r_pq - mu_q) / sigma_q.  Z_p starts at
- * z + p * pstride with leading dimension ldz; targets is batch x (n k) FP32; mu and sigma
- * are (n k) FP32.  Runs on the handle's stream and returns when done. */
+ * q = j k + c: r_pq = (Z_p[j, c] - [j == idx[c]] - sum_{l=1..order} eps_p^l T_l[j, c]) /
+ * eps_p^(order+1); mu_q and sigma_q are the mean and standard deviation of r_.q over the
+ * batch, weighted by weights[p]^2 (FP64 [batch]; NULL: uniform) and summed in problem
+ * order (sigma_q = 1 where it would be below 1e-300); targets[p, q] = (r_pq - mu_q) /
+ * sigma_q.  Z_p starts at z + p * pstride with leading dimension ldz; targets is
+ * batch x (n k) FP32; mu and sigma are (n k) FP32; eps[p] must be non-zero.  Runs on the
+ * handle's stream and returns when done. */
 ipt_status ipt_mlp_targets(ipt_handle h, const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz,
-                           int64_t pstride, const int32_t *idx, const double *scale, float *targets, float *mu,
-                           float *sigma);
+                           int64_t pstride, const int32_t *idx, const double *eps, int32_t order, const double *terms,
+                           const double *weights, float *targets, float *mu, float *sigma);
+
+/* Rayleigh-Schroedinger terms of M = D + Delta on the requested columns (App. B, eq.
+ * ARS-alpha; the series IPT contains, App. C): with Z^[0] = E and d^[s]_c = (Delta Z^[s])_{idx[c] c},
+ *   Z^[l] = G o (sum_{s=0}^{l-1} Z^[l-1-s] diag(d^[s]) - Delta Z^[l-1]),  l = 1..order,
+ * so that sum_l eps^l Z^[l] is the perturbation series of D + eps Delta.  theta [n],
+ * delta n x n row-major (lda >= n), idx [k]; terms receives order x n x k FP64 (term l
+ * row-major n x k at terms + (l-1) n k).  FP64 throughout.  Errors: IPT_EINVAL (sizes,
+ * NULL pointers, an index outside [0, n), 1 <= order <= 16), IPT_EDEGENERATE
+ * (theta_j == theta_idx[c] for j != idx[c], or theta not finite). */
+ipt_status ipt_rs_terms(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                        const int32_t *idx, int32_t order, double *terms);
+
+/* Series warm starts Z0_p = E + sum_{l=1..order} eps[p]^l T_l (the Rayleigh-Schroedinger
+ * partial sum of the family member D + eps[p] Delta, App. B) for p < count, from the terms
+ * of ipt_rs_terms (order x n x k; NULL when order = 0); entry idx[c] of column c is 1.
+ * z0 of problem p starts at z0 + p * pstride (leading dimension ldz0 >= k). */
+ipt_status ipt_rs_start(ipt_handle h, const double *eps, int32_t count, int32_t order, const double *terms, int64_t n,
+                        int64_t k, const int32_t *idx, double *z0, int64_t ldz0, int64_t pstride);
 
 /* Static description of a status code. */
 const char *ipt_status_string(ipt_status s);

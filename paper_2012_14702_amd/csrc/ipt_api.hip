@@ -1288,18 +1288,27 @@ ipt_status ipt_batched_set_tiles(ipt_handle h, const int32_t *tiles) {
 struct ipt_mlp_context {
     ipt_handle h = nullptr;
     int in = 0, hid = 0, depth = 0, out = 0;
+    int nl = 0;                        // linear layers (depth + 1)
+    int ip = 0, hp = 0, op = 0;        // in, hidden, out padded to MLP_TILE
     int64_t nparam = 0;
-    std::vector<int64_t> woff, boff;  // per linear layer (depth + 1 layers)
-    std::vector<int> lin, lout;
-    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
-    __bf16 *wb = nullptr;
-    float *act = nullptr;  // activations H_1..H_depth (batch x hid each)
-    float *dpre = nullptr, *dpre2 = nullptr;  // gradient scratch (batch x hid)
-    float *y = nullptr, *gy = nullptr;        // output and its gradient (batch x out)
-    double *partial = nullptr;
+    std::vector<int64_t> woff, boff;   // per linear layer
+    std::vector<int> lin, lout, linp, loutp;
+    float *w = nullptr, *g = nullptr, *am = nullptr, *av = nullptr;  // FP32 weights, gradient, Adam moments
+    void *wmem = nullptr;              // BF16 copies W_l and W_l^T of every layer
+    std::vector<__bf16 *> wb, wbt;
+    int32_t *adam_t = nullptr;         // Adam steps taken (device)
     float *loss_dev = nullptr;
-    int cap_batch = 0;
-    int adam_step = 0;
+    // batch buffers, for batches up to cap_bp (a multiple of MLP_TILE)
+    int cap_bp = 0;
+    void *bmem = nullptr;
+    __bf16 *xb = nullptr, *xt = nullptr;
+    std::vector<__bf16 *> hb, ht;      // hidden activations H_1..H_depth and their transposes
+    __bf16 *gy = nullptr, *gyt = nullptr;
+    __bf16 *gp[2] = {nullptr, nullptr}, *gpt[2] = {nullptr, nullptr};
+    float *split = nullptr;
+    std::vector<float *> colp;
+    double *lossp = nullptr;
+    hipStream_t cap = nullptr;         // capture stream of the training step's graph
 };
 
 namespace {
@@ -1312,70 +1321,200 @@ ipt_status mlp_fail(ipt_mlp m, ipt_status st, const std::string &msg) { return f
         if (e_ != hipSuccess) return mlp_fail((m), IPT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+inline int pad_tile(int v) { return (int)round_up(v, MLP_TILE); }
+
 void mlp_free_batch(ipt_mlp m) {
-    for (void *p : {(void *)m->act, (void *)m->dpre, (void *)m->dpre2, (void *)m->y, (void *)m->gy, (void *)m->partial})
-        if (p) (void)hipFree(p);
-    m->act = m->dpre = m->dpre2 = m->y = m->gy = nullptr;
-    m->partial = nullptr;
-    m->cap_batch = 0;
+    if (m->bmem) (void)hipFree(m->bmem);
+    m->bmem = nullptr;
+    m->cap_bp = 0;
 }
+
+// split counts of the three products of layer l at padded batch bp
+int split_dh(const ipt_mlp m, int bp, int l) { return mlp_split_count(bp, m->linp[l], m->loutp[l]); }
+int split_fwd(const ipt_mlp m, int bp, int l) { return mlp_split_count(bp, m->loutp[l], m->linp[l]); }
+int split_dw(const ipt_mlp m, int bp, int l) { return mlp_split_count(m->loutp[l], m->linp[l], bp); }
 
 ipt_status mlp_ensure_batch(ipt_mlp m, int batch) {
-    if (batch <= m->cap_batch) return IPT_OK;
+    const int bp = pad_tile(batch);
+    if (bp <= m->cap_bp) return IPT_OK;
     IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
     mlp_free_batch(m);
-    const size_t nb = (size_t)batch;
-    if (hipMalloc(&m->act, sizeof(float) * nb * m->hid * m->depth) != hipSuccess ||
-        hipMalloc(&m->dpre, sizeof(float) * nb * m->hid) != hipSuccess ||
-        hipMalloc(&m->dpre2, sizeof(float) * nb * m->hid) != hipSuccess ||
-        hipMalloc(&m->y, sizeof(float) * nb * m->out) != hipSuccess ||
-        hipMalloc(&m->gy, sizeof(float) * nb * m->out) != hipSuccess ||
-        hipMalloc(&m->partial, sizeof(double) * 4096) != hipSuccess) {
+    int64_t split_floats = 0;
+    for (int l = 0; l < m->nl; ++l) {
+        if (l > 0) split_floats = std::max(split_floats, (int64_t)split_dh(m, bp, l) * bp * m->linp[l]);
+        if (l < m->depth) split_floats = std::max(split_floats, (int64_t)split_fwd(m, bp, l) * bp * m->loutp[l]);
+        split_floats = std::max(split_floats, (int64_t)split_dw(m, bp, l) * m->loutp[l] * m->linp[l]);
+    }
+    auto layout = [&](Carve &cv) {
+        m->xb = cv.take<__bf16>((size_t)bp * m->ip);
+        m->xt = cv.take<__bf16>((size_t)bp * m->ip);
+        m->hb.assign(m->depth, nullptr);
+        m->ht.assign(m->depth, nullptr);
+        for (int l = 0; l < m->depth; ++l) {
+            m->hb[l] = cv.take<__bf16>((size_t)bp * m->hp);
+            m->ht[l] = cv.take<__bf16>((size_t)bp * m->hp);
+        }
+        m->gy = cv.take<__bf16>((size_t)bp * m->op);
+        m->gyt = cv.take<__bf16>((size_t)bp * m->op);
+        for (int q = 0; q < 2; ++q) {
+            m->gp[q] = cv.take<__bf16>((size_t)bp * m->hp);
+            m->gpt[q] = cv.take<__bf16>((size_t)bp * m->hp);
+        }
+        m->split = cv.take<float>((size_t)std::max<int64_t>(split_floats, 1));
+        m->colp.assign(m->nl, nullptr);
+        for (int l = 0; l < m->nl; ++l) m->colp[l] = cv.take<float>((size_t)(bp / MLP_SLAB) * m->loutp[l]);
+        m->lossp = cv.take<double>((size_t)(bp / MLP_TILE) * (m->op / MLP_TILE));
+    };
+    Carve sizing;
+    layout(sizing);
+    if (hipMalloc(&m->bmem, sizing.off + 256) != hipSuccess) {
         (void)hipGetLastError();
-        mlp_free_batch(m);
+        m->bmem = nullptr;
         return mlp_fail(m, IPT_ENOMEM, "MLP activation buffers");
     }
-    m->cap_batch = batch;
+    Carve cv;
+    cv.base = (char *)m->bmem;
+    layout(cv);
+    m->cap_bp = bp;
     return IPT_OK;
 }
 
-// Forward pass: activations into m->act, output into y.
-ipt_status mlp_forward_impl(ipt_mlp m, const float *x, int batch, float *y) {
-    hipStream_t s = m->h->stream;
-    const float *hin = x;
-    for (int l = 0; l <= m->depth; ++l) {
-        const bool last = l == m->depth;
-        float *dst = last ? y : m->act + (size_t)l * batch * m->hid;
-        IPT_MHIP(m, mlp_gemm(s, hin, false, m->lin[l], true, m->wb + m->woff[l], true, m->lin[l], true, dst,
-                             m->lout[l], m->w + m->boff[l], nullptr, 0, batch, m->lout[l], m->lin[l],
-                             last ? 0 : 1));
-        hin = dst;
+MlpEpi epi0() {
+    MlpEpi e;
+    memset(&e, 0, sizeof(e));
+    return e;
+}
+
+// Input packing and the hidden layers: H_l = tanh(H_{l-1} W_l^T + b_l), stored with H_l^T.
+hipError_t mlp_hidden(ipt_mlp m, hipStream_t s, int batch) {
+    const int bp = pad_tile(batch);
+    for (int l = 0; l < m->depth; ++l) {
+        MlpEpi e = epi0();
+        e.mvalid = batch;
+        e.nvalid = m->lout[l];
+        e.bias = m->w + m->boff[l];
+        e.tanh_act = 1;
+        e.c16 = m->hb[l];
+        e.ldc16 = m->hp;
+        e.ct16 = m->ht[l];
+        e.ldct16 = bp;
+        const __bf16 *A = l == 0 ? m->xb : m->hb[l - 1];
+        const int S = split_fwd(m, bp, l);
+        hipError_t err;
+        if (S > 1) {  // few tiles: split K, then bias and tanh in the reduction
+            MlpEpi es = epi0();
+            es.c32 = m->split;
+            err = mlp_gemm(s, MLP_EPI_SPLIT, A, m->linp[l], m->wb[l], m->linp[l], bp, m->loutp[l], m->linp[l], S, es);
+            if (err == hipSuccess) err = mlp_split_reduce(s, MLP_EPI_ACT, m->split, S, bp, m->loutp[l], e);
+        } else {
+            err = mlp_gemm(s, MLP_EPI_ACT, A, m->linp[l], m->wb[l], m->linp[l], bp, m->loutp[l], m->linp[l], 1, e);
+        }
+        if (err != hipSuccess) return err;
     }
-    return IPT_OK;
+    return hipSuccess;
 }
 
-// Loss and gradient of every parameter into m->g (forward included).
-ipt_status mlp_backward_impl(ipt_mlp m, const float *x, const float *tg, int batch) {
-    hipStream_t s = m->h->stream;
-    if (ipt_status st = mlp_forward_impl(m, x, batch, m->y)) return st;
-    IPT_MHIP(m, mlp_mse(s, m->y, tg, m->gy, (int64_t)batch * m->out, m->partial, m->loss_dev));
-    const float *dcur = m->gy;  // gradient of the current layer's pre-activation
-    float *bufs[2] = {m->dpre, m->dpre2};
-    for (int l = m->depth; l >= 0; --l) {
-        const float *hin = l == 0 ? x : m->act + (size_t)(l - 1) * batch * m->hid;
-        // dW_l = dPre_l^T H_{l-1}: M = out_l, N = in_l, K = batch (both operands r-contiguous)
-        IPT_MHIP(m, mlp_gemm(s, dcur, false, m->lout[l], false, hin, false, m->lin[l], false, m->g + m->woff[l],
-                             m->lin[l], nullptr, nullptr, 0, m->lout[l], m->lin[l], batch, 0));
-        IPT_MHIP(m, mlp_colsum(s, dcur, batch, m->lout[l], m->g + m->boff[l]));
+// One step of the loss and its gradient after the hidden layers: output layer with the
+// loss epilogue, then layer by layer the input gradient (split K, with the tanh
+// derivative) before the weight gradient (which, with adam, updates W_l and its BF16
+// copies), then the biases and the loss.
+hipError_t mlp_backward(ipt_mlp m, hipStream_t s, const float *tg, const float *roww, int batch, bool adam, float lr) {
+    const int bp = pad_tile(batch), L = m->nl, last = L - 1;
+    hipError_t err;
+    {
+        MlpEpi e = epi0();
+        e.mvalid = batch;
+        e.nvalid = m->out;
+        e.bias = m->w + m->boff[last];
+        e.tgt = tg;
+        e.roww = roww;
+        e.ldt = m->out;
+        e.scale = (float)(2.0 / ((double)batch * (double)m->out));
+        e.lossp = m->lossp;
+        e.c16 = m->gy;
+        e.ldc16 = m->op;
+        e.ct16 = m->gyt;
+        e.ldct16 = bp;
+        e.colp = m->colp[last];
+        e.ldcolp = m->op;
+        if ((err = mlp_gemm(s, MLP_EPI_MSE, m->hb[m->depth - 1], m->hp, m->wb[last], m->linp[last], bp, m->op,
+                            m->linp[last], 1, e)) != hipSuccess)
+            return err;
+    }
+    const __bf16 *cur = m->gy, *curt = m->gyt;
+    int64_t ldcur = m->op;
+    for (int l = last; l >= 0; --l) {
         if (l > 0) {
-            // dPre_{l-1} = (dPre_l W_l) o (1 - H_{l-1}^2): M = batch, N = in_l, K = out_l
-            float *dnext = bufs[l & 1];
-            IPT_MHIP(m, mlp_gemm(s, dcur, false, m->lout[l], true, m->wb + m->woff[l], true, m->lin[l], false, dnext,
-                                 m->lin[l], nullptr, hin, m->lin[l], batch, m->lin[l], m->lout[l], 2));
-            dcur = dnext;
+            const int S = split_dh(m, bp, l);
+            MlpEpi es = epi0();
+            es.c32 = m->split;
+            if ((err = mlp_gemm(s, MLP_EPI_SPLIT, cur, ldcur, m->wbt[l], m->loutp[l], bp, m->linp[l], m->loutp[l], S,
+                                es)) != hipSuccess)
+                return err;
+            const int q = l & 1;
+            MlpEpi e = epi0();
+            e.mvalid = batch;
+            e.nvalid = m->lin[l];
+            e.h = m->hb[l - 1];
+            e.ldh = m->hp;
+            e.c16 = m->gp[q];
+            e.ldc16 = m->hp;
+            e.ct16 = m->gpt[q];
+            e.ldct16 = bp;
+            e.colp = m->colp[l - 1];
+            e.ldcolp = m->loutp[l - 1];
+            if ((err = mlp_split_reduce(s, MLP_EPI_SPLIT, m->split, S, bp, m->linp[l], e)) != hipSuccess) return err;
+        }
+        MlpEpi e = epi0();
+        e.mvalid = m->lout[l];
+        e.nvalid = m->lin[l];
+        if (adam) {
+            e.w = m->w + m->woff[l];
+            e.am = m->am + m->woff[l];
+            e.av = m->av + m->woff[l];
+            e.adam_t = m->adam_t;
+            e.lr = lr;
+            e.c16 = m->wb[l];
+            e.ldc16 = m->linp[l];
+            e.ct16 = m->wbt[l];
+            e.ldct16 = m->loutp[l];
+        } else {
+            e.c32 = m->g + m->woff[l];
+            e.ldc32 = m->lin[l];
+        }
+        const __bf16 *B = l == 0 ? m->xt : m->ht[l - 1];
+        const int S = adam ? split_dw(m, bp, l) : 1;
+        if (S > 1) {  // few tiles: split K (the batch), then Adam in the reduction
+            MlpEpi es = epi0();
+            es.c32 = m->split;
+            if ((err = mlp_gemm(s, MLP_EPI_SPLIT, curt, bp, B, bp, m->loutp[l], m->linp[l], bp, S, es)) != hipSuccess ||
+                (err = mlp_split_reduce(s, MLP_EPI_ADAM, m->split, S, m->loutp[l], m->linp[l], e)) != hipSuccess)
+                return err;
+        } else if ((err = mlp_gemm(s, adam ? MLP_EPI_ADAM : MLP_EPI_GRAD, curt, bp, B, bp, m->loutp[l], m->linp[l], bp,
+                                   1, e)) != hipSuccess) {
+            return err;
+        }
+        if (l > 0) {
+            cur = m->gp[l & 1];
+            curt = m->gpt[l & 1];
+            ldcur = m->hp;
         }
     }
-    return IPT_OK;
+    MlpBiasLayers bl;
+    memset(&bl, 0, sizeof(bl));
+    bl.count = L;
+    for (int l = 0; l < L; ++l) {
+        bl.lout[l] = m->lout[l];
+        bl.boff[l] = m->boff[l];
+        bl.colp[l] = m->colp[l];
+        bl.ldcolp[l] = m->loutp[l];
+        // the output layer's sums come per GEMM tile, the hidden layers' per reduction slab
+        bl.mtiles[l] = l == L - 1 ? bp / MLP_TILE : bp / MLP_SLAB;
+    }
+    if ((err = mlp_bias_step(s, bl, adam ? 1 : 0, m->w, m->g, m->am, m->av, m->adam_t, lr)) != hipSuccess)
+        return err;
+    return mlp_loss_step(s, m->lossp, (bp / MLP_TILE) * (m->op / MLP_TILE),
+                         1.0 / ((double)batch * (double)m->out), m->loss_dev, m->adam_t, adam ? 1 : 0);
 }
 
 uint64_t splitmix64(uint64_t &x) {
@@ -1383,6 +1522,20 @@ uint64_t splitmix64(uint64_t &x) {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
     return z ^ (z >> 31);
+}
+
+hipError_t mlp_pack_all_weights(ipt_mlp m, hipStream_t s) {
+    for (int l = 0; l < m->nl; ++l) {
+        hipError_t e = mlp_pack_weights(s, m->w + m->woff[l], m->lout[l], m->lin[l], m->wb[l], m->wbt[l], m->loutp[l],
+                                        m->linp[l]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+ipt_status mlp_check_x(ipt_mlp m, const float *x, int32_t batch) {
+    if (!x || batch < 1 || batch > (1 << 20)) return mlp_fail(m, IPT_EINVAL, "bad MLP input (batch in [1, 2^20])");
+    return IPT_OK;
 }
 
 }  // namespace
@@ -1393,8 +1546,9 @@ ipt_status ipt_mlp_create(ipt_handle h, int32_t in_dim, int32_t hidden, int32_t 
                           ipt_mlp *out) {
     if (!h || !out) return IPT_EINVAL;
     *out = nullptr;
-    if (in_dim < 1 || hidden < 1 || depth < 1 || depth > 16 || out_dim < 1)
-        return fail(h, IPT_EINVAL, "MLP sizes must be >= 1 (depth <= 16)");
+    if (in_dim < 1 || hidden < 1 || depth < 1 || depth > 16 || out_dim < 1 || in_dim > (1 << 16) ||
+        hidden > (1 << 16) || out_dim > (1 << 26))
+        return fail(h, IPT_EINVAL, "MLP sizes must be >= 1 (depth <= 16, in and hidden <= 2^16, out <= 2^26)");
     DeviceGuard guard(h->device);
     ipt_mlp m = new (std::nothrow) ipt_mlp_context();
     if (!m) return IPT_ENOMEM;
@@ -1403,15 +1557,22 @@ ipt_status ipt_mlp_create(ipt_handle h, int32_t in_dim, int32_t hidden, int32_t 
     m->hid = hidden;
     m->depth = depth;
     m->out = out_dim;
-    int64_t off = 0;
+    m->nl = depth + 1;
+    m->ip = pad_tile(in_dim);
+    m->hp = pad_tile(hidden);
+    m->op = pad_tile(out_dim);
+    int64_t off = 0, wbytes = 0;
     for (int l = 0; l <= depth; ++l) {
         const int li = l == 0 ? in_dim : hidden, lo = l == depth ? out_dim : hidden;
         m->lin.push_back(li);
         m->lout.push_back(lo);
+        m->linp.push_back(pad_tile(li));
+        m->loutp.push_back(pad_tile(lo));
         m->woff.push_back(off);
         off += (int64_t)li * lo;
         m->boff.push_back(off);
         off += lo;
+        wbytes += 2 * (int64_t)m->linp[l] * m->loutp[l];
     }
     m->nparam = off;
     std::vector<float> host(off, 0.f);
@@ -1425,16 +1586,24 @@ ipt_status ipt_mlp_create(ipt_handle h, int32_t in_dim, int32_t hidden, int32_t 
     }
     const size_t bytes = sizeof(float) * off;
     if (hipMalloc(&m->w, bytes) != hipSuccess || hipMalloc(&m->g, bytes) != hipSuccess ||
-        hipMalloc(&m->m, bytes) != hipSuccess || hipMalloc(&m->v, bytes) != hipSuccess ||
-        hipMalloc(&m->wb, sizeof(__bf16) * off) != hipSuccess || hipMalloc(&m->loss_dev, sizeof(float)) != hipSuccess) {
+        hipMalloc(&m->am, bytes) != hipSuccess || hipMalloc(&m->av, bytes) != hipSuccess ||
+        hipMalloc(&m->wmem, sizeof(__bf16) * wbytes + 256 * 2 * m->nl) != hipSuccess ||
+        hipMalloc(&m->adam_t, sizeof(int32_t)) != hipSuccess || hipMalloc(&m->loss_dev, sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         ipt_mlp_destroy(m);
         return fail(h, IPT_ENOMEM, "MLP parameter buffers");
     }
+    Carve cv;
+    cv.base = (char *)m->wmem;
+    for (int l = 0; l <= depth; ++l) {
+        m->wb.push_back(cv.take<__bf16>((size_t)m->linp[l] * m->loutp[l]));
+        m->wbt.push_back(cv.take<__bf16>((size_t)m->linp[l] * m->loutp[l]));
+    }
     hipStream_t s = h->stream;
     if (hipMemcpyAsync(m->w, host.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemsetAsync(m->m, 0, bytes, s) != hipSuccess || hipMemsetAsync(m->v, 0, bytes, s) != hipSuccess ||
-        mlp_to_bf16(s, m->w, m->wb, off) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        hipMemsetAsync(m->am, 0, bytes, s) != hipSuccess || hipMemsetAsync(m->av, 0, bytes, s) != hipSuccess ||
+        hipMemsetAsync(m->adam_t, 0, sizeof(int32_t), s) != hipSuccess || mlp_pack_all_weights(m, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
         ipt_mlp_destroy(m);
         return fail(h, IPT_EHIP, "MLP initialisation");
     }
@@ -1447,8 +1616,10 @@ ipt_status ipt_mlp_destroy(ipt_mlp m) {
     DeviceGuard guard(m->h->device);
     (void)hipStreamSynchronize(m->h->stream);
     mlp_free_batch(m);
-    for (void *p : {(void *)m->w, (void *)m->g, (void *)m->m, (void *)m->v, (void *)m->wb, (void *)m->loss_dev})
+    for (void *p : {(void *)m->w, (void *)m->g, (void *)m->am, (void *)m->av, (void *)m->wmem, (void *)m->adam_t,
+                    (void *)m->loss_dev})
         if (p) (void)hipFree(p);
+    if (m->cap) (void)hipStreamDestroy(m->cap);
     delete m;
     return IPT_OK;
 }
@@ -1467,76 +1638,180 @@ ipt_status ipt_mlp_set_params(ipt_mlp m, const float *src) {
     if (!m || !src) return IPT_EINVAL;
     DeviceGuard guard(m->h->device);
     IPT_MHIP(m, hipMemcpyAsync(m->w, src, sizeof(float) * m->nparam, hipMemcpyDeviceToDevice, m->h->stream));
-    IPT_MHIP(m, mlp_to_bf16(m->h->stream, m->w, m->wb, m->nparam));
+    IPT_MHIP(m, mlp_pack_all_weights(m, m->h->stream));
     IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
     return IPT_OK;
 }
 
 ipt_status ipt_mlp_forward(ipt_mlp m, const float *x, int32_t batch, float *y) {
-    if (!m || !x || !y || batch < 1) return m ? mlp_fail(m, IPT_EINVAL, "bad MLP forward arguments") : IPT_EINVAL;
+    if (!m) return IPT_EINVAL;
+    if (ipt_status st = mlp_check_x(m, x, batch)) return st;
+    if (!y) return mlp_fail(m, IPT_EINVAL, "y must be non-NULL");
     DeviceGuard guard(m->h->device);
     if (ipt_status st = mlp_ensure_batch(m, batch)) return st;
-    if (ipt_status st = mlp_forward_impl(m, x, batch, y)) return st;
-    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    hipStream_t s = m->h->stream;
+    const int bp = pad_tile(batch);
+    IPT_MHIP(m, mlp_pack_x(s, x, batch, m->in, m->xb, m->xt, bp, m->ip));
+    IPT_MHIP(m, mlp_hidden(m, s, batch));
+    MlpEpi e = epi0();
+    e.mvalid = batch;
+    e.nvalid = m->out;
+    e.bias = m->w + m->boff[m->nl - 1];
+    e.c32 = y;
+    e.ldc32 = m->out;
+    IPT_MHIP(m, mlp_gemm(s, MLP_EPI_F32, m->hb[m->depth - 1], m->hp, m->wb[m->nl - 1], m->hp, bp, m->op, m->hp, 1, e));
+    IPT_MHIP(m, hipStreamSynchronize(s));
     return IPT_OK;
 }
 
-ipt_status ipt_mlp_loss_grad(ipt_mlp m, const float *x, const float *targets, int32_t batch, float *loss,
-                             float *grad) {
-    if (!m || !x || !targets || batch < 1) return m ? mlp_fail(m, IPT_EINVAL, "bad MLP arguments") : IPT_EINVAL;
+ipt_status ipt_mlp_loss_grad(ipt_mlp m, const float *x, const float *targets, const float *weights, int32_t batch,
+                             float *loss, float *grad) {
+    if (!m) return IPT_EINVAL;
+    if (ipt_status st = mlp_check_x(m, x, batch)) return st;
+    if (!targets) return mlp_fail(m, IPT_EINVAL, "targets must be non-NULL");
     DeviceGuard guard(m->h->device);
     if (ipt_status st = mlp_ensure_batch(m, batch)) return st;
-    if (ipt_status st = mlp_backward_impl(m, x, targets, batch)) return st;
-    if (grad)
-        IPT_MHIP(m, hipMemcpyAsync(grad, m->g, sizeof(float) * m->nparam, hipMemcpyDeviceToDevice, m->h->stream));
+    hipStream_t s = m->h->stream;
+    IPT_MHIP(m, mlp_pack_x(s, x, batch, m->in, m->xb, m->xt, pad_tile(batch), m->ip));
+    IPT_MHIP(m, mlp_hidden(m, s, batch));
+    IPT_MHIP(m, mlp_backward(m, s, targets, weights, batch, false, 0.f));
+    if (grad) IPT_MHIP(m, hipMemcpyAsync(grad, m->g, sizeof(float) * m->nparam, hipMemcpyDeviceToDevice, s));
     float l = 0.f;
-    IPT_MHIP(m, hipMemcpyAsync(&l, m->loss_dev, sizeof(float), hipMemcpyDeviceToHost, m->h->stream));
-    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    IPT_MHIP(m, hipMemcpyAsync(&l, m->loss_dev, sizeof(float), hipMemcpyDeviceToHost, s));
+    IPT_MHIP(m, hipStreamSynchronize(s));
     if (loss) *loss = l;
     return IPT_OK;
 }
 
-ipt_status ipt_mlp_train(ipt_mlp m, const float *x, const float *targets, int32_t batch, int32_t steps, float lr,
-                         float *loss) {
-    if (!m || !x || !targets || batch < 1 || steps < 0 || !(lr > 0.f))
-        return m ? mlp_fail(m, IPT_EINVAL, "bad MLP training arguments") : IPT_EINVAL;
+ipt_status ipt_mlp_train(ipt_mlp m, const float *x, const float *targets, const float *weights, int32_t batch,
+                         int32_t steps, float lr, float *loss) {
+    if (!m) return IPT_EINVAL;
+    if (ipt_status st = mlp_check_x(m, x, batch)) return st;
+    if (!targets || steps < 0 || !(lr > 0.f)) return mlp_fail(m, IPT_EINVAL, "bad MLP training arguments");
     DeviceGuard guard(m->h->device);
     if (ipt_status st = mlp_ensure_batch(m, batch)) return st;
-    for (int32_t it = 0; it < steps; ++it) {
-        if (ipt_status st = mlp_backward_impl(m, x, targets, batch)) return st;
-        m->adam_step += 1;
-        IPT_MHIP(m, mlp_adam(m->h->stream, m->w, m->wb, m->g, m->m, m->v, m->nparam, lr, m->adam_step));
+    hipStream_t s = m->h->stream;
+    IPT_MHIP(m, mlp_pack_x(s, x, batch, m->in, m->xb, m->xt, pad_tile(batch), m->ip));
+    if (steps > 0) {
+        // one Adam step as a graph (its launches depend only on this call's arguments;
+        // the step count lives on the device), replayed `steps` times on the stream
+        if (!m->cap) IPT_MHIP(m, hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking));
+        IPT_MHIP(m, hipStreamBeginCapture(m->cap, hipStreamCaptureModeRelaxed));
+        hipError_t e1 = mlp_hidden(m, m->cap, batch);
+        if (e1 == hipSuccess) e1 = mlp_backward(m, m->cap, targets, weights, batch, true, lr);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(m->cap, &graph);
+        hipGraphExec_t exec = nullptr;
+        hipError_t e3 = (e1 == hipSuccess && e2 == hipSuccess) ? hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)
+                                                                : (e1 != hipSuccess ? e1 : e2);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            return mlp_fail(m, IPT_EHIP, std::string("training-step graph: ") + hipGetErrorString(e3));
+        }
+        hipError_t e4 = hipSuccess;
+        for (int32_t it = 0; it < steps && e4 == hipSuccess; ++it) e4 = hipGraphLaunch(exec, s);
+        const hipError_t e5 = hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(exec);
+        if (e4 != hipSuccess || e5 != hipSuccess)
+            return mlp_fail(m, IPT_EHIP, std::string("training steps: ") + hipGetErrorString(e4 != hipSuccess ? e4 : e5));
     }
     float l = 0.f;
-    IPT_MHIP(m, hipMemcpyAsync(&l, m->loss_dev, sizeof(float), hipMemcpyDeviceToHost, m->h->stream));
-    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    IPT_MHIP(m, hipMemcpyAsync(&l, m->loss_dev, sizeof(float), hipMemcpyDeviceToHost, s));
+    IPT_MHIP(m, hipStreamSynchronize(s));
     if (loss) *loss = l;
     return IPT_OK;
 }
 
 ipt_status ipt_mlp_predict_z0(ipt_mlp m, const float *x, int32_t batch, const float *mu, const float *sigma,
-                              const double *scale, int64_t n, int64_t k, const int32_t *idx, double *z0, int64_t ldz0,
-                              int64_t pstride) {
-    if (!m || !x || !mu || !sigma || !scale || !idx || !z0 || batch < 1 || n < 1 || k < 1 || k > n || ldz0 < k ||
-        n * k != m->out || pstride < (n - 1) * ldz0 + k)
-        return m ? mlp_fail(m, IPT_EINVAL, "bad warm-start arguments (out_dim must be n k)") : IPT_EINVAL;
+                              const double *eps, int32_t order, const double *terms, int64_t n, int64_t k,
+                              const int32_t *idx, double *z0, int64_t ldz0, int64_t pstride) {
+    if (!m) return IPT_EINVAL;
+    if (ipt_status st = mlp_check_x(m, x, batch)) return st;
+    if (!mu || !sigma || !eps || !idx || !z0 || n < 1 || k < 1 || k > n || ldz0 < k || n * k != m->out ||
+        pstride < (n - 1) * ldz0 + k || order < 0 || order > 16 || (order > 0 && !terms))
+        return mlp_fail(m, IPT_EINVAL, "bad warm-start arguments (out_dim must be n k, 0 <= order <= 16)");
     DeviceGuard guard(m->h->device);
     if (ipt_status st = mlp_ensure_batch(m, batch)) return st;
-    if (ipt_status st = mlp_forward_impl(m, x, batch, m->y)) return st;
-    IPT_MHIP(m, mlp_warm_start(m->h->stream, m->y, m->out, mu, sigma, scale, n, k, idx, z0, ldz0, pstride, batch));
-    IPT_MHIP(m, hipStreamSynchronize(m->h->stream));
+    hipStream_t s = m->h->stream;
+    const int bp = pad_tile(batch);
+    IPT_MHIP(m, mlp_pack_x(s, x, batch, m->in, m->xb, m->xt, bp, m->ip));
+    IPT_MHIP(m, mlp_hidden(m, s, batch));
+    MlpEpi e = epi0();
+    e.mvalid = batch;
+    e.nvalid = m->out;
+    e.bias = m->w + m->boff[m->nl - 1];
+    e.z0 = z0;
+    e.ldz0 = ldz0;
+    e.pstride = pstride;
+    e.kcols = k;
+    e.idx = idx;
+    e.mu = mu;
+    e.sigma = sigma;
+    e.eps = eps;
+    e.terms = terms;
+    e.order = order;
+    IPT_MHIP(m, mlp_gemm(s, MLP_EPI_WARM, m->hb[m->depth - 1], m->hp, m->wb[m->nl - 1], m->hp, bp, m->op, m->hp, 1, e));
+    IPT_MHIP(m, hipStreamSynchronize(s));
     return IPT_OK;
 }
 
 ipt_status ipt_mlp_targets(ipt_handle h, const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz,
-                           int64_t pstride, const int32_t *idx, const double *scale, float *targets, float *mu,
-                           float *sigma) {
+                           int64_t pstride, const int32_t *idx, const double *eps, int32_t order, const double *terms,
+                           const double *weights, float *targets, float *mu, float *sigma) {
     if (!h) return IPT_EINVAL;
-    if (!z || !idx || !scale || !targets || !mu || !sigma || batch < 1 || n < 1 || k < 1 || k > n || ldz < k ||
-        pstride < (n - 1) * ldz + k)
+    if (!z || !idx || !eps || !targets || !mu || !sigma || batch < 1 || n < 1 || k < 1 || k > n || ldz < k ||
+        pstride < (n - 1) * ldz + k || order < 0 || order > 16 || (order > 0 && !terms))
         return fail(h, IPT_EINVAL, "bad target arguments");
     DeviceGuard guard(h->device);
-    IPT_HIP(h, mlp_targets(h->stream, z, batch, n, k, ldz, pstride, idx, scale, targets, mu, sigma));
+    IPT_HIP(h, mlp_targets(h->stream, z, batch, n, k, ldz, pstride, idx, eps, order, terms, weights, targets, mu,
+                           sigma));
+    IPT_HIP(h, hipStreamSynchronize(h->stream));
+    return IPT_OK;
+}
+
+ipt_status ipt_rs_terms(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
+                        const int32_t *idx, int32_t order, double *terms) {
+    if (!h) return IPT_EINVAL;
+    h->last_error.clear();
+    if (n < 1 || n > (int64_t(1) << 20) || k < 1 || k > n || lda < n || order < 1 || order > 16)
+        return fail(h, IPT_EINVAL, "need 1 <= k <= n <= 2^20, lda >= n, 1 <= order <= 16");
+    if (!theta || !delta || !idx || !terms) return fail(h, IPT_EINVAL, "theta, delta, idx and terms must be non-NULL");
+    DeviceGuard guard(h->device);
+    hipStream_t s = h->stream;
+    Carve sizing;
+    sizing.take<double>((size_t)n * k);
+    sizing.take<double>((size_t)order * k);
+    sizing.take<int32_t>(1);
+    if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
+    Carve cv;
+    cv.base = (char *)h->ws;
+    double *y = cv.take<double>((size_t)n * k);
+    double *d = cv.take<double>((size_t)order * k);
+    int32_t *err = cv.take<int32_t>(1);
+    IPT_HIP(h, rs_clear(s, err));
+    IPT_HIP(h, rs_gather(s, delta, lda, idx, n, k, y, err));
+    for (int32_t l = 1; l <= order; ++l) {
+        if (l > 1) IPT_HIP(h, rs_product(s, delta, lda, terms + (int64_t)(l - 2) * n * k, n, k, y));
+        IPT_HIP(h, rs_term(s, theta, idx, y, terms, d, l, n, k, err));
+    }
+    int32_t herr = 0;
+    IPT_HIP(h, hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    IPT_HIP(h, hipStreamSynchronize(s));
+    if (herr & 1) return fail(h, IPT_EINVAL, "idx out of range");
+    if (herr & 2) return fail(h, IPT_EDEGENERATE, "theta_j == theta_idx[c] for some j != idx[c], or theta not finite");
+    return IPT_OK;
+}
+
+ipt_status ipt_rs_start(ipt_handle h, const double *eps, int32_t count, int32_t order, const double *terms, int64_t n,
+                        int64_t k, const int32_t *idx, double *z0, int64_t ldz0, int64_t pstride) {
+    if (!h) return IPT_EINVAL;
+    h->last_error.clear();
+    if (!eps || !idx || !z0 || (order > 0 && !terms) || count < 1 || n < 1 || k < 1 || k > n || ldz0 < k ||
+        pstride < (n - 1) * ldz0 + k || order < 0 || order > 16)
+        return fail(h, IPT_EINVAL, "bad series-start arguments");
+    DeviceGuard guard(h->device);
+    IPT_HIP(h, rs_start(h->stream, eps, count, order, terms, n, k, idx, z0, ldz0, pstride));
     IPT_HIP(h, hipStreamSynchronize(h->stream));
     return IPT_OK;
 }

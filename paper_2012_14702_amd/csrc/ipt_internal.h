@@ -250,6 +250,7 @@ int bgemm_grid(int tile);  // persistent grid size (CUs x resident blocks)
 // both dimensions.  C[M x N] = A[M x K] B[N x K]^T, 128 x 128 tiles, then one of the
 // epilogues below.
 constexpr int MLP_TILE = 128;
+constexpr int MLP_SLAB = 8;   // rows per block of the split-K reduction (its column sums come per slab)
 enum : int {
     MLP_EPI_ACT = 0,    // + bias, optional tanh; BF16 C and C^T (zero outside mvalid x nvalid)
     MLP_EPI_MSE = 1,    // + bias; g = scale (y - t) in BF16 as C and C^T, loss and column-sum partials
@@ -270,10 +271,11 @@ struct MlpEpi {
     float *c32;                    // FP32 C, leading dimension ldc32
     int64_t ldc32;
     const float *tgt;              // MSE targets [mvalid x nvalid], leading dimension ldt
+    const float *roww;             // MSE: per-row loss weights (null: 1)
     int64_t ldt;
     float scale;                   // MSE: 2 / (number of outputs)
     double *lossp;                 // MSE: per-block sums of (y - t)^2
-    float *colp;                   // column sums of the stored BF16 C, per 128-row tile: [M/128][ldcolp]
+    float *colp;                   // column sums of the stored BF16 C: [M/128][ldcolp] (split reduce: [M/MLP_SLAB])
     int64_t ldcolp;
     const __bf16 *h;               // split reduce: the activation H of the layer below (tanh derivative)
     int64_t ldh;
@@ -290,10 +292,11 @@ struct MlpEpi {
 };
 hipError_t mlp_gemm(hipStream_t s, int mode, const __bf16 *A, int64_t lda, const __bf16 *B, int64_t ldb, int M, int N,
                     int K, int splits, const MlpEpi &e);
-// Sum of the split-K partials (FP32 [splits][M][N]) in split order, times the tanh
-// derivative (1 - h^2) of the stored activation; BF16 C and C^T and column sums as
-// the epilogues do.
-hipError_t mlp_split_dtanh(hipStream_t s, const float *part, int splits, int M, int N, const MlpEpi &e);
+// Sum of the split-K partials (FP32 [splits][M][N]) in split order, then mode
+// MLP_EPI_SPLIT: times the tanh derivative (1 - h^2) of the stored activation e.h;
+// MLP_EPI_ACT: + bias, tanh; MLP_EPI_ADAM: Adam on the weights; BF16 C (required), C^T
+// and the column sums per MLP_SLAB rows when given.
+hipError_t mlp_split_reduce(hipStream_t s, int mode, const float *part, int splits, int M, int N, const MlpEpi &e);
 int mlp_split_count(int M, int N, int K);
 // Padded BF16 copies W [loutp x linp] and W^T [linp x loutp] of a layer from the FP32 weights.
 hipError_t mlp_pack_weights(hipStream_t s, const float *w, int lout, int lin, __bf16 *wb, __bf16 *wbt, int loutp,
@@ -306,25 +309,31 @@ struct MlpBiasLayers {
     int64_t boff[17];              // offset of the bias in the parameter layout
     const float *colp[17];         // that layer's column-sum partials [mtiles][ld]
     int64_t ldcolp[17];
+    int32_t mtiles[17];
 };
-// Bias gradients (column sums over the 128-row tiles, in tile order); Adam on the
-// biases when adam (else the gradient goes to g).
-hipError_t mlp_bias_step(hipStream_t s, const MlpBiasLayers &L, int mtiles, int adam, float *w, float *g, float *am,
-                         float *av, const int32_t *adam_t, float lr);
+// Bias gradients (column sums over the row tiles, in tile order); Adam on the biases
+// when adam (else the gradient goes to g).
+hipError_t mlp_bias_step(hipStream_t s, const MlpBiasLayers &L, int adam, float *w, float *g, float *am, float *av,
+                         const int32_t *adam_t, float lr);
 // Loss = sum of the per-block partials / count; with adam, the step counter advances.
 hipError_t mlp_loss_step(hipStream_t s, const double *lossp, int nparts, double inv_count, float *loss,
                          int32_t *adam_t, int adam);
 hipError_t mlp_targets(hipStream_t s, const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz,
                        int64_t pstride, const int32_t *idx, const double *eps, int32_t order, const double *terms,
-                       float *targets, float *mu, float *sigma);
+                       const double *weights, float *targets, float *mu, float *sigma);
 
 // Rayleigh-Schroedinger terms of M = D + Delta on requested columns (ipt_rs.hip).
+// err: bit 0 = an index outside [0, n), bit 1 = theta_j == theta_i (or not finite) for a
+// requested i and j != i.  rs_clear zeroes it.
+hipError_t rs_clear(hipStream_t s, int32_t *err);
 hipError_t rs_gather(hipStream_t s, const double *delta, int64_t lda, const int32_t *idx, int64_t n, int64_t k,
-                     double *y);
+                     double *y, int32_t *err);
 hipError_t rs_product(hipStream_t s, const double *delta, int64_t lda, const double *z, int64_t n, int64_t k,
                       double *y);
-hipError_t rs_term(hipStream_t s, const double *theta, const int32_t *idx, const double *y, const double *terms,
-                   double *d, int32_t l, int64_t n, int64_t k);
+hipError_t rs_term(hipStream_t s, const double *theta, const int32_t *idx, const double *y, double *terms, double *d,
+                   int32_t l, int64_t n, int64_t k, int32_t *err);
+hipError_t rs_start(hipStream_t s, const double *eps, int32_t count, int32_t order, const double *terms, int64_t n,
+                    int64_t k, const int32_t *idx, double *z0, int64_t ldz0, int64_t pstride);
 
 // IPT-ACX extrapolation over row-major iterate slots z, f1, f2, f3 (n rows, leading
 // dimension ld, kc columns with states `state`) after a cycle of order p

@@ -42,7 +42,8 @@ __device__ inline uint16_t bf16_bits(float v) {
 __device__ inline float bits_f32(uint16_t u) { return (float)__builtin_bit_cast(__bf16, u); }
 
 // The 128 x 128 BF16 tile in LDS (out[r * OLD + c], values already zero outside the
-// valid region) goes to C (row-major), C^T and the per-tile column sums.
+// valid region) goes to C (row-major) and C^T.  For C^T, lane l of a wave reads column
+// l of the tile (consecutive 2-byte LDS words) and writes 8 consecutive rows of it.
 __device__ void store_tile(const uint16_t *out, const MlpEpi &e, int m0, int n0) {
     const int t = threadIdx.x;
     if (e.c16) {
@@ -55,17 +56,25 @@ __device__ void store_tile(const uint16_t *out, const MlpEpi &e, int m0, int n0)
     if (e.ct16) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const int u = t + 256 * i, c = u >> 4, ch = u & 15;
+            const int u = t + 256 * i, c = u & (GT - 1), ch = u >> 7;
             u16x8 v;
 #pragma unroll
             for (int q = 0; q < 8; ++q) v[q] = out[(ch * 8 + q) * OLD + c];
             *(u16x8 *)(e.ct16 + (int64_t)(n0 + c) * e.ldct16 + m0 + ch * 8) = v;
         }
     }
-    if (e.colp && t < GT) {
-        float acc = 0.f;
-        for (int r = 0; r < GT; ++r) acc += bits_f32(out[r * OLD + t]);
-        e.colp[(int64_t)(m0 / GT) * e.ldcolp + n0 + t] = acc;
+}
+
+// a / b and a % b for non-negative a, b > 0, in 32 bits when both fit (a 64-bit
+// division is several times longer)
+__device__ inline void divmod_nn(int64_t a, int64_t b, int64_t &q, int64_t &r) {
+    if (((a | b) >> 31) == 0) {
+        const uint32_t qa = (uint32_t)a / (uint32_t)b;
+        q = qa;
+        r = a - (int64_t)qa * b;
+    } else {
+        q = a / b;
+        r = a - q * b;
     }
 }
 
@@ -75,10 +84,11 @@ __device__ inline double wave_sum_d(double v) {
     return v;
 }
 
-// Adam (beta 0.9 / 0.999, eps 1e-8) on one weight; returns the new weight.
-__device__ inline float adam_update(float *w, float *m, float *v, float g, float lr, int32_t step) {
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+// Adam (beta 0.9 / 0.999, eps 1e-8) on one weight; returns the new weight.  c1, c2 are
+// the bias corrections 1 - beta^step of the step (computed once per thread).
+constexpr float ADAM_B1 = 0.9f, ADAM_B2 = 0.999f;
+__device__ inline float adam_update(float *w, float *m, float *v, float g, float lr, float c1, float c2) {
+    const float b1 = ADAM_B1, b2 = ADAM_B2, eps = 1e-8f;
     const float mv = b1 * *m + (1.f - b1) * g;
     const float vv = b2 * *v + (1.f - b2) * g * g;
     *m = mv;
@@ -187,7 +197,8 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const __bf16 *__restrict__ A, 
             for (int y = 0; y < 4; ++y) {
                 const int q = n0 + cbase + 16 * y;
                 if (q >= e.nvalid) continue;
-                const int64_t j = q / e.kcols, c = q - j * e.kcols;
+                int64_t j, c;
+                divmod_nn(q, e.kcols, j, c);
                 const bool unit = (j == e.idx[c]);
                 const double bv = e.bias ? (double)e.bias[q] : 0.0;
                 const double mu = e.mu[q], sg = e.sigma[q];
@@ -214,8 +225,13 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const __bf16 *__restrict__ A, 
     // the BF16-output epilogues: values into the LDS tile, then store_tile
     uint16_t *out = smem;  // the last K step ended with a barrier
     float lsum = 0.f;
-    int32_t step = 0;
-    if (MODE == MLP_EPI_ADAM) step = *e.adam_t + 1;
+    float c1 = 1.f, c2 = 1.f;
+    if (MODE == MLP_EPI_ADAM) {
+        const float step = (float)(*e.adam_t + 1);
+        c1 = 1.f - powf(ADAM_B1, step);
+        c2 = 1.f - powf(ADAM_B2, step);
+    }
+    float csum[4] = {0.f, 0.f, 0.f, 0.f};  // column sums of the stored values over this lane's rows
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -231,18 +247,34 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const __bf16 *__restrict__ A, 
                 if (MODE == MLP_EPI_ACT) {
                     if (e.tanh_act) v = tanhf(v);
                 } else if (MODE == MLP_EPI_MSE) {
-                    const float d = ok ? v - e.tgt[(int64_t)gr * e.ldt + gc] : 0.f;
+                    const float ws = (ok && e.roww) ? e.roww[gr] : 1.f;
+                    const float d = ok ? (v - e.tgt[(int64_t)gr * e.ldt + gc]) * ws : 0.f;
                     lsum += d * d;
-                    v = e.scale * d;
+                    v = (e.scale * ws) * d;
                 } else if (MODE == MLP_EPI_ADAM) {
                     if (ok) {
                         const int64_t wi = (int64_t)gr * e.nvalid + gc;
-                        v = adam_update(e.w + wi, e.am + wi, e.av + wi, v, e.lr, step);
+                        v = adam_update(e.w + wi, e.am + wi, e.av + wi, v, e.lr, c1, c2);
                     }
                 }
-                out[lrow * OLD + lc] = ok ? bf16_bits(v) : (uint16_t)0;
+                const uint16_t b = ok ? bf16_bits(v) : (uint16_t)0;
+                out[lrow * OLD + lc] = b;
+                csum[y] += bits_f32(b);
             }
         }
+    if (e.colp) {
+        // the 4 row groups of the wave (lane / 16), then the two waves sharing columns
+        __shared__ float cred[2][GT];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            float v = csum[y];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 16) cred[wm][cbase + 16 * y] = v;
+        }
+        __syncthreads();
+        if (t < GT) e.colp[(int64_t)(m0 / GT) * e.ldcolp + n0 + t] = cred[0][t] + cred[1][t];
+    }
     if (MODE == MLP_EPI_MSE) {
         __shared__ double red[4];
         const double ws = wave_sum_d((double)lsum);
@@ -254,24 +286,73 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const __bf16 *__restrict__ A, 
     store_tile(out, e, m0, n0);
 }
 
-// Split-K sum in split order, times (1 - h^2), into the LDS tile, then store_tile.
-__global__ __launch_bounds__(256) void k_split_dtanh(const float *part, int splits, int M, int N, MlpEpi e) {
-    __shared__ __attribute__((aligned(16))) uint16_t out[GT * OLD];
-    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+// Split-K sum in split order over a slab of MLP_SLAB rows x 128 columns per block
+// (thread t sums column t % 128 of 4 rows, its loads for 8 splits at a time in
+// flight), then the layer's epilogue: the tanh derivative (1 - h^2) of the stored
+// activation (MLP_EPI_SPLIT: hidden gradients), bias and tanh (MLP_EPI_ACT), or Adam on
+// the weights (MLP_EPI_ADAM); BF16 C row by row, then C^T (8 consecutive rows of a
+// column per 16-byte store) and the slab's column sums through LDS.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_split_reduce(const float *part, int splits, int M, int N, MlpEpi e) {
+    __shared__ uint16_t slab[MLP_SLAB][GT];
+    const int t = threadIdx.x, c = t & (GT - 1), rq = (t >> 7) * 4;
+    const int m0 = blockIdx.y * MLP_SLAB, n0 = blockIdx.x * GT, gc = n0 + c;
     const int64_t mn = (int64_t)M * N;
-    for (int i = 0; i < GT * GT / 256; ++i) {
-        const int u = threadIdx.x + 256 * i, r = u >> 7, c = u & (GT - 1);
-        const int gr = m0 + r, gc = n0 + c;
-        float v = 0.f;
-        const float *p = part + (int64_t)gr * N + gc;
-        for (int z = 0; z < splits; ++z) v += p[z * mn];
-        const float hv = (float)e.h[(int64_t)gr * e.ldh + gc];
-        v *= 1.f - hv * hv;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    const float *p = part + (int64_t)(m0 + rq) * N + gc;
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {
+        float v[8][4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[u][r] = p[(z + u) * mn + (int64_t)r * N];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] += v[u][r];
+    }
+    for (; z < splits; ++z)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] += p[z * mn + (int64_t)r * N];
+    float c1 = 1.f, c2 = 1.f;
+    if (MODE == MLP_EPI_ADAM) {
+        const float step = (float)(*e.adam_t + 1);
+        c1 = 1.f - powf(ADAM_B1, step);
+        c2 = 1.f - powf(ADAM_B2, step);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gr = m0 + rq + r;
         const bool ok = gr < e.mvalid && gc < e.nvalid;
-        out[r * OLD + c] = ok ? bf16_bits(v) : (uint16_t)0;
+        float v = acc[r];
+        if (MODE == MLP_EPI_SPLIT) {
+            const float hv = (float)e.h[(int64_t)gr * e.ldh + gc];
+            v *= 1.f - hv * hv;
+        } else if (MODE == MLP_EPI_ACT) {
+            if (ok) v = tanhf(v + e.bias[gc]);
+        } else if (MODE == MLP_EPI_ADAM) {
+            if (ok) {
+                const int64_t wi = (int64_t)gr * e.nvalid + gc;
+                v = adam_update(e.w + wi, e.am + wi, e.av + wi, v, e.lr, c1, c2);
+            }
+        }
+        const uint16_t b = ok ? bf16_bits(v) : (uint16_t)0;
+        slab[rq + r][c] = b;
+        *(uint16_t *)(e.c16 + (int64_t)gr * e.ldc16 + gc) = b;
     }
     __syncthreads();
-    store_tile(out, e, m0, n0);
+    if (t < GT) {
+        u16x8 v;
+        float cs = 0.f;
+#pragma unroll
+        for (int q = 0; q < MLP_SLAB; ++q) {
+            v[q] = slab[q][t];
+            cs += bits_f32(v[q]);
+        }
+        if (e.ct16) *(u16x8 *)(e.ct16 + (int64_t)(n0 + t) * e.ldct16 + m0) = v;
+        if (e.colp) e.colp[(int64_t)(m0 / MLP_SLAB) * e.ldcolp + n0 + t] = cs;
+    }
 }
 
 __global__ void k_pack_weights(const float *w, int lout, int lin, __bf16 *wb, __bf16 *wbt, int loutp, int linp) {
@@ -294,11 +375,16 @@ __global__ void k_pack_x(const float *x, int batch, int in, __bf16 *xb, __bf16 *
     }
 }
 
-__global__ void k_bias_step(MlpBiasLayers L, int mtiles, int adam, float *w, float *g, float *am, float *av,
+__global__ void k_bias_step(MlpBiasLayers L, int adam, float *w, float *g, float *am, float *av,
                             const int32_t *adam_t, float lr) {
     int64_t total = 0;
     for (int l = 0; l < L.count; ++l) total += L.lout[l];
-    const int32_t step = adam ? *adam_t + 1 : 0;
+    float c1 = 1.f, c2 = 1.f;
+    if (adam) {
+        const float step = (float)(*adam_t + 1);
+        c1 = 1.f - powf(ADAM_B1, step);
+        c2 = 1.f - powf(ADAM_B2, step);
+    }
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < total; u += (int64_t)gridDim.x * blockDim.x) {
         int l = 0;
         int64_t o = u;
@@ -307,10 +393,20 @@ __global__ void k_bias_step(MlpBiasLayers L, int mtiles, int adam, float *w, flo
             ++l;
         }
         float db = 0.f;
-        for (int mt = 0; mt < mtiles; ++mt) db += L.colp[l][(int64_t)mt * L.ldcolp[l] + o];
+        const float *cp = L.colp[l] + o;
+        const int64_t ld = L.ldcolp[l];
+        int mt = 0;
+        for (; mt + 8 <= L.mtiles[l]; mt += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = cp[(int64_t)(mt + u) * ld];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) db += v[u];
+        }
+        for (; mt < L.mtiles[l]; ++mt) db += cp[(int64_t)mt * ld];
         const int64_t wi = L.boff[l] + o;
         if (adam)
-            adam_update(w + wi, am + wi, av + wi, db, lr, step);
+            adam_update(w + wi, am + wi, av + wi, db, lr, c1, c2);
         else
             g[wi] = db;
     }
@@ -337,11 +433,12 @@ __global__ void k_loss_step(const double *lossp, int nparts, double inv_count, f
 // E + sum_{l <= order} eps_p^l T_l, divided by eps_p^(order + 1), standardised over the
 // batch (mean and deviation summed in problem order).
 __global__ void k_targets(const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz, int64_t pstride,
-                          const int32_t *idx, const double *eps, int32_t order, const double *terms, float *targets,
-                          float *mu, float *sigma) {
+                          const int32_t *idx, const double *eps, int32_t order, const double *terms,
+                          const double *weights, float *targets, float *mu, float *sigma) {
     const int64_t nk = n * k;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nk; q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = q / k, c = q - j * k;
+        int64_t j, c;
+        divmod_nn(q, k, j, c);
         const double e0 = (j == idx[c]) ? 1.0 : 0.0;
         auto rem = [&](int32_t p) {
             const double ep = eps[p];
@@ -352,15 +449,21 @@ __global__ void k_targets(const double *z, int32_t batch, int64_t n, int64_t k, 
             }
             return (z[p * pstride + j * ldz + c] - base) / (pw * ep);
         };
-        double s = 0.0;
-        for (int32_t p = 0; p < batch; ++p) s += rem(p);
-        const double mean = s / batch;
+        // weighted by weights[p]^2 (uniform when weights is NULL)
+        double s = 0.0, sw = 0.0;
+        for (int32_t p = 0; p < batch; ++p) {
+            const double w2 = weights ? weights[p] * weights[p] : 1.0;
+            s += w2 * rem(p);
+            sw += w2;
+        }
+        const double mean = s / sw;
         double v = 0.0;
         for (int32_t p = 0; p < batch; ++p) {
+            const double w2 = weights ? weights[p] * weights[p] : 1.0;
             const double r = rem(p) - mean;
-            v += r * r;
+            v += w2 * (r * r);
         }
-        double sd = sqrt(v / batch);
+        double sd = sqrt(v / sw);
         if (!(sd >= 1e-300)) sd = 1.0;
         mu[q] = (float)mean;
         sigma[q] = (float)sd;
@@ -396,18 +499,24 @@ hipError_t mlp_gemm(hipStream_t s, int mode, const __bf16 *A, int64_t lda, const
 }
 
 int mlp_split_count(int M, int N, int K) {
-    // enough blocks for the chip (about 256) without splitting K below 256
+    // enough blocks for the chip (about 256) without splitting K below two K steps
     const int tiles = (M / GT) * (N / GT);
     int want = tiles >= 256 ? 1 : 256 / tiles;
     int best = 1;
     for (int sp = 1; sp <= want; ++sp)
-        if (K % (GK * sp) == 0 && K / sp >= 256) best = sp;
+        if (K % (GK * sp) == 0 && K / sp >= 2 * GK) best = sp;
     return best;
 }
 
-hipError_t mlp_split_dtanh(hipStream_t s, const float *part, int splits, int M, int N, const MlpEpi &e) {
-    if (M % GT || N % GT) return hipErrorInvalidValue;
-    k_split_dtanh<<<dim3(N / GT, M / GT), 256, 0, s>>>(part, splits, M, N, e);
+hipError_t mlp_split_reduce(hipStream_t s, int mode, const float *part, int splits, int M, int N, const MlpEpi &e) {
+    if (M % GT || N % GT || !e.c16) return hipErrorInvalidValue;
+    const dim3 g(N / GT, M / MLP_SLAB);
+    switch (mode) {
+        case MLP_EPI_SPLIT: k_split_reduce<MLP_EPI_SPLIT><<<g, 256, 0, s>>>(part, splits, M, N, e); break;
+        case MLP_EPI_ACT: k_split_reduce<MLP_EPI_ACT><<<g, 256, 0, s>>>(part, splits, M, N, e); break;
+        case MLP_EPI_ADAM: k_split_reduce<MLP_EPI_ADAM><<<g, 256, 0, s>>>(part, splits, M, N, e); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -422,11 +531,11 @@ hipError_t mlp_pack_x(hipStream_t s, const float *x, int batch, int in, __bf16 *
     return hipGetLastError();
 }
 
-hipError_t mlp_bias_step(hipStream_t s, const MlpBiasLayers &L, int mtiles, int adam, float *w, float *g, float *am,
-                         float *av, const int32_t *adam_t, float lr) {
+hipError_t mlp_bias_step(hipStream_t s, const MlpBiasLayers &L, int adam, float *w, float *g, float *am, float *av,
+                         const int32_t *adam_t, float lr) {
     int64_t total = 0;
     for (int l = 0; l < L.count; ++l) total += L.lout[l];
-    k_bias_step<<<capped(total), 256, 0, s>>>(L, mtiles, adam, w, g, am, av, adam_t, lr);
+    k_bias_step<<<capped(total), 256, 0, s>>>(L, adam, w, g, am, av, adam_t, lr);
     return hipGetLastError();
 }
 
@@ -438,8 +547,9 @@ hipError_t mlp_loss_step(hipStream_t s, const double *lossp, int nparts, double 
 
 hipError_t mlp_targets(hipStream_t s, const double *z, int32_t batch, int64_t n, int64_t k, int64_t ldz,
                        int64_t pstride, const int32_t *idx, const double *eps, int32_t order, const double *terms,
-                       float *targets, float *mu, float *sigma) {
-    k_targets<<<capped(n * k), 256, 0, s>>>(z, batch, n, k, ldz, pstride, idx, eps, order, terms, targets, mu, sigma);
+                       const double *weights, float *targets, float *mu, float *sigma) {
+    k_targets<<<capped(n * k), 256, 0, s>>>(z, batch, n, k, ldz, pstride, idx, eps, order, terms, weights, targets, mu,
+                                            sigma);
     return hipGetLastError();
 }
 

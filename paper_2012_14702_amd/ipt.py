@@ -444,12 +444,15 @@ def _bind_mlp(lib):
     lib.ipt_mlp_get_params.argtypes = [p, p]
     lib.ipt_mlp_set_params.argtypes = [p, p]
     lib.ipt_mlp_forward.argtypes = [p, p, i32, p]
-    lib.ipt_mlp_loss_grad.argtypes = [p, p, p, i32, C.POINTER(C.c_float), p]
-    lib.ipt_mlp_train.argtypes = [p, p, p, i32, i32, C.c_float, C.POINTER(C.c_float)]
-    lib.ipt_mlp_predict_z0.argtypes = [p, p, i32, p, p, p, i64, i64, p, p, i64, i64]
-    lib.ipt_mlp_targets.argtypes = [p, p, i32, i64, i64, i64, i64, p, p, p, p, p]
+    lib.ipt_mlp_loss_grad.argtypes = [p, p, p, p, i32, C.POINTER(C.c_float), p]
+    lib.ipt_mlp_train.argtypes = [p, p, p, p, i32, i32, C.c_float, C.POINTER(C.c_float)]
+    lib.ipt_mlp_predict_z0.argtypes = [p, p, i32, p, p, p, i32, p, i64, i64, p, p, i64, i64]
+    lib.ipt_mlp_targets.argtypes = [p, p, i32, i64, i64, i64, i64, p, p, i32, p, p, p, p, p]
+    lib.ipt_rs_terms.argtypes = [p, i64, p, p, i64, i64, p, i32, p]
+    lib.ipt_rs_start.argtypes = [p, p, i32, i32, p, i64, i64, p, p, i64, i64]
     for fn in ("ipt_mlp_create", "ipt_mlp_destroy", "ipt_mlp_get_params", "ipt_mlp_set_params", "ipt_mlp_forward",
-               "ipt_mlp_loss_grad", "ipt_mlp_train", "ipt_mlp_predict_z0", "ipt_mlp_targets"):
+               "ipt_mlp_loss_grad", "ipt_mlp_train", "ipt_mlp_predict_z0", "ipt_mlp_targets", "ipt_rs_terms",
+               "ipt_rs_start"):
         getattr(lib, fn).restype = C.c_int
     _mlp_bound = True
 
@@ -494,27 +497,38 @@ class MLP:
         self._chk(self._lib.ipt_mlp_forward(self._m, _ptr(x), x.shape[0], _ptr(y)), "ipt_mlp_forward")
         return y
 
-    def loss_grad(self, x, targets):
+    def loss_grad(self, x, targets, weights=None):
+        """Loss and gradient; weights: optional FP32 [batch] per-example loss weights."""
         import torch
         g = torch.empty(self.num_params, dtype=torch.float32, device=x.device)
         loss = C.c_float()
-        self._chk(self._lib.ipt_mlp_loss_grad(self._m, _ptr(x.contiguous()), _ptr(targets.contiguous()), x.shape[0],
+        _check(weights, torch.float32, "weights")
+        self._chk(self._lib.ipt_mlp_loss_grad(self._m, _ptr(x.contiguous()), _ptr(targets.contiguous()),
+                                              None if weights is None else _ptr(weights.contiguous()), x.shape[0],
                                               C.byref(loss), _ptr(g)), "ipt_mlp_loss_grad")
         return float(loss.value), g
 
-    def train(self, x, targets, steps, lr=1e-3):
+    def train(self, x, targets, steps, lr=1e-3, weights=None):
+        import torch
         loss = C.c_float()
-        self._chk(self._lib.ipt_mlp_train(self._m, _ptr(x.contiguous()), _ptr(targets.contiguous()), x.shape[0],
+        _check(weights, torch.float32, "weights")
+        self._chk(self._lib.ipt_mlp_train(self._m, _ptr(x.contiguous()), _ptr(targets.contiguous()),
+                                          None if weights is None else _ptr(weights.contiguous()), x.shape[0],
                                           int(steps), float(lr), C.byref(loss)), "ipt_mlp_train")
         return float(loss.value)
 
-    def predict_z0(self, x, mu, sigma, scale, n, k, idx):
-        """Warm starts Z0 [batch, n, k] (FP64) for the inputs x [batch, in_dim]."""
+    def predict_z0(self, x, mu, sigma, eps, n, k, idx, terms=None, z0=None):
+        """Warm starts Z0 [batch, n, k] (FP64) for the inputs x [batch, in_dim] of family
+        members eps [batch] (FP64): E + sum_l eps^l T_l + eps^(order+1) (mu + sigma y),
+        with T = terms [order, n, k] (ipt_rs_terms) or no terms."""
         import torch
         b = x.shape[0]
-        z0 = torch.empty((b, n, k), dtype=torch.float64, device=x.device)
+        if z0 is None:
+            z0 = torch.empty((b, n, k), dtype=torch.float64, device=x.device)
+        order = 0 if terms is None else terms.shape[0]
         self._chk(self._lib.ipt_mlp_predict_z0(self._m, _ptr(x.contiguous()), b, _ptr(mu.contiguous()),
-                                               _ptr(sigma.contiguous()), _ptr(scale.contiguous()), n, k,
+                                               _ptr(sigma.contiguous()), _ptr(eps.contiguous()), order,
+                                               None if terms is None else _ptr(terms.contiguous()), n, k,
                                                _ptr(idx.contiguous()), _ptr(z0), k, n * k), "ipt_mlp_predict_z0")
         return z0
 
@@ -530,9 +544,11 @@ class MLP:
             pass
 
 
-def ipt_mlp_targets(z, idx, scale, handle=None):
-    """Standardised targets (ipt_mlp_targets) from solutions z [batch, n, k] (FP64):
-    returns (targets [batch, n k], mu [n k], sigma [n k]) as FP32 GPU tensors."""
+def ipt_mlp_targets(z, idx, eps, terms=None, weights=None, handle=None):
+    """Standardised targets (ipt_mlp_targets) from solutions z [batch, n, k] (FP64) of
+    family members eps [batch] (FP64), as remainders after E + sum_l eps^l T_l (terms
+    [order, n, k] or None): returns (targets [batch, n k], mu [n k], sigma [n k]) as FP32
+    GPU tensors."""
     import torch
     lib = load_library()
     _bind_mlp(lib)
@@ -542,8 +558,48 @@ def ipt_mlp_targets(z, idx, scale, handle=None):
     tg = torch.empty((b, n * k), dtype=torch.float32, device=z.device)
     mu = torch.empty(n * k, dtype=torch.float32, device=z.device)
     sd = torch.empty(n * k, dtype=torch.float32, device=z.device)
-    st = lib.ipt_mlp_targets(h.ptr, _ptr(z), b, n, k, k, n * k, _ptr(idx.contiguous()), _ptr(scale.contiguous()),
-                             _ptr(tg), _ptr(mu), _ptr(sd))
+    order = 0 if terms is None else terms.shape[0]
+    st = lib.ipt_mlp_targets(h.ptr, _ptr(z), b, n, k, k, n * k, _ptr(idx.contiguous()), _ptr(eps.contiguous()), order,
+                             None if terms is None else _ptr(terms.contiguous()),
+                             None if weights is None else _ptr(weights.contiguous()), _ptr(tg), _ptr(mu), _ptr(sd))
     if st != IPT_OK:
         raise IPTError(st, "ipt_mlp_targets: " + h.last_error())
     return tg, mu, sd
+
+
+def ipt_rs_terms(theta, delta, idx, order, handle=None):
+    """Rayleigh-Schroedinger terms Z^[1..order] of D + Delta on the columns idx
+    (ipt_rs_terms): returns terms [order, n, k] (FP64 GPU tensor)."""
+    import torch
+    lib = load_library()
+    _bind_mlp(lib)
+    h = _handle(handle)
+    _check(theta, torch.float64, "theta")
+    _check(delta, torch.float64, "delta")
+    _check(idx, torch.int32, "idx")
+    n, k = theta.shape[0], idx.shape[0]
+    if delta.dim() != 2 or delta.shape[0] != n or delta.shape[1] != n or delta.stride(1) != 1:
+        raise ValueError("delta must be n x n with unit column stride")
+    terms = torch.empty((order, n, k), dtype=torch.float64, device=theta.device)
+    st = lib.ipt_rs_terms(h.ptr, n, _ptr(theta), _ptr(delta), delta.stride(0), k, _ptr(idx.contiguous()), order,
+                          _ptr(terms))
+    if st != IPT_OK:
+        raise IPTError(st, "ipt_rs_terms: " + h.last_error())
+    return terms
+
+
+def ipt_rs_start(terms, eps, idx, handle=None):
+    """Series warm starts (ipt_rs_start): Z0 [batch, n, k] = E + sum_l eps^l T_l for the
+    family members eps [batch] (FP64 GPU tensor), terms [order, n, k] from ipt_rs_terms."""
+    import torch
+    lib = load_library()
+    _bind_mlp(lib)
+    h = _handle(handle)
+    order, n, k = terms.shape
+    b = eps.shape[0]
+    z0 = torch.empty((b, n, k), dtype=torch.float64, device=terms.device)
+    st = lib.ipt_rs_start(h.ptr, _ptr(eps.contiguous()), b, order, _ptr(terms.contiguous()), n, k,
+                          _ptr(idx.contiguous()), _ptr(z0), k, n * k)
+    if st != IPT_OK:
+        raise IPTError(st, "ipt_rs_start: " + h.last_error())
+    return z0
