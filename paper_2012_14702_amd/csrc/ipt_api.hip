@@ -1012,7 +1012,6 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     DevOpts dopt = dev_opts(o);
     dopt.low_type = IPT_LOW_NONE;  // the sparse ladder runs FP32 then FP64 sweeps
     dopt.mid_x3 = 0;
-    dopt.first_product = 1;
     const bool ladder = dopt.ladder;
     const bool cold = (z0 == nullptr);
     const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
@@ -1048,7 +1047,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         cs.lam = cv.take<double>(kpc);
         cs.resid = cv.take<double>(kpc);
         *bitmap = cv.take<uint32_t>((n + 31) / 32);
-        *scratch = norm ? cv.take<double>(2 * n) : nullptr;
+        *scratch = norm ? cv.take<double>(norm1_csr_scratch_doubles(n)) : nullptr;
         *val32 = (ladder && nnz > 0) ? cv.take<float>(nnz) : nullptr;
         *ctrl = cv.take<Ctrl>(1);
     };
@@ -1073,13 +1072,12 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kpc, bitmap, start_prec, (int32_t)(kpc / TILE_N + 1), 0));
     IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
     IPT_HIP(h, launch_check_csr(s, ctrl, row_ptr, col, n, nnz));
-    if (norm) IPT_HIP(h, launch_norm1_csr(s, ctrl, theta, row_ptr, col, val, n, scratch));
+    if (norm) IPT_HIP(h, launch_norm1_csr(s, ctrl, theta, row_ptr, col, val, n, nnz, scratch));
     if (ladder && nnz > 0) IPT_HIP(h, launch_val32(s, val, val32, nnz));
-    IPT_HIP(h, launch_load_z0(s, ctrl, z0, ldz0, zb[0], ldzb, cs.idx, n, n, k, ldzb));
-    if (ladder) {
-        if (cold) IPT_HIP(h, launch_fill_f32(s, zlo[0], n * ldzb));
-        else IPT_HIP(h, launch_zlo_init(s, zb[0], zlo[0], ldzb, cs.idx, n, k));
-    }
+    // A cold start's first sweep reads no iterate (Z = E: the product-free sweep); only
+    // ACX keeps E in slot 0 as the base of its first cycle.
+    if (!cold || acx) IPT_HIP(h, launch_load_z0(s, ctrl, z0, ldz0, zb[0], ldzb, cs.idx, n, n, k, ldzb));
+    if (ladder && !cold) IPT_HIP(h, launch_zlo_init(s, zb[0], zlo[0], ldzb, cs.idx, n, k));
     if (ldzb != k) {  // padding column of the other buffers
         for (int q = 1; q < (acx ? 4 : 2); ++q)
             IPT_HIP(h, launch_load_z0(s, ctrl, nullptr, 0, zb[q], ldzb, cs.idx, n, n, k, ldzb));
@@ -1093,15 +1091,16 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     for (int32_t t = 1; t <= o.max_iter; ++t) {
         int32_t q, pc;
         acx_phase(dopt.acx, t, q, pc);
-        const int32_t in_par = acx ? PAR_BUF0 : ((t - 1) & 1), out_par = acx ? PAR_BUF1 : (t & 1);
+        const bool unit = cold && t == 1;  // the product-free first sweep (d from row i inside it)
+        const int32_t in_par = acx ? PAR_BUF0 : (unit ? PAR_UNIT : ((t - 1) & 1)), out_par = acx ? PAR_BUF1 : (t & 1);
         double *zin = acx ? zb[q] : zb[(t - 1) & 1], *zout = acx ? zb[q + 1] : zb[t & 1];
-        IPT_HIP(h, launch_diag_csr(s, ctrl, row_ptr, col, val, zin, ldzb, cs, dvec, k));
+        if (!unit) IPT_HIP(h, launch_diag_csr(s, ctrl, row_ptr, col, val, zin, ldzb, cs, dvec, k));
         IPT_HIP(h, timer.mark(t, 0, s));
         IPT_HIP(h, launch_spmm_sweep(s, ctrl, row_ptr, col, val, val32, theta, zin, zout,
                                      ladder ? zlo[(t - 1) & 1] : nullptr, ladder ? zlo[t & 1] : nullptr, cs, dvec,
-                                     part, n, k, ldzb, kpc));
+                                     part, n, k, ldzb, kpc, unit ? 1 : 0));
         IPT_HIP(h, timer.mark(t, 1, s));
-        IPT_HIP(h, launch_reduce_parts(s, ctrl, cs, part, nrt, kpc));
+        IPT_HIP(h, launch_reduce_parts(s, ctrl, cs, part, nrt, k, kpc));
         IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, 1, kpc, t, in_par, out_par));
         IPT_HIP(h, launch_control(s, ctrl, dopt, t));
         if (acx && q == pc - 1)

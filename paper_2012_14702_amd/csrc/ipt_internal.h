@@ -138,8 +138,10 @@ hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, con
                              uint64_t *bmax);
 int64_t prep_delta_chunks(int64_t np);
 int64_t prep_delta_blocks(int64_t np);
+// scratch: norm1_csr_scratch_doubles(n) doubles
+int64_t norm1_csr_scratch_doubles(int64_t n);
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
-                            const int32_t *col, const double *val, int64_t n, double *scratch);
+                            const int32_t *col, const double *val, int64_t n, int64_t nnz, double *scratch);
 // set_zscale: also the power-of-two scale of the FP16 shadow of Z - E from max |Z - E|
 // (a warm-started ladder whose first sweep is on an FP16-shadowed rung).
 hipError_t launch_load_z0(hipStream_t s, Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
@@ -172,11 +174,13 @@ hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count);  // zero fil
 
 // Sparse sweeps (ipt_spmm.hip)
 int64_t spmm_row_tiles(int64_t n);
-hipError_t launch_reduce_parts(hipStream_t s, const Ctrl *ctrl, ColState cs, double *part, int64_t nblk, int64_t kpc);
+// part: [nblk][ldp][NPART] partials of the sweep; the sums land in part[c][q] (c < kpc)
+hipError_t launch_reduce_parts(hipStream_t s, const Ctrl *ctrl, ColState cs, double *part, int64_t nblk, int64_t ldp,
+                               int64_t kpc);
 hipError_t launch_spmm_sweep(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
                              const double *val, const float *val32, const double *theta, const double *zin,
-                             double *zout, const float *zlo_in, float *zlo_out, ColState cs, const double *dvec,
-                             double *part, int64_t n, int64_t k, int64_t ldz, int64_t kpc);
+                             double *zout, const float *zlo_in, float *zlo_out, ColState cs, double *dvec,
+                             double *part, int64_t n, int64_t k, int64_t ldz, int64_t kpc, int32_t unit_in);
 hipError_t launch_diag_csr(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
                            const double *val, const double *zin, int64_t ldz, ColState cs, double *dvec, int64_t k);
 hipError_t launch_check_csr(hipStream_t s, Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, int64_t n,

@@ -234,33 +234,80 @@ __global__ void k_norm1_reduce(Ctrl *ctrl, const double *colpart, int64_t n, int
 // takes no part in any decision, so the order of the sums is free.  (An exact check
 // that |M| is symmetric, which would turn the column sums into row sums, reads a
 // random line of row_ptr, col and val per entry and costs as much as the atomics.)
-__global__ void k_norm1_csr_part(const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, const double *val,
-                                 int64_t n, double *scratch) {
+// |M|_1 of a CSR matrix: the column sums of |Delta| off the diagonal are accumulated
+// as fixed-point integers (deterministic in any order), at a power-of-two scale from
+// S = sum |val| that keeps every column sum below 2^62:
+//   k_csr_abs_sum  : per-block sums of |val| (and clears the integer column sums),
+//   k_csr_abs_scale: S and the scale 2^(62 - ceil(log2 S)) (0 when S is not finite),
+//   k_csr_colsum   : one 64-bit integer atomic add per off-diagonal entry,
+//   k_norm1_csr_reduce: per column, the sum / scale + |theta_j + Delta_jj| (the diagonal
+//                    entries of row j, in storage order), maximum over columns.
+constexpr int CSR_SUM_BLOCKS = 1024;
+__global__ __launch_bounds__(256) void k_csr_abs_sum(const Ctrl *ctrl, const double *val, int64_t nnz,
+                                                     uint64_t *acc, int64_t n, double *part) {
+    if (ctrl->error) return;
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+        a += fabs(val[p]);
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        acc[j] = 0;
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_csr_abs_scale(const Ctrl *ctrl, const double *part, int nb, double *scale) {
+    if (ctrl->error) return;
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) a += part[b];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double S = sh[0];
+        *scale = !isfinite(S) ? 0.0 : (S > 0.0 ? exp2(fmin(62.0 - ceil(log2(S)), 1000.0)) : 1.0);
+    }
+}
+
+__global__ void k_csr_colsum(const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, const double *val,
+                             int64_t n, const double *scale, uint64_t *acc) {
     if (ctrl->error) return;  // the structure checks ran first; never walk a malformed matrix
+    const double sc = *scale;
+    if (!(sc > 0.0)) return;
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= n) return;
     for (int32_t p = row_ptr[j]; p < row_ptr[j + 1]; ++p) {
         const int32_t c = col[p];
-        if (c == j) atomicAdd(&scratch[n + c], val[p]);
-        else atomicAdd(&scratch[c], fabs(val[p]));
+        if (c != j)
+            atomicAdd((unsigned long long *)&acc[c], (unsigned long long)llrint(fabs(val[p]) * sc));
     }
 }
 
 // Block: grid-stride over columns, one atomic max per block.
-__global__ __launch_bounds__(256) void k_norm1_csr_reduce(Ctrl *ctrl, const double *theta, const double *scratch,
-                                                          int64_t n) {
+__global__ __launch_bounds__(256) void k_norm1_csr_reduce(Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
+                                                          const int32_t *col, const double *val, const uint64_t *acc,
+                                                          const double *scale, int64_t n) {
     if (ctrl->error) return;
+    const double sc = *scale;
     uint64_t m = 0;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t b = dbits(scratch[c] + fabs(theta[c] + scratch[n + c]));
+        double dg = 0.0;
+        for (int32_t p = row_ptr[c]; p < row_ptr[c + 1]; ++p)
+            if (col[p] == c) dg += val[p];
+        const double off = sc > 0.0 ? (double)acc[c] / sc : NAN;  // NaN (reported as +inf) for a non-finite Delta
+        const uint64_t b = dbits(off + fabs(theta[c] + dg));
         m = b > m ? b : m;
     }
     block_atomic_max(&ctrl->norm1_bits, m);
-}
-
-__global__ void k_zero_f64(double *p, int64_t count) {
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
-        p[t] = 0.0;
 }
 
 // Z <- z0 with Z[idx[c], c] = 1 (chart U_i), or Z <- E when z0 is NULL; padding zero.
@@ -984,11 +1031,20 @@ hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count) {
     return hipGetLastError();
 }
 
+int64_t norm1_csr_scratch_doubles(int64_t n) { return n + CSR_SUM_BLOCKS + 2; }
+
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
-                            const int32_t *col, const double *val, int64_t n, double *scratch) {
-    k_zero_f64<<<blocks_for(2 * n, 256) < 2048 ? blocks_for(2 * n, 256) : 2048, 256, 0, s>>>(scratch, 2 * n);
-    k_norm1_csr_part<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, row_ptr, col, val, n, scratch);
-    k_norm1_csr_reduce<<<blocks_for(n, 256) < 512 ? blocks_for(n, 256) : 512, 256, 0, s>>>(ctrl, theta, scratch, n);
+                            const int32_t *col, const double *val, int64_t n, int64_t nnz, double *scratch) {
+    uint64_t *acc = (uint64_t *)scratch;
+    double *part = scratch + n, *scale = part + CSR_SUM_BLOCKS;
+    const int64_t work = nnz > n ? nnz : n;
+    int nb = blocks_for(work, 256);
+    nb = nb < 1 ? 1 : (nb > CSR_SUM_BLOCKS ? CSR_SUM_BLOCKS : nb);
+    k_csr_abs_sum<<<nb, 256, 0, s>>>(ctrl, val, nnz, acc, n, part);
+    k_csr_abs_scale<<<1, 256, 0, s>>>(ctrl, part, nb, scale);
+    k_csr_colsum<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, row_ptr, col, val, n, scale, acc);
+    k_norm1_csr_reduce<<<blocks_for(n, 256) < 512 ? blocks_for(n, 256) : 512, 256, 0, s>>>(ctrl, theta, row_ptr, col,
+                                                                                         val, acc, scale, n);
     return hipGetLastError();
 }
 

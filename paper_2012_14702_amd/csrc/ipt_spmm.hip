@@ -13,6 +13,10 @@
 // FP32 sweeps of the precision ladder read an FP32 copy of val and the FP32 shadow
 // of Z - E; Delta E is added exactly in FP64 (the lane meets entry (j, idx[c]) while
 // walking row j).  Every sweep writes the FP32 shadow of W - E for the next one.
+//
+// The first sweep of a cold start (unit_in) needs no product: Z = E, so Y = Delta E is
+// the entries (j, idx[c]) that the lanes meet while walking their rows (no gathers), and
+// d_c = Delta_ii comes from row i itself (eq. dyn at Z = I: F(I) = I - G o Delta).
 #include <math.h>
 
 #include "ipt_internal.h"
@@ -34,11 +38,18 @@ struct SpArgs {
     const float *zlo_in;  // FP32 shadow of Z - E (ladder only)
     float *zlo_out;       // FP32 shadow of W - E (ladder only)
     ColState cs;
-    const double *dvec;
+    double *dvec;         // read (d of this sweep), or written by a unit_in sweep
     double *part;
     int64_t n, k, ldz, kpc;
     int32_t kg;           // lanes per row
+    int32_t unit_in;      // Z = E (the product-free first sweep)
 };
+
+// Entries of a row whose gathers are issued together.  The kernel is bound by the
+// latency of its loads, so its occupancy matters most: four (64 VGPRs, 8 waves per
+// SIMD) ran faster than 8 or 16 with the operands staged in LDS (more registers, half
+// the waves), and faster than 16 rows per block (fixed latency per block dominated).
+constexpr int SP_GATHER = 4;
 
 __global__ __launch_bounds__(256) void k_spmm_sweep(const Ctrl *ctrl, SpArgs a) {
     if (ctrl->error || ctrl->done) return;
@@ -65,51 +76,51 @@ __global__ __launch_bounds__(256) void k_spmm_sweep(const Ctrl *ctrl, SpArgs a) 
             const int64_t j = jb + sub;
             if (j >= r1 || !colok) continue;
             const int32_t pb = a.row_ptr[j], pe = a.row_ptr[j + 1];
+            // the epilogue's loads of row j, issued before the walk so they overlap it
+            const double z = a.zin[j * a.ldz + c];
+            const double tj = a.theta[j];
             double y = 0.0, ye = 0.0;
             float y32 = 0.f;
-            // Entries are taken four at a time so that four gathers of Z rows are in
-            // flight per lane; the sum still runs in storage order.
-            int32_t p = pb;
+            // Entries are taken SP_GATHER at a time so that their gathers of Z rows are in
+            // flight together (a lane past the row's end re-reads row j, and its term is
+            // skipped); the sum still runs in storage order.
             if (!f32) {
-                for (; p + 4 <= pe; p += 4) {
-                    int32_t cq[4];
-                    double vq[4], zq[4];
+                for (int32_t p = pb; p < pe; p += SP_GATHER) {
+                    int32_t cq[SP_GATHER];
+                    double vq[SP_GATHER], zq[SP_GATHER];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        cq[u] = a.col[p + u];
-                        vq[u] = a.val[p + u];
+                    for (int u = 0; u < SP_GATHER; ++u) {
+                        const bool in = p + u < pe;
+                        cq[u] = in ? a.col[p + u] : (int32_t)j;
+                        vq[u] = in ? a.val[p + u] : 0.0;
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) zq[u] = a.zin[(int64_t)cq[u] * a.ldz + c];
+                    for (int u = 0; u < SP_GATHER; ++u) zq[u] = a.zin[(int64_t)cq[u] * a.ldz + c];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) y += vq[u] * zq[u];
+                    for (int u = 0; u < SP_GATHER; ++u)
+                        if (p + u < pe) y += vq[u] * zq[u];
                 }
-                for (; p < pe; ++p) y += a.val[p] * a.zin[(int64_t)a.col[p] * a.ldz + c];
             } else {
-                for (; p + 4 <= pe; p += 4) {
-                    int32_t cq[4];
-                    float vq[4], zq[4];
+                for (int32_t p = pb; p < pe; p += SP_GATHER) {
+                    int32_t cq[SP_GATHER];
+                    float vq[SP_GATHER], zq[SP_GATHER];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        cq[u] = a.col[p + u];
-                        vq[u] = a.val32[p + u];
+                    for (int u = 0; u < SP_GATHER; ++u) {
+                        const bool in = p + u < pe;
+                        cq[u] = in ? a.col[p + u] : (int32_t)j;
+                        vq[u] = in ? a.val32[p + u] : 0.f;
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) zq[u] = a.zlo_in[(int64_t)cq[u] * a.ldz + c];
+                    for (int u = 0; u < SP_GATHER; ++u) zq[u] = a.zlo_in[(int64_t)cq[u] * a.ldz + c];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        y32 += vq[u] * zq[u];
-                        if (cq[u] == i) ye += a.val[p + u];
-                    }
-                }
-                for (; p < pe; ++p) {
-                    const int32_t cp = a.col[p];
-                    y32 += a.val32[p] * a.zlo_in[(int64_t)cp * a.ldz + c];
-                    if (cp == i) ye += a.val[p];
+                    for (int u = 0; u < SP_GATHER; ++u)
+                        if (p + u < pe) {
+                            y32 += vq[u] * zq[u];
+                            if (cq[u] == i) ye += a.val[p + u];
+                        }
                 }
                 y = ye + (double)y32;
             }
-            const double z = a.zin[j * a.ldz + c];
             double w, st, gs, de;
             if (j == i) {
                 w = 1.0;
@@ -117,7 +128,7 @@ __global__ __launch_bounds__(256) void k_spmm_sweep(const Ctrl *ctrl, SpArgs a) 
                 gs = 0.0;
                 de = 0.0;
             } else {
-                const double gap = a.theta[j] - ti;
+                const double gap = tj - ti;
                 w = (z * d - y) / gap;
                 st = w - z;
                 gs = gap * st;
@@ -148,10 +159,99 @@ __global__ __launch_bounds__(256) void k_spmm_sweep(const Ctrl *ctrl, SpArgs a) 
         if (threadIdx.x < kg) {
             const int t = threadIdx.x;
             const int64_t cc = c0 + t;
-            if (cc < a.kpc) {
+            if (cc < a.k) {  // partial rows of k columns: [block][k][NPART]
 #pragma unroll
                 for (int q = 0; q < NPART; ++q)
-                    a.part[((int64_t)blockIdx.x * a.kpc + cc) * NPART + q] =
+                    a.part[((int64_t)blockIdx.x * a.k + cc) * NPART + q] =
+                        ((red[0][t][q] + red[1][t][q]) + red[2][t][q]) + red[3][t][q];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The product-free first sweep of a cold start (Z = E): per row j and column c,
+// y = sum of the entries (j, i = idx[c]) in storage order (Delta E, no gathers), W from
+// the fused update with z = [j == i], and d_c = Delta_ii written by the lane of row i.
+// Same lane layout and partial sums as k_spmm_sweep; a kernel of its own so that the
+// product kernel keeps its register budget.
+__global__ __launch_bounds__(256) void k_spmm_unit(const Ctrl *ctrl, SpArgs a) {
+    if (ctrl->error || ctrl->done) return;
+    __shared__ double red[4][64][NPART];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int kg = a.kg;
+    const int rows_per_pass = 64 / kg;
+    const int sub = lane / kg, cl = lane % kg;
+    const int64_t r0 = (int64_t)blockIdx.x * SP_ROWS;
+    int64_t r1 = r0 + SP_ROWS;
+    if (r1 > a.n) r1 = a.n;
+    for (int64_t c0 = 0; c0 < a.k; c0 += 64) {
+        const int64_t c = c0 + cl;
+        const bool colok = c < a.k && a.cs.state[c] == COL_ACTIVE;
+        const int32_t i = colok ? a.cs.idx[c] : 0;
+        const double ti = a.theta[i];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int64_t jb = r0 + (int64_t)wv * rows_per_pass; jb < r1; jb += 4 * rows_per_pass) {
+            const int64_t j = jb + sub;
+            if (j >= r1 || !colok) continue;
+            const int32_t pb = a.row_ptr[j], pe = a.row_ptr[j + 1];
+            const double tj = a.theta[j];
+            double y = 0.0;
+            // the row's entries eight at a time, their loads issued together
+            for (int32_t p = pb; p < pe; p += 8) {
+                int32_t cq[8];
+                double vq[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool in = p + u < pe;
+                    cq[u] = in ? a.col[p + u] : -1;
+                    vq[u] = in ? a.val[p + u] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (cq[u] == i) y += vq[u];
+            }
+            double w, st, gs, de;
+            if (j == i) {
+                a.dvec[c] = y;  // d_c = Delta_ii for this sweep's finalize
+                w = 1.0;
+                st = 0.0;
+                gs = 0.0;
+                de = 0.0;
+            } else {
+                const double gap = tj - ti;
+                w = -y / gap;  // (z d - y) / gap with z = 0
+                st = w;
+                gs = gap * st;
+                de = w;
+            }
+            a.zout[j * a.ldz + c] = w;
+            if (a.zlo_out) a.zlo_out[j * a.ldz + c] = (float)(j == i ? 0.0 : w);
+            s0 += st * st;
+            s1 += (j == i) ? 1.0 : 0.0;
+            s2 += gs * gs;
+            s3 += de * de;
+        }
+        for (int off = kg; off < 64; off <<= 1) {
+            s0 += __shfl_xor(s0, off);
+            s1 += __shfl_xor(s1, off);
+            s2 += __shfl_xor(s2, off);
+            s3 += __shfl_xor(s3, off);
+        }
+        if (lane < kg) {
+            red[wv][lane][0] = s0;
+            red[wv][lane][1] = s1;
+            red[wv][lane][2] = s2;
+            red[wv][lane][3] = s3;
+        }
+        __syncthreads();
+        if (threadIdx.x < kg) {
+            const int t = threadIdx.x;
+            const int64_t cc = c0 + t;
+            if (cc < a.k) {
+#pragma unroll
+                for (int q = 0; q < NPART; ++q)
+                    a.part[((int64_t)blockIdx.x * a.k + cc) * NPART + q] =
                         ((red[0][t][q] + red[1][t][q]) + red[2][t][q]) + red[3][t][q];
             }
         }
@@ -163,14 +263,14 @@ __global__ __launch_bounds__(256) void k_spmm_sweep(const Ctrl *ctrl, SpArgs a) 
 // of part[blk][c][q].  Block per (column, quantity); thread t adds blocks t, t + 256,
 // ... in order, then a fixed tree over the 256 threads.
 __global__ __launch_bounds__(256) void k_reduce_parts(const Ctrl *ctrl, const ColState cs, double *part, int64_t nblk,
-                                                      int64_t kpc) {
+                                                      int64_t ldp) {
     if (ctrl->error || ctrl->done) return;
     __shared__ double sh[256];
     const int64_t c = blockIdx.x >> 2;
     const int q = blockIdx.x & 3;
     if (cs.state[c] != COL_ACTIVE) return;
     double acc = 0.0;
-    for (int64_t b = threadIdx.x; b < nblk; b += 256) acc += part[(b * kpc + c) * NPART + q];
+    for (int64_t b = threadIdx.x; b < nblk; b += 256) acc += part[(b * ldp + c) * NPART + q];
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -228,19 +328,23 @@ inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) /
 
 int64_t spmm_row_tiles(int64_t n) { return (n + SP_ROWS - 1) / SP_ROWS; }
 
-hipError_t launch_reduce_parts(hipStream_t s, const Ctrl *ctrl, ColState cs, double *part, int64_t nblk, int64_t kpc) {
-    k_reduce_parts<<<(unsigned)(kpc * 4), 256, 0, s>>>(ctrl, cs, part, nblk, kpc);
+hipError_t launch_reduce_parts(hipStream_t s, const Ctrl *ctrl, ColState cs, double *part, int64_t nblk, int64_t ldp,
+                               int64_t kpc) {
+    k_reduce_parts<<<(unsigned)(kpc * 4), 256, 0, s>>>(ctrl, cs, part, nblk, ldp);
     return hipGetLastError();
 }
 
 hipError_t launch_spmm_sweep(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
                              const double *val, const float *val32, const double *theta, const double *zin,
-                             double *zout, const float *zlo_in, float *zlo_out, ColState cs, const double *dvec,
-                             double *part, int64_t n, int64_t k, int64_t ldz, int64_t kpc) {
+                             double *zout, const float *zlo_in, float *zlo_out, ColState cs, double *dvec,
+                             double *part, int64_t n, int64_t k, int64_t ldz, int64_t kpc, int32_t unit_in) {
     int kg = 1;
     while (kg < k && kg < 64) kg <<= 1;
-    SpArgs a{row_ptr, col, val, val32, theta, zin, zout, zlo_in, zlo_out, cs, dvec, part, n, k, ldz, kpc, kg};
-    k_spmm_sweep<<<(unsigned)spmm_row_tiles(n), 256, 0, s>>>(ctrl, a);
+    SpArgs a{row_ptr, col, val, val32, theta, zin, zout, zlo_in, zlo_out, cs, dvec, part, n, k, ldz, kpc, kg, unit_in};
+    if (unit_in)
+        k_spmm_unit<<<(unsigned)spmm_row_tiles(n), 256, 0, s>>>(ctrl, a);
+    else
+        k_spmm_sweep<<<(unsigned)spmm_row_tiles(n), 256, 0, s>>>(ctrl, a);
     return hipGetLastError();
 }
 
