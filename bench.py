@@ -101,6 +101,94 @@ def cpu_baseline(theta, delta, seconds):
                       "plain C FP64, OpenMP over columns); %.1f s" % (cols - 1, n, dt)}
 
 
+def _timeboxed(unit_fn, budget):
+    """Runs unit_fn() (which returns the eigenpairs it converged) until budget seconds
+    have passed (at least once); returns (eigenpairs, seconds, units)."""
+    done, units = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        done += unit_fn(units)
+        units += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget:
+            return done, dt, units
+
+
+def cpu_baselines(host_dense, seconds):
+    """The oracle (plain C FP64 IPT, OpenMP over columns) timed on this host for every
+    configuration, on all cores and on one core, each on a bounded sample of the
+    configuration's work (eigenpairs/s of the sample; the columns and problems are
+    independent, so the rate scales)."""
+    import numpy as np
+    import oracle
+    import workloads
+    threads = oracle.max_threads()
+    out = {"cores_all": threads, "host_cpus": os.cpu_count()}
+    th1, de1 = workloads.dense_sym_gaussian(256, 0.01, 0)
+    ths, rps, cols, vals = workloads.sparse_sym_uniform(200000, seed=0)
+    idx16 = workloads.lowest_indices(ths, 16)
+    ns = workloads.batched_sizes(4096, 32, 512, 0)
+    order = np.random.default_rng(7).permutation(4096)
+    thf, basef = workloads.family_base(1024, 0)
+    idx32 = workloads.lowest_indices(thf, 32)
+    eps_te = workloads.family_eps(128, 0.0, 0.08, seed=2)
+    budget = max(0.5, seconds / 12.0)
+
+    def dense_cols(th, de, per):
+        n = th.shape[0]
+        def unit(u):
+            lo = (u * per) % n
+            ids = np.arange(lo, min(n, lo + per), dtype=np.int32)
+            r = oracle.ipt_dense(th, de, idx=ids, tol=1e-10, resid=False)
+            return int((r.status == 0).sum())
+        return unit
+
+    def c1(u):
+        r = oracle.ipt_dense(th1, de1, tol=1e-12, resid=False)
+        return int((r.status == 0).sum())
+
+    def c3(u):
+        r = oracle.ipt_csr(ths, rps, cols, vals, idx16, tol=1e-10, resid=False)
+        return int((r.status == 0).sum())
+
+    def c4(u):
+        b = int(order[u % 4096])
+        th, de = workloads.batched_problem(b, int(ns[b]), 0.02, 0)
+        r = oracle.ipt_dense(th, de, tol=1e-10, max_iter=64, resid=False)
+        return int((r.status == 0).sum())
+
+    def c5(u):
+        e = float(eps_te[u % 128])
+        r = oracle.ipt_dense(thf, e * basef, idx=idx32, tol=1e-10, resid=False)
+        return int((r.status == 0).sum())
+
+    th2a, de2a = host_dense[0.01]
+    th2b, de2b = host_dense[0.05]
+    cases = [("dense n=256 eps=0.01 full spectrum, tol 1e-12", c1, "whole solves"),
+             ("dense n=4096 eps=0.01, tol 1e-10", None, "columns in blocks of 2 x cores"),
+             ("dense n=4096 eps=0.05, tol 1e-10", None, "columns in blocks of 2 x cores"),
+             ("sparse n=200000 k=16 lowest, tol 1e-10", c3, "whole solves"),
+             ("batched n~U{32..512}, tol 1e-10, 64 sweeps", c4, "whole problems in a fixed random order"),
+             ("learned family n=1024 k=32 cold start, tol 1e-10", c5, "test members in order")]
+    res = {}
+    for label, fn, sample in cases:
+        res[label] = {}
+        for cores in (threads, 1):
+            oracle.set_threads(cores)
+            f = fn
+            if f is None:
+                th, de = (th2a, de2a) if "0.01" in label else (th2b, de2b)
+                f = dense_cols(th, de, 2 * cores)
+            got, dt, units = _timeboxed(f, budget if cores > 1 else 2 * budget)
+            res[label]["all_cores" if cores > 1 else "one_core"] = {
+                "value": round(got / dt, 2), "unit": "eigenpairs/s", "cores": cores,
+                "sample": "%d units (%s), %d eigenpairs, %.2f s" % (units, sample, got, dt)}
+        log("cpu baseline %s: %s" % (label, {k: v["value"] for k, v in res[label].items()}))
+    oracle.set_threads(threads)
+    out["configs"] = res
+    return out
+
+
 def dtype_of(sweep_prec, mode):
     """The arithmetic of the headline solve's sweeps, in the order they ran (the
     ladder's rungs follow the steps, so this is read from the solve, not the mode)."""
@@ -171,6 +259,7 @@ def bench_batched(ipt, handle, args):
     """Batched workload: problems with n ~ U{32..512}, theta sorted U(0, n),
     Delta = 0.02 (R + R^T)/2, R iid N(0, 1/n), full spectra, tol 1e-10, max 64 sweeps;
     FP32 split-form sweeps + FP64 finish vs plain FP64."""
+    import numpy as np
     import torch
     import workloads
     B = args.batch
@@ -212,6 +301,41 @@ def bench_batched(ipt, handle, args):
         log("batched %s: %.2f ms/solve, %d/%d converged, %d sweeps, %.2f sweep-equivalents" % (
             name, sec * 1e3, inf["converged"], int(ns.sum()), inf["sweeps"], inf["matvecs"] / float(ns.sum())))
         del r
+    # Roofline of the batched GEMM on a full sweep: sweep 2 (every column still active
+    # after the product-free first sweep) timed on its own (host-launched sweeps with
+    # events around the GEMM launches); algorithmic flops sum_b 2 n_b^3, algorithmic
+    # bytes per entry of Delta_b: the Delta shadow and the Z operand (4 + 4 B for FP32
+    # tiles, 8 + 8 for FP64), the epilogue's read of Z and write of W (8 + 8 B) and, for
+    # FP32 tiles, the FP32 shadow of W - E (4 B).
+    n3 = float((ns.astype(np.float64) ** 3).sum())
+    n2 = float((ns.astype(np.float64) ** 2).sum())
+    roof = {}
+    for name, prec, peak, bpe in (("ladder", ipt.PREC_LADDER, PEAK["fp32"], 28.0),
+                                  ("fp64", ipt.PREC_FP64, PEAK["fp64"], 32.0)):
+        if args.batched_modes and name not in args.batched_modes.split(","):
+            continue
+        o = ipt.default_opts(tol=1e-10, precision=prec, max_iter=64, flags=ipt.FLAG_TIME_KERNELS)
+        run = lambda: ipt.ipt_solve_batched(ns, thd, ded, th_off, de_off, opts=o, handle=handle, z_out=z_out,
+                                            lam_out=lam_out, status_out=st_out)
+        _time(run, 1)
+        _, r = _time(run, 1)
+        inf = r.info
+        t2 = inf["sweep_ms"][1]
+        full = inf["sweep_active"][1] == int(ns.sum())
+        gemm_ms = sum(inf["sweep_ms"][1:])
+        tf = 2.0 * n3 / (t2 * 1e-3) / 1e12
+        roof[name] = {"bound": "mfma", "unit": "TFLOP/s", "peak": peak, "sweep2_ms": round(t2, 4),
+                      "sweep2_all_columns_active": bool(full), "achieved": round(tf, 2), "frac": round(tf / peak, 4),
+                      "flops_per_full_sweep": 2.0 * n3,
+                      "bytes_per_full_sweep": bpe * n2,
+                      "GBps": round(bpe * n2 / (t2 * 1e-3) / 1e9, 1),
+                      "frac_of_hbm": round(bpe * n2 / (t2 * 1e-3) / 1e9 / HBM_PEAK, 4),
+                      "gemm_ms_all_sweeps": round(gemm_ms, 3), "solve_ms_timed_kernels": round(inf["time_ms"], 3),
+                      "sweeps": inf["sweeps"]}
+        log("batched roofline %s: sweep 2 %.3f ms, %.1f TFLOP/s (%.1f%% of peak), %.0f GB/s" % (
+            name, t2, tf, 100 * tf / peak, bpe * n2 / (t2 * 1e-3) / 1e9))
+        del r
+    res["roofline"] = roof
     res["tiles"] = {"bucket_upper_n": [64 * (q + 1) for q in buckets], "tile": [tiles[q] for q in buckets],
                     "tune_s": round(t_tune, 3)}
     return {"workload": "batched %d problems n~U{32..512}, theta=sort(U(0,n)), Delta=0.02*sym N(0,1/n), "
@@ -244,6 +368,78 @@ def bench_morgan(ipt, handle, args):
             log("morgan k=%d %s: %.3f ms/solve, %d/%d converged, %d sweeps, %d matvecs" % (
                 k, name, sec * 1e3, inf["converged"], k, inf["sweeps"], inf["matvecs"]))
     return {"workload": "Morgan tridiagonal n=5000, off-diagonal 0.5, k lowest, tol 1e-12", "modes": res}
+
+
+def bench_nonsym(ipt, handle, args):
+    """The paper's dense test family (Sec. 6.2): D = diag(1..n), Delta = eps R with R iid
+    U[0,1] (non-centred, non-symmetric), eps = 0.01, full spectrum, tol 1e-10; plain FP64
+    and the ladder (the epilogue's next d reads Delta_ij itself, the matrix not being
+    symmetric)."""
+    import numpy as np
+    import torch
+    import workloads
+    dev = torch.device("cuda:0")
+    n = args.nonsym_n
+    t0 = time.perf_counter()
+    th, de = workloads.dense_uniform_nonsym(n, 0.01, 0)
+    thd, ded = torch.from_numpy(th).to(dev), torch.from_numpy(de).to(dev)
+    del de
+    log("nonsym n=%d inputs in %.1f s" % (n, time.perf_counter() - t0))
+    zbuf = torch.empty((n, n), dtype=torch.float64, device=dev)
+    res = {}
+    for name, prec in (("fp64", ipt.PREC_FP64), ("ladder", ipt.PREC_LADDER)):
+        o = ipt.default_opts(tol=1e-10, precision=prec, flags=ipt.FLAG_TIME_KERNELS)
+        sec, infos, r = solve_many(ipt, handle, thd, ded, zbuf, o, 1)
+        sec, infos, r = solve_many(ipt, handle, thd, ded, zbuf, o, 2)
+        inf = infos[-1]
+        fl, ms, la = gemm_stats(infos, n, "fp64")
+        res[name] = {"ms_per_solve": round(sec * 1e3, 3), "eigenpairs_per_s": round(inf["converged"] / sec, 1),
+                     "converged": inf["converged"], "sweeps": inf["sweeps"], "sweep_prec": inf["sweep_prec"],
+                     "sweep_active": inf["sweep_active"], "max_resid": inf["max_resid"],
+                     "fp64_gemm_tflops": round(fl / (ms * 1e-3) / 1e12, 2) if ms > 0 else None,
+                     "fp64_gemm_frac_of_peak": round(fl / (ms * 1e-3) / 1e12 / PEAK["fp64"], 4) if ms > 0 else None}
+        log("nonsym n=%d %s: %.2f ms/solve, %d converged, sweeps %s" % (n, name, sec * 1e3, inf["converged"],
+                                                                        inf["sweep_prec"]))
+        del r
+    res["ladder_speedup_vs_fp64"] = round(res["fp64"]["ms_per_solve"] / res["ladder"]["ms_per_solve"], 3)
+    return {"workload": "paper's dense family diag(1..n) + 0.01 U[0,1] (non-symmetric), n=%d, full spectrum, "
+                        "tol 1e-10" % n, "modes": res}
+
+
+def bench_morgan_sweep(ipt, handle, args):
+    """Morgan's tridiagonal matrix (n = 5000, theta_i = i) with off-diagonal eps over a
+    grid (the failure study of Sec. 6.1): status, sweeps and matvecs of the ground state
+    (k = 1) and of the 50 lowest eigenpairs, plain IPT against IPT-ACX, tol 1e-12,
+    at most 2000 applications of F."""
+    import numpy as np
+    import torch
+    import workloads
+    dev = torch.device("cuda:0")
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    grid = [0.1, 0.3, 0.5, 0.6, 0.7, 0.75, 1.0, 1.5, 2.0]
+    res = {}
+    for off in grid:
+        th, rp, col, val = workloads.morgan_tridiagonal(5000, off)
+        thd, rpd, cold, vald = tt(th), tt(rp), tt(col), tt(val)
+        row = {}
+        for k in (1, 50):
+            idx = tt(np.arange(k, dtype=np.int32))
+            for name, flags in (("plain", 0), ("acx", ipt.FLAG_ACX)):
+                o = ipt.default_opts(tol=1e-12, precision=ipt.PREC_FP64, max_iter=2000, flags=flags | ipt.FLAG_NO_NORM)
+                t0 = time.perf_counter()
+                r = ipt.ipt_solve_csr(thd, rpd, cold, vald, idx, opts=o, handle=handle, colinfo=False)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                inf = r.info
+                row["k%d_%s" % (k, name)] = {"converged": inf["converged"], "diverged": inf["diverged"],
+                                              "not_converged": inf["not_converged"], "sweeps": inf["sweeps"],
+                                              "matvecs": inf["matvecs"], "ms": round(dt * 1e3, 3)}
+        res["%g" % off] = row
+        log("morgan off-diagonal %g: k=1 plain %s/%d sweeps, acx %s/%d; k=50 plain %d conv, acx %d conv" % (
+            off, row["k1_plain"]["converged"], row["k1_plain"]["sweeps"], row["k1_acx"]["converged"],
+            row["k1_acx"]["sweeps"], row["k50_plain"]["converged"], row["k50_acx"]["converged"]))
+    return {"workload": "Morgan tridiagonal n=5000, theta_i=i, off-diagonal eps, k=1 and 50 lowest, tol 1e-12, "
+                        "at most 2000 applications of F", "by_offdiagonal": res}
 
 
 def bench_continuation(ipt, handle, args):
@@ -451,9 +647,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "ladder", "ladder_fp32_mma", "fp64"], default="all",
                     help="restrict the dense workload to one mode (for profiler runs)")
-    ap.add_argument("--extra", default="sparse,morgan,batched,learned,continuation,complex",
-                    help="comma list of secondary workloads to time: sparse, morgan, batched, learned, "
-                         "continuation, complex ('' for none)")
+    ap.add_argument("--extra", default="sparse,morgan,batched,learned,nonsym,morgan_sweep,continuation,complex",
+                    help="comma list of secondary workloads to time: sparse, morgan, batched, learned, nonsym, "
+                         "morgan_sweep, continuation, complex ('' for none)")
+    ap.add_argument("--nonsym-n", type=int, default=16384, help="size of the paper's non-symmetric dense family")
     ap.add_argument("--complex-n", type=int, default=4096, help="size of the complex workload")
     ap.add_argument("--train-steps", type=int, default=3000, help="Adam steps of the warm-start network")
     ap.add_argument("--learned-order", type=int, default=2,
@@ -497,8 +694,8 @@ def main():
         extras = [e for e in args.extra.split(",") if e]
         out = {}
         for name, fn in (("sparse", bench_sparse), ("morgan", bench_morgan), ("batched", bench_batched),
-                         ("learned", bench_learned), ("continuation", bench_continuation),
-                         ("complex", bench_complex)):
+                         ("learned", bench_learned), ("nonsym", bench_nonsym), ("morgan_sweep", bench_morgan_sweep),
+                         ("continuation", bench_continuation), ("complex", bench_complex)):
             if name in extras:
                 out[name] = fn(ipt, handle, args)
         print(json.dumps(out), flush=True)
@@ -534,7 +731,8 @@ def main():
                                     "device_ms": float(np.mean([i["time_ms"] for i in infos])),
                                     "sweeps": infos[-1]["sweeps"], "sweep_prec": infos[-1]["sweep_prec"],
                                     "sweep_active": infos[-1]["sweep_active"],
-                                    "sweep_max_step": [float("%.3g" % s) for s in infos[-1]["sweep_max_step"]]}
+                                    "sweep_max_step": [float("%.3g" % s) for s in infos[-1]["sweep_max_step"]],
+                                    "max_resid": max(float(i["max_resid"]) for i in infos)}
             log("eps=%g mode=%s: %.3f ms/solve, %d converged, sweeps %s" % (
                 eps, name, sec * 1e3, conv, infos[-1]["sweep_prec"]))
         del thd, ded
@@ -594,7 +792,9 @@ def main():
                                          "ms_per_solve": round(v["sec"] * 1e3, 4), "device_ms": round(v["device_ms"], 4),
                                          "converged": v["conv"], "sweeps": v["sweeps"], "sweep_prec": v["sweep_prec"],
                                          "sweep_active": v["sweep_active"],
-                                         "sweep_max_step": v["sweep_max_step"]}
+                                         "sweep_max_step": v["sweep_max_step"],
+                                         "max_resid": v["max_resid"],
+                                         "max_resid_within_1e-10": v["max_resid"] <= 1e-10}
                   for (e, m), v in results.items()},
     }
     if ("fp64" in modes) and ("ladder" in modes):
@@ -611,6 +811,10 @@ def main():
         out["batched"] = bench_batched(ipt, handle, args)
     if "learned" in extras:
         out["learned"] = bench_learned(ipt, handle, args)
+    if "nonsym" in extras:
+        out["nonsym"] = bench_nonsym(ipt, handle, args)
+    if "morgan_sweep" in extras:
+        out["morgan_sweep"] = bench_morgan_sweep(ipt, handle, args)
     if "continuation" in extras:
         out["continuation"] = bench_continuation(ipt, handle, args)
     if "complex" in extras:
@@ -619,6 +823,8 @@ def main():
         log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
         th, de = host[args.eps]
         out["cpu_baseline"] = cpu_baseline(th, de, args.cpu_seconds)
+        if 0.01 in host and 0.05 in host:
+            out["cpu_baseline"]["all_configs"] = cpu_baselines(host, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

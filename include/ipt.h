@@ -169,6 +169,8 @@ typedef struct ipt_info {
      * low-precision, FP32 or FP64 GEMM / SpMM) and the number of such sweeps. */
     float prec_ms[4];
     int32_t prec_sweeps[4];
+    /* With IPT_FLAG_TIME_KERNELS: device time of each sweep's product kernel(s). */
+    float sweep_ms[IPT_HIST];
 } ipt_info;
 
 /* Optional per-column device outputs (any member may be NULL). */

@@ -227,6 +227,7 @@ struct Timer {
             if (hipEventElapsedTime(&ms, h->tev[(size_t)(t - 1) * 2], h->tev[(size_t)(t - 1) * 2 + 1]) == hipSuccess) {
                 info->prec_ms[q] += ms;
                 info->prec_sweeps[q] += 1;
+                info->sweep_ms[t - 1] = ms;
             }
         }
     }

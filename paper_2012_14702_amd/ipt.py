@@ -42,7 +42,7 @@ class Info(C.Structure):
                 ("max_resid", C.c_double), ("time_ms", C.c_float), ("hist_len", C.c_int32),
                 ("sweep_prec", C.c_int32 * IPT_HIST), ("sweep_active", C.c_int32 * IPT_HIST),
                 ("sweep_max_step", C.c_double * IPT_HIST), ("prec_ms", C.c_float * 4),
-                ("prec_sweeps", C.c_int32 * 4)]
+                ("prec_sweeps", C.c_int32 * 4), ("sweep_ms", C.c_float * IPT_HIST)]
 
     def as_dict(self):
         h = self.hist_len
@@ -52,7 +52,8 @@ class Info(C.Structure):
                 "sweep_prec": [SWEEP_NAMES[p] for p in self.sweep_prec[:h]],
                 "sweep_active": list(self.sweep_active[:h]), "sweep_max_step": list(self.sweep_max_step[:h]),
                 "prec_ms": {SWEEP_NAMES[q]: self.prec_ms[q] for q in range(4)},
-                "prec_sweeps": {SWEEP_NAMES[q]: self.prec_sweeps[q] for q in range(4)}}
+                "prec_sweeps": {SWEEP_NAMES[q]: self.prec_sweeps[q] for q in range(4)},
+                "sweep_ms": list(self.sweep_ms[:h])}
 
 
 class ColInfo(C.Structure):

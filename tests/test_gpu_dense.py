@@ -263,3 +263,31 @@ def test_large_full_spectrum_sampled(ipt, eps, prec):
     check(g.z[:, cols], g.lam[cols], g.status[cols], ref, oracle.norm1(th, de), 1e-10,
           gpu_sweeps=g.sweeps[cols] if prec == "fp64" else None)
     assert np.all(g.z[np.arange(4096), np.arange(4096)] == 1.0)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["fp64", "ladder"])
+def test_paper_family_benchmarked_size_sampled(ipt, prec):
+    """The paper's non-symmetric dense family diag(i) + 0.01 U[0,1] (Sec. 6.2) at the
+    benchmarked n = 16384, full spectrum, plain FP64 and the ladder; the oracle solves a
+    sample of 40 columns (first, last, tile edges, random)."""
+    say("dense nonsym n=16384 %s" % prec)
+    n = 16384
+    th, de = W.dense_uniform_nonsym(n, 0.01, 0)
+    p = ipt.PREC_LADDER if prec == "ladder" else ipt.PREC_FP64
+    r = ipt.ipt_solve_dense(t(th), t(de), tol=1e-10, precision=p, colinfo=False)
+    cols = np.unique(np.concatenate([[0, 1, 127, 128, 8191, 8192, n - 2, n - 1],
+                                     np.random.default_rng(9).integers(0, n, 32)])).astype(np.int32)
+    st = r.status.cpu().numpy()
+    assert np.all(st == 0)
+    gz = r.z[:, torch_index(cols)].cpu().numpy()
+    gl = r.lam.cpu().numpy()[cols]
+    del r
+    ref = oracle.ipt_dense(th, de, idx=cols, tol=1e-10, resid=False)
+    check(gz, gl, st[cols], ref, oracle.norm1(th, de), 1e-10)
+    assert np.all(gz[cols, np.arange(cols.shape[0])] == 1.0)
+
+
+def torch_index(a):
+    import torch
+    return torch.from_numpy(np.asarray(a, dtype=np.int64)).to(dev())
