@@ -824,7 +824,7 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
     LookaheadPoll poll{h, ctrl};
     // d of a sweep comes from the previous sweep's product epilogue (plain sweeps: the
     // input is the previous output W), else from a pass over Delta and Z.
-    bool d_ready = false;
+    bool d_ready = false, copied = false;
     for (int32_t t = 1; t <= o.max_iter; ++t) {
         const bool first_exact = cold && t == 1;
         // Plain sweeps ping-pong between two buffers; an ACX cycle runs slot q -> q + 1
@@ -856,12 +856,23 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
         if (acx && q == pc - 1)
             IPT_HIP(h, launch_acx(s, ctrl, cs.state, zb[0], zb[1], zb[2], zb[3], kp, n, kp, pc, acx_part, acx_sigma));
         if (plan.at(t, o.max_iter)) {
+            // The first poll sits where the solve is expected to stop and waits for
+            // itself: a copy-out that runs only if the device is done goes before it,
+            // so the outputs are written while the host reads the stop words.
+            const bool spec = poll.first;
+            if (spec)
+                IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lambda_out, col_status, n, k, ci,
+                                          true));
             bool stop;
             if (ipt_status st = poll.push(stop)) return st;
-            if (stop) break;
+            if (stop) {
+                copied = spec;
+                break;
+            }
         }
     }
-    IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lambda_out, col_status, n, k, ci));
+    if (!copied)
+        IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lambda_out, col_status, n, k, ci));
     return finish(h, ctrl, k, info, &timer);
 }
 
@@ -1089,6 +1100,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     if (o.sync_every <= 0) plan.first = cold ? 3 : 2;  // sparse near-diagonal solves take few sweeps
     if (ipt_status st = ensure_poll(h)) return st;
     LookaheadPoll poll{h, ctrl};
+    bool copied = false;
     for (int32_t t = 1; t <= o.max_iter; ++t) {
         int32_t q, pc;
         acx_phase(dopt.acx, t, q, pc);
@@ -1107,12 +1119,20 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         if (acx && q == pc - 1)
             IPT_HIP(h, launch_acx(s, ctrl, cs.state, zb[0], zb[1], zb[2], zb[3], ldzb, n, k, pc, acx_part, acx_sigma));
         if (plan.at(t, o.max_iter)) {
+            const bool spec = poll.first;  // as in the dense solve: copy-out before the first poll
+            if (spec)
+                IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], ldzb, z_out, ldz, lambda_out, col_status, n, k,
+                                          ci, true));
             bool stop;
             if (ipt_status st = poll.push(stop)) return st;
-            if (stop) break;
+            if (stop) {
+                copied = spec;
+                break;
+            }
         }
     }
-    IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], ldzb, z_out, ldz, lambda_out, col_status, n, k, ci));
+    if (!copied)
+        IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], ldzb, z_out, ldz, lambda_out, col_status, n, k, ci));
     return finish(h, ctrl, k, info, &timer);
 }
 

@@ -35,6 +35,7 @@ struct Ctrl {
     int32_t prec_mask;  // batched: bit PREC_F32 set when a tile of this sweep ran in FP32
     int32_t kact;       // dense: active columns entering the next sweep (length of ColState::alist)
     int32_t sym;        // dense: 1 once Delta is verified exactly symmetric (Delta_ji may stand for Delta_ij)
+    int32_t theta_order;  // bit 0: theta not strictly increasing, bit 1: not strictly decreasing
     uint64_t acc_maxstep;  // finalize accumulator: max s_c (bit pattern of a non-negative double)
     uint64_t acc_maxres;   // max normalised eigen-residual over converged columns (bits)
     uint64_t dec_maxstep;  // max deciding step over decided columns (bits)
@@ -164,9 +165,11 @@ hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState
                            const double *theta_im = nullptr, const double *dvec_im = nullptr,
                            double *lam_im = nullptr);
 hipError_t launch_control(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep);
+// only_if_done: the kernel does nothing unless the device has set its done flag (a
+// copy-out enqueued where the solve is expected to stop, before the host knows).
 hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
                           int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out,
-                          int64_t n, int64_t k, const ipt_colinfo *ci);
+                          int64_t n, int64_t k, const ipt_colinfo *ci, bool only_if_done = false);
 hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int64_t ldzb, ColState cs, void *zt,
                          int64_t ldt, int64_t np, int64_t kp, int32_t low_type, int32_t mid_x3 = 0);
 

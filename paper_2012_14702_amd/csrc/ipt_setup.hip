@@ -77,8 +77,27 @@ __global__ void k_init_cols(Ctrl *ctrl, ColState cs, const int32_t *idx_user, in
 }
 
 // theta must be finite, and theta_j != theta_i for every j != i = idx[c]: the
-// inverse gaps G_ji are then defined for every requested column.
+// inverse gaps G_ji are then defined for every requested column.  A strictly monotone
+// theta (k_theta_order: one comparison per adjacent pair) has distinct entries, and
+// the pairwise check then returns at once.
+__global__ void k_theta_order(Ctrl *ctrl, const double *theta, int64_t n) {
+    int32_t bits = 0;
+    bool bad = false;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const double a = theta[j];
+        bad |= !isfinite(a);
+        if (j + 1 < n) {
+            const double b = theta[j + 1];
+            if (!(b > a)) bits |= 1;
+            if (!(b < a)) bits |= 2;
+        }
+    }
+    if (bad) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
+    if (bits) atomicOr(&ctrl->theta_order, bits);
+}
+
 __global__ void k_check_theta(Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n, int64_t k) {
+    if (ctrl->theta_order != 3) return;  // strictly monotone (and finite, checked with the order)
     __shared__ double ti[256];
     __shared__ int32_t ii[256];
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -881,8 +900,9 @@ __global__ __launch_bounds__(256) void k_set_dscale(Ctrl *ctrl, const uint64_t *
 __global__ __launch_bounds__(256) void k_copyout(const Ctrl *ctrl, ColState cs, const double *buf0,
                                                  const double *buf1, int64_t ldzb, double *z_out, int64_t ldz,
                                                  double *lambda_out, int32_t *status_out, int64_t n, int64_t k,
-                                                 int32_t cw, int32_t *ci_sweeps, double *ci_step, double *ci_resid) {
-    if (ctrl->error) return;
+                                                 int32_t cw, int32_t *ci_sweeps, double *ci_step, double *ci_resid,
+                                                 int32_t only_if_done) {
+    if (ctrl->error || (only_if_done && !ctrl->done)) return;
     const int rl = threadIdx.x / cw, rstep = 256 / cw;
     const int64_t c = blockIdx.x * (int64_t)cw + (threadIdx.x % cw);
     const int64_t j0 = (int64_t)blockIdx.y * 64;
@@ -1007,6 +1027,8 @@ hipError_t launch_scan_delta(hipStream_t s, Ctrl *ctrl, const double *delta, int
 
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
                               int64_t k) {
+    const int ob = blocks_for(n, 256) < 256 ? blocks_for(n, 256) : 256;
+    k_theta_order<<<ob, 256, 0, s>>>(ctrl, theta, n);
     dim3 g(blocks_for(n, 256), blocks_for(k, 256));
     k_check_theta<<<g, 256, 0, s>>>(ctrl, theta, idx, n, k);
     return hipGetLastError();
@@ -1102,13 +1124,14 @@ hipError_t launch_control(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t s
 
 hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
                           int64_t ldzb, double *z_out, int64_t ldz, double *lambda_out, int32_t *status_out, int64_t n,
-                          int64_t k, const ipt_colinfo *ci) {
+                          int64_t k, const ipt_colinfo *ci, bool only_if_done) {
     const int gy = blocks_for(n, 64) < 65535 ? blocks_for(n, 64) : 65535;
     int32_t cw = 1;
     while (cw < 256 && cw < k) cw <<= 1;
     dim3 g(blocks_for(k, cw), gy);
     k_copyout<<<g, 256, 0, s>>>(ctrl, cs, buf0, buf1, ldzb, z_out, ldz, lambda_out, status_out, n, k, cw,
-                                ci ? ci->sweeps : nullptr, ci ? ci->step : nullptr, ci ? ci->resid : nullptr);
+                                ci ? ci->sweeps : nullptr, ci ? ci->step : nullptr, ci ? ci->resid : nullptr,
+                                only_if_done ? 1 : 0);
     return hipGetLastError();
 }
 
