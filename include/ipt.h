@@ -31,6 +31,19 @@
  *     IPT_EINVAL, IPT_EDEGENERATE, IPT_ENOMEM and IPT_EHIP the output arrays are
  *     unspecified.  IPT_ENOTCONV means every output is written and some column's
  *     status is not IPT_CONVERGED.
+ *   - Logging: with IPT_LOG set (to anything but "0") in the environment, every
+ *     solve prints to stderr, after its outputs are written, one summary line (the
+ *     ipt_info fields) and one line per sweep (precision, active columns, max step
+ *     s_c and, with IPT_FLAG_TIME_KERNELS, the product kernel's time).  The lines
+ *     come from the history the device keeps, so logging adds no synchronisation
+ *     inside a solve.
+ *   - Debug mode: with IPT_GUARD set (to anything but "0") when a handle is created,
+ *     every slice a solve carves out of the handle's workspace is followed by a
+ *     4 KiB guard band of a known pattern, written before the solve's first kernel
+ *     and checked after its last; a changed band fails the solve with IPT_EGUARD and
+ *     ipt_last_error names the band.  IPT_GUARD=selftest also overwrites 8 bytes of
+ *     the second band from the host before each solve, so that the check must fire.
+ *     The no-allocation solve and the network calls carve no bands.
  */
 #ifndef IPT_H
 #define IPT_H
@@ -47,7 +60,8 @@ typedef enum ipt_status {
     IPT_EDEGENERATE = 2, /* theta_j == theta_idx[c] for some j != idx[c]: G undefined (Sec. 3) */
     IPT_ENOTCONV = 3,    /* outputs written, some column NOT_CONVERGED or DIVERGED */
     IPT_EHIP = 4,        /* a HIP runtime call failed */
-    IPT_ENOMEM = 5       /* workspace allocation failed */
+    IPT_ENOMEM = 5,      /* workspace allocation failed */
+    IPT_EGUARD = 6       /* debug mode only (IPT_GUARD): a kernel wrote into a workspace guard band */
 } ipt_status;
 
 /* Per-column status written to col_status[c]. */
@@ -124,7 +138,10 @@ typedef struct ipt_opts {
  * only FP64 sweeps certify a column.  (The sparse and batched ladders always use FP32.) */
 #define IPT_FLAG_MID_FP32 16
 /* A choice of D (the concluding section's use of the freedom in choosing D to widen
- * the convergence domain), batched solves only.  Before solving, each problem is
+ * the convergence domain), for batched solves and for full-spectrum dense solves
+ * (ipt_solve_dense with k = n, idx and z0 NULL, lda = ldz = n <= 4096, no continuation
+ * or homotopy: run as a batch of one problem, so a ladder runs the batched FP32 and FP64
+ * sweeps and opts.low_type is ignored).  Before solving, each problem is
  * re-partitioned, M unchanged:
  *  1. Near-degenerate pairs: i, j that are each other's strongest coupling relative
  *     to the gap, r_ij = |Delta_ij| / |theta_i - theta_j| > IPT_PAIR_TAU, with
@@ -135,8 +152,9 @@ typedef struct ipt_opts {
  *     s_i = sum_{k != i} Delta_ik Delta_ki / ((theta + Delta_ii)_i - (theta + Delta_kk)_k),
  *     Delta'_ii = -s_i.
  * IPT runs on (theta', Delta') (same eigenvalues) and z = R z' is returned, so a paired
- * column c is normalized by (R^T z)_c = 1 instead of z_c = 1.  The re-partitioned
- * copies of the pools take a second workspace of their size. */
+ * column c is normalized by (R^T z)_c = 1 instead of z_c = 1.  Residuals are normalised
+ * by |M'|_1 of the re-partitioned matrix (reported as info.norm1 by a dense solve).  The
+ * re-partitioned copies of the pools take a second workspace of their size. */
 #define IPT_FLAG_CHOOSE_D 32
 #define IPT_PAIR_TAU 0.05
 /* Ladder rule (dense and sparse): the precision of the next sweep follows the steps

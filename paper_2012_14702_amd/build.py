@@ -33,6 +33,39 @@ def build(jobs: int = 4) -> str:
     return LIB
 
 
+# Host sanitizer variant: the library's host code (argument checks, workspace layout,
+# sweep loops, polling) built with the address and undefined-behaviour sanitizers, the
+# kernels as above, and a driver that calls every entry point through the C ABI.
+SAN = ["-g", "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+       "-Xarch_host", "-fno-sanitize-recover=undefined"]
+SAN_DIR = os.path.join(HERE, "_build_hostsan")
+SAN_LIB = os.path.join(SAN_DIR, "libipt_hostsan.so")
+SAN_DRIVER = os.path.join(SAN_DIR, "abi_sanitize_driver")
+DRIVER_SRC = os.path.join(os.path.dirname(HERE), "tests", "abi_sanitize_driver.cpp")
+
+
+def build_hostsan(jobs: int = 4) -> str:
+    os.makedirs(SAN_DIR, exist_ok=True)
+    procs, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(SAN_DIR, src.replace(".hip", ".o"))
+        objs.append(obj)
+        cmd = [HIPCC] + FLAGS + SAN + ["-c", os.path.join(CSRC, src), "-o", obj]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        if len(procs) >= jobs:
+            _wait(procs.pop(0))
+    for p in procs:
+        _wait(p)
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", SAN_LIB + ".tmp"] + SAN + objs)
+    os.replace(SAN_LIB + ".tmp", SAN_LIB)
+    include = os.path.join(os.path.dirname(HERE), "include")
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-std=c++17", "-O1"] + SAN +
+                          ["-I", include, DRIVER_SRC, "-o", SAN_DRIVER + ".tmp", "-L", SAN_DIR, "-lipt_hostsan",
+                           "-Wl,-rpath," + SAN_DIR])
+    os.replace(SAN_DRIVER + ".tmp", SAN_DRIVER)
+    return SAN_DRIVER
+
+
 def _wait(item):
     src, p = item
     out, _ = p.communicate()
@@ -47,3 +80,5 @@ def _wait(item):
 
 if __name__ == "__main__":
     print(build())
+    if len(sys.argv) > 1 and sys.argv[1] == "hostsan":
+        print(build_hostsan())

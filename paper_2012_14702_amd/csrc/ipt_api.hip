@@ -3,6 +3,8 @@
 // sweep runs in the device kernels; the host only launches and, every
 // sync_every sweeps, reads the device stop flag.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -61,6 +63,12 @@ struct ipt_context {
     std::vector<unsigned char> bgraph_key;     // the launch arguments it was captured with
     int32_t *poll_host = nullptr;              // pinned [2][2]: error/done words of two polls in flight
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    // debug mode (IPT_GUARD at ipt_create): guard bands of the running solve's workspace
+    bool guard = false, guard_poke = false, guard_armed = false;
+    std::vector<size_t> bands;                 // byte offsets of the bands from guard_base
+    char *guard_base = nullptr;
+    void *band_mem = nullptr;                  // device copy of the offsets, then the damage word
+    size_t band_bytes = 0;
     ipt_context() {
         for (int q = 0; q < IPT_TILE_BUCKETS; ++q) batch_tile[q] = q < 3 ? 64 : 128;
     }
@@ -91,15 +99,27 @@ ipt_status fail(ipt_handle h, ipt_status st, const std::string &msg) {
         if (e_ != hipSuccess) return fail((h), IPT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// Bump allocator over the handle's workspace (256-byte aligned slices).
+// Bump allocator over the handle's workspace (256-byte aligned slices).  In the debug
+// mode every slice is followed by a guard band (and one precedes the first); the pass
+// with a base records where the bands are.
+constexpr size_t GUARD_BYTES = 4096;
 struct Carve {
     size_t off = 0;
     char *base = nullptr;
+    size_t gbytes = 0;
+    std::vector<size_t> *bands = nullptr;
+    void band() {
+        if (!gbytes) return;
+        off = (off + 255) & ~size_t(255);
+        if (bands) bands->push_back(off);
+        off += gbytes;
+    }
     template <typename T>
     T *take(size_t count) {
         off = (off + 255) & ~size_t(255);
         T *p = base ? (T *)(base + off) : nullptr;
         off += count * sizeof(T);
+        band();
         return p;
     }
 };
@@ -126,6 +146,58 @@ ipt_status ensure_buf(ipt_handle h, void *&buf, size_t &have, size_t bytes) {
 }
 
 ipt_status ensure_ws(ipt_handle h, size_t bytes) { return ensure_buf(h, h->ws, h->ws_bytes, bytes); }
+
+// A workspace carve for handle h: base NULL for the sizing pass.  Guard bands only in
+// the debug mode and where the solve may allocate (the no-allocation solve has none).
+Carve carve(ipt_handle h, char *base, bool guarded = true) {
+    Carve c;
+    c.base = base;
+    if (h->guard && guarded) {
+        c.gbytes = GUARD_BYTES;
+        if (base) {
+            h->bands.clear();
+            c.bands = &h->bands;
+        }
+        c.band();
+    }
+    return c;
+}
+
+// Debug mode: fill the bands of the carve just laid out with the guard pattern (and,
+// in the self-test mode, overwrite 8 bytes of the second band from the host, as a
+// kernel writing past the first slice would).  Stream-ordered before the solve.
+ipt_status guard_arm(ipt_handle h, const Carve &cv) {
+    h->guard_armed = false;
+    if (!cv.bands || h->bands.empty()) return IPT_OK;
+    const size_t nb = h->bands.size(), list_bytes = round_up(nb * sizeof(uint64_t), 256);
+    if (ipt_status st = ensure_buf(h, h->band_mem, h->band_bytes, list_bytes + 256)) return st;
+    uint64_t *list = (uint64_t *)h->band_mem;
+    int32_t *damage = (int32_t *)((char *)h->band_mem + list_bytes);
+    IPT_HIP(h, hipMemcpyAsync(list, h->bands.data(), nb * sizeof(uint64_t), hipMemcpyHostToDevice, h->stream));
+    IPT_HIP(h, launch_guard_fill(h->stream, cv.base, list, (int64_t)nb, (int64_t)(GUARD_BYTES / 8), damage));
+    if (h->guard_poke && nb > 1) IPT_HIP(h, hipMemsetAsync(cv.base + h->bands[1] + 64, 0, 8, h->stream));
+    IPT_HIP(h, hipStreamSynchronize(h->stream));  // the host list may change with the next solve
+    h->guard_base = cv.base;
+    h->guard_armed = true;
+    return IPT_OK;
+}
+
+// Debug mode, after the solve's last kernel: IPT_EGUARD names the first damaged band.
+ipt_status guard_check(ipt_handle h) {
+    if (!h->guard_armed) return IPT_OK;
+    h->guard_armed = false;
+    const size_t nb = h->bands.size(), list_bytes = round_up(nb * sizeof(uint64_t), 256);
+    const uint64_t *list = (const uint64_t *)h->band_mem;
+    int32_t *damage = (int32_t *)((char *)h->band_mem + list_bytes);
+    IPT_HIP(h, launch_guard_check(h->stream, h->guard_base, list, (int64_t)nb, (int64_t)(GUARD_BYTES / 8), damage));
+    int32_t bad = 0;
+    IPT_HIP(h, hipMemcpyAsync(&bad, damage, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
+    IPT_HIP(h, hipStreamSynchronize(h->stream));
+    if (bad == INT32_MAX) return IPT_OK;
+    return fail(h, IPT_EGUARD,
+                "workspace guard band " + std::to_string(bad) + " (byte offset " + std::to_string(h->bands[bad]) +
+                    ") was overwritten: a kernel wrote past the end of slice " + std::to_string(bad - 1));
+}
 
 ipt_status check_opts(ipt_handle h, const ipt_opts *in, ipt_opts &o) {
     ipt_opts_default(&o);
@@ -247,19 +319,60 @@ PollPlan poll_plan(const ipt_opts &o, bool cold) {
     return PollPlan{cold ? 4 : 3, 1};
 }
 
-ipt_status finish(ipt_handle h, Ctrl *dev, int64_t k, ipt_info *info, Timer *timer) {
+// IPT_LOG set (and not "0") in the environment: every solve prints a summary line and
+// one line per sweep to stderr, from the history the device keeps (nothing is added
+// to the solve itself; the lines are written after its final synchronisation).
+bool log_enabled() {
+    const char *e = getenv("IPT_LOG");  // read at every solve, so it can be switched at run time
+    return e && *e && strcmp(e, "0") != 0;
+}
+
+void log_solve(const char *kind, int64_t k, const ipt_info &inf, ipt_status st, bool timed) {
+    static const char *prec_name[4] = {"exact-first", "low", "fp32", "fp64"};
+    fprintf(stderr,
+            "[ipt] %s: columns=%lld status=%s sweeps=%d converged=%d not_converged=%d diverged=%d matvecs=%lld "
+            "max_step=%.3e max_resid=%.3e norm1=%.6e time_ms=%.3f\n",
+            kind, (long long)k, st == IPT_OK ? "IPT_OK" : "IPT_ENOTCONV", inf.sweeps, inf.converged, inf.not_converged, inf.diverged,
+            (long long)inf.matvecs, inf.max_step, inf.max_resid, inf.norm1, inf.time_ms);
+    for (int q = 0; q < inf.hist_len; ++q) {
+        const int p = inf.sweep_prec[q];
+        fprintf(stderr, "[ipt] %s sweep %d: %s active=%d max_step=%.3e", kind, q + 1,
+                (p >= 0 && p < 4) ? prec_name[p] : "?", inf.sweep_active[q], inf.sweep_max_step[q]);
+        if (timed) fprintf(stderr, " product_ms=%.4f", inf.sweep_ms[q]);
+        fputc('\n', stderr);
+    }
+    fflush(stderr);
+}
+
+// End of a solve: wait for it, turn device errors into status codes, fill *info.
+// maxres_dev (batched solves): the max residual the copy-out reduced on the device.
+ipt_status finish(ipt_handle h, Ctrl *dev, int64_t k, ipt_info *info, Timer *timer, const char *kind,
+                  const double *maxres_dev, const uint64_t *norm_bits_dev = nullptr) {
     IPT_HIP(h, hipEventRecord(h->ev_stop, h->stream));
     IPT_HIP(h, hipMemcpyAsync(h->host_ctrl, dev, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
     IPT_HIP(h, hipStreamSynchronize(h->stream));
     float ms = 0.f;
     IPT_HIP(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
+    if (ipt_status st = guard_check(h)) return st;
     const Ctrl &c = *h->host_ctrl;
     if (c.error == IPT_EDEGENERATE)
         return fail(h, IPT_EDEGENERATE, "theta_j == theta_idx[c] for some j != idx[c]: inverse gap undefined");
     if (c.error) return fail(h, IPT_EINVAL, "idx out of range or repeated, or theta not finite");
-    fill_info(c, info, ms);
-    if (timer) timer->collect(c, info);
-    if (c.n_conv == k) return IPT_OK;
+    const bool logging = log_enabled();
+    ipt_info local;
+    ipt_info *out = info ? info : (logging ? &local : nullptr);
+    fill_info(c, out, ms);
+    if (timer) timer->collect(c, out);
+    if (out && maxres_dev) {
+        double mr = 0.0, nm = 0.0;
+        IPT_HIP(h, hipMemcpy(&mr, maxres_dev, sizeof(double), hipMemcpyDeviceToHost));
+        if (norm_bits_dev) IPT_HIP(h, hipMemcpy(&nm, norm_bits_dev, sizeof(double), hipMemcpyDeviceToHost));
+        out->max_resid = mr;
+        out->norm1 = nm;  // a batch of one problem reports its |M|_1
+    }
+    const ipt_status st = (c.n_conv == k) ? IPT_OK : IPT_ENOTCONV;
+    if (logging) log_solve(kind, k, *out, st, timer && timer->on);
+    if (st == IPT_OK) return IPT_OK;
     h->last_error = "some columns did not converge";
     return IPT_ENOTCONV;
 }
@@ -306,7 +419,7 @@ struct BatchGraphKey {
     DevOpts dopt;
     Ctrl *ctrl;
     int64_t total_cols;
-    int32_t grid[3], has[3], chunk;
+    int32_t grid[NCLS], has[NCLS], chunk;
 };
 
 template <typename F>
@@ -342,7 +455,7 @@ ipt_status ensure_batch_graph(ipt_handle h, const BatchGraphKey &key, F capture)
 ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
                        const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
                        const double *delta_pool, const ipt_opts &o, double *z_pool, double *lambda_pool,
-                       int32_t *status_pool, ipt_info *info, int force_T) {
+                       int32_t *status_pool, ipt_info *info, int force_T, const ipt_colinfo *ci = nullptr) {
     if (count < 1) return fail(h, IPT_EINVAL, "count must be >= 1");
     if (!ns || !theta_off || !delta_off || !z_off || !theta_pool || !delta_pool || !z_pool || !lambda_pool ||
         !status_pool)
@@ -365,15 +478,24 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return ns[x] > ns[y]; });
     std::vector<BatchMeta> meta(count);
     std::vector<int4> it_s1;
-    int64_t offz = 0, offc = 0, offp = 0, offq = 0, offf = 0, cap[3] = {0, 0, 0};
+    int64_t offz = 0, offc = 0, offp = 0, offq = 0, offf = 0, cap[NCLS] = {0, 0, 0, 0}, capx[NCLS][NXCD] = {};
+    double load[3][NXCD] = {};
     for (int32_t b : order) {
         const int64_t n = ns[b];
         const int T = force_T ? force_T : h->batch_tile[(n - 1) / 64];
         const int64_t np = round_up(n, T), nt = np / T, ncb = (np + 63) / 64;
+        const int cl = T == 32 ? 0 : (T == 64 ? 1 : 2);
+        // deal the problem to the least loaded die of its class (work ~ np^3)
+        int x = 0;
+        for (int y = 1; y < NXCD; ++y)
+            if (load[cl][y] < load[cl][x]) x = y;
+        load[cl][x] += (double)np * np * np;
         BatchMeta &m = meta[b];
         m.n = (int32_t)n;
         m.T = T;
         m.np = (int32_t)np;
+        m.xcd = x;
+        capx[cl][x] += nt * nt;
         m.offd = delta_off[b];
         m.offt = theta_off[b];
         m.offo = z_off[b];
@@ -387,18 +509,29 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
         offp += nt * n * NPART;
         offq += nt * n;
         offf += nt;
-        cap[T == 32 ? 0 : (T == 64 ? 1 : 2)] += nt * nt;
+        cap[cl] += nt * nt;
+        if (np % 64 == 0) {  // at most one narrow column tile per problem: its nt row tiles
+            cap[CLS_NARROW] += nt;
+            capx[CLS_NARROW][x] += nt;
+        }
         for (int tm = 0; tm < nt; ++tm)
             for (int cb = 0; cb < ncb; ++cb) it_s1.push_back(make_int4(b, tm, cb, 0));
     }
     const int64_t total_cols = offc, total_tiles = offf, total_q = offq;
-    if (total_cols > INT32_MAX / 2 || cap[0] > INT32_MAX / 2 || cap[1] > INT32_MAX / 2 || cap[2] > INT32_MAX / 2)
+    if (total_cols > INT32_MAX / 2 || cap[0] > INT32_MAX / 2 || cap[1] > INT32_MAX / 2 || cap[2] > INT32_MAX / 2 ||
+        cap[3] > INT32_MAX / 2)
         return fail(h, IPT_EINVAL, "batch too large");
 
     BatchLaunch L;
     memset(&L, 0, sizeof(L));
     BatchLists lists;
     memset(&lists, 0, sizeof(lists));
+    int64_t segcap[NCLS] = {0, 0, 0, 0};
+    for (int c = 0; c < NCLS; ++c) {
+        for (int x = 0; x < NXCD; ++x) segcap[c] = std::max(segcap[c], capx[c][x]);
+        if (NXCD * segcap[c] > INT32_MAX / 2) return fail(h, IPT_EINVAL, "batch too large");
+        lists.segcap[c] = (int32_t)segcap[c];
+    }
     BatchMeta *dmeta;
     int4 *ds1;
     double *maxres;
@@ -434,21 +567,21 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
         L.dpart = cv.take<double>(total_q);
         L.normpart = cv.take<double>(total_q);
         L.tflag = cv.take<uint32_t>(2 * total_tiles);
-        for (int c = 0; c < 3; ++c)
-            for (int p = 0; p < 2; ++p) lists.l[c][p] = cv.take<int4>(cap[c] + 1);
-        cnt = cv.take<int32_t>(9);
+        for (int c = 0; c < NCLS; ++c)
+            for (int p = 0; p < 2; ++p) lists.l[c][p] = cv.take<int4>(NXCD * segcap[c] + 1);
+        cnt = cv.take<int32_t>(BLIST_WORDS);
         maxres = cv.take<double>(1);
         ctrl = cv.take<Ctrl>(1);
     };
-    Carve sizing;
+    Carve sizing = carve(h, nullptr);
     layout(sizing);
     if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
     if (ipt_status st = ensure_poll(h)) return st;
-    Carve cv;
-    cv.base = (char *)h->ws;
+    Carve cv = carve(h, (char *)h->ws);
     layout(cv);
+    if (ipt_status st = guard_arm(h, cv)) return st;
     lists.counts = cnt;
-    lists.tickets = cnt + 6;
+    lists.tickets = cnt + BLIST_COUNTS;
     L.meta = dmeta;
     L.theta = theta_pool;
     L.delta = delta_pool;
@@ -470,9 +603,11 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
     key.ctrl = ctrl;
     key.total_cols = total_cols;
     key.chunk = o.sync_every > 0 ? o.sync_every : 4;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NCLS; ++c) {
         key.has[c] = cap[c] > 0;
-        key.grid[c] = cap[c] > 0 ? (int32_t)std::min<int64_t>(bgemm_grid(tsize[c]), cap[c]) : 0;
+        // a multiple of NXCD blocks, so that every die has blocks starting on its own segment
+        const int64_t full = c == CLS_NARROW ? bnarrow_grid() : bgemm_grid(tsize[c]);
+        key.grid[c] = cap[c] > 0 ? (int32_t)round_up(std::min<int64_t>(full, cap[c]), NXCD) : 0;
     }
     // One sweep after the first: the GEMM per tile class (largest tiles first), the
     // finalize, the control kernel.
@@ -481,6 +616,8 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
         hipError_t e = timer.mark(t_host, 0, st);
         for (int c = 2; c >= 0 && e == hipSuccess; --c)
             if (key.has[c]) e = launch_bgemm(st, ctrl, L, lists, tsize[c], key.grid[c], dopt.acx);
+        if (e == hipSuccess && key.has[CLS_NARROW])
+            e = launch_bnarrow(st, ctrl, L, lists, key.grid[CLS_NARROW], dopt.acx);
         if (e == hipSuccess) e = timer.mark(t_host, 1, st);
         if (e == hipSuccess) e = launch_bfinalize(st, ctrl, dopt, L, total_cols, lists);
         if (e == hipSuccess) e = launch_bplan(st, ctrl, L, lists, count);
@@ -501,7 +638,7 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
     IPT_HIP(h, timer.ensure());
     IPT_HIP(h, hipEventRecord(h->ev_start, s));
     IPT_HIP(h, launch_ctrl_init(s, ctrl, PREC_EXACT_FIRST, total_cols));
-    IPT_HIP(h, launch_fill_f32(s, (float *)cnt, 9));
+    IPT_HIP(h, launch_fill_f32(s, (float *)cnt, BLIST_WORDS));
     IPT_HIP(h, launch_fill_f32(s, (float *)maxres, 2));
     IPT_HIP(h, launch_binit(s, ctrl, L, count, ladder ? PREC_F32 : PREC_F64));
     // sweep 1: product-free
@@ -529,15 +666,10 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
         if (ipt_status st = poll.push(stop)) return st;
         if (stop) break;
     }
-    IPT_HIP(h, launch_bcopyout(s, ctrl, L, ds1, (int64_t)it_s1.size(), z_pool, lambda_pool, status_pool, maxres));
-    ipt_status st = finish(h, ctrl, total_cols, info, &timer);
-    if (info && (st == IPT_OK || st == IPT_ENOTCONV)) {
-        double mr = 0.0;
-        IPT_HIP(h, hipMemcpy(&mr, maxres, sizeof(double), hipMemcpyDeviceToHost));
-        info->max_resid = mr;
-        info->norm1 = 0.0;
-    }
-    return st;
+    IPT_HIP(h, launch_bcopyout(s, ctrl, L, ds1, (int64_t)it_s1.size(), z_pool, lambda_pool, status_pool, maxres,
+                               ci ? ci->sweeps : nullptr, ci ? ci->step : nullptr, ci ? ci->resid : nullptr));
+    return finish(h, ctrl, total_cols, info, &timer, "batched", maxres,
+                  count == 1 ? L.col.norm_bits : nullptr);
 }
 
 }  // namespace
@@ -576,6 +708,10 @@ ipt_status ipt_create(ipt_handle *out, void *stream) {
         return IPT_ENOMEM;
     }
     h->stream = (hipStream_t)stream;
+    if (const char *g = getenv("IPT_GUARD")) {
+        h->guard = *g && strcmp(g, "0") != 0;
+        h->guard_poke = strcmp(g, "selftest") == 0;
+    }
     // set-up that no solve may do later: the poll buffers (pinned host memory) and the
     // device address of the no-allocation workspace on this device
     const hipError_t es = init_scratch(h->device);
@@ -594,6 +730,7 @@ ipt_status ipt_destroy(ipt_handle h) {
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
     if (h->pws) (void)hipFree(h->pws);
+    if (h->band_mem) (void)hipFree(h->band_mem);
     if (h->host_ctrl) (void)hipHostFree(h->host_ctrl);
     (void)hipEventDestroy(h->ev_start);
     (void)hipEventDestroy(h->ev_stop);
@@ -621,6 +758,7 @@ const char *ipt_status_string(ipt_status s) {
         case IPT_ENOTCONV: return "IPT_ENOTCONV: some columns did not converge";
         case IPT_EHIP: return "IPT_EHIP: HIP runtime error";
         case IPT_ENOMEM: return "IPT_ENOMEM: out of device memory";
+        case IPT_EGUARD: return "IPT_EGUARD: a workspace guard band was overwritten (debug mode)";
     }
     return "unknown ipt_status";
 }
@@ -683,6 +821,11 @@ namespace {
 
 // The dense solve.  noalloc: the workspace is the device's no-allocation array
 // (scratch_ptr) instead of the handle's, and nothing is allocated.
+ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
+                         const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
+                         const double *delta_pool, const ipt_opts &o, double *z_pool, double *lambda_pool,
+                         int32_t *status_pool, ipt_info *info, const ipt_colinfo *ci);
+
 ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const double *delta, int64_t lda, int64_t k,
                        const int32_t *idx, const double *z0, int64_t ldz0, const ipt_opts *opts, double *z_out,
                        int64_t ldz, double *lambda_out, int32_t *col_status, ipt_info *info, const ipt_colinfo *ci,
@@ -700,6 +843,19 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
     if (ipt_status st = check_opts(h, opts, o)) return st;
     if (noalloc && (o.homotopy_q > 1 || (o.flags & IPT_FLAG_TIME_KERNELS)))
         return fail(h, IPT_EINVAL, "the no-allocation solve takes neither opts.homotopy_q > 1 nor IPT_FLAG_TIME_KERNELS");
+    if (o.flags & IPT_FLAG_CHOOSE_D) {
+        // the choice of D re-partitions the whole problem: a full-spectrum cold solve, run
+        // as a batch of one problem (ns = n, every offset 0)
+        if (noalloc || idx || z0 || k != n || lda != n || ldz != n || n > 4096 || o.cont_alpha > 0.0 ||
+            o.homotopy_q > 1)
+            return fail(h, IPT_EINVAL,
+                        "IPT_FLAG_CHOOSE_D on a dense solve: full spectrum (k = n, idx NULL), cold start, lda = ldz = n, "
+                        "n <= 4096, no continuation, homotopy or no-allocation entry");
+        DeviceGuard guard(h->device);
+        const int32_t nn = (int32_t)n;
+        const int64_t zero = 0;
+        return batched_pairs(h, 1, &nn, &zero, &zero, &zero, theta, delta, o, z_out, lambda_out, col_status, info, ci);
+    }
     if (o.homotopy_q > 1) return homotopy_dense(h, n, theta, delta, lda, k, idx, z0, ldz0, o, z_out, ldz, lambda_out,
                                                 col_status, info, ci);
     const DevOpts dopt = dev_opts(o);
@@ -766,11 +922,11 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
     void *dlo, *zt;
     float *d32;
     Ctrl *ctrl;
-    Carve sizing;
+    Carve sizing = carve(h, nullptr, !noalloc);
     layout(sizing, zb, cs, &dnp, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
     Carve cv;
     if (noalloc) {
-        cv.base = (char *)scratch_ptr(h->device);
+        cv = carve(h, (char *)scratch_ptr(h->device), false);
         if (!cv.base) return fail(h, IPT_EINVAL, "no no-allocation workspace on this device");
         if (sizing.off > IPT_NOALLOC_SCRATCH_BYTES)
             return fail(h, IPT_EINVAL, "this solve needs " + std::to_string(sizing.off) +
@@ -778,9 +934,10 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
                                            std::to_string((size_t)IPT_NOALLOC_SCRATCH_BYTES));
     } else {
         if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
-        cv.base = (char *)h->ws;
+        cv = carve(h, (char *)h->ws);
     }
     layout(cv, zb, cs, &dnp, &dvec, &part, &bitmap, &scratch, &dpad, &dlo, &d32, &zt, &ctrl);
+    if (ipt_status st = guard_arm(h, cv)) return st;
 
     Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
     IPT_HIP(h, timer.ensure());
@@ -793,7 +950,7 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
     // continuation sweeps rescale W after the product, so d comes from the pass over Delta
     const bool cont = o.cont_alpha > 0.0;
     const bool fuse_d = !acx && !cont;
-    IPT_HIP(h, launch_ctrl_init(s, ctrl, start_prec, k, fuse_d ? 1 : 0, o.cont_alpha));
+    IPT_HIP(h, launch_ctrl_init(s, ctrl, start_prec, k, fuse_d ? 1 : 0, o.cont_alpha, bitmap, n));
     // Row-major pass over Delta (copy, BF16/FP32 shadows, |M|_1, max |Delta|), then the
     // tile-pair pass (symmetry, FP16 shadows at the power-of-two scale from that max)
     const double *dA = direct ? delta : dpad;
@@ -806,9 +963,9 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
     if (fuse_d || want_max)
         IPT_HIP(h, launch_scan_delta(s, ctrl, delta, lda, n, np, fuse_d, low16 ? (_Float16 *)dlo : nullptr,
                                      mid_x3 ? (_Float16 *)d32 : nullptr));
-    IPT_HIP(h, launch_init_cols(s, ctrl, cs, idx, n, k, kp, bitmap, (int32_t)ntn, 0));
-    IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
-    IPT_HIP(h, launch_plan_dense(s, ctrl, cs, kp));
+    // column state, the packed list of the first sweep and theta's order in one launch
+    IPT_HIP(h, launch_init_cols(s, ctrl, cs, idx, n, k, kp, bitmap, (int32_t)ntn, 0, true, theta));
+    IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k, true));
     const bool padded = (np != n) || (kp != k);
     if (cold && !acx) {
         if (padded) IPT_HIP(h, launch_zero_pad(s, zb[0], kp, n, np, k, kp));
@@ -873,7 +1030,7 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
     }
     if (!copied)
         IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lambda_out, col_status, n, k, ci));
-    return finish(h, ctrl, k, info, &timer);
+    return finish(h, ctrl, k, info, &timer, "dense", nullptr);
 }
 
 }  // namespace
@@ -954,23 +1111,22 @@ ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const
     ColState cs;
     uint32_t *bitmap;
     Ctrl *ctrl;
-    Carve sizing;
+    Carve sizing = carve(h, nullptr);
     layout(sizing, zb, cs, &d_re, &d_im, &dpart, &lam_im, &th_re, &th_im, &part, &part2, &bitmap, &ctrl);
     if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
-    Carve cv;
-    cv.base = (char *)h->ws;
+    Carve cv = carve(h, (char *)h->ws);
     layout(cv, zb, cs, &d_re, &d_im, &dpart, &lam_im, &th_re, &th_im, &part, &part2, &bitmap, &ctrl);
+    if (ipt_status st = guard_arm(h, cv)) return st;
 
     Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
     IPT_HIP(h, timer.ensure());
     IPT_HIP(h, hipEventRecord(h->ev_start, s));
     // the first sweep of a cold start needs no product (Delta E is a gather)
     const bool cold = (z0 == nullptr);
-    IPT_HIP(h, launch_ctrl_init(s, ctrl, cold ? PREC_EXACT_FIRST : PREC_F64, k));
+    IPT_HIP(h, launch_ctrl_init(s, ctrl, cold ? PREC_EXACT_FIRST : PREC_F64, k, 0, 0.0, bitmap, n));
     IPT_HIP(h, launch_zsetup(s, ctrl, theta, delta, lda, th_re, th_im, part2, n));
-    IPT_HIP(h, launch_init_cols(s, ctrl, cs, idx, n, k, kp, bitmap, (int32_t)ntn, 0));
+    IPT_HIP(h, launch_init_cols(s, ctrl, cs, idx, n, k, kp, bitmap, (int32_t)ntn, 0, true));
     IPT_HIP(h, launch_zcheck_gaps(s, ctrl, th_re, th_im, cs.idx, n, k));
-    IPT_HIP(h, launch_plan_dense(s, ctrl, cs, kp));
     IPT_HIP(h, launch_zload(s, ctrl, z0, ldz0, zb[0], kp, cs.idx, n, np, k));
     IPT_HIP(h, launch_zload(s, ctrl, nullptr, 0, zb[1], kp, cs.idx, n, np, k));
 
@@ -1001,7 +1157,7 @@ ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const
         }
     }
     IPT_HIP(h, launch_zcopyout(s, ctrl, cs, zb[0], zb[1], kp, z_out, ldz, lam_im, lambda_out, col_status, n, k, ci));
-    return finish(h, ctrl, k, info, &timer);
+    return finish(h, ctrl, k, info, &timer, "complex", nullptr);
 }
 
 ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int32_t *row_ptr, const int32_t *col,
@@ -1068,12 +1224,12 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     ColState cs;
     uint32_t *bitmap;
     Ctrl *ctrl;
-    Carve sizing;
+    Carve sizing = carve(h, nullptr);
     layout(sizing, zb, zlo, cs, &dvec, &part, &bitmap, &scratch, &val32, &ctrl);
     if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
-    Carve cv;
-    cv.base = (char *)h->ws;
+    Carve cv = carve(h, (char *)h->ws);
     layout(cv, zb, zlo, cs, &dvec, &part, &bitmap, &scratch, &val32, &ctrl);
+    if (ipt_status st = guard_arm(h, cv)) return st;
 
     Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
     IPT_HIP(h, timer.ensure());
@@ -1133,7 +1289,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     }
     if (!copied)
         IPT_HIP(h, launch_copyout(s, ctrl, cs, zb[0], zb[1], ldzb, z_out, ldz, lambda_out, col_status, n, k, ci));
-    return finish(h, ctrl, k, info, &timer);
+    return finish(h, ctrl, k, info, &timer, "csr", nullptr);
 }
 
 namespace {
@@ -1141,10 +1297,10 @@ namespace {
 // IPT_FLAG_CHOOSE_D on a batch: copies of the pools (at the caller's offsets) are
 // re-partitioned (near-degenerate pairs rotated out, level shifts moved into D), the
 // batch is solved on them, and the eigenvectors are rotated back in z_pool.
-static ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
+ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, const int64_t *theta_off,
                          const int64_t *delta_off, const int64_t *z_off, const double *theta_pool,
                          const double *delta_pool, const ipt_opts &o, double *z_pool, double *lambda_pool,
-                         int32_t *status_pool, ipt_info *info) {
+                         int32_t *status_pool, ipt_info *info, const ipt_colinfo *ci) {
     if (count < 1 || !ns || !theta_off || !delta_off || !z_off || !theta_pool || !delta_pool || !z_pool)
         return fail(h, IPT_EINVAL, "bad batch description");
     int64_t tlo = INT64_MAX, thi = 0, dhi = 0;
@@ -1192,7 +1348,7 @@ static ipt_status batched_pairs(ipt_handle h, int32_t count, const int32_t *ns, 
     ipt_opts o2 = o;
     o2.flags &= ~IPT_FLAG_CHOOSE_D;
     const ipt_status st = batched_run(h, count, ns, theta_off, delta_off, z_off, tp, dp, o2, z_pool, lambda_pool,
-                                      status_pool, info, 0);
+                                      status_pool, info, 0, ci);
     if (st != IPT_OK && st != IPT_ENOTCONV) return st;
     IPT_HIP(h, launch_pair_rows(s, count, dn, dto, dzo, dld, dk, z_pool, partner, cs, 0));
     IPT_HIP(h, hipStreamSynchronize(s));
@@ -1214,7 +1370,7 @@ ipt_status ipt_solve_batched(ipt_handle h, int32_t count, const int32_t *ns, con
     if (o.flags & IPT_FLAG_CHOOSE_D) {
         DeviceGuard guard(h->device);
         return batched_pairs(h, count, ns, theta_off, delta_off, z_off, theta_pool, delta_pool, o, z_pool,
-                             lambda_pool, status_pool, info);
+                             lambda_pool, status_pool, info, nullptr);
     }
     return batched_run(h, count, ns, theta_off, delta_off, z_off, theta_pool, delta_pool, o, z_pool, lambda_pool,
                        status_pool, info, 0);

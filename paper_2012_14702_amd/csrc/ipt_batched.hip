@@ -234,7 +234,6 @@ struct BT {
     static constexpr int LDB = T + 16;
     static constexpr int SMEM = 2 * T * LDA * (int)sizeof(E) + 2 * BK * LDB * (int)sizeof(E);
     static_assert(PA >= 1 && PB >= 1, "tile too small for the loader");
-    static_assert(SMEM >= 2 * T * (NPART + 1) * 8, "epilogue reduction must fit in the operand LDS");
 };
 
 template <int T>
@@ -251,7 +250,6 @@ __device__ __forceinline__ void btile(char *smem, int32_t *scol, const BArgs &a,
     constexpr int MI = T / 32;  // 16 x 16 MFMA blocks per wave and dimension (waves are 2 x 2)
     typedef E ATile[T][LDA];
     typedef E BTile[BK][LDB];
-    double(*red)[T][NPART + 1] = (double(*)[T][NPART + 1])smem;  // epilogue reuse of the operand LDS
     ATile *As = (ATile *)smem;
     BTile *Bs = (BTile *)(smem + 2 * sizeof(ATile));
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
@@ -306,6 +304,11 @@ __device__ __forceinline__ void btile(char *smem, int32_t *scol, const BArgs &a,
         }                                                                                               \
         _Pragma("unroll") for (int q = 0; q < NB; ++q) Bs[S][b_r + RB * q][b_c] = rb[q];                \
     } while (0)
+    // 16 x 16 blocks of this wave past the problem's rows or the tile's packed columns
+    // are skipped (wave-uniform bounds: scalar branches around their MFMAs)
+    const int wmu = __builtin_amdgcn_readfirstlane(wm), wnu = __builtin_amdgcn_readfirstlane(wn);
+    const int rows_live = n - r0 - wmu * (T / 2);
+    const int cols_live = (kact - p0 < T ? kact - p0 : T) - wnu * (T / 2);
     typedef typename std::conditional<F64, d4_t, f4_t>::type ACC;
     ACC acc[MI][MI];
 #pragma unroll
@@ -330,6 +333,7 @@ __device__ __forceinline__ void btile(char *smem, int32_t *scol, const BArgs &a,
             for (int x = 0; x < MI; ++x)
 #pragma unroll
                 for (int y = 0; y < MI; ++y) {
+                    if (16 * x >= rows_live || 16 * y >= cols_live) continue;
                     if constexpr (F64)
                         acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[x], fb[y], acc[x][y], 0, 0, 0);
                     else
@@ -341,92 +345,365 @@ __device__ __forceinline__ void btile(char *smem, int32_t *scol, const BArgs &a,
     }
 #undef IPT_BLOAD
 #undef IPT_BSTORE
-    // epilogue (column c continues e_c), in groups of YB column blocks so that only
-    // their partial sums are live at once
+    // Epilogue (column c continues e_c).  The accumulators go through LDS (in two
+    // halves of T/2 rows when the whole tile does not fit: the waves of row half h write
+    // theirs), and each thread then owns one packed column and every (256/T)-th row, so
+    // that a wave's loads and stores run along rows (coalesced for contiguous packed
+    // columns) and a thread issues the loads of up to 8 rows before their arithmetic.
+    // Addresses are always valid (rows < np lie in the padded buffers, empty slots read
+    // column 0, theta is clamped to row n - 1); the arithmetic skips what is not there.
+    typedef typename std::conditional<F64, double, float>::type Acc;
+    constexpr int YP = T + 1;                                  // LDS pitch of the staged rows
+    constexpr int NH = (T * YP * (int)sizeof(Acc) <= C::SMEM) ? 1 : 2;  // staging passes
+    constexpr int RH = T / NH;                                 // rows staged per pass
+    constexpr int G = 256 / T;                                 // threads per column
+    constexpr int RPT = RH / G;                                // rows per thread and pass
+    constexpr int LB = RPT < 4 ? RPT : 4;                      // rows per load batch
+    static_assert(RH * YP * (int)sizeof(Acc) <= C::SMEM, "staged rows must fit in the operand LDS");
+    static_assert(G * T * (NPART + 1) * 8 <= C::SMEM, "epilogue reduction must fit in the operand LDS");
+    static_assert(RPT % LB == 0, "row batches");
+    Acc(*ys)[YP] = (Acc(*)[YP])smem;
     const double *tb = a.theta + m.offt;
     float *zlo_out = F64 ? nullptr : (in_buf ? a.zlo0 : a.zlo1) + m.offz;
     // Delta_cj of the next d: for an exactly symmetric Delta_b it is the coalesced Delta_jc
     const bool sym = a.col.asym[b] == 0;
-    constexpr int YB = MI > 2 ? 2 : MI;
+    const bool need_jc = !F64 || sym;
+    const int cc = tid % T, rg = tid / T;
+    const int c_raw = p0 + cc < kact ? al[p0 + cc] : -1;
+    const bool act = c_raw >= 0 && a.col.state[m.offc + c_raw] == COL_ACTIVE;
+    const int c = act ? c_raw : 0;
+    const double ti = act ? tb[c] : 0.0, dd = act ? a.col.d[m.offc + c] : 0.0;
+    double sums[NPART + 1];
 #pragma unroll
-    for (int y0 = 0; y0 < MI; y0 += YB) {
-        int cols[YB];
-        bool act[YB];
-        double ti[YB], dd[YB];
-        double sums[YB][NPART + 1];
+    for (int q2 = 0; q2 < NPART + 1; ++q2) sums[q2] = 0.0;
 #pragma unroll
-        for (int u = 0; u < YB; ++u) {
-            const int pi = p0 + wn * (T / 2) + 16 * (y0 + u) + (lane & 15);
-            const int c = pi < kact ? al[pi] : -1;
-            cols[u] = c;
-            act[u] = c >= 0 && a.col.state[m.offc + c] == COL_ACTIVE;
-            ti[u] = act[u] ? tb[c] : 0.0;
-            dd[u] = act[u] ? a.col.d[m.offc + c] : 0.0;
+    for (int h = 0; h < NH; ++h) {
+        if (NH == 1 || wm == h) {
 #pragma unroll
-            for (int q = 0; q < NPART + 1; ++q) sums[u][q] = 0.0;
-        }
+            for (int x = 0; x < MI; ++x)
 #pragma unroll
-        for (int x = 0; x < MI; ++x)
+                for (int y = 0; y < MI; ++y)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                // f64 MFMA: row 4r + l/16; f32 MFMA: row 4(l/16) + r
-                const int lr = F64 ? (16 * x + 4 * r + (lane >> 4)) : (16 * x + 4 * (lane >> 4) + r);
-                const int j = r0 + wm * (T / 2) + lr;
-                if (j >= n) continue;
-                const double tj = tb[j];
-#pragma unroll
-                for (int u = 0; u < YB; ++u) {
-                    if (!act[u]) continue;
-                    const int c = cols[u];
-                    const int64_t e = (int64_t)j * np + c;
-                    const double z = zin[e];
-                    const double adj = (!F64 || sym) ? Ad[e] : 0.0;
-                    double wvv, st, gs, de;
-                    if (j == c) {
-                        wvv = 1.0;
-                        st = wvv - z;
-                        gs = 0.0;
-                        de = 0.0;
-                    } else {
-                        const double acv = (double)acc[x][y0 + u][r];
-                        const double yv = F64 ? acv : adj + acv;  // split form: Delta E exact
-                        const double gap = tj - ti[u];
-                        wvv = (z * dd[u] - yv) / gap;
-                        st = wvv - z;
-                        gs = gap * st;
-                        de = wvv;
+                    for (int r = 0; r < 4; ++r) {
+                        // f64 MFMA: row 4r + l/16; f32 MFMA: row 4(l/16) + r (within the wave's 16-row block)
+                        const int lr = F64 ? (16 * x + 4 * r + (lane >> 4)) : (16 * x + 4 * (lane >> 4) + r);
+                        const int row = (NH == 1 ? wm * (T / 2) : 0) + lr;
+                        ys[row][wn * (T / 2) + 16 * y + (lane & 15)] = acc[x][y][r];
                     }
-                    zout[e] = wvv;
-                    if constexpr (!F64) zlo_out[e] = (float)(j == c ? 0.0 : wvv);
-                    sums[u][0] += st * st;
-                    sums[u][1] += z * z;
-                    sums[u][2] += gs * gs;
-                    sums[u][3] += de * de;
-                    sums[u][4] += (sym ? adj : Ad[(int64_t)c * np + j]) * wvv;  // next sweep's d_c
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q0 = 0; q0 < RPT; q0 += LB) {
+            double zv[LB], av[LB], tj[LB];
+            Acc yv[LB];
+#pragma unroll
+            for (int q1 = 0; q1 < LB; ++q1) {
+                const int row = rg + G * (q0 + q1);
+                const int j = r0 + h * RH + row;  // < np
+                const int64_t e = (int64_t)j * np + c;
+                tj[q1] = tb[j < n ? j : n - 1];
+                zv[q1] = zin[e];
+                av[q1] = need_jc ? Ad[e] : 0.0;
+                yv[q1] = ys[row][cc];
+            }
+#pragma unroll
+            for (int q1 = 0; q1 < LB; ++q1) {
+                const int j = r0 + h * RH + rg + G * (q0 + q1);
+                if (!act || j >= n) continue;
+                const int64_t e = (int64_t)j * np + c;
+                const double z = zv[q1];
+                double wvv, st, gs, de;
+                if (j == c) {
+                    wvv = 1.0;
+                    st = wvv - z;
+                    gs = 0.0;
+                    de = 0.0;
+                } else {
+                    const double acv = (double)yv[q1];
+                    const double yy = F64 ? acv : av[q1] + acv;  // split form: Delta E exact
+                    const double gap = tj[q1] - ti;
+                    wvv = (z * dd - yy) / gap;
+                    st = wvv - z;
+                    gs = gap * st;
+                    de = wvv;
                 }
+                zout[e] = wvv;
+                if constexpr (!F64) zlo_out[e] = (float)(j == c ? 0.0 : wvv);
+                sums[0] += st * st;
+                sums[1] += z * z;
+                sums[2] += gs * gs;
+                sums[3] += de * de;
+                sums[4] += (sym ? av[q1] : Ad[(int64_t)c * np + j]) * wvv;  // next sweep's d_c
             }
+        }
+        __syncthreads();
+    }
+    // per-column sums over the G row groups, in a fixed order
+    double(*red)[T][NPART + 1] = (double(*)[T][NPART + 1])smem;
 #pragma unroll
-        for (int u = 0; u < YB; ++u)
+    for (int q2 = 0; q2 < NPART + 1; ++q2) red[rg][cc][q2] = sums[q2];
+    __syncthreads();
+    if (tid < T && c_raw >= 0) {
+        double v[NPART + 1];
 #pragma unroll
-            for (int q = 0; q < NPART + 1; ++q) {
-                double v = sums[u][q];
-                v += __shfl_xor(v, 16);
-                v += __shfl_xor(v, 32);
-                if (lane < 16) red[wm][wn * (T / 2) + 16 * (y0 + u) + lane][q] = v;
-            }
+        for (int q2 = 0; q2 < NPART + 1; ++q2) {
+            v[q2] = red[0][tid][q2];
+#pragma unroll
+            for (int g = 1; g < G; ++g) v[q2] += red[g][tid][q2];
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < NPART; ++q2) a.part[m.offp + ((int64_t)tm * n + c_raw) * NPART + q2] = v[q2];
+        a.dpart[m.offq + (int64_t)tm * n + c_raw] = v[NPART];
     }
     __syncthreads();
-    if (tid < T) {
-        const int pi = p0 + tid;
-        const int c = pi < kact ? al[pi] : -1;
-        if (c >= 0) {
+}
+
+// Narrow tiles (at most 16 packed columns: late sweeps, when few columns of a problem
+// are left) stream the tile's Delta rows: each wave takes 16 rows and the whole K
+// range, its Delta operand loaded straight into registers (32 contiguous bytes per
+// lane, one K chunk ahead) and the <= 16 iterate columns staged through LDS in K chunks.
+// Within a chunk the MFMA's K order is permuted -- lane group g holds k = 4g .. 4g + 3
+// of each 16-wide sub-block and the MFMA of step e takes their e-th element -- and the
+// B operand follows the same order.  Rows pass 64 at a time (T = 128: two passes;
+// T = 32: two waves).  Needs np % 64 == 0.
+constexpr int SK_KC = 64;  // K chunk of the narrow path
+template <bool F64>
+struct SkCfg {
+    typedef typename std::conditional<F64, double, float>::type E;
+    typedef typename std::conditional<F64, d4_t, f4_t>::type V4;
+    static constexpr int SMEM = 2 * SK_KC * 16 * (int)sizeof(E) + 4 * 16 * (NPART + 1) * 8;
+};
+
+// Four consecutive Delta entries of a narrow-tile row at element offset k0 (32 or 16 bytes).
+template <bool F64>
+__device__ __forceinline__ typename SkCfg<F64>::V4 sk_load_a(const typename SkCfg<F64>::E *arow, int k0) {
+    typedef typename SkCfg<F64>::V4 V4;
+    if constexpr (F64) {
+        const double2 *pp = (const double2 *)(arow + k0);
+        const double2 lo = pp[0], hi = pp[1];
+        return V4{lo.x, lo.y, hi.x, hi.y};
+    } else {
+        const float4 f = *(const float4 *)(arow + k0);
+        return V4{f.x, f.y, f.z, f.w};
+    }
+}
+
+template <bool F64>
+__device__ __forceinline__ void btile_skinny(char *smem, int32_t *scol, const BArgs &a, const BatchMeta &m, int b,
+                                             int tm, int tn, int32_t t, int32_t acx) {
+    typedef SkCfg<F64> C;
+    typedef typename C::E E;
+    typedef typename C::V4 V4;
+    const int T = m.T;
+    E(*Bs)[SK_KC][16] = (E(*)[SK_KC][16])smem;
+    double(*red)[16][NPART + 1] = (double(*)[16][NPART + 1])(smem + 2 * SK_KC * 16 * sizeof(E));
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, lc = lane & 15;
+    const int n = m.n, np = m.np;
+    int32_t q, pc;
+    acx_phase(acx, t, q, pc);
+    const int32_t in_buf = acx ? q : (t - 1) & 1, out_buf = acx ? q + 1 : in_buf ^ 1;
+    const double *Ad = a.dpad + m.offz;
+    const double *zin = a.zs[in_buf] + m.offz;
+    double *zout = a.zs[out_buf] + m.offz;
+    const E *Ag = F64 ? (const E *)Ad : (const E *)(a.d32 + m.offz);
+    const E *Bg = F64 ? (const E *)zin : (const E *)((in_buf ? a.zlo1 : a.zlo0) + m.offz);
+    float *zlo_out = F64 ? nullptr : (in_buf ? a.zlo0 : a.zlo1) + m.offz;
+    const int r0 = tm * T, p0 = tn * T;
+    const int32_t *al = a.col.alist + m.offc;
+    const int kact = a.col.kact[b];
+    if (tid < 16) scol[tid] = p0 + tid < kact ? al[p0 + tid] : -1;
+    __syncthreads();
+    const double *tb = a.theta + m.offt;
+    const bool sym = a.col.asym[b] == 0;
+    const bool need_jc = !F64 || sym;
+    // this lane's epilogue column
+    const int c_raw = scol[lc];
+    const bool act = c_raw >= 0 && a.col.state[m.offc + c_raw] == COL_ACTIVE;
+    const int c = act ? c_raw : 0;
+    const double ti = act ? tb[c] : 0.0, dd = act ? a.col.d[m.offc + c] : 0.0;
+    // B staging: thread -> (k row (tid + 256 i) / 16, column tid % 16), four entries per chunk
+    const int bcol = scol[tid & 15];
+    double sums[NPART + 1];
 #pragma unroll
-            for (int q = 0; q < NPART; ++q)
-                a.part[m.offp + ((int64_t)tm * n + c) * NPART + q] = red[0][tid][q] + red[1][tid][q];
-            a.dpart[m.offq + (int64_t)tm * n + c] = red[0][tid][NPART] + red[1][tid][NPART];
+    for (int q2 = 0; q2 < NPART + 1; ++q2) sums[q2] = 0.0;
+    const int nch = np / SK_KC;
+    const int PASSES = T >= 64 ? T / 64 : 1;
+    const bool wave_rows = wv * 16 < T;  // T = 32: waves 2 and 3 hold no rows
+    for (int pass = 0; pass < PASSES; ++pass) {
+        const int rw = r0 + pass * 64 + wv * 16;  // first row of this wave
+        const E *arow = Ag + (int64_t)(wave_rows ? rw + lc : r0) * np + 4 * g;
+        V4 acc = V4{0, 0, 0, 0};
+        V4 av[4];
+        E bv[4];
+        auto load_b = [&](int ch) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kr = (tid + 256 * i) >> 4;
+                bv[i] = bcol >= 0 ? Bg[(int64_t)(ch * SK_KC + kr) * np + bcol] : (E)0;
+            }
+        };
+        // sub-block s2 of a chunk in av[s2], refilled with the next chunk's sub-block right
+        // after the MFMAs that read it
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) av[s2] = sk_load_a<F64>(arow, 16 * s2);
+        load_b(0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Bs[0][(tid + 256 * i) >> 4][(tid + 256 * i) & 15] = bv[i];
+        __syncthreads();
+        for (int ch = 0; ch < nch; ++ch) {
+            const int cur = ch & 1, nxt = ch + 1 < nch ? ch + 1 : ch;
+            load_b(nxt);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) {
+                if (wave_rows) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const E fb = Bs[cur][16 * s2 + 4 * g + e][lc];
+                        if constexpr (F64)
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2][e], fb, acc, 0, 0, 0);
+                        else
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s2][e], fb, acc, 0, 0, 0);
+                    }
+                }
+                av[s2] = sk_load_a<F64>(arow, nxt * SK_KC + 16 * s2);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Bs[cur ^ 1][(tid + 256 * i) >> 4][(tid + 256 * i) & 15] = bv[i];
+            __syncthreads();
+        }
+        if (!wave_rows) continue;
+        // epilogue of the wave's 16 rows x 16 columns: lane holds 4 rows of column lc
+        double zv[4], ajc[4], tj[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int lr = F64 ? (4 * r + g) : (4 * g + r);
+            const int j = rw + lr;  // < np
+            const int64_t e = (int64_t)j * np + c;
+            tj[r] = tb[j < n ? j : n - 1];
+            zv[r] = zin[e];
+            ajc[r] = need_jc ? Ad[e] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int lr = F64 ? (4 * r + g) : (4 * g + r);
+            const int j = rw + lr;
+            if (!act || j >= n) continue;
+            const int64_t e = (int64_t)j * np + c;
+            const double z = zv[r];
+            double wvv, st, gs, de;
+            if (j == c) {
+                wvv = 1.0;
+                st = wvv - z;
+                gs = 0.0;
+                de = 0.0;
+            } else {
+                const double acv = (double)acc[r];
+                const double yy = F64 ? acv : ajc[r] + acv;  // split form: Delta E exact
+                const double gap = tj[r] - ti;
+                wvv = (z * dd - yy) / gap;
+                st = wvv - z;
+                gs = gap * st;
+                de = wvv;
+            }
+            zout[e] = wvv;
+            if constexpr (!F64) zlo_out[e] = (float)(j == c ? 0.0 : wvv);
+            sums[0] += st * st;
+            sums[1] += z * z;
+            sums[2] += gs * gs;
+            sums[3] += de * de;
+            sums[4] += (sym ? ajc[r] : Ad[(int64_t)c * np + j]) * wvv;  // next sweep's d_c
+        }
+    }
+    // per-column sums: the 4 lane groups, then the waves in order
+#pragma unroll
+    for (int q2 = 0; q2 < NPART + 1; ++q2) {
+        double v = sums[q2];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (g == 0) red[wv][lc][q2] = v;
+    }
+    __syncthreads();
+    if (tid < 16) {
+        const int cc = scol[tid];
+        if (cc >= 0) {
+            double v[NPART + 1];
+#pragma unroll
+            for (int q2 = 0; q2 < NPART + 1; ++q2) v[q2] = ((red[0][tid][q2] + red[1][tid][q2]) + red[2][tid][q2]) + red[3][tid][q2];
+#pragma unroll
+            for (int q2 = 0; q2 < NPART; ++q2) a.part[m.offp + ((int64_t)tm * n + cc) * NPART + q2] = v[q2];
+            a.dpart[m.offq + (int64_t)tm * n + cc] = v[NPART];
         }
     }
     __syncthreads();
+}
+
+// Next work item of a persistent GEMM block (thread 0): its own die's segment first,
+// then the others in turn; a drained segment is left for good.  -1 when none is left.
+__device__ inline int32_t next_item(const int32_t *counts, int32_t *tickets, int32_t segcap, int &x, int &left) {
+    while (left > 0) {
+        const int32_t cnt = counts[x];
+        // a segment seen drained (tickets only grow) is skipped without an atomic
+        if (__hip_atomic_load(&tickets[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < cnt) {
+            const int32_t tk = atomicAdd(&tickets[x], 1);
+            if (tk < cnt) return x * segcap + tk;
+        }
+        x = (x + 1) % NXCD;
+        --left;
+    }
+    return -1;
+}
+
+// Items of a class in the running sweep (all segments): a block of an empty launch
+// leaves at once.
+__device__ inline bool class_empty(const int32_t *counts) {
+    __shared__ int32_t s_total;
+    if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        for (int x = 0; x < NXCD; ++x) tot += counts[x];
+        s_total = tot;
+    }
+    __syncthreads();
+    return s_total == 0;
+}
+
+// Persistent GEMM over the narrow-tile list (items of any tile size).
+__global__ __launch_bounds__(256, 4) void k_bnarrow(const Ctrl *ctrl, BArgs a, BatchLists lists, int32_t acx) {
+    if (ctrl->error || ctrl->done) return;
+    const int32_t t = cur_sweep(ctrl);
+    const int4 *items = lists.l[CLS_NARROW][t & 1];
+    const int32_t *counts = lists.counts + (2 * CLS_NARROW + (t & 1)) * NXCD;
+    int32_t *tickets = lists.tickets + CLS_NARROW * NXCD;
+    constexpr int SM = SkCfg<true>::SMEM > SkCfg<false>::SMEM ? SkCfg<true>::SMEM : SkCfg<false>::SMEM;
+    __shared__ __attribute__((aligned(16))) char smem[SM];
+    __shared__ int32_t scol[16];
+    __shared__ int32_t cur_item;
+    if (class_empty(counts)) return;
+    int x = blockIdx.x % NXCD, left = NXCD;
+    const int32_t segcap = lists.segcap[CLS_NARROW];
+    if (threadIdx.x == 0) cur_item = next_item(counts, tickets, segcap, x, left);
+    __syncthreads();
+    for (;;) {
+        const int32_t it = __builtin_amdgcn_readfirstlane(cur_item);  // uniform: the item lives in scalar registers
+        if (it < 0) break;
+        // the ticket of the following item is taken now; its latency hides behind this item
+        int32_t tk = 0;
+        if (threadIdx.x == 0) tk = atomicAdd(&tickets[x], 1);
+        const int4 w = items[it];
+        const BatchMeta m = a.meta[w.x];
+        if (a.tflag[m.offf + w.z] == (uint32_t)PREC_F64) btile_skinny<true>(smem, scol, a, m, w.x, w.y, w.z, t, acx);
+        else btile_skinny<false>(smem, scol, a, m, w.x, w.y, w.z, t, acx);
+        // (the tile ends with a barrier: every thread has read cur_item)
+        if (threadIdx.x == 0) {
+            if (tk < counts[x]) {
+                cur_item = x * segcap + tk;
+            } else {  // this segment is drained: the other dies' segments in turn
+                x = (x + 1) % NXCD;
+                --left;
+                cur_item = next_item(counts, tickets, segcap, x, left);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 template <int T>
@@ -436,20 +713,37 @@ __global__ __launch_bounds__(256, (T == 128 ? 2 : (T == 64 ? 4 : 5))) void k_bge
     constexpr int C = tile_class<T>();
     const int32_t t = cur_sweep(ctrl);
     const int4 *items = lists.l[C][t & 1];
-    const int32_t nitems = lists.counts[2 * C + (t & 1)];
+    const int32_t *counts = lists.counts + (2 * C + (t & 1)) * NXCD;
+    int32_t *tickets = lists.tickets + C * NXCD;
     __shared__ __attribute__((aligned(16))) char smem[bsmem<T>()];
     __shared__ int32_t scol[T];
     __shared__ int32_t cur_item;
+    if (class_empty(counts)) return;
+    int x = blockIdx.x % NXCD, left = NXCD;
+    const int32_t segcap = lists.segcap[C];
+    if (threadIdx.x == 0) cur_item = next_item(counts, tickets, segcap, x, left);
+    __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) cur_item = atomicAdd(&lists.tickets[C], 1);
-        __syncthreads();
-        const int32_t it = cur_item;
-        __syncthreads();
-        if (it >= nitems) break;
+        const int32_t it = __builtin_amdgcn_readfirstlane(cur_item);  // uniform: the item lives in scalar registers
+        if (it < 0) break;
+        // the ticket of the following item is taken now; its latency hides behind this item
+        int32_t tk = 0;
+        if (threadIdx.x == 0) tk = atomicAdd(&tickets[x], 1);
         const int4 w = items[it];
         const BatchMeta m = a.meta[w.x];
         if (a.tflag[m.offf + w.z] == (uint32_t)PREC_F64) btile<T, true>(smem, scol, a, m, w.x, w.y, w.z, t, acx);
         else btile<T, false>(smem, scol, a, m, w.x, w.y, w.z, t, acx);
+        // (the tile ends with a barrier: every thread has read cur_item)
+        if (threadIdx.x == 0) {
+            if (tk < counts[x]) {
+                cur_item = x * segcap + tk;
+            } else {  // this segment is drained: the other dies' segments in turn
+                x = (x + 1) % NXCD;
+                --left;
+                cur_item = next_item(counts, tickets, segcap, x, left);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -607,7 +901,7 @@ __global__ __launch_bounds__(256) void k_bplan(const Ctrl *ctrl, BArgs a, BatchL
     const BatchMeta m = a.meta[b];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __shared__ int s_w[4];
-    __shared__ int s_base, s_items;
+    __shared__ int s_base, s_items, s_items2;
     __shared__ uint32_t s_tprec[128];  // n <= 4096, T >= 32
     for (int i = threadIdx.x; i < 128; i += 256) s_tprec[i] = 0;
     if (threadIdx.x == 0) s_base = 0;
@@ -634,13 +928,22 @@ __global__ __launch_bounds__(256) void k_bplan(const Ctrl *ctrl, BArgs a, BatchL
     for (int pos = threadIdx.x; pos < kact; pos += 256) a.col.cprec[m.offc + al[pos]] = (int32_t)s_tprec[pos / m.T];
     for (int tn = threadIdx.x; tn < tiles; tn += 256) a.tflag[m.offf + tn] = s_tprec[tn];
     const int cl = tile_class_of(m.T), nx = (t + 1) & 1;
+    // a last column tile of at most 16 columns goes to the narrow list (only the last
+    // one can be: every tile before it is full)
+    const bool narrow = tiles > 0 && kact - (tiles - 1) * m.T <= 16 && m.np % SK_KC == 0;
+    const int wide = narrow ? tiles - 1 : tiles;
     if (threadIdx.x == 0) {
         a.col.kact[b] = kact;
-        s_items = tiles ? atomicAdd(&lists.counts[2 * cl + nx], tiles * nt) : 0;
+        s_items = wide ? atomicAdd(&lists.counts[(2 * cl + nx) * NXCD + m.xcd], wide * nt) : 0;
+        s_items2 = narrow ? atomicAdd(&lists.counts[(2 * CLS_NARROW + nx) * NXCD + m.xcd], nt) : 0;
     }
     __syncthreads();
-    int4 *lst = lists.l[cl][nx];
-    for (int e = threadIdx.x; e < tiles * nt; e += 256) lst[s_items + e] = make_int4(b, e % nt, e / nt, 0);
+    int4 *lst = lists.l[cl][nx] + (int64_t)m.xcd * lists.segcap[cl];
+    for (int e = threadIdx.x; e < wide * nt; e += 256) lst[s_items + e] = make_int4(b, e % nt, e / nt, 0);
+    if (narrow) {
+        int4 *ln = lists.l[CLS_NARROW][nx] + (int64_t)m.xcd * lists.segcap[CLS_NARROW];
+        for (int e = threadIdx.x; e < nt; e += 256) ln[s_items2 + e] = make_int4(b, e, tiles - 1, 0);
+    }
 }
 
 // Sweep bookkeeping of the batch: reduce the finalize blocks' partials in block
@@ -690,10 +993,11 @@ __global__ __launch_bounds__(256) void k_bcontrol(Ctrl *ctrl, DevOpts o, BArgs a
     ctrl->active = (int32_t)r[0][BP_STILL];
     ctrl->sweeps = t;
     if (ctrl->active == 0 || t >= o.max_iter) ctrl->done = 1;
-    for (int cl = 0; cl < 3; ++cl) {
-        lists.counts[2 * cl + (t & 1)] = 0;
-        lists.tickets[cl] = 0;
-    }
+    for (int cl = 0; cl < NCLS; ++cl)
+        for (int x = 0; x < NXCD; ++x) {
+            lists.counts[(2 * cl + (t & 1)) * NXCD + x] = 0;
+            lists.tickets[cl * NXCD + x] = 0;
+        }
 }
 
 // Outputs: the final iterate of each column into z_pool (row-major, leading dimension
@@ -701,7 +1005,8 @@ __global__ __launch_bounds__(256) void k_bcontrol(Ctrl *ctrl, DevOpts o, BArgs a
 // (problem, row tile, 64 columns), as for the first sweep.
 __global__ __launch_bounds__(256) void k_bcopyout(const Ctrl *ctrl, BArgs a, const int4 *items, int64_t nitems,
                                                   double *z_pool, double *lambda_pool, int32_t *status_pool,
-                                                  double *max_resid_out) {
+                                                  double *max_resid_out, int32_t *ci_sweeps, double *ci_step,
+                                                  double *ci_resid) {
     if (ctrl->error) return;
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -729,6 +1034,9 @@ __global__ __launch_bounds__(256) void k_bcopyout(const Ctrl *ctrl, BArgs a, con
                 const double r = a.col.resid[gc] / (nrm > 0.0 ? nrm : 1.0);
                 a.col.resid[gc] = r;
                 if (st == COL_CONVERGED) rb = dbits(r);
+                if (ci_sweeps) ci_sweeps[m.offt + c] = a.col.sweeps[gc];
+                if (ci_step) ci_step[m.offt + c] = a.col.step[gc];
+                if (ci_resid) ci_resid[m.offt + c] = r;
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
@@ -756,18 +1064,28 @@ __device__ inline bool acx_cycle_end(const Ctrl *ctrl, int32_t &t, int32_t &pc) 
     return q == pc - 1;
 }
 
+// Item it of the next sweep's work, counted over the classes and die segments in turn.
 __device__ inline bool acx_item(const BatchLists &lists, int32_t t, int64_t it, int4 &w) {
     const int nx = (t + 1) & 1;
     int64_t base = 0;
-    for (int cl = 0; cl < 3; ++cl) {
-        const int64_t cnt = lists.counts[2 * cl + nx];
-        if (it < base + cnt) {
-            w = lists.l[cl][nx][it - base];
-            return true;
+    for (int cl = 0; cl < NCLS; ++cl)
+        for (int x = 0; x < NXCD; ++x) {
+            const int64_t cnt = lists.counts[(2 * cl + nx) * NXCD + x];
+            if (it < base + cnt) {
+                w = lists.l[cl][nx][(int64_t)x * lists.segcap[cl] + (it - base)];
+                return true;
+            }
+            base += cnt;
         }
-        base += cnt;
-    }
     return false;
+}
+
+__device__ inline int64_t acx_total(const BatchLists &lists, int32_t t) {
+    const int nx = (t + 1) & 1;
+    int64_t total = 0;
+    for (int cl = 0; cl < NCLS; ++cl)
+        for (int x = 0; x < NXCD; ++x) total += lists.counts[(2 * cl + nx) * NXCD + x];
+    return total;
 }
 
 __device__ inline void acx_diffs(int32_t p, double z, double a1, double a2, double a3, double &d1, double &d2,
@@ -781,8 +1099,7 @@ __global__ __launch_bounds__(256) void k_bacx_dots(const Ctrl *ctrl, BArgs a, Ba
     int32_t t, pc;
     if (!acx_cycle_end(ctrl, t, pc)) return;
     __shared__ double sh[2][256];
-    const int64_t total = (int64_t)lists.counts[(t + 1) & 1] + lists.counts[2 + ((t + 1) & 1)] +
-                          lists.counts[4 + ((t + 1) & 1)];
+    const int64_t total = acx_total(lists, t);
     for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
         int4 w;
         acx_item(lists, t, it, w);
@@ -823,8 +1140,7 @@ __global__ __launch_bounds__(256) void k_bacx_dots(const Ctrl *ctrl, BArgs a, Ba
 __global__ __launch_bounds__(256) void k_bacx_update(const Ctrl *ctrl, BArgs a, BatchLists lists, int64_t total_cols) {
     int32_t t, pc;
     if (!acx_cycle_end(ctrl, t, pc)) return;
-    const int64_t total = (int64_t)lists.counts[(t + 1) & 1] + lists.counts[2 + ((t + 1) & 1)] +
-                          lists.counts[4 + ((t + 1) & 1)];
+    const int64_t total = acx_total(lists, t);
     for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
         int4 w;
         acx_item(lists, t, it, w);
@@ -890,6 +1206,20 @@ hipError_t launch_bsweep1(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L,
     return hipGetLastError();
 }
 
+int bnarrow_grid() {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 512;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bnarrow, 256, 0) != hipSuccess || per <= 0) per = 1;
+    return cus * per;
+}
+
+hipError_t launch_bnarrow(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int grid,
+                         int32_t acx) {
+    k_bnarrow<<<grid, 256, 0, s>>>(ctrl, L, lists, acx);
+    return hipGetLastError();
+}
+
 hipError_t launch_bgemm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int tile,
                         int grid, int32_t acx) {
     if (tile == 32) k_bgemm<32><<<grid, 256, 0, s>>>(ctrl, L, lists, acx);
@@ -924,9 +1254,11 @@ hipError_t launch_bcontrol(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const Ba
 }
 
 hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
-                           double *z_pool, double *lambda_pool, int32_t *status_pool, double *max_resid_out) {
+                           double *z_pool, double *lambda_pool, int32_t *status_pool, double *max_resid_out,
+                           int32_t *ci_sweeps, double *ci_step, double *ci_resid) {
     const int g = nitems < 8192 ? (int)nitems : 8192;
-    k_bcopyout<<<g > 0 ? g : 1, 256, 0, s>>>(ctrl, L, items, nitems, z_pool, lambda_pool, status_pool, max_resid_out);
+    k_bcopyout<<<g > 0 ? g : 1, 256, 0, s>>>(ctrl, L, items, nitems, z_pool, lambda_pool, status_pool, max_resid_out,
+                                            ci_sweeps, ci_step, ci_resid);
     return hipGetLastError();
 }
 

@@ -106,12 +106,17 @@ enum : int32_t { LT_BF16 = 0, LT_F16 = 1, LT_F32 = 2 };
 // Setup and bookkeeping (ipt_setup.hip)
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp);
-// The column part of launch_init (after a separate launch_ctrl_init).
+// The column part of launch_init (after a separate launch_ctrl_init): bitmap_zeroed
+// when that launch cleared the bitmap; with theta it also checks theta's order (then
+// launch_check_theta(..., order_done = true)).  With cs.alist it writes the packed
+// list of the first sweep (all k columns in order; ctrl->kact = k from the reset).
 hipError_t launch_init_cols(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
-                            int64_t kp, uint32_t *bitmap, int32_t ntiles_n, int32_t start_stamp);
-// sym0 = 1 when the symmetry scan runs next (it clears sym on the first asymmetric pair).
+                            int64_t kp, uint32_t *bitmap, int32_t ntiles_n, int32_t start_stamp,
+                            bool bitmap_zeroed = false, const double *theta = nullptr);
+// sym0 = 1 when the symmetry scan runs next (it clears sym on the first asymmetric pair);
+// bitmap (n bits) is cleared for launch_init_cols when given.
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0 = 0,
-                            double cont_alpha = 0.0);
+                            double cont_alpha = 0.0, uint32_t *bitmap = nullptr, int64_t n_bits = 0);
 // Continuation sweep (scale s = Ctrl::escale < 1): the sweep computed W = F(Z) of the
 // unscaled partition; the continuation map is E + s (F(Z) - E), so the off-diagonal
 // entries of this sweep's active columns are multiplied by s in place.  Nothing is
@@ -131,7 +136,7 @@ hipError_t launch_plan_dense(hipStream_t s, Ctrl *ctrl, ColState cs, int64_t kp)
 // Dense: the plan of the next sweep followed by the control step, in one launch.
 hipError_t launch_control_plan(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, ColState cs, int64_t kp);
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
-                              int64_t k);
+                              int64_t k, bool order_done = false);
 // colpart holds prep_delta_chunks(np) x n doubles; bmax (prep_delta_blocks(np) words of
 // per-block maxima of |Delta|), when given, also sets ctrl->dscale.
 hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, const double *delta, int64_t lda,
@@ -174,6 +179,11 @@ hipError_t launch_cast_z(hipStream_t s, const Ctrl *ctrl, const double *zin, int
                          int64_t ldt, int64_t np, int64_t kp, int32_t low_type, int32_t mid_x3 = 0);
 
 hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count);  // zero fill
+// debug-mode workspace guard bands (nb bands of `words` 64-bit words at base + list[b])
+hipError_t launch_guard_fill(hipStream_t s, char *base, const uint64_t *list, int64_t nb, int64_t words,
+                             int32_t *damage);
+hipError_t launch_guard_check(hipStream_t s, const char *base, const uint64_t *list, int64_t nb, int64_t words,
+                              int32_t *damage);
 
 // Sparse sweeps (ipt_spmm.hip)
 int64_t spmm_row_tiles(int64_t n);
@@ -199,7 +209,7 @@ hipError_t launch_zlo_init(hipStream_t s, const double *zb, float *zlo, int64_t 
 // its columns, its partial sums (offp, NPART per row tile and column), its
 // per-row-tile d and norm partials (offq) and its column-tile flags (offf).
 struct BatchMeta {
-    int32_t n, T, np, pad_;
+    int32_t n, T, np, xcd;  // xcd: the accelerator die whose work list holds the problem's tiles
     int64_t offd, offt, offo, offz, offc, offp, offq, offf;
 };
 struct BatchCols {  // per column of all problems, concatenated
@@ -230,11 +240,24 @@ struct BatchLaunch {
 };
 // Work lists of (problem, row tile, column tile, 0) items per tile class (T = 32, 64,
 // 128) and sweep parity, filled by the finalize of the previous sweep.
+// Work lists of the batched GEMM, per tile class and sweep parity.  Each list is cut
+// into NXCD segments, one per accelerator die (XCD, with its own L2): the problems
+// are dealt to the dies, a block of the persistent GEMM works through the segment
+// of the die it runs on (workgroups are dispatched round-robin over the dies) and
+// then helps with the others, so the tiles of one problem, which share its Delta
+// and Z panels, are mostly computed under one L2.
+// Classes 0..2 hold the tiles of size 32, 64 and 128; class CLS_NARROW holds the
+// (last) column tiles of at most 16 columns, whatever their size.
+constexpr int NXCD = 8;
+constexpr int CLS_NARROW = 3, NCLS = 4;
 struct BatchLists {
-    int4 *l[3][2];
-    int32_t *counts;   // [3][2] items in each list
-    int32_t *tickets;  // [3] next item of the running sweep, per class
+    int4 *l[NCLS][2];
+    int32_t segcap[NCLS];  // entries per die segment in the lists of a class (segment x starts at x segcap)
+    int32_t *counts;       // [NCLS][2][NXCD] items in each segment
+    int32_t *tickets;      // [NCLS][NXCD] next item of the running sweep, per class and segment
 };
+constexpr int BLIST_COUNTS = NCLS * 2 * NXCD;                 // words of BatchLists::counts
+constexpr int BLIST_WORDS = BLIST_COUNTS + NCLS * NXCD;        // counts, then tickets
 int bfinalize_blocks(int64_t total_cols);
 hipError_t launch_binit(hipStream_t s, Ctrl *ctrl, const BatchLaunch &L, int32_t count, int32_t start_prec);
 hipError_t launch_bsweep1(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
@@ -243,13 +266,17 @@ hipError_t launch_bacx(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, co
                        int64_t total_cols);
 hipError_t launch_bgemm(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int tile,
                         int grid, int32_t acx);
+int bnarrow_grid();
+hipError_t launch_bnarrow(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int grid,
+                         int32_t acx);
 hipError_t launch_bfinalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
                             const BatchLists &lists);
 hipError_t launch_bcontrol(hipStream_t s, Ctrl *ctrl, const DevOpts &o, const BatchLaunch &L, int64_t total_cols,
                            const BatchLists &lists);
 hipError_t launch_bplan(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const BatchLists &lists, int32_t count);
 hipError_t launch_bcopyout(hipStream_t s, const Ctrl *ctrl, const BatchLaunch &L, const int4 *items, int64_t nitems,
-                           double *z_pool, double *lambda_pool, int32_t *status_pool, double *max_resid_out);
+                           double *z_pool, double *lambda_pool, int32_t *status_pool, double *max_resid_out,
+                           int32_t *ci_sweeps = nullptr, double *ci_step = nullptr, double *ci_resid = nullptr);
 int bgemm_grid(int tile);  // persistent grid size (CUs x resident blocks)
 
 // MLP kernels (ipt_mlp.hip).  Every matrix the GEMM reads is BF16, row-major with

@@ -24,14 +24,19 @@ __device__ inline uint64_t dbits(double x) {
 
 __device__ inline double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
 
-__global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k, int32_t sym0, double cont_alpha) {
+// Control block reset (every solve starts with all k columns active, in order: the
+// packed list k_init_cols writes), and optionally the zeroed duplicate-index bitmap.
+__global__ void k_ctrl_init(Ctrl *ctrl, int32_t start_prec, int64_t k, int32_t sym0, double cont_alpha,
+                            uint32_t *bitmap, int64_t bitmap_words) {
     uint32_t *w = (uint32_t *)ctrl;
     constexpr int words = (int)(sizeof(Ctrl) / sizeof(uint32_t));
     for (int q = threadIdx.x; q < words; q += blockDim.x) w[q] = 0u;
+    for (int64_t q = threadIdx.x; q < bitmap_words; q += blockDim.x) bitmap[q] = 0u;
     __syncthreads();
     if (threadIdx.x == 0) {
         ctrl->prec = start_prec;
         ctrl->active = (int32_t)k;
+        ctrl->kact = (int32_t)k;
         ctrl->sym = sym0;
         ctrl->prev_maxstep = INFINITY;
         ctrl->dscale = 1.0;
@@ -47,11 +52,37 @@ __global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t v) {
         p[t] = v;
 }
 
+// Column state of a solve (the requested indices checked: in range, no repeats); with
+// cs.alist the packed list of the first sweep (column c at position c), and with theta
+// the order check of theta (finite; k_theta_order's flags) over the same grid.
+__device__ inline void theta_order_flags(Ctrl *ctrl, const double *theta, int64_t n, int64_t j0, int64_t stride) {
+    int32_t bits = 0;
+    bool bad = false;
+    for (int64_t j = j0; j < n; j += stride) {
+        const double a = theta[j];
+        bad |= !isfinite(a);
+        if (j + 1 < n) {
+            const double b = theta[j + 1];
+            if (!(b > a)) bits |= 1;
+            if (!(b < a)) bits |= 2;
+        }
+    }
+    // one atomic per wave and flag
+    const bool any_bad = __ballot(bad) != 0;
+    const int32_t wbits = (__ballot(bits & 1) ? 1 : 0) | (__ballot(bits & 2) ? 2 : 0);
+    if ((threadIdx.x & 63) == 0) {
+        if (any_bad) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
+        if (wbits) atomicOr(&ctrl->theta_order, wbits);
+    }
+}
+
 __global__ void k_init_cols(Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k, int64_t kp,
-                            uint32_t *bitmap, int32_t ntiles, int32_t start_stamp) {
+                            uint32_t *bitmap, int32_t ntiles, int32_t start_stamp, const double *theta) {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (theta) theta_order_flags(ctrl, theta, n, c, (int64_t)gridDim.x * blockDim.x);
     if (c < ntiles) cs.tile_stamp[c] = start_stamp;
     if (c >= kp) return;
+    if (cs.alist) cs.alist[c] = (int32_t)c;  // positions past k are never read (kact = k)
     int32_t state = COL_PAD, i = 0;
     if (c < k) {
         const int64_t ii = idx_user ? (int64_t)idx_user[c] : c;
@@ -81,19 +112,7 @@ __global__ void k_init_cols(Ctrl *ctrl, ColState cs, const int32_t *idx_user, in
 // theta (k_theta_order: one comparison per adjacent pair) has distinct entries, and
 // the pairwise check then returns at once.
 __global__ void k_theta_order(Ctrl *ctrl, const double *theta, int64_t n) {
-    int32_t bits = 0;
-    bool bad = false;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        const double a = theta[j];
-        bad |= !isfinite(a);
-        if (j + 1 < n) {
-            const double b = theta[j + 1];
-            if (!(b > a)) bits |= 1;
-            if (!(b < a)) bits |= 2;
-        }
-    }
-    if (bad) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
-    if (bits) atomicOr(&ctrl->theta_order, bits);
+    theta_order_flags(ctrl, theta, n, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 __global__ void k_check_theta(Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n, int64_t k) {
@@ -138,7 +157,7 @@ __device__ inline void block_atomic_max(uint64_t *p, uint64_t v);  // one atomic
 // sums of |M| for |M|_1 = max_c sum_j |M_jc|, M = diag(theta) + Delta.  Block: 256 columns x
 // PREP_ROWS rows; thread (cx, ry) holds columns 4cx..4cx+3 (16-byte loads) and walks
 // rows ry, ry + 4, ..., four rows in flight.
-constexpr int PREP_ROWS = 128;
+constexpr int PREP_ROWS = 32;
 
 template <typename TL>
 __global__ __launch_bounds__(256) void k_prep_delta(Ctrl *ctrl, const double *theta, const double *delta,
@@ -942,13 +961,26 @@ __global__ __launch_bounds__(256) void k_copyout(const Ctrl *ctrl, ColState cs, 
 // zt[c][j] = lowp(scale * (Z_jc - [j == i])).  Only Z - E goes through low
 // precision; Delta E is added back exactly in FP64 by the GEMM epilogue.  The
 // element type follows the precision the ladder chose for this sweep (nothing is
-// done for an FP64 sweep).  64 x 64 tiles transposed through LDS.
+// done for an FP64 sweep).  64 x 64 tiles transposed through LDS: 16-byte loads along
+// the rows of Z (a thread keeps two columns, whose idx and state it reads once), and
+// each thread stores 8 consecutive rows of one column of the shadow at once.
 template <typename T>
-__device__ __forceinline__ void cast_z_tile(double (*tile)[65], T *zt, int64_t ldt, int64_t c0, int64_t j0) {
-    const int t = threadIdx.x;
-    for (int q = 0; q < 16; ++q) {
-        const int cc = (t >> 6) + 4 * q, r = t & 63;
-        zt[(c0 + cc) * ldt + j0 + r] = to_low<T>(tile[r][cc]);
+__device__ __forceinline__ void cast_z_store(double (*tile)[65], T *zt, int64_t ldt, int64_t c0, int64_t j0,
+                                             T *zlo) {
+    typedef T t8_t __attribute__((ext_vector_type(8)));
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        const int u = threadIdx.x + 256 * w, cc = u >> 3, r0 = 8 * (u & 7);
+        t8_t h, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const double x = tile[r0 + e][cc];
+            h[e] = to_low<T>(x);
+            if (zlo) l[e] = to_low<T>(x - (double)h[e]);
+        }
+        const int64_t o = (c0 + cc) * ldt + j0 + r0;
+        *(t8_t *)(zt + o) = h;
+        if (zlo) *(t8_t *)(zlo + o) = l;
     }
 }
 
@@ -962,28 +994,31 @@ __global__ __launch_bounds__(256) void k_cast_z(const Ctrl *ctrl, const double *
     const double scale = f16 ? ctrl->zscale : 1.0;
     __shared__ double tile[64][65];
     const int64_t j0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-    const int t = threadIdx.x;
-    for (int q = 0; q < 16; ++q) {
-        const int r = (t >> 6) + 4 * q, cc = t & 63;
-        const int64_t j = j0 + r, c = c0 + cc;
-        double v = zin[j * ldzb + c];
-        if (j == cs.idx[c] && cs.state[c] != COL_PAD) v -= 1.0;
-        tile[r][cc] = v * scale;
+    const int cp = threadIdx.x & 31, ry = threadIdx.x >> 5;
+    const int64_t ca = c0 + 2 * cp;
+    const int64_t ia = cs.state[ca] != COL_PAD ? cs.idx[ca] : -1;
+    const int64_t ib = cs.state[ca + 1] != COL_PAD ? cs.idx[ca + 1] : -1;
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = *(const double2 *)(zin + (j0 + ry + 8 * q) * ldzb + ca);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int r = ry + 8 * q;
+        const int64_t j = j0 + r;
+        tile[r][2 * cp] = (j == ia ? v[q].x - 1.0 : v[q].x) * scale;
+        tile[r][2 * cp + 1] = (j == ib ? v[q].y - 1.0 : v[q].y) * scale;
     }
     __syncthreads();
     if (x3) {  // hi/lo FP16 halves (kp x ldt each)
-        _Float16 *zh = (_Float16 *)zt, *zl = zh + kp * ldt;
-        const int t2 = threadIdx.x;
-        for (int q = 0; q < 16; ++q) {
-            const int cc = (t2 >> 6) + 4 * q, r = t2 & 63;
-            const double x = tile[r][cc];
-            const _Float16 hi = to_low<_Float16>(x);
-            zh[(c0 + cc) * ldt + j0 + r] = hi;
-            zl[(c0 + cc) * ldt + j0 + r] = to_low<_Float16>(x - (double)hi);
-        }
-    } else if (prec == PREC_F32) cast_z_tile<float>(tile, (float *)zt, ldt, c0, j0);
-    else if (f16) cast_z_tile<_Float16>(tile, (_Float16 *)zt, ldt, c0, j0);
-    else cast_z_tile<__bf16>(tile, (__bf16 *)zt, ldt, c0, j0);
+        _Float16 *zh = (_Float16 *)zt;
+        cast_z_store<_Float16>(tile, zh, ldt, c0, j0, zh + kp * ldt);
+    } else if (prec == PREC_F32) {
+        cast_z_store<float>(tile, (float *)zt, ldt, c0, j0, nullptr);
+    } else if (f16) {
+        cast_z_store<_Float16>(tile, (_Float16 *)zt, ldt, c0, j0, nullptr);
+    } else {
+        cast_z_store<__bf16>(tile, (__bf16 *)zt, ldt, c0, j0, nullptr);
+    }
 }
 
 inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) / per); }
@@ -994,16 +1029,20 @@ inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) /
 
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp) {
-    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k, 0, 0.0);
-    return launch_init_cols(s, ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp);
+    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k, 0, 0.0, bitmap, (n + 31) / 32);
+    return launch_init_cols(s, ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp, true);
 }
 
 hipError_t launch_init_cols(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
-                            int64_t kp, uint32_t *bitmap, int32_t ntiles_n, int32_t start_stamp) {
+                            int64_t kp, uint32_t *bitmap, int32_t ntiles_n, int32_t start_stamp, bool bitmap_zeroed,
+                            const double *theta) {
     const int64_t words = (n + 31) / 32;
-    k_fill_u32<<<blocks_for(words, 256) < 1024 ? blocks_for(words, 256) : 1024, 256, 0, s>>>(bitmap, words, 0u);
-    const int64_t m = kp > ntiles_n ? kp : ntiles_n;
-    k_init_cols<<<blocks_for(m, 256), 256, 0, s>>>(ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp);
+    if (!bitmap_zeroed)
+        k_fill_u32<<<blocks_for(words, 256) < 1024 ? blocks_for(words, 256) : 1024, 256, 0, s>>>(bitmap, words, 0u);
+    int64_t m = kp > ntiles_n ? kp : ntiles_n;
+    if (theta && m < n) m = n < 65536 ? n : 65536;  // theta's order check strides over the grid
+    k_init_cols<<<blocks_for(m, 256), 256, 0, s>>>(ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp,
+                                                   theta);
     return hipGetLastError();
 }
 
@@ -1013,8 +1052,8 @@ hipError_t launch_plan_dense(hipStream_t s, Ctrl *ctrl, ColState cs, int64_t kp)
 }
 
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0,
-                            double cont_alpha) {
-    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, active, sym0, cont_alpha);
+                            double cont_alpha, uint32_t *bitmap, int64_t n_bits) {
+    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, active, sym0, cont_alpha, bitmap, bitmap ? (n_bits + 31) / 32 : 0);
     return hipGetLastError();
 }
 
@@ -1026,9 +1065,9 @@ hipError_t launch_scan_delta(hipStream_t s, Ctrl *ctrl, const double *delta, int
 }
 
 hipError_t launch_check_theta(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *idx, int64_t n,
-                              int64_t k) {
+                              int64_t k, bool order_done) {
     const int ob = blocks_for(n, 256) < 256 ? blocks_for(n, 256) : 256;
-    k_theta_order<<<ob, 256, 0, s>>>(ctrl, theta, n);
+    if (!order_done) k_theta_order<<<ob, 256, 0, s>>>(ctrl, theta, n);
     dim3 g(blocks_for(n, 256), blocks_for(k, 256));
     k_check_theta<<<g, 256, 0, s>>>(ctrl, theta, idx, n, k);
     return hipGetLastError();
@@ -1045,6 +1084,40 @@ hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, con
     k_prep_delta<__bf16><<<g, 256, 0, s>>>(ctrl, theta, delta, lda, n, np, dpad, dlo, d32, colpart, bmax);
     if (colpart) k_norm1_reduce<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, colpart, n, chunks);
     if (bmax) k_set_dscale<<<1, 256, 0, s>>>(ctrl, bmax, prep_delta_blocks(np));
+    return hipGetLastError();
+}
+
+// Debug-mode guard bands: nb bands of `words` 64-bit words at byte offsets list[b] from
+// base.  Fill writes the pattern (and resets the damage word to "none"); check records
+// the lowest band index that holds anything else.  One block per band.
+constexpr uint64_t GUARD_PATTERN = 0x7ff4a5a55a5aa5a5ull;  // a signalling-NaN bit pattern
+
+__global__ __launch_bounds__(256) void k_guard_fill(char *base, const uint64_t *list, int64_t words,
+                                                    int32_t *damage) {
+    uint64_t *g = (uint64_t *)(base + list[blockIdx.x]);
+    for (int64_t w = threadIdx.x; w < words; w += 256) g[w] = GUARD_PATTERN;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *damage = INT32_MAX;
+}
+
+__global__ __launch_bounds__(256) void k_guard_check(const char *base, const uint64_t *list, int64_t words,
+                                                     int32_t *damage) {
+    const uint64_t *g = (const uint64_t *)(base + list[blockIdx.x]);
+    bool bad = false;
+    for (int64_t w = threadIdx.x; w < words; w += 256) bad |= g[w] != GUARD_PATTERN;
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicMin(damage, (int32_t)blockIdx.x);
+}
+
+hipError_t launch_guard_fill(hipStream_t s, char *base, const uint64_t *list, int64_t nb, int64_t words,
+                             int32_t *damage) {
+    if (nb < 1) return hipSuccess;
+    k_guard_fill<<<(unsigned)nb, 256, 0, s>>>(base, list, words, damage);
+    return hipGetLastError();
+}
+
+hipError_t launch_guard_check(hipStream_t s, const char *base, const uint64_t *list, int64_t nb, int64_t words,
+                              int32_t *damage) {
+    if (nb < 1) return hipSuccess;
+    k_guard_check<<<(unsigned)nb, 256, 0, s>>>(base, list, words, damage);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libipt.so")
 
-IPT_OK, IPT_EINVAL, IPT_EDEGENERATE, IPT_ENOTCONV, IPT_EHIP, IPT_ENOMEM = range(6)
+IPT_OK, IPT_EINVAL, IPT_EDEGENERATE, IPT_ENOTCONV, IPT_EHIP, IPT_ENOMEM, IPT_EGUARD = range(7)
 CONVERGED, NOT_CONVERGED, DIVERGED = 0, 1, 2
 PREC_FP64, PREC_LADDER = 0, 1
 LOW_BF16, LOW_FP16, LOW_NONE = 0, 1, 2
@@ -225,7 +225,7 @@ def _colinfo(k, want):
     return ci, (sw, stp, res)
 
 
-def _finish(lib, h, st, z, lam, status, info, extra, raise_on=(IPT_EINVAL, IPT_EDEGENERATE, IPT_EHIP, IPT_ENOMEM)):
+def _finish(lib, h, st, z, lam, status, info, extra, raise_on=(IPT_EINVAL, IPT_EDEGENERATE, IPT_EHIP, IPT_ENOMEM, IPT_EGUARD)):
     if st in raise_on:
         raise IPTError(st, h.last_error())
     r = Result(z=z, lam=lam, status=status, info=info.as_dict(), code=st)

@@ -291,3 +291,60 @@ def test_paper_family_benchmarked_size_sampled(ipt, prec):
 def torch_index(a):
     import torch
     return torch.from_numpy(np.asarray(a, dtype=np.int64)).to(dev())
+
+
+def test_ipt_log_lines(ipt, capfd, monkeypatch):
+    """IPT_LOG=1: one summary line and one line per sweep on stderr, matching ipt_info;
+    nothing without it."""
+    say("dense IPT_LOG n=256 ladder")
+    th, de = W.dense_sym_gaussian(256, 0.01, 0)
+    monkeypatch.setenv("IPT_LOG", "1")
+    capfd.readouterr()
+    g = _solve(ipt, th, de, tol=1e-10, precision=ipt.PREC_LADDER, flags=ipt.FLAG_TIME_KERNELS)
+    err = capfd.readouterr().err
+    lines = [x for x in err.splitlines() if x.startswith("[ipt] dense")]
+    inf = g.info
+    assert len(lines) == 1 + inf["sweeps"], err
+    head = dict(f.split("=") for f in lines[0].split(": ", 1)[1].split())
+    assert int(head["sweeps"]) == inf["sweeps"] and int(head["converged"]) == inf["converged"] == 256
+    assert head["status"] == "IPT_OK"
+    for q, ln in enumerate(lines[1:]):
+        assert ln.startswith("[ipt] dense sweep %d: " % (q + 1)), ln
+        f = dict(x.split("=") for x in ln.split(": ", 1)[1].split()[1:])
+        assert int(f["active"]) == inf["sweep_active"][q]
+        assert float(f["max_step"]) == pytest.approx(inf["sweep_max_step"][q], rel=1e-3)
+        assert "product_ms" in f
+    monkeypatch.setenv("IPT_LOG", "0")
+    _solve(ipt, th, de, tol=1e-10)
+    assert "[ipt]" not in capfd.readouterr().err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "ladder"])
+def test_dense_choice_of_d_parity(ipt, prec):
+    """IPT_FLAG_CHOOSE_D on a dense full-spectrum solve (n = 300, pairs planted beyond the
+    2x2 bound, one at a 64-row tile edge): every column against the oracle's rotated
+    solve (the same pairing, rotation and chart); all converge, which the plain solve
+    does not; column info and the norm of the re-partitioned matrix are filled."""
+    say("dense choice of D n=300 %s" % prec)
+    rng = np.random.default_rng(21)
+    n = 300
+    th = np.arange(1.0, n + 1.0)
+    r = rng.standard_normal((n, n)) * 0.01 / np.sqrt(n)
+    de = (r + r.T) / 2.0
+    for i, j in [(10, 11), (63, 64), (200, 201)]:
+        th[j] = th[i] + 0.02
+        de[i, j] = de[j, i] = 1.5 * 0.02
+    p = ipt.PREC_LADDER if prec == "ladder" else ipt.PREC_FP64
+    g = _solve(ipt, th, de, tol=1e-10, precision=p, max_iter=64, flags=ipt.FLAG_CHOOSE_D)
+    plain = _solve(ipt, th, de, tol=1e-10, precision=p, max_iter=64)
+    th2, de2, partner, cs = oracle.choose_d(th, de, ipt.PAIR_TAU)
+    rr = oracle.ipt_dense(th2, de2, tol=1e-10, max_iter=64)
+    rr["z"] = oracle.pair_back_rotate(rr.z, partner, cs)
+    out = check(g.z, g.lam, g.status, rr, oracle.norm1(th, de), 1e-10, max_iter=64)
+    assert out["compared"] == n
+    assert np.all(g.status == 0) and np.any(plain.status != 0)
+    # |M'|_1 of the re-partitioned matrix the sweeps ran on (M' = R^T M R)
+    assert abs(g.info["norm1"] - oracle.norm1(th2, de2)) <= 1e-12 * oracle.norm1(th2, de2)
+    assert np.all(g.sweeps >= 1) and np.all(g.resid[g.status == 0] <= 1e-9)
+    with pytest.raises(ipt.IPTError):   # a subset of columns cannot be re-partitioned
+        ipt.ipt_solve_dense(t(th), t(de), idx=t(np.arange(5, dtype=np.int32)), flags=ipt.FLAG_CHOOSE_D)
