@@ -877,6 +877,11 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
 
     // Workspace layout (sizes first, then carve).
     const bool acx = dopt.acx != 0;
+    // The caller's z_out serves as iterate buffer 0 when it has that buffer's shape (no
+    // padding rows or columns, ldz = kp) and is not the warm start: a column certified by
+    // a sweep that read buffer 0 (odd sweeps) is then already in place, and the copy-out
+    // skips it.  Not with ACX, whose slots have other roles.
+    const bool alias_out = !acx && np == n && kp == k && ldz == kp && (const double *)z_out != z0;
     double *acx_part = nullptr, *acx_sigma = nullptr, *ypart = nullptr;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
@@ -885,7 +890,7 @@ ipt_status solve_dense(ipt_handle h, int64_t n, const double *theta, const doubl
     const SplitBounds sb = split_bounds(np, kp, nblk);
     auto layout = [&](Carve &cv, double **zb, ColState &cs, double **dnp, double **dvec, double **part, uint32_t **bitmap,
                       double **scratch, double **dpad, void **dlo, float **d32, void **zt, Ctrl **ctrl) {
-        zb[0] = cv.take<double>(np * kp);
+        zb[0] = alias_out ? z_out : cv.take<double>(np * kp);
         zb[1] = cv.take<double>(np * kp);
         zb[2] = acx ? cv.take<double>(np * kp) : nullptr;
         zb[3] = acx ? cv.take<double>(np * kp) : nullptr;
@@ -1191,9 +1196,11 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     const int64_t nrt = spmm_row_tiles(n);
     const bool acx = dopt.acx != 0;
     double *acx_part = nullptr, *acx_sigma = nullptr;
+    // z_out as iterate buffer 0 when it has its shape (ldz = ldzb = k), as in the dense solve
+    const bool alias_out = !acx && ldz == ldzb && k == ldzb && (const double *)z_out != z0;
     auto layout = [&](Carve &cv, double **zb, float **zlo, ColState &cs, double **dvec, double **part,
                       uint32_t **bitmap, double **scratch, float **val32, Ctrl **ctrl) {
-        zb[0] = cv.take<double>(n * ldzb);
+        zb[0] = alias_out ? z_out : cv.take<double>(n * ldzb);
         zb[1] = cv.take<double>(n * ldzb);
         zb[2] = acx ? cv.take<double>(n * ldzb) : nullptr;
         zb[3] = acx ? cv.take<double>(n * ldzb) : nullptr;

@@ -156,12 +156,22 @@ __global__ __launch_bounds__(256) void k_bsweep1(const Ctrl *ctrl, BArgs a, cons
                 }
             }
             __syncthreads();
-#pragma unroll 2
+            // the eight rows' loads go out together (clamped to valid addresses), then the
+            // writes of each row
+            double dv[8], tv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int j = j0 + ry + 4 * i;
+                const int jc = j < n ? j : n - 1, cc = colok ? c : 0;
+                dv[i] = db[(int64_t)jc * n + cc];
+                tv[i] = tb[jc];
+            }
+#pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int jj = ry + 4 * i, j = j0 + jj;
                 if (c >= np) continue;
                 const bool in = colok && j < n;
-                const double djc = in ? db[(int64_t)j * n + c] : 0.0;
+                const double djc = in ? dv[i] : 0.0;
                 const int64_t e = m.offz + (int64_t)j * np + c;
                 a.dpad[e] = djc;
                 double wv = 0.0;
@@ -171,7 +181,7 @@ __global__ __launch_bounds__(256) void k_bsweep1(const Ctrl *ctrl, BArgs a, cons
                         v[1] += 1.0;
                         v[5] += fabs(djc + ti);
                     } else {
-                        const double gap = tb[j] - ti;
+                        const double gap = tv[i] - ti;
                         wv = -djc / gap;
                         v[0] += wv * wv;
                         v[2] += (gap * wv) * (gap * wv);
@@ -1010,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_bcopyout(const Ctrl *ctrl, BArgs a, con
     if (ctrl->error) return;
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const int4 w = items[it];
+        const int4 w = items[__builtin_amdgcn_readfirstlane((int32_t)it)];
         const BatchMeta m = a.meta[w.x];
         const int n = m.n, np = m.np, tm = w.y;
         const int c = w.z * 64 + cx;
@@ -1021,8 +1031,19 @@ __global__ __launch_bounds__(256) void k_bcopyout(const Ctrl *ctrl, BArgs a, con
             const double *src = a.zs[par == PAR_BUF1 ? 1 : 0] + m.offz;
             double *dst = z_pool + m.offo;
             const int j1 = min(n, tm * m.T + m.T);
-            for (int j = tm * m.T + ry; j < j1; j += 4)
-                dst[(int64_t)j * n + c] = (par == PAR_UNIT) ? (j == c ? 1.0 : 0.0) : src[(int64_t)j * np + c];
+            // eight rows' loads in flight before their stores (rows < np are inside the
+            // padded buffer, so the loads need no bounds check)
+            for (int j0 = tm * m.T + ry; j0 < j1; j0 += 32) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int j = j0 + 4 * u;
+                    v[u] = (par == PAR_UNIT) ? (j == c ? 1.0 : 0.0) : src[(int64_t)(j < np ? j : np - 1) * np + c];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (j0 + 4 * u < j1) dst[(int64_t)(j0 + 4 * u) * n + c] = v[u];
+            }
         }
         if (tm == 0 && ry == 0) {  // one wave per item: per-column outputs
             uint64_t rb = 0;

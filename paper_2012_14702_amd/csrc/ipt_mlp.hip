@@ -98,11 +98,25 @@ __device__ inline float adam_update(float *w, float *m, float *v, float g, float
     return nw;
 }
 
+// The loss and Adam epilogues read FP32 data per output (targets; weights and moments):
+// their accumulators go through LDS in two halves of 64 rows (FP32, after the BF16
+// output tile), and each thread then takes 4 consecutive columns of a row at a time,
+// so those reads and the Adam writes are 16-byte accesses along rows, four rows' loads
+// in flight before their arithmetic.
+constexpr int FLD = GT + 4;                                   // FP32 half-tile pitch (floats)
+constexpr int SMEM_STAGED = GT * OLD + 2 * (GT / 2) * FLD;    // BF16 tile + FP32 half (in BF16 units)
+template <int MODE>
+constexpr int mlp_smem() {
+    return (MODE == MLP_EPI_MSE || MODE == MLP_EPI_ADAM || MODE == MLP_EPI_WARM)
+               ? (SMEM_STAGED > SMEM_BF16 ? SMEM_STAGED : SMEM_BF16)
+               : SMEM_BF16;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_mlp_gemm(const __bf16 *__restrict__ A, int64_t lda,
                                                   const __bf16 *__restrict__ B, int64_t ldb, int Kc, int M, int N,
                                                   MlpEpi e) {
-    __shared__ __attribute__((aligned(16))) uint16_t smem[SMEM_BF16];
+    __shared__ __attribute__((aligned(16))) uint16_t smem[mlp_smem<MODE>()];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int64_t kbeg = (int64_t)blockIdx.z * Kc;
@@ -190,35 +204,60 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const __bf16 *__restrict__ A, 
         return;
     }
     if (MODE == MLP_EPI_WARM) {
+        // accumulators through LDS (two halves of 64 rows, FP32); each thread then takes 4
+        // consecutive outputs q of a member row at a time (consecutive columns c of Z0)
+        float(*fh)[FLD] = (float(*)[FLD])(smem + GT * OLD);
         const int32_t ord = e.order;
+        const int cq = t & 31, rp = t >> 5;
+        int64_t jj[4], cc[4];
+        bool qok[4], unit[4];
+        double bv[4], mu[4], sg[4];
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int u = 0; u < 4; ++u) {
+            const int q = n0 + 4 * cq + u;
+            qok[u] = q < e.nvalid;
+            const int qq = qok[u] ? q : 0;
+            divmod_nn(qq, e.kcols, jj[u], cc[u]);
+            unit[u] = jj[u] == e.idx[cc[u]];
+            bv[u] = e.bias ? (double)e.bias[qq] : 0.0;
+            mu[u] = e.mu[qq];
+            sg[u] = e.sigma[qq];
+        }
 #pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                const int q = n0 + cbase + 16 * y;
-                if (q >= e.nvalid) continue;
-                int64_t j, c;
-                divmod_nn(q, e.kcols, j, c);
-                const bool unit = (j == e.idx[c]);
-                const double bv = e.bias ? (double)e.bias[q] : 0.0;
-                const double mu = e.mu[q], sg = e.sigma[q];
+        for (int h = 0; h < 2; ++h) {
+            if (wm == h) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int p = m0 + rbase + 16 * x + r;
-                    if (p >= e.mvalid) continue;
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) fh[4 * (lane >> 4) + 16 * x + r][cbase + 16 * y] = acc[x][y][r];
+            }
+            __syncthreads();
+#pragma unroll 2
+            for (int i = 0; i < 8; ++i) {
+                const int lrow = rp + 8 * i, p = m0 + h * 64 + lrow;
+                if (p >= e.mvalid) continue;
+                const double ep = e.eps[p];
+                const f4_t a4 = *(const f4_t *)&fh[lrow][4 * cq];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!qok[u]) continue;
+                    const int q = n0 + 4 * cq + u;
                     double v = 1.0;
-                    if (!unit) {
-                        const double ep = e.eps[p];
+                    if (!unit[u]) {
                         double base = 0.0, pw = 1.0;
                         for (int l = 1; l <= ord; ++l) {
                             pw *= ep;
                             base += pw * e.terms[(int64_t)(l - 1) * e.nvalid + q];
                         }
-                        v = base + pw * ep * (mu + sg * ((double)acc[x][y][r] + bv));
+                        v = base + pw * ep * (mu[u] + sg[u] * ((double)a4[u] + bv[u]));
                     }
-                    e.z0[(int64_t)p * e.pstride + j * e.ldz0 + c] = v;
+                    e.z0[(int64_t)p * e.pstride + jj[u] * e.ldz0 + cc[u]] = v;
                 }
             }
+            __syncthreads();
+        }
         return;
     }
 
@@ -230,6 +269,138 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const __bf16 *__restrict__ A, 
         const float step = (float)(*e.adam_t + 1);
         c1 = 1.f - powf(ADAM_B1, step);
         c2 = 1.f - powf(ADAM_B2, step);
+    }
+    if constexpr (MODE == MLP_EPI_MSE || MODE == MLP_EPI_ADAM) {
+        float(*fh)[FLD] = (float(*)[FLD])(smem + GT * OLD);
+        const int cq = t & 31, rp = t >> 5;  // columns 4 cq .. 4 cq + 3, rows rp, rp + 8, ...
+        const int lc0 = 4 * cq, gc0 = n0 + lc0;
+        // the 4 columns: all valid (16-byte path) or checked one by one
+        const bool vec = gc0 + 4 <= e.nvalid &&
+                         (MODE == MLP_EPI_MSE ? (e.ldt & 3) == 0 && ((uintptr_t)e.tgt & 15) == 0
+                                              : (e.nvalid & 3) == 0 &&
+                                                    (((uintptr_t)e.w | (uintptr_t)e.am | (uintptr_t)e.av) & 15) == 0);
+        float bv[4] = {0.f, 0.f, 0.f, 0.f};
+        if (MODE == MLP_EPI_MSE && e.bias)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bv[q] = gc0 + q < e.nvalid ? e.bias[gc0 + q] : 0.f;
+        float csv[4] = {0.f, 0.f, 0.f, 0.f};  // column sums of the stored values over this thread's rows
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (wm == h) {
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) fh[4 * (lane >> 4) + 16 * x + r][cbase + 16 * y] = acc[x][y][r];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i0 = 0; i0 < 8; i0 += 4) {
+                f4_t ld0[4], ld1[4], ld2[4];  // targets, or weights / moments
+                float rw[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int lrow = h * 64 + rp + 8 * (i0 + i), gr = m0 + lrow;
+                    const bool rok = gr < e.mvalid;
+                    rw[i] = 1.f;
+                    if (MODE == MLP_EPI_MSE) {
+                        if (rok && e.roww) rw[i] = e.roww[gr];
+                        const float *tp = e.tgt + (int64_t)(rok ? gr : 0) * e.ldt + gc0;
+                        if (vec) {
+                            ld0[i] = *(const f4_t *)tp;
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) ld0[i][q] = gc0 + q < e.nvalid ? tp[q] : 0.f;
+                        }
+                    } else {
+                        const int64_t wi = (int64_t)(rok ? gr : 0) * e.nvalid + gc0;
+                        if (vec) {
+                            ld0[i] = *(const f4_t *)(e.w + wi);
+                            ld1[i] = *(const f4_t *)(e.am + wi);
+                            ld2[i] = *(const f4_t *)(e.av + wi);
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const bool ok = gc0 + q < e.nvalid;
+                                ld0[i][q] = ok ? e.w[wi + q] : 0.f;
+                                ld1[i][q] = ok ? e.am[wi + q] : 0.f;
+                                ld2[i][q] = ok ? e.av[wi + q] : 0.f;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int lrow = h * 64 + rp + 8 * (i0 + i), gr = m0 + lrow;
+                    const bool rok = gr < e.mvalid;
+                    const f4_t a4 = *(const f4_t *)&fh[lrow - h * 64][lc0];
+                    f4_t nw = f4_t{0.f, 0.f, 0.f, 0.f}, nm = nw, nv = nw;
+                    uint16_t b[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool ok = rok && gc0 + q < e.nvalid;
+                        float v = a4[q] + bv[q];
+                        if (MODE == MLP_EPI_MSE) {
+                            const float ws = (ok && e.roww) ? rw[i] : 1.f;
+                            const float d = ok ? (v - ld0[i][q]) * ws : 0.f;
+                            lsum += d * d;
+                            v = (e.scale * ws) * d;
+                        } else if (ok) {
+                            float w = ld0[i][q], m = ld1[i][q], vv = ld2[i][q];
+                            v = adam_update(&w, &m, &vv, v, e.lr, c1, c2);
+                            nw[q] = w;
+                            nm[q] = m;
+                            nv[q] = vv;
+                        }
+                        b[q] = ok ? bf16_bits(v) : (uint16_t)0;
+                        csv[q] += bits_f32(b[q]);
+                    }
+                    if (MODE == MLP_EPI_ADAM && rok) {
+                        const int64_t wi = (int64_t)gr * e.nvalid + gc0;
+                        if (vec) {
+                            *(f4_t *)(e.w + wi) = nw;
+                            *(f4_t *)(e.am + wi) = nm;
+                            *(f4_t *)(e.av + wi) = nv;
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                if (gc0 + q < e.nvalid) {
+                                    e.w[wi + q] = nw[q];
+                                    e.am[wi + q] = nm[q];
+                                    e.av[wi + q] = nv[q];
+                                }
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) out[lrow * OLD + lc0 + q] = b[q];
+                }
+            }
+            __syncthreads();
+        }
+        if (e.colp) {
+            // the 8 row phases in order, through LDS (the FP32 half is free again)
+            float(*cred)[GT] = (float(*)[GT])(smem + GT * OLD);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cred[rp][lc0 + q] = csv[q];
+            __syncthreads();
+            if (t < GT) {
+                float v = cred[0][t];
+#pragma unroll
+                for (int g = 1; g < 8; ++g) v += cred[g][t];
+                e.colp[(int64_t)(m0 / GT) * e.ldcolp + n0 + t] = v;
+            }
+        }
+        if (MODE == MLP_EPI_MSE) {
+            __shared__ double red[4];
+            const double ws = wave_sum_d((double)lsum);
+            if (lane == 0) red[wv] = ws;
+            __syncthreads();
+            if (t == 0) e.lossp[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+        }
+        __syncthreads();
+        store_tile(out, e, m0, n0);
+        return;
     }
     float csum[4] = {0.f, 0.f, 0.f, 0.f};  // column sums of the stored values over this lane's rows
 #pragma unroll

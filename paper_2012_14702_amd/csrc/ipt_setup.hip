@@ -929,7 +929,9 @@ __global__ __launch_bounds__(256) void k_copyout(const Ctrl *ctrl, ColState cs, 
     const int32_t par = cs.par[c];
     const int32_t i = cs.idx[c];
     const double *src = (par == PAR_BUF1) ? buf1 : buf0;
-    for (int64_t jb = j0; jb < n; jb += (int64_t)gridDim.y * 64) {
+    // an iterate buffer that is z_out itself already holds the column in place
+    const bool in_place = par != PAR_UNIT && src == z_out && ldzb == ldz;
+    for (int64_t jb = in_place ? n : j0; jb < n; jb += (int64_t)gridDim.y * 64) {
         int64_t j1 = jb + 64;
         if (j1 > n) j1 = n;
         // eight rows per step, their loads issued together
