@@ -567,6 +567,7 @@ ipt_status batched_run(ipt_handle h, int32_t count, const int32_t *ns, const int
         L.dpart = cv.take<double>(total_q);
         L.normpart = cv.take<double>(total_q);
         L.tflag = cv.take<uint32_t>(2 * total_tiles);
+        L.ncols = cv.take<int32_t>((size_t)count * 16);
         for (int c = 0; c < NCLS; ++c)
             for (int p = 0; p < 2; ++p) lists.l[c][p] = cv.take<int4>(NXCD * segcap[c] + 1);
         cnt = cv.take<int32_t>(BLIST_WORDS);

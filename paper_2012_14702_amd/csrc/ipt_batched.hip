@@ -518,21 +518,20 @@ __device__ __forceinline__ void btile_skinny(char *smem, int32_t *scol, const BA
     const E *Ag = F64 ? (const E *)Ad : (const E *)(a.d32 + m.offz);
     const E *Bg = F64 ? (const E *)zin : (const E *)((in_buf ? a.zlo1 : a.zlo0) + m.offz);
     float *zlo_out = F64 ? nullptr : (in_buf ? a.zlo0 : a.zlo1) + m.offz;
-    const int r0 = tm * T, p0 = tn * T;
-    const int32_t *al = a.col.alist + m.offc;
-    const int kact = a.col.kact[b];
-    if (tid < 16) scol[tid] = p0 + tid < kact ? al[p0 + tid] : -1;
-    __syncthreads();
+    const int r0 = tm * T;
+    (void)tn;
     const double *tb = a.theta + m.offt;
     const bool sym = a.col.asym[b] == 0;
     const bool need_jc = !F64 || sym;
-    // this lane's epilogue column
-    const int c_raw = scol[lc];
+    // this lane's epilogue column, and the B column of this thread (the same: tid % 16),
+    // from the tile's column list the plan wrote
+    const int32_t *nc = a.ncols + (int64_t)b * 16;
+    const int c_raw = nc[lc];
     const bool act = c_raw >= 0 && a.col.state[m.offc + c_raw] == COL_ACTIVE;
     const int c = act ? c_raw : 0;
     const double ti = act ? tb[c] : 0.0, dd = act ? a.col.d[m.offc + c] : 0.0;
     // B staging: thread -> (k row (tid + 256 i) / 16, column tid % 16), four entries per chunk
-    const int bcol = scol[tid & 15];
+    const int bcol = c_raw;
     double sums[NPART + 1];
 #pragma unroll
     for (int q2 = 0; q2 < NPART + 1; ++q2) sums[q2] = 0.0;
@@ -634,7 +633,7 @@ __device__ __forceinline__ void btile_skinny(char *smem, int32_t *scol, const BA
     }
     __syncthreads();
     if (tid < 16) {
-        const int cc = scol[tid];
+        const int cc = nc[tid];
         if (cc >= 0) {
             double v[NPART + 1];
 #pragma unroll
@@ -700,7 +699,7 @@ __global__ __launch_bounds__(256, 4) void k_bnarrow(const Ctrl *ctrl, BArgs a, B
         if (threadIdx.x == 0) tk = atomicAdd(&tickets[x], 1);
         const int4 w = items[it];
         const BatchMeta m = a.meta[w.x];
-        if (a.tflag[m.offf + w.z] == (uint32_t)PREC_F64) btile_skinny<true>(smem, scol, a, m, w.x, w.y, w.z, t, acx);
+        if (w.w == PREC_F64) btile_skinny<true>(smem, scol, a, m, w.x, w.y, w.z, t, acx);
         else btile_skinny<false>(smem, scol, a, m, w.x, w.y, w.z, t, acx);
         // (the tile ends with a barrier: every thread has read cur_item)
         if (threadIdx.x == 0) {
@@ -951,8 +950,12 @@ __global__ __launch_bounds__(256) void k_bplan(const Ctrl *ctrl, BArgs a, BatchL
     int4 *lst = lists.l[cl][nx] + (int64_t)m.xcd * lists.segcap[cl];
     for (int e = threadIdx.x; e < wide * nt; e += 256) lst[s_items + e] = make_int4(b, e % nt, e / nt, 0);
     if (narrow) {
+        // the narrow items carry the tile's precision; its columns go to ncols
+        const int p0 = (tiles - 1) * m.T;
+        if (threadIdx.x < 16) a.ncols[(int64_t)b * 16 + threadIdx.x] = p0 + threadIdx.x < kact ? al[p0 + threadIdx.x] : -1;
         int4 *ln = lists.l[CLS_NARROW][nx] + (int64_t)m.xcd * lists.segcap[CLS_NARROW];
-        for (int e = threadIdx.x; e < nt; e += 256) ln[s_items2 + e] = make_int4(b, e, tiles - 1, 0);
+        const int prec = (int)s_tprec[tiles - 1];
+        for (int e = threadIdx.x; e < nt; e += 256) ln[s_items2 + e] = make_int4(b, e, tiles - 1, prec);
     }
 }
 

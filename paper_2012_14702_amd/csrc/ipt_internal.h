@@ -236,6 +236,7 @@ struct BatchLaunch {
     double *normpart;  // [total_q] column sums of |M_b| per row tile (first sweep)
     uint64_t *bpart;   // [finalize blocks][8] per-block batch counters
     uint32_t *tflag;   // [total column tiles] precision of each packed column tile of the next sweep
+    int32_t *ncols;    // [problems][16] the columns of a problem's narrow tile (-1 past its end)
     int64_t total_tiles, total_q;
 };
 // Work lists of (problem, row tile, column tile, 0) items per tile class (T = 32, 64,
