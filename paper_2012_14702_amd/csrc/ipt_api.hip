@@ -1245,11 +1245,10 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     // A cold start's first sweep multiplies Delta by E, which is exact in every
     // precision (the low-precision part Z - E is zero), so it may certify.
     const int32_t start_prec = cold ? PREC_EXACT_FIRST : (ladder ? PREC_F32 : PREC_F64);
-    IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kpc, bitmap, start_prec, (int32_t)(kpc / TILE_N + 1), 0));
-    IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k));
-    IPT_HIP(h, launch_check_csr(s, ctrl, row_ptr, col, n, nnz));
+    IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kpc, bitmap, start_prec, (int32_t)(kpc / TILE_N + 1), 0, theta));
+    IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k, true));
+    IPT_HIP(h, launch_check_csr(s, ctrl, row_ptr, col, n, nnz, val, val32));
     if (norm) IPT_HIP(h, launch_norm1_csr(s, ctrl, theta, row_ptr, col, val, n, nnz, scratch));
-    if (ladder && nnz > 0) IPT_HIP(h, launch_val32(s, val, val32, nnz));
     // A cold start's first sweep reads no iterate (Z = E: the product-free sweep); only
     // ACX keeps E in slot 0 as the base of its first cycle.
     if (!cold || acx) IPT_HIP(h, launch_load_z0(s, ctrl, z0, ldz0, zb[0], ldzb, cs.idx, n, n, k, ldzb));
@@ -1271,15 +1270,21 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         const bool unit = cold && t == 1;  // the product-free first sweep (d from row i inside it)
         const int32_t in_par = acx ? PAR_BUF0 : (unit ? PAR_UNIT : ((t - 1) & 1)), out_par = acx ? PAR_BUF1 : (t & 1);
         double *zin = acx ? zb[q] : zb[(t - 1) & 1], *zout = acx ? zb[q + 1] : zb[t & 1];
-        if (!unit) IPT_HIP(h, launch_diag_csr(s, ctrl, row_ptr, col, val, zin, ldzb, cs, dvec, k));
+        // d of a plain sweep after the first comes from the previous sweep's tail
+        if (!unit && (acx || t == 1)) IPT_HIP(h, launch_diag_csr(s, ctrl, row_ptr, col, val, zin, ldzb, cs, dvec, k));
         IPT_HIP(h, timer.mark(t, 0, s));
         IPT_HIP(h, launch_spmm_sweep(s, ctrl, row_ptr, col, val, val32, theta, zin, zout,
                                      ladder ? zlo[(t - 1) & 1] : nullptr, ladder ? zlo[t & 1] : nullptr, cs, dvec,
                                      part, n, k, ldzb, kpc, unit ? 1 : 0));
         IPT_HIP(h, timer.mark(t, 1, s));
-        IPT_HIP(h, launch_reduce_parts(s, ctrl, cs, part, nrt, k, kpc));
-        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, 1, kpc, t, in_par, out_par));
-        IPT_HIP(h, launch_control(s, ctrl, dopt, t));
+        if (acx) {
+            IPT_HIP(h, launch_reduce_parts(s, ctrl, cs, part, nrt, k, kpc));
+            IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, 1, kpc, t, in_par, out_par));
+            IPT_HIP(h, launch_control(s, ctrl, dopt, t));
+        } else {
+            IPT_HIP(h, launch_csr_tail(s, ctrl, dopt, cs, dvec, theta, part, nrt, k, kpc, t, in_par, out_par, row_ptr,
+                                       col, val, zout, ldzb));
+        }
         if (acx && q == pc - 1)
             IPT_HIP(h, launch_acx(s, ctrl, cs.state, zb[0], zb[1], zb[2], zb[3], ldzb, n, k, pc, acx_part, acx_sigma));
         if (plan.at(t, o.max_iter)) {

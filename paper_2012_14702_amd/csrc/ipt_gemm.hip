@@ -24,6 +24,8 @@
 //    correction Z - E sees low precision.
 #include <math.h>
 
+#include <type_traits>
+
 #include "ipt_internal.h"
 
 namespace ipt {
@@ -528,55 +530,84 @@ __device__ __forceinline__ void gemm_x3_body(char *smem, double (*red)[BN][NRED]
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    uint4 st[4][2];  // staged chunks: A hi, A lo, B hi, B lo x two rows
-    auto load = [&](int64_t k) {
+    // Two register stages: the chunks of K step kt + 2 are loaded while step kt is
+    // multiplied out of LDS and step kt + 1 waits in the other stage, so a load has two
+    // steps of matrix work to arrive in.  st[p][m][q]: stage p, operand m (A hi, A lo,
+    // B hi, B lo), row l_r + 64 q; every index is a constant after unrolling.
+    // (a native vector type: the register arrays of HIP's uint4 struct were left in scratch)
+    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+    u4v st[2][4][2];
+    const int nk = (int)((k1 - k0) / X3_BK);
+    const int klast = nk > 0 ? nk - 1 : 0;
+    auto swz = [](int r, int chunk) { return 8 * (chunk ^ ((r >> 2) & 3)); };
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int64_t k = k0 + (int64_t)(p < klast ? p : klast) * X3_BK;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int64_t ao = (int64_t)(l_r + 64 * q) * ldd + k + l_c;
-            st[0][q] = *(const uint4 *)(Ah + ao);
-            st[1][q] = *(const uint4 *)(Al + ao);
-            st[2][q] = boff[q] >= 0 ? *(const uint4 *)(g.zth + boff[q] + k) : uint4{0u, 0u, 0u, 0u};
-            st[3][q] = boff[q] >= 0 ? *(const uint4 *)(g.ztl + boff[q] + k) : uint4{0u, 0u, 0u, 0u};
+            st[p][0][q] = *(const u4v *)(Ah + ao);
+            st[p][1][q] = *(const u4v *)(Al + ao);
+            st[p][2][q] = boff[q] >= 0 ? *(const u4v *)(g.zth + boff[q] + k) : u4v{0u, 0u, 0u, 0u};
+            st[p][3][q] = boff[q] >= 0 ? *(const u4v *)(g.ztl + boff[q] + k) : u4v{0u, 0u, 0u, 0u};
         }
-    };
-    auto swz = [](int r, int chunk) { return 8 * (chunk ^ ((r >> 2) & 3)); };
-    auto put = [&](int stage) {
+    }
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-                *(uint4 *)&S[4 * stage + m][l_r + 64 * q][swz(l_r + 64 * q, l_c >> 3)] = st[m][q];
-    };
-    const int nk = (int)((k1 - k0) / X3_BK);
-    load(k0);
-    put(0);
+        for (int q = 0; q < 2; ++q)
+            *(u4v *)&S[m][l_r + 64 * q][swz(l_r + 64 * q, l_c >> 3)] = st[0][m][q];
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        load(k0 + (int64_t)(kt + 1 < nk ? kt + 1 : kt) * X3_BK);
-        const int kc = lane >> 4;  // this lane's 16-byte chunk of the K slice
-        h8_t ah[4], al[4];
+    const int kc = lane >> 4;  // this lane's 16-byte chunk of the K slice
+    // K ranges are multiples of 64 (two steps): step kt + p sits in LDS stage p; the
+    // stage is a template constant, so every index into st is one
+    int kt = 0;
+    auto half = [&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        {
+            // stage p of the registers was stored to LDS: load step kt + p + 2 into it
+            const int kn = kt + p + 2;
+            const int64_t k = k0 + (int64_t)(kn < klast ? kn : klast) * X3_BK;
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-            const int r = wm * 64 + 16 * ib + (lane & 15);
-            ah[ib] = *(const h8_t *)&S[4 * cur + 0][r][swz(r, kc)];
-            al[ib] = *(const h8_t *)&S[4 * cur + 1][r][swz(r, kc)];
-        }
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            if (SPLIT && jb >= nj) continue;
-            const int r = wn * 64 + 16 * jb + (lane & 15);
-            const h8_t bh = *(const h8_t *)&S[4 * cur + 2][r][swz(r, kc)];
-            const h8_t bl = *(const h8_t *)&S[4 * cur + 3][r][swz(r, kc)];
+            for (int q = 0; q < 2; ++q) {
+                const int64_t ao = (int64_t)(l_r + 64 * q) * ldd + k + l_c;
+                st[p][0][q] = *(const u4v *)(Ah + ao);
+                st[p][1][q] = *(const u4v *)(Al + ao);
+                st[p][2][q] = boff[q] >= 0 ? *(const u4v *)(g.zth + boff[q] + k) : u4v{0u, 0u, 0u, 0u};
+                st[p][3][q] = boff[q] >= 0 ? *(const u4v *)(g.ztl + boff[q] + k) : u4v{0u, 0u, 0u, 0u};
+            }
+            h8_t ah[4], al[4];
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib) {
-                acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[ib], bh, acc[ib][jb], 0, 0, 0);
-                acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[ib], bl, acc[ib][jb], 0, 0, 0);
-                acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[ib], bh, acc[ib][jb], 0, 0, 0);
+                const int r = wm * 64 + 16 * ib + (lane & 15);
+                ah[ib] = *(const h8_t *)&S[4 * p + 0][r][swz(r, kc)];
+                al[ib] = *(const h8_t *)&S[4 * p + 1][r][swz(r, kc)];
             }
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                if (SPLIT && jb >= nj) continue;
+                const int r = wn * 64 + 16 * jb + (lane & 15);
+                const h8_t bh = *(const h8_t *)&S[4 * p + 2][r][swz(r, kc)];
+                const h8_t bl = *(const h8_t *)&S[4 * p + 3][r][swz(r, kc)];
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) {
+                    acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[ib], bh, acc[ib][jb], 0, 0, 0);
+                    acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[ib], bl, acc[ib][jb], 0, 0, 0);
+                    acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[ib], bh, acc[ib][jb], 0, 0, 0);
+                }
+            }
+            // step kt + p + 1 (register stage p ^ 1) to the other LDS stage
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    *(u4v *)&S[4 * (p ^ 1) + m][l_r + 64 * q][swz(l_r + 64 * q, l_c >> 3)] = st[p ^ 1][m][q];
+            __syncthreads();
         }
-        put(cur ^ 1);
-        __syncthreads();
+    };
+    for (; kt < nk; kt += 2) {
+        half(std::integral_constant<int, 0>{});
+        half(std::integral_constant<int, 1>{});
     }
 
     // f32-accumulating 16x16 MFMAs: lane l, register r holds row 4(l/16) + r, column l%16.
@@ -599,17 +630,19 @@ __device__ __forceinline__ void gemm_x3_body(char *smem, double (*red)[BN][NRED]
 }
 
 // The sweep's product over the K range [k0, k1), in the precision the ladder chose;
-// SPLIT writes the partial tile instead of running the epilogue.
-template <bool SPLIT>
+// SPLIT writes the partial tile instead of running the epilogue.  X3: the three-product
+// FP32-class rung, which has a kernel of its own (k_sweep_x3).
+template <bool SPLIT, bool X3>
 __device__ __forceinline__ void sweep_tile(const Ctrl *ctrl, const GemmArgs &g, char *smem, double (*red)[BN][NRED],
                                            const PackedCols scol, int tm, int64_t k0, int64_t k1, double *yp) {
     const int32_t prec = ctrl->prec;
     const bool sym = ctrl->sym != 0;
-    if (prec == PREC_F64) {
+    if constexpr (X3) {
+        gemm_x3_body<SPLIT>(smem, red, scol, g, 1.0 / (ctrl->dscale * ctrl->zscale), tm, k0, k1, yp, sym);
+    } else if (prec == PREC_F64) {
         gemm_f64_body<SPLIT>(smem, red, scol, g, tm, k0, k1, yp, sym);
     } else if (prec == PREC_F32) {
-        if (g.mid_x3) gemm_x3_body<SPLIT>(smem, red, scol, g, 1.0 / (ctrl->dscale * ctrl->zscale), tm, k0, k1, yp, sym);
-        else gemm_low_body<float, SPLIT>(smem, red, scol, g, g.d32, 1.0, tm, k0, k1, yp, sym);
+        gemm_low_body<float, SPLIT>(smem, red, scol, g, g.d32, 1.0, tm, k0, k1, yp, sym);
     } else if (prec == PREC_LOW) {
         if (g.low_type == LT_F16)
             gemm_low_body<_Float16, SPLIT>(smem, red, scol, g, (const _Float16 *)g.dlo,
@@ -622,8 +655,8 @@ __device__ __forceinline__ void sweep_tile(const Ctrl *ctrl, const GemmArgs &g, 
 // One sweep's product.  Sweeps with enough tiles: block -> (row tile, packed column
 // tile), whole K range, fused epilogue.  Narrow sweeps: block -> (split s, packed
 // column tile, row tile) over a K range, partial tile written for k_sweep_split_epi.
-__global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArgs g, int32_t regular_blocks) {
-    if (ctrl->error || ctrl->done) return;
+template <bool X3>
+__device__ __forceinline__ void sweep_gemm(const Ctrl *ctrl, const GemmArgs &g, int32_t regular_blocks) {
     const int ntm = (int)(g.np / BM), ntn = (int)(g.kp / BN);
     const int32_t kact = ctrl->kact;
     const SplitPlan sp = split_plan(kact, ntm, g.np, g.nblk);
@@ -639,7 +672,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArg
         // column tiles run over the packed active columns; tiles past them have no work
         if ((int64_t)tn * BN >= kact) return;
         const PackedCols scol{g.cs.alist + (int64_t)tn * BN, (int32_t)(kact - (int64_t)tn * BN)};
-        sweep_tile<false>(ctrl, g, smem, red, scol, tm, 0, g.np, nullptr);
+        sweep_tile<false, X3>(ctrl, g, smem, red, scol, tm, 0, g.np, nullptr);
     } else {
         const int64_t per = (int64_t)ntm * sp.nct;
         if ((int64_t)blockIdx.x >= per * sp.S) return;
@@ -649,8 +682,23 @@ __global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArg
         const int64_t k0 = (int64_t)s * nk64 / sp.S * 64, k1 = (int64_t)(s + 1) * nk64 / sp.S * 64;
         const PackedCols scol{g.cs.alist + (int64_t)tn * BN, (int32_t)(kact - (int64_t)tn * BN)};
         double *yp = g.ypart + (((int64_t)s * sp.nct + tn) * ntm + tm) * (int64_t)(BM * BN);
-        sweep_tile<true>(ctrl, g, smem, nullptr, scol, tm, k0, k1, yp);
+        sweep_tile<true, X3>(ctrl, g, smem, nullptr, scol, tm, k0, k1, yp);
     }
+}
+
+// The sweep's product in FP64, BF16/FP16 or FP32; a three-product FP32-class sweep is
+// left to k_sweep_x3, launched beside it (the precision is decided on the device).
+__global__ __launch_bounds__(256, 2) void k_sweep_gemm(const Ctrl *ctrl, GemmArgs g, int32_t regular_blocks) {
+    if (ctrl->error || ctrl->done) return;
+    if (g.mid_x3 && ctrl->prec == PREC_F32) return;
+    sweep_gemm<false>(ctrl, g, regular_blocks);
+}
+
+// The three-product FP32-class sweep: a kernel of its own so that the K loop is not
+// held to the FP64 body's register budget (it keeps two staged loads in flight).
+__global__ __launch_bounds__(256, 2) void k_sweep_x3(const Ctrl *ctrl, GemmArgs g, int32_t regular_blocks) {
+    if (ctrl->error || ctrl->done || ctrl->prec != PREC_F32) return;
+    sweep_gemm<true>(ctrl, g, regular_blocks);
 }
 
 // Narrow sweep, epilogue: Y of the tile = the split partials summed in split order.
@@ -721,6 +769,7 @@ hipError_t launch_sweep_gemm(hipStream_t s, const Ctrl *ctrl, const double *delt
     const SplitBounds b = split_bounds(np, kp, nblk);
     const int64_t grid = b.split_blocks > blocks ? b.split_blocks : blocks;
     k_sweep_gemm<<<(unsigned)grid, 256, 0, s>>>(ctrl, g, blocks);
+    if (mid_x3) k_sweep_x3<<<(unsigned)grid, 256, 0, s>>>(ctrl, g, blocks);
     if (b.split_blocks > 0) {
         const int64_t eg = b.epi_blocks < nblk / 2 ? b.epi_blocks : nblk / 2;
         k_sweep_split_epi<<<(unsigned)(eg > 0 ? eg : 1), 256, 0, s>>>(ctrl, g);

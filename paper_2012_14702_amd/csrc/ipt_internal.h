@@ -104,8 +104,10 @@ enum : int32_t { LT_BF16 = 0, LT_F16 = 1, LT_F32 = 2 };
 // -------------------------------------------------------------- launchers
 
 // Setup and bookkeeping (ipt_setup.hip)
+// With theta, the column part also checks theta's order (as launch_init_cols).
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
-                       int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp);
+                       int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp,
+                       const double *theta = nullptr);
 // The column part of launch_init (after a separate launch_ctrl_init): bitmap_zeroed
 // when that launch cleared the bitmap; with theta it also checks theta's order (then
 // launch_check_theta(..., order_done = true)).  With cs.alist it writes the packed
@@ -170,6 +172,14 @@ hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState
                            const double *theta_im = nullptr, const double *dvec_im = nullptr,
                            double *lam_im = nullptr);
 hipError_t launch_control(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep);
+// CSR sweep tail (plain sweeps, not IPT-ACX): the per-column sums of the SpMM's row-tile
+// partials (launch_reduce_parts), then one single-block launch for the finalize of every
+// column, d = (Delta W)_ic of the next sweep for the columns still active (W = zout, as
+// launch_diag_csr) and the control step.
+hipError_t launch_csr_tail(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, double *dvec,
+                           const double *theta, double *part, int64_t nblk, int64_t k, int64_t kpc, int32_t sweep,
+                           int32_t in_par, int32_t out_par, const int32_t *row_ptr, const int32_t *col,
+                           const double *val, const double *zout, int64_t ldz);
 // only_if_done: the kernel does nothing unless the device has set its done flag (a
 // copy-out enqueued where the solve is expected to stop, before the host knows).
 hipError_t launch_copyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
@@ -196,9 +206,9 @@ hipError_t launch_spmm_sweep(hipStream_t s, const Ctrl *ctrl, const int32_t *row
                              double *part, int64_t n, int64_t k, int64_t ldz, int64_t kpc, int32_t unit_in);
 hipError_t launch_diag_csr(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
                            const double *val, const double *zin, int64_t ldz, ColState cs, double *dvec, int64_t k);
+// CSR structure checks; with val32 the same pass writes the FP32 copy of val.
 hipError_t launch_check_csr(hipStream_t s, Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, int64_t n,
-                            int64_t nnz);
-hipError_t launch_val32(hipStream_t s, const double *val, float *val32, int64_t nnz);
+                            int64_t nnz, const double *val = nullptr, float *val32 = nullptr);
 hipError_t launch_zlo_init(hipStream_t s, const double *zb, float *zlo, int64_t ldz, const int32_t *idx, int64_t n,
                            int64_t k);
 

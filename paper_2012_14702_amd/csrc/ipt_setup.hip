@@ -67,12 +67,14 @@ __device__ inline void theta_order_flags(Ctrl *ctrl, const double *theta, int64_
             if (!(b < a)) bits |= 2;
         }
     }
-    // one atomic per wave and flag
-    const bool any_bad = __ballot(bad) != 0;
-    const int32_t wbits = (__ballot(bits & 1) ? 1 : 0) | (__ballot(bits & 2) ? 2 : 0);
-    if ((threadIdx.x & 63) == 0) {
+    // one atomic per block and flag, and none for a flag another block has already set
+    // (atomics on one word serialise: one per wave cost tens of microseconds at n = 2e5)
+    const bool any_bad = __syncthreads_or(bad) != 0;
+    const int32_t wbits = (__syncthreads_or(bits & 1) ? 1 : 0) | (__syncthreads_or(bits & 2) ? 2 : 0);
+    if (threadIdx.x == 0) {
         if (any_bad) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
-        if (wbits) atomicOr(&ctrl->theta_order, wbits);
+        if (wbits & ~__hip_atomic_load(&ctrl->theta_order, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicOr(&ctrl->theta_order, wbits);
     }
 }
 
@@ -89,9 +91,11 @@ __global__ void k_init_cols(Ctrl *ctrl, ColState cs, const int32_t *idx_user, in
         if (ii < 0 || ii >= n) {
             atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
         } else {
-            const uint32_t bit = 1u << (ii & 31);
-            const uint32_t old = atomicOr(&bitmap[ii >> 5], bit);
-            if (old & bit) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);  // duplicate index
+            if (idx_user) {  // the default columns 0 .. k-1 cannot repeat
+                const uint32_t bit = 1u << (ii & 31);
+                const uint32_t old = atomicOr(&bitmap[ii >> 5], bit);
+                if (old & bit) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);  // duplicate index
+            }
             i = (int32_t)ii;
         }
         state = COL_ACTIVE;
@@ -675,14 +679,15 @@ __device__ inline void block_atomic_max(uint64_t *p, uint64_t v) {
 // product-free first sweep) may certify a column; a certified column keeps its
 // input iterate and lambda_c = theta_i + d_c of this sweep (Alg. 1/2 return steps).
 // Block: 64 columns; thread (cx, g) sums row tiles g, g + 4, ...; wave 0 decides.
-__global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColState cs, double *dvec,
-                                                  const double *theta, const double *part, int64_t nrt, int64_t kp,
-                                                  int32_t sweep, int32_t in_par, int32_t out_par, const double *dnp,
-                                                  const double *theta_im, const double *dvec_im, double *lam_im) {
-    if (ctrl->error || ctrl->done) return;
+// The finalize of columns 64 blk .. 64 blk + 63 by one block of 256 threads (k_finalize
+// runs one such group per block; the CSR sweep tail runs all groups in its last block).
+__device__ void finalize_cols(Ctrl *ctrl, const DevOpts &o, ColState cs, double *dvec, const double *theta,
+                              const double *part, int64_t nrt, int64_t kp, int32_t sweep, int32_t in_par,
+                              int32_t out_par, const double *dnp, const double *theta_im, const double *dvec_im,
+                              double *lam_im, int64_t blk) {
     __shared__ double sh[4][NPART + 1][64];
     const int cx = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int64_t c = (int64_t)blockIdx.x * 64 + cx;
+    const int64_t c = blk * 64 + cx;
     const bool act = cs.state[c] == COL_ACTIVE;
     double p[NPART] = {0.0, 0.0, 0.0, 0.0}, dn = 0.0;
     if (act) {
@@ -699,7 +704,10 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
     for (int q = 0; q < NPART; ++q) sh[g][q][cx] = p[q];
     sh[g][NPART][cx] = dn;
     __syncthreads();
-    if (g != 0) return;
+    if (g != 0) {
+        __syncthreads();  // sh is free again for the next group once wave 0 has read it
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < NPART; ++q) p[q] = ((sh[0][q][cx] + sh[1][q][cx]) + sh[2][q][cx]) + sh[3][q][cx];
     dn = ((sh[0][NPART][cx] + sh[1][NPART][cx]) + sh[2][NPART][cx]) + sh[3][NPART][cx];
@@ -773,6 +781,50 @@ __global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColStat
     wave_count(&ctrl->n_conv, decided == COL_CONVERGED);
     wave_count(&ctrl->n_div, decided == COL_DIVERGED);
     wave_count(&ctrl->n_notconv, decided == COL_NOT_CONVERGED);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_finalize(Ctrl *ctrl, DevOpts o, ColState cs, double *dvec,
+                                                  const double *theta, const double *part, int64_t nrt, int64_t kp,
+                                                  int32_t sweep, int32_t in_par, int32_t out_par, const double *dnp,
+                                                  const double *theta_im, const double *dvec_im, double *lam_im) {
+    if (ctrl->error || ctrl->done) return;
+    finalize_cols(ctrl, o, cs, dvec, theta, part, nrt, kp, sweep, in_par, out_par, dnp, theta_im, dvec_im, lam_im,
+                  blockIdx.x);
+}
+
+__device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep);
+
+// CSR sweep tail (plain sweeps), one block, after the per-column sums of the SpMM's
+// row-tile partials: the finalize of every column, the next sweep's d for the columns
+// still active (one wave per column, as k_diag_csr, on this sweep's output) and the
+// control step.  One launch instead of three; the work itself is a few microseconds.
+__global__ __launch_bounds__(256) void k_csr_tail(Ctrl *ctrl, DevOpts o, ColState cs, double *dvec,
+                                                  const double *theta, const double *part, int64_t kpc,
+                                                  int32_t sweep, int32_t in_par, int32_t out_par,
+                                                  const int32_t *row_ptr, const int32_t *col, const double *val,
+                                                  const double *zout, int64_t ldz, int64_t k) {
+    if (ctrl->error || ctrl->done) return;
+    for (int64_t blk = 0; blk < kpc / 64; ++blk)
+        finalize_cols(ctrl, o, cs, dvec, theta, part, 1, kpc, sweep, in_par, out_par, nullptr, nullptr, nullptr,
+                      nullptr, blk);
+    // the column states were written by this block before the finalize's last barrier
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t cc = wv; cc < k; cc += 4) {
+        if (cs.state[cc] != COL_ACTIVE) continue;  // the same for the whole wave
+        const int32_t i = cs.idx[cc];
+        double a2 = 0.0;
+        for (int32_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += 64) a2 += val[p] * zout[(int64_t)col[p] * ldz + cc];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a2 += __shfl_xor(a2, off);
+        if (lane == 0) dvec[cc] = a2;
+    }
+    if (threadIdx.x == 0) {
+        // the finalize's counters were accumulated with device-scope atomics: drop any
+        // copy of the control block this compute unit's cache still holds
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        control_step(ctrl, o, sweep);
+    }
 }
 
 // The active columns in ascending order: the packed column positions of the next
@@ -816,7 +868,6 @@ __global__ __launch_bounds__(1024) void k_plan_dense(Ctrl *ctrl, ColState cs, in
 // Bookkeeping after sweep t and the precision of sweep t+1 (the ladder): leave the
 // low rung when the max step is <= tau_low or stops falling, leave FP32 when it is
 // <= tau_32 or stops falling; FP64 is final.
-__device__ void control_step(Ctrl *ctrl, const DevOpts &o, int32_t sweep);
 
 __global__ void k_control(Ctrl *ctrl, DevOpts o, int32_t sweep) {
     if (ctrl->error || ctrl->done) return;
@@ -1030,9 +1081,10 @@ inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) /
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
-                       int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp) {
+                       int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp,
+                       const double *theta) {
     k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k, 0, 0.0, bitmap, (n + 31) / 32);
-    return launch_init_cols(s, ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp, true);
+    return launch_init_cols(s, ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp, true, theta);
 }
 
 hipError_t launch_init_cols(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
@@ -1042,7 +1094,8 @@ hipError_t launch_init_cols(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_
     if (!bitmap_zeroed)
         k_fill_u32<<<blocks_for(words, 256) < 1024 ? blocks_for(words, 256) : 1024, 256, 0, s>>>(bitmap, words, 0u);
     int64_t m = kp > ntiles_n ? kp : ntiles_n;
-    if (theta && m < n) m = n < 65536 ? n : 65536;  // theta's order check strides over the grid
+    // theta's order check strides over the grid: one element per thread up to n = 2^20
+    if (theta && m < n) m = n < (int64_t(1) << 20) ? n : (int64_t(1) << 20);
     k_init_cols<<<blocks_for(m, 256), 256, 0, s>>>(ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp,
                                                    theta);
     return hipGetLastError();
@@ -1189,6 +1242,16 @@ hipError_t launch_finalize(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState
 
 hipError_t launch_control_plan(hipStream_t s, Ctrl *ctrl, const DevOpts &o, int32_t sweep, ColState cs, int64_t kp) {
     k_control_plan<<<1, 1024, 0, s>>>(ctrl, o, sweep, cs, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_tail(hipStream_t s, Ctrl *ctrl, const DevOpts &o, ColState cs, double *dvec,
+                           const double *theta, double *part, int64_t nblk, int64_t k, int64_t kpc, int32_t sweep,
+                           int32_t in_par, int32_t out_par, const int32_t *row_ptr, const int32_t *col,
+                           const double *val, const double *zout, int64_t ldz) {
+    if (hipError_t e = launch_reduce_parts(s, ctrl, cs, part, nblk, k, kpc)) return e;
+    k_csr_tail<<<1, 256, 0, s>>>(ctrl, o, cs, dvec, theta, part, kpc, sweep, in_par, out_par, row_ptr, col, val, zout,
+                                 ldz, k);
     return hipGetLastError();
 }
 

@@ -297,19 +297,18 @@ __global__ void k_diag_csr(const Ctrl *ctrl, const int32_t *row_ptr, const int32
 }
 
 // CSR structure checks: row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, and
-// every column index in [0, n).
-__global__ void k_check_csr(Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz) {
+// every column index in [0, n).  With val32, the FP32 copy of val in the same pass.
+__global__ void k_check_csr(Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
+                            const double *val, float *val32) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     bool bad = false;
     if (t == 0) bad |= row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz;
     if (t < n) bad |= row_ptr[t + 1] < row_ptr[t];
-    for (int64_t p = t; p < nnz; p += (int64_t)gridDim.x * blockDim.x) bad |= col[p] < 0 || (int64_t)col[p] >= n;
+    for (int64_t p = t; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+        bad |= col[p] < 0 || (int64_t)col[p] >= n;
+        if (val32) val32[p] = (float)val[p];
+    }
     if (bad) atomicMax(&ctrl->error, (int32_t)IPT_EINVAL);
-}
-
-__global__ void k_val32(const double *val, float *val32, int64_t nnz) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
-        val32[p] = (float)val[p];
 }
 
 // FP32 shadow of Z0 - E for a warm start (zero elsewhere).
@@ -355,19 +354,11 @@ hipError_t launch_diag_csr(hipStream_t s, const Ctrl *ctrl, const int32_t *row_p
 }
 
 hipError_t launch_check_csr(hipStream_t s, Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, int64_t n,
-                            int64_t nnz) {
+                            int64_t nnz, const double *val, float *val32) {
     int b = blocks_for(n + 1 > nnz ? n + 1 : nnz, 256);
     if (b > 4096) b = 4096;
     if (b < blocks_for(n, 256)) b = blocks_for(n, 256);
-    k_check_csr<<<b, 256, 0, s>>>(ctrl, row_ptr, col, n, nnz);
-    return hipGetLastError();
-}
-
-hipError_t launch_val32(hipStream_t s, const double *val, float *val32, int64_t nnz) {
-    int b = blocks_for(nnz, 256);
-    if (b > 4096) b = 4096;
-    if (b < 1) b = 1;
-    k_val32<<<b, 256, 0, s>>>(val, val32, nnz);
+    k_check_csr<<<b, 256, 0, s>>>(ctrl, row_ptr, col, n, nnz, val, val32);
     return hipGetLastError();
 }
 
