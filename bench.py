@@ -254,7 +254,25 @@ def bench_sparse(ipt, handle, args):
                      "spmm_fp64_GBps": round(per / (ms / max(nl, 1) * 1e-3) / 1e9, 1) if nl else None,
                      "spmm_fp64_frac_of_hbm": round(per / (ms / max(nl, 1) * 1e-3) / 1e9 / HBM_PEAK, 4) if nl else None}
         log("sparse %s: %.3f ms/solve, sweeps %s" % (name, sec * 1e3, inf["sweep_prec"]))
-    return {"workload": "sparse n=200000, ~12 sym off-diagonals/row U(-0.05,0.05), k=16 lowest, tol 1e-10",
+    # the same matrix over C^n: imaginary parts sign(l - j) val / 2 on the off-diagonal
+    # entries (a Hermitian perturbation), the complex CSR solve (FP64 sweeps)
+    if not args.sparse_modes or "complex" in args.sparse_modes.split(","):
+        import numpy as np
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        valz = val + 0.5j * np.sign(col - rows) * val
+        thz, valzd = T(th.astype(np.complex128)), T(valz.astype(np.complex128))
+        o = ipt.default_opts(tol=1e-10, precision=ipt.PREC_FP64, flags=ipt.FLAG_NO_NORM)
+        run = lambda: ipt.ipt_solve_csr_z(thz, rpd, cold, valzd, idx, opts=o, handle=handle, colinfo=False)
+        _time(run, 3)
+        sec, r = _time(run, max(5, args.steps))
+        inf = r.info
+        res["complex_fp64"] = {"eigenpairs_per_s": round(int(inf["converged"]) / sec, 1),
+                               "ms_per_solve": round(sec * 1e3, 4), "converged": inf["converged"],
+                               "sweeps": inf["sweeps"], "sweep_prec": inf["sweep_prec"]}
+        log("sparse complex_fp64: %.3f ms/solve, %d converged, sweeps %s" % (sec * 1e3, int(inf["converged"]),
+                                                                             inf["sweep_prec"]))
+    return {"workload": "sparse n=200000, ~12 sym off-diagonals/row U(-0.05,0.05), k=16 lowest, tol 1e-10; "
+                        "complex_fp64: the same pattern with imaginary parts sign(l - j) val / 2 (Hermitian)",
             "nnz": nnz, "modes": res}
 
 

@@ -289,6 +289,27 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
                          int32_t *col_status, ipt_info *info, const ipt_colinfo *ci);
 
 /*
+ * Sparse solve over C^n (Sec. 2 states IPT for complex M; Sec. 6.1 is the use case of
+ * a few eigenpairs of a large sparse near-diagonal M): Delta in CSR form with complex
+ * entries, the same map, stopping test and lambda = theta_i + (Delta z)_i as
+ * ipt_solve_dense_z.
+ *   theta      [n] complex, finite
+ *   row_ptr, col, nnz   as for ipt_solve_csr (duplicate entries are summed)
+ *   val        [nnz] complex
+ *   z0, z_out, lambda_out, ldz0, ldz   complex, as for ipt_solve_dense_z
+ * Complex numbers are (re, im) pairs of doubles; theta, val, z0, z_out and lambda_out
+ * must be 16-byte aligned.  |M|_1 (unless IPT_FLAG_NO_NORM) and the eigen-residual use
+ * the modulus.  Sweeps are FP64 (the first sweep of a cold start needs no product):
+ * opts.precision must be IPT_PREC_FP64, and IPT_FLAG_ACX, IPT_FLAG_CHOOSE_D,
+ * opts.cont_alpha and opts.homotopy_q > 1 are rejected with IPT_EINVAL.
+ * IPT_EDEGENERATE when theta_j == theta_i (both parts) for a requested i and j != i.
+ */
+ipt_status ipt_solve_csr_z(ipt_handle h, int64_t n, const double *theta, const int32_t *row_ptr, const int32_t *col,
+                           const double *val, int64_t nnz, int64_t k, const int32_t *idx, const double *z0,
+                           int64_t ldz0, const ipt_opts *opts, double *z_out, int64_t ldz, double *lambda_out,
+                           int32_t *col_status, ipt_info *info, const ipt_colinfo *ci);
+
+/*
  * Batched full-spectrum solve of `count` independent dense problems of uneven size
  * (Alg. 2 applied to each M_b = D_b + Delta_b; the columns of all problems are
  * independent, so one sweep advances every active column of the batch).

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libipt.so")
 SOURCES = ["ipt_api.hip", "ipt_setup.hip", "ipt_gemm.hip", "ipt_spmm.hip", "ipt_batched.hip", "ipt_mlp.hip",
-           "ipt_acx.hip", "ipt_pairs.hip", "ipt_complex.hip", "ipt_rs.hip"]
+           "ipt_acx.hip", "ipt_pairs.hip", "ipt_complex.hip", "ipt_zcsr.hip", "ipt_rs.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          # packed FP32 instructions are kept out of every kernel

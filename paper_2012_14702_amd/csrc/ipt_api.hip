@@ -1166,6 +1166,114 @@ ipt_status ipt_solve_dense_z(ipt_handle h, int64_t n, const double *theta, const
     return finish(h, ctrl, k, info, &timer, "complex", nullptr);
 }
 
+ipt_status ipt_solve_csr_z(ipt_handle h, int64_t n, const double *theta, const int32_t *row_ptr, const int32_t *col,
+                           const double *val, int64_t nnz, int64_t k, const int32_t *idx, const double *z0,
+                           int64_t ldz0, const ipt_opts *opts, double *z_out, int64_t ldz, double *lambda_out,
+                           int32_t *col_status, ipt_info *info, const ipt_colinfo *ci) {
+    if (!h) return IPT_EINVAL;
+    h->last_error.clear();
+    if (n < 1 || n > (int64_t(1) << 30)) return fail(h, IPT_EINVAL, "n must be in [1, 2^30]");
+    if (k < 1 || k > n) return fail(h, IPT_EINVAL, "k must be in [1, n]");
+    if (nnz < 0 || nnz > INT32_MAX) return fail(h, IPT_EINVAL, "nnz must be in [0, 2^31)");
+    if (ldz < k) return fail(h, IPT_EINVAL, "ldz must be >= k");
+    if (z0 && ldz0 < k) return fail(h, IPT_EINVAL, "ldz0 must be >= k");
+    if (!theta || !row_ptr || (nnz > 0 && (!col || !val)) || !z_out || !lambda_out || !col_status)
+        return fail(h, IPT_EINVAL, "theta, row_ptr, col, val, z_out, lambda_out and col_status must be non-NULL");
+    if ((((uintptr_t)theta | (uintptr_t)val | (uintptr_t)z_out | (uintptr_t)lambda_out | (uintptr_t)z0) & 15) != 0)
+        return fail(h, IPT_EINVAL, "complex arrays must be 16-byte aligned");
+    ipt_opts o;
+    if (ipt_status st = check_opts(h, opts, o)) return st;
+    if (o.precision != IPT_PREC_FP64 || (o.flags & (IPT_FLAG_ACX | IPT_FLAG_CHOOSE_D)) || o.cont_alpha > 0.0 ||
+        o.homotopy_q > 1)
+        return fail(h, IPT_EINVAL,
+                    "complex solves run plain FP64 sweeps (no ladder, ACX, choice of D, continuation or homotopy)");
+    const DevOpts dopt = dev_opts(o);
+    const bool cold = (z0 == nullptr);
+    const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
+    DeviceGuard guard(h->device);
+    hipStream_t s = h->stream;
+
+    const int64_t kpc = round_up(k, 64);  // column-state and partial-sum layout
+    const int64_t ldzb = k;               // Z buffers: n x k complex
+    const int64_t nrb = zspmm_row_blocks(n);
+    auto layout = [&](Carve &cv, double **zb, ColState &cs, double **d_re, double **d_im, double **lam_im,
+                      double **th_re, double **th_im, double **part, uint32_t **bitmap, double **scratch,
+                      Ctrl **ctrl) {
+        zb[0] = cv.take<double>(2 * n * ldzb);
+        zb[1] = cv.take<double>(2 * n * ldzb);
+        *d_re = cv.take<double>(kpc);
+        *d_im = cv.take<double>(kpc);
+        *lam_im = cv.take<double>(kpc);
+        *th_re = cv.take<double>(n);
+        *th_im = cv.take<double>(n);
+        *part = cv.take<double>(nrb * kpc * NPART);
+        cs.state = cv.take<int32_t>(kpc);
+        cs.sweeps = cv.take<int32_t>(kpc);
+        cs.grow = cv.take<int32_t>(kpc);
+        cs.par = cv.take<int32_t>(kpc);
+        cs.idx = cv.take<int32_t>(kpc);
+        cs.tile_stamp = cv.take<int32_t>(kpc / TILE_N + 1);
+        cs.alist = nullptr;
+        cs.prev = cv.take<double>(kpc);
+        cs.step = cv.take<double>(kpc);
+        cs.lam = cv.take<double>(kpc);
+        cs.resid = cv.take<double>(kpc);
+        *bitmap = cv.take<uint32_t>((n + 31) / 32);
+        *scratch = norm ? cv.take<double>(norm1_csr_scratch_doubles(n)) : nullptr;
+        *ctrl = cv.take<Ctrl>(1);
+    };
+    double *zb[2], *d_re, *d_im, *lam_im, *th_re, *th_im, *part, *scratch;
+    ColState cs;
+    uint32_t *bitmap;
+    Ctrl *ctrl;
+    Carve sizing = carve(h, nullptr);
+    layout(sizing, zb, cs, &d_re, &d_im, &lam_im, &th_re, &th_im, &part, &bitmap, &scratch, &ctrl);
+    if (ipt_status st = ensure_ws(h, sizing.off + 256)) return st;
+    Carve cv = carve(h, (char *)h->ws);
+    layout(cv, zb, cs, &d_re, &d_im, &lam_im, &th_re, &th_im, &part, &bitmap, &scratch, &ctrl);
+    if (ipt_status st = guard_arm(h, cv)) return st;
+
+    Timer timer{h, (o.flags & IPT_FLAG_TIME_KERNELS) != 0, o.max_iter};
+    IPT_HIP(h, timer.ensure());
+    IPT_HIP(h, hipEventRecord(h->ev_start, s));
+    // A cold start's first sweep multiplies Delta by E, which is exact, so it may certify.
+    IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kpc, bitmap, cold ? PREC_EXACT_FIRST : PREC_F64,
+                           (int32_t)(kpc / TILE_N + 1), 0));
+    IPT_HIP(h, launch_zsetup(s, ctrl, theta, nullptr, 0, th_re, th_im, nullptr, n));  // theta's parts, finiteness
+    IPT_HIP(h, launch_zcheck_gaps(s, ctrl, th_re, th_im, cs.idx, n, k));
+    IPT_HIP(h, launch_check_csr(s, ctrl, row_ptr, col, n, nnz));
+    if (norm) IPT_HIP(h, launch_norm1_csr(s, ctrl, th_re, row_ptr, col, val, n, nnz, scratch, th_im));
+    // a cold start's first sweep reads no iterate (Z = E: the product-free sweep)
+    if (!cold) IPT_HIP(h, launch_zload(s, ctrl, z0, ldz0, zb[0], ldzb, cs.idx, n, n, k));
+
+    PollPlan plan = poll_plan(o, cold);
+    if (o.sync_every <= 0) plan.first = cold ? 3 : 2;  // sparse near-diagonal solves take few sweeps
+    if (ipt_status st = ensure_poll(h)) return st;
+    LookaheadPoll poll{h, ctrl};
+    for (int32_t t = 1; t <= o.max_iter; ++t) {
+        const bool unit = cold && t == 1;
+        const int32_t in_par = unit ? PAR_UNIT : ((t - 1) & 1), out_par = t & 1;
+        const double *zin = zb[(t - 1) & 1];
+        double *zout = zb[t & 1];
+        if (!unit) IPT_HIP(h, launch_zdiag_csr(s, ctrl, row_ptr, col, val, zin, ldzb, cs, d_re, d_im, k));
+        IPT_HIP(h, timer.mark(t, 0, s));
+        IPT_HIP(h, launch_zspmm_sweep(s, ctrl, row_ptr, col, val, th_re, th_im, zin, zout, cs, d_re, d_im, part, n,
+                                      k, ldzb, unit ? 1 : 0));
+        IPT_HIP(h, timer.mark(t, 1, s));
+        IPT_HIP(h, launch_reduce_parts(s, ctrl, cs, part, nrb, k, kpc));
+        IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, d_re, th_re, part, 1, kpc, t, in_par, out_par, nullptr, th_im,
+                                   d_im, lam_im));
+        IPT_HIP(h, launch_control(s, ctrl, dopt, t));
+        if (plan.at(t, o.max_iter)) {
+            bool stop;
+            if (ipt_status st = poll.push(stop)) return st;
+            if (stop) break;
+        }
+    }
+    IPT_HIP(h, launch_zcopyout(s, ctrl, cs, zb[0], zb[1], ldzb, z_out, ldz, lam_im, lambda_out, col_status, n, k, ci));
+    return finish(h, ctrl, k, info, &timer, "csr_z", nullptr);
+}
+
 ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int32_t *row_ptr, const int32_t *col,
                          const double *val, int64_t nnz, int64_t k, const int32_t *idx, const double *z0, int64_t ldz0,
                          const ipt_opts *opts, double *z_out, int64_t ldz, double *lambda_out, int32_t *col_status,

@@ -146,10 +146,12 @@ hipError_t launch_prep_delta(hipStream_t s, Ctrl *ctrl, const double *theta, con
                              uint64_t *bmax);
 int64_t prep_delta_chunks(int64_t np);
 int64_t prep_delta_blocks(int64_t np);
-// scratch: norm1_csr_scratch_doubles(n) doubles
+// scratch: norm1_csr_scratch_doubles(n) doubles.  With theta_im, the matrix is complex:
+// theta is its real part and val holds nnz (re, im) pairs.
 int64_t norm1_csr_scratch_doubles(int64_t n);
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
-                            const int32_t *col, const double *val, int64_t n, int64_t nnz, double *scratch);
+                            const int32_t *col, const double *val, int64_t n, int64_t nnz, double *scratch,
+                            const double *theta_im = nullptr);
 // set_zscale: also the power-of-two scale of the FP16 shadow of Z - E from max |Z - E|
 // (a warm-started ladder whose first sweep is on an FP16-shadowed rung).
 hipError_t launch_load_z0(hipStream_t s, Ctrl *ctrl, const double *z0, int64_t ldz0, double *zb, int64_t ldzb,
@@ -443,5 +445,19 @@ hipError_t launch_zsweep(hipStream_t s, const Ctrl *ctrl, const double *delta, i
 hipError_t launch_zcopyout(hipStream_t s, const Ctrl *ctrl, ColState cs, const double *buf0, const double *buf1,
                            int64_t kp, double *z_out, int64_t ldz, const double *lam_im, double *lambda_out,
                            int32_t *status_out, int64_t n, int64_t k, const ipt_colinfo *ci);
+
+// ------------------------------------------------------ complex CSR (ipt_zcsr.hip)
+// Sparse IPT over C^n: val holds nnz (re, im) pairs; Z buffers are n x ldz complex.
+// The sweep writes per-row-block partial sums part[block][k][NPART] (reduced by
+// launch_reduce_parts with ldp = k); unit_in: the product-free first sweep of a cold
+// start, which also writes d_c = Delta_ii.
+int64_t zspmm_row_blocks(int64_t n);
+hipError_t launch_zspmm_sweep(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
+                              const double *val, const double *th_re, const double *th_im, const double *zin,
+                              double *zout, ColState cs, double *d_re, double *d_im, double *part, int64_t n,
+                              int64_t k, int64_t ldz, int32_t unit_in);
+hipError_t launch_zdiag_csr(hipStream_t s, const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col,
+                            const double *val, const double *zin, int64_t ldz, ColState cs, double *d_re,
+                            double *d_im, int64_t k);
 
 }  // namespace ipt

@@ -284,14 +284,22 @@ __global__ void k_norm1_reduce(Ctrl *ctrl, const double *colpart, int64_t n, int
 //   k_csr_colsum   : one 64-bit integer atomic add per off-diagonal entry,
 //   k_norm1_csr_reduce: per column, the sum / scale + |theta_j + Delta_jj| (the diagonal
 //                    entries of row j, in storage order), maximum over columns.
+// Complex entries (cplx: val holds (re, im) pairs, theta_im the imaginary parts of
+// theta) enter by their modulus.
 constexpr int CSR_SUM_BLOCKS = 1024;
+__device__ inline double csr_abs(const double *val, int64_t p, int32_t cplx) {
+    if (!cplx) return fabs(val[p]);
+    const double re = val[2 * p], im = val[2 * p + 1];
+    return sqrt(re * re + im * im);
+}
+
 __global__ __launch_bounds__(256) void k_csr_abs_sum(const Ctrl *ctrl, const double *val, int64_t nnz,
-                                                     uint64_t *acc, int64_t n, double *part) {
+                                                     uint64_t *acc, int64_t n, double *part, int32_t cplx) {
     if (ctrl->error) return;
     __shared__ double sh[256];
     double a = 0.0;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
-        a += fabs(val[p]);
+        a += csr_abs(val, p, cplx);
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
         acc[j] = 0;
     sh[threadIdx.x] = a;
@@ -321,7 +329,7 @@ __global__ __launch_bounds__(256) void k_csr_abs_scale(const Ctrl *ctrl, const d
 }
 
 __global__ void k_csr_colsum(const Ctrl *ctrl, const int32_t *row_ptr, const int32_t *col, const double *val,
-                             int64_t n, const double *scale, uint64_t *acc) {
+                             int64_t n, const double *scale, uint64_t *acc, int32_t cplx) {
     if (ctrl->error) return;  // the structure checks ran first; never walk a malformed matrix
     const double sc = *scale;
     if (!(sc > 0.0)) return;
@@ -330,23 +338,28 @@ __global__ void k_csr_colsum(const Ctrl *ctrl, const int32_t *row_ptr, const int
     for (int32_t p = row_ptr[j]; p < row_ptr[j + 1]; ++p) {
         const int32_t c = col[p];
         if (c != j)
-            atomicAdd((unsigned long long *)&acc[c], (unsigned long long)llrint(fabs(val[p]) * sc));
+            atomicAdd((unsigned long long *)&acc[c], (unsigned long long)llrint(csr_abs(val, p, cplx) * sc));
     }
 }
 
 // Block: grid-stride over columns, one atomic max per block.
 __global__ __launch_bounds__(256) void k_norm1_csr_reduce(Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
                                                           const int32_t *col, const double *val, const uint64_t *acc,
-                                                          const double *scale, int64_t n) {
+                                                          const double *scale, int64_t n, const double *theta_im) {
     if (ctrl->error) return;
     const double sc = *scale;
+    const int32_t cplx = theta_im != nullptr;
     uint64_t m = 0;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        double dg = 0.0;
+        double dg = 0.0, dgi = 0.0;
         for (int32_t p = row_ptr[c]; p < row_ptr[c + 1]; ++p)
-            if (col[p] == c) dg += val[p];
+            if (col[p] == c) {
+                dg += cplx ? val[2 * p] : val[p];
+                if (cplx) dgi += val[2 * p + 1];
+            }
         const double off = sc > 0.0 ? (double)acc[c] / sc : NAN;  // NaN (reported as +inf) for a non-finite Delta
-        const uint64_t b = dbits(off + fabs(theta[c] + dg));
+        const double dre = theta[c] + dg, dim = cplx ? theta_im[c] + dgi : 0.0;
+        const uint64_t b = dbits(off + (cplx ? sqrt(dre * dre + dim * dim) : fabs(dre)));
         m = b > m ? b : m;
     }
     block_atomic_max(&ctrl->norm1_bits, m);
@@ -1184,17 +1197,19 @@ hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count) {
 int64_t norm1_csr_scratch_doubles(int64_t n) { return n + CSR_SUM_BLOCKS + 2; }
 
 hipError_t launch_norm1_csr(hipStream_t s, Ctrl *ctrl, const double *theta, const int32_t *row_ptr,
-                            const int32_t *col, const double *val, int64_t n, int64_t nnz, double *scratch) {
+                            const int32_t *col, const double *val, int64_t n, int64_t nnz, double *scratch,
+                            const double *theta_im) {
+    const int32_t cplx = theta_im != nullptr;
     uint64_t *acc = (uint64_t *)scratch;
     double *part = scratch + n, *scale = part + CSR_SUM_BLOCKS;
     const int64_t work = nnz > n ? nnz : n;
     int nb = blocks_for(work, 256);
     nb = nb < 1 ? 1 : (nb > CSR_SUM_BLOCKS ? CSR_SUM_BLOCKS : nb);
-    k_csr_abs_sum<<<nb, 256, 0, s>>>(ctrl, val, nnz, acc, n, part);
+    k_csr_abs_sum<<<nb, 256, 0, s>>>(ctrl, val, nnz, acc, n, part, cplx);
     k_csr_abs_scale<<<1, 256, 0, s>>>(ctrl, part, nb, scale);
-    k_csr_colsum<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, row_ptr, col, val, n, scale, acc);
+    k_csr_colsum<<<blocks_for(n, 256), 256, 0, s>>>(ctrl, row_ptr, col, val, n, scale, acc, cplx);
     k_norm1_csr_reduce<<<blocks_for(n, 256) < 512 ? blocks_for(n, 256) : 512, 256, 0, s>>>(ctrl, theta, row_ptr, col,
-                                                                                         val, acc, scale, n);
+                                                                                         val, acc, scale, n, theta_im);
     return hipGetLastError();
 }
 

@@ -112,6 +112,7 @@ def load_library():
                                     C.POINTER(Info), C.POINTER(ColInfo)]
     lib.ipt_solve_csr.argtypes = [p, i64, p, p, p, p, i64, i64, p, p, i64, C.POINTER(Opts), p, i64, p, p,
                                   C.POINTER(Info), C.POINTER(ColInfo)]
+    lib.ipt_solve_csr_z.argtypes = lib.ipt_solve_csr.argtypes
     lib.ipt_solve_batched.argtypes = [p, i32, p, p, p, p, p, p, C.POINTER(Opts), p, p, p, C.POINTER(Info)]
     lib.ipt_batched_tune.argtypes = [p, i32, p, p, p, p, p, p, p, p, p, p]
     lib.ipt_batched_get_tiles.argtypes = [p, p]
@@ -121,7 +122,7 @@ def load_library():
     lib.ipt_last_error.argtypes = [p]
     lib.ipt_last_error.restype = C.c_char_p
     for fn in ("ipt_create", "ipt_destroy", "ipt_set_stream", "ipt_solve_dense", "ipt_solve_dense_noalloc",
-               "ipt_solve_dense_z", "ipt_solve_csr",
+               "ipt_solve_dense_z", "ipt_solve_csr", "ipt_solve_csr_z",
                "ipt_solve_batched", "ipt_batched_tune", "ipt_batched_get_tiles", "ipt_batched_set_tiles"):
         getattr(lib, fn).restype = C.c_int
     _lib = lib
@@ -342,6 +343,34 @@ def ipt_solve_csr(theta, row_ptr, col, val, idx, z0=None, opts=None, handle=None
     st = lib.ipt_solve_csr(h.ptr, n, _ptr(theta), _ptr(row_ptr), _ptr(col), _ptr(val), val.shape[0], k, _ptr(idx),
                            _ptr(z0), z0.stride(0) if z0 is not None else 0, C.byref(o), _ptr(z), z.stride(0),
                            _ptr(lam), _ptr(status), C.byref(info), C.byref(ci) if ci is not None else None)
+    return _finish(lib, h, st, z, lam, status, info, extra)
+
+
+def ipt_solve_csr_z(theta, row_ptr, col, val, idx, z0=None, opts=None, handle=None, colinfo=True, **kw):
+    """Sparse IPT over C^n (ipt_solve_csr_z): theta [n] and val [nnz] complex128, int32
+    row_ptr / col, requested columns idx [k] int32, optional warm start z0 [n, k]
+    complex128.  Returns a Result with z [n, k] and lam [k] complex128."""
+    import torch
+    lib = load_library()
+    h = _handle(handle)
+    _check(theta, torch.complex128, "theta")
+    _check(row_ptr, torch.int32, "row_ptr")
+    _check(col, torch.int32, "col")
+    _check(val, torch.complex128, "val")
+    _check(idx, torch.int32, "idx")
+    _check(z0, torch.complex128, "z0")
+    n = theta.shape[0]
+    k = idx.shape[0]
+    dev = theta.device
+    z = torch.empty((n, k), dtype=torch.complex128, device=dev)
+    lam = torch.empty(k, dtype=torch.complex128, device=dev)
+    status = torch.empty(k, dtype=torch.int32, device=dev)
+    o = _opts(opts, kw)
+    info = Info()
+    ci, extra = _colinfo(k, colinfo)
+    st = lib.ipt_solve_csr_z(h.ptr, n, _ptr(theta), _ptr(row_ptr), _ptr(col), _ptr(val), val.shape[0], k, _ptr(idx),
+                             _ptr(z0), z0.stride(0) if z0 is not None else 0, C.byref(o), _ptr(z), z.stride(0),
+                             _ptr(lam), _ptr(status), C.byref(info), C.byref(ci) if ci is not None else None)
     return _finish(lib, h, st, z, lam, status, info, extra)
 
 

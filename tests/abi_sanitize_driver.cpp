@@ -70,6 +70,8 @@ static void no_device_calls() {
            IPT_EINVAL);
     EXPECT(ipt_solve_csr(nullptr, 1, &x, &i, &i, &x, 0, 1, &i, nullptr, 0, nullptr, &x, 1, &x, &i, nullptr,
                          nullptr) == IPT_EINVAL);
+    EXPECT(ipt_solve_csr_z(nullptr, 1, &x, &i, &i, &x, 0, 1, &i, nullptr, 0, nullptr, &x, 1, &x, &i, nullptr,
+                           nullptr) == IPT_EINVAL);
     EXPECT(ipt_solve_batched(nullptr, 1, &i, nullptr, nullptr, nullptr, &x, &x, nullptr, &x, &x, &i, nullptr) ==
            IPT_EINVAL);
     EXPECT(ipt_mlp_destroy(nullptr) == IPT_EINVAL);
@@ -203,6 +205,30 @@ static void gpu_calls() {
             oc.precision = prec;
             EXPECT(ipt_solve_csr(h, m, dths, drp, dcol, dval, (int64_t)col.size(), kk, didx, nullptr, 0, &oc, dz2, kk,
                                  dl2, dst2, &info, nullptr) == IPT_OK);
+        }
+        // the same pattern over C^n: imaginary parts on the off-diagonal pairs (Hermitian)
+        {
+            std::vector<double> valz(2 * val.size()), thz(2 * m);
+            for (int64_t j = 0; j < m; ++j) {
+                thz[2 * j] = ths[j];
+                thz[2 * j + 1] = 0.0;
+                for (int32_t p = rp[j]; p < rp[j + 1]; ++p) {
+                    valz[2 * p] = val[p];
+                    valz[2 * p + 1] = (col[p] > j ? 0.01 : -0.01) * val[p];
+                }
+            }
+            double *dvz = dev_copy(valz), *dtz = dev_copy(thz), *dzz = dev_alloc<double>(2 * m * kk),
+                   *dlz = dev_alloc<double>(2 * kk);
+            EXPECT(ipt_solve_csr_z(h, m, dtz, drp, dcol, dvz, (int64_t)col.size(), kk, didx, nullptr, 0, &o, dzz, kk,
+                                   dlz, dst2, &info, nullptr) == IPT_OK);
+            ipt_opts ol = o;
+            ol.precision = IPT_PREC_LADDER;
+            EXPECT(ipt_solve_csr_z(h, m, dtz, drp, dcol, dvz, (int64_t)col.size(), kk, didx, nullptr, 0, &ol, dzz, kk,
+                                   dlz, dst2, &info, nullptr) == IPT_EINVAL);
+            (void)hipFree(dvz);
+            (void)hipFree(dtz);
+            (void)hipFree(dzz);
+            (void)hipFree(dlz);
         }
         (void)hipFree(drp);
         (void)hipFree(dcol);
