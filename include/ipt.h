@@ -101,8 +101,8 @@ typedef struct ipt_opts {
                          * the non-finite and div_norm rules (on the scaled iterate) end a
                          * column, and the growth rule restarts.  It moves the start e_i
                          * (or z0) along with the fixed point as the perturbation grows.
-                         * Dense solves with precision = IPT_PREC_FP64 and without
-                         * IPT_FLAG_ACX only; elsewhere IPT_EINVAL */
+                         * Real dense and CSR solves with precision = IPT_PREC_FP64 and
+                         * without IPT_FLAG_ACX only; elsewhere IPT_EINVAL */
     int32_t homotopy_q; /* 0 or 1 (default): one solve.  Q > 1 (at most 1000): the homotopy
                          * restart of the concluding section, dense solves only: stages
                          * q = 1..Q solve the partition D + (q/Q) Delta (each entry times the

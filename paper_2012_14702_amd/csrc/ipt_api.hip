@@ -1289,7 +1289,6 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         return fail(h, IPT_EINVAL, "theta, row_ptr, col, val, z_out, lambda_out and col_status must be non-NULL");
     ipt_opts o;
     if (ipt_status st = check_opts(h, opts, o)) return st;
-    if (o.cont_alpha > 0.0) return fail(h, IPT_EINVAL, "opts.cont_alpha: continuation is for dense solves");
     if (o.homotopy_q > 1) return fail(h, IPT_EINVAL, "opts.homotopy_q: the homotopy restart is for dense solves");
     DevOpts dopt = dev_opts(o);
     dopt.low_type = IPT_LOW_NONE;  // the sparse ladder runs FP32 then FP64 sweeps
@@ -1297,6 +1296,7 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     const bool ladder = dopt.ladder;
     const bool cold = (z0 == nullptr);
     const bool norm = !(o.flags & IPT_FLAG_NO_NORM);
+    const bool cont = o.cont_alpha > 0.0;  // FP64 sweeps, no ACX (check_opts)
     DeviceGuard guard(h->device);
     hipStream_t s = h->stream;
 
@@ -1353,7 +1353,8 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
     // A cold start's first sweep multiplies Delta by E, which is exact in every
     // precision (the low-precision part Z - E is zero), so it may certify.
     const int32_t start_prec = cold ? PREC_EXACT_FIRST : (ladder ? PREC_F32 : PREC_F64);
-    IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kpc, bitmap, start_prec, (int32_t)(kpc / TILE_N + 1), 0, theta));
+    IPT_HIP(h, launch_init(s, ctrl, cs, idx, n, k, kpc, bitmap, start_prec, (int32_t)(kpc / TILE_N + 1), 0, theta,
+                           o.cont_alpha));
     IPT_HIP(h, launch_check_theta(s, ctrl, theta, cs.idx, n, k, true));
     IPT_HIP(h, launch_check_csr(s, ctrl, row_ptr, col, n, nnz, val, val32));
     if (norm) IPT_HIP(h, launch_norm1_csr(s, ctrl, theta, row_ptr, col, val, n, nnz, scratch));
@@ -1379,13 +1380,16 @@ ipt_status ipt_solve_csr(ipt_handle h, int64_t n, const double *theta, const int
         const int32_t in_par = acx ? PAR_BUF0 : (unit ? PAR_UNIT : ((t - 1) & 1)), out_par = acx ? PAR_BUF1 : (t & 1);
         double *zin = acx ? zb[q] : zb[(t - 1) & 1], *zout = acx ? zb[q + 1] : zb[t & 1];
         // d of a plain sweep after the first comes from the previous sweep's tail
-        if (!unit && (acx || t == 1)) IPT_HIP(h, launch_diag_csr(s, ctrl, row_ptr, col, val, zin, ldzb, cs, dvec, k));
+        const bool tail = !acx && !cont;
+        if (!unit && (!tail || t == 1)) IPT_HIP(h, launch_diag_csr(s, ctrl, row_ptr, col, val, zin, ldzb, cs, dvec, k));
         IPT_HIP(h, timer.mark(t, 0, s));
         IPT_HIP(h, launch_spmm_sweep(s, ctrl, row_ptr, col, val, val32, theta, zin, zout,
                                      ladder ? zlo[(t - 1) & 1] : nullptr, ladder ? zlo[t & 1] : nullptr, cs, dvec,
                                      part, n, k, ldzb, kpc, unit ? 1 : 0));
         IPT_HIP(h, timer.mark(t, 1, s));
-        if (acx) {
+        // continuation: W <- E + s (W - E) on this sweep's active columns (scale s < 1)
+        if (cont) IPT_HIP(h, launch_cont_blend_cols(s, ctrl, zout, ldzb, cs, n, k));
+        if (!tail) {
             IPT_HIP(h, launch_reduce_parts(s, ctrl, cs, part, nrt, k, kpc));
             IPT_HIP(h, launch_finalize(s, ctrl, dopt, cs, dvec, theta, part, 1, kpc, t, in_par, out_par));
             IPT_HIP(h, launch_control(s, ctrl, dopt, t));

@@ -104,10 +104,11 @@ enum : int32_t { LT_BF16 = 0, LT_F16 = 1, LT_F32 = 2 };
 // -------------------------------------------------------------- launchers
 
 // Setup and bookkeeping (ipt_setup.hip)
-// With theta, the column part also checks theta's order (as launch_init_cols).
+// With theta, the column part also checks theta's order (as launch_init_cols);
+// cont_alpha > 0 starts the continuation's scale (as launch_ctrl_init).
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp,
-                       const double *theta = nullptr);
+                       const double *theta = nullptr, double cont_alpha = 0.0);
 // The column part of launch_init (after a separate launch_ctrl_init): bitmap_zeroed
 // when that launch cleared the bitmap; with theta it also checks theta's order (then
 // launch_check_theta(..., order_done = true)).  With cs.alist it writes the packed
@@ -119,14 +120,17 @@ hipError_t launch_init_cols(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_
 // bitmap (n bits) is cleared for launch_init_cols when given.
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl *ctrl, int32_t start_prec, int64_t active, int32_t sym0 = 0,
                             double cont_alpha = 0.0, uint32_t *bitmap = nullptr, int64_t n_bits = 0);
+// dst = scale * Delta, n x n with leading dimension n (the homotopy restart's stages).
+hipError_t launch_scale_copy(hipStream_t s, double *dst, const double *src, int64_t lda, int64_t n, double scale);
 // Continuation sweep (scale s = Ctrl::escale < 1): the sweep computed W = F(Z) of the
 // unscaled partition; the continuation map is E + s (F(Z) - E), so the off-diagonal
 // entries of this sweep's active columns are multiplied by s in place.  Nothing is
-// done once s = 1.
-// dst = scale * Delta, n x n with leading dimension n (the homotopy restart's stages).
-hipError_t launch_scale_copy(hipStream_t s, double *dst, const double *src, int64_t lda, int64_t n, double scale);
+// done once s = 1.  launch_cont_blend takes the columns from the packed list (dense
+// solves), launch_cont_blend_cols the columns 0 .. k-1 still active (CSR solves).
 hipError_t launch_cont_blend(hipStream_t s, const Ctrl *ctrl, double *w, int64_t ldw, ColState cs, int64_t n,
                              int64_t kp);
+hipError_t launch_cont_blend_cols(hipStream_t s, const Ctrl *ctrl, double *w, int64_t ldw, ColState cs, int64_t n,
+                                  int64_t k);
 // Tile pairs of Delta over the padded np x np, after launch_prep_delta: want_sym
 // clears ctrl->sym unless Delta equals its transpose bit for bit; f16 (the FP16 low
 // rung) and hi (hi/lo of the three-product rung, lo = hi + np^2) receive the FP16

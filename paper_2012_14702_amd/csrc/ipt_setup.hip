@@ -1095,8 +1095,8 @@ inline int blocks_for(int64_t count, int per) { return (int)((count + per - 1) /
 
 hipError_t launch_init(hipStream_t s, Ctrl *ctrl, ColState cs, const int32_t *idx_user, int64_t n, int64_t k,
                        int64_t kp, uint32_t *bitmap, int32_t start_prec, int32_t ntiles_n, int32_t start_stamp,
-                       const double *theta) {
-    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k, 0, 0.0, bitmap, (n + 31) / 32);
+                       const double *theta, double cont_alpha) {
+    k_ctrl_init<<<1, 256, 0, s>>>(ctrl, start_prec, k, 0, cont_alpha, bitmap, (n + 31) / 32);
     return launch_init_cols(s, ctrl, cs, idx_user, n, k, kp, bitmap, ntiles_n, start_stamp, true, theta);
 }
 
@@ -1302,6 +1302,29 @@ __global__ __launch_bounds__(256) void k_cont_blend(const Ctrl *ctrl, double *w,
     const int32_t i = cs.idx[c];
     for (int64_t j = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); j < n; j += (int64_t)gridDim.y * 4)
         if (j != i) w[j * ldw + c] *= es;
+}
+
+// The same blend for solves without a packed list (CSR): the columns still active in
+// this sweep (their state is not yet updated by the finalize), block = 64 columns x 4
+// row lanes.
+__global__ __launch_bounds__(256) void k_cont_blend_cols(const Ctrl *ctrl, double *w, int64_t ldw, ColState cs,
+                                                         int64_t n, int64_t k) {
+    if (ctrl->error || ctrl->done) return;
+    const double es = ctrl->escale;
+    if (!(es < 1.0)) return;
+    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (c >= k || cs.state[c] != COL_ACTIVE) return;
+    const int32_t i = cs.idx[c];
+    for (int64_t j = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); j < n; j += (int64_t)gridDim.y * 4)
+        if (j != i) w[j * ldw + c] *= es;
+}
+
+hipError_t launch_cont_blend_cols(hipStream_t s, const Ctrl *ctrl, double *w, int64_t ldw, ColState cs, int64_t n,
+                                  int64_t k) {
+    const int64_t rows = (n + 3) / 4;
+    dim3 g((unsigned)((k + 63) / 64), (unsigned)(rows < 1024 ? rows : 1024));
+    k_cont_blend_cols<<<g, 256, 0, s>>>(ctrl, w, ldw, cs, n, k);
+    return hipGetLastError();
 }
 
 hipError_t launch_cont_blend(hipStream_t s, const Ctrl *ctrl, double *w, int64_t ldw, ColState cs, int64_t n,

@@ -1,4 +1,4 @@
-"""GPU parity of the non-autonomous continuation (opts.cont_alpha, dense FP64
+"""GPU parity of the non-autonomous continuation (opts.cont_alpha, dense and CSR FP64
 sweeps) against the oracle's continuation, through the C ABI."""
 import numpy as np
 import pytest
@@ -89,12 +89,85 @@ def test_continuation_rejected_elsewhere(ipt):
         assert e.value.status == ipt.IPT_EINVAL, kw
     th_s, rp, col, val = W.sparse_sym_uniform(64, 3, 0.05, 1)
     with pytest.raises(ipt.IPTError) as e:
-        ipt.ipt_solve_csr(t(th_s), t(rp), t(col), t(val), t(np.arange(4, dtype=np.int32)), cont_alpha=0.5)
+        ipt.ipt_solve_csr(t(th_s), t(rp), t(col), t(val), t(np.arange(4, dtype=np.int32)), cont_alpha=0.5,
+                          precision=ipt.PREC_LADDER)
+    assert e.value.status == ipt.IPT_EINVAL
+    with pytest.raises(ipt.IPTError) as e:
+        ipt.ipt_solve_csr_z(t(th_s.astype(complex)), t(rp), t(col), t(val.astype(complex)),
+                            t(np.arange(4, dtype=np.int32)), cont_alpha=0.5)
     assert e.value.status == ipt.IPT_EINVAL
     ns, thb, deb, _, _ = W.batched_sym_gaussian(3, 8, 40, 0.02, seed=1)
     with pytest.raises(ipt.IPTError) as e:
         ipt.ipt_solve_batched(ns, t(thb), t(deb), cont_alpha=0.5)
     assert e.value.status == ipt.IPT_EINVAL
+
+
+# ------------------------------------------------------------- continuation, CSR
+
+def _dense_of(n, rp, col, val):
+    de = np.zeros((n, n))
+    for j in range(n):
+        for p in range(rp[j], rp[j + 1]):
+            de[j, col[p]] += val[p]
+    return de
+
+
+def _csr_of(de):
+    n = de.shape[0]
+    rows, cols = np.nonzero(de)
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, rows + 1, 1)
+    return np.cumsum(rp).astype(np.int32), cols.astype(np.int32), de[rows, cols].astype(np.float64)
+
+
+def _solve_csr(ipt, th, rp, col, val, idx, **kw):
+    return host(ipt.ipt_solve_csr(t(th), t(rp), t(col), t(val), t(np.asarray(idx, np.int32)), **kw))
+
+
+def test_csr_three_by_three_rescued(ipt):
+    """The 3 x 3 example at eps = -0.475 in CSR form: the continuation converges on the
+    column plain IPT loses, as the oracle's continuation on the same matrix."""
+    say("continuation csr 3x3 eps=-0.475 alpha=0.5")
+    th, de = W.three_by_three(-0.475)
+    rp, col, val = _csr_of(de)
+    idx = np.arange(3, dtype=np.int32)
+    plain = _solve_csr(ipt, th, rp, col, val, idx, tol=1e-12, max_iter=2000)
+    g = _solve_csr(ipt, th, rp, col, val, idx, tol=1e-12, max_iter=2000, cont_alpha=0.5)
+    ref = oracle.ipt_dense_cont(th, de, 0.5, tol=1e-12, max_iter=2000)
+    check(g.z, g.lam, g.status, ref, oracle.norm1(th, de), 1e-12, gpu_sweeps=g.sweeps, max_iter=2000)
+    assert plain.status[1] == ipt.DIVERGED and g.status[1] == ipt.CONVERGED
+    assert g.sweeps[1] >= 54
+
+
+@pytest.mark.parametrize("n,k,alpha,seed", [(1500, 37, 0.7, 1), (2000, 64, 0.5, 2), (600, 100, 0.5, 3)])
+def test_csr_continuation_parity(ipt, n, k, alpha, seed):
+    """Sparse perturbations (several lane groupings, more than 64 columns) against the
+    oracle's continuation on the densified matrix; no column certifies before the
+    scale's switch to 1."""
+    say("continuation csr n=%d k=%d alpha=%g" % (n, k, alpha))
+    th, rp, col, val = W.sparse_sym_uniform(n, pairs_per_row=3, amp=0.1, seed=seed)
+    idx = np.sort(np.random.default_rng(seed).choice(n, k, replace=False)).astype(np.int32)
+    g = _solve_csr(ipt, th, rp, col, val, idx, tol=1e-10, max_iter=400, cont_alpha=alpha)
+    de = _dense_of(n, rp, col, val)
+    ref = oracle.ipt_dense_cont(th, de, alpha, idx=idx, tol=1e-10, max_iter=400, resid=False)
+    out = check(g.z, g.lam, g.status, ref, oracle.norm1(th, csr=(rp, col, val)), 1e-10, gpu_sweeps=g.sweeps,
+                max_iter=400)
+    assert out["compared"] == k
+    switch = int(np.ceil(54 / np.log2(1 / alpha)))
+    assert np.all(g.sweeps >= switch - 2)
+
+
+def test_csr_budget_ends_during_continuation(ipt):
+    """max_iter = 10 at alpha = 0.8 on a CSR matrix: every column ends NOT_CONVERGED with
+    the tenth iterate of the continuation map, the oracle's to rounding."""
+    say("continuation csr budget n=800")
+    th, rp, col, val = W.sparse_sym_uniform(800, pairs_per_row=3, amp=0.05, seed=6)
+    idx = np.arange(0, 800, 25, dtype=np.int32)
+    g = _solve_csr(ipt, th, rp, col, val, idx, tol=1e-10, max_iter=10, cont_alpha=0.8)
+    ref = oracle.ipt_dense_cont(th, _dense_of(800, rp, col, val), 0.8, idx=idx, tol=1e-10, max_iter=10, resid=False)
+    assert np.all(g.status == ipt.NOT_CONVERGED) and np.all(ref.status == oracle.NOT_CONVERGED)
+    assert np.max(np.abs(g.z - ref.z)) < 1e-13
+    assert np.max(np.abs(g.lam - ref.lam)) < 1e-13 * oracle.norm1(th, csr=(rp, col, val))
 
 
 # ---------------------------------------------------------------- homotopy restart
