@@ -1689,6 +1689,25 @@ MlpEpi epi0() {
 // Input packing and the hidden layers: H_l = tanh(H_{l-1} W_l^T + b_l), stored with H_l^T.
 hipError_t mlp_hidden(ipt_mlp m, hipStream_t s, int batch) {
     const int bp = pad_tile(batch);
+    if (mlp_fused_fits(m->depth, m->linp.data(), m->loutp.data())) {
+        // narrow hidden layers: all of them in one launch, activations kept in LDS
+        MlpFused f;
+        memset(&f, 0, sizeof(f));
+        f.xb = m->xb;
+        f.ip = m->ip;
+        f.hp = m->hp;
+        f.depth = m->depth;
+        for (int l = 0; l < m->depth; ++l) {
+            f.w[l] = m->wb[l];
+            f.bias[l] = m->w + m->boff[l];
+            f.hb[l] = m->hb[l];
+            f.ht[l] = m->ht[l];
+            f.linp[l] = m->linp[l];
+            f.loutp[l] = m->loutp[l];
+            f.lout[l] = m->lout[l];
+        }
+        return mlp_hidden_fused(s, f, batch, bp);
+    }
     for (int l = 0; l < m->depth; ++l) {
         MlpEpi e = epi0();
         e.mvalid = batch;

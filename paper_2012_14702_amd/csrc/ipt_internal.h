@@ -341,6 +341,21 @@ struct MlpEpi {
     const double *terms;           // order x (nvalid) analytic terms T_l (may be null when order = 0)
     int32_t order;
 };
+// Every hidden layer of a network whose padded widths are at most 256 in one launch
+// (mlp_fused_fits): xb is the packed BF16 input (bp x ip), w[l] the BF16 W_l (loutp x
+// linp), bias[l] the FP32 b_l; writes H_l (bp x hp) and H_l^T (hp x bp) as the
+// bias + tanh epilogue of the GEMM path.
+constexpr int MLP_MAX_LAYERS = 16;
+struct MlpFused {
+    const __bf16 *xb;
+    int32_t ip, hp, depth;
+    const __bf16 *w[MLP_MAX_LAYERS];
+    const float *bias[MLP_MAX_LAYERS];
+    __bf16 *hb[MLP_MAX_LAYERS], *ht[MLP_MAX_LAYERS];
+    int32_t linp[MLP_MAX_LAYERS], loutp[MLP_MAX_LAYERS], lout[MLP_MAX_LAYERS];
+};
+bool mlp_fused_fits(int depth, const int *linp, const int *loutp);
+hipError_t mlp_hidden_fused(hipStream_t s, const MlpFused &f, int batch, int bp);
 hipError_t mlp_gemm(hipStream_t s, int mode, const __bf16 *A, int64_t lda, const __bf16 *B, int64_t ldb, int M, int N,
                     int K, int splits, const MlpEpi &e);
 // Sum of the split-K partials (FP32 [splits][M][N]) in split order, then mode

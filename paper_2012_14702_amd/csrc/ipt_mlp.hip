@@ -526,6 +526,82 @@ __global__ __launch_bounds__(256) void k_split_reduce(const float *part, int spl
     }
 }
 
+// Every hidden layer of a narrow network (padded widths <= MLP_FUSED_W) in one launch:
+// a block owns 16 rows of the batch and keeps their activations in LDS from layer to
+// layer.  Layer l: H_l = tanh(H_{l-1} W_l^T + b_l); wave w computes columns 64 w ..
+// 64 w + 63 of the 16 rows with v_mfma_f32_16x16x32_bf16 over the whole K (A from LDS,
+// B = rows of W_l straight from global memory, all of a layer's 16-byte loads issued
+// together), FP32 accumulation, then
+// bias, tanh and the BF16 rounding of the split-K path; H_l goes to LDS for the next
+// layer and to H_l (row-major) and H_l^T in global memory for the backward products.
+// Rows past the batch and columns past the layer's width are zero, as in the GEMM path.
+constexpr int MLP_FUSED_W = 256;
+constexpr int FP_LD = MLP_FUSED_W + 8;  // LDS pitch of an activation row (BF16): 528 bytes
+__global__ __launch_bounds__(256) void k_mlp_hidden_fused(MlpFused f, int batch, int bp) {
+    __shared__ __attribute__((aligned(16))) uint16_t hs[2][16][FP_LD];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int m0 = blockIdx.x * 16;
+    // the packed BF16 input rows (zero-padded to ip by the packer)
+    for (int e = t; e < 16 * (f.ip / 8); e += 256) {
+        const int r = e / (f.ip / 8), c8 = (e % (f.ip / 8)) * 8;
+        *(u16x8 *)&hs[0][r][c8] = *(const u16x8 *)((const uint16_t *)f.xb + (int64_t)(m0 + r) * f.ip + c8);
+    }
+    __syncthreads();
+    for (int l = 0; l < f.depth; ++l) {
+        const int cur = l & 1, K = f.linp[l], N = f.loutp[l];
+        const uint16_t *W = (const uint16_t *)f.w[l];
+        const bool live = wv * 64 < N;  // the wave's 64 columns hold data
+        f4_t acc[4];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) acc[jb] = f4_t{0.f, 0.f, 0.f, 0.f};
+        if (live) {
+            // every B fragment of the layer is loaded before the first product, so the
+            // layer waits for one round of loads, not one per K step
+            constexpr int KS = MLP_FUSED_W / 32;
+            bf8_t bq[KS][4];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                if (32 * ks < K)
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+                        bq[ks][jb] = *(const bf8_t *)(W + (int64_t)(wv * 64 + 16 * jb + (lane & 15)) * K + 32 * ks +
+                                                      8 * (lane >> 4));
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                if (32 * ks < K) {
+                    const bf8_t a = *(const bf8_t *)&hs[cur][lane & 15][32 * ks + 8 * (lane >> 4)];
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+                        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[ks][jb], acc[jb], 0, 0, 0);
+                }
+        }
+        // lane l, register r of block jb: row 4 (l / 16) + r, column 64 w + 16 jb + l % 16
+        if (live) {
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const int n = wv * 64 + 16 * jb + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 4 * (lane >> 4) + r;
+                    const bool ok = m0 + row < batch && n < f.lout[l];
+                    const uint16_t b = ok ? bf16_bits(tanhf(acc[jb][r] + f.bias[l][n])) : (uint16_t)0;
+                    hs[cur ^ 1][row][n] = b;
+                    *((uint16_t *)f.hb[l] + (int64_t)(m0 + row) * f.hp + n) = b;
+                }
+            }
+        }
+        __syncthreads();
+        // H_l^T: column n holds the block's 16 rows contiguously (two 16-byte stores)
+        for (int e = t; e < 2 * N; e += 256) {
+            const int n = e >> 1, h8 = (e & 1) * 8;
+            u16x8 v;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = hs[cur ^ 1][h8 + q][n];
+            *(u16x8 *)((uint16_t *)f.ht[l] + (int64_t)n * bp + m0 + h8) = v;
+        }
+    }
+}
+
 __global__ void k_pack_weights(const float *w, int lout, int lin, __bf16 *wb, __bf16 *wbt, int loutp, int linp) {
     const int64_t total = (int64_t)loutp * linp;
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < total; u += (int64_t)gridDim.x * blockDim.x) {
@@ -666,6 +742,19 @@ hipError_t mlp_gemm(hipStream_t s, int mode, const __bf16 *A, int64_t lda, const
         case MLP_EPI_WARM: k_mlp_gemm<MLP_EPI_WARM><<<g, 256, 0, s>>>(A, lda, B, ldb, Kc, M, N, e); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+bool mlp_fused_fits(int depth, const int *linp, const int *loutp) {
+    if (depth < 1 || depth > MLP_MAX_LAYERS) return false;
+    for (int l = 0; l < depth; ++l)
+        if (linp[l] > MLP_FUSED_W || loutp[l] > MLP_FUSED_W || linp[l] % 32) return false;
+    return true;
+}
+
+hipError_t mlp_hidden_fused(hipStream_t s, const MlpFused &f, int batch, int bp) {
+    if (bp % 16 || !mlp_fused_fits(f.depth, f.linp, f.loutp)) return hipErrorInvalidValue;
+    k_mlp_hidden_fused<<<(unsigned)(bp / 16), 256, 0, s>>>(f, batch, bp);
     return hipGetLastError();
 }
 
