@@ -1687,25 +1687,31 @@ MlpEpi epi0() {
 }
 
 // Input packing and the hidden layers: H_l = tanh(H_{l-1} W_l^T + b_l), stored with H_l^T.
+// The arguments of the one-launch hidden layers; false when the network does not fit them.
+static bool mlp_fused_args(ipt_mlp m, MlpFused &f) {
+    if (!mlp_fused_fits(m->depth, m->linp.data(), m->loutp.data())) return false;
+    memset(&f, 0, sizeof(f));
+    f.xb = m->xb;
+    f.ip = m->ip;
+    f.hp = m->hp;
+    f.depth = m->depth;
+    for (int l = 0; l < m->depth; ++l) {
+        f.w[l] = m->wb[l];
+        f.bias[l] = m->w + m->boff[l];
+        f.hb[l] = m->hb[l];
+        f.ht[l] = m->ht[l];
+        f.linp[l] = m->linp[l];
+        f.loutp[l] = m->loutp[l];
+        f.lout[l] = m->lout[l];
+    }
+    return true;
+}
+
 hipError_t mlp_hidden(ipt_mlp m, hipStream_t s, int batch) {
     const int bp = pad_tile(batch);
-    if (mlp_fused_fits(m->depth, m->linp.data(), m->loutp.data())) {
+    MlpFused f;
+    if (mlp_fused_args(m, f)) {
         // narrow hidden layers: all of them in one launch, activations kept in LDS
-        MlpFused f;
-        memset(&f, 0, sizeof(f));
-        f.xb = m->xb;
-        f.ip = m->ip;
-        f.hp = m->hp;
-        f.depth = m->depth;
-        for (int l = 0; l < m->depth; ++l) {
-            f.w[l] = m->wb[l];
-            f.bias[l] = m->w + m->boff[l];
-            f.hb[l] = m->hb[l];
-            f.ht[l] = m->ht[l];
-            f.linp[l] = m->linp[l];
-            f.loutp[l] = m->loutp[l];
-            f.lout[l] = m->lout[l];
-        }
         return mlp_hidden_fused(s, f, batch, bp);
     }
     for (int l = 0; l < m->depth; ++l) {
@@ -1971,8 +1977,6 @@ ipt_status ipt_mlp_forward(ipt_mlp m, const float *x, int32_t batch, float *y) {
     if (ipt_status st = mlp_ensure_batch(m, batch)) return st;
     hipStream_t s = m->h->stream;
     const int bp = pad_tile(batch);
-    IPT_MHIP(m, mlp_pack_x(s, x, batch, m->in, m->xb, m->xt, bp, m->ip));
-    IPT_MHIP(m, mlp_hidden(m, s, batch));
     MlpEpi e = epi0();
     e.mvalid = batch;
     e.nvalid = m->out;
@@ -2071,6 +2075,14 @@ ipt_status ipt_mlp_predict_z0(ipt_mlp m, const float *x, int32_t batch, const fl
     e.eps = eps;
     e.terms = terms;
     e.order = order;
+    MlpFused f;
+    if (mlp_fused_args(m, f)) {
+        // narrow hidden layers: one launch reading x itself (no packed copy, no H^T)
+        IPT_MHIP(m, mlp_hidden_fused(s, f, batch, bp, x, m->in));
+    } else {
+        IPT_MHIP(m, mlp_pack_x(s, x, batch, m->in, m->xb, m->xt, bp, m->ip));
+        IPT_MHIP(m, mlp_hidden(m, s, batch));
+    }
     IPT_MHIP(m, mlp_gemm(s, MLP_EPI_WARM, m->hb[m->depth - 1], m->hp, m->wb[m->nl - 1], m->hp, bp, m->op, m->hp, 1, e));
     IPT_MHIP(m, hipStreamSynchronize(s));
     return IPT_OK;

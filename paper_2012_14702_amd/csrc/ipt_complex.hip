@@ -329,16 +329,19 @@ __global__ void k_zprep_theta(Ctrl *ctrl, const double2 *theta, double *th_re, d
 }
 
 // theta_j == theta_i (both parts) for a requested i and j != i: the inverse gap is
-// undefined (IPT_EDEGENERATE).  Block per requested column.
+// undefined (IPT_EDEGENERATE).  Block per (requested column, chunk of rows), so that a
+// few requested columns of a long theta still spread over the chip.
 __global__ void k_zcheck_gaps(Ctrl *ctrl, const double *th_re, const double *th_im, const int32_t *idx, int64_t n,
-                              int64_t k) {
+                              int64_t k, int64_t chunk) {
     if (ctrl->error) return;
     const int64_t c = blockIdx.x;
     if (c >= k) return;
     const int32_t i = idx[c];
     const double a = th_re[i], b = th_im[i];
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
     bool bad = false;
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) bad |= (j != i) && th_re[j] == a && th_im[j] == b;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) bad |= (j != i) && th_re[j] == a && th_im[j] == b;
     if (bad) atomicMax(&ctrl->error, (int32_t)IPT_EDEGENERATE);
 }
 
@@ -445,7 +448,10 @@ int64_t zsetup_part2_doubles(int64_t n) { return (int64_t)ZCH * n; }
 
 hipError_t launch_zcheck_gaps(hipStream_t s, Ctrl *ctrl, const double *th_re, const double *th_im, const int32_t *idx,
                               int64_t n, int64_t k) {
-    k_zcheck_gaps<<<(unsigned)k, 256, 0, s>>>(ctrl, th_re, th_im, idx, n, k);
+    int64_t chunk = 4096;  // 16 rows per thread
+    if ((n + chunk - 1) / chunk > 65535) chunk = (n + 65534) / 65535;
+    const dim3 g((unsigned)k, (unsigned)((n + chunk - 1) / chunk));
+    k_zcheck_gaps<<<g, 256, 0, s>>>(ctrl, th_re, th_im, idx, n, k, chunk);
     return hipGetLastError();
 }
 

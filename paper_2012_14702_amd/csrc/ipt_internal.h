@@ -355,7 +355,9 @@ struct MlpFused {
     int32_t linp[MLP_MAX_LAYERS], loutp[MLP_MAX_LAYERS], lout[MLP_MAX_LAYERS];
 };
 bool mlp_fused_fits(int depth, const int *linp, const int *loutp);
-hipError_t mlp_hidden_fused(hipStream_t s, const MlpFused &f, int batch, int bp);
+// x null: input from the packed f.xb, H_l and H_l^T stored (training); x non-null: the
+// BF16 of x [batch x in] (in <= linp[0]) read directly and H_l^T not stored (inference).
+hipError_t mlp_hidden_fused(hipStream_t s, const MlpFused &f, int batch, int bp, const float *x = nullptr, int in = 0);
 hipError_t mlp_gemm(hipStream_t s, int mode, const __bf16 *A, int64_t lda, const __bf16 *B, int64_t ldb, int M, int N,
                     int K, int splits, const MlpEpi &e);
 // Sum of the split-K partials (FP32 [splits][M][N]) in split order, then mode

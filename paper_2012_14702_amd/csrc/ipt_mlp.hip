@@ -26,9 +26,11 @@ namespace {
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
 
 constexpr int GT = MLP_TILE;   // tile rows and columns
 constexpr int GK = 32;         // K step
+constexpr int WARM_REG_ORDER = 4;  // warm-start series orders held in registers
 constexpr int GLD = GK + 8;    // LDS pitch of an operand row in BF16 (80 bytes: 16 rows hit distinct banks)
 constexpr int OLD = GT + 8;    // LDS pitch of an output row in BF16 (272 bytes)
 constexpr int STAGE = 2 * GT * GLD;             // A and B of one stage
@@ -110,6 +112,119 @@ constexpr int mlp_smem() {
     return (MODE == MLP_EPI_MSE || MODE == MLP_EPI_ADAM || MODE == MLP_EPI_WARM)
                ? (SMEM_STAGED > SMEM_BF16 ? SMEM_STAGED : SMEM_BF16)
                : SMEM_BF16;
+}
+
+// The warm-start epilogue (MLP_EPI_WARM) of a 128 x 128 output tile held as the
+// four waves' 64 x 64 quarters (acc of wave (wm, wn), cbase = 64 wn + lane % 16): the
+// network's output y of member p and entry q = j kcols + c is the standardised remainder
+// after the analytic series start, so Z0_jc = sum_{l <= order} eps^l T_l + eps^(order+1)
+// (mu + sigma (y + bias)), and 1 at the requested entry of each column.  fh: 64 x FLD
+// floats of LDS; every thread of the block calls it (it holds barriers).
+__device__ __forceinline__ void warm_epilogue(const f4_t (&acc)[4][4], const MlpEpi &e, float (*fh)[FLD], int m0,
+                                              int n0, int t, int lane, int wm, int cbase) {
+    // accumulators through LDS (two halves of 64 rows, FP32); each thread then takes 4
+    // consecutive outputs q of a member row at a time (consecutive columns c of Z0)
+    const int32_t ord = e.order;
+    const int cq = t & 31, rp = t >> 5;
+    // When kcols is a multiple of 4 (so is nvalid = n kcols), the four outputs of a
+    // thread are four consecutive columns of one row of Z0, all in range or all out;
+    // with even strides and a 16-byte aligned Z0 they leave as two 16-byte stores, and
+    // the series terms T_l (they do not depend on the member) sit in registers.  The
+    // arithmetic is the same in both forms.
+    const bool vec = (e.kcols & 3) == 0 && (e.ldz0 & 1) == 0 && (e.pstride & 1) == 0 &&
+                     ((uintptr_t)e.z0 & 15) == 0 && ord <= WARM_REG_ORDER;
+    int64_t jj[4], cc[4];
+    bool qok[4], unit[4];
+    double bv[4], mu[4], sg[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int q = n0 + 4 * cq + u;
+        qok[u] = q < e.nvalid;
+        const int qq = qok[u] ? q : 0;
+        divmod_nn(qq, e.kcols, jj[u], cc[u]);
+        unit[u] = jj[u] == e.idx[cc[u]];
+        bv[u] = e.bias ? (double)e.bias[qq] : 0.0;
+        mu[u] = e.mu[qq];
+        sg[u] = e.sigma[qq];
+    }
+    double tr[WARM_REG_ORDER][4];
+#pragma unroll
+    for (int l = 0; l < WARM_REG_ORDER; ++l)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            tr[l][u] = (vec && l < ord && qok[u]) ? e.terms[(int64_t)l * e.nvalid + n0 + 4 * cq + u] : 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (wm == h) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) fh[4 * (lane >> 4) + 16 * x + r][cbase + 16 * y] = acc[x][y][r];
+        }
+        __syncthreads();
+        if (vec) {
+            if (qok[0]) {
+                double epr[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int p = m0 + h * 64 + rp + 8 * i;
+                    epr[i] = p < e.mvalid ? e.eps[p] : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int lrow = rp + 8 * i, p = m0 + h * 64 + lrow;
+                    if (p >= e.mvalid) continue;
+                    const double ep = epr[i];
+                    const f4_t a4 = *(const f4_t *)&fh[lrow][4 * cq];
+                    d2_t v[2];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        double vu = 1.0;
+                        if (!unit[u]) {
+                            double base = 0.0, pw = 1.0;
+#pragma unroll
+                            for (int l = 0; l < WARM_REG_ORDER; ++l)
+                                if (l < ord) {
+                                    pw *= ep;
+                                    base += pw * tr[l][u];
+                                }
+                            vu = base + pw * ep * (mu[u] + sg[u] * ((double)a4[u] + bv[u]));
+                        }
+                        v[u >> 1][u & 1] = vu;
+                    }
+                    d2_t *dst = (d2_t *)(e.z0 + (int64_t)p * e.pstride + jj[0] * e.ldz0 + cc[0]);
+                    dst[0] = v[0];
+                    dst[1] = v[1];
+                }
+            }
+        } else {
+#pragma unroll 2
+            for (int i = 0; i < 8; ++i) {
+                const int lrow = rp + 8 * i, p = m0 + h * 64 + lrow;
+                if (p >= e.mvalid) continue;
+                const double ep = e.eps[p];
+                const f4_t a4 = *(const f4_t *)&fh[lrow][4 * cq];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!qok[u]) continue;
+                    const int q = n0 + 4 * cq + u;
+                    double v = 1.0;
+                    if (!unit[u]) {
+                        double base = 0.0, pw = 1.0;
+                        for (int l = 1; l <= ord; ++l) {
+                            pw *= ep;
+                            base += pw * e.terms[(int64_t)(l - 1) * e.nvalid + q];
+                        }
+                        v = base + pw * ep * (mu[u] + sg[u] * ((double)a4[u] + bv[u]));
+                    }
+                    e.z0[(int64_t)p * e.pstride + jj[u] * e.ldz0 + cc[u]] = v;
+                }
+            }
+        }
+        __syncthreads();
+    }
 }
 
 template <int MODE>
@@ -204,60 +319,7 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const __bf16 *__restrict__ A, 
         return;
     }
     if (MODE == MLP_EPI_WARM) {
-        // accumulators through LDS (two halves of 64 rows, FP32); each thread then takes 4
-        // consecutive outputs q of a member row at a time (consecutive columns c of Z0)
-        float(*fh)[FLD] = (float(*)[FLD])(smem + GT * OLD);
-        const int32_t ord = e.order;
-        const int cq = t & 31, rp = t >> 5;
-        int64_t jj[4], cc[4];
-        bool qok[4], unit[4];
-        double bv[4], mu[4], sg[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int q = n0 + 4 * cq + u;
-            qok[u] = q < e.nvalid;
-            const int qq = qok[u] ? q : 0;
-            divmod_nn(qq, e.kcols, jj[u], cc[u]);
-            unit[u] = jj[u] == e.idx[cc[u]];
-            bv[u] = e.bias ? (double)e.bias[qq] : 0.0;
-            mu[u] = e.mu[qq];
-            sg[u] = e.sigma[qq];
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (wm == h) {
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) fh[4 * (lane >> 4) + 16 * x + r][cbase + 16 * y] = acc[x][y][r];
-            }
-            __syncthreads();
-#pragma unroll 2
-            for (int i = 0; i < 8; ++i) {
-                const int lrow = rp + 8 * i, p = m0 + h * 64 + lrow;
-                if (p >= e.mvalid) continue;
-                const double ep = e.eps[p];
-                const f4_t a4 = *(const f4_t *)&fh[lrow][4 * cq];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (!qok[u]) continue;
-                    const int q = n0 + 4 * cq + u;
-                    double v = 1.0;
-                    if (!unit[u]) {
-                        double base = 0.0, pw = 1.0;
-                        for (int l = 1; l <= ord; ++l) {
-                            pw *= ep;
-                            base += pw * e.terms[(int64_t)(l - 1) * e.nvalid + q];
-                        }
-                        v = base + pw * ep * (mu[u] + sg[u] * ((double)a4[u] + bv[u]));
-                    }
-                    e.z0[(int64_t)p * e.pstride + jj[u] * e.ldz0 + cc[u]] = v;
-                }
-            }
-            __syncthreads();
-        }
+        warm_epilogue(acc, e, (float(*)[FLD])(smem + GT * OLD), m0, n0, t, lane, wm, cbase);
         return;
     }
 
@@ -530,42 +592,70 @@ __global__ __launch_bounds__(256) void k_split_reduce(const float *part, int spl
 // a block owns 16 rows of the batch and keeps their activations in LDS from layer to
 // layer.  Layer l: H_l = tanh(H_{l-1} W_l^T + b_l); wave w computes columns 64 w ..
 // 64 w + 63 of the 16 rows with v_mfma_f32_16x16x32_bf16 over the whole K (A from LDS,
-// B = rows of W_l straight from global memory, all of a layer's 16-byte loads issued
-// together), FP32 accumulation, then
+// B = rows of W_l straight from global memory), FP32 accumulation, then
 // bias, tanh and the BF16 rounding of the split-K path; H_l goes to LDS for the next
 // layer and to H_l (row-major) and H_l^T in global memory for the backward products.
 // Rows past the batch and columns past the layer's width are zero, as in the GEMM path.
 constexpr int MLP_FUSED_W = 256;
 constexpr int FP_LD = MLP_FUSED_W + 8;  // LDS pitch of an activation row (BF16): 528 bytes
-__global__ __launch_bounds__(256) void k_mlp_hidden_fused(MlpFused f, int batch, int bp) {
-    __shared__ __attribute__((aligned(16))) uint16_t hs[2][16][FP_LD];
+// The hidden layers of the 16 batch rows m0.. (hs: two LDS activation buffers).  The
+// input is the packed BF16 f.xb, or with x non-null the BF16 of x [batch x in] with the
+// packer's zero padding; H_l^T is stored only with store_t.
+__device__ __forceinline__ void hidden_slab(const MlpFused &f, const float *x, int in, int batch, int bp, int m0,
+                                            uint16_t (*hs)[16][FP_LD], bool store_t) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int m0 = blockIdx.x * 16;
-    // the packed BF16 input rows (zero-padded to ip by the packer)
-    for (int e = t; e < 16 * (f.ip / 8); e += 256) {
-        const int r = e / (f.ip / 8), c8 = (e % (f.ip / 8)) * 8;
-        *(u16x8 *)&hs[0][r][c8] = *(const u16x8 *)((const uint16_t *)f.xb + (int64_t)(m0 + r) * f.ip + c8);
+    // every B fragment of a layer and its bias are loaded before the layer's first
+    // product, so a layer waits for one round of loads, not one per K step; the next
+    // layer's round is issued as soon as the products have consumed this one, and its
+    // latency hides behind this layer's tanh and stores
+    constexpr int KS = MLP_FUSED_W / 32;
+    bf8_t bq[KS][4];
+    float bb[4];
+    auto load_layer = [&](int l) {
+        const int K = f.linp[l];
+        if (wv * 64 >= f.loutp[l]) return;  // the wave's 64 columns hold no data
+        const uint16_t *W = (const uint16_t *)f.w[l];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            if (32 * ks < K)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    bq[ks][jb] = *(const bf8_t *)(W + (int64_t)(wv * 64 + 16 * jb + (lane & 15)) * K + 32 * ks +
+                                                  8 * (lane >> 4));
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            const int n = wv * 64 + 16 * jb + (lane & 15);
+            bb[jb] = n < f.lout[l] ? f.bias[l][n] : 0.f;
+        }
+    };
+    load_layer(0);
+    if (!x) {
+        // the packed BF16 input rows (zero-padded to ip by the packer)
+        for (int e = t; e < 16 * (f.ip / 8); e += 256) {
+            const int r = e / (f.ip / 8), c8 = (e % (f.ip / 8)) * 8;
+            *(u16x8 *)&hs[0][r][c8] = *(const u16x8 *)((const uint16_t *)f.xb + (int64_t)(m0 + r) * f.ip + c8);
+        }
+    } else {
+        // as the packer: BF16 of x, zero past the batch and the input width (zeros first,
+        // then one load per thread and pass, so that a thread's loads do not queue)
+        for (int e = t; e < 16 * (f.ip / 8); e += 256) {
+            const int r = e / (f.ip / 8), c8 = (e % (f.ip / 8)) * 8;
+            *(u16x8 *)&hs[0][r][c8] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+        __syncthreads();
+        for (int e = t; e < 16 * in; e += 256) {
+            const int r = e / in, i = e - r * in;
+            if (m0 + r < batch) hs[0][r][i] = bf16_bits(x[(int64_t)(m0 + r) * in + i]);
+        }
     }
     __syncthreads();
     for (int l = 0; l < f.depth; ++l) {
         const int cur = l & 1, K = f.linp[l], N = f.loutp[l];
-        const uint16_t *W = (const uint16_t *)f.w[l];
         const bool live = wv * 64 < N;  // the wave's 64 columns hold data
         f4_t acc[4];
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) acc[jb] = f4_t{0.f, 0.f, 0.f, 0.f};
         if (live) {
-            // every B fragment of the layer is loaded before the first product, so the
-            // layer waits for one round of loads, not one per K step
-            constexpr int KS = MLP_FUSED_W / 32;
-            bf8_t bq[KS][4];
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-                if (32 * ks < K)
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-                        bq[ks][jb] = *(const bf8_t *)(W + (int64_t)(wv * 64 + 16 * jb + (lane & 15)) * K + 32 * ks +
-                                                      8 * (lane >> 4));
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
                 if (32 * ks < K) {
@@ -574,7 +664,12 @@ __global__ __launch_bounds__(256) void k_mlp_hidden_fused(MlpFused f, int batch,
                     for (int jb = 0; jb < 4; ++jb)
                         acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[ks][jb], acc[jb], 0, 0, 0);
                 }
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[jb][r] += bb[jb];
         }
+        if (l + 1 < f.depth) load_layer(l + 1);
         // lane l, register r of block jb: row 4 (l / 16) + r, column 64 w + 16 jb + l % 16
         if (live) {
 #pragma unroll
@@ -584,7 +679,7 @@ __global__ __launch_bounds__(256) void k_mlp_hidden_fused(MlpFused f, int batch,
                 for (int r = 0; r < 4; ++r) {
                     const int row = 4 * (lane >> 4) + r;
                     const bool ok = m0 + row < batch && n < f.lout[l];
-                    const uint16_t b = ok ? bf16_bits(tanhf(acc[jb][r] + f.bias[l][n])) : (uint16_t)0;
+                    const uint16_t b = ok ? bf16_bits(tanhf(acc[jb][r])) : (uint16_t)0;
                     hs[cur ^ 1][row][n] = b;
                     *((uint16_t *)f.hb[l] + (int64_t)(m0 + row) * f.hp + n) = b;
                 }
@@ -592,7 +687,7 @@ __global__ __launch_bounds__(256) void k_mlp_hidden_fused(MlpFused f, int batch,
         }
         __syncthreads();
         // H_l^T: column n holds the block's 16 rows contiguously (two 16-byte stores)
-        for (int e = t; e < 2 * N; e += 256) {
+        for (int e = t; store_t && e < 2 * N; e += 256) {
             const int n = e >> 1, h8 = (e & 1) * 8;
             u16x8 v;
 #pragma unroll
@@ -600,6 +695,12 @@ __global__ __launch_bounds__(256) void k_mlp_hidden_fused(MlpFused f, int batch,
             *(u16x8 *)((uint16_t *)f.ht[l] + (int64_t)n * bp + m0 + h8) = v;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_hidden_fused(MlpFused f, const float *x, int in, int batch, int bp,
+                                                          int store_t) {
+    __shared__ __attribute__((aligned(16))) uint16_t hs[2][16][FP_LD];
+    hidden_slab(f, x, in, batch, bp, blockIdx.x * 16, hs, store_t != 0);
 }
 
 __global__ void k_pack_weights(const float *w, int lout, int lin, __bf16 *wb, __bf16 *wbt, int loutp, int linp) {
@@ -752,9 +853,10 @@ bool mlp_fused_fits(int depth, const int *linp, const int *loutp) {
     return true;
 }
 
-hipError_t mlp_hidden_fused(hipStream_t s, const MlpFused &f, int batch, int bp) {
-    if (bp % 16 || !mlp_fused_fits(f.depth, f.linp, f.loutp)) return hipErrorInvalidValue;
-    k_mlp_hidden_fused<<<(unsigned)(bp / 16), 256, 0, s>>>(f, batch, bp);
+hipError_t mlp_hidden_fused(hipStream_t s, const MlpFused &f, int batch, int bp, const float *x, int in) {
+    if (bp % 16 || !mlp_fused_fits(f.depth, f.linp, f.loutp) || (x && (in < 1 || in > f.linp[0])))
+        return hipErrorInvalidValue;
+    k_mlp_hidden_fused<<<(unsigned)(bp / 16), 256, 0, s>>>(f, x, in, batch, bp, x ? 0 : 1);
     return hipGetLastError();
 }
 

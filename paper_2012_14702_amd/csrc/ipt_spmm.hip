@@ -25,6 +25,7 @@ namespace ipt {
 
 namespace {
 
+constexpr int UNIT_UP = 4;   // passes of the product-free sweep whose loads go out together
 constexpr int SP_ROWS = 64;  // rows per block (one partial-sum row tile before the block reduction)
 
 struct SpArgs {
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(256) void k_spmm_unit(const Ctrl *ctrl, SpArgs a) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int kg = a.kg;
     const int rows_per_pass = 64 / kg;
-    const int sub = lane / kg, cl = lane % kg;
+    const int sub = lane / kg, cl = lane % kg, g0 = sub * kg;  // g0: first lane of the row's group
     const int64_t r0 = (int64_t)blockIdx.x * SP_ROWS;
     int64_t r1 = r0 + SP_ROWS;
     if (r1 > a.n) r1 = a.n;
@@ -191,46 +192,73 @@ __global__ __launch_bounds__(256) void k_spmm_unit(const Ctrl *ctrl, SpArgs a) {
         const int32_t i = colok ? a.cs.idx[c] : 0;
         const double ti = a.theta[i];
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (int64_t jb = r0 + (int64_t)wv * rows_per_pass; jb < r1; jb += 4 * rows_per_pass) {
-            const int64_t j = jb + sub;
-            if (j >= r1 || !colok) continue;
-            const int32_t pb = a.row_ptr[j], pe = a.row_ptr[j + 1];
-            const double tj = a.theta[j];
-            double y = 0.0;
-            // the row's entries eight at a time, their loads issued together
-            for (int32_t p = pb; p < pe; p += 8) {
-                int32_t cq[8];
-                double vq[8];
+        // UNIT_UP passes of the wave at a time: their row pointers, then the first kg
+        // entries of each of their rows (lane cl of a row's group loads entry pb + cl), are
+        // loaded together, so a wave waits for two rounds of loads per UNIT_UP passes
+        // instead of one per pointer and per eight entries; every lane of the group then
+        // scans the row's entries in storage order through shuffles within the group.
+        const int64_t pstep = 4 * rows_per_pass;
+        for (int64_t jb = r0 + (int64_t)wv * rows_per_pass; jb < r1; jb += UNIT_UP * pstep) {
+            int64_t jq[UNIT_UP];
+            int32_t pb[UNIT_UP], pe[UNIT_UP], ce[UNIT_UP];
+            double ve[UNIT_UP], tq[UNIT_UP];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const bool in = p + u < pe;
-                    cq[u] = in ? a.col[p + u] : -1;
-                    vq[u] = in ? a.val[p + u] : 0.0;
+            for (int q = 0; q < UNIT_UP; ++q) {
+                jq[q] = jb + q * pstep + sub;
+                const bool rin = jq[q] < r1;
+                pb[q] = rin ? a.row_ptr[jq[q]] : 0;
+                pe[q] = rin ? a.row_ptr[jq[q] + 1] : 0;
+                tq[q] = rin ? a.theta[jq[q]] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < UNIT_UP; ++q) {
+                const bool in = pb[q] + cl < pe[q];
+                ce[q] = in ? a.col[pb[q] + cl] : -1;
+                ve[q] = in ? a.val[pb[q] + cl] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < UNIT_UP; ++q) {
+                // all lanes of the group take part in the shuffles (the group shares the row)
+                double y = 0.0;
+                for (int32_t p0 = pb[q]; p0 < pe[q]; p0 += kg) {
+                    int32_t cv = ce[q];
+                    double vv = ve[q];
+                    if (p0 != pb[q]) {
+                        const bool in = p0 + cl < pe[q];
+                        cv = in ? a.col[p0 + cl] : -1;
+                        vv = in ? a.val[p0 + cl] : 0.0;
+                    }
+                    const int nin = pe[q] - p0 < kg ? pe[q] - p0 : kg;
+                    for (int u = 0; u < nin; ++u) {
+                        const int32_t cu = __shfl(cv, g0 + u);
+                        const double vu = __shfl(vv, g0 + u);
+                        if (cu == i) y += vu;
+                    }
                 }
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (cq[u] == i) y += vq[u];
+                const int64_t j = jq[q];
+                if (j >= r1 || !colok) continue;
+                const double tj = tq[q];
+                double w, st, gs, de;
+                if (j == i) {
+                    a.dvec[c] = y;  // d_c = Delta_ii for this sweep's finalize
+                    w = 1.0;
+                    st = 0.0;
+                    gs = 0.0;
+                    de = 0.0;
+                } else {
+                    const double gap = tj - ti;
+                    w = -y / gap;  // (z d - y) / gap with z = 0
+                    st = w;
+                    gs = gap * st;
+                    de = w;
+                }
+                a.zout[j * a.ldz + c] = w;
+                if (a.zlo_out) a.zlo_out[j * a.ldz + c] = (float)(j == i ? 0.0 : w);
+                s0 += st * st;
+                s1 += (j == i) ? 1.0 : 0.0;
+                s2 += gs * gs;
+                s3 += de * de;
             }
-            double w, st, gs, de;
-            if (j == i) {
-                a.dvec[c] = y;  // d_c = Delta_ii for this sweep's finalize
-                w = 1.0;
-                st = 0.0;
-                gs = 0.0;
-                de = 0.0;
-            } else {
-                const double gap = tj - ti;
-                w = -y / gap;  // (z d - y) / gap with z = 0
-                st = w;
-                gs = gap * st;
-                de = w;
-            }
-            a.zout[j * a.ldz + c] = w;
-            if (a.zlo_out) a.zlo_out[j * a.ldz + c] = (float)(j == i ? 0.0 : w);
-            s0 += st * st;
-            s1 += (j == i) ? 1.0 : 0.0;
-            s2 += gs * gs;
-            s3 += de * de;
         }
         for (int off = kg; off < 64; off <<= 1) {
             s0 += __shfl_xor(s0, off);

@@ -85,11 +85,14 @@ def test_series_terms_and_start_match_the_oracle(ipt):
     assert e.value.status == ipt.IPT_EDEGENERATE
 
 
-def test_targets_and_prediction_definitions(ipt):
+@pytest.mark.parametrize("hidden", [32, 384])
+def test_targets_and_prediction_definitions(ipt, hidden):
     """ipt_mlp_targets and ipt_mlp_predict_z0 on synthetic inputs against their
     definitions: targets are the remainders (Z - E - sum_l eps^l T_l) / eps^(order+1)
     standardised with weighted mean and spread, and a prediction is E + sum_l eps^l T_l + eps^(order+1) (mu + sigma y)
-    with y the network output (within its BF16-network bounds)."""
+    with y the network output (within its BF16-network bounds). Hidden width 32: the
+    one-launch hidden layers reading x itself; 384: the packed input and the per-layer
+    products."""
     import torch
     say("mlp targets and prediction n=64 k=5")
     n, k, order, b = 64, 5, 2, 9
@@ -114,7 +117,7 @@ def test_targets_and_prediction_definitions(ipt):
     np.testing.assert_allclose(mu.cpu().numpy(), m_, rtol=1e-6, atol=1e-30)
     np.testing.assert_allclose(sd.cpu().numpy(), s_, rtol=1e-6)
     np.testing.assert_allclose(tg.cpu().numpy(), (rem - m_) / s_, rtol=1e-5, atol=1e-5)
-    dims = (2, 32, 2, n * k)
+    dims = (2, hidden, 2, n * k)
     net, p, _, _ = _random_net(ipt, dims, b, 11)
     x = np.stack([eps / 0.08, (eps / 0.08) ** 2], axis=1).astype(np.float32)
     mu_h = rng.standard_normal(n * k).astype(np.float32)
@@ -128,6 +131,36 @@ def test_targets_and_prediction_definitions(ipt):
         want[idx, np.arange(k)] = 1.0
         tol = sc * (sd_h * yb[p_]).reshape(n, k) + 1e-15
         assert np.all(np.abs(z0[p_] - want) <= tol + 1e-12 * sc)
+
+
+@pytest.mark.parametrize("n,k,hidden,depth,order", [(1024, 32, 256, 2, 2), (97, 5, 128, 3, 3), (64, 8, 32, 1, 0),
+                                                     (40, 4, 256, 2, 6), (50, 4, 384, 1, 1)])
+def test_prediction_rows_do_not_depend_on_the_batch(ipt, n, k, hidden, depth, order):
+    """A member's warm start does not depend on the other members or on the batch's
+    padding: the first 100 members of a 200-member prediction (two 128-row tiles) equal
+    a 100-member prediction bit for bit, and so does a repeat and a 7-member call. Hidden
+    layers of width <= 256 run as one launch reading x itself; 384 takes the packed
+    input and the per-layer products. Vector stores of the epilogue (k a multiple of 4,
+    order <= 4) and scalar ones (k = 5; order 6)."""
+    say("mlp prediction rows n=%d k=%d hidden=%d depth=%d order=%d" % (n, k, hidden, depth, order))
+    dims = (2, hidden, depth, n * k)
+    net, _, _, _ = _random_net(ipt, dims, 8, 21, scale=0.1)
+    rng = np.random.default_rng(22)
+    b = 200
+    eps = rng.uniform(0.005, 0.02, b)
+    x = np.stack([eps / 0.02, (eps / 0.02) ** 2], axis=1).astype(np.float32)
+    idx = np.sort(rng.choice(n, k, replace=False)).astype(np.int32)
+    mu = rng.standard_normal(n * k).astype(np.float32)
+    sd = rng.uniform(0.5, 2.0, n * k).astype(np.float32)
+    terms = rng.standard_normal((order, n, k)) if order else None
+    kw = dict(terms=None if terms is None else t(terms))
+    z_all = net.predict_z0(t(x), t(mu), t(sd), t(eps), n, k, t(idx), **kw).cpu().numpy()
+    z_few = net.predict_z0(t(x[:100]), t(mu), t(sd), t(eps[:100]), n, k, t(idx), **kw).cpu().numpy()
+    assert np.array_equal(z_all[:100], z_few)
+    assert np.array_equal(net.predict_z0(t(x[:100]), t(mu), t(sd), t(eps[:100]), n, k, t(idx), **kw).cpu().numpy(), z_few)
+    assert np.array_equal(net.predict_z0(t(x[:7]), t(mu), t(sd), t(eps[:7]), n, k, t(idx), **kw).cpu().numpy(), z_few[:7])
+    assert np.all(z_few[:, idx, np.arange(k)] == 1.0)
+    assert np.all(np.isfinite(z_few))
 
 
 def test_training_reduces_loss(ipt):

@@ -167,6 +167,12 @@ def test_zcsr_errors(ipt):
     with pytest.raises(ipt.IPTError) as e:
         _solve(ipt, th2, rp, col, val, idx)
     assert e.value.status == ipt.IPT_EDEGENERATE
+    # a coincidence far down a long theta (the check runs in chunks of 4096 rows)
+    thl, rpl, coll, vall = _sparse(10000, "general", 2, 0.02, 1)
+    thl[9000] = thl[9]
+    with pytest.raises(ipt.IPTError) as e:
+        _solve(ipt, thl, rpl, coll, vall, idx)
+    assert e.value.status == ipt.IPT_EDEGENERATE
     bad = col.copy()
     bad[0] = 64  # column out of range
     with pytest.raises(ipt.IPTError) as e:
